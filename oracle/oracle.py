@@ -1,0 +1,356 @@
+"""Python handle on the FP64 CPU oracle (``sl_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU
+baseline of the benchmark use this module; the product library never does.
+
+The lattice is built here by lattice-vector enumeration: for every site and
+every lattice vector within two unit cells, the ideal distance decides the
+exchange shell, so a small periodic box that reaches the same neighbour
+through several images counts each image as its own bond.  Sites are
+numbered canonically, ((z*Ly + y)*Lx + x)*nb + b, with basis b = 0 at the
+cell corner and b = 1 at the body centre (bcc), all sites shifted by a
+quarter of the lattice constant so that none lies on an electron-grid face.
+The spin update order uses the checkerboard colouring
+colour = 2b + (x + y + z) mod 2 (bcc, four colours) or (x + y + z) mod 2
+(simple cubic, two colours); the builder asserts that no bond joins two
+spins of one colour.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sl_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "libsl_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OrDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("n_colours", C.c_int32),
+        ("colour", C.POINTER(C.c_int32)), ("ctr_id", C.POINTER(C.c_int32)),
+        ("species", C.POINTER(C.c_int32)), ("n_species", C.c_int32),
+        ("mu_s", C.POINTER(C.c_double)), ("mass_s", C.POINTER(C.c_double)),
+        ("nbr_off", C.POINTER(C.c_int32)), ("nbr_j", C.POINTER(C.c_int32)),
+        ("nbr_J", C.POINTER(C.c_double)),
+        ("x0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
+        ("s0", C.POINTER(C.c_double)),
+        ("box", C.c_double * 3), ("B", C.c_double * 3), ("alpha", C.c_double),
+        ("dt", C.c_double), ("noise_mode", C.c_int32), ("mu_ref", C.c_double),
+        ("seed", C.c_uint32), ("run_id", C.c_uint32), ("lattice_live", C.c_int32),
+        ("morse", C.c_double * 4), ("tn", C.c_int32 * 3), ("ttm_mode", C.c_int32),
+        ("Te0", C.POINTER(C.c_double)), ("gamma_e", C.c_double), ("G_el", C.c_double),
+        ("kappa_e", C.c_double), ("n_sub", C.c_int32), ("S0", C.c_double),
+        ("t0", C.c_double), ("fwhm", C.c_double), ("profile", C.c_int32),
+        ("depth", C.c_double),
+    ]
+
+
+class OrObs(C.Structure):
+    _fields_ = [
+        ("t", C.c_double), ("step", C.c_int64), ("M", (C.c_double * 3) * 4),
+        ("m", C.c_double * 3), ("m_abs", C.c_double), ("E_ex", C.c_double),
+        ("E_z", C.c_double), ("KE", C.c_double), ("PE", C.c_double), ("E_e", C.c_double),
+        ("Te_mean", C.c_double), ("Te_max", C.c_double), ("Tl", C.c_double),
+        ("Tspin", C.c_double * 4),
+    ]
+
+    def to_dict(self) -> dict:
+        return {
+            "t": self.t, "step": self.step,
+            "M": np.array([[self.M[s][k] for k in range(3)] for s in range(4)]),
+            "m": np.array([self.m[k] for k in range(3)]), "m_abs": self.m_abs,
+            "E_ex": self.E_ex, "E_z": self.E_z, "KE": self.KE, "PE": self.PE,
+            "E_e": self.E_e, "Te_mean": self.Te_mean, "Te_max": self.Te_max,
+            "Tl": self.Tl, "Tspin": np.array([self.Tspin[s] for s in range(4)]),
+        }
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [C.POINTER(OrDesc)]
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_step.restype = C.c_int
+        L.or_step.argtypes = [C.c_void_p, C.c_int64]
+        L.or_get_state.argtypes = [C.c_void_p] + [C.POINTER(C.c_double)] * 5
+        L.or_set_spins.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.or_get_step.restype = C.c_int64
+        L.or_get_step.argtypes = [C.c_void_p]
+        L.or_observables.argtypes = [C.c_void_p, C.POINTER(OrObs)]
+        L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                       C.POINTER(C.c_uint32)]
+        L.or_normals3.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, C.c_uint32,
+                                  C.POINTER(C.c_double)]
+        L.or_llg_exact_flow.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.c_double, C.c_double]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+# ------------------------------------------------------------------ helpers
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+    return out
+
+
+def normals3(seed: int, run: int, cid: int, step: int, stream: int) -> np.ndarray:
+    out = np.zeros(3)
+    lib().or_normals3(seed, run, cid, step, stream, _p(out, C.c_double))
+    return out
+
+
+def llg_exact_flow(s, w, alpha: float, tau: float) -> np.ndarray:
+    s = np.array(s, dtype=np.float64)
+    w = np.array(w, dtype=np.float64)
+    lib().or_llg_exact_flow(_p(s, C.c_double), _p(w, C.c_double), alpha, tau)
+    return s
+
+
+# ------------------------------------------------------------- lattice build
+
+@dataclass
+class Topology:
+    n: int
+    n_colours: int
+    colour: np.ndarray       # int32 [n]
+    ctr_id: np.ndarray       # int32 [n]
+    pos: np.ndarray          # float64 [n,3]
+    box: tuple
+    nbr_off: np.ndarray      # int32 [n+1]
+    nbr_j: np.ndarray        # int32 [nnz]
+    nbr_shell: np.ndarray    # int32 [nnz]
+
+
+def lattice_topology(lattice: int, ncell, a: float, n_shells: int) -> Topology:
+    """Sites, colours and exchange neighbours of a periodic sc (0) or bcc (1)
+    lattice by enumeration of lattice vectors."""
+    Lx, Ly, Lz = (int(v) for v in ncell)
+    if lattice == 0:
+        basis = np.array([[0.0, 0.0, 0.0]])
+        shells = [1.0, np.sqrt(2.0)]
+    elif lattice == 1:
+        basis = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])
+        shells = [np.sqrt(3.0) / 2.0, 1.0]
+    else:
+        raise ValueError("lattice")
+    nb = basis.shape[0]
+    n = nb * Lx * Ly * Lz
+    z, y, x, b = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), np.arange(nb),
+                             indexing="ij")
+    x, y, z, b = x.ravel(), y.ravel(), z.ravel(), b.ravel()
+    idx = ((z * Ly + y) * Lx + x) * nb + b
+    assert np.array_equal(idx, np.arange(n))
+    cell = np.stack([x, y, z], axis=1).astype(np.float64)
+    pos = (cell + 0.25 + basis[b]) * a
+    parity = (x + y + z) % 2
+    colour = (2 * b + parity) if nb == 2 else parity
+    # every (basis b, lattice-vector offset, basis b2) with an ideal distance
+    # on one of the first n_shells shells
+    nbrs = [[] for _ in range(nb)]
+    R = 2
+    for bi in range(nb):
+        for dz in range(-R, R + 1):
+            for dy in range(-R, R + 1):
+                for dx in range(-R, R + 1):
+                    for bj in range(nb):
+                        d = np.array([dx, dy, dz], dtype=np.float64) + basis[bj] - basis[bi]
+                        dist = np.sqrt((d * d).sum())
+                        for sh in range(n_shells):
+                            if abs(dist - shells[sh]) < 1e-9:
+                                nbrs[bi].append((dx, dy, dz, bj, sh))
+    zmax = max(len(v) for v in nbrs)
+    J = np.zeros((n, zmax), dtype=np.int64)
+    SH = np.zeros((n, zmax), dtype=np.int64)
+    for bi in range(nb):
+        sel = np.nonzero(b == bi)[0]
+        for q, (dx, dy, dz, bj, sh) in enumerate(nbrs[bi]):
+            xj = (x[sel] + dx) % Lx
+            yj = (y[sel] + dy) % Ly
+            zj = (z[sel] + dz) % Lz
+            J[sel, q] = ((zj * Ly + yj) * Lx + xj) * nb + bj
+            SH[sel, q] = sh
+    counts = np.array([len(nbrs[bi]) for bi in range(nb)])[b]
+    assert np.all(counts == zmax)
+    nbr_off = np.arange(0, n * zmax + 1, zmax, dtype=np.int32)
+    nbr_j = J.ravel().astype(np.int32)
+    nbr_shell = SH.ravel().astype(np.int32)
+    # proper colouring: no bond inside a colour
+    own = np.repeat(np.arange(n), zmax)
+    assert not np.any(colour[own] == colour[nbr_j]), "improper colouring"
+    return Topology(n=n, n_colours=2 * nb, colour=colour.astype(np.int32),
+                    ctr_id=np.arange(n, dtype=np.int32), pos=pos,
+                    box=(a * Lx, a * Ly, a * Lz), nbr_off=nbr_off, nbr_j=nbr_j,
+                    nbr_shell=nbr_shell)
+
+
+# --------------------------------------------------------------- the system
+
+class Oracle:
+    """One run of the FP64 oracle.
+
+    ``spec`` is a ``SystemSpec``-like object (attributes as in
+    ``paper_2608_18541_amd.inputs.SystemSpec``); ``species``, ``spins`` and
+    ``vel`` are the initial state in canonical site order.  ``topology``
+    overrides the lattice (used for dimers and isolated spins).
+    """
+
+    def __init__(self, spec, species, spins, vel=None, disp=None, Te=None,
+                 topology: Optional[Topology] = None):
+        if topology is None:
+            topology = lattice_topology(spec.lattice, spec.ncell, spec.a, spec.n_shells)
+        t = topology
+        n = t.n
+        self.n = n
+        self.topology = t
+        sp = np.ascontiguousarray(np.asarray(species, dtype=np.int32).reshape(n))
+        # exchange constant of every neighbour entry from shell and species pair
+        Jtab = np.asarray(spec.J, dtype=np.float64)
+        own = np.repeat(np.arange(n), np.diff(t.nbr_off))
+        nbr_J = Jtab[t.nbr_shell, sp[own], sp[t.nbr_j]]
+        self._keep = {}
+        k = self._keep
+        k["colour"] = np.ascontiguousarray(t.colour, dtype=np.int32)
+        k["ctr_id"] = np.ascontiguousarray(t.ctr_id, dtype=np.int32)
+        k["species"] = sp
+        k["mu"] = np.ascontiguousarray(np.asarray(spec.mu, dtype=np.float64))
+        k["mass"] = np.ascontiguousarray(np.asarray(spec.mass, dtype=np.float64))
+        k["nbr_off"] = np.ascontiguousarray(t.nbr_off, dtype=np.int32)
+        k["nbr_j"] = np.ascontiguousarray(t.nbr_j, dtype=np.int32)
+        k["nbr_J"] = np.ascontiguousarray(nbr_J, dtype=np.float64)
+        x0 = np.array(t.pos, dtype=np.float64)
+        if disp is not None:
+            x0 = x0 + np.asarray(disp, dtype=np.float64).reshape(n, 3)
+        k["x0"] = np.ascontiguousarray(x0)
+        k["v0"] = np.ascontiguousarray(np.zeros((n, 3)) if vel is None
+                                       else np.asarray(vel, dtype=np.float64).reshape(n, 3))
+        k["s0"] = np.ascontiguousarray(np.asarray(spins, dtype=np.float64).reshape(n, 3))
+        ncell = int(np.prod(spec.tn))
+        if Te is None:
+            Te = np.full(ncell, float(spec.Te0))
+        k["Te0"] = np.ascontiguousarray(np.asarray(Te, dtype=np.float64).reshape(ncell))
+        d = OrDesc()
+        d.n = n
+        d.n_colours = t.n_colours
+        d.colour = _p(k["colour"], C.c_int32)
+        d.ctr_id = _p(k["ctr_id"], C.c_int32)
+        d.species = _p(k["species"], C.c_int32)
+        d.n_species = spec.n_species
+        d.mu_s = _p(k["mu"], C.c_double)
+        d.mass_s = _p(k["mass"], C.c_double)
+        d.nbr_off = _p(k["nbr_off"], C.c_int32)
+        d.nbr_j = _p(k["nbr_j"], C.c_int32)
+        d.nbr_J = _p(k["nbr_J"], C.c_double)
+        d.x0 = _p(k["x0"], C.c_double)
+        d.v0 = _p(k["v0"], C.c_double)
+        d.s0 = _p(k["s0"], C.c_double)
+        d.box = (C.c_double * 3)(*t.box)
+        d.B = (C.c_double * 3)(*spec.B)
+        d.alpha = spec.alpha
+        d.dt = spec.dt
+        d.noise_mode = spec.noise_mode
+        d.mu_ref = spec.mu_ref
+        d.seed = spec.seed & 0xFFFFFFFF
+        d.run_id = spec.run_id & 0xFFFFFFFF
+        d.lattice_live = spec.lattice_mode
+        d.morse = (C.c_double * 4)(*spec.morse)
+        d.tn = (C.c_int32 * 3)(*spec.tn)
+        d.ttm_mode = spec.ttm_mode
+        d.Te0 = _p(k["Te0"], C.c_double)
+        d.gamma_e = spec.gamma_e
+        d.G_el = spec.G_el
+        d.kappa_e = spec.kappa_e
+        d.n_sub = spec.n_sub
+        d.S0 = spec.S0
+        d.t0 = spec.t0
+        d.fwhm = spec.fwhm
+        d.profile = spec.profile
+        d.depth = spec.depth
+        if spec.lattice_mode == 1:
+            for bx in t.box:
+                assert bx > 2.0 * spec.morse[3], "box must exceed twice the Morse cutoff"
+        self._h = lib().or_create(C.byref(d))
+        self.spec = spec
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_destroy(h)
+            self._h = None
+
+    def step(self, n: int = 1) -> None:
+        rc = lib().or_step(self._h, int(n))
+        if rc != 0:
+            raise FloatingPointError("oracle: negative electron energy density")
+
+    @property
+    def step_count(self) -> int:
+        return int(lib().or_get_step(self._h))
+
+    def state(self) -> dict:
+        n = self.n
+        x = np.zeros((n, 3)); v = np.zeros((n, 3)); s = np.zeros((n, 3)); F = np.zeros((n, 3))
+        Te = np.zeros(int(np.prod(self.spec.tn)))
+        lib().or_get_state(self._h, _p(x, C.c_double), _p(v, C.c_double), _p(s, C.c_double),
+                           _p(F, C.c_double), _p(Te, C.c_double))
+        return {"x": x, "v": v, "s": s, "F": F, "Te": Te}
+
+    def set_spins(self, s) -> None:
+        a = np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(self.n, 3))
+        lib().or_set_spins(self._h, _p(a, C.c_double))
+
+    def observables(self) -> dict:
+        o = OrObs()
+        lib().or_observables(self._h, C.byref(o))
+        return o.to_dict()
+
+
+def generic_topology(n: int, bonds, colours, box=(100.0, 100.0, 100.0), pos=None,
+                     shell_of_bond=None) -> Topology:
+    """Topology from an explicit bond list [(i, j), ...] (each bond once)."""
+    lists = [[] for _ in range(n)]
+    shells = [[] for _ in range(n)]
+    for q, (i, j) in enumerate(bonds):
+        sh = 0 if shell_of_bond is None else shell_of_bond[q]
+        lists[i].append(j); shells[i].append(sh)
+        lists[j].append(i); shells[j].append(sh)
+    off = np.zeros(n + 1, dtype=np.int32)
+    for i in range(n):
+        off[i + 1] = off[i] + len(lists[i])
+    nj = np.array([j for l in lists for j in l], dtype=np.int32)
+    ns = np.array([s for l in shells for s in l], dtype=np.int32)
+    colours = np.asarray(colours, dtype=np.int32)
+    if pos is None:
+        pos = np.zeros((n, 3)) + 0.5
+    return Topology(n=n, n_colours=int(colours.max()) + 1, colour=colours,
+                    ctr_id=np.arange(n, dtype=np.int32), pos=np.asarray(pos, dtype=np.float64),
+                    box=tuple(box), nbr_off=off, nbr_j=nj, nbr_shell=ns)

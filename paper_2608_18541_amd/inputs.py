@@ -1,0 +1,237 @@
+"""Seeded synthetic inputs: workload presets and initial states.
+
+This module holds no step of the dynamics.  It turns the published workload
+descriptions (lattice, species, moments, couplings, two-temperature
+parameters) into plain numbers in metal units (Angstrom, ps, eV, amu, K, T)
+and draws seeded initial states, so that the HIP library and the test
+oracle start from identical inputs.
+
+Workload shapes follow the paper's validation systems: a bcc-Fe block with
+a Morse lattice (Results A), the Gd25(FeCo)75 random alloy with
+antiferromagnetic Fe-Gd coupling (Methods D, Table 1), ensembles of
+independent realizations (Methods F) and mixed-size request streams.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+
+# --- unit conversions of input parameters (CODATA 2018) ----------------------
+EV = 1.602176634e-19            # J per eV
+KB_EV = 8.617333262e-5          # eV / K
+AMU_KG = 1.66053906660e-27
+# 1 amu (A/ps)^2 in eV
+MVV2E = AMU_KG * 1.0e4 / EV
+
+LATTICE_SC = 0
+LATTICE_BCC = 1
+
+SPECIES_TM = 0                  # transition metal (Fe/Co merged)
+SPECIES_GD = 1
+
+
+def joule_to_ev(j: float) -> float:
+    return j / EV
+
+
+def w_per_m3k_to_metal(g: float) -> float:
+    """W m^-3 K^-1 -> eV ps^-1 A^-3 K^-1."""
+    return g / EV * 1.0e-12 * 1.0e-30
+
+
+def j_per_m3k2_to_metal(g: float) -> float:
+    """J m^-3 K^-2 -> eV A^-3 K^-2."""
+    return g / EV * 1.0e-30
+
+
+def w_per_m3_to_metal(s: float) -> float:
+    """W m^-3 -> eV ps^-1 A^-3."""
+    return s / EV * 1.0e-12 * 1.0e-30
+
+
+def w_per_mk_to_metal(k: float) -> float:
+    """W m^-1 K^-1 -> eV ps^-1 A^-1 K^-1."""
+    return k / EV * 1.0e-12 * 1.0e-10
+
+
+@dataclass
+class SystemSpec:
+    """Everything that defines one run, in metal units."""
+    lattice: int = LATTICE_BCC
+    ncell: tuple = (6, 6, 6)
+    a: float = 2.8665
+    n_species: int = 1
+    mu: tuple = (2.2, 0.0, 0.0, 0.0)            # Bohr magnetons
+    mass: tuple = (55.845, 0.0, 0.0, 0.0)       # amu
+    n_shells: int = 2
+    # J[shell][si][sj] in eV
+    J: tuple = (((0.022, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0)),
+                ((0.011, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0)))
+    B: tuple = (0.0, 0.0, 1.0)
+    alpha: float = 0.1
+    noise_mode: int = 0
+    mu_ref: float = 0.0
+    lattice_mode: int = 1                       # 0 frozen, 1 live
+    morse: tuple = (0.4174, 1.3885, 2.845, 5.0)  # D eV, a 1/A, r0 A, rc A
+    skin: float = 0.5
+    dt: float = 1.0e-4                          # ps (0.1 fs)
+    seed: int = 1234
+    run_id: int = 0
+    # electron-temperature grid
+    tn: tuple = (3, 3, 3)
+    ttm_mode: int = 0                           # 0 fixed field, 1 two-temperature
+    Te0: float = 300.0
+    gamma_e: float = 0.0
+    G_el: float = 0.0
+    kappa_e: float = 0.0
+    n_sub: int = 1
+    S0: float = 0.0
+    t0: float = 0.0
+    fwhm: float = 0.0
+    profile: int = 0
+    depth: float = 0.0
+
+    @property
+    def nbasis(self) -> int:
+        return 1 if self.lattice == LATTICE_SC else 2
+
+    @property
+    def n_sites(self) -> int:
+        L = self.ncell
+        return self.nbasis * L[0] * L[1] * L[2]
+
+    @property
+    def box(self) -> tuple:
+        return tuple(self.a * L for L in self.ncell)
+
+    @property
+    def n_tcells(self) -> int:
+        return self.tn[0] * self.tn[1] * self.tn[2]
+
+
+@dataclass
+class InitialState:
+    species: np.ndarray          # int8 [n]
+    spins: np.ndarray            # float64 [n, 3]
+    vel: np.ndarray              # float64 [n, 3]  A/ps
+    disp: Optional[np.ndarray] = None   # float64 [n, 3] A from ideal sites
+
+
+def _rng(seed: int, run_id: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(run_id), int(stream)]))
+
+
+# --- initial-state generators ---------------------------------------------------
+
+def species_bernoulli(n: int, p: float, seed: int, run_id: int) -> np.ndarray:
+    """Random binary alloy: each site independently Gd with probability p."""
+    rng = _rng(seed, run_id, 4)
+    return (rng.random(n) < p).astype(np.int8)
+
+
+def spins_tilted(n: int, max_deg: float, seed: int, run_id: int) -> np.ndarray:
+    """Unit spins uniform on the spherical cap within max_deg of +z."""
+    rng = _rng(seed, run_id, 2)
+    cmin = math.cos(math.radians(max_deg))
+    c = 1.0 - rng.random(n) * (1.0 - cmin)
+    phi = rng.random(n) * 2.0 * math.pi
+    sn = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+    s = np.stack([sn * np.cos(phi), sn * np.sin(phi), c], axis=1)
+    return s / np.linalg.norm(s, axis=1, keepdims=True)
+
+
+def spins_antiparallel(species: np.ndarray) -> np.ndarray:
+    """Gd along +z, transition metal along -z."""
+    s = np.zeros((species.shape[0], 3))
+    s[:, 2] = np.where(species == SPECIES_GD, 1.0, -1.0)
+    return s
+
+
+def spins_random(n: int, seed: int, run_id: int) -> np.ndarray:
+    rng = _rng(seed, run_id, 2)
+    s = rng.standard_normal((n, 3))
+    return s / np.linalg.norm(s, axis=1, keepdims=True)
+
+
+def maxwell_velocities(masses: np.ndarray, T: float, seed: int, run_id: int) -> np.ndarray:
+    """Gaussian velocities at temperature T with the centre-of-mass motion
+    removed and the kinetic energy rescaled to exactly (3N-3)/2 k_B T."""
+    n = masses.shape[0]
+    rng = _rng(seed, run_id, 3)
+    sd = np.sqrt(KB_EV * T / (masses * MVV2E))
+    v = rng.standard_normal((n, 3)) * sd[:, None]
+    p = (masses[:, None] * v).sum(axis=0)
+    v -= p / masses.sum()
+    if T <= 0.0 or n < 2:
+        return np.zeros_like(v)
+    ke = 0.5 * (masses[:, None] * MVV2E * v * v).sum()
+    target = 0.5 * (3 * n - 3) * KB_EV * T
+    return v * math.sqrt(target / ke)
+
+
+# --- workload presets --------------------------------------------------------------
+
+def fe_bcc_spec(L: int = 6, **kw) -> SystemSpec:
+    """bcc Fe, a = 2.8665 A, mu = 2.2 mu_B, J1 = 22 meV, J2 = 11 meV,
+    alpha = 0.1, B = 1 T along z, Morse lattice, fixed 300 K grid."""
+    s = SystemSpec(lattice=LATTICE_BCC, ncell=(L, L, L), a=2.8665, n_species=1,
+                   mu=(2.2, 0, 0, 0), mass=(55.845, 0, 0, 0), n_shells=2,
+                   J=(((0.022, 0, 0, 0), (0,) * 4, (0,) * 4, (0,) * 4),
+                      ((0.011, 0, 0, 0), (0,) * 4, (0,) * 4, (0,) * 4)),
+                   B=(0.0, 0.0, 1.0), alpha=0.1, lattice_mode=1,
+                   morse=(0.4174, 1.3885, 2.845, 5.0), skin=0.5, dt=1.0e-4,
+                   tn=(3, 3, 3), ttm_mode=0, Te0=300.0)
+    return replace(s, **kw)
+
+
+GDFECO_J_TMTM = joule_to_ev(2.835e-21)
+GDFECO_J_GDGD = joule_to_ev(1.26e-21)
+GDFECO_J_TMGD = joule_to_ev(-1.09e-21)
+
+
+def gdfeco_sc_spec(L: int = 32, alpha: float = 0.01, S0: float = 0.0, tn: int = 8,
+                   **kw) -> SystemSpec:
+    """Gd25(FeCo)75 on a simple-cubic lattice, a = 3.52 A: moments 1.92 / 7.63
+    mu_B, nearest-neighbour exchange TM-TM, Gd-Gd and antiferromagnetic TM-Gd,
+    B = 0, the Morse lattice of the Fe block (same potential and mass for
+    both species), two-temperature grid with C_e = gamma_e T_e,
+    gamma_e = 225 J m^-3 K^-2, G_el = 6.6e17 W m^-3 K^-1, 50 fs laser."""
+    J1 = ((GDFECO_J_TMTM, GDFECO_J_TMGD, 0, 0), (GDFECO_J_TMGD, GDFECO_J_GDGD, 0, 0),
+          (0,) * 4, (0,) * 4)
+    s = SystemSpec(lattice=LATTICE_SC, ncell=(L, L, L), a=3.52, n_species=2,
+                   mu=(1.92, 7.63, 0, 0), mass=(55.845, 55.845, 0, 0), n_shells=1,
+                   J=(J1, ((0,) * 4,) * 4), B=(0.0, 0.0, 0.0), alpha=alpha,
+                   lattice_mode=1, morse=(0.4174, 1.3885, 2.845, 5.0), skin=0.5,
+                   dt=1.0e-4, tn=(tn, tn, tn), ttm_mode=1, Te0=300.0,
+                   gamma_e=j_per_m3k2_to_metal(225.0),
+                   G_el=w_per_m3k_to_metal(6.6e17), kappa_e=0.0, n_sub=1,
+                   S0=S0, t0=0.1, fwhm=0.05, profile=0)
+    return replace(s, **kw)
+
+
+def initial_state(spec: SystemSpec, kind: str = "tilt", p_gd: float = 0.25,
+                  T_lattice: float = 300.0) -> InitialState:
+    """Seeded initial state for a spec.  kind: 'tilt' (within 10 degrees of
+    +z), 'afm' (Gd +z, TM -z) or 'random'."""
+    n = spec.n_sites
+    if spec.n_species > 1:
+        species = species_bernoulli(n, p_gd, spec.seed, spec.run_id)
+    else:
+        species = np.zeros(n, dtype=np.int8)
+    if kind == "tilt":
+        spins = spins_tilted(n, 10.0, spec.seed, spec.run_id)
+    elif kind == "afm":
+        spins = spins_antiparallel(species)
+    elif kind == "random":
+        spins = spins_random(n, spec.seed, spec.run_id)
+    else:
+        raise ValueError(kind)
+    masses = np.asarray(spec.mass, dtype=np.float64)[species.astype(np.int64)]
+    if spec.lattice_mode == 1 and T_lattice > 0:
+        vel = maxwell_velocities(masses, T_lattice, spec.seed, spec.run_id)
+    else:
+        vel = np.zeros((n, 3))
+    return InitialState(species=species, spins=spins, vel=vel)
