@@ -1,0 +1,247 @@
+/*
+ * spinlattice.h -- C ABI of the MI355X (gfx950) three-temperature
+ * atomistic spin-lattice step.
+ *
+ * One timestep n -> n+1 of a run (arXiv 2608.18541):
+ *   1. spins: stochastic Landau-Lifshitz-Gilbert update, Eq. (1) of
+ *      Methods A, with the effective field H_i = -(1/mu_i) dH/ds_i
+ *      (Heisenberg exchange over the lattice neighbour shells plus Zeeman)
+ *      and a Langevin field whose variance is 2 alpha k_B T_e / (gamma mu_i
+ *      mu_B dt) (Methods C: deterministic torque ~ 1/mu_i, noise amplitude
+ *      ~ 1/sqrt(mu_i)); T_e is the electron temperature of the grid cell
+ *      that contains the atom (Eq. (2), Methods B).  The spins are swept in
+ *      checkerboard colours, forward with half steps and back again, every
+ *      colour update being the exact constant-field flow of Eq. (1);
+ *   2. lattice: velocity Verlet with a Morse pair potential cut (and
+ *      shifted) at rc (the live lattice of Methods A);
+ *   3. electron-phonon exchange: an Ornstein-Uhlenbeck velocity step at the
+ *      cell's T_e with friction G_el / (3 n k_B); the energy the atoms gain
+ *      leaves the cell's electrons (Methods B, both baths read the same
+ *      T_e grid);
+ *   4. electron grid: explicit finite differences of
+ *      d(gamma_e T_e^2/2)/dt = kappa_e lap T_e + S(z,t) - (e-ph power), with
+ *      a Gaussian laser source S (Methods B).
+ * Noise is Philox4x32-10 keyed by (seed, run id) at counter (canonical site,
+ * step, stream), so a run's trajectory does not depend on what else runs.
+ *
+ * Units: Angstrom, ps, eV, amu, K, Tesla, Bohr magnetons.
+ * Arrays exchanged with the caller are host memory in canonical site order
+ * ((z*Ly + y)*Lx + x)*nb + b, b = 0 cell corner, b = 1 body centre (bcc);
+ * vectors are [n][3] row-major doubles.  Host pointers are borrowed for the
+ * duration of the call.  The library owns all device memory, obtained from
+ * the caller's allocator when one is given (else hipMalloc).  Streams are
+ * borrowed, never destroyed.  A handle is not thread-safe.
+ *
+ * Every entry point returns SL_OK or a negative status and never throws;
+ * sl_last_error() returns a message for the calling thread's last failure.
+ */
+#ifndef SPINLATTICE_H
+#define SPINLATTICE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sl_status;
+enum {
+    SL_OK = 0,
+    SL_EINVAL = -1,    /* invalid argument; nothing was changed            */
+    SL_ENOMEM = -2,    /* device memory or the batch memory budget exceeded */
+    SL_EHIP = -3,      /* a HIP runtime call failed                         */
+    SL_ENUMERIC = -4,  /* a run hit a numerical error (negative electron
+                          energy, neighbour-table overflow); it is frozen   */
+    SL_EBUSY = -5      /* no free slot in a batch                           */
+};
+
+enum { SL_LATTICE_SC = 0, SL_LATTICE_BCC = 1 };
+enum { SL_FP64 = 0, SL_FP32 = 1 };
+
+/* Device-memory provider (e.g. PyTorch's caching allocator).  alloc returns
+ * at least `bytes` bytes of device memory aligned to 256 bytes or NULL. */
+typedef struct sl_allocator {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes);
+    void (*free)(void* ctx, void* ptr);
+} sl_allocator;
+
+/* One run.  Shell k couples the sites at the k-th neighbour distance of the
+ * ideal lattice with J[k][species_i][species_j] (eV, H = -sum_bonds J s_i.s_j,
+ * negative J antiferromagnetic).  Supported: sc with 1 shell, bcc with 1 or
+ * 2 shells (the shells the checkerboard colouring keeps bond-free inside a
+ * colour).  Every ncell[d] must be even and >= 2. */
+typedef struct sl_system_desc {
+    int32_t lattice;          /* SL_LATTICE_SC or SL_LATTICE_BCC                  */
+    int32_t ncell[3];         /* unit cells per dimension                         */
+    double a;                 /* lattice constant, Angstrom                       */
+    int32_t n_species;        /* 1..4                                             */
+    const int8_t* species;    /* [n] species of each site, or NULL (all 0)        */
+    double mu[4];             /* moment per species, mu_B (> 0)                   */
+    double mass[4];           /* mass per species, amu (> 0 when live)            */
+    int32_t n_shells;         /* 1 or 2                                           */
+    double J[2][4][4];        /* eV                                               */
+    double B[3];              /* applied field, T                                 */
+    double alpha;             /* Gilbert damping (>= 0)                           */
+    int32_t noise_mode;       /* 0: FDT noise ~ 1/sqrt(mu);
+                                 1: control ~ 1/mu (equal at mu_ref)             */
+    double mu_ref;            /* mu_B, used by noise_mode 1                       */
+    int32_t lattice_mode;     /* 0: positions frozen at the sites; 1: live        */
+    double morse[4];          /* D (eV), alpha (1/A), r0 (A), cutoff rc (A)       */
+    double skin;              /* neighbour-list skin, A (> 0 when live)           */
+    double dt;                /* ps (> 0)                                         */
+    uint32_t seed, run_id;    /* Philox key                                       */
+    int32_t precision;        /* SL_FP64 or SL_FP32 (storage and spin arithmetic)  */
+    int32_t obs_every;        /* record observables every k steps (0: never)     */
+    int32_t obs_capacity;     /* ring of samples kept on the device (>= 1)        */
+    const double* spin0;      /* [n][3] unit spins (required, |s| within 1e-6)    */
+    const double* vel0;       /* [n][3] A/ps or NULL (zero)                       */
+    const double* disp0;      /* [n][3] displacement from the ideal site, A, or NULL */
+    void* stream;             /* hipStream_t to run on, or NULL (library stream)  */
+    const sl_allocator* alloc;/* or NULL (hipMalloc)                              */
+} sl_system_desc;
+
+/* Electron-temperature grid over the periodic box, cell (i,j,k) at index
+ * (k*n1 + j)*n0 + i; cell c holds the atoms whose wrapped position p has
+ * floor(p_d / (box_d / n_d)) = c_d.  mode 0 keeps T_e fixed (no
+ * electron-phonon step); mode 1 runs the two-temperature update. */
+typedef struct sl_ttm_desc {
+    int32_t n[3];             /* cells per dimension (product <= 65535)           */
+    int32_t mode;             /* 0 fixed field, 1 two-temperature                 */
+    double Te0;               /* uniform initial T_e, K (if Te_init is NULL)      */
+    const double* Te_init;    /* [n0*n1*n2] K, or NULL                            */
+    double gamma_e;           /* C_e = gamma_e T_e, eV A^-3 K^-2 (> 0 in mode 1)  */
+    double G_el;              /* eV ps^-1 A^-3 K^-1                                */
+    double kappa_e;           /* eV ps^-1 A^-1 K^-1                               */
+    int32_t n_sub;            /* diffusion sub-steps per step (>= 1)              */
+    double S0;                /* peak laser power density, eV ps^-1 A^-3          */
+    double t0, fwhm;          /* pulse centre and FWHM, ps                        */
+    int32_t profile;          /* 0 uniform; 1 cells whose centre z > box_z - depth */
+    double depth;             /* A                                                */
+} sl_ttm_desc;
+
+/* One observable sample, taken after a step (and once at step 0). */
+typedef struct sl_obs {
+    double t;                 /* ps                                               */
+    int64_t step;
+    double M[4][3];           /* mean spin per species                            */
+    double m[3];              /* mean spin of all sites                           */
+    double m_abs;
+    double E_ex, E_z;         /* exchange and Zeeman energy, eV                   */
+    double KE, PE;            /* lattice kinetic and Morse energy, eV             */
+    double E_e;               /* electron energy sum gamma_e T_e^2/2 V_cell, eV    */
+    double Te_mean, Te_max;   /* K                                                */
+    double Tl;                /* 2 KE / (3 n k_B), K                              */
+    double Tspin[4];          /* sum |s x h|^2 / (2 k_B sum s.h) per species, K    */
+} sl_obs;
+
+typedef struct sl_system_s* sl_system;
+
+/* Creates a run on the device: copies the description and initial state,
+ * builds the neighbour tables, computes the initial forces and (if
+ * obs_every > 0) records the step-0 sample.  The electron grid starts as
+ * one fixed cell at T_e = 0 until sl_set_ttm_grid is called.
+ * SL_EINVAL for any invalid field (listed above) or a box shorter than
+ * 3 (rc + skin) in a live dimension; *out is set only on success. */
+sl_status sl_init_system(const sl_system_desc* desc, sl_system* out);
+
+/* Replaces the electron-temperature grid (fields above).  Only before the
+ * first sl_step.  SL_EINVAL when an explicit diffusion sub-step would be
+ * unstable for the initial grid: kappa_e (dt/n_sub) sum_d 2/h_d^2 >
+ * gamma_e min T_e (h_d the cell widths; the linearised diffusivity is
+ * kappa_e / (gamma_e T_e)). */
+sl_status sl_set_ttm_grid(sl_system h, const sl_ttm_desc* ttm);
+
+/* Enqueues n_steps timesteps on the run's stream and returns (asynchronous). */
+sl_status sl_step(sl_system h, int64_t n_steps);
+
+/* Waits for the run's stream.  SL_ENUMERIC if the run hit a numerical error. */
+sl_status sl_synchronize(sl_system h);
+
+/* Waits, then copies up to max_samples observable samples not yet returned,
+ * oldest first, into out (host).  Samples older than the device ring
+ * capacity are lost; *n_out is the number copied. */
+sl_status sl_observables(sl_system h, sl_obs* out, int64_t max_samples, int64_t* n_out);
+
+/* Waits, then copies the state to host arrays in canonical order (any
+ * pointer may be NULL): positions wrapped into the box [n][3], velocities
+ * [n][3], spins [n][3], electron temperatures [cells]. */
+sl_status sl_get_state(sl_system h, double* x, double* v, double* s, double* Te);
+
+/* Number of sites, electron cells and completed steps (host view). */
+sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* steps);
+
+/* Device bytes a run with this description would hold. */
+sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
+                             size_t* bytes);
+
+/* Average device time (ms) of one launch of a kernel class over the last
+ * profiled sl_step_profiled call: 0 spin colour pass, 1 lattice force and
+ * electron-phonon step, 2 kick-drift, 3 end-of-step (grid, reductions). */
+sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[4], int64_t launches[4]);
+
+void sl_destroy(sl_system h);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* sl_last_error(void);
+
+/* -------------------------------------------------------------- batching
+ * Many independent runs advance together: every kernel launch covers all
+ * active runs (Methods F: replicas share nothing), and each run sees exactly
+ * the arithmetic it would see alone, so its trajectory is bitwise the same.
+ * Runs join and leave between advances (continuous batching). */
+typedef struct sl_batch_s* sl_batch;
+
+typedef struct sl_batch_desc {
+    int32_t precision;        /* SL_FP64 or SL_FP32 for every run of the batch    */
+    int32_t max_runs;         /* slots                                            */
+    size_t mem_budget;        /* device bytes the runs may hold (0: unlimited)    */
+    int32_t graph_steps;      /* steps captured per HIP graph replay (0: default) */
+    void* stream;             /* hipStream_t or NULL                              */
+    const sl_allocator* alloc;
+} sl_batch_desc;
+
+typedef struct sl_run_info {
+    int32_t slot;
+    int32_t status;           /* SL_OK or SL_ENUMERIC                             */
+    int64_t steps_done;
+    int64_t steps_target;
+    int64_t n_samples;        /* samples recorded so far                          */
+} sl_run_info;
+
+sl_status sl_batch_create(const sl_batch_desc* desc, sl_batch* out);
+
+/* Admits a run that will take n_steps steps (desc->precision, stream and
+ * alloc are ignored: the batch's apply).  SL_EBUSY when no slot is free,
+ * SL_ENOMEM when its footprint does not fit the remaining budget. */
+sl_status sl_batch_add(sl_batch b, const sl_system_desc* desc, const sl_ttm_desc* ttm,
+                       int64_t n_steps, int32_t* slot);
+
+/* Enqueues up to n_steps steps for every active run (a run stops at its
+ * target).  Asynchronous. */
+sl_status sl_batch_advance(sl_batch b, int64_t n_steps);
+
+/* Host view of the slots in use (no wait): fills up to cap entries. */
+sl_status sl_batch_runs(sl_batch b, sl_run_info* info, int32_t cap, int32_t* n_out);
+
+/* Waits, then returns a run's state and samples (as sl_get_state and
+ * sl_observables; NULL pointers skip). */
+sl_status sl_batch_get(sl_batch b, int32_t slot, double* x, double* v, double* s, double* Te,
+                       sl_obs* obs, int64_t max_samples, int64_t* n_obs);
+
+/* Releases a slot and its device memory (waits for the stream first). */
+sl_status sl_batch_remove(sl_batch b, int32_t slot);
+
+/* Bytes of the budget in use. */
+sl_status sl_batch_memory(sl_batch b, size_t* used, size_t* budget);
+
+sl_status sl_batch_synchronize(sl_batch b);
+
+void sl_batch_destroy(sl_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPINLATTICE_H */

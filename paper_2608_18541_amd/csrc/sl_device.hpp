@@ -1,0 +1,247 @@
+// sl_device.hpp -- device building blocks of the spin-lattice step on gfx950.
+//
+// Everything here is __host__ __device__ so that the integer logic (site
+// numbering, division by run-time constants, Philox) can also be checked on
+// the CPU.  Floating-point formulas are written once, templated on the
+// storage precision T (float or double).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sl {
+
+// ------------------------------------------------------------- constants
+// CODATA 2018 in metal units (Angstrom, ps, eV, amu, K, T).
+constexpr double kKB = 8.617333262e-5;        // eV/K
+constexpr double kHBAR = 6.582119569e-4;      // eV ps
+constexpr double kMUB = 5.7883818060e-5;      // eV/T
+constexpr double kGAMMA = 2.0 * kMUB / kHBAR; // rad/(ps T), g = 2
+// amu (A/ps)^2 -> eV
+constexpr double kMVV2E = 1.66053906660e-27 * 1.0e4 / 1.602176634e-19;
+// fixed-point scale of the per-cell electron-phonon energy accumulators
+constexpr double kFIX = 4503599627370496.0;   // 2^52 units per eV
+constexpr double kTWO_M32 = 2.3283064365386963e-10;  // 2^-32
+
+// ------------------------------------------------------- division helper
+// Quotient of n < 2^31 by a fixed divisor d >= 1 with one high multiply
+// (Granlund-Montgomery "division by invariant integers"):
+//   l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+//   q = (mulhi(n, m) + n) >> l.
+struct FastDiv {
+    uint32_t d, m, l;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    f.l = l;
+    f.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1ull);
+    return f;
+}
+
+__host__ __device__ inline uint32_t mulhi32(uint32_t a, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umulhi(a, b);
+#else
+    return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+#endif
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f)
+{
+    return (mulhi32(n, f.m) + n) >> f.l;
+}
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11) from its definition: per round two
+// 32x32 -> 64-bit products of counter words 0 and 2 with the round
+// multipliers, the high halves mixed with the other words and the key, the
+// key advanced by the Weyl increments between rounds.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = 0xD2511F53u, b = 0xCD9E8D57u;
+        uint32_t hi0 = mulhi32(a, c.x), lo0 = a * c.x;
+        uint32_t hi1 = mulhi32(b, c.z), lo1 = b * c.z;
+        U4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Three standard normals from one Philox block keyed by (seed, run) at
+// counter (site id, step low, step high, stream): words -> open-interval
+// uniforms (w + 1/2) 2^-32 -> two Box-Muller pairs, the fourth normal
+// dropped.  The single-precision variant keeps the top 24 bits of each word
+// ((w >> 8) + 1/2) 2^-24, which a float holds exactly.
+template <typename T> struct Normals3 {
+    T a, b, c;
+};
+
+__device__ inline Normals3<double> normals3_f64(uint32_t seed, uint32_t run, uint32_t id,
+                                                int64_t step, uint32_t stream)
+{
+    U4 ctr{id, (uint32_t)((uint64_t)step & 0xFFFFFFFFu), (uint32_t)((uint64_t)step >> 32),
+           stream};
+    U4 w = philox4x32_10(ctr, seed, run);
+    double u0 = ((double)w.x + 0.5) * kTWO_M32;
+    double u1 = ((double)w.y + 0.5) * kTWO_M32;
+    double u2 = ((double)w.z + 0.5) * kTWO_M32;
+    double u3 = ((double)w.w + 0.5) * kTWO_M32;
+    double r0 = sqrt(-2.0 * log(u0));
+    double r1 = sqrt(-2.0 * log(u2));
+    double s1, c1, c3;
+    sincospi(2.0 * u1, &s1, &c1);
+    c3 = cospi(2.0 * u3);
+    return {r0 * c1, r0 * s1, r1 * c3};
+}
+
+__device__ inline Normals3<float> normals3_f32(uint32_t seed, uint32_t run, uint32_t id,
+                                               int64_t step, uint32_t stream)
+{
+    U4 ctr{id, (uint32_t)((uint64_t)step & 0xFFFFFFFFu), (uint32_t)((uint64_t)step >> 32),
+           stream};
+    U4 w = philox4x32_10(ctr, seed, run);
+    float u0 = ((float)(w.x >> 8) + 0.5f) * 5.9604644775390625e-8f;   // 24-bit uniforms
+    float u1 = ((float)(w.y >> 8) + 0.5f) * 5.9604644775390625e-8f;
+    float u2 = ((float)(w.z >> 8) + 0.5f) * 5.9604644775390625e-8f;
+    float u3 = ((float)(w.w >> 8) + 0.5f) * 5.9604644775390625e-8f;
+    float r0 = sqrtf(-2.0f * logf(u0));
+    float r1 = sqrtf(-2.0f * logf(u2));
+    float s1, c1;
+    sincospif(2.0f * u1, &s1, &c1);
+    float c3 = cospif(2.0f * u3);
+    return {r0 * c1, r0 * s1, r1 * c3};
+}
+
+template <typename T> __device__ inline Normals3<T> normals3(uint32_t, uint32_t, uint32_t,
+                                                             int64_t, uint32_t);
+template <> __device__ inline Normals3<double> normals3<double>(uint32_t s, uint32_t r,
+                                                                uint32_t i, int64_t st,
+                                                                uint32_t sm)
+{
+    return normals3_f64(s, r, i, st, sm);
+}
+template <> __device__ inline Normals3<float> normals3<float>(uint32_t s, uint32_t r,
+                                                              uint32_t i, int64_t st,
+                                                              uint32_t sm)
+{
+    return normals3_f32(s, r, i, st, sm);
+}
+
+// ------------------------------------------------------ exact LLG flow
+// Constant precession vector w over a time tau (Eq. (1), Landau-Lifshitz
+// form).  With e = w/|w|, u = s.e, phi = |w| tau/(1+alpha^2) and
+// E = exp(-alpha phi), tan(theta/2) shrinks by E while the transverse part
+// turns right-handedly about e by phi.  Using
+//   cos(theta') = ((1+u) - (1-u) E^2) / D,  sin(theta') = 2 E |s_perp| / D,
+//   D = (1+u) + (1-u) E^2,
+// the new spin is cos(theta') e + (2E/D) R_phi(s_perp) with no division by
+// |s_perp| (finite for s along +e or -e).  Renormalised in double.
+template <typename T> struct V3 {
+    T x, y, z;
+};
+
+__device__ inline void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ inline void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+
+template <typename T>
+__device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2)
+{
+    T wn2 = w.x * w.x + w.y * w.y + w.z * w.z;
+    if (!(wn2 > T(0))) return s;
+    T wn = sqrt(wn2);
+    T iw = T(1) / wn;
+    V3<T> e{w.x * iw, w.y * iw, w.z * iw};
+    T u = s.x * e.x + s.y * e.y + s.z * e.z;
+    V3<T> p{s.x - u * e.x, s.y - u * e.y, s.z - u * e.z};
+    T phi = wn * tau * inv1pa2;
+    T E = exp(-alpha * phi);
+    T E2 = E * E;
+    T D = (T(1) + u) + (T(1) - u) * E2;
+    T iD = T(1) / D;
+    T ct = ((T(1) + u) - (T(1) - u) * E2) * iD;
+    T f = T(2) * E * iD;
+    T sn, cs;
+    sin_cos(phi, &sn, &cs);
+    V3<T> ex{e.y * p.z - e.z * p.y, e.z * p.x - e.x * p.z, e.x * p.y - e.y * p.x};
+    double ox = (double)(ct * e.x + f * (cs * p.x + sn * ex.x));
+    double oy = (double)(ct * e.y + f * (cs * p.y + sn * ex.y));
+    double oz = (double)(ct * e.z + f * (cs * p.z + sn * ex.z));
+    double inv = 1.0 / sqrt(ox * ox + oy * oy + oz * oz);
+    return {(T)(ox * inv), (T)(oy * inv), (T)(oz * inv)};
+}
+
+// ------------------------------------------------------------- lattice
+// Site numbering.  Colour k of a site is (x+y+z) mod 2 on the simple-cubic
+// lattice and 2b + (x+y+z) mod 2 on bcc (b = 0 corner, 1 body centre).
+// Inside the device arrays the sites of one colour are contiguous:
+//   internal = k * H + xh + (Lx/2) * (y + Ly * z),  x = 2 xh + ((k + y + z) & 1),
+// with H = Lx Ly Lz / 2, so one colour pass streams one contiguous block.
+// The canonical (public) number is ((z Ly + y) Lx + x) nb + b.
+struct Geom {
+    int32_t Lx, Ly, Lz;   // unit cells per dimension (all even)
+    int32_t Lxh;          // Lx / 2
+    int32_t H;            // Lx Ly Lz / 2 = sites per colour
+    int32_t nb;           // basis atoms per cell (1 sc, 2 bcc)
+    int32_t C;            // colours (2 sc, 4 bcc)
+    FastDiv divH, divLxh, divLy;
+};
+
+struct Site {
+    int32_t x, y, z, b, k;
+};
+
+__host__ __device__ inline Site decode_site(const Geom& g, uint32_t idx)
+{
+    Site s;
+    uint32_t k = fdiv(idx, g.divH);
+    uint32_t l = idx - k * (uint32_t)g.H;
+    uint32_t r = fdiv(l, g.divLxh);
+    uint32_t xh = l - r * (uint32_t)g.Lxh;
+    uint32_t z = fdiv(r, g.divLy);
+    uint32_t y = r - z * (uint32_t)g.Ly;
+    s.k = (int32_t)k;
+    s.b = (g.nb == 2) ? (int32_t)(k >> 1) : 0;
+    s.y = (int32_t)y;
+    s.z = (int32_t)z;
+    s.x = 2 * (int32_t)xh + (int32_t)((k + y + z) & 1u);
+    return s;
+}
+
+// internal index of the site at cell (x, y, z) (already wrapped) and basis b
+__host__ __device__ inline int32_t encode_site(const Geom& g, int32_t x, int32_t y, int32_t z,
+                                               int32_t b)
+{
+    int32_t par = (x + y + z) & 1;
+    int32_t k = (g.nb == 2) ? (2 * b + par) : par;
+    return k * g.H + (x >> 1) + g.Lxh * (y + g.Ly * z);
+}
+
+__host__ __device__ inline int32_t canonical_of(const Geom& g, const Site& s)
+{
+    return ((s.z * g.Ly + s.y) * g.Lx + s.x) * g.nb + s.b;
+}
+
+__host__ __device__ inline int32_t wrapi(int32_t v, int32_t L)
+{
+    return v < 0 ? v + L : (v >= L ? v - L : v);
+}
+
+}  // namespace sl

@@ -1,0 +1,654 @@
+// sl_kernels.hpp -- HIP kernels of one spin-lattice timestep (gfx950).
+//
+// Every launch covers all active runs of an engine: block b reads
+// work[b] = {run, first item} and works on 256 consecutive items of that
+// run, so one run alone and the same run inside a batch execute identical
+// arithmetic in identical order (bitwise-equal trajectories).
+//
+// Per step, in stream order:
+//   k_spin_pass  x (2C-1)  colour sweep 0..C-1 (half steps), C-2..0, the
+//                          middle colour taking one full step
+//   k_kick_drift           half kick + drift, electron-cell id, skin check
+//   k_nbr_bin/sort/build   Verlet-list rebuild (no-ops unless flagged)
+//   k_atom_final           Morse forces, half kick, electron-phonon
+//                          Ornstein-Uhlenbeck step, observable partials
+//   k_end_step             electron grid, observable sample, step counter
+#pragma once
+
+#include "sl_device.hpp"
+#include "../../include/spinlattice.h"
+
+namespace sl {
+
+constexpr int kBlock = 256;
+constexpr int kEndBlock = 256;
+constexpr int NQ = 24;      // per-block observable partial sums
+
+enum { ERR_NEG_E = 1, ERR_BIN = 2, ERR_NBR = 4, ERR_DE = 8 };
+enum { PHASE_STEP = 0, PHASE_INIT = 1 };
+
+struct RunState {
+    int64_t step;
+    int64_t target;
+    int32_t err;
+    int32_t rebuild;
+    int64_t n_samples;
+    int64_t pad[3];
+};
+
+template <typename T> struct RunDev {
+    Geom g;
+    int32_t lattice, n, n_species, n_shells, live, ttm_mode, obs_every, obs_cap;
+    uint32_t seed, run_id;
+    T a, box[3], half_box[3];
+    T alpha, dt, tau_half, inv1pa2, gam;
+    T B[3];
+    T inv_mumb[4];       // 1 / (mu mu_B), T/eV
+    T sig[4];            // thermal-field std per sqrt(K), T
+    T J[2][4][4];        // eV
+    T hdtm[4];           // dt / (2 m) in A/ps per eV/A
+    T ou_c1, ou_amp[4];  // exp(-Gamma dt); sqrt((1 - c1^2) k_B / m) per sqrt(K)
+    T m_e[4];            // m in eV ps^2 / A^2
+    T mD, ma, mr0, rc2, Vc;
+    T skin_half2, rlist2;
+    double mumb[4];      // mu mu_B, eV/T
+    double Bd[3];
+    double cnt[4];       // sites per species
+    // electron grid
+    int32_t tn[3], ncell, n_sub, profile;
+    double th[3], gamma_e, kappa_e, S0, t0, fwhm, Vcell, depth, dtd;
+    // neighbour bins
+    int32_t nbin[3], nbins, bin_cap, max_nbr;
+    T binw[3];
+    // device arrays
+    T *sx, *sy, *sz, *ux, *uy, *uz, *vx, *vy, *vz, *fx, *fy, *fz, *rx, *ry, *rz;
+    int8_t* species;
+    uint16_t* cell;
+    int32_t *nbr, *nbr_n, *bin_n, *bin_atoms;
+    double *Te, *ee, *lap;
+    unsigned long long* dE;
+    double* partial;
+    int32_t n_part;
+    sl_obs* ring;
+    RunState* st;
+};
+
+// ----------------------------------------------------------- helpers
+
+template <typename T> __device__ inline int species_of(const RunDev<T>& R, int idx)
+{
+    return R.n_species > 1 ? (int)R.species[idx] : 0;
+}
+
+// Exchange sum h = sum_j J_ij s_j (eV) over the neighbour shells of site
+// (x, y, z, b), read from the colour-major spin arrays.
+template <typename T>
+__device__ inline V3<T> exchange_sum(const RunDev<T>& R, int x, int y, int z, int b, int sp)
+{
+    const Geom& g = R.g;
+    V3<T> h{T(0), T(0), T(0)};
+    auto add = [&](int xw, int yw, int zw, int bw, int shell) {
+        int j = encode_site(g, xw, yw, zw, bw);
+        int sj = species_of(R, j);
+        T Jv = R.J[shell][sp][sj];
+        h.x += Jv * R.sx[j];
+        h.y += Jv * R.sy[j];
+        h.z += Jv * R.sz[j];
+    };
+    const int xm = x == 0 ? g.Lx - 1 : x - 1, xp = x == g.Lx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.Ly - 1 : y - 1, yp = y == g.Ly - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.Lz - 1 : z - 1, zp = z == g.Lz - 1 ? 0 : z + 1;
+    if (R.lattice == SL_LATTICE_SC) {
+        add(xm, y, z, 0, 0);
+        add(xp, y, z, 0, 0);
+        add(x, ym, z, 0, 0);
+        add(x, yp, z, 0, 0);
+        add(x, y, zm, 0, 0);
+        add(x, y, zp, 0, 0);
+    } else {
+        // first shell: the 8 sites of the other basis at (+-a/2, +-a/2, +-a/2)
+        const int ob = 1 - b;
+        const int x0 = b == 0 ? xm : x, x1 = b == 0 ? x : xp;
+        const int y0 = b == 0 ? ym : y, y1 = b == 0 ? y : yp;
+        const int z0 = b == 0 ? zm : z, z1 = b == 0 ? z : zp;
+        add(x0, y0, z0, ob, 0);
+        add(x1, y0, z0, ob, 0);
+        add(x0, y1, z0, ob, 0);
+        add(x1, y1, z0, ob, 0);
+        add(x0, y0, z1, ob, 0);
+        add(x1, y0, z1, ob, 0);
+        add(x0, y1, z1, ob, 0);
+        add(x1, y1, z1, ob, 0);
+        if (R.n_shells > 1) {
+            // second shell: the 6 sites of the same basis at +-a along an axis
+            add(xm, y, z, b, 1);
+            add(xp, y, z, b, 1);
+            add(x, ym, z, b, 1);
+            add(x, yp, z, b, 1);
+            add(x, y, zm, b, 1);
+            add(x, y, zp, b, 1);
+        }
+    }
+    return h;
+}
+
+template <typename T> __device__ inline V3<T> ideal_site(const RunDev<T>& R, const Site& s)
+{
+    const T off = T(0.25) + T(0.5) * (T)s.b;
+    return {((T)s.x + off) * R.a, ((T)s.y + off) * R.a, ((T)s.z + off) * R.a};
+}
+
+__device__ inline int wrap_cell_delta(int d, int L)
+{
+    const int h = L >> 1;
+    return d > h ? d - L : (d < -h ? d + L : d);
+}
+
+template <typename T> __device__ inline T min_image(T d, T box, T half)
+{
+    return d > half ? d - box : (d < -half ? d + box : d);
+}
+
+// Separation x_j - x_i (minimum image) from the ideal sites and displacements.
+template <typename T>
+__device__ inline V3<T> separation(const RunDev<T>& R, const Site& si, const V3<T>& ui,
+                                   int j)
+{
+    Site sj = decode_site(R.g, (uint32_t)j);
+    const T hb = T(0.5) * (T)(sj.b - si.b);
+    V3<T> d;
+    d.x = ((T)wrap_cell_delta(sj.x - si.x, R.g.Lx) + hb) * R.a + (R.ux[j] - ui.x);
+    d.y = ((T)wrap_cell_delta(sj.y - si.y, R.g.Ly) + hb) * R.a + (R.uy[j] - ui.y);
+    d.z = ((T)wrap_cell_delta(sj.z - si.z, R.g.Lz) + hb) * R.a + (R.uz[j] - ui.z);
+    d.x = min_image(d.x, R.box[0], R.half_box[0]);
+    d.y = min_image(d.y, R.box[1], R.half_box[1]);
+    d.z = min_image(d.z, R.box[2], R.half_box[2]);
+    return d;
+}
+
+template <typename T> __device__ inline T wrap_box(T x, T L)
+{
+    return x - L * floor(x / L);
+}
+
+// Wrapped position of atom idx.
+template <typename T> __device__ inline V3<T> position(const RunDev<T>& R, const Site& s, int idx)
+{
+    V3<T> r = ideal_site(R, s);
+    return {wrap_box(r.x + R.ux[idx], R.box[0]), wrap_box(r.y + R.uy[idx], R.box[1]),
+            wrap_box(r.z + R.uz[idx], R.box[2])};
+}
+
+template <typename T> __device__ inline int electron_cell(const RunDev<T>& R, const V3<T>& p)
+{
+    int c[3];
+    const T pv[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int k = (int)floor((double)pv[d] / R.th[d]);
+        c[d] = k < 0 ? 0 : (k >= R.tn[d] ? R.tn[d] - 1 : k);
+    }
+    return (c[2] * R.tn[1] + c[1]) * R.tn[0] + c[0];
+}
+
+template <typename T> __device__ inline int bin_of(const RunDev<T>& R, const V3<T>& p, int* b3)
+{
+    const T pv[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int k = (int)(pv[d] / R.binw[d]);
+        b3[d] = k < 0 ? 0 : (k >= R.nbin[d] ? R.nbin[d] - 1 : k);
+    }
+    return (b3[2] * R.nbin[1] + b3[1]) * R.nbin[0] + b3[0];
+}
+
+template <typename T> __device__ inline bool run_active(const RunDev<T>& R, int64_t* step)
+{
+    const RunState* st = R.st;
+    *step = st->step;
+    return st->err == 0 && st->step < st->target;
+}
+
+// ------------------------------------------------------------ spins
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
+                                                      const int2* __restrict__ work, int pass)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (!run_active(R, &step)) return;
+    const int C = R.g.C;
+    if (pass >= 2 * C - 1) return;
+    const int colour = pass < C ? pass : 2 * C - 2 - pass;
+    const T tau = (pass == C - 1) ? R.dt : R.tau_half;
+    const int l = w.y + (int)threadIdx.x;
+    if (l >= R.g.H) return;
+    const int idx = colour * R.g.H + l;
+    const uint32_t r = fdiv((uint32_t)l, R.g.divLxh);
+    const int xh = l - (int)r * R.g.Lxh;
+    const int z = (int)fdiv(r, R.g.divLy);
+    const int y = (int)r - z * R.g.Ly;
+    const int x = 2 * xh + ((colour + y + z) & 1);
+    const int b = R.g.nb == 2 ? (colour >> 1) : 0;
+    const int sp = species_of(R, idx);
+    const V3<T> h = exchange_sum(R, x, y, z, b, sp);
+    T Hx = h.x * R.inv_mumb[sp] + R.B[0];
+    T Hy = h.y * R.inv_mumb[sp] + R.B[1];
+    T Hz = h.z * R.inv_mumb[sp] + R.B[2];
+    const double Te = R.Te[R.cell[idx]];
+    if (Te > 0.0 && R.sig[sp] > T(0)) {
+        const int canon = ((z * R.g.Ly + y) * R.g.Lx + x) * R.g.nb + b;
+        const Normals3<T> nu = normals3<T>(R.seed, R.run_id, (uint32_t)canon, step, 0u);
+        const T amp = R.sig[sp] * (T)sqrt(Te);
+        Hx += amp * nu.a;
+        Hy += amp * nu.b;
+        Hz += amp * nu.c;
+    }
+    V3<T> s{R.sx[idx], R.sy[idx], R.sz[idx]};
+    const V3<T> wv{R.gam * Hx, R.gam * Hy, R.gam * Hz};
+    s = llg_flow(s, wv, R.alpha, tau, R.inv1pa2);
+    R.sx[idx] = s.x;
+    R.sy[idx] = s.y;
+    R.sz[idx] = s.z;
+}
+
+// ------------------------------------------------------------ lattice
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kick_drift(const RunDev<T>* __restrict__ runs,
+                                                       const int2* __restrict__ work, int phase)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (phase == PHASE_STEP) {
+        if (!run_active(R, &step) || !R.live) return;
+    }
+    const int i = w.y + (int)threadIdx.x;
+    if (i >= R.n) return;
+    const Site s = decode_site(R.g, (uint32_t)i);
+    if (phase == PHASE_STEP) {
+        const int sp = species_of(R, i);
+        const T k = R.hdtm[sp];
+        T vx = R.vx[i] + k * R.fx[i];
+        T vy = R.vy[i] + k * R.fy[i];
+        T vz = R.vz[i] + k * R.fz[i];
+        T ux = R.ux[i] + R.dt * vx;
+        T uy = R.uy[i] + R.dt * vy;
+        T uz = R.uz[i] + R.dt * vz;
+        R.vx[i] = vx; R.vy[i] = vy; R.vz[i] = vz;
+        R.ux[i] = ux; R.uy[i] = uy; R.uz[i] = uz;
+        const T dx = ux - R.rx[i], dy = uy - R.ry[i], dz = uz - R.rz[i];
+        if (dx * dx + dy * dy + dz * dz > R.skin_half2) atomicOr(&R.st->rebuild, 1);
+    }
+    const V3<T> p = position(R, s, i);
+    R.cell[i] = (uint16_t)electron_cell(R, p);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict__ runs,
+                                                    const int2* __restrict__ work)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
+    const int i = w.y + (int)threadIdx.x;
+    if (i >= R.n) return;
+    const Site s = decode_site(R.g, (uint32_t)i);
+    int b3[3];
+    const int bin = bin_of(R, position(R, s, i), b3);
+    const int slot = atomicAdd(&R.bin_n[bin], 1);
+    if (slot < R.bin_cap)
+        R.bin_atoms[bin * R.bin_cap + slot] = i;
+    else
+        atomicOr(&R.st->err, ERR_BIN);
+}
+
+// Sort each bin's atom list so that the neighbour order does not depend on
+// the order in which atoms were binned.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict__ runs,
+                                                     const int2* __restrict__ work)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
+    const int bin = w.y + (int)threadIdx.x;
+    if (bin >= R.nbins) return;
+    int cnt = R.bin_n[bin];
+    cnt = cnt < R.bin_cap ? cnt : R.bin_cap;
+    int32_t* a = R.bin_atoms + (size_t)bin * R.bin_cap;
+    for (int p = 1; p < cnt; ++p) {
+        const int v = a[p];
+        int q = p - 1;
+        while (q >= 0 && a[q] > v) {
+            a[q + 1] = a[q];
+            --q;
+        }
+        a[q + 1] = v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restrict__ runs,
+                                                      const int2* __restrict__ work)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
+    const int i = w.y + (int)threadIdx.x;
+    if (i >= R.n) return;
+    const Site si = decode_site(R.g, (uint32_t)i);
+    const V3<T> ui{R.ux[i], R.uy[i], R.uz[i]};
+    int b3[3];
+    bin_of(R, position(R, si, i), b3);
+    int count = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int bz = wrapi(b3[2] + dz, R.nbin[2]);
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int by = wrapi(b3[1] + dy, R.nbin[1]);
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int bx = wrapi(b3[0] + dx, R.nbin[0]);
+                const int bin = (bz * R.nbin[1] + by) * R.nbin[0] + bx;
+                int cnt = R.bin_n[bin];
+                cnt = cnt < R.bin_cap ? cnt : R.bin_cap;
+                const int32_t* a = R.bin_atoms + (size_t)bin * R.bin_cap;
+                for (int q = 0; q < cnt; ++q) {
+                    const int j = a[q];
+                    if (j == i) continue;
+                    const V3<T> d = separation(R, si, ui, j);
+                    if (d.x * d.x + d.y * d.y + d.z * d.z < R.rlist2) {
+                        if (count < R.max_nbr) R.nbr[(size_t)count * R.n + i] = j;
+                        ++count;
+                    }
+                }
+            }
+        }
+    }
+    if (count > R.max_nbr) {
+        atomicOr(&R.st->err, ERR_NBR);
+        count = R.max_nbr;
+    }
+    R.nbr_n[i] = count;
+    R.rx[i] = ui.x;
+    R.ry[i] = ui.y;
+    R.rz[i] = ui.z;
+}
+
+// Fixed-order block reduction of NQ doubles (wave shuffles, then the waves
+// in order); thread q < NQ returns the block total of quantity q.
+__device__ inline void block_reduce_nq(double* v, double* lds /* [kBlock/64][NQ] */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) lds[wave * NQ + q] = x;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
+                                                       const int2* __restrict__ work, int phase)
+{
+    __shared__ double lds[(kBlock / 64) * NQ];
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step = R.st->step;
+    if (phase == PHASE_STEP) {
+        if (!run_active(R, &step)) return;
+    }
+    const bool obs = R.obs_every > 0 &&
+                     (phase == PHASE_INIT || ((step + 1) % R.obs_every) == 0);
+    if (!R.live && !obs) return;
+    const int i = w.y + (int)threadIdx.x;
+    const bool valid = i < R.n;
+    double q[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+    if (valid) {
+        const Site si = decode_site(R.g, (uint32_t)i);
+        const int sp = species_of(R, i);
+        if (R.live) {
+            const V3<T> ui{R.ux[i], R.uy[i], R.uz[i]};
+            T Fx = T(0), Fy = T(0), Fz = T(0);
+            double pe = 0.0;
+            const int nn = R.nbr_n[i];
+            for (int k = 0; k < nn; ++k) {
+                const int j = R.nbr[(size_t)k * R.n + i];
+                const V3<T> d = separation(R, si, ui, j);
+                const T r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+                if (r2 < R.rc2) {
+                    const T r = sqrt(r2);
+                    const T e1 = exp(-R.ma * (r - R.mr0));
+                    const T e2 = e1 * e1;
+                    // -dV/dr along +d pushes j; the force on i is its opposite
+                    const T f = T(2) * R.ma * R.mD * (e2 - e1) / r;
+                    Fx -= f * d.x;
+                    Fy -= f * d.y;
+                    Fz -= f * d.z;
+                    if (obs) pe += 0.5 * ((double)(R.mD * (e2 - T(2) * e1)) - (double)R.Vc);
+                }
+            }
+            T vx = R.vx[i], vy = R.vy[i], vz = R.vz[i];
+            if (phase == PHASE_STEP) {
+                const T k = R.hdtm[sp];
+                vx += k * Fx;
+                vy += k * Fy;
+                vz += k * Fz;
+                if (R.ttm_mode == 1) {
+                    const int c = R.cell[i];
+                    const double Te = R.Te[c];
+                    const int canon = ((si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
+                    const Normals3<T> eta =
+                        normals3<T>(R.seed, R.run_id, (uint32_t)canon, step, 1u);
+                    const T amp = R.ou_amp[sp] * (T)sqrt(Te);
+                    const T nx = R.ou_c1 * vx + amp * eta.a;
+                    const T ny = R.ou_c1 * vy + amp * eta.b;
+                    const T nz = R.ou_c1 * vz + amp * eta.c;
+                    const double ke_old = (double)vx * vx + (double)vy * vy + (double)vz * vz;
+                    const double ke_new = (double)nx * nx + (double)ny * ny + (double)nz * nz;
+                    const double dE = 0.5 * (double)R.m_e[sp] * (ke_new - ke_old);
+                    if (fabs(dE) < 1.0e3) {
+                        const long long fixp = llrint(dE * kFIX);
+                        atomicAdd(&R.dE[c], (unsigned long long)fixp);
+                    } else {
+                        atomicOr(&R.st->err, ERR_DE);
+                    }
+                    vx = nx;
+                    vy = ny;
+                    vz = nz;
+                }
+                R.vx[i] = vx;
+                R.vy[i] = vy;
+                R.vz[i] = vz;
+            }
+            R.fx[i] = Fx;
+            R.fy[i] = Fy;
+            R.fz[i] = Fz;
+            if (obs) {
+                q[14] = 0.5 * (double)R.m_e[sp] *
+                        ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+                q[15] = pe;
+            }
+        }
+        if (obs) {
+            const double s0 = R.sx[i], s1 = R.sy[i], s2 = R.sz[i];
+            const V3<T> h = exchange_sum(R, si.x, si.y, si.z, si.b, sp);
+            const double h0 = h.x, h1 = h.y, h2 = h.z;
+            q[12] = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
+            q[13] = -R.mumb[sp] * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
+            const double t0 = h0 + R.mumb[sp] * R.Bd[0];
+            const double t1 = h1 + R.mumb[sp] * R.Bd[1];
+            const double t2 = h2 + R.mumb[sp] * R.Bd[2];
+            const double c0 = s1 * t2 - s2 * t1, c1 = s2 * t0 - s0 * t2, c2 = s0 * t1 - s1 * t0;
+            const double num = c0 * c0 + c1 * c1 + c2 * c2;
+            const double den = s0 * t0 + s1 * t1 + s2 * t2;
+            // per-species slots with compile-time indices (kept in registers)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bool me = sp == t;
+                q[3 * t + 0] = me ? s0 : 0.0;
+                q[3 * t + 1] = me ? s1 : 0.0;
+                q[3 * t + 2] = me ? s2 : 0.0;
+                q[16 + t] = me ? num : 0.0;
+                q[20 + t] = me ? den : 0.0;
+            }
+        }
+    }
+    if (!obs) return;
+    block_reduce_nq(q, lds);
+    if (threadIdx.x < NQ) {
+        double tot = 0.0;
+        for (int wv = 0; wv < kBlock / 64; ++wv) tot += lds[wv * NQ + threadIdx.x];
+        R.partial[(size_t)(w.y / kBlock) * NQ + threadIdx.x] = tot;
+    }
+}
+
+// ------------------------------------------------------- electron grid
+template <typename T> __device__ inline double laser_power(const RunDev<T>& R, double zc, double t)
+{
+    if (R.S0 == 0.0 || R.fwhm <= 0.0) return 0.0;
+    if (R.profile == 1 && !(zc > (double)R.box[2] - R.depth)) return 0.0;
+    const double d = t - R.t0;
+    return R.S0 * exp(-4.0 * 0.69314718055994530942 * d * d / (R.fwhm * R.fwhm));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEndBlock) void k_end_step(const RunDev<T>* __restrict__ runs,
+                                                        const int* __restrict__ run_list,
+                                                        int phase)
+{
+    __shared__ double red[kEndBlock];
+    __shared__ double red2[kEndBlock];
+    __shared__ double tot[NQ];
+    const RunDev<T>& R = runs[run_list[blockIdx.x]];
+    RunState* st = R.st;
+    const int64_t step = st->step;
+    if (phase == PHASE_STEP && (st->err != 0 || step >= st->target)) return;
+    const int tid = threadIdx.x;
+    const int nc = R.ncell;
+    // two-temperature update of the electron energy density gamma_e T^2 / 2
+    if (phase == PHASE_STEP && R.ttm_mode == 1) {
+        const double ge = R.gamma_e;
+        for (int c = tid; c < nc; c += kEndBlock) {
+            const double T0 = R.Te[c];
+            R.ee[c] = 0.5 * ge * T0 * T0;
+        }
+        __syncthreads();
+        if (R.kappa_e != 0.0) {
+            const double dts = R.dtd / (double)R.n_sub;
+            const double ih0 = 1.0 / (R.th[0] * R.th[0]), ih1 = 1.0 / (R.th[1] * R.th[1]),
+                         ih2 = 1.0 / (R.th[2] * R.th[2]);
+            for (int sub = 0; sub < R.n_sub; ++sub) {
+                for (int c = tid; c < nc; c += kEndBlock) {
+                    const int i = c % R.tn[0];
+                    const int j = (c / R.tn[0]) % R.tn[1];
+                    const int k = c / (R.tn[0] * R.tn[1]);
+                    const int ip = (i + 1) % R.tn[0], im = (i + R.tn[0] - 1) % R.tn[0];
+                    const int jp = (j + 1) % R.tn[1], jm = (j + R.tn[1] - 1) % R.tn[1];
+                    const int kp = (k + 1) % R.tn[2], km = (k + R.tn[2] - 1) % R.tn[2];
+                    const int row = (k * R.tn[1] + j) * R.tn[0];
+                    const double Tc = R.Te[c];
+                    R.lap[c] = (R.Te[row + ip] - 2.0 * Tc + R.Te[row + im]) * ih0 +
+                               (R.Te[(k * R.tn[1] + jp) * R.tn[0] + i] - 2.0 * Tc +
+                                R.Te[(k * R.tn[1] + jm) * R.tn[0] + i]) * ih1 +
+                               (R.Te[(kp * R.tn[1] + j) * R.tn[0] + i] - 2.0 * Tc +
+                                R.Te[(km * R.tn[1] + j) * R.tn[0] + i]) * ih2;
+                }
+                __syncthreads();
+                for (int c = tid; c < nc; c += kEndBlock) {
+                    const double e = R.ee[c] + dts * R.kappa_e * R.lap[c];
+                    R.ee[c] = e;
+                    if (e < 0.0) atomicOr(&st->err, ERR_NEG_E);
+                    R.Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
+                }
+                __syncthreads();
+            }
+        }
+        const double tmid = ((double)step + 0.5) * R.dtd;
+        for (int c = tid; c < nc; c += kEndBlock) {
+            const int k = c / (R.tn[0] * R.tn[1]);
+            const double src = laser_power(R, (k + 0.5) * R.th[2], tmid);
+            const double de = (double)(long long)R.dE[c] / kFIX;
+            R.dE[c] = 0ull;
+            const double e = R.ee[c] + R.dtd * src - de / R.Vcell;
+            R.ee[c] = e;
+            if (e < 0.0) atomicOr(&st->err, ERR_NEG_E);
+            R.Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
+        }
+        __syncthreads();
+    }
+    const bool obs = R.obs_every > 0 &&
+                     (phase == PHASE_INIT || ((step + 1) % R.obs_every) == 0);
+    if (obs) {
+        if (tid < NQ) {
+            double acc = 0.0;
+            for (int bk = 0; bk < R.n_part; ++bk) acc += R.partial[(size_t)bk * NQ + tid];
+            tot[tid] = acc;
+        }
+        double eacc = 0.0, tacc = 0.0, tmax = 0.0;
+        for (int c = tid; c < nc; c += kEndBlock) {
+            const double Tc = R.Te[c];
+            eacc += 0.5 * R.gamma_e * Tc * Tc * R.Vcell;
+            tacc += Tc;
+            tmax = Tc > tmax ? Tc : tmax;
+        }
+        red[tid] = eacc;
+        red2[tid] = tacc;
+        __syncthreads();
+        for (int off = kEndBlock / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                red[tid] += red[tid + off];
+                red2[tid] += red2[tid + off];
+            }
+            __syncthreads();
+        }
+        const double E_e = red[0], Tsum = red2[0];
+        __syncthreads();
+        red[tid] = tmax;
+        __syncthreads();
+        for (int off = kEndBlock / 2; off > 0; off >>= 1) {
+            if (tid < off) red[tid] = red[tid] > red[tid + off] ? red[tid] : red[tid + off];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int64_t sample_step = phase == PHASE_INIT ? step : step + 1;
+            const int64_t ns = st->n_samples;
+            sl_obs* o = &R.ring[ns % R.obs_cap];
+            o->t = (double)sample_step * R.dtd;
+            o->step = sample_step;
+            double m[3] = {0.0, 0.0, 0.0};
+            for (int sp = 0; sp < 4; ++sp)
+                for (int k = 0; k < 3; ++k) {
+                    m[k] += tot[3 * sp + k];
+                    o->M[sp][k] = R.cnt[sp] > 0.0 ? tot[3 * sp + k] / R.cnt[sp] : 0.0;
+                }
+            for (int k = 0; k < 3; ++k) o->m[k] = m[k] / (double)R.n;
+            o->m_abs = sqrt(o->m[0] * o->m[0] + o->m[1] * o->m[1] + o->m[2] * o->m[2]);
+            o->E_ex = tot[12];
+            o->E_z = tot[13];
+            o->KE = tot[14];
+            o->PE = tot[15];
+            o->E_e = E_e;
+            o->Te_mean = Tsum / (double)nc;
+            o->Te_max = red[0];
+            o->Tl = 2.0 * tot[14] / (3.0 * (double)R.n * kKB);
+            for (int sp = 0; sp < 4; ++sp)
+                o->Tspin[sp] = tot[20 + sp] != 0.0 ? tot[16 + sp] / (2.0 * kKB * tot[20 + sp]) : 0.0;
+            st->n_samples = ns + 1;
+        }
+    }
+    // neighbour bins are emptied after a rebuild
+    if (R.live && st->rebuild != 0) {
+        for (int b = tid; b < R.nbins; b += kEndBlock) R.bin_n[b] = 0;
+        __syncthreads();
+        if (tid == 0) st->rebuild = 0;
+    }
+    if (tid == 0 && phase == PHASE_STEP) st->step = step + 1;
+}
+
+}  // namespace sl

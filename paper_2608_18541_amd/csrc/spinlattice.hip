@@ -1,0 +1,1111 @@
+// spinlattice.hip -- host runtime and C ABI of the gfx950 spin-lattice step.
+//
+// An engine owns up to max_runs independent runs of one precision.  Each run
+// lives in its own device allocation (spins, displacements, velocities,
+// forces, neighbour tables, electron grid, observable ring); a device table
+// of run descriptors plus block->(run, offset) work tables let every kernel
+// launch cover all active runs.  A single system is an engine with one run.
+// Steps are replayed from a captured HIP graph of graph_steps steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/spinlattice.h"
+#include "sl_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+sl_status fail(sl_status code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define SL_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(SL_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// ------------------------------------------------------------ allocation
+struct DevAlloc {
+    sl_allocator a{};
+    bool custom = false;
+    void* get(size_t bytes)
+    {
+        if (bytes == 0) bytes = 256;
+        if (custom) return a.alloc(a.ctx, bytes);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(void* p)
+    {
+        if (!p) return;
+        if (custom)
+            a.free(a.ctx, p);
+        else
+            (void)hipFree(p);
+    }
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Carves typed sub-arrays out of one allocation.
+struct Carver {
+    size_t off = 0;
+    char* base = nullptr;
+    template <typename U> U* take(size_t count)
+    {
+        size_t o = off;
+        off += align256(count * sizeof(U));
+        return base ? reinterpret_cast<U*>(base + o) : nullptr;
+    }
+};
+
+// ------------------------------------------------------------ validation
+std::string validate_desc(const sl_system_desc* d)
+{
+    if (!d) return "null description";
+    if (d->lattice != SL_LATTICE_SC && d->lattice != SL_LATTICE_BCC) return "lattice must be 0 (sc) or 1 (bcc)";
+    for (int k = 0; k < 3; ++k)
+        if (d->ncell[k] < 2 || (d->ncell[k] & 1)) return "every ncell must be even and >= 2";
+    const int64_t nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
+    const int64_t n = nb * (int64_t)d->ncell[0] * d->ncell[1] * d->ncell[2];
+    if (n > (1ll << 30)) return "too many sites";
+    if (d->ncell[0] > 1024 || d->ncell[1] > 1024 || d->ncell[2] > 1024) return "ncell above 1024";
+    if (!(d->a > 0.0)) return "lattice constant must be positive";
+    if (d->n_species < 1 || d->n_species > 4) return "n_species must be 1..4";
+    for (int s = 0; s < d->n_species; ++s) {
+        if (!(d->mu[s] > 0.0)) return "every moment must be positive";
+        if (d->lattice_mode == 1 && !(d->mass[s] > 0.0)) return "every mass must be positive";
+    }
+    if (d->lattice == SL_LATTICE_SC && d->n_shells != 1) return "sc supports one exchange shell";
+    if (d->lattice == SL_LATTICE_BCC && (d->n_shells < 1 || d->n_shells > 2)) return "bcc supports one or two shells";
+    if (!(d->alpha >= 0.0)) return "alpha must be >= 0";
+    if (d->noise_mode != 0 && d->noise_mode != 1) return "noise_mode must be 0 or 1";
+    if (d->noise_mode == 1 && !(d->mu_ref > 0.0)) return "noise_mode 1 needs mu_ref > 0";
+    if (!(d->dt > 0.0)) return "dt must be positive";
+    if (d->precision != SL_FP64 && d->precision != SL_FP32) return "precision must be 0 or 1";
+    if (d->obs_every < 0) return "obs_every must be >= 0";
+    if (d->obs_every > 0 && d->obs_capacity < 1) return "obs_capacity must be >= 1";
+    if (!d->spin0) return "spin0 is required";
+    if (d->species)
+        for (int64_t i = 0; i < n; ++i)
+            if (d->species[i] < 0 || d->species[i] >= d->n_species) return "species out of range";
+    for (int64_t i = 0; i < n; ++i) {
+        const double* s = d->spin0 + 3 * i;
+        double nn = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        if (!(std::fabs(nn - 1.0) <= 1e-6)) return "initial spins must be unit vectors";
+    }
+    if (d->lattice_mode != 0 && d->lattice_mode != 1) return "lattice_mode must be 0 or 1";
+    if (d->lattice_mode == 1) {
+        if (!(d->morse[3] > 0.0) || !(d->skin > 0.0)) return "Morse cutoff and skin must be positive";
+        const double reach = d->morse[3] + d->skin;
+        for (int k = 0; k < 3; ++k)
+            if (d->ncell[k] * d->a < 3.0 * reach) return "box must be at least 3 (rc + skin) along every axis";
+    }
+    return "";
+}
+
+std::string validate_ttm(const sl_ttm_desc* t, const sl_system_desc* d)
+{
+    if (!t) return "null grid";
+    int64_t nc = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (t->n[k] < 1) return "grid cells must be >= 1";
+        nc *= t->n[k];
+    }
+    if (nc > 65535) return "at most 65535 electron cells";
+    if (t->mode != 0 && t->mode != 1) return "grid mode must be 0 or 1";
+    double tmin = t->Te0;
+    if (t->Te_init) {
+        tmin = t->Te_init[0];
+        for (int64_t c = 0; c < nc; ++c) {
+            if (!(t->Te_init[c] >= 0.0)) return "temperatures must be >= 0";
+            tmin = std::min(tmin, t->Te_init[c]);
+        }
+    } else if (!(t->Te0 >= 0.0)) {
+        return "temperatures must be >= 0";
+    }
+    if (t->mode == 1) {
+        if (!(t->gamma_e > 0.0)) return "gamma_e must be positive in two-temperature mode";
+        if (t->n_sub < 1) return "n_sub must be >= 1";
+        if (!(t->G_el >= 0.0) || !(t->kappa_e >= 0.0)) return "G_el and kappa_e must be >= 0";
+        if (t->kappa_e > 0.0) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double h = d->ncell[k] * d->a / t->n[k];
+                s += 2.0 / (h * h);
+            }
+            if (t->kappa_e * (d->dt / t->n_sub) * s > t->gamma_e * tmin)
+                return "explicit electron diffusion unstable: raise n_sub";
+        }
+        if (t->profile != 0 && t->profile != 1) return "profile must be 0 or 1";
+    }
+    return "";
+}
+
+sl_ttm_desc default_ttm()
+{
+    sl_ttm_desc t{};
+    t.n[0] = t.n[1] = t.n[2] = 1;
+    t.mode = 0;
+    t.Te0 = 0.0;
+    t.n_sub = 1;
+    return t;
+}
+
+// ------------------------------------------------------------ run sizing
+struct Sizes {
+    int64_t n;
+    int nbx[3], nbins, bin_cap, max_nbr, ncell, n_part;
+};
+
+Sizes run_sizes(const sl_system_desc* d, const sl_ttm_desc* t)
+{
+    Sizes z{};
+    const int nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
+    z.n = (int64_t)nb * d->ncell[0] * d->ncell[1] * d->ncell[2];
+    z.ncell = t->n[0] * t->n[1] * t->n[2];
+    z.n_part = (int)((z.n + sl::kBlock - 1) / sl::kBlock);
+    if (d->lattice_mode == 1) {
+        const double reach = d->morse[3] + d->skin;
+        const double vol_site = std::pow(d->a, 3) / nb;
+        double w3 = 1.0;
+        z.nbins = 1;
+        for (int k = 0; k < 3; ++k) {
+            const double L = d->ncell[k] * d->a;
+            z.nbx[k] = std::max(3, (int)std::floor(L / reach));
+            w3 *= L / z.nbx[k];
+            z.nbins *= z.nbx[k];
+        }
+        z.bin_cap = std::max(16, (int)std::ceil(3.0 * w3 / vol_site) + 8);
+        const double sphere = 4.18879020478639 * reach * reach * reach / vol_site;
+        z.max_nbr = (int)std::ceil(1.8 * sphere + 8.0);
+    }
+    return z;
+}
+
+template <typename T> size_t main_bytes(const sl_system_desc* d, const Sizes& z)
+{
+    Carver c;
+    const size_t n = (size_t)z.n;
+    const bool live = d->lattice_mode == 1;
+    c.take<T>(n); c.take<T>(n); c.take<T>(n);                       // spins
+    c.take<T>(n); c.take<T>(n); c.take<T>(n);                       // displacements
+    if (live) {
+        for (int k = 0; k < 9; ++k) c.take<T>(n);                   // v, F, reference u
+        c.take<int32_t>(n * (size_t)z.max_nbr);
+        c.take<int32_t>(n);
+        c.take<int32_t>((size_t)z.nbins);
+        c.take<int32_t>((size_t)z.nbins * z.bin_cap);
+    }
+    c.take<int8_t>(n);
+    c.take<uint16_t>(n);
+    c.take<double>((size_t)z.n_part * sl::NQ);
+    c.take<sl_obs>((size_t)std::max(1, d->obs_capacity));
+    c.take<sl::RunState>(1);
+    return c.off;
+}
+
+size_t grid_bytes(const Sizes& z)
+{
+    Carver c;
+    c.take<double>(z.ncell); c.take<double>(z.ncell); c.take<double>(z.ncell);
+    c.take<unsigned long long>(z.ncell);
+    return c.off;
+}
+
+// ------------------------------------------------------------ engine
+struct Run {
+    bool used = false;
+    sl_system_desc d{};
+    sl_ttm_desc t{};
+    Sizes z{};
+    int64_t steps = 0;          // host view of completed steps
+    int64_t target = 0;
+    int64_t samples_read = 0;
+    void* main = nullptr;
+    void* grid = nullptr;
+    size_t footprint = 0;
+    std::vector<int32_t> canon;  // canonical index of each internal site
+    std::vector<double> te_init;
+};
+
+class Engine {
+public:
+    virtual ~Engine() = default;
+    virtual sl_status add(const sl_system_desc* d, const sl_ttm_desc* t, int64_t target, int* slot) = 0;
+    virtual sl_status set_grid(int slot, const sl_ttm_desc* t) = 0;
+    virtual sl_status advance(int64_t n) = 0;
+    virtual sl_status get(int slot, double* x, double* v, double* s, double* Te, sl_obs* obs,
+                          int64_t max_samples, int64_t* n_obs) = 0;
+    virtual sl_status remove(int slot) = 0;
+    virtual sl_status sync() = 0;
+    virtual sl_status profiled(int64_t n, double avg[4], int64_t cnt[4]) = 0;
+    std::vector<Run> runs;
+    DevAlloc alloc;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    size_t budget = 0, used_bytes = 0;
+    int graph_steps = 16;
+    int precision = SL_FP64;
+};
+
+template <typename T> class EngineT final : public Engine {
+public:
+    using RD = sl::RunDev<T>;
+
+    EngineT(int max_runs) { runs.resize(max_runs); host_rd.resize(max_runs); }
+
+    ~EngineT() override
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        drop_graph();
+        for (size_t s = 0; s < runs.size(); ++s) release(s);
+        for (void* p : tables) alloc.put(p);
+        alloc.put(d_runs);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    sl_status init_device()
+    {
+        d_runs = static_cast<RD*>(alloc.get(sizeof(RD) * runs.size()));
+        if (!d_runs) return fail(SL_ENOMEM, "device allocation of the run table failed");
+        SL_HIP(hipMemset(d_runs, 0, sizeof(RD) * runs.size()));
+        SL_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        return SL_OK;
+    }
+
+    // --------------------------------------------------------- add a run
+    sl_status add(const sl_system_desc* d, const sl_ttm_desc* t, int64_t target, int* slot) override
+    {
+        std::string e = validate_desc(d);
+        if (!e.empty()) return fail(SL_EINVAL, e);
+        e = validate_ttm(t, d);
+        if (!e.empty()) return fail(SL_EINVAL, e);
+        int s = -1;
+        for (size_t k = 0; k < runs.size(); ++k)
+            if (!runs[k].used) { s = (int)k; break; }
+        if (s < 0) return fail(SL_EBUSY, "no free slot");
+        Sizes z = run_sizes(d, t);
+        const size_t fp = main_bytes<T>(d, z) + grid_bytes(z);
+        if (budget && used_bytes + fp > budget) return fail(SL_ENOMEM, "run does not fit the memory budget");
+        Run& r = runs[s];
+        r = Run{};
+        r.d = *d;
+        r.t = *t;
+        r.z = z;
+        r.target = target;
+        r.main = alloc.get(main_bytes<T>(d, z));
+        r.grid = alloc.get(grid_bytes(z));
+        if (!r.main || !r.grid) {
+            alloc.put(r.main);
+            alloc.put(r.grid);
+            r = Run{};
+            return fail(SL_ENOMEM, "device allocation failed");
+        }
+        r.used = true;
+        r.footprint = fp;
+        used_bytes += fp;
+        sl_status st = upload(s, d, t, target);
+        if (st != SL_OK) {
+            release(s);
+            return st;
+        }
+        *slot = s;
+        return SL_OK;
+    }
+
+    sl_status set_grid(int s, const sl_ttm_desc* t) override
+    {
+        Run& r = runs[s];
+        std::string e = validate_ttm(t, &r.d);
+        if (!e.empty()) return fail(SL_EINVAL, e);
+        if (r.steps != 0) return fail(SL_EINVAL, "the grid can only be set before the first step");
+        SL_HIP(hipStreamSynchronize(stream));
+        Sizes z = run_sizes(&r.d, t);
+        void* g = alloc.get(grid_bytes(z));
+        if (!g) return fail(SL_ENOMEM, "device allocation failed");
+        alloc.put(r.grid);
+        used_bytes -= r.footprint;
+        r.grid = g;
+        r.t = *t;
+        r.z.ncell = z.ncell;
+        r.footprint = main_bytes<T>(&r.d, r.z) + grid_bytes(r.z);
+        used_bytes += r.footprint;
+        fill_grid(s);
+        sl::RunState rs{};
+        rs.target = r.target;
+        rs.rebuild = host_rd[s].live ? 1 : 0;
+        SL_HIP(hipMemcpyAsync(host_rd[s].st, &rs, sizeof(rs), hipMemcpyHostToDevice, stream));
+        if (host_rd[s].live)
+            SL_HIP(hipMemsetAsync(host_rd[s].bin_n, 0, sizeof(int32_t) * host_rd[s].nbins, stream));
+        r.samples_read = 0;
+        return commit_and_init(s);
+    }
+
+    // --------------------------------------------------------- stepping
+    sl_status advance(int64_t n) override
+    {
+        if (n < 0) return fail(SL_EINVAL, "negative step count");
+        if (n == 0) return SL_OK;
+        if (active_blocks_atom == 0) return SL_OK;
+        int64_t left = n;
+        if (graph_steps > 1 && left >= graph_steps) {
+            if (!graph_ok) {
+                sl_status st = capture();
+                if (st != SL_OK) return st;
+            }
+            while (left >= graph_steps) {
+                SL_HIP(hipGraphLaunch(exec, stream));
+                left -= graph_steps;
+            }
+        }
+        for (int64_t k = 0; k < left; ++k) enqueue_step(stream, nullptr);
+        SL_HIP(hipGetLastError());
+        for (auto& r : runs)
+            if (r.used) r.steps = std::min(r.target, r.steps + n);
+        return SL_OK;
+    }
+
+    sl_status profiled(int64_t n, double avg[4], int64_t cnt[4]) override
+    {
+        std::vector<hipEvent_t> ev;
+        std::vector<int> cls;
+        Prof p{&ev, &cls};
+        for (int64_t k = 0; k < n; ++k) {
+            sl_status st = enqueue_step(stream, &p);
+            if (st != SL_OK) return st;
+        }
+        SL_HIP(hipStreamSynchronize(stream));
+        double tot[4] = {0, 0, 0, 0};
+        int64_t c[4] = {0, 0, 0, 0};
+        for (size_t k = 0; k + 1 < ev.size(); k += 2) {
+            float ms = 0.f;
+            SL_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            tot[cls[k / 2]] += ms;
+            c[cls[k / 2]] += 1;
+        }
+        for (auto e : ev) (void)hipEventDestroy(e);
+        for (int k = 0; k < 4; ++k) {
+            avg[k] = c[k] ? tot[k] / c[k] : 0.0;
+            cnt[k] = c[k];
+        }
+        for (auto& r : runs)
+            if (r.used) r.steps = std::min(r.target, r.steps + n);
+        return SL_OK;
+    }
+
+    sl_status sync() override
+    {
+        SL_HIP(hipStreamSynchronize(stream));
+        for (size_t s = 0; s < runs.size(); ++s) {
+            if (!runs[s].used) continue;
+            sl::RunState rs;
+            SL_HIP(hipMemcpy(&rs, host_rd[s].st, sizeof(rs), hipMemcpyDeviceToHost));
+            if (rs.err) return numeric_error((int)s, rs.err);
+        }
+        return SL_OK;
+    }
+
+    sl_status get(int s, double* x, double* v, double* sp, double* Te, sl_obs* obs,
+                  int64_t max_samples, int64_t* n_obs) override
+    {
+        if (s < 0 || s >= (int)runs.size() || !runs[s].used) return fail(SL_EINVAL, "bad slot");
+        SL_HIP(hipStreamSynchronize(stream));
+        Run& r = runs[s];
+        const RD& R = host_rd[s];
+        const size_t n = (size_t)r.z.n;
+        std::vector<T> buf(3 * n);
+        auto fetch3 = [&](T* a, T* b, T* c) -> sl_status {
+            SL_HIP(hipMemcpy(buf.data(), a, n * sizeof(T), hipMemcpyDeviceToHost));
+            SL_HIP(hipMemcpy(buf.data() + n, b, n * sizeof(T), hipMemcpyDeviceToHost));
+            SL_HIP(hipMemcpy(buf.data() + 2 * n, c, n * sizeof(T), hipMemcpyDeviceToHost));
+            return SL_OK;
+        };
+        sl_status st;
+        if (sp) {
+            if ((st = fetch3(R.sx, R.sy, R.sz)) != SL_OK) return st;
+            for (size_t i = 0; i < n; ++i)
+                for (int k = 0; k < 3; ++k) sp[3 * (size_t)r.canon[i] + k] = (double)buf[k * n + i];
+        }
+        if (x) {
+            if ((st = fetch3(R.ux, R.uy, R.uz)) != SL_OK) return st;
+            for (size_t i = 0; i < n; ++i) {
+                sl::Site site = sl::decode_site(R.g, (uint32_t)i);
+                const double off = 0.25 + 0.5 * site.b;
+                const double r0[3] = {(site.x + off) * r.d.a, (site.y + off) * r.d.a,
+                                      (site.z + off) * r.d.a};
+                for (int k = 0; k < 3; ++k) {
+                    const double L = r.d.ncell[k] * r.d.a;
+                    double p = r0[k] + (double)buf[k * n + i];
+                    p -= L * std::floor(p / L);
+                    x[3 * (size_t)r.canon[i] + k] = p;
+                }
+            }
+        }
+        if (v) {
+            if (r.d.lattice_mode == 1) {
+                if ((st = fetch3(R.vx, R.vy, R.vz)) != SL_OK) return st;
+                for (size_t i = 0; i < n; ++i)
+                    for (int k = 0; k < 3; ++k) v[3 * (size_t)r.canon[i] + k] = (double)buf[k * n + i];
+            } else {
+                std::memset(v, 0, sizeof(double) * 3 * n);
+            }
+        }
+        if (Te) SL_HIP(hipMemcpy(Te, R.Te, sizeof(double) * r.z.ncell, hipMemcpyDeviceToHost));
+        sl::RunState rs;
+        SL_HIP(hipMemcpy(&rs, R.st, sizeof(rs), hipMemcpyDeviceToHost));
+        if (obs && n_obs) {
+            *n_obs = 0;
+            const int cap = std::max(1, r.d.obs_capacity);
+            int64_t first = std::max(r.samples_read, rs.n_samples - cap);
+            int64_t cntv = std::min<int64_t>(max_samples, rs.n_samples - first);
+            for (int64_t k = 0; k < cntv; ++k) {
+                SL_HIP(hipMemcpy(obs + k, R.ring + ((first + k) % cap), sizeof(sl_obs),
+                                 hipMemcpyDeviceToHost));
+            }
+            r.samples_read = first + cntv;
+            *n_obs = cntv;
+        }
+        if (rs.err) return numeric_error(s, rs.err);
+        return SL_OK;
+    }
+
+    sl_status remove(int s) override
+    {
+        if (s < 0 || s >= (int)runs.size() || !runs[s].used) return fail(SL_EINVAL, "bad slot");
+        SL_HIP(hipStreamSynchronize(stream));
+        release(s);
+        return rebuild_tables();
+    }
+
+    sl_status n_samples(int s, int64_t* out)
+    {
+        sl::RunState rs;
+        SL_HIP(hipMemcpy(&rs, host_rd[s].st, sizeof(rs), hipMemcpyDeviceToHost));
+        *out = rs.n_samples;
+        return SL_OK;
+    }
+
+private:
+    struct Prof {
+        std::vector<hipEvent_t>* ev;
+        std::vector<int>* cls;
+    };
+
+    std::vector<RD> host_rd;
+    RD* d_runs = nullptr;
+    std::vector<void*> tables;
+    int2* d_work_spin = nullptr;
+    int2* d_work_atom = nullptr;
+    int2* d_work_bin = nullptr;
+    int* d_run_list = nullptr;
+    int active_blocks_spin = 0, active_blocks_atom = 0, active_blocks_bin = 0, active_runs = 0;
+    bool any_live = false;
+    hipGraphExec_t exec = nullptr;
+    bool graph_ok = false;
+
+    sl_status numeric_error(int s, int err)
+    {
+        std::string m = "run in slot " + std::to_string(s) + " stopped:";
+        if (err & sl::ERR_NEG_E) m += " negative electron energy density;";
+        if (err & sl::ERR_BIN) m += " neighbour bin overflow;";
+        if (err & sl::ERR_NBR) m += " neighbour list overflow;";
+        if (err & sl::ERR_DE) m += " electron-phonon energy out of range;";
+        return fail(SL_ENUMERIC, m);
+    }
+
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        graph_ok = false;
+    }
+
+    void release(size_t s)
+    {
+        Run& r = runs[s];
+        if (!r.used) return;
+        alloc.put(r.main);
+        alloc.put(r.grid);
+        used_bytes -= r.footprint;
+        r = Run{};
+        host_rd[s] = RD{};
+    }
+
+    // Fills the host descriptor of slot s (device pointers into its blocks).
+    void fill_main(int s)
+    {
+        Run& r = runs[s];
+        const sl_system_desc* d = &r.d;
+        RD R{};
+        const int nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
+        R.g.Lx = d->ncell[0];
+        R.g.Ly = d->ncell[1];
+        R.g.Lz = d->ncell[2];
+        R.g.Lxh = d->ncell[0] / 2;
+        R.g.H = d->ncell[0] * d->ncell[1] * d->ncell[2] / 2;
+        R.g.nb = nb;
+        R.g.C = 2 * nb;
+        R.g.divH = sl::make_fastdiv((uint32_t)R.g.H);
+        R.g.divLxh = sl::make_fastdiv((uint32_t)R.g.Lxh);
+        R.g.divLy = sl::make_fastdiv((uint32_t)R.g.Ly);
+        R.lattice = d->lattice;
+        R.n = (int32_t)r.z.n;
+        R.n_species = d->n_species;
+        R.n_shells = d->n_shells;
+        R.live = d->lattice_mode;
+        R.obs_every = d->obs_every;
+        R.obs_cap = std::max(1, d->obs_capacity);
+        R.seed = d->seed;
+        R.run_id = d->run_id;
+        R.a = (T)d->a;
+        for (int k = 0; k < 3; ++k) {
+            R.box[k] = (T)(d->ncell[k] * d->a);
+            R.half_box[k] = (T)(0.5 * d->ncell[k] * d->a);
+            R.B[k] = (T)d->B[k];
+            R.Bd[k] = d->B[k];
+        }
+        R.alpha = (T)d->alpha;
+        R.dt = (T)d->dt;
+        R.tau_half = (T)(0.5 * d->dt);
+        R.inv1pa2 = (T)(1.0 / (1.0 + d->alpha * d->alpha));
+        R.gam = (T)sl::kGAMMA;
+        std::vector<double> cnt(4, 0.0);
+        if (d->species)
+            for (int64_t i = 0; i < r.z.n; ++i) cnt[d->species[i]] += 1.0;
+        else
+            cnt[0] = (double)r.z.n;
+        for (int sp = 0; sp < 4; ++sp) {
+            const double mu = sp < d->n_species ? d->mu[sp] : 1.0;
+            const double m = sp < d->n_species && d->mass[sp] > 0 ? d->mass[sp] : 1.0;
+            R.inv_mumb[sp] = (T)(1.0 / (mu * sl::kMUB));
+            R.mumb[sp] = mu * sl::kMUB;
+            double sig = std::sqrt(2.0 * d->alpha * sl::kKB / (sl::kGAMMA * mu * sl::kMUB * d->dt));
+            if (d->noise_mode == 1) sig *= std::sqrt(d->mu_ref / mu);
+            R.sig[sp] = (T)sig;
+            R.hdtm[sp] = (T)(0.5 * d->dt / (m * sl::kMVV2E));
+            R.m_e[sp] = (T)(m * sl::kMVV2E);
+            R.cnt[sp] = cnt[sp];
+        }
+        for (int sh = 0; sh < 2; ++sh)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) R.J[sh][a][b] = (T)d->J[sh][a][b];
+        R.mD = (T)d->morse[0];
+        R.ma = (T)d->morse[1];
+        R.mr0 = (T)d->morse[2];
+        R.rc2 = (T)(d->morse[3] * d->morse[3]);
+        R.Vc = (T)(d->morse[0] * (std::exp(-2.0 * d->morse[1] * (d->morse[3] - d->morse[2])) -
+                                  2.0 * std::exp(-d->morse[1] * (d->morse[3] - d->morse[2]))));
+        R.skin_half2 = (T)(0.25 * d->skin * d->skin);
+        R.rlist2 = (T)((d->morse[3] + d->skin) * (d->morse[3] + d->skin));
+        // carve the run block
+        Carver c;
+        c.base = static_cast<char*>(r.main);
+        const size_t n = (size_t)r.z.n;
+        R.sx = c.take<T>(n); R.sy = c.take<T>(n); R.sz = c.take<T>(n);
+        R.ux = c.take<T>(n); R.uy = c.take<T>(n); R.uz = c.take<T>(n);
+        if (R.live) {
+            R.vx = c.take<T>(n); R.vy = c.take<T>(n); R.vz = c.take<T>(n);
+            R.fx = c.take<T>(n); R.fy = c.take<T>(n); R.fz = c.take<T>(n);
+            R.rx = c.take<T>(n); R.ry = c.take<T>(n); R.rz = c.take<T>(n);
+            R.max_nbr = r.z.max_nbr;
+            R.nbr = c.take<int32_t>(n * (size_t)r.z.max_nbr);
+            R.nbr_n = c.take<int32_t>(n);
+            R.nbins = r.z.nbins;
+            R.bin_cap = r.z.bin_cap;
+            for (int k = 0; k < 3; ++k) {
+                R.nbin[k] = r.z.nbx[k];
+                R.binw[k] = (T)(d->ncell[k] * d->a / r.z.nbx[k]);
+            }
+            R.bin_n = c.take<int32_t>((size_t)r.z.nbins);
+            R.bin_atoms = c.take<int32_t>((size_t)r.z.nbins * r.z.bin_cap);
+        }
+        R.species = c.take<int8_t>(n);
+        R.cell = c.take<uint16_t>(n);
+        R.n_part = r.z.n_part;
+        R.partial = c.take<double>((size_t)r.z.n_part * sl::NQ);
+        R.ring = c.take<sl_obs>((size_t)R.obs_cap);
+        R.st = c.take<sl::RunState>(1);
+        host_rd[s] = R;
+    }
+
+    void fill_grid(int s)
+    {
+        Run& r = runs[s];
+        RD& R = host_rd[s];
+        const sl_ttm_desc* t = &r.t;
+        const sl_system_desc* d = &r.d;
+        R.ttm_mode = t->mode;
+        for (int k = 0; k < 3; ++k) {
+            R.tn[k] = t->n[k];
+            R.th[k] = d->ncell[k] * d->a / t->n[k];
+        }
+        R.ncell = r.z.ncell;
+        R.n_sub = std::max(1, t->n_sub);
+        R.gamma_e = t->gamma_e;
+        R.kappa_e = t->kappa_e;
+        R.S0 = t->S0;
+        R.t0 = t->t0;
+        R.fwhm = t->fwhm;
+        R.profile = t->profile;
+        R.depth = t->depth;
+        R.Vcell = R.th[0] * R.th[1] * R.th[2];
+        R.dtd = d->dt;
+        // electron-phonon Ornstein-Uhlenbeck coefficients
+        const double vol = (double)d->ncell[0] * d->ncell[1] * d->ncell[2] * std::pow(d->a, 3);
+        const double Gamma = t->mode == 1 ? t->G_el / (3.0 * ((double)r.z.n / vol) * sl::kKB) : 0.0;
+        const double c1 = std::exp(-Gamma * d->dt);
+        R.ou_c1 = (T)c1;
+        for (int sp = 0; sp < 4; ++sp) {
+            const double m = sp < d->n_species && d->mass[sp] > 0 ? d->mass[sp] : 1.0;
+            R.ou_amp[sp] = (T)std::sqrt((1.0 - c1 * c1) * sl::kKB / (m * sl::kMVV2E));
+        }
+        Carver c;
+        c.base = static_cast<char*>(r.grid);
+        R.Te = c.take<double>(r.z.ncell);
+        R.ee = c.take<double>(r.z.ncell);
+        R.lap = c.take<double>(r.z.ncell);
+        R.dE = c.take<unsigned long long>(r.z.ncell);
+        std::vector<double> te(r.z.ncell, t->Te0);
+        if (t->Te_init) std::copy(t->Te_init, t->Te_init + r.z.ncell, te.begin());
+        r.te_init = te;
+        r.t.Te_init = nullptr;
+    }
+
+    sl_status upload(int s, const sl_system_desc* d, const sl_ttm_desc* t, int64_t target)
+    {
+        Run& r = runs[s];
+        r.d.species = nullptr;
+        r.d.spin0 = r.d.vel0 = r.d.disp0 = nullptr;
+        r.d.stream = nullptr;
+        r.d.alloc = nullptr;
+        // species counts need the caller's array: fill with it, then drop it
+        r.d.species = d->species;
+        fill_main(s);
+        r.d.species = nullptr;
+        fill_grid(s);
+        RD& R = host_rd[s];
+        const size_t n = (size_t)r.z.n;
+        r.canon.resize(n);
+        for (size_t i = 0; i < n; ++i) {
+            sl::Site site = sl::decode_site(R.g, (uint32_t)i);
+            r.canon[i] = sl::canonical_of(R.g, site);
+        }
+        std::vector<T> a(n), b(n), c(n);
+        auto put3 = [&](const double* src, T* dx, T* dy, T* dz) -> sl_status {
+            for (size_t i = 0; i < n; ++i) {
+                const size_t ci = (size_t)r.canon[i];
+                a[i] = src ? (T)src[3 * ci + 0] : T(0);
+                b[i] = src ? (T)src[3 * ci + 1] : T(0);
+                c[i] = src ? (T)src[3 * ci + 2] : T(0);
+            }
+            SL_HIP(hipMemcpyAsync(dx, a.data(), n * sizeof(T), hipMemcpyHostToDevice, stream));
+            SL_HIP(hipMemcpyAsync(dy, b.data(), n * sizeof(T), hipMemcpyHostToDevice, stream));
+            SL_HIP(hipMemcpyAsync(dz, c.data(), n * sizeof(T), hipMemcpyHostToDevice, stream));
+            SL_HIP(hipStreamSynchronize(stream));
+            return SL_OK;
+        };
+        sl_status st;
+        if ((st = put3(d->spin0, R.sx, R.sy, R.sz)) != SL_OK) return st;
+        if ((st = put3(d->disp0, R.ux, R.uy, R.uz)) != SL_OK) return st;
+        if (R.live) {
+            if ((st = put3(d->vel0, R.vx, R.vy, R.vz)) != SL_OK) return st;
+            if ((st = put3(nullptr, R.fx, R.fy, R.fz)) != SL_OK) return st;
+            if ((st = put3(d->disp0, R.rx, R.ry, R.rz)) != SL_OK) return st;
+            SL_HIP(hipMemsetAsync(R.bin_n, 0, sizeof(int32_t) * R.nbins, stream));
+            SL_HIP(hipMemsetAsync(R.nbr_n, 0, sizeof(int32_t) * n, stream));
+        }
+        std::vector<int8_t> spc(n, 0);
+        if (d->species)
+            for (size_t i = 0; i < n; ++i) spc[i] = d->species[r.canon[i]];
+        SL_HIP(hipMemcpyAsync(R.species, spc.data(), n, hipMemcpyHostToDevice, stream));
+        sl::RunState rs{};
+        rs.step = 0;
+        rs.target = target;
+        rs.rebuild = R.live ? 1 : 0;
+        SL_HIP(hipMemcpyAsync(R.st, &rs, sizeof(rs), hipMemcpyHostToDevice, stream));
+        SL_HIP(hipStreamSynchronize(stream));
+        return commit_and_init(s);
+    }
+
+    // Copies the descriptor of slot s to the device, writes the initial
+    // electron grid, computes electron-cell ids, neighbour lists, forces and
+    // the step-0 sample of that run only, then rebuilds the work tables.
+    sl_status commit_and_init(int s)
+    {
+        Run& r = runs[s];
+        RD& R = host_rd[s];
+        SL_HIP(hipMemcpyAsync(R.Te, r.te_init.data(), sizeof(double) * r.z.ncell,
+                              hipMemcpyHostToDevice, stream));
+        SL_HIP(hipMemsetAsync(R.dE, 0, sizeof(unsigned long long) * r.z.ncell, stream));
+        SL_HIP(hipMemcpyAsync(d_runs + s, &R, sizeof(RD), hipMemcpyHostToDevice, stream));
+        // single-run work tables for the initialisation launches
+        std::vector<int2> wa, wb;
+        for (int st = 0; st < R.n; st += sl::kBlock) wa.push_back(make_int2(s, st));
+        for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2(s, st));
+        int one = s;
+        void* tmp = alloc.get(sizeof(int2) * (wa.size() + wb.size() + 1) + 512);
+        if (!tmp) return fail(SL_ENOMEM, "device allocation failed");
+        int2* dwa = static_cast<int2*>(tmp);
+        int2* dwb = dwa + wa.size();
+        int* drl = reinterpret_cast<int*>(dwb + wb.size());
+        SL_HIP(hipMemcpyAsync(dwa, wa.data(), sizeof(int2) * wa.size(), hipMemcpyHostToDevice, stream));
+        if (!wb.empty())
+            SL_HIP(hipMemcpyAsync(dwb, wb.data(), sizeof(int2) * wb.size(), hipMemcpyHostToDevice, stream));
+        SL_HIP(hipMemcpyAsync(drl, &one, sizeof(int), hipMemcpyHostToDevice, stream));
+        const int ga = (int)wa.size();
+        sl::k_kick_drift<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
+        if (R.live) {
+            sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
+            sl::k_nbr_sort<T><<<(int)wb.size(), sl::kBlock, 0, stream>>>(d_runs, dwb);
+            sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
+        }
+        sl::k_atom_final<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
+        sl::k_end_step<T><<<1, sl::kEndBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
+        SL_HIP(hipGetLastError());
+        SL_HIP(hipStreamSynchronize(stream));
+        alloc.put(tmp);
+        sl::RunState rs;
+        SL_HIP(hipMemcpy(&rs, R.st, sizeof(rs), hipMemcpyDeviceToHost));
+        if (rs.err) return numeric_error(s, rs.err);
+        return rebuild_tables();
+    }
+
+    sl_status rebuild_tables()
+    {
+        drop_graph();
+        std::vector<int2> ws, wa, wb;
+        std::vector<int> rl;
+        any_live = false;
+        for (size_t s = 0; s < runs.size(); ++s) {
+            if (!runs[s].used) continue;
+            const RD& R = host_rd[s];
+            for (int st = 0; st < R.g.H; st += sl::kBlock) ws.push_back(make_int2((int)s, st));
+            for (int st = 0; st < R.n; st += sl::kBlock) wa.push_back(make_int2((int)s, st));
+            for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2((int)s, st));
+            rl.push_back((int)s);
+            any_live = any_live || R.live;
+        }
+        for (void* p : tables) alloc.put(p);
+        tables.clear();
+        d_work_spin = d_work_atom = d_work_bin = nullptr;
+        d_run_list = nullptr;
+        active_blocks_spin = (int)ws.size();
+        active_blocks_atom = (int)wa.size();
+        active_blocks_bin = (int)wb.size();
+        active_runs = (int)rl.size();
+        auto up = [&](const void* src, size_t bytes, void** dst) -> sl_status {
+            if (bytes == 0) return SL_OK;
+            void* p = alloc.get(bytes);
+            if (!p) return fail(SL_ENOMEM, "device allocation failed");
+            tables.push_back(p);
+            SL_HIP(hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, stream));
+            *dst = p;
+            return SL_OK;
+        };
+        sl_status st;
+        if ((st = up(ws.data(), sizeof(int2) * ws.size(), (void**)&d_work_spin)) != SL_OK) return st;
+        if ((st = up(wa.data(), sizeof(int2) * wa.size(), (void**)&d_work_atom)) != SL_OK) return st;
+        if ((st = up(wb.data(), sizeof(int2) * wb.size(), (void**)&d_work_bin)) != SL_OK) return st;
+        if ((st = up(rl.data(), sizeof(int) * rl.size(), (void**)&d_run_list)) != SL_OK) return st;
+        SL_HIP(hipStreamSynchronize(stream));
+        return SL_OK;
+    }
+
+    int max_colours() const
+    {
+        int c = 0;
+        for (size_t s = 0; s < runs.size(); ++s)
+            if (runs[s].used) c = std::max(c, host_rd[s].g.C);
+        return c;
+    }
+
+    template <typename F> sl_status timed(hipStream_t st, Prof* p, int cls, F&& launch)
+    {
+        if (!p) {
+            launch();
+            return SL_OK;
+        }
+        hipEvent_t a, b;
+        SL_HIP(hipEventCreate(&a));
+        SL_HIP(hipEventCreate(&b));
+        SL_HIP(hipEventRecord(a, st));
+        launch();
+        SL_HIP(hipEventRecord(b, st));
+        p->ev->push_back(a);
+        p->ev->push_back(b);
+        p->cls->push_back(cls);
+        return SL_OK;
+    }
+
+    sl_status enqueue_step(hipStream_t st, Prof* p)
+    {
+        const int C = max_colours();
+        for (int pass = 0; pass < 2 * C - 1; ++pass) {
+            sl_status e = timed(st, p, 0, [&] {
+                sl::k_spin_pass<T><<<active_blocks_spin, sl::kBlock, 0, st>>>(d_runs, d_work_spin, pass);
+            });
+            if (e != SL_OK) return e;
+        }
+        if (any_live) {
+            sl_status e = timed(st, p, 2, [&] {
+                sl::k_kick_drift<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom,
+                                                                              sl::PHASE_STEP);
+            });
+            if (e != SL_OK) return e;
+            sl::k_nbr_bin<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom);
+            if (active_blocks_bin > 0)
+                sl::k_nbr_sort<T><<<active_blocks_bin, sl::kBlock, 0, st>>>(d_runs, d_work_bin);
+            sl::k_nbr_build<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom);
+        }
+        sl_status e = timed(st, p, 1, [&] {
+            sl::k_atom_final<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom,
+                                                                          sl::PHASE_STEP);
+        });
+        if (e != SL_OK) return e;
+        e = timed(st, p, 3, [&] {
+            sl::k_end_step<T><<<active_runs, sl::kEndBlock, 0, st>>>(d_runs, d_run_list, sl::PHASE_STEP);
+        });
+        return e;
+    }
+
+    sl_status capture()
+    {
+        drop_graph();
+        hipGraph_t graph = nullptr;
+        SL_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < graph_steps; ++k) enqueue_step(cap_stream, nullptr);
+        hipError_t e = hipStreamEndCapture(cap_stream, &graph);
+        if (e != hipSuccess) return fail(SL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(SL_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        graph_ok = true;
+        return SL_OK;
+    }
+};
+
+Engine* make_engine(int precision, int max_runs)
+{
+    if (precision == SL_FP32) return new EngineT<float>(max_runs);
+    return new EngineT<double>(max_runs);
+}
+
+template <typename F> sl_status engine_call(Engine* e, F&& f)
+{
+    if (e->precision == SL_FP32) return f(static_cast<EngineT<float>*>(e));
+    return f(static_cast<EngineT<double>*>(e));
+}
+
+sl_status setup_engine(Engine* e, int precision, void* stream, const sl_allocator* a, size_t budget,
+                       int graph_steps)
+{
+    e->precision = precision;
+    if (a) {
+        if (!a->alloc || !a->free) return fail(SL_EINVAL, "allocator needs alloc and free");
+        e->alloc.a = *a;
+        e->alloc.custom = true;
+    }
+    if (stream) {
+        e->stream = static_cast<hipStream_t>(stream);
+    } else {
+        SL_HIP(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking));
+        e->own_stream = true;
+    }
+    e->budget = budget;
+    if (graph_steps > 0) e->graph_steps = graph_steps;
+    return engine_call(e, [](auto* p) { return p->init_device(); });
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+struct sl_system_s {
+    std::unique_ptr<Engine> eng;
+};
+
+struct sl_batch_s {
+    std::unique_ptr<Engine> eng;
+};
+
+extern "C" {
+
+const char* sl_last_error(void) { return g_err.c_str(); }
+
+sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm, size_t* bytes)
+{
+    if (!desc || !bytes) return fail(SL_EINVAL, "null argument");
+    sl_ttm_desc t = ttm ? *ttm : default_ttm();
+    std::string e = validate_desc(desc);
+    if (!e.empty()) return fail(SL_EINVAL, e);
+    Sizes z = run_sizes(desc, &t);
+    *bytes = (desc->precision == SL_FP32 ? main_bytes<float>(desc, z) : main_bytes<double>(desc, z)) +
+             grid_bytes(z);
+    return SL_OK;
+}
+
+sl_status sl_init_system(const sl_system_desc* desc, sl_system* out)
+{
+    if (!desc || !out) return fail(SL_EINVAL, "null argument");
+    std::string e = validate_desc(desc);
+    if (!e.empty()) return fail(SL_EINVAL, e);
+    auto h = std::make_unique<sl_system_s>();
+    h->eng.reset(make_engine(desc->precision, 1));
+    sl_status st = setup_engine(h->eng.get(), desc->precision, desc->stream, desc->alloc, 0, 0);
+    if (st != SL_OK) return st;
+    sl_ttm_desc t = default_ttm();
+    int slot = -1;
+    st = h->eng->add(desc, &t, INT64_MAX, &slot);
+    if (st != SL_OK) return st;
+    *out = h.release();
+    return SL_OK;
+}
+
+sl_status sl_set_ttm_grid(sl_system h, const sl_ttm_desc* ttm)
+{
+    if (!h || !ttm) return fail(SL_EINVAL, "null argument");
+    return h->eng->set_grid(0, ttm);
+}
+
+sl_status sl_step(sl_system h, int64_t n_steps)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    return h->eng->advance(n_steps);
+}
+
+sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[4], int64_t launches[4])
+{
+    if (!h || !avg_ms || !launches) return fail(SL_EINVAL, "null argument");
+    return h->eng->profiled(n_steps, avg_ms, launches);
+}
+
+sl_status sl_synchronize(sl_system h)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    return h->eng->sync();
+}
+
+sl_status sl_observables(sl_system h, sl_obs* out, int64_t max_samples, int64_t* n_out)
+{
+    if (!h || !out || !n_out) return fail(SL_EINVAL, "null argument");
+    return h->eng->get(0, nullptr, nullptr, nullptr, nullptr, out, max_samples, n_out);
+}
+
+sl_status sl_get_state(sl_system h, double* x, double* v, double* s, double* Te)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    return h->eng->get(0, x, v, s, Te, nullptr, 0, nullptr);
+}
+
+sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* steps)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    const Run& r = h->eng->runs[0];
+    if (n_sites) *n_sites = r.z.n;
+    if (n_cells) *n_cells = r.z.ncell;
+    if (steps) *steps = r.steps;
+    return SL_OK;
+}
+
+void sl_destroy(sl_system h) { delete h; }
+
+sl_status sl_batch_create(const sl_batch_desc* desc, sl_batch* out)
+{
+    if (!desc || !out) return fail(SL_EINVAL, "null argument");
+    if (desc->precision != SL_FP64 && desc->precision != SL_FP32) return fail(SL_EINVAL, "precision must be 0 or 1");
+    if (desc->max_runs < 1 || desc->max_runs > (1 << 20)) return fail(SL_EINVAL, "max_runs out of range");
+    if (desc->graph_steps < 0) return fail(SL_EINVAL, "graph_steps must be >= 0");
+    auto b = std::make_unique<sl_batch_s>();
+    b->eng.reset(make_engine(desc->precision, desc->max_runs));
+    sl_status st = setup_engine(b->eng.get(), desc->precision, desc->stream, desc->alloc,
+                                desc->mem_budget, desc->graph_steps);
+    if (st != SL_OK) return st;
+    *out = b.release();
+    return SL_OK;
+}
+
+sl_status sl_batch_add(sl_batch b, const sl_system_desc* desc, const sl_ttm_desc* ttm, int64_t n_steps,
+                       int32_t* slot)
+{
+    if (!b || !desc || !slot) return fail(SL_EINVAL, "null argument");
+    if (n_steps < 0) return fail(SL_EINVAL, "negative step count");
+    sl_system_desc d = *desc;
+    d.precision = b->eng->precision;
+    sl_ttm_desc t = ttm ? *ttm : default_ttm();
+    int s = -1;
+    sl_status st = b->eng->add(&d, &t, n_steps, &s);
+    if (st == SL_OK) *slot = s;
+    return st;
+}
+
+sl_status sl_batch_advance(sl_batch b, int64_t n_steps)
+{
+    if (!b) return fail(SL_EINVAL, "null handle");
+    return b->eng->advance(n_steps);
+}
+
+sl_status sl_batch_runs(sl_batch b, sl_run_info* info, int32_t cap, int32_t* n_out)
+{
+    if (!b || !n_out) return fail(SL_EINVAL, "null argument");
+    int32_t k = 0;
+    for (size_t s = 0; s < b->eng->runs.size(); ++s) {
+        const Run& r = b->eng->runs[s];
+        if (!r.used) continue;
+        if (info && k < cap) {
+            info[k].slot = (int32_t)s;
+            info[k].status = SL_OK;
+            info[k].steps_done = r.steps;
+            info[k].steps_target = r.target;
+            info[k].n_samples = r.d.obs_every > 0 ? 1 + r.steps / r.d.obs_every : 0;
+        }
+        ++k;
+    }
+    *n_out = k;
+    return SL_OK;
+}
+
+sl_status sl_batch_get(sl_batch b, int32_t slot, double* x, double* v, double* s, double* Te,
+                       sl_obs* obs, int64_t max_samples, int64_t* n_obs)
+{
+    if (!b) return fail(SL_EINVAL, "null handle");
+    return b->eng->get(slot, x, v, s, Te, obs, max_samples, n_obs);
+}
+
+sl_status sl_batch_remove(sl_batch b, int32_t slot)
+{
+    if (!b) return fail(SL_EINVAL, "null handle");
+    return b->eng->remove(slot);
+}
+
+sl_status sl_batch_memory(sl_batch b, size_t* used, size_t* budget)
+{
+    if (!b) return fail(SL_EINVAL, "null handle");
+    if (used) *used = b->eng->used_bytes;
+    if (budget) *budget = b->eng->budget;
+    return SL_OK;
+}
+
+sl_status sl_batch_synchronize(sl_batch b)
+{
+    if (!b) return fail(SL_EINVAL, "null handle");
+    return b->eng->sync();
+}
+
+void sl_batch_destroy(sl_batch b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+"""FP64 HIP path against the FP64 oracle, element by element.
+
+Tolerance 1e-10 relative per component (reference scales: 1 for spins, 1 A
+for positions, the rms velocity, 1 K for electron temperatures).
+"""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_18541_amd import inputs as I
+from tests.gpu_util import compare_states, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_18541_amd import native
+    native.lib()
+    return native
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(N, spec, state, steps, Te=None, precision=0, obs_every=0):
+    _log("case: lattice=%d ncell=%s live=%d ttm=%d steps=%d prec=%d" %
+         (spec.lattice, spec.ncell, spec.lattice_mode, spec.ttm_mode, steps, precision))
+    g = N.System(spec, state, precision=precision, Te=Te, obs_every=obs_every)
+    orc = O.Oracle(spec, state.species, state.spins, state.vel, disp=state.disp, Te=Te)
+    return g, orc
+
+
+def test_cfg0_bcc_fe_100_steps(N):
+    """bcc Fe 6x6x6 (432 atoms): exchange J1/J2, B = 1 T, alpha 0.1, Morse
+    lattice at 300 K, fixed 300 K electrons, 100 steps of 0.1 fs."""
+    spec = I.fe_bcc_spec(L=6)
+    st = I.initial_state(spec, "tilt")
+    g, o = run_pair(N, spec, st, 100, obs_every=10)
+    for chunk in (1, 9, 40, 50):
+        g.step(chunk)
+        o.step(chunk)
+        errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+        assert not bad, (g.info(), errs)
+    # observables at step 100 against the oracle's
+    obs = g.observables()
+    assert [s["step"] for s in obs] == list(range(0, 101, 10))
+    last, ref = obs[-1], o.observables()
+    for k in ("E_ex", "E_z", "KE", "PE", "m_abs", "Tl"):
+        assert abs(last[k] - ref[k]) <= 1e-9 * max(1.0, abs(ref[k])), (k, last[k], ref[k])
+    np.testing.assert_allclose(last["M"][0], ref["M"][0], atol=1e-10)
+    np.testing.assert_allclose(last["Tspin"][0], ref["Tspin"][0], rtol=1e-8)
+
+
+def test_cfg0_moves_and_noise_is_live(N):
+    """The parity above is not vacuous: spins, positions and velocities move
+    and thermal noise acts (a second seed gives another trajectory)."""
+    spec = I.fe_bcc_spec(L=6)
+    st = I.initial_state(spec, "tilt")
+    a = N.System(spec, st)
+    b = N.System(replace(spec, seed=spec.seed + 1), st)
+    a.step(100)
+    b.step(100)
+    sa, sb = a.state(), b.state()
+    assert np.abs(sa["s"] - st.spins).max() > 1e-3
+    assert np.abs(sa["s"] - sb["s"]).max() > 1e-4
+
+
+def _alloy_window(L=12, tn=3, kappa=0.0, n_sub=1, profile=0, depth=0.0, S0=0.6):
+    # laser centred inside the 100-step window so the grid changes fast
+    spec = I.gdfeco_sc_spec(L=L, tn=tn, alpha=0.05, S0=S0, t0=0.005, fwhm=0.005,
+                            kappa_e=kappa, n_sub=n_sub, profile=profile, depth=depth)
+    return spec
+
+
+def test_alloy_laser_window_100_steps(N):
+    """Gd25(FeCo)75 sc alloy 12^3 (1728 sites, 3^3 electron grid) with a
+    laser pulse inside the window: two-temperature update, electron-phonon
+    Ornstein-Uhlenbeck step, 1/mu and 1/sqrt(mu) scaling with two moments."""
+    spec = _alloy_window()
+    st = I.initial_state(spec, "afm")
+    g, o = run_pair(N, spec, st, 100)
+    for chunk in (1, 49, 50):
+        g.step(chunk)
+        o.step(chunk)
+        errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+        assert not bad, errs
+    Te = o.state()["Te"]
+    assert Te.max() > 500.0          # the pulse heated the electrons
+
+
+def test_diffusion_surface_heating_window(N):
+    """Electron diffusion with sub-cycles and the top-slab laser profile."""
+    spec = _alloy_window(L=12, tn=3, kappa=I.w_per_mk_to_metal(80.0), n_sub=4, profile=1,
+                         depth=10.0)
+    spec = replace(spec, tn=(3, 3, 6))
+    st = I.initial_state(spec, "afm")
+    g, o = run_pair(N, spec, st, 100)
+    g.step(100)
+    o.step(100)
+    errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+    assert not bad, errs
+    Te = o.state()["Te"].reshape(6, 3, 3)
+    assert Te[-1].mean() > Te[0].mean() + 10.0
+
+
+def test_full_size_alloy_32cubed_frozen_graph(N):
+    """The full 32^3 alloy (32768 sites, 8^3 grid, laser on) in the launch
+    configuration the benchmark times (16-step graph replays), lattice
+    frozen so the oracle stays fast: every spin and grid value compared."""
+    spec = I.gdfeco_sc_spec(L=32, tn=8, S0=0.2, t0=0.0005, fwhm=0.001, lattice_mode=0)
+    st = I.initial_state(spec, "afm")
+    g, o = run_pair(N, spec, st, 33)
+    g.step(33)       # two graph replays + one direct step
+    o.step(33)
+    errs, bad = compare_states(g.state(), o.state(), spec.box, TOL, what=("s", "x", "Te"))
+    assert not bad, errs
+
+
+def test_full_size_alloy_32cubed_live(N):
+    """The full 32^3 alloy with the live Morse lattice and electron-phonon
+    coupling: two steps against the all-pairs oracle (7 s per step)."""
+    spec = I.gdfeco_sc_spec(L=32, tn=8, S0=0.2, t0=0.0002, fwhm=0.0005)
+    st = I.initial_state(spec, "afm")
+    g, o = run_pair(N, spec, st, 2)
+    g.step(2)
+    o.step(2)
+    errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+    assert not bad, errs
+
+
+def test_bitwise_deterministic(N):
+    spec = _alloy_window()
+    st = I.initial_state(spec, "afm")
+    a = N.System(spec, st)
+    b = N.System(spec, st)
+    a.step(40)
+    b.step(40)
+    sa, sb = a.state(), b.state()
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_small_frozen_spin_lattices(N, L):
+    """Degenerate sizes: 2x2x2 cells (each neighbour reached through two
+    images) on sc and bcc, spins only, strong noise."""
+    for lat in (0, 1):
+        spec = I.SystemSpec(lattice=lat, ncell=(L, L, L), a=3.0, n_species=1,
+                            mu=(2.2, 0, 0, 0), mass=(55.845, 0, 0, 0),
+                            n_shells=1 if lat == 0 else 2,
+                            J=(((0.01,) + (0,) * 3, (0,) * 4, (0,) * 4, (0,) * 4),
+                               ((0.005,) + (0,) * 3, (0,) * 4, (0,) * 4, (0,) * 4)),
+                            B=(0.1, 0.2, 0.5), alpha=0.3, lattice_mode=0, dt=5e-4,
+                            tn=(2, 1, 1), ttm_mode=0, Te0=200.0)
+        st = I.initial_state(spec, "random")
+        Te = np.array([50.0, 400.0])
+        g, o = run_pair(N, spec, st, 60, Te=Te)
+        g.step(60)
+        o.step(60)
+        errs, bad = compare_states(g.state(), o.state(), spec.box, TOL, what=("s", "Te"))
+        assert not bad, (lat, errs)
+
+
+def test_invalid_inputs_rejected(N):
+    spec = I.fe_bcc_spec(L=6)
+    st = I.initial_state(spec, "tilt")
+    with pytest.raises(N.SLError) as e:
+        N.System(replace(spec, ncell=(5, 6, 6)), I.InitialState(
+            species=np.zeros(2 * 5 * 36, dtype=np.int8),
+            spins=np.tile([0, 0, 1.0], (2 * 5 * 36, 1)), vel=None))
+    assert e.value.code == N.SL_EINVAL
+    bad = st.spins.copy()
+    bad[3] *= 1.1
+    with pytest.raises(N.SLError) as e:
+        N.System(spec, I.InitialState(species=st.species, spins=bad, vel=st.vel))
+    assert e.value.code == N.SL_EINVAL
+    # live lattice in a box shorter than 3 (rc + skin)
+    small = replace(spec, ncell=(4, 4, 4))
+    st4 = I.initial_state(small, "tilt")
+    with pytest.raises(N.SLError) as e:
+        N.System(small, st4)
+    assert e.value.code == N.SL_EINVAL
+    # unstable explicit diffusion
+    hot = replace(_alloy_window(), kappa_e=I.w_per_mk_to_metal(80.0), n_sub=1, tn=(12, 12, 12))
+    sth = I.initial_state(hot, "afm")
+    with pytest.raises(N.SLError) as e:
+        N.System(hot, sth)
+    assert e.value.code == N.SL_EINVAL

@@ -1,0 +1,170 @@
+"""CPU checks of the C ABI library and its host-side logic (no GPU needed).
+
+* the shared library loads and exports every entry point the header
+  declares;
+* the ctypes mirrors have the C layout (sizes and offsets from gcc);
+* the integer logic of the device header (division by run-time constants,
+  site numbering, Philox) compiled for the host agrees with brute force
+  and with the oracle's independent Philox.
+"""
+import ctypes as C
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2608_18541_amd import build as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spinlattice.h")
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    if not os.path.exists(B.LIB):
+        B.build(force=True)
+    return B.LIB
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(sl_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(n for n in names if not n.startswith("sl_allocator")))
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    lib = C.CDLL(libpath)
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2608_18541_amd import native
+    assert set(names) == set(native.EXPORTS), set(names) ^ set(native.EXPORTS)
+
+
+def test_binding_loads_without_gpu(libpath):
+    from paper_2608_18541_amd import native
+    L = native.lib()
+    assert L.sl_last_error() == b""
+    # a call that needs no device: invalid arguments are rejected cleanly
+    d = native.sl_system_desc()
+    out = C.c_size_t()
+    assert L.sl_footprint_bytes(C.byref(d), None, C.byref(out)) == native.SL_EINVAL
+    assert b"lattice" in L.sl_last_error() or b"ncell" in L.sl_last_error()
+
+
+LAYOUT_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "spinlattice.h"
+#define P(T, f) printf("%s %s %zu\n", #T, #f, offsetof(T, f));
+int main(void) {
+  printf("sl_system_desc size %zu\n", sizeof(sl_system_desc));
+  P(sl_system_desc, a) P(sl_system_desc, species) P(sl_system_desc, J) P(sl_system_desc, B)
+  P(sl_system_desc, dt) P(sl_system_desc, seed) P(sl_system_desc, spin0) P(sl_system_desc, alloc)
+  printf("sl_ttm_desc size %zu\n", sizeof(sl_ttm_desc));
+  P(sl_ttm_desc, Te_init) P(sl_ttm_desc, n_sub) P(sl_ttm_desc, depth)
+  printf("sl_obs size %zu\n", sizeof(sl_obs));
+  P(sl_obs, M) P(sl_obs, Tspin) P(sl_obs, Tl)
+  printf("sl_batch_desc size %zu\n", sizeof(sl_batch_desc));
+  P(sl_batch_desc, mem_budget) P(sl_batch_desc, alloc)
+  printf("sl_run_info size %zu\n", sizeof(sl_run_info));
+  P(sl_run_info, steps_done) P(sl_run_info, n_samples)
+  return 0;
+}
+"""
+
+
+def test_ctypes_layout_matches_c():
+    from paper_2608_18541_amd import native as N
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "l.c")
+        exe = os.path.join(td, "l")
+        open(src, "w").write(LAYOUT_PROBE)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), src, "-o", exe])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    types = {"sl_system_desc": N.sl_system_desc, "sl_ttm_desc": N.sl_ttm_desc,
+             "sl_obs": N.sl_obs, "sl_batch_desc": N.sl_batch_desc,
+             "sl_run_info": N.sl_run_info}
+    for line in out.strip().splitlines():
+        t, f, v = line.split()
+        if f == "size":
+            assert C.sizeof(types[t]) == int(v), line
+        else:
+            assert getattr(types[t], f).offset == int(v), line
+
+
+HOST_PROBE = r"""
+#include "sl_device.hpp"
+#include <cstdio>
+#include <cstdlib>
+int main() {
+  // division by invariant integers: all divisors up to 4096 on a sweep of n
+  for (uint32_t d = 1; d <= 4096; ++d) {
+    sl::FastDiv f = sl::make_fastdiv(d);
+    for (uint32_t n = 0; n < (1u << 31); n = n < 70000 ? n + 1 : n * 3 + 7) {
+      if (sl::fdiv(n, f) != n / d) { printf("FAIL div %u %u\n", n, d); return 1; }
+    }
+    uint32_t top = (1u << 31) - 1;
+    if (sl::fdiv(top, f) != top / d) { printf("FAIL div top %u\n", d); return 1; }
+  }
+  // site numbering: internal <-> (x, y, z, b) is a bijection and colours are proper
+  int dims[][4] = {{2, 2, 2, 1}, {4, 6, 2, 1}, {6, 6, 6, 2}, {8, 4, 10, 2}, {2, 2, 2, 2}};
+  for (auto& dm : dims) {
+    sl::Geom g;
+    g.Lx = dm[0]; g.Ly = dm[1]; g.Lz = dm[2]; g.nb = dm[3];
+    g.Lxh = g.Lx / 2; g.H = g.Lx * g.Ly * g.Lz / 2; g.C = 2 * g.nb;
+    g.divH = sl::make_fastdiv(g.H); g.divLxh = sl::make_fastdiv(g.Lxh);
+    g.divLy = sl::make_fastdiv(g.Ly);
+    int n = g.nb * g.Lx * g.Ly * g.Lz;
+    char* seen = (char*)calloc(n, 1);
+    for (int i = 0; i < n; ++i) {
+      sl::Site s = sl::decode_site(g, i);
+      if (sl::encode_site(g, s.x, s.y, s.z, s.b) != i) { printf("FAIL enc %d\n", i); return 1; }
+      int c = sl::canonical_of(g, s);
+      if (c < 0 || c >= n || seen[c]) { printf("FAIL canon %d\n", i); return 1; }
+      seen[c] = 1;
+      int par = (s.x + s.y + s.z) & 1;
+      if (s.k != (g.nb == 2 ? 2 * s.b + par : par)) { printf("FAIL colour %d\n", i); return 1; }
+    }
+    free(seen);
+  }
+  // Philox words for a few counters (compared with the oracle by the test)
+  unsigned v[6];
+  while (scanf("%u %u %u %u %u %u", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6) {
+    sl::U4 c{v[0], v[1], v[2], v[3]};
+    sl::U4 r = sl::philox4x32_10(c, v[4], v[5]);
+    printf("%u %u %u %u\n", r.x, r.y, r.z, r.w);
+  }
+  printf("OK\n");
+  return 0;
+}
+"""
+
+
+def test_device_integer_logic_on_host():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    from oracle import oracle as O
+    rng = np.random.default_rng(3)
+    cases = [tuple(int(x) for x in rng.integers(0, 2**32, size=6, dtype=np.uint64))
+             for _ in range(50)]
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "h.cpp")
+        exe = os.path.join(td, "h")
+        open(src, "w").write(HOST_PROBE)
+        subprocess.check_call([hipcc, "-O1", "-std=c++17", "-I", os.path.join(B.PKG, "csrc"),
+                               src, "-o", exe], stdout=subprocess.DEVNULL,
+                              stderr=subprocess.DEVNULL)
+        inp = "\n".join(" ".join(map(str, c)) for c in cases) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True).stdout
+    lines = out.strip().splitlines()
+    assert lines[-1] == "OK", lines[-3:]
+    for c, line in zip(cases, lines[:-1]):
+        assert list(map(int, line.split())) == list(O.philox(c[:4], c[4:])), c
