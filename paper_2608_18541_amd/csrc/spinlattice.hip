@@ -323,6 +323,7 @@ public:
         sl_status st = upload(s, d, t, target);
         if (st != SL_OK) {
             release(s);
+            tables_dirty = true;
             return st;
         }
         *slot = s;
@@ -362,6 +363,10 @@ public:
     {
         if (n < 0) return fail(SL_EINVAL, "negative step count");
         if (n == 0) return SL_OK;
+        if (tables_dirty) {
+            sl_status st = rebuild_tables();
+            if (st != SL_OK) return st;
+        }
         if (active_blocks_atom == 0) return SL_OK;
         int64_t left = n;
         if (graph_steps > 1 && left >= graph_steps) {
@@ -383,6 +388,10 @@ public:
 
     sl_status profiled(int64_t n, double avg[4], int64_t cnt[4]) override
     {
+        if (tables_dirty) {
+            sl_status st = rebuild_tables();
+            if (st != SL_OK) return st;
+        }
         std::vector<hipEvent_t> ev;
         std::vector<int> cls;
         Prof p{&ev, &cls};
@@ -490,7 +499,9 @@ public:
         if (s < 0 || s >= (int)runs.size() || !runs[s].used) return fail(SL_EINVAL, "bad slot");
         SL_HIP(hipStreamSynchronize(stream));
         release(s);
-        return rebuild_tables();
+        tables_dirty = true;
+        drop_graph();
+        return SL_OK;
     }
 
     sl_status n_samples(int s, int64_t* out)
@@ -518,6 +529,7 @@ private:
     bool any_live = false;
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
+    bool tables_dirty = true;
 
     sl_status numeric_error(int s, int err)
     {
@@ -783,12 +795,15 @@ private:
         sl::RunState rs;
         SL_HIP(hipMemcpy(&rs, R.st, sizeof(rs), hipMemcpyDeviceToHost));
         if (rs.err) return numeric_error(s, rs.err);
-        return rebuild_tables();
+        tables_dirty = true;
+        drop_graph();
+        return SL_OK;
     }
 
     sl_status rebuild_tables()
     {
         drop_graph();
+        tables_dirty = false;
         std::vector<int2> ws, wa, wb;
         std::vector<int> rl;
         any_live = false;

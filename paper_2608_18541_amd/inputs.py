@@ -235,3 +235,60 @@ def initial_state(spec: SystemSpec, kind: str = "tilt", p_gd: float = 0.25,
     else:
         vel = np.zeros((n, 3))
     return InitialState(species=species, spins=spins, vel=vel)
+
+
+# --- laser amplitude ---------------------------------------------------------------
+
+def _peak_te_0d(S0_si: float, gamma_e: float, C_l: float, G: float, t0: float, fwhm: float,
+                T0: float = 300.0, dt: float = 2.0e-16) -> float:
+    """Peak electron temperature of the zero-dimensional two-temperature
+    model gamma_e T_e dT_e/dt = -G (T_e - T_l) + S(t), C_l dT_l/dt =
+    G (T_e - T_l) (SI units), integrated with classical RK4."""
+    def rhs(t, Te, Tl):
+        S = S0_si * math.exp(-4.0 * math.log(2.0) * (t - t0) ** 2 / fwhm ** 2)
+        q = G * (Te - Tl)
+        return (S - q) / (gamma_e * Te), q / C_l
+    Te, Tl, t, peak = T0, T0, 0.0, T0
+    t_end = t0 + 4.0 * fwhm
+    while t < t_end:
+        a1, b1 = rhs(t, Te, Tl)
+        a2, b2 = rhs(t + dt / 2, Te + dt / 2 * a1, Tl + dt / 2 * b1)
+        a3, b3 = rhs(t + dt / 2, Te + dt / 2 * a2, Tl + dt / 2 * b2)
+        a4, b4 = rhs(t + dt, Te + dt * a3, Tl + dt * b3)
+        Te += dt / 6 * (a1 + 2 * a2 + 2 * a3 + a4)
+        Tl += dt / 6 * (b1 + 2 * b2 + 2 * b3 + b4)
+        t += dt
+        peak = max(peak, Te)
+    return peak
+
+
+def calibrate_laser(target_peak: float, fwhm_s: float, t0_s: float, gamma_e: float = 225.0,
+                    C_l: float = 3.1e6, G: float = 6.6e17) -> float:
+    """Peak source power density (W m^-3) for which the zero-dimensional
+    two-temperature model reaches target_peak (bisection)."""
+    lo, hi = 0.0, 1.0e23
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if _peak_te_0d(mid, gamma_e, C_l, G, t0_s, fwhm_s) < target_peak:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+_S0_CACHE = {}
+
+
+def laser_S0_metal(target_peak: float, fwhm_ps: float, t0_ps: float) -> float:
+    """Calibrated source amplitude in eV ps^-1 A^-3 (cached)."""
+    key = (round(target_peak, 6), round(fwhm_ps, 9), round(t0_ps, 9))
+    if key not in _S0_CACHE:
+        _S0_CACHE[key] = w_per_m3_to_metal(calibrate_laser(target_peak, fwhm_ps * 1e-12,
+                                                           t0_ps * 1e-12))
+    return _S0_CACHE[key]
+
+
+def cfg1_S0() -> float:
+    """32^3 alloy workload: 50 fs FWHM pulse centred at 100 fs, peak
+    T_e about 1800 K."""
+    return laser_S0_metal(1800.0, 0.05, 0.1)

@@ -1,0 +1,182 @@
+"""Batched runs and the FP32 path on the GPU.
+
+* a run inside a batch (any mix of sizes, lattices, targets, admission
+  times) is bitwise identical to the same run alone, in FP64 and FP32;
+* slots and the memory budget are enforced;
+* FP32 agrees with FP64 statistically and stays close over short windows.
+"""
+import math
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_18541_amd import inputs as I
+from tests.gpu_util import compare_states
+
+pytestmark = pytest.mark.gpu
+
+KB = 8.617333262e-5
+MUB = 5.7883818060e-5
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_18541_amd import native
+    native.lib()
+    return native
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_runs():
+    runs = []
+    for k, L in enumerate((6, 8, 10)):
+        spec = I.gdfeco_sc_spec(L=L, tn=2, alpha=0.02 * (k + 1), S0=0.3, t0=0.002, fwhm=0.002,
+                                seed=100 + k, run_id=k)
+        runs.append((spec, I.initial_state(spec, "afm")))
+    spec = I.fe_bcc_spec(L=6, seed=7, run_id=9)
+    runs.append((spec, I.initial_state(spec, "tilt")))
+    spec = I.fe_bcc_spec(L=4, lattice_mode=0, seed=8, run_id=10, Te0=500.0)
+    runs.append((spec, I.initial_state(spec, "random")))
+    return runs
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_equals_alone_bitwise(N, prec):
+    runs = _mixed_runs()
+    targets = [37, 50, 64, 45, 70]
+    _log("batch: %d runs prec=%d" % (len(runs), prec))
+    b = N.Batch(precision=prec, max_runs=8)
+    slots = [b.add(sp, st, t, obs_every=5) for (sp, st), t in zip(runs, targets)]
+    b.advance(30)
+    b.advance(40)          # every run reaches its target inside this call
+    for (sp, st), t, s in zip(runs, targets, slots):
+        alone = N.System(sp, st, precision=prec, obs_every=5)
+        alone.step(t)
+        a = alone.state()
+        g = b.get(s)
+        for k in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[k], g[k]), (s, k)
+        oa = alone.observables()
+        assert [o["step"] for o in g["obs"]] == [o["step"] for o in oa]
+        assert all(x["E_ex"] == y["E_ex"] for x, y in zip(oa, g["obs"]))
+        alone.close()
+    info = b.runs()
+    assert [r["steps_done"] for r in info] == targets
+
+
+def test_late_admission_and_removal(N):
+    """Continuous batching: a run admitted while others are mid-flight, and
+    a slot reused after removal, still match their solo trajectories."""
+    runs = _mixed_runs()
+    b = N.Batch(precision=1, max_runs=2)
+    s0 = b.add(*runs[0], 100)
+    b.advance(24)
+    s1 = b.add(*runs[1], 30)
+    b.advance(30)
+    g1 = b.get(s1)
+    b.remove(s1)
+    s2 = b.add(*runs[3], 20)
+    with pytest.raises(N.SLError) as e:
+        b.add(*runs[2], 10)
+    assert e.value.code == N.SL_EBUSY
+    b.advance(46)
+    g0, g2 = b.get(s0), b.get(s2)
+    for (sp, st), steps, g in ((runs[0], 100, g0), (runs[1], 30, g1), (runs[3], 20, g2)):
+        alone = N.System(sp, st, precision=1)
+        alone.step(steps)
+        a = alone.state()
+        for k in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[k], g[k]), k
+
+
+def test_memory_budget(N):
+    spec, st = _mixed_runs()[1]
+    fp = N.footprint_bytes(spec, precision=1, obs_capacity=4096)
+    b = N.Batch(precision=1, max_runs=8, mem_budget=int(2.5 * fp))
+    assert b.add(spec, st, 10) is not None
+    assert b.add(spec, st, 10) is not None
+    assert b.try_add(spec, st, 10) is None
+    used, budget = b.memory()
+    assert used == 2 * fp and budget == int(2.5 * fp)
+
+
+def _isolated_spins(prec, mu, T, Bz):
+    """32^3 sc lattice with J = 0: 32768 independent spins."""
+    spec = I.SystemSpec(lattice=0, ncell=(32, 32, 32), a=3.0, n_species=1, mu=(mu, 0, 0, 0),
+                        mass=(55.845, 0, 0, 0), n_shells=1,
+                        J=(((0.0,) * 4,) * 4, ((0.0,) * 4,) * 4), B=(0.0, 0.0, Bz), alpha=0.5,
+                        lattice_mode=0, dt=5e-4, tn=(1, 1, 1), ttm_mode=0, Te0=T, seed=31)
+    st = I.InitialState(species=np.zeros(spec.n_sites, dtype=np.int8),
+                        spins=np.tile([0.0, 0.0, 1.0], (spec.n_sites, 1)), vel=None)
+    return spec, st
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_langevin_function_on_gpu(N, prec):
+    """Thermal equilibrium of the GPU path itself: <s_z> = coth x - 1/x for
+    two moments, from 32768 independent spins (FP64 and FP32)."""
+    T, Bz = 50.0, 67.0
+    for mu in (2.2, 7.63):
+        spec, st = _isolated_spins(prec, mu, T, Bz)
+        g = N.System(spec, st, precision=prec, obs_every=50, obs_capacity=256)
+        g.step(2000)
+        g.observables()
+        g.step(4000)
+        obs = g.observables()
+        mz = np.array([o["m"][2] for o in obs])
+        x = mu * MUB * Bz / (KB * T)
+        ref = 1.0 / math.tanh(x) - 1.0 / x
+        assert abs(mz.mean() - ref) < 0.01, (prec, mu, mz.mean(), ref)
+
+
+def test_fp32_short_window_close_to_oracle(N):
+    """FP32 storage and spin arithmetic track the FP64 oracle closely over a
+    short window (the difference is rounding, amplified by the dynamics)."""
+    spec = I.fe_bcc_spec(L=6)
+    st = I.initial_state(spec, "tilt")
+    g = N.System(spec, st, precision=1)
+    o = O.Oracle(spec, st.species, st.spins, st.vel)
+    g.step(20)
+    o.step(20)
+    errs, bad = compare_states(g.state(), o.state(), spec.box, 2e-4)
+    assert not bad, errs
+
+
+def test_fp32_ensemble_matches_fp64(N):
+    """Sublattice M_z(t) of a laser-heated alloy: FP32 and FP64 ensembles
+    over the same 24 seeds agree within their statistical error bars; the
+    FP32 - FP64 difference is reported."""
+    nrun = 24
+    steps, every = 1500, 100
+    means = {}
+    for prec in (0, 1):
+        b = N.Batch(precision=prec, max_runs=nrun)
+        slots = []
+        for r in range(nrun):
+            spec = I.gdfeco_sc_spec(L=10, tn=2, alpha=0.05, S0=0.08, t0=0.03, fwhm=0.02,
+                                    seed=500, run_id=r)
+            slots.append(b.add(spec, I.initial_state(spec, "afm"), steps, obs_every=every))
+        b.advance(steps)
+        traj = []
+        for s in slots:
+            obs = b.get(s)["obs"]
+            traj.append([[o["M"][1][2], o["M"][0][2]] for o in obs])
+        means[prec] = np.array(traj)           # [run, sample, (Gd, TM)]
+    a, c = means[0], means[1]
+    diff = a.mean(axis=0) - c.mean(axis=0)
+    err = np.sqrt(a.var(axis=0, ddof=1) / nrun + c.var(axis=0, ddof=1) / nrun) + 1e-6
+    _log("FP32-FP64 max |dM| = %.3e, max |dM|/err = %.2f" % (np.abs(diff).max(),
+                                                           (np.abs(diff) / err).max()))
+    assert np.all(np.abs(diff) < 4.0 * err + 2e-3)
+    # the pulse did demagnetise the sublattices
+    assert a[:, -1, 1].mean() < 0.97
