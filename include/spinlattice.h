@@ -15,9 +15,11 @@
  *   2. lattice: velocity Verlet with a Morse pair potential cut (and
  *      shifted) at rc (the live lattice of Methods A);
  *   3. electron-phonon exchange: an Ornstein-Uhlenbeck velocity step at the
- *      cell's T_e with friction G_el / (3 n k_B); the energy the atoms gain
- *      leaves the cell's electrons (Methods B, both baths read the same
- *      T_e grid);
+ *      cell's T_e with friction G_el / (3 n k_B); the cell's electrons lose
+ *      the mean energy the step hands to its atoms given their velocities,
+ *      (1 - c1^2)(3/2 k_B T_e - m v^2/2) per atom (Methods B: both baths
+ *      read the same T_e grid; the coupling is the two-temperature term
+ *      with the cell's atomic temperature);
  *   4. electron grid: explicit finite differences of
  *      d(gamma_e T_e^2/2)/dt = kappa_e lap T_e + S(z,t) - (e-ph power), with
  *      a Gaussian laser source S (Methods B).

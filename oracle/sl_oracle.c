@@ -355,8 +355,12 @@ static void or_lattice_step(or_system* S)
 /* Electron-phonon exchange as an exact Ornstein-Uhlenbeck step on the
  * velocities at the electron temperature of the atom's cell.  The friction
  * rate Gamma = G_el / (3 n_atoms k_B) gives the same mean power
- * G_el (T_e - T_l) per volume as the textbook two-temperature coupling; the
- * kinetic energy each atom gains is taken out of its cell's electrons. */
+ * G_el (T_e - T_l) per volume as the textbook two-temperature coupling.
+ * The electrons of the cell lose the mean energy the step hands to each of
+ * its atoms given the atom's velocity, (1 - c1^2)(3/2 k_B T_e - m v^2 / 2):
+ * summed over the cell this is the volumetric coupling with the cell's
+ * instantaneous atomic temperature, conserving energy on average without
+ * feeding the per-step noise into the (small) electron heat capacity. */
 static void or_eph_step(or_system* S)
 {
     int32_t n = S->n;
@@ -369,15 +373,14 @@ static void or_eph_step(or_system* S)
         double eta[3];
         or_normals3(S->d.seed, S->d.run_id, (uint32_t)S->ctr_id[i], S->step, 1u, eta);
         double amp = sqrt((1.0 - c1 * c1) * OR_KB * T / (S->mass[i] * OR_MVV2E));
-        double ke_old = 0.0, ke_new = 0.0;
+        double vv = 0.0;
         for (int k = 0; k < 3; ++k) {
             double v = S->v[3 * i + k];
-            double vn = c1 * v + amp * eta[k];
-            ke_old += v * v;
-            ke_new += vn * vn;
-            S->v[3 * i + k] = vn;
+            vv += v * v;
+            S->v[3 * i + k] = c1 * v + amp * eta[k];
         }
-        S->dE[c] += 0.5 * S->mass[i] * OR_MVV2E * (ke_new - ke_old);
+        double ke = 0.5 * S->mass[i] * OR_MVV2E * vv;
+        S->dE[c] += (1.0 - c1 * c1) * (1.5 * OR_KB * T - ke);
     }
 }
 

@@ -11,7 +11,8 @@
 //   k_kick_drift           half kick + drift, electron-cell id, skin check
 //   k_nbr_bin/sort/build   Verlet-list rebuild (no-ops unless flagged)
 //   k_atom_final           Morse forces, half kick, electron-phonon
-//                          Ornstein-Uhlenbeck step, observable partials
+//                          Ornstein-Uhlenbeck step and its mean energy per
+//                          electron cell, observable partials
 //   k_end_step             electron grid, observable sample, step counter
 #pragma once
 
@@ -48,6 +49,7 @@ template <typename T> struct RunDev {
     T J[2][4][4];        // eV
     T hdtm[4];           // dt / (2 m) in A/ps per eV/A
     T ou_c1, ou_amp[4];  // exp(-Gamma dt); sqrt((1 - c1^2) k_B / m) per sqrt(K)
+    double ou_1mc2;      // 1 - c1^2
     T m_e[4];            // m in eV ps^2 / A^2
     T mD, ma, mr0, rc2, Vc;
     T skin_half2, rlist2;
@@ -449,9 +451,10 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
                     const T nx = R.ou_c1 * vx + amp * eta.a;
                     const T ny = R.ou_c1 * vy + amp * eta.b;
                     const T nz = R.ou_c1 * vz + amp * eta.c;
-                    const double ke_old = (double)vx * vx + (double)vy * vy + (double)vz * vz;
-                    const double ke_new = (double)nx * nx + (double)ny * ny + (double)nz * nz;
-                    const double dE = 0.5 * (double)R.m_e[sp] * (ke_new - ke_old);
+                    // mean energy the step hands to this atom given its velocity
+                    const double ke = 0.5 * (double)R.m_e[sp] *
+                                      ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+                    const double dE = R.ou_1mc2 * (1.5 * kKB * Te - ke);
                     if (fabs(dE) < 1.0e3) {
                         const long long fixp = llrint(dE * kFIX);
                         atomicAdd(&R.dE[c], (unsigned long long)fixp);

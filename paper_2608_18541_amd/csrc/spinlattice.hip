@@ -683,6 +683,7 @@ private:
         const double Gamma = t->mode == 1 ? t->G_el / (3.0 * ((double)r.z.n / vol) * sl::kKB) : 0.0;
         const double c1 = std::exp(-Gamma * d->dt);
         R.ou_c1 = (T)c1;
+        R.ou_1mc2 = 1.0 - c1 * c1;
         for (int sp = 0; sp < 4; ++sp) {
             const double m = sp < d->n_species && d->mass[sp] > 0 ? d->mass[sp] : 1.0;
             R.ou_amp[sp] = (T)std::sqrt((1.0 - c1 * c1) * sl::kKB / (m * sl::kMVV2E));

@@ -239,53 +239,67 @@ def initial_state(spec: SystemSpec, kind: str = "tilt", p_gd: float = 0.25,
 
 # --- laser amplitude ---------------------------------------------------------------
 
-def _peak_te_0d(S0_si: float, gamma_e: float, C_l: float, G: float, t0: float, fwhm: float,
-                T0: float = 300.0, dt: float = 2.0e-16) -> float:
+def peak_te_0d(S0_si, gamma_e: float, C_l: float, G: float, t0: float, fwhm: float,
+               T0: float = 300.0, dt: float = 2.0e-16):
     """Peak electron temperature of the zero-dimensional two-temperature
     model gamma_e T_e dT_e/dt = -G (T_e - T_l) + S(t), C_l dT_l/dt =
-    G (T_e - T_l) (SI units), integrated with classical RK4."""
+    G (T_e - T_l) (SI units), classical RK4, vectorised over S0_si."""
+    S0 = np.atleast_1d(np.asarray(S0_si, dtype=np.float64))
+
     def rhs(t, Te, Tl):
-        S = S0_si * math.exp(-4.0 * math.log(2.0) * (t - t0) ** 2 / fwhm ** 2)
+        S = S0 * math.exp(-4.0 * math.log(2.0) * (t - t0) ** 2 / fwhm ** 2)
         q = G * (Te - Tl)
         return (S - q) / (gamma_e * Te), q / C_l
-    Te, Tl, t, peak = T0, T0, 0.0, T0
+    Te = np.full_like(S0, T0)
+    Tl = np.full_like(S0, T0)
+    peak = Te.copy()
+    t = 0.0
     t_end = t0 + 4.0 * fwhm
     while t < t_end:
         a1, b1 = rhs(t, Te, Tl)
         a2, b2 = rhs(t + dt / 2, Te + dt / 2 * a1, Tl + dt / 2 * b1)
         a3, b3 = rhs(t + dt / 2, Te + dt / 2 * a2, Tl + dt / 2 * b2)
         a4, b4 = rhs(t + dt, Te + dt * a3, Tl + dt * b3)
-        Te += dt / 6 * (a1 + 2 * a2 + 2 * a3 + a4)
-        Tl += dt / 6 * (b1 + 2 * b2 + 2 * b3 + b4)
+        Te = Te + dt / 6 * (a1 + 2 * a2 + 2 * a3 + a4)
+        Tl = Tl + dt / 6 * (b1 + 2 * b2 + 2 * b3 + b4)
         t += dt
-        peak = max(peak, Te)
+        peak = np.maximum(peak, Te)
     return peak
 
 
-def calibrate_laser(target_peak: float, fwhm_s: float, t0_s: float, gamma_e: float = 225.0,
-                    C_l: float = 3.1e6, G: float = 6.6e17) -> float:
-    """Peak source power density (W m^-3) for which the zero-dimensional
-    two-temperature model reaches target_peak (bisection)."""
-    lo, hi = 0.0, 1.0e23
-    for _ in range(60):
+def calibrate_laser(targets, fwhm_s: float, t0_s: float, gamma_e: float = 225.0,
+                    C_l: float = 3.1e6, G: float = 6.6e17):
+    """Peak source power densities (W m^-3) for which the zero-dimensional
+    two-temperature model reaches each target peak T_e (vectorised
+    bisection)."""
+    tg = np.atleast_1d(np.asarray(targets, dtype=np.float64))
+    lo = np.zeros_like(tg)
+    hi = np.full_like(tg, 1.0e24)
+    for _ in range(56):
         mid = 0.5 * (lo + hi)
-        if _peak_te_0d(mid, gamma_e, C_l, G, t0_s, fwhm_s) < target_peak:
-            lo = mid
-        else:
-            hi = mid
+        below = peak_te_0d(mid, gamma_e, C_l, G, t0_s, fwhm_s) < tg
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
     return 0.5 * (lo + hi)
 
 
 _S0_CACHE = {}
 
 
+def laser_S0_many(targets, fwhm_ps: float, t0_ps: float) -> np.ndarray:
+    """Calibrated source amplitudes in eV ps^-1 A^-3 (cached per target)."""
+    tg = [round(float(x), 6) for x in np.atleast_1d(targets)]
+    key0 = (round(fwhm_ps, 9), round(t0_ps, 9))
+    todo = sorted(set(x for x in tg if (key0, x) not in _S0_CACHE))
+    if todo:
+        vals = calibrate_laser(todo, fwhm_ps * 1e-12, t0_ps * 1e-12)
+        for x, v in zip(todo, vals):
+            _S0_CACHE[(key0, x)] = w_per_m3_to_metal(float(v))
+    return np.array([_S0_CACHE[(key0, x)] for x in tg])
+
+
 def laser_S0_metal(target_peak: float, fwhm_ps: float, t0_ps: float) -> float:
-    """Calibrated source amplitude in eV ps^-1 A^-3 (cached)."""
-    key = (round(target_peak, 6), round(fwhm_ps, 9), round(t0_ps, 9))
-    if key not in _S0_CACHE:
-        _S0_CACHE[key] = w_per_m3_to_metal(calibrate_laser(target_peak, fwhm_ps * 1e-12,
-                                                           t0_ps * 1e-12))
-    return _S0_CACHE[key]
+    return float(laser_S0_many([target_peak], fwhm_ps, t0_ps)[0])
 
 
 def cfg1_S0() -> float:

@@ -1,0 +1,97 @@
+"""Ensemble and request-stream workloads built from the seeded presets.
+
+* ``phase_diagram``: independent realizations of the laser-heated
+  Gd25(FeCo)75 alloy over a grid of damping values x peak electron
+  temperatures x seeds (Methods F: replicas share nothing; Methods G: n
+  realizations per condition with an independent alloy and noise seed
+  each).
+* ``request_trace``: a Poisson stream of alloy simulations of mixed size,
+  composition, peak temperature and length.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+from typing import List, Optional
+
+import numpy as np
+
+from . import inputs as I
+
+
+@dataclass
+class RunSpec:
+    """A run to perform; its seeded initial state is drawn on demand."""
+    spec: I.SystemSpec
+    n_steps: int
+    tag: tuple = ()
+    kind: str = "afm"
+    p_gd: float = 0.25
+
+    @property
+    def state(self) -> I.InitialState:
+        return I.initial_state(self.spec, self.kind, p_gd=self.p_gd)
+
+
+def alloy_run(L: int, alpha: float, T_peak: float, seed: int, run_id: int, n_steps: int,
+              p_gd: float = 0.25, fwhm: float = 0.05, t0: float = 0.1,
+              lattice_mode: int = 1) -> RunSpec:
+    """One realization: sc alloy L^3 with the electron grid at 14.08 A cells
+    (L/4 cells per side), laser calibrated to T_peak."""
+    tn = max(1, L // 4)
+    S0 = I.laser_S0_metal(T_peak, fwhm, t0)
+    spec = I.gdfeco_sc_spec(L=L, tn=tn, alpha=alpha, S0=S0, fwhm=fwhm, t0=t0, seed=seed,
+                            run_id=run_id, lattice_mode=lattice_mode)
+    return RunSpec(spec, n_steps, (alpha, T_peak), "afm", p_gd)
+
+
+def phase_diagram(L: int = 16, n_alpha: int = 8, n_temp: int = 8, n_seeds: int = 20,
+                  n_steps: int = 20000, seed: int = 2026, alpha_range=(0.005, 0.04),
+                  temp_range=(800.0, 2400.0), lattice_mode: int = 1) -> List[RunSpec]:
+    """alpha log-spaced x T_peak linearly spaced x seeds; run_id enumerates
+    the runs so every realization has its own alloy and noise stream."""
+    a0, a1 = alpha_range
+    alphas = [a0 * (a1 / a0) ** (k / max(1, n_alpha - 1)) for k in range(n_alpha)]
+    t0, t1 = temp_range
+    temps = [t0 + k * (t1 - t0) / max(1, n_temp - 1) for k in range(n_temp)]
+    I.laser_S0_many(temps, 0.05, 0.1)        # calibrate every peak at once
+    out = []
+    rid = 0
+    for a in alphas:
+        for T in temps:
+            for s in range(n_seeds):
+                out.append(alloy_run(L, a, T, seed, rid, n_steps, lattice_mode=lattice_mode))
+                rid += 1
+    return out
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float           # seconds after the start of the trace
+    run: RunSpec
+
+
+def request_trace(n: int = 600, rate: float = 50.0, seed: int = 7,
+                  sizes=(8, 16, 24, 32, 48), x_range=(0.18, 0.32),
+                  temp_range=(1000.0, 2200.0), steps_range=(5000, 30000),
+                  steps_scale: float = 1.0, lattice_mode: int = 1) -> List[Request]:
+    """Poisson arrivals (mean `rate` per second) of alloy simulations with a
+    uniformly drawn cubic size, Gd fraction, peak T_e and step count
+    (step counts multiplied by steps_scale)."""
+    rng = np.random.default_rng(seed)
+    draws = []
+    t = 0.0
+    for k in range(n):
+        t += rng.exponential(1.0 / rate)
+        draws.append((t, int(rng.choice(sizes)), float(rng.uniform(*x_range)),
+                      float(rng.uniform(*temp_range)),
+                      int(rng.integers(steps_range[0], steps_range[1] + 1))))
+    I.laser_S0_many([d[3] for d in draws], 0.05, 0.1)
+    out = []
+    for k in range(n):
+        t, L, x, T, steps = draws[k]
+        steps = max(1, int(round(steps * steps_scale)))
+        run = alloy_run(L, 0.01, T, seed, k, steps, p_gd=x, lattice_mode=lattice_mode)
+        out.append(Request(k, t, run))
+    return out
