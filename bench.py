@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["spin_pass", "atom_final", "kick_drift", "end_step"]
+KERNELS = ["spin_pass", "atom_final", "kick_drift", "grid"]
 
 
 def bytes_per_unit(kernel: str, fp: int, n_species: int, z_list: float) -> float:
@@ -68,6 +68,139 @@ def cpu_baseline(spec, st, budget_s: float = 20.0) -> dict:
                       "%.1f s" % (steps, el)}
 
 
+def plain_step_time(N, run, steps: int = 1000) -> float:
+    """Seconds per step of one run alone on the plain FP64 path."""
+    s = N.System(run.spec, run.state, precision=N.SL_FP64, obs_every=100)
+    s.step(50)
+    s.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    s.close()
+    return el
+
+
+def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
+    """The alloy phase diagram (8 alpha x 8 peak T_e x seeds, 16^3 runs) in
+    one batch, FP32 and FP64; switching probabilities per cell."""
+    from paper_2608_18541_amd.stats import switched, wilson_ci
+    runs = W.phase_diagram(L=16, n_seeds=n_seeds, n_steps=n_steps)
+    res = {}
+    flags = {}
+    for prec in (N.SL_FP32, N.SL_FP64):
+        b = N.Batch(precision=prec, max_runs=len(runs))
+        slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
+                 for r in runs]
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.advance(n_steps)
+        try:
+            b.synchronize()
+        except N.SLError:
+            pass                    # runs that stopped are counted below
+        el = time.perf_counter() - t0
+        fl, failed = [], 0
+        for s in slots:
+            try:
+                mz = [o["M"][1][2] for o in b.get(s, max_samples=n_steps // 20 + 2)["obs"]]
+                fl.append(switched(mz))
+            except N.SLError:
+                failed += 1
+                fl.append(False)
+        flags[prec] = np.array(fl).reshape(8, 8, n_seeds)
+        res["fp32" if prec else "fp64"] = {"seconds": round(el, 3),
+                                           "runs_per_s": round(len(runs) / el, 3),
+                                           "atom_steps_per_s": len(runs) * 4096 * n_steps / el,
+                                           "failed_runs": failed}
+        print("bench: phase diagram prec %d: %.2f s" % (prec, el), file=sys.stderr, flush=True)
+        b.close()
+    t_plain = plain_step_time(N, runs[0], 1000)
+    plain_rps = 1.0 / (t_plain * n_steps)
+    p32 = flags[N.SL_FP32].mean(axis=2)
+    p64 = flags[N.SL_FP64].mean(axis=2)
+    agree = float((flags[N.SL_FP32] == flags[N.SL_FP64]).mean())
+    k = flags[N.SL_FP32].sum(axis=2)
+    ci = [wilson_ci(int(v), n_seeds) for v in k.ravel()]
+    res.update({
+        "workload": "Gd25(FeCo)75 sc 16^3 x (8 alpha 0.005-0.04 log) x (8 peak T_e 800-2400 K)"
+                    " x %d seeds = %d runs, %d steps" % (n_seeds, len(runs), n_steps),
+        "plain_fp64_runs_per_s": round(plain_rps, 4),
+        "plain_us_per_step": round(t_plain * 1e6, 2),
+        "speedup_fp32_vs_plain": round(res["fp32"]["runs_per_s"] / plain_rps, 1),
+        "speedup_fp64_vs_plain": round(res["fp64"]["runs_per_s"] / plain_rps, 1),
+        "P_fp32": np.round(p32, 3).tolist(), "P_fp64": np.round(p64, 3).tolist(),
+        "max_abs_dP_fp32_fp64": float(np.abs(p32 - p64).max()),
+        "paired_flag_agreement": agree,
+        "wilson_halfwidth_max": float(max(h - l for l, h in ci) / 2),
+    })
+    return res
+
+
+def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
+    """Poisson request stream served with continuous batching (FP32), and a
+    one-request-at-a-time plain FP64 baseline on the same trace."""
+    trace = W.request_trace(n=n_req, rate=50.0, seed=7, steps_scale=steps_scale)
+    batch = N.Batch(precision=N.SL_FP32, max_runs=512, mem_budget=24 << 30)
+    srv = S.Server(batch, chunk=500, obs_every=100)
+    res = srv.run(trace)
+    st = S.summarize(res, srv.makespan)
+    batch.close()
+    # plain path: measured per-size step time, requests served in arrival order
+    per_size = {}
+    for L in sorted(set(r.run.spec.ncell[0] for r in trace)):
+        rr = next(r for r in trace if r.run.spec.ncell[0] == L)
+        per_size[L] = plain_step_time(N, rr.run, 500)
+    base = S.fifo_baseline(trace, lambda r: per_size[r.run.spec.ncell[0]] * r.run.n_steps)
+    bst = S.summarize(base, max(r.finished for r in base))
+    return {"requests": st.n, "trace": "Poisson 50/s, sizes {8,16,24,32,48}^3, x U(0.18,0.32),"
+                                       " T_peak U(1000,2200) K, steps U{5000..30000} x %g"
+                                       % steps_scale,
+            "served_req_per_s": round(st.throughput, 3), "served_makespan_s": round(st.makespan, 2),
+            "served_p50_s": round(st.p50, 3), "served_p99_s": round(st.p99, 3),
+            "served_atom_steps_per_s": st.atom_steps_per_s,
+            "plain_req_per_s": round(bst.throughput, 4), "plain_makespan_s": round(bst.makespan, 1),
+            "plain_p50_s": round(bst.p50, 2), "plain_p99_s": round(bst.p99, 2),
+            "plain_us_per_step": {str(k): round(v * 1e6, 2) for k, v in per_size.items()},
+            "plain_latency_method": "FIFO replay of measured plain FP64 per-step times"}
+
+
+def large_run(N, I, steps: int) -> dict:
+    """bcc Fe 64^3 (524288 atoms) FP32 with surface laser heating; the
+    spin colour pass's achieved bandwidth; FP32 error against FP64 after 10
+    steps."""
+    spec = I.fe_large_spec()
+    st = I.initial_state(spec, "tilt")
+    s32 = N.System(spec, st, precision=N.SL_FP32, obs_every=100)
+    s32.step(20)
+    s32.synchronize()
+    t0 = time.perf_counter()
+    s32.step(steps)
+    s32.synchronize()
+    el = time.perf_counter() - t0
+    avg, cnt = s32.step_profiled(20)
+    s32.close()
+    H = spec.n_sites / 4
+    bpu = bytes_per_unit("spin_pass", 1, spec.n_species, 0)
+    ach = bpu * H / (avg[0] * 1e-3) / 1e9
+    a32 = N.System(spec, st, precision=N.SL_FP32)
+    a64 = N.System(spec, st, precision=N.SL_FP64)
+    a32.step(10)
+    a64.step(10)
+    g32, g64 = a32.state(), a64.state()
+    a32.close()
+    a64.close()
+    return {"workload": "bcc Fe 64^3 (524288 atoms) FP32, 32^3 grid, kappa_e 80 W/m/K, "
+                        "100 fs top-10 nm pulse",
+            "atom_steps_per_s": spec.n_sites * steps / el, "ms_per_step": el / steps * 1e3,
+            "spin_pass": {"avg_launch_us": round(avg[0] * 1e3, 3), "achieved_GBs": round(ach, 1),
+                          "frac": round(ach / HBM_PEAK_GBS, 4)},
+            "per_step_us": {k: round(avg[i] * cnt[i] / 20 * 1e3, 2) for i, k in enumerate(KERNELS)},
+            "fp32_vs_fp64_10_steps": {"max_abs_ds": float(np.abs(g32["s"] - g64["s"]).max()),
+                                      "max_abs_dv_rel": float(np.abs(g32["v"] - g64["v"]).max() /
+                                                              np.sqrt((g64["v"] ** 2).mean()))}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +208,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, served and large-run measurements")
+    ap.add_argument("--extras", default="batched,serving,large",
+                    help="comma list of extra measurements")
+    ap.add_argument("--pd-steps", type=int, default=20000)
+    ap.add_argument("--pd-seeds", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-steps-scale", type=float, default=1.0)
+    ap.add_argument("--large-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported "
@@ -132,6 +274,15 @@ def main() -> int:
                    "parallelism": "single run"},
         "roofline": roof,
     }
+    extras = [] if args.no_extras else [e for e in args.extras.split(",") if e]
+    from paper_2608_18541_amd import serve as S
+    from paper_2608_18541_amd import workloads as W
+    if "batched" in extras:
+        out["batched"] = batched_phase_diagram(N, W, args.pd_steps, args.pd_seeds)
+    if "serving" in extras:
+        out["serving"] = serving(N, W, S, args.serve_requests, args.serve_steps_scale)
+    if "large" in extras:
+        out["large"] = large_run(N, I, args.large_steps)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, st)

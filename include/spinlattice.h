@@ -235,6 +235,12 @@ sl_status sl_batch_get(sl_batch b, int32_t slot, double* x, double* v, double* s
 /* Releases a slot and its device memory (waits for the stream first). */
 sl_status sl_batch_remove(sl_batch b, int32_t slot);
 
+/* As sl_batch_advance, launching every kernel directly with HIP events
+ * around each; returns the average device time (ms) per launch of each
+ * kernel class (as sl_step_profiled) and the launch counts. */
+sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[4],
+                                    int64_t launches[4]);
+
 /* Bytes of the budget in use. */
 sl_status sl_batch_memory(sl_batch b, size_t* used, size_t* budget);
 

@@ -9,11 +9,16 @@
 //   k_spin_pass  x (2C-1)  colour sweep 0..C-1 (half steps), C-2..0, the
 //                          middle colour taking one full step
 //   k_kick_drift           half kick + drift, electron-cell id, skin check
-//   k_nbr_bin/sort/build   Verlet-list rebuild (no-ops unless flagged)
+//   k_nbr_bin/sort/build   Verlet-list rebuild (exit at once unless flagged)
 //   k_atom_final           Morse forces, half kick, electron-phonon
 //                          Ornstein-Uhlenbeck step and its mean energy per
 //                          electron cell, observable partials
-//   k_end_step             electron grid, observable sample, step counter
+//   k_ttm_diffuse x n_sub  explicit electron diffusion sub-steps (runs with
+//                          kappa_e > 0 only)
+//   k_grid                 laser source and electron-phonon energy per
+//                          cell of large grids
+//   k_finalize             one block per run: small grids, the observable
+//                          sample, the step counter
 #pragma once
 
 #include "sl_device.hpp"
@@ -22,8 +27,8 @@
 namespace sl {
 
 constexpr int kBlock = 256;
-constexpr int kEndBlock = 256;
 constexpr int NQ = 24;      // per-block observable partial sums
+constexpr int kLdsCells = 2048;   // electron grids up to this size are summed in LDS
 
 enum { ERR_NEG_E = 1, ERR_BIN = 2, ERR_NBR = 4, ERR_DE = 8 };
 enum { PHASE_STEP = 0, PHASE_INIT = 1 };
@@ -34,7 +39,10 @@ struct RunState {
     int32_t err;
     int32_t rebuild;
     int64_t n_samples;
-    int64_t pad[3];
+    int32_t bad_atom;    // first atom that overflowed a neighbour table (+1), for diagnostics
+    int32_t bad_count;
+    int64_t bad_step;
+    int64_t pad;
 };
 
 template <typename T> struct RunDev {
@@ -66,8 +74,9 @@ template <typename T> struct RunDev {
     T *sx, *sy, *sz, *ux, *uy, *uz, *vx, *vy, *vz, *fx, *fy, *fz, *rx, *ry, *rz;
     int8_t* species;
     uint16_t* cell;
-    int32_t *nbr, *nbr_n, *bin_n, *bin_atoms;
-    double *Te, *ee, *lap;
+    int32_t *nbr, *nbr_n;
+    int32_t *bin_n, *bin_atoms;      // [nbins], [nbins][bin_cap]
+    double *Te, *ee, *Te_alt;        // T_e, energy density, diffusion ping-pong buffer
     unsigned long long* dE;
     double* partial;
     int32_t n_part;
@@ -83,55 +92,80 @@ template <typename T> __device__ inline int species_of(const RunDev<T>& R, int i
 }
 
 // Exchange sum h = sum_j J_ij s_j (eV) over the neighbour shells of site
-// (x, y, z, b), read from the colour-major spin arrays.
+// (x, y, z, b), read from the colour-major spin arrays.  All neighbour
+// indices are formed first and all their loads issued together; the
+// coupling J[shell][sp][sj] is selected in registers from the run's table.
+template <typename T> __device__ inline T select4(int k, T a, T b, T c, T d)
+{
+    return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+}
+
+template <typename T, int NN>
+__device__ __forceinline__ V3<T> exchange_gather(const RunDev<T>& R, const int (&j)[NN],
+                                        const int (&sh)[NN], int nn, int sp)
+{
+    T ax[NN], ay[NN], az[NN];
+    int sj[NN];
+    const bool multi = R.n_species > 1;
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+        if (q < nn) {
+            ax[q] = R.sx[j[q]];
+            ay[q] = R.sy[j[q]];
+            az[q] = R.sz[j[q]];
+            sj[q] = multi ? (int)R.species[j[q]] : 0;
+        }
+    }
+    // couplings of this site's species to each species, per shell
+    T row[2][4];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            row[s2][t] = select4(sp, R.J[s2][0][t], R.J[s2][1][t], R.J[s2][2][t], R.J[s2][3][t]);
+    V3<T> h{T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+        if (q < nn) {
+            const T Jv = sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
+                                    : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
+            h.x += Jv * ax[q];
+            h.y += Jv * ay[q];
+            h.z += Jv * az[q];
+        }
+    }
+    return h;
+}
+
 template <typename T>
-__device__ inline V3<T> exchange_sum(const RunDev<T>& R, int x, int y, int z, int b, int sp)
+__device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, int x, int y, int z, int b, int sp)
 {
     const Geom& g = R.g;
-    V3<T> h{T(0), T(0), T(0)};
-    auto add = [&](int xw, int yw, int zw, int bw, int shell) {
-        int j = encode_site(g, xw, yw, zw, bw);
-        int sj = species_of(R, j);
-        T Jv = R.J[shell][sp][sj];
-        h.x += Jv * R.sx[j];
-        h.y += Jv * R.sy[j];
-        h.z += Jv * R.sz[j];
-    };
     const int xm = x == 0 ? g.Lx - 1 : x - 1, xp = x == g.Lx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? g.Ly - 1 : y - 1, yp = y == g.Ly - 1 ? 0 : y + 1;
     const int zm = z == 0 ? g.Lz - 1 : z - 1, zp = z == g.Lz - 1 ? 0 : z + 1;
     if (R.lattice == SL_LATTICE_SC) {
-        add(xm, y, z, 0, 0);
-        add(xp, y, z, 0, 0);
-        add(x, ym, z, 0, 0);
-        add(x, yp, z, 0, 0);
-        add(x, y, zm, 0, 0);
-        add(x, y, zp, 0, 0);
-    } else {
-        // first shell: the 8 sites of the other basis at (+-a/2, +-a/2, +-a/2)
-        const int ob = 1 - b;
-        const int x0 = b == 0 ? xm : x, x1 = b == 0 ? x : xp;
-        const int y0 = b == 0 ? ym : y, y1 = b == 0 ? y : yp;
-        const int z0 = b == 0 ? zm : z, z1 = b == 0 ? z : zp;
-        add(x0, y0, z0, ob, 0);
-        add(x1, y0, z0, ob, 0);
-        add(x0, y1, z0, ob, 0);
-        add(x1, y1, z0, ob, 0);
-        add(x0, y0, z1, ob, 0);
-        add(x1, y0, z1, ob, 0);
-        add(x0, y1, z1, ob, 0);
-        add(x1, y1, z1, ob, 0);
-        if (R.n_shells > 1) {
-            // second shell: the 6 sites of the same basis at +-a along an axis
-            add(xm, y, z, b, 1);
-            add(xp, y, z, b, 1);
-            add(x, ym, z, b, 1);
-            add(x, yp, z, b, 1);
-            add(x, y, zm, b, 1);
-            add(x, y, zp, b, 1);
-        }
+        const int j[6] = {encode_site(g, xm, y, z, 0), encode_site(g, xp, y, z, 0),
+                          encode_site(g, x, ym, z, 0), encode_site(g, x, yp, z, 0),
+                          encode_site(g, x, y, zm, 0), encode_site(g, x, y, zp, 0)};
+        const int sh[6] = {0, 0, 0, 0, 0, 0};
+        return exchange_gather<T, 6>(R, j, sh, 6, sp);
     }
-    return h;
+    // first shell: the 8 sites of the other basis at (+-a/2, +-a/2, +-a/2);
+    // second shell: the 6 sites of the same basis at +-a along an axis
+    const int ob = 1 - b;
+    const int x0 = b == 0 ? xm : x, x1 = b == 0 ? x : xp;
+    const int y0 = b == 0 ? ym : y, y1 = b == 0 ? y : yp;
+    const int z0 = b == 0 ? zm : z, z1 = b == 0 ? z : zp;
+    const int j[14] = {encode_site(g, x0, y0, z0, ob), encode_site(g, x1, y0, z0, ob),
+                       encode_site(g, x0, y1, z0, ob), encode_site(g, x1, y1, z0, ob),
+                       encode_site(g, x0, y0, z1, ob), encode_site(g, x1, y0, z1, ob),
+                       encode_site(g, x0, y1, z1, ob), encode_site(g, x1, y1, z1, ob),
+                       encode_site(g, xm, y, z, b),    encode_site(g, xp, y, z, b),
+                       encode_site(g, x, ym, z, b),    encode_site(g, x, yp, z, b),
+                       encode_site(g, x, y, zm, b),    encode_site(g, x, y, zp, b)};
+    const int sh[14] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
+    return exchange_gather<T, 14>(R, j, sh, R.n_shells > 1 ? 14 : 8, sp);
 }
 
 template <typename T> __device__ inline V3<T> ideal_site(const RunDev<T>& R, const Site& s)
@@ -300,13 +334,18 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict_
     int b3[3];
     const int bin = bin_of(R, position(R, s, i), b3);
     const int slot = atomicAdd(&R.bin_n[bin], 1);
-    if (slot < R.bin_cap)
-        R.bin_atoms[bin * R.bin_cap + slot] = i;
-    else
+    if (slot < R.bin_cap) {
+        R.bin_atoms[(size_t)bin * R.bin_cap + slot] = i;
+    } else {
+        if (atomicCAS(&R.st->bad_atom, 0, i + 1) == 0) {
+            R.st->bad_count = slot + 1;
+            R.st->bad_step = R.st->step;
+        }
         atomicOr(&R.st->err, ERR_BIN);
+    }
 }
 
-// Sort each bin's atom list so that the neighbour order does not depend on
+// Sorts each bin's atoms so that the neighbour order does not depend on
 // the order in which atoms were binned.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict__ runs,
@@ -331,6 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict
     }
 }
 
+// Verlet list of atom i: every atom within rc + skin in its own and the 26
+// surrounding bins, in bin order and ascending index within a bin.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restrict__ runs,
                                                       const int2* __restrict__ work)
@@ -345,6 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
     int b3[3];
     bin_of(R, position(R, si, i), b3);
     int count = 0;
+    const size_t n = (size_t)R.n;
     for (int dz = -1; dz <= 1; ++dz) {
         const int bz = wrapi(b3[2] + dz, R.nbin[2]);
         for (int dy = -1; dy <= 1; ++dy) {
@@ -360,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
                     if (j == i) continue;
                     const V3<T> d = separation(R, si, ui, j);
                     if (d.x * d.x + d.y * d.y + d.z * d.z < R.rlist2) {
-                        if (count < R.max_nbr) R.nbr[(size_t)count * R.n + i] = j;
+                        if (count < R.max_nbr) R.nbr[(size_t)count * n + i] = j;
                         ++count;
                     }
                 }
@@ -368,6 +410,10 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
         }
     }
     if (count > R.max_nbr) {
+        if (atomicCAS(&R.st->bad_atom, 0, i + 1) == 0) {
+            R.st->bad_count = count;
+            R.st->bad_step = R.st->step;
+        }
         atomicOr(&R.st->err, ERR_NBR);
         count = R.max_nbr;
     }
@@ -397,6 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
                                                        const int2* __restrict__ work, int phase)
 {
     __shared__ double lds[(kBlock / 64) * NQ];
+    __shared__ unsigned long long cacc[kLdsCells];
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     int64_t step = R.st->step;
@@ -406,6 +453,14 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
     const bool obs = R.obs_every > 0 &&
                      (phase == PHASE_INIT || ((step + 1) % R.obs_every) == 0);
     if (!R.live && !obs) return;
+    // electron-phonon energy per cell: first summed in LDS (fixed point, so
+    // the order does not matter), then one global atomic per touched cell
+    const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
+    const bool lds_acc = eph && R.ncell <= kLdsCells;
+    if (lds_acc) {
+        for (int c = threadIdx.x; c < R.ncell; c += kBlock) cacc[c] = 0ull;
+        __syncthreads();
+    }
     const int i = w.y + (int)threadIdx.x;
     const bool valid = i < R.n;
     double q[NQ];
@@ -419,20 +474,35 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
             T Fx = T(0), Fy = T(0), Fz = T(0);
             double pe = 0.0;
             const int nn = R.nbr_n[i];
-            for (int k = 0; k < nn; ++k) {
-                const int j = R.nbr[(size_t)k * R.n + i];
-                const V3<T> d = separation(R, si, ui, j);
-                const T r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-                if (r2 < R.rc2) {
-                    const T r = sqrt(r2);
-                    const T e1 = exp(-R.ma * (r - R.mr0));
-                    const T e2 = e1 * e1;
-                    // -dV/dr along +d pushes j; the force on i is its opposite
-                    const T f = T(2) * R.ma * R.mD * (e2 - e1) / r;
-                    Fx -= f * d.x;
-                    Fy -= f * d.y;
-                    Fz -= f * d.z;
-                    if (obs) pe += 0.5 * ((double)(R.mD * (e2 - T(2) * e1)) - (double)R.Vc);
+            const size_t n = (size_t)R.n;
+            // neighbours in chunks of 8: all index loads, then all position
+            // loads, then the arithmetic (two memory round trips per chunk)
+            for (int k0 = 0; k0 < nn; k0 += 8) {
+                int jj[8];
+                T dx[8], dy[8], dz[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) jj[q] = k0 + q < nn ? R.nbr[(size_t)(k0 + q) * n + i] : i;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const V3<T> d = separation(R, si, ui, jj[q]);
+                    dx[q] = d.x;
+                    dy[q] = d.y;
+                    dz[q] = d.z;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const T r2 = dx[q] * dx[q] + dy[q] * dy[q] + dz[q] * dz[q];
+                    if (k0 + q < nn && r2 < R.rc2) {
+                        const T r = sqrt(r2);
+                        const T e1 = exp(-R.ma * (r - R.mr0));
+                        const T e2 = e1 * e1;
+                        // -dV/dr along +d pushes j; the force on i is its opposite
+                        const T f = T(2) * R.ma * R.mD * (e2 - e1) / r;
+                        Fx -= f * dx[q];
+                        Fy -= f * dy[q];
+                        Fz -= f * dz[q];
+                        if (obs) pe += 0.5 * ((double)(R.mD * (e2 - T(2) * e1)) - (double)R.Vc);
+                    }
                 }
             }
             T vx = R.vx[i], vy = R.vy[i], vz = R.vz[i];
@@ -457,7 +527,10 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
                     const double dE = R.ou_1mc2 * (1.5 * kKB * Te - ke);
                     if (fabs(dE) < 1.0e3) {
                         const long long fixp = llrint(dE * kFIX);
-                        atomicAdd(&R.dE[c], (unsigned long long)fixp);
+                        if (lds_acc)
+                            atomicAdd(&cacc[c], (unsigned long long)fixp);
+                        else
+                            atomicAdd(&R.dE[c], (unsigned long long)fixp);
                     } else {
                         atomicOr(&R.st->err, ERR_DE);
                     }
@@ -502,6 +575,11 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
             }
         }
     }
+    if (lds_acc) {
+        __syncthreads();
+        for (int c = threadIdx.x; c < R.ncell; c += kBlock)
+            if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
+    }
     if (!obs) return;
     block_reduce_nq(q, lds);
     if (threadIdx.x < NQ) {
@@ -520,13 +598,82 @@ template <typename T> __device__ inline double laser_power(const RunDev<T>& R, d
     return R.S0 * exp(-4.0 * 0.69314718055994530942 * d * d / (R.fwhm * R.fwhm));
 }
 
+// One explicit diffusion sub-step of e = gamma_e T^2 / 2 with the periodic
+// 7-point Laplacian: reads T from one buffer, writes the next.  The first
+// sub-step of a step starts e from the current T.
 template <typename T>
-__global__ __launch_bounds__(kEndBlock) void k_end_step(const RunDev<T>* __restrict__ runs,
-                                                        const int* __restrict__ run_list,
-                                                        int phase)
+__global__ __launch_bounds__(kBlock) void k_ttm_diffuse(const RunDev<T>* __restrict__ runs,
+                                                        const int2* __restrict__ work, int sub)
 {
-    __shared__ double red[kEndBlock];
-    __shared__ double red2[kEndBlock];
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (!run_active(R, &step)) return;
+    if (R.ttm_mode != 1 || R.kappa_e == 0.0 || sub >= R.n_sub) return;
+    const int c = w.y + (int)threadIdx.x;
+    if (c >= R.ncell) return;
+    const double* src = (sub & 1) ? R.Te_alt : R.Te;
+    double* dst = (sub & 1) ? R.Te : R.Te_alt;
+    const int n0 = R.tn[0], n1 = R.tn[1], n2 = R.tn[2];
+    const int i = c % n0, j = (c / n0) % n1, k = c / (n0 * n1);
+    const int ip = (i + 1) % n0, im = (i + n0 - 1) % n0;
+    const int jp = (j + 1) % n1, jm = (j + n1 - 1) % n1;
+    const int kp = (k + 1) % n2, km = (k + n2 - 1) % n2;
+    const int row = (k * n1 + j) * n0;
+    const double Tc = src[c];
+    const double lap = (src[row + ip] - 2.0 * Tc + src[row + im]) / (R.th[0] * R.th[0]) +
+                       (src[(k * n1 + jp) * n0 + i] - 2.0 * Tc + src[(k * n1 + jm) * n0 + i]) /
+                           (R.th[1] * R.th[1]) +
+                       (src[(kp * n1 + j) * n0 + i] - 2.0 * Tc + src[(km * n1 + j) * n0 + i]) /
+                           (R.th[2] * R.th[2]);
+    const double e0 = sub == 0 ? 0.5 * R.gamma_e * Tc * Tc : R.ee[c];
+    const double e = e0 + (R.dtd / (double)R.n_sub) * R.kappa_e * lap;
+    R.ee[c] = e;
+    if (e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
+    dst[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / R.gamma_e);
+}
+
+// Laser source and electron-phonon energy of one cell (two-temperature
+// mode): e = (after diffusion, or gamma_e T^2 / 2) + dt S(z, t + dt/2)
+// - dE / V, T_e = sqrt(2 e / gamma_e).
+template <typename T> __device__ inline void cell_update(const RunDev<T>& R, int c, int64_t step)
+{
+    const double ge = R.gamma_e;
+    const double T0 = R.Te[c];
+    const double e0 = R.kappa_e != 0.0 ? R.ee[c] : 0.5 * ge * T0 * T0;
+    const int k = c / (R.tn[0] * R.tn[1]);
+    const double tmid = ((double)step + 0.5) * R.dtd;
+    const double src = laser_power(R, (k + 0.5) * R.th[2], tmid);
+    const double de = (double)(long long)R.dE[c] / kFIX;
+    R.dE[c] = 0ull;
+    const double e = e0 + R.dtd * src - de / R.Vcell;
+    R.ee[c] = e;
+    if (e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
+    R.Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
+}
+
+// Cell-parallel update of large electron grids (ncell > kSmallGrid).
+constexpr int kSmallGrid = 4096;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ runs,
+                                                 const int2* __restrict__ work)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (!run_active(R, &step) || R.ttm_mode != 1 || R.ncell <= kSmallGrid) return;
+    const int c = w.y + (int)threadIdx.x;
+    if (c < R.ncell) cell_update(R, c, step);
+}
+
+// One block per run: small electron grids, the observable sample (fixed
+// order over blocks and cells), bins emptied after a rebuild, step + 1.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
+                                                     const int* __restrict__ run_list, int phase)
+{
+    __shared__ double red[3][kBlock];
     __shared__ double tot[NQ];
     const RunDev<T>& R = runs[run_list[blockIdx.x]];
     RunState* st = R.st;
@@ -534,55 +681,8 @@ __global__ __launch_bounds__(kEndBlock) void k_end_step(const RunDev<T>* __restr
     if (phase == PHASE_STEP && (st->err != 0 || step >= st->target)) return;
     const int tid = threadIdx.x;
     const int nc = R.ncell;
-    // two-temperature update of the electron energy density gamma_e T^2 / 2
-    if (phase == PHASE_STEP && R.ttm_mode == 1) {
-        const double ge = R.gamma_e;
-        for (int c = tid; c < nc; c += kEndBlock) {
-            const double T0 = R.Te[c];
-            R.ee[c] = 0.5 * ge * T0 * T0;
-        }
-        __syncthreads();
-        if (R.kappa_e != 0.0) {
-            const double dts = R.dtd / (double)R.n_sub;
-            const double ih0 = 1.0 / (R.th[0] * R.th[0]), ih1 = 1.0 / (R.th[1] * R.th[1]),
-                         ih2 = 1.0 / (R.th[2] * R.th[2]);
-            for (int sub = 0; sub < R.n_sub; ++sub) {
-                for (int c = tid; c < nc; c += kEndBlock) {
-                    const int i = c % R.tn[0];
-                    const int j = (c / R.tn[0]) % R.tn[1];
-                    const int k = c / (R.tn[0] * R.tn[1]);
-                    const int ip = (i + 1) % R.tn[0], im = (i + R.tn[0] - 1) % R.tn[0];
-                    const int jp = (j + 1) % R.tn[1], jm = (j + R.tn[1] - 1) % R.tn[1];
-                    const int kp = (k + 1) % R.tn[2], km = (k + R.tn[2] - 1) % R.tn[2];
-                    const int row = (k * R.tn[1] + j) * R.tn[0];
-                    const double Tc = R.Te[c];
-                    R.lap[c] = (R.Te[row + ip] - 2.0 * Tc + R.Te[row + im]) * ih0 +
-                               (R.Te[(k * R.tn[1] + jp) * R.tn[0] + i] - 2.0 * Tc +
-                                R.Te[(k * R.tn[1] + jm) * R.tn[0] + i]) * ih1 +
-                               (R.Te[(kp * R.tn[1] + j) * R.tn[0] + i] - 2.0 * Tc +
-                                R.Te[(km * R.tn[1] + j) * R.tn[0] + i]) * ih2;
-                }
-                __syncthreads();
-                for (int c = tid; c < nc; c += kEndBlock) {
-                    const double e = R.ee[c] + dts * R.kappa_e * R.lap[c];
-                    R.ee[c] = e;
-                    if (e < 0.0) atomicOr(&st->err, ERR_NEG_E);
-                    R.Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
-                }
-                __syncthreads();
-            }
-        }
-        const double tmid = ((double)step + 0.5) * R.dtd;
-        for (int c = tid; c < nc; c += kEndBlock) {
-            const int k = c / (R.tn[0] * R.tn[1]);
-            const double src = laser_power(R, (k + 0.5) * R.th[2], tmid);
-            const double de = (double)(long long)R.dE[c] / kFIX;
-            R.dE[c] = 0ull;
-            const double e = R.ee[c] + R.dtd * src - de / R.Vcell;
-            R.ee[c] = e;
-            if (e < 0.0) atomicOr(&st->err, ERR_NEG_E);
-            R.Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
-        }
+    if (phase == PHASE_STEP && R.ttm_mode == 1 && nc <= kSmallGrid) {
+        for (int c = tid; c < nc; c += kBlock) cell_update(R, c, step);
         __syncthreads();
     }
     const bool obs = R.obs_every > 0 &&
@@ -594,28 +694,22 @@ __global__ __launch_bounds__(kEndBlock) void k_end_step(const RunDev<T>* __restr
             tot[tid] = acc;
         }
         double eacc = 0.0, tacc = 0.0, tmax = 0.0;
-        for (int c = tid; c < nc; c += kEndBlock) {
+        for (int c = tid; c < nc; c += kBlock) {
             const double Tc = R.Te[c];
             eacc += 0.5 * R.gamma_e * Tc * Tc * R.Vcell;
             tacc += Tc;
             tmax = Tc > tmax ? Tc : tmax;
         }
-        red[tid] = eacc;
-        red2[tid] = tacc;
+        red[0][tid] = eacc;
+        red[1][tid] = tacc;
+        red[2][tid] = tmax;
         __syncthreads();
-        for (int off = kEndBlock / 2; off > 0; off >>= 1) {
+        for (int off = kBlock / 2; off > 0; off >>= 1) {
             if (tid < off) {
-                red[tid] += red[tid + off];
-                red2[tid] += red2[tid + off];
+                red[0][tid] += red[0][tid + off];
+                red[1][tid] += red[1][tid + off];
+                red[2][tid] = red[2][tid] > red[2][tid + off] ? red[2][tid] : red[2][tid + off];
             }
-            __syncthreads();
-        }
-        const double E_e = red[0], Tsum = red2[0];
-        __syncthreads();
-        red[tid] = tmax;
-        __syncthreads();
-        for (int off = kEndBlock / 2; off > 0; off >>= 1) {
-            if (tid < off) red[tid] = red[tid] > red[tid + off] ? red[tid] : red[tid + off];
             __syncthreads();
         }
         if (tid == 0) {
@@ -636,18 +730,18 @@ __global__ __launch_bounds__(kEndBlock) void k_end_step(const RunDev<T>* __restr
             o->E_z = tot[13];
             o->KE = tot[14];
             o->PE = tot[15];
-            o->E_e = E_e;
-            o->Te_mean = Tsum / (double)nc;
-            o->Te_max = red[0];
+            o->E_e = red[0][0];
+            o->Te_mean = red[1][0] / (double)nc;
+            o->Te_max = red[2][0];
             o->Tl = 2.0 * tot[14] / (3.0 * (double)R.n * kKB);
             for (int sp = 0; sp < 4; ++sp)
                 o->Tspin[sp] = tot[20 + sp] != 0.0 ? tot[16 + sp] / (2.0 * kKB * tot[20 + sp]) : 0.0;
             st->n_samples = ns + 1;
         }
     }
-    // neighbour bins are emptied after a rebuild
+    // neighbour bins are emptied after a rebuild, ready for the next one
     if (R.live && st->rebuild != 0) {
-        for (int b = tid; b < R.nbins; b += kEndBlock) R.bin_n[b] = 0;
+        for (int b = tid; b < R.nbins; b += kBlock) R.bin_n[b] = 0;
         __syncthreads();
         if (tid == 0) st->rebuild = 0;
     }

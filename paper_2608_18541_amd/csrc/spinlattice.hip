@@ -189,9 +189,16 @@ Sizes run_sizes(const sl_system_desc* d, const sl_ttm_desc* t)
             w3 *= L / z.nbx[k];
             z.nbins *= z.nbx[k];
         }
-        z.bin_cap = std::max(16, (int)std::ceil(3.0 * w3 / vol_site) + 8);
-        const double sphere = 4.18879020478639 * reach * reach * reach / vol_site;
-        z.max_nbr = (int)std::ceil(1.8 * sphere + 8.0);
+        // capacities bound the densest packing the pair potential allows:
+        // close packing at the Morse minimum, sqrt(2)/r0^3 atoms per A^3
+        // (a strained lattice may collapse locally towards it) or the
+        // lattice density if that is larger, with a margin for thermal
+        // compression
+        const double r0 = std::max(d->morse[2], 0.5);
+        const double dens = std::max(1.4142135623730951 / (r0 * r0 * r0), 1.0 / vol_site);
+        z.bin_cap = (int)std::ceil(2.0 * w3 * dens) + 8;
+        const double sphere = 4.18879020478639 * reach * reach * reach * dens;
+        z.max_nbr = (int)std::ceil(1.6 * sphere + 8.0);
     }
     return z;
 }
@@ -524,8 +531,13 @@ private:
     int2* d_work_spin = nullptr;
     int2* d_work_atom = nullptr;
     int2* d_work_bin = nullptr;
+    int2* d_work_cell = nullptr;
+    int2* d_work_diff = nullptr;
     int* d_run_list = nullptr;
-    int active_blocks_spin = 0, active_blocks_atom = 0, active_blocks_bin = 0, active_runs = 0;
+    int active_runs = 0;
+    int active_blocks_spin = 0, active_blocks_atom = 0, active_blocks_bin = 0, active_blocks_cell = 0,
+        active_blocks_diff = 0;
+    int max_sub = 0;
     bool any_live = false;
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
@@ -533,7 +545,14 @@ private:
 
     sl_status numeric_error(int s, int err)
     {
+        sl::RunState rs{};
+        (void)hipMemcpy(&rs, host_rd[s].st, sizeof(rs), hipMemcpyDeviceToHost);
         std::string m = "run in slot " + std::to_string(s) + " stopped:";
+        if (rs.bad_atom > 0)
+            m += " [atom " + std::to_string(rs.bad_atom - 1) + " count " +
+                 std::to_string(rs.bad_count) + " at step " + std::to_string(rs.bad_step) +
+                 ", list capacity " + std::to_string(host_rd[s].max_nbr) + ", bin capacity " +
+                 std::to_string(host_rd[s].bin_cap) + "]";
         if (err & sl::ERR_NEG_E) m += " negative electron energy density;";
         if (err & sl::ERR_BIN) m += " neighbour bin overflow;";
         if (err & sl::ERR_NBR) m += " neighbour list overflow;";
@@ -692,8 +711,9 @@ private:
         c.base = static_cast<char*>(r.grid);
         R.Te = c.take<double>(r.z.ncell);
         R.ee = c.take<double>(r.z.ncell);
-        R.lap = c.take<double>(r.z.ncell);
+        R.Te_alt = c.take<double>(r.z.ncell);
         R.dE = c.take<unsigned long long>(r.z.ncell);
+
         std::vector<double> te(r.z.ncell, t->Te0);
         if (t->Te_init) std::copy(t->Te_init, t->Te_init + r.z.ncell, te.begin());
         r.te_init = te;
@@ -768,28 +788,29 @@ private:
         SL_HIP(hipMemsetAsync(R.dE, 0, sizeof(unsigned long long) * r.z.ncell, stream));
         SL_HIP(hipMemcpyAsync(d_runs + s, &R, sizeof(RD), hipMemcpyHostToDevice, stream));
         // single-run work tables for the initialisation launches
-        std::vector<int2> wa, wb;
+        std::vector<int2> wa, wb, wc;
         for (int st = 0; st < R.n; st += sl::kBlock) wa.push_back(make_int2(s, st));
         for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2(s, st));
-        int one = s;
-        void* tmp = alloc.get(sizeof(int2) * (wa.size() + wb.size() + 1) + 512);
+        void* tmp = alloc.get(sizeof(int2) * (wa.size() + wb.size() + wc.size()) + 512);
         if (!tmp) return fail(SL_ENOMEM, "device allocation failed");
         int2* dwa = static_cast<int2*>(tmp);
         int2* dwb = dwa + wa.size();
-        int* drl = reinterpret_cast<int*>(dwb + wb.size());
+        int2* dwc = dwb + wb.size();
+        int* drl = reinterpret_cast<int*>(dwc + wc.size());
+        const int one = s;
+        SL_HIP(hipMemcpyAsync(drl, &one, sizeof(int), hipMemcpyHostToDevice, stream));
         SL_HIP(hipMemcpyAsync(dwa, wa.data(), sizeof(int2) * wa.size(), hipMemcpyHostToDevice, stream));
         if (!wb.empty())
             SL_HIP(hipMemcpyAsync(dwb, wb.data(), sizeof(int2) * wb.size(), hipMemcpyHostToDevice, stream));
-        SL_HIP(hipMemcpyAsync(drl, &one, sizeof(int), hipMemcpyHostToDevice, stream));
         const int ga = (int)wa.size();
         sl::k_kick_drift<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
         if (R.live) {
             sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
-            sl::k_nbr_sort<T><<<(int)wb.size(), sl::kBlock, 0, stream>>>(d_runs, dwb);
+            sl::k_nbr_sort<T><<<(R.nbins + sl::kBlock - 1) / sl::kBlock, sl::kBlock, 0, stream>>>(d_runs, dwb);
             sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         }
         sl::k_atom_final<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
-        sl::k_end_step<T><<<1, sl::kEndBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
+        sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
         SL_HIP(hipGetLastError());
         SL_HIP(hipStreamSynchronize(stream));
         alloc.put(tmp);
@@ -805,26 +826,35 @@ private:
     {
         drop_graph();
         tables_dirty = false;
-        std::vector<int2> ws, wa, wb;
+        std::vector<int2> ws, wa, wb, wc, wd;
         std::vector<int> rl;
         any_live = false;
+        max_sub = 0;
         for (size_t s = 0; s < runs.size(); ++s) {
             if (!runs[s].used) continue;
             const RD& R = host_rd[s];
             for (int st = 0; st < R.g.H; st += sl::kBlock) ws.push_back(make_int2((int)s, st));
             for (int st = 0; st < R.n; st += sl::kBlock) wa.push_back(make_int2((int)s, st));
             for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2((int)s, st));
+            if (R.ttm_mode == 1 && R.ncell > sl::kSmallGrid)
+                for (int st = 0; st < R.ncell; st += sl::kBlock) wc.push_back(make_int2((int)s, st));
             rl.push_back((int)s);
+            if (R.ttm_mode == 1 && R.kappa_e != 0.0) {
+                for (int st = 0; st < R.ncell; st += sl::kBlock) wd.push_back(make_int2((int)s, st));
+                max_sub = std::max(max_sub, R.n_sub);
+            }
             any_live = any_live || R.live;
         }
         for (void* p : tables) alloc.put(p);
         tables.clear();
-        d_work_spin = d_work_atom = d_work_bin = nullptr;
-        d_run_list = nullptr;
+        d_work_spin = d_work_atom = d_work_bin = d_work_cell = d_work_diff = nullptr;
         active_blocks_spin = (int)ws.size();
         active_blocks_atom = (int)wa.size();
         active_blocks_bin = (int)wb.size();
+        active_blocks_cell = (int)wc.size();
+        active_blocks_diff = (int)wd.size();
         active_runs = (int)rl.size();
+        d_run_list = nullptr;
         auto up = [&](const void* src, size_t bytes, void** dst) -> sl_status {
             if (bytes == 0) return SL_OK;
             void* p = alloc.get(bytes);
@@ -838,6 +868,8 @@ private:
         if ((st = up(ws.data(), sizeof(int2) * ws.size(), (void**)&d_work_spin)) != SL_OK) return st;
         if ((st = up(wa.data(), sizeof(int2) * wa.size(), (void**)&d_work_atom)) != SL_OK) return st;
         if ((st = up(wb.data(), sizeof(int2) * wb.size(), (void**)&d_work_bin)) != SL_OK) return st;
+        if ((st = up(wc.data(), sizeof(int2) * wc.size(), (void**)&d_work_cell)) != SL_OK) return st;
+        if ((st = up(wd.data(), sizeof(int2) * wd.size(), (void**)&d_work_diff)) != SL_OK) return st;
         if ((st = up(rl.data(), sizeof(int) * rl.size(), (void**)&d_run_list)) != SL_OK) return st;
         SL_HIP(hipStreamSynchronize(stream));
         return SL_OK;
@@ -894,8 +926,20 @@ private:
                                                                           sl::PHASE_STEP);
         });
         if (e != SL_OK) return e;
+        for (int sub = 0; sub < max_sub; ++sub) {
+            e = timed(st, p, 3, [&] {
+                sl::k_ttm_diffuse<T><<<active_blocks_diff, sl::kBlock, 0, st>>>(d_runs, d_work_diff, sub);
+            });
+            if (e != SL_OK) return e;
+        }
+        if (active_blocks_cell > 0) {
+            e = timed(st, p, 3, [&] {
+                sl::k_grid<T><<<active_blocks_cell, sl::kBlock, 0, st>>>(d_runs, d_work_cell);
+            });
+            if (e != SL_OK) return e;
+        }
         e = timed(st, p, 3, [&] {
-            sl::k_end_step<T><<<active_runs, sl::kEndBlock, 0, st>>>(d_runs, d_run_list, sl::PHASE_STEP);
+            sl::k_finalize<T><<<active_runs, sl::kBlock, 0, st>>>(d_runs, d_run_list, sl::PHASE_STEP);
         });
         return e;
     }
@@ -1073,6 +1117,12 @@ sl_status sl_batch_advance(sl_batch b, int64_t n_steps)
 {
     if (!b) return fail(SL_EINVAL, "null handle");
     return b->eng->advance(n_steps);
+}
+
+sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[4], int64_t launches[4])
+{
+    if (!b || !avg_ms || !launches) return fail(SL_EINVAL, "null argument");
+    return b->eng->profiled(n_steps, avg_ms, launches);
 }
 
 sl_status sl_batch_runs(sl_batch b, sl_run_info* info, int32_t cap, int32_t* n_out)

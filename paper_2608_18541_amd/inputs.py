@@ -306,3 +306,17 @@ def cfg1_S0() -> float:
     """32^3 alloy workload: 50 fs FWHM pulse centred at 100 fs, peak
     T_e about 1800 K."""
     return laser_S0_metal(1800.0, 0.05, 0.1)
+
+
+def fe_large_spec(L: int = 64, tn: int = 32, **kw) -> SystemSpec:
+    """bcc Fe L^3 cells with the Fe-block exchange and Morse lattice, tn^3
+    grid with the alloy's two-temperature constants, kappa_e = 80 W/m/K
+    (4 diffusion sub-steps), 100 fs pulse absorbed in the top 10 nm with
+    peak T_e about 1500 K (surface heating)."""
+    t0, fwhm = 0.2, 0.1
+    s = fe_bcc_spec(L=L, tn=(tn, tn, tn), ttm_mode=1, Te0=300.0,
+                    gamma_e=j_per_m3k2_to_metal(225.0), G_el=w_per_m3k_to_metal(6.6e17),
+                    kappa_e=w_per_mk_to_metal(80.0), n_sub=4,
+                    S0=laser_S0_metal(1500.0, fwhm, t0), t0=t0, fwhm=fwhm, profile=1,
+                    depth=100.0)
+    return replace(s, **kw)

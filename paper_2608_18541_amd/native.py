@@ -104,6 +104,8 @@ EXPORTS = {
     "sl_batch_add": (C.c_int32, [C.c_void_p, C.POINTER(sl_system_desc), C.POINTER(sl_ttm_desc),
                                  C.c_int64, C.POINTER(C.c_int32)]),
     "sl_batch_advance": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "sl_batch_advance_profiled": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(C.c_double),
+                                              C.POINTER(C.c_int64)]),
     "sl_batch_runs": (C.c_int32, [C.c_void_p, C.POINTER(sl_run_info), C.c_int32,
                                   C.POINTER(C.c_int32)]),
     "sl_batch_get": (C.c_int32, [C.c_void_p, C.c_int32] + [C.POINTER(C.c_double)] * 4 +
@@ -374,6 +376,12 @@ class Batch:
 
     def advance(self, n: int) -> None:
         check(lib().sl_batch_advance(self._h, int(n)))
+
+    def advance_profiled(self, n: int):
+        avg = (C.c_double * 4)()
+        cnt = (C.c_int64 * 4)()
+        check(lib().sl_batch_advance_profiled(self._h, int(n), avg, cnt))
+        return list(avg), list(cnt)
 
     def runs(self) -> list:
         cap = 1 << 16

@@ -37,6 +37,7 @@ class Result:
     switched: Optional[bool] = None
     mz_gd: Optional[np.ndarray] = None
     state: Optional[dict] = None
+    error: Optional[str] = None
 
     @property
     def latency(self) -> float:
@@ -108,20 +109,27 @@ class Server:
                     self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
                 continue
             self.ex.advance(self.chunk)
-            self.ex.synchronize()
+            try:
+                self.ex.synchronize()
+            except RuntimeError:
+                pass                             # reported per run when collected
             self.log.append((self.clock() - t0, len(active), len(waiting)))
             for info in self.ex.runs():
                 s = info["slot"]
                 if s not in active or info["steps_done"] < info["steps_target"]:
                     continue
                 req, t_adm = active.pop(s)
-                out = self.ex.get(s)
+                err = None
+                try:
+                    out = self.ex.get(s)
+                except RuntimeError as e:       # the run stopped on a numerical error
+                    out, err = {}, str(e)
                 fin = self.clock() - t0
                 mz = np.array([o["M"][1][2] for o in out.get("obs", [])])
                 res = Result(rid=req.rid, arrival=req.arrival, admitted=t_adm, finished=fin,
                              n_steps=req.run.n_steps, n_sites=req.run.spec.n_sites,
                              switched=switched(mz) if mz.size > 1 else None, mz_gd=mz,
-                             state=out if self.keep_state else None)
+                             state=out if self.keep_state else None, error=err)
                 done.append(res)
                 self.ex.remove(s)
         self.makespan = self.clock() - t0
