@@ -183,6 +183,21 @@ sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
  * electron-phonon step, 2 kick-drift, 3 end-of-step (grid, reductions). */
 sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[4], int64_t launches[4]);
 
+/* Launch shape of the step kernels.  Every choice performs the same
+ * arithmetic in the same order for each site, atom and cell, so results are
+ * bitwise identical; only the speed changes (an autotuner picks it). */
+typedef struct sl_tuning {
+    int32_t spin_block;       /* threads per block of the colour passes: 64, 128, 256 */
+    int32_t spin_spt;         /* sites per thread in a colour pass: 1, 2, 4          */
+    int32_t atom_block;       /* threads per block of the lattice kernels: 64..256   */
+    int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256         */
+} sl_tuning;
+
+/* Waits for the stream, then applies a launch shape (SL_EINVAL if out of
+ * range; nothing changes then). */
+sl_status sl_set_tuning(sl_system h, const sl_tuning* t);
+sl_status sl_get_tuning(sl_system h, sl_tuning* t);
+
 void sl_destroy(sl_system h);
 
 /* Message of the calling thread's last failed call ("" if none). */
@@ -240,6 +255,10 @@ sl_status sl_batch_remove(sl_batch b, int32_t slot);
  * kernel class (as sl_step_profiled) and the launch counts. */
 sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[4],
                                     int64_t launches[4]);
+
+/* Launch shape of a batch (as sl_set_tuning / sl_get_tuning). */
+sl_status sl_batch_set_tuning(sl_batch b, const sl_tuning* t);
+sl_status sl_batch_get_tuning(sl_batch b, sl_tuning* t);
 
 /* Bytes of the budget in use. */
 sl_status sl_batch_memory(sl_batch b, size_t* used, size_t* budget);

@@ -122,11 +122,13 @@ __device__ inline Normals3<float> normals3_f32(uint32_t seed, uint32_t run, uint
     float u1 = ((float)(w.y >> 8) + 0.5f) * 5.9604644775390625e-8f;
     float u2 = ((float)(w.z >> 8) + 0.5f) * 5.9604644775390625e-8f;
     float u3 = ((float)(w.w >> 8) + 0.5f) * 5.9604644775390625e-8f;
-    float r0 = sqrtf(-2.0f * logf(u0));
-    float r1 = sqrtf(-2.0f * logf(u2));
+    // hardware log / sin / cos (a few ulp): the single-precision path is
+    // compared with double precision statistically, not per trajectory
+    float r0 = sqrtf(-2.0f * __logf(u0));
+    float r1 = sqrtf(-2.0f * __logf(u2));
     float s1, c1;
-    sincospif(2.0f * u1, &s1, &c1);
-    float c3 = cospif(2.0f * u3);
+    __sincosf(6.28318530717958648f * u1, &s1, &c1);
+    float c3 = __cosf(6.28318530717958648f * u3);
     return {r0 * c1, r0 * s1, r1 * c3};
 }
 
@@ -159,7 +161,9 @@ template <typename T> struct V3 {
 };
 
 __device__ inline void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ inline void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ inline void sin_cos(float x, float* s, float* c) { __sincosf(x, s, c); }
+__device__ inline double expo(double x) { return exp(x); }
+__device__ inline float expo(float x) { return __expf(x); }
 
 template <typename T>
 __device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2)
@@ -172,7 +176,7 @@ __device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2)
     T u = s.x * e.x + s.y * e.y + s.z * e.z;
     V3<T> p{s.x - u * e.x, s.y - u * e.y, s.z - u * e.z};
     T phi = wn * tau * inv1pa2;
-    T E = exp(-alpha * phi);
+    T E = expo(-alpha * phi);
     T E2 = E * E;
     T D = (T(1) + u) + (T(1) - u) * E2;
     T iD = T(1) / D;

@@ -45,6 +45,12 @@ struct RunState {
     int64_t pad;
 };
 
+// Wrapped absolute position of an atom, padded to a 16/32-byte vector so a
+// neighbour's position is one load.
+template <typename T> struct alignas(4 * sizeof(T)) Pos4 {
+    T x, y, z, w;
+};
+
 template <typename T> struct RunDev {
     Geom g;
     int32_t lattice, n, n_species, n_shells, live, ttm_mode, obs_every, obs_cap;
@@ -72,6 +78,7 @@ template <typename T> struct RunDev {
     T binw[3];
     // device arrays
     T *sx, *sy, *sz, *ux, *uy, *uz, *vx, *vy, *vz, *fx, *fy, *fz, *rx, *ry, *rz;
+    Pos4<T>* pos;                    // wrap(ideal site + u), refreshed by k_kick_drift
     int8_t* species;
     uint16_t* cell;
     int32_t *nbr, *nbr_n;
@@ -185,21 +192,35 @@ template <typename T> __device__ inline T min_image(T d, T box, T half)
     return d > half ? d - box : (d < -half ? d + box : d);
 }
 
-// Separation x_j - x_i (minimum image) from the ideal sites and displacements.
+// Separation x_j - x_i (minimum image) from the wrapped positions.
 template <typename T>
-__device__ inline V3<T> separation(const RunDev<T>& R, const Site& si, const V3<T>& ui,
-                                   int j)
+__device__ inline V3<T> separation(const RunDev<T>& R, const Pos4<T>& pi, int j)
 {
-    Site sj = decode_site(R.g, (uint32_t)j);
-    const T hb = T(0.5) * (T)(sj.b - si.b);
-    V3<T> d;
-    d.x = ((T)wrap_cell_delta(sj.x - si.x, R.g.Lx) + hb) * R.a + (R.ux[j] - ui.x);
-    d.y = ((T)wrap_cell_delta(sj.y - si.y, R.g.Ly) + hb) * R.a + (R.uy[j] - ui.y);
-    d.z = ((T)wrap_cell_delta(sj.z - si.z, R.g.Lz) + hb) * R.a + (R.uz[j] - ui.z);
+    const Pos4<T> pj = R.pos[j];
+    V3<T> d{pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
     d.x = min_image(d.x, R.box[0], R.half_box[0]);
     d.y = min_image(d.y, R.box[1], R.half_box[1]);
     d.z = min_image(d.z, R.box[2], R.half_box[2]);
     return d;
+}
+
+// Morse force factor f = -dV/dr / r and pair energy V(r) - V(rc).  The
+// single-precision path uses the hardware exponential and reciprocal
+// square root; double precision stays correctly rounded.
+__device__ inline float morse_f(float r2, float a, float D, float r0, float* r_out)
+{
+    const float ir = rsqrtf(r2);
+    const float r = r2 * ir;
+    *r_out = r;
+    const float e1 = __expf(-a * (r - r0));
+    return 2.0f * a * D * (e1 * e1 - e1) * ir;
+}
+__device__ inline double morse_f(double r2, double a, double D, double r0, double* r_out)
+{
+    const double r = sqrt(r2);
+    *r_out = r;
+    const double e1 = exp(-a * (r - r0));
+    return 2.0 * a * D * (e1 * e1 - e1) / r;
 }
 
 template <typename T> __device__ inline T wrap_box(T x, T L)
@@ -246,20 +267,13 @@ template <typename T> __device__ inline bool run_active(const RunDev<T>& R, int6
 }
 
 // ------------------------------------------------------------ spins
+// One colour pass.  Block b updates the SPT * blockDim sites of its tile
+// starting at work[b].y; a site's arithmetic does not depend on SPT or the
+// block size, so every launch shape gives bitwise-identical spins.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
-                                                      const int2* __restrict__ work, int pass)
+__device__ __forceinline__ void spin_site(const RunDev<T>& R, int colour, T tau, int l,
+                                          int64_t step)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    int64_t step;
-    if (!run_active(R, &step)) return;
-    const int C = R.g.C;
-    if (pass >= 2 * C - 1) return;
-    const int colour = pass < C ? pass : 2 * C - 2 - pass;
-    const T tau = (pass == C - 1) ? R.dt : R.tau_half;
-    const int l = w.y + (int)threadIdx.x;
-    if (l >= R.g.H) return;
     const int idx = colour * R.g.H + l;
     const uint32_t r = fdiv((uint32_t)l, R.g.divLxh);
     const int xh = l - (int)r * R.g.Lxh;
@@ -287,6 +301,25 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     R.sx[idx] = s.x;
     R.sy[idx] = s.y;
     R.sz[idx] = s.z;
+}
+
+template <typename T, int SPT>
+__global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
+                                                      const int2* __restrict__ work, int pass)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (!run_active(R, &step)) return;
+    const int C = R.g.C;
+    if (pass >= 2 * C - 1) return;
+    const int colour = pass < C ? pass : 2 * C - 2 - pass;
+    const T tau = (pass == C - 1) ? R.dt : R.tau_half;
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int l = w.y + k * (int)blockDim.x + (int)threadIdx.x;
+        if (l < R.g.H) spin_site(R, colour, tau, l, step);
+    }
 }
 
 // ------------------------------------------------------------ lattice
@@ -319,6 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(const RunDev<T>* __restri
     }
     const V3<T> p = position(R, s, i);
     R.cell[i] = (uint16_t)electron_cell(R, p);
+    if (R.live) R.pos[i] = Pos4<T>{p.x, p.y, p.z, T(0)};
 }
 
 template <typename T>
@@ -330,9 +364,9 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict_
     if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
     const int i = w.y + (int)threadIdx.x;
     if (i >= R.n) return;
-    const Site s = decode_site(R.g, (uint32_t)i);
+    const Pos4<T> pi = R.pos[i];
     int b3[3];
-    const int bin = bin_of(R, position(R, s, i), b3);
+    const int bin = bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     const int slot = atomicAdd(&R.bin_n[bin], 1);
     if (slot < R.bin_cap) {
         R.bin_atoms[(size_t)bin * R.bin_cap + slot] = i;
@@ -381,10 +415,10 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
     if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
     const int i = w.y + (int)threadIdx.x;
     if (i >= R.n) return;
-    const Site si = decode_site(R.g, (uint32_t)i);
     const V3<T> ui{R.ux[i], R.uy[i], R.uz[i]};
+    const Pos4<T> pi = R.pos[i];
     int b3[3];
-    bin_of(R, position(R, si, i), b3);
+    bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     int count = 0;
     const size_t n = (size_t)R.n;
     for (int dz = -1; dz <= 1; ++dz) {
@@ -400,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
                 for (int q = 0; q < cnt; ++q) {
                     const int j = a[q];
                     if (j == i) continue;
-                    const V3<T> d = separation(R, si, ui, j);
+                    const V3<T> d = separation(R, pi, j);
                     if (d.x * d.x + d.y * d.y + d.z * d.z < R.rlist2) {
                         if (count < R.max_nbr) R.nbr[(size_t)count * n + i] = j;
                         ++count;
@@ -423,26 +457,22 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
     R.rz[i] = ui.z;
 }
 
-// Fixed-order block reduction of NQ doubles (wave shuffles, then the waves
-// in order); thread q < NQ returns the block total of quantity q.
-__device__ inline void block_reduce_nq(double* v, double* lds /* [kBlock/64][NQ] */)
+// Fixed-order wave reduction of NQ doubles; lane 0 returns the sums.
+__device__ inline void wave_reduce_nq(double* v)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         double x = v[q];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-        if (lane == 0) lds[wave * NQ + q] = x;
+        v[q] = x;
     }
-    __syncthreads();
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work, int phase)
 {
-    __shared__ double lds[(kBlock / 64) * NQ];
     __shared__ unsigned long long cacc[kLdsCells];
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
@@ -458,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
     const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
     const bool lds_acc = eph && R.ncell <= kLdsCells;
     if (lds_acc) {
-        for (int c = threadIdx.x; c < R.ncell; c += kBlock) cacc[c] = 0ull;
+        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
         __syncthreads();
     }
     const int i = w.y + (int)threadIdx.x;
@@ -470,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         const Site si = decode_site(R.g, (uint32_t)i);
         const int sp = species_of(R, i);
         if (R.live) {
-            const V3<T> ui{R.ux[i], R.uy[i], R.uz[i]};
+            const Pos4<T> pi = R.pos[i];
             T Fx = T(0), Fy = T(0), Fz = T(0);
             double pe = 0.0;
             const int nn = R.nbr_n[i];
@@ -484,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
                 for (int q = 0; q < 8; ++q) jj[q] = k0 + q < nn ? R.nbr[(size_t)(k0 + q) * n + i] : i;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const V3<T> d = separation(R, si, ui, jj[q]);
+                    const V3<T> d = separation(R, pi, jj[q]);
                     dx[q] = d.x;
                     dy[q] = d.y;
                     dz[q] = d.z;
@@ -493,15 +523,16 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
                 for (int q = 0; q < 8; ++q) {
                     const T r2 = dx[q] * dx[q] + dy[q] * dy[q] + dz[q] * dz[q];
                     if (k0 + q < nn && r2 < R.rc2) {
-                        const T r = sqrt(r2);
-                        const T e1 = exp(-R.ma * (r - R.mr0));
-                        const T e2 = e1 * e1;
+                        T r;
                         // -dV/dr along +d pushes j; the force on i is its opposite
-                        const T f = T(2) * R.ma * R.mD * (e2 - e1) / r;
+                        const T f = morse_f(r2, R.ma, R.mD, R.mr0, &r);
                         Fx -= f * dx[q];
                         Fy -= f * dy[q];
                         Fz -= f * dz[q];
-                        if (obs) pe += 0.5 * ((double)(R.mD * (e2 - T(2) * e1)) - (double)R.Vc);
+                        if (obs) {
+                            const double e1 = exp(-(double)R.ma * ((double)r - (double)R.mr0));
+                            pe += 0.5 * ((double)R.mD * (e1 * e1 - 2.0 * e1) - (double)R.Vc);
+                        }
                     }
                 }
             }
@@ -577,15 +608,17 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
     }
     if (lds_acc) {
         __syncthreads();
-        for (int c = threadIdx.x; c < R.ncell; c += kBlock)
+        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
             if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
     }
     if (!obs) return;
-    block_reduce_nq(q, lds);
-    if (threadIdx.x < NQ) {
-        double tot = 0.0;
-        for (int wv = 0; wv < kBlock / 64; ++wv) tot += lds[wv * NQ + threadIdx.x];
-        R.partial[(size_t)(w.y / kBlock) * NQ + threadIdx.x] = tot;
+    // one row of partial sums per 64 consecutive atoms (a wave), so the
+    // sample does not depend on the block size
+    wave_reduce_nq(q);
+    if ((threadIdx.x & 63) == 0 && i < R.n) {
+        double* row = R.partial + (size_t)(i >> 6) * NQ;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) row[k] = q[k];
     }
 }
 

@@ -177,7 +177,7 @@ Sizes run_sizes(const sl_system_desc* d, const sl_ttm_desc* t)
     const int nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
     z.n = (int64_t)nb * d->ncell[0] * d->ncell[1] * d->ncell[2];
     z.ncell = t->n[0] * t->n[1] * t->n[2];
-    z.n_part = (int)((z.n + sl::kBlock - 1) / sl::kBlock);
+    z.n_part = (int)((z.n + 63) / 64);   // one row of observable partials per wave
     if (d->lattice_mode == 1) {
         const double reach = d->morse[3] + d->skin;
         const double vol_site = std::pow(d->a, 3) / nb;
@@ -217,6 +217,7 @@ template <typename T> size_t main_bytes(const sl_system_desc* d, const Sizes& z)
         c.take<int32_t>((size_t)z.nbins);
         c.take<int32_t>((size_t)z.nbins * z.bin_cap);
     }
+    if (live) c.take<sl::Pos4<T>>(n);
     c.take<int8_t>(n);
     c.take<uint16_t>(n);
     c.take<double>((size_t)z.n_part * sl::NQ);
@@ -268,6 +269,9 @@ public:
     size_t budget = 0, used_bytes = 0;
     int graph_steps = 16;
     int precision = SL_FP64;
+    // launch shape (every choice gives bitwise-identical results)
+    int spin_block = 256, spin_spt = 1, atom_block = 256;
+    virtual sl_status retune() = 0;
 };
 
 template <typename T> class EngineT final : public Engine {
@@ -511,6 +515,14 @@ public:
         return SL_OK;
     }
 
+    sl_status retune() override
+    {
+        SL_HIP(hipStreamSynchronize(stream));
+        tables_dirty = true;
+        drop_graph();
+        return SL_OK;
+    }
+
     sl_status n_samples(int s, int64_t* out)
     {
         sl::RunState rs;
@@ -666,6 +678,7 @@ private:
             R.bin_n = c.take<int32_t>((size_t)r.z.nbins);
             R.bin_atoms = c.take<int32_t>((size_t)r.z.nbins * r.z.bin_cap);
         }
+        if (R.live) R.pos = c.take<sl::Pos4<T>>(n);
         R.species = c.take<int8_t>(n);
         R.cell = c.take<uint16_t>(n);
         R.n_part = r.z.n_part;
@@ -833,8 +846,8 @@ private:
         for (size_t s = 0; s < runs.size(); ++s) {
             if (!runs[s].used) continue;
             const RD& R = host_rd[s];
-            for (int st = 0; st < R.g.H; st += sl::kBlock) ws.push_back(make_int2((int)s, st));
-            for (int st = 0; st < R.n; st += sl::kBlock) wa.push_back(make_int2((int)s, st));
+            for (int st = 0; st < R.g.H; st += spin_block * spin_spt) ws.push_back(make_int2((int)s, st));
+            for (int st = 0; st < R.n; st += atom_block) wa.push_back(make_int2((int)s, st));
             for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2((int)s, st));
             if (R.ttm_mode == 1 && R.ncell > sl::kSmallGrid)
                 for (int st = 0; st < R.ncell; st += sl::kBlock) wc.push_back(make_int2((int)s, st));
@@ -906,23 +919,28 @@ private:
         const int C = max_colours();
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
             sl_status e = timed(st, p, 0, [&] {
-                sl::k_spin_pass<T><<<active_blocks_spin, sl::kBlock, 0, st>>>(d_runs, d_work_spin, pass);
+                if (spin_spt == 4)
+                    sl::k_spin_pass<T, 4><<<active_blocks_spin, spin_block, 0, st>>>(d_runs, d_work_spin, pass);
+                else if (spin_spt == 2)
+                    sl::k_spin_pass<T, 2><<<active_blocks_spin, spin_block, 0, st>>>(d_runs, d_work_spin, pass);
+                else
+                    sl::k_spin_pass<T, 1><<<active_blocks_spin, spin_block, 0, st>>>(d_runs, d_work_spin, pass);
             });
             if (e != SL_OK) return e;
         }
         if (any_live) {
             sl_status e = timed(st, p, 2, [&] {
-                sl::k_kick_drift<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom,
+                sl::k_kick_drift<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom,
                                                                               sl::PHASE_STEP);
             });
             if (e != SL_OK) return e;
-            sl::k_nbr_bin<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom);
+            sl::k_nbr_bin<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom);
             if (active_blocks_bin > 0)
                 sl::k_nbr_sort<T><<<active_blocks_bin, sl::kBlock, 0, st>>>(d_runs, d_work_bin);
-            sl::k_nbr_build<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom);
+            sl::k_nbr_build<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom);
         }
         sl_status e = timed(st, p, 1, [&] {
-            sl::k_atom_final<T><<<active_blocks_atom, sl::kBlock, 0, st>>>(d_runs, d_work_atom,
+            sl::k_atom_final<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom,
                                                                           sl::PHASE_STEP);
         });
         if (e != SL_OK) return e;
@@ -1079,6 +1097,55 @@ sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* step
     if (n_sites) *n_sites = r.z.n;
     if (n_cells) *n_cells = r.z.ncell;
     if (steps) *steps = r.steps;
+    return SL_OK;
+}
+
+static sl_status set_tuning(Engine* e, const sl_tuning* t)
+{
+    if (!t) return fail(SL_EINVAL, "null tuning");
+    const bool blk_ok = [](int b) { return b == 64 || b == 128 || b == 256; }(t->spin_block) &&
+                        [](int b) { return b == 64 || b == 128 || b == 256; }(t->atom_block);
+    if (!blk_ok) return fail(SL_EINVAL, "block sizes must be 64, 128 or 256");
+    if (t->spin_spt != 1 && t->spin_spt != 2 && t->spin_spt != 4) return fail(SL_EINVAL, "spin_spt must be 1, 2 or 4");
+    if (t->graph_steps < 1 || t->graph_steps > 256) return fail(SL_EINVAL, "graph_steps must be 1..256");
+    e->spin_block = t->spin_block;
+    e->spin_spt = t->spin_spt;
+    e->atom_block = t->atom_block;
+    e->graph_steps = t->graph_steps;
+    return e->retune();
+}
+
+static void get_tuning(const Engine* e, sl_tuning* t)
+{
+    t->spin_block = e->spin_block;
+    t->spin_spt = e->spin_spt;
+    t->atom_block = e->atom_block;
+    t->graph_steps = e->graph_steps;
+}
+
+sl_status sl_set_tuning(sl_system h, const sl_tuning* t)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    return set_tuning(h->eng.get(), t);
+}
+
+sl_status sl_get_tuning(sl_system h, sl_tuning* t)
+{
+    if (!h || !t) return fail(SL_EINVAL, "null argument");
+    get_tuning(h->eng.get(), t);
+    return SL_OK;
+}
+
+sl_status sl_batch_set_tuning(sl_batch b, const sl_tuning* t)
+{
+    if (!b) return fail(SL_EINVAL, "null handle");
+    return set_tuning(b->eng.get(), t);
+}
+
+sl_status sl_batch_get_tuning(sl_batch b, sl_tuning* t)
+{
+    if (!b || !t) return fail(SL_EINVAL, "null argument");
+    get_tuning(b->eng.get(), t);
     return SL_OK;
 }
 

@@ -77,6 +77,14 @@ class sl_batch_desc(C.Structure):
     ]
 
 
+class sl_tuning(C.Structure):
+    _fields_ = [("spin_block", C.c_int32), ("spin_spt", C.c_int32), ("atom_block", C.c_int32),
+                ("graph_steps", C.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class sl_run_info(C.Structure):
     _fields_ = [
         ("slot", C.c_int32), ("status", C.c_int32), ("steps_done", C.c_int64),
@@ -98,6 +106,10 @@ EXPORTS = {
                                        C.POINTER(C.c_size_t)]),
     "sl_step_profiled": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]),
+    "sl_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(sl_tuning)]),
+    "sl_get_tuning": (C.c_int32, [C.c_void_p, C.POINTER(sl_tuning)]),
+    "sl_batch_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(sl_tuning)]),
+    "sl_batch_get_tuning": (C.c_int32, [C.c_void_p, C.POINTER(sl_tuning)]),
     "sl_destroy": (None, [C.c_void_p]),
     "sl_last_error": (C.c_char_p, []),
     "sl_batch_create": (C.c_int32, [C.POINTER(sl_batch_desc), C.POINTER(C.c_void_p)]),
@@ -322,6 +334,22 @@ class System:
         check(lib().sl_step_profiled(self._h, int(n), avg, cnt))
         return list(avg), list(cnt)
 
+    def set_tuning(self, **kw) -> None:
+        t = sl_tuning()
+        check(lib().sl_get_tuning(self._h, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        check(lib().sl_set_tuning(self._h, C.byref(t)))
+
+    def tuning(self) -> dict:
+        t = sl_tuning()
+        check(lib().sl_get_tuning(self._h, C.byref(t)))
+        return t.to_dict()
+
+    # uniform interface used by the autotuner
+    def advance(self, n: int) -> None:
+        self.step(n)
+
 
 # ------------------------------------------------------------ batches
 
@@ -376,6 +404,18 @@ class Batch:
 
     def advance(self, n: int) -> None:
         check(lib().sl_batch_advance(self._h, int(n)))
+
+    def set_tuning(self, **kw) -> None:
+        t = sl_tuning()
+        check(lib().sl_batch_get_tuning(self._h, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        check(lib().sl_batch_set_tuning(self._h, C.byref(t)))
+
+    def tuning(self) -> dict:
+        t = sl_tuning()
+        check(lib().sl_batch_get_tuning(self._h, C.byref(t)))
+        return t.to_dict()
 
     def advance_profiled(self, n: int):
         avg = (C.c_double * 4)()

@@ -180,3 +180,32 @@ def test_fp32_ensemble_matches_fp64(N):
     assert np.all(np.abs(diff) < 4.0 * err + 2e-3)
     # the pulse did demagnetise the sublattices
     assert a[:, -1, 1].mean() < 0.97
+
+
+def test_launch_shapes_are_bitwise_identical(N):
+    """Every launch shape the autotuner may choose gives the same bits: a
+    batch stepped under several settings (and then autotuned) equals the
+    runs stepped alone with the default setting."""
+    from paper_2608_18541_amd.autotune import autotune
+    runs = _mixed_runs()[:4]
+    for prec in (0, 1):
+        b = N.Batch(precision=prec, max_runs=4)
+        slots = [b.add(sp, st, 10_000) for sp, st in runs]
+        shapes = [dict(spin_block=64, spin_spt=4, atom_block=128, graph_steps=8),
+                  dict(spin_block=128, spin_spt=2, atom_block=64, graph_steps=32),
+                  dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=1)]
+        for sh in shapes:
+            b.set_tuning(**sh)
+            b.advance(17)
+        best = autotune(b, steps=8, use_cache=False)
+        assert set(best) == {"spin_block", "spin_spt", "atom_block", "graph_steps"}
+        info = {r["slot"]: r["steps_done"] for r in b.runs()}
+        for (sp, st), s in zip(runs, slots):
+            alone = N.System(sp, st, precision=prec)
+            alone.step(info[s])
+            a = alone.state()
+            g = b.get(s)
+            for k in ("s", "x", "v", "Te"):
+                assert np.array_equal(a[k], g[k]), (prec, s, k)
+            alone.close()
+        b.close()
