@@ -178,10 +178,12 @@ sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* step
 sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
                              size_t* bytes);
 
-/* Average device time (ms) of one launch of a kernel class over the last
- * profiled sl_step_profiled call: 0 spin colour pass, 1 lattice force and
- * electron-phonon step, 2 kick-drift, 3 end-of-step (grid, reductions). */
-sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[4], int64_t launches[4]);
+/* Runs n_steps (at most 4096) launching every kernel directly with HIP
+ * events around each; returns the average device time (ms) per launch of
+ * each kernel class and the launch counts: 0 spin colour pass, 1 lattice
+ * force and electron-phonon step, 2 kick-drift, 3 electron grid and
+ * end-of-step reductions, 4 persistent kernel (one launch for all steps). */
+sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5]);
 
 /* Launch shape of the step kernels.  Every choice performs the same
  * arithmetic in the same order for each site, atom and cell, so results are
@@ -191,6 +193,10 @@ typedef struct sl_tuning {
     int32_t spin_spt;         /* sites per thread in a colour pass: 1, 2, 4          */
     int32_t atom_block;       /* threads per block of the lattice kernels: 64..256   */
     int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256         */
+    int32_t persist_block;    /* 0: all runs on the multi-kernel step; 256 or 512:
+                                 runs that fit in LDS advance in a persistent kernel,
+                                 one block of this many threads per run (batches
+                                 default to 512, single systems to 0)               */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of
@@ -253,8 +259,8 @@ sl_status sl_batch_remove(sl_batch b, int32_t slot);
 /* As sl_batch_advance, launching every kernel directly with HIP events
  * around each; returns the average device time (ms) per launch of each
  * kernel class (as sl_step_profiled) and the launch counts. */
-sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[4],
-                                    int64_t launches[4]);
+sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[5],
+                                    int64_t launches[5]);
 
 /* Launch shape of a batch (as sl_set_tuning / sl_get_tuning). */
 sl_status sl_batch_set_tuning(sl_batch b, const sl_tuning* t);

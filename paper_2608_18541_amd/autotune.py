@@ -1,7 +1,9 @@
 """Autotuner of the kernels' launch shape.
 
 The knobs are the colour-pass block size and sites per thread, the lattice
-kernels' block size and the number of steps captured per HIP graph replay.
+kernels' block size, the number of steps captured per HIP graph replay and
+the block size of the persistent per-run kernel (0 keeps every run on the
+multi-kernel step).
 Every setting performs the same arithmetic for every site, atom and cell,
 so the tuner times real steps of the run being tuned: a coordinate search
 (one knob at a time, the others held) keeps the fastest setting, and the
@@ -15,6 +17,7 @@ import time
 from typing import Dict, List, Optional
 
 KNOBS = {
+    "persist_block": (0, 256, 512),
     "graph_steps": (8, 16, 32, 64),
     "spin_spt": (1, 2, 4),
     "spin_block": (64, 128, 256),
@@ -62,7 +65,7 @@ def autotune(target, key: Optional[str] = None, steps: int = 64, rounds: int = 2
     chosen setting.  Each candidate is timed against the current best in
     interleaved rounds (best, candidate, best, candidate, ...), so a
     workload that speeds up or slows down as it evolves does not bias the
-    comparison; a candidate replaces the best when its median time is at
+    comparison; a candidate replaces the best when its fastest round is at
     least 3% lower.  ``key`` names the workload for the cache (the search is
     skipped when a setting is cached)."""
     cache = _load_cache() if use_cache and key else {}
@@ -81,7 +84,7 @@ def autotune(target, key: Optional[str] = None, steps: int = 64, rounds: int = 2
                 for cfg, acc in ((best, tb), (trial, tt)):
                     target.set_tuning(**cfg)
                     acc.append(_time_steps(target, _steps_for(cfg, steps)))
-            mb, mt = sorted(tb)[len(tb) // 2], sorted(tt)[len(tt) // 2]
+            mb, mt = min(tb), min(tt)
             if log is not None:
                 log.append((dict(trial), mt, mb))
             if mt < 0.97 * mb:

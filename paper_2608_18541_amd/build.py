@@ -24,6 +24,9 @@ def compile_flags() -> list:
     return ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared",
             # packed FP32 instructions stay off
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # multiply-adds are fused only within one source expression, so a
+            # device function inlined into different kernels rounds the same
+            "-ffp-contract=on",
             "-Wno-unused-command-line-argument"]
 
 

@@ -19,6 +19,8 @@
 //                          cell of large grids
 //   k_finalize             one block per run: small grids, the observable
 //                          sample, the step counter
+// or, for runs small enough to live in LDS, k_persist: one block per run
+// advancing many steps in one launch.
 #pragma once
 
 #include "sl_device.hpp"
@@ -27,7 +29,7 @@
 namespace sl {
 
 constexpr int kBlock = 256;
-constexpr int NQ = 24;      // per-block observable partial sums
+constexpr int NQ = 24;      // observable partial sums per wave of 64 atoms
 constexpr int kLdsCells = 2048;   // electron grids up to this size are summed in LDS
 
 enum { ERR_NEG_E = 1, ERR_BIN = 2, ERR_NBR = 4, ERR_DE = 8 };
@@ -91,11 +93,29 @@ template <typename T> struct RunDev {
     RunState* st;
 };
 
-// ----------------------------------------------------------- helpers
+// ----------------------------------------------------------- views
+// Where the hot arrays of a run live while a kernel works on it: the run's
+// global arrays (the multi-kernel step) or copies in LDS (the persistent
+// per-run kernel).  Every per-site, per-atom and per-cell computation below
+// takes a view, so both executors run literally the same arithmetic.
+template <typename T> struct View {
+    T *sx, *sy, *sz;
+    const int8_t* species;
+    uint16_t* cell;
+    Pos4<T>* pos;
+    double* Te;
+    double* partial;
+};
 
-template <typename T> __device__ inline int species_of(const RunDev<T>& R, int idx)
+template <typename T> __device__ inline View<T> global_view(const RunDev<T>& R)
 {
-    return R.n_species > 1 ? (int)R.species[idx] : 0;
+    return View<T>{R.sx, R.sy, R.sz, R.species, R.cell, R.pos, R.Te, R.partial};
+}
+
+template <typename T>
+__device__ inline int species_of(const RunDev<T>& R, const View<T>& V, int idx)
+{
+    return R.n_species > 1 ? (int)V.species[idx] : 0;
 }
 
 // Exchange sum h = sum_j J_ij s_j (eV) over the neighbour shells of site
@@ -108,8 +128,9 @@ template <typename T> __device__ inline T select4(int k, T a, T b, T c, T d)
 }
 
 template <typename T, int NN>
-__device__ __forceinline__ V3<T> exchange_gather(const RunDev<T>& R, const int (&j)[NN],
-                                        const int (&sh)[NN], int nn, int sp)
+__device__ __forceinline__ V3<T> exchange_gather(const RunDev<T>& R, const View<T>& V,
+                                                 const int (&j)[NN], const int (&sh)[NN], int nn,
+                                                 int sp)
 {
     T ax[NN], ay[NN], az[NN];
     int sj[NN];
@@ -117,10 +138,10 @@ __device__ __forceinline__ V3<T> exchange_gather(const RunDev<T>& R, const int (
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
         if (q < nn) {
-            ax[q] = R.sx[j[q]];
-            ay[q] = R.sy[j[q]];
-            az[q] = R.sz[j[q]];
-            sj[q] = multi ? (int)R.species[j[q]] : 0;
+            ax[q] = V.sx[j[q]];
+            ay[q] = V.sy[j[q]];
+            az[q] = V.sz[j[q]];
+            sj[q] = multi ? (int)V.species[j[q]] : 0;
         }
     }
     // couplings of this site's species to each species, per shell
@@ -145,7 +166,8 @@ __device__ __forceinline__ V3<T> exchange_gather(const RunDev<T>& R, const int (
 }
 
 template <typename T>
-__device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, int x, int y, int z, int b, int sp)
+__device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, const View<T>& V, int x, int y,
+                                              int z, int b, int sp)
 {
     const Geom& g = R.g;
     const int xm = x == 0 ? g.Lx - 1 : x - 1, xp = x == g.Lx - 1 ? 0 : x + 1;
@@ -156,7 +178,7 @@ __device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, int x, int y, 
                           encode_site(g, x, ym, z, 0), encode_site(g, x, yp, z, 0),
                           encode_site(g, x, y, zm, 0), encode_site(g, x, y, zp, 0)};
         const int sh[6] = {0, 0, 0, 0, 0, 0};
-        return exchange_gather<T, 6>(R, j, sh, 6, sp);
+        return exchange_gather<T, 6>(R, V, j, sh, 6, sp);
     }
     // first shell: the 8 sites of the other basis at (+-a/2, +-a/2, +-a/2);
     // second shell: the 6 sites of the same basis at +-a along an axis
@@ -172,19 +194,13 @@ __device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, int x, int y, 
                        encode_site(g, x, ym, z, b),    encode_site(g, x, yp, z, b),
                        encode_site(g, x, y, zm, b),    encode_site(g, x, y, zp, b)};
     const int sh[14] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
-    return exchange_gather<T, 14>(R, j, sh, R.n_shells > 1 ? 14 : 8, sp);
+    return exchange_gather<T, 14>(R, V, j, sh, R.n_shells > 1 ? 14 : 8, sp);
 }
 
 template <typename T> __device__ inline V3<T> ideal_site(const RunDev<T>& R, const Site& s)
 {
     const T off = T(0.25) + T(0.5) * (T)s.b;
     return {((T)s.x + off) * R.a, ((T)s.y + off) * R.a, ((T)s.z + off) * R.a};
-}
-
-__device__ inline int wrap_cell_delta(int d, int L)
-{
-    const int h = L >> 1;
-    return d > h ? d - L : (d < -h ? d + L : d);
 }
 
 template <typename T> __device__ inline T min_image(T d, T box, T half)
@@ -194,9 +210,9 @@ template <typename T> __device__ inline T min_image(T d, T box, T half)
 
 // Separation x_j - x_i (minimum image) from the wrapped positions.
 template <typename T>
-__device__ inline V3<T> separation(const RunDev<T>& R, const Pos4<T>& pi, int j)
+__device__ inline V3<T> separation(const RunDev<T>& R, const View<T>& V, const Pos4<T>& pi, int j)
 {
-    const Pos4<T> pj = R.pos[j];
+    const Pos4<T> pj = V.pos[j];
     V3<T> d{pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
     d.x = min_image(d.x, R.box[0], R.half_box[0]);
     d.y = min_image(d.y, R.box[1], R.half_box[1]);
@@ -204,9 +220,9 @@ __device__ inline V3<T> separation(const RunDev<T>& R, const Pos4<T>& pi, int j)
     return d;
 }
 
-// Morse force factor f = -dV/dr / r and pair energy V(r) - V(rc).  The
-// single-precision path uses the hardware exponential and reciprocal
-// square root; double precision stays correctly rounded.
+// Morse force factor f = -dV/dr / r.  The single-precision path uses the
+// hardware exponential and reciprocal square root; double precision stays
+// correctly rounded.
 __device__ inline float morse_f(float r2, float a, float D, float r0, float* r_out)
 {
     const float ir = rsqrtf(r2);
@@ -228,7 +244,7 @@ template <typename T> __device__ inline T wrap_box(T x, T L)
     return x - L * floor(x / L);
 }
 
-// Wrapped position of atom idx.
+// Wrapped position of atom idx from its ideal site and displacement.
 template <typename T> __device__ inline V3<T> position(const RunDev<T>& R, const Site& s, int idx)
 {
     V3<T> r = ideal_site(R, s);
@@ -267,12 +283,11 @@ template <typename T> __device__ inline bool run_active(const RunDev<T>& R, int6
 }
 
 // ------------------------------------------------------------ spins
-// One colour pass.  Block b updates the SPT * blockDim sites of its tile
-// starting at work[b].y; a site's arithmetic does not depend on SPT or the
-// block size, so every launch shape gives bitwise-identical spins.
+// Update of site l of a colour: field from the current neighbours, thermal
+// field from the step's Philox block, exact flow over tau.
 template <typename T>
-__device__ __forceinline__ void spin_site(const RunDev<T>& R, int colour, T tau, int l,
-                                          int64_t step)
+__device__ __forceinline__ void spin_site(const RunDev<T>& R, const View<T>& V, int colour, T tau,
+                                          int l, int64_t step)
 {
     const int idx = colour * R.g.H + l;
     const uint32_t r = fdiv((uint32_t)l, R.g.divLxh);
@@ -281,12 +296,12 @@ __device__ __forceinline__ void spin_site(const RunDev<T>& R, int colour, T tau,
     const int y = (int)r - z * R.g.Ly;
     const int x = 2 * xh + ((colour + y + z) & 1);
     const int b = R.g.nb == 2 ? (colour >> 1) : 0;
-    const int sp = species_of(R, idx);
-    const V3<T> h = exchange_sum(R, x, y, z, b, sp);
+    const int sp = species_of(R, V, idx);
+    const V3<T> h = exchange_sum(R, V, x, y, z, b, sp);
     T Hx = h.x * R.inv_mumb[sp] + R.B[0];
     T Hy = h.y * R.inv_mumb[sp] + R.B[1];
     T Hz = h.z * R.inv_mumb[sp] + R.B[2];
-    const double Te = R.Te[R.cell[idx]];
+    const double Te = V.Te[V.cell[idx]];
     if (Te > 0.0 && R.sig[sp] > T(0)) {
         const int canon = ((z * R.g.Ly + y) * R.g.Lx + x) * R.g.nb + b;
         const Normals3<T> nu = normals3<T>(R.seed, R.run_id, (uint32_t)canon, step, 0u);
@@ -295,49 +310,32 @@ __device__ __forceinline__ void spin_site(const RunDev<T>& R, int colour, T tau,
         Hy += amp * nu.b;
         Hz += amp * nu.c;
     }
-    V3<T> s{R.sx[idx], R.sy[idx], R.sz[idx]};
+    V3<T> s{V.sx[idx], V.sy[idx], V.sz[idx]};
     const V3<T> wv{R.gam * Hx, R.gam * Hy, R.gam * Hz};
     s = llg_flow(s, wv, R.alpha, tau, R.inv1pa2);
-    R.sx[idx] = s.x;
-    R.sy[idx] = s.y;
-    R.sz[idx] = s.z;
+    V.sx[idx] = s.x;
+    V.sy[idx] = s.y;
+    V.sz[idx] = s.z;
 }
 
-template <typename T, int SPT>
-__global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
-                                                      const int2* __restrict__ work, int pass)
+template <typename T> __device__ inline void pass_colour(const RunDev<T>& R, int pass, int* colour, T* tau)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    int64_t step;
-    if (!run_active(R, &step)) return;
     const int C = R.g.C;
-    if (pass >= 2 * C - 1) return;
-    const int colour = pass < C ? pass : 2 * C - 2 - pass;
-    const T tau = (pass == C - 1) ? R.dt : R.tau_half;
-#pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-        const int l = w.y + k * (int)blockDim.x + (int)threadIdx.x;
-        if (l < R.g.H) spin_site(R, colour, tau, l, step);
-    }
+    *colour = pass < C ? pass : 2 * C - 2 - pass;
+    *tau = (pass == C - 1) ? R.dt : R.tau_half;
 }
 
 // ------------------------------------------------------------ lattice
+// Half kick and drift of atom i (step phase), then its electron cell and
+// wrapped position; returns whether it moved more than half the skin since
+// its list was built.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_kick_drift(const RunDev<T>* __restrict__ runs,
-                                                       const int2* __restrict__ work, int phase)
+__device__ __forceinline__ bool kick_drift_atom(const RunDev<T>& R, const View<T>& V, int i, int phase)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    int64_t step;
-    if (phase == PHASE_STEP) {
-        if (!run_active(R, &step) || !R.live) return;
-    }
-    const int i = w.y + (int)threadIdx.x;
-    if (i >= R.n) return;
     const Site s = decode_site(R.g, (uint32_t)i);
+    bool far = false;
     if (phase == PHASE_STEP) {
-        const int sp = species_of(R, i);
+        const int sp = species_of(R, V, i);
         const T k = R.hdtm[sp];
         T vx = R.vx[i] + k * R.fx[i];
         T vy = R.vy[i] + k * R.fy[i];
@@ -348,23 +346,17 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(const RunDev<T>* __restri
         R.vx[i] = vx; R.vy[i] = vy; R.vz[i] = vz;
         R.ux[i] = ux; R.uy[i] = uy; R.uz[i] = uz;
         const T dx = ux - R.rx[i], dy = uy - R.ry[i], dz = uz - R.rz[i];
-        if (dx * dx + dy * dy + dz * dz > R.skin_half2) atomicOr(&R.st->rebuild, 1);
+        far = dx * dx + dy * dy + dz * dz > R.skin_half2;
     }
     const V3<T> p = position(R, s, i);
-    R.cell[i] = (uint16_t)electron_cell(R, p);
-    if (R.live) R.pos[i] = Pos4<T>{p.x, p.y, p.z, T(0)};
+    V.cell[i] = (uint16_t)electron_cell(R, p);
+    if (R.live) V.pos[i] = Pos4<T>{p.x, p.y, p.z, T(0)};
+    return far;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict__ runs,
-                                                    const int2* __restrict__ work)
+template <typename T> __device__ inline void nbr_bin_atom(const RunDev<T>& R, const View<T>& V, int i)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    const int i = w.y + (int)threadIdx.x;
-    if (i >= R.n) return;
-    const Pos4<T> pi = R.pos[i];
+    const Pos4<T> pi = V.pos[i];
     int b3[3];
     const int bin = bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     const int slot = atomicAdd(&R.bin_n[bin], 1);
@@ -379,17 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict_
     }
 }
 
-// Sorts each bin's atoms so that the neighbour order does not depend on
-// the order in which atoms were binned.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict__ runs,
-                                                     const int2* __restrict__ work)
+// Sorts a bin's atoms so that the neighbour order does not depend on the
+// order in which atoms were binned.
+template <typename T> __device__ inline void nbr_sort_bin(const RunDev<T>& R, int bin)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    const int bin = w.y + (int)threadIdx.x;
-    if (bin >= R.nbins) return;
     int cnt = R.bin_n[bin];
     cnt = cnt < R.bin_cap ? cnt : R.bin_cap;
     int32_t* a = R.bin_atoms + (size_t)bin * R.bin_cap;
@@ -406,17 +391,10 @@ __global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict
 
 // Verlet list of atom i: every atom within rc + skin in its own and the 26
 // surrounding bins, in bin order and ascending index within a bin.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restrict__ runs,
-                                                      const int2* __restrict__ work)
+template <typename T> __device__ inline void nbr_build_atom(const RunDev<T>& R, const View<T>& V, int i)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    const int i = w.y + (int)threadIdx.x;
-    if (i >= R.n) return;
     const V3<T> ui{R.ux[i], R.uy[i], R.uz[i]};
-    const Pos4<T> pi = R.pos[i];
+    const Pos4<T> pi = V.pos[i];
     int b3[3];
     bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     int count = 0;
@@ -434,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
                 for (int q = 0; q < cnt; ++q) {
                     const int j = a[q];
                     if (j == i) continue;
-                    const V3<T> d = separation(R, pi, j);
+                    const V3<T> d = separation(R, V, pi, j);
                     if (d.x * d.x + d.y * d.y + d.z * d.z < R.rlist2) {
                         if (count < R.max_nbr) R.nbr[(size_t)count * n + i] = j;
                         ++count;
@@ -457,166 +435,135 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
     R.rz[i] = ui.z;
 }
 
-// Fixed-order wave reduction of NQ doubles; lane 0 returns the sums.
-__device__ inline void wave_reduce_nq(double* v)
+// Forces on atom i at the new positions, the second half kick, the
+// electron-phonon Ornstein-Uhlenbeck step (its mean energy added to `acc`
+// of the atom's cell, fixed point) and, on sample steps, the atom's
+// observable terms q[NQ].
+template <typename T>
+__device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const View<T>& V, int i,
+                                                int phase, int64_t step, bool obs,
+                                                unsigned long long* acc, double* q)
 {
+    const Site si = decode_site(R.g, (uint32_t)i);
+    const int sp = species_of(R, V, i);
+    if (R.live) {
+        const Pos4<T> pi = V.pos[i];
+        T Fx = T(0), Fy = T(0), Fz = T(0);
+        double pe = 0.0;
+        const int nn = R.nbr_n[i];
+        const size_t n = (size_t)R.n;
+        // neighbours in chunks of 8: all index loads, then all position
+        // loads, then the arithmetic (two memory round trips per chunk)
+        for (int k0 = 0; k0 < nn; k0 += 8) {
+            int jj[8];
+            T dx[8], dy[8], dz[8];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double x = v[q];
+            for (int q8 = 0; q8 < 8; ++q8)
+                jj[q8] = k0 + q8 < nn ? R.nbr[(size_t)(k0 + q8) * n + i] : i;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-        v[q] = x;
+            for (int q8 = 0; q8 < 8; ++q8) {
+                const V3<T> d = separation(R, V, pi, jj[q8]);
+                dx[q8] = d.x;
+                dy[q8] = d.y;
+                dz[q8] = d.z;
+            }
+#pragma unroll
+            for (int q8 = 0; q8 < 8; ++q8) {
+                const T r2 = dx[q8] * dx[q8] + dy[q8] * dy[q8] + dz[q8] * dz[q8];
+                if (k0 + q8 < nn && r2 < R.rc2) {
+                    T r;
+                    // -dV/dr along +d pushes j; the force on i is its opposite
+                    const T f = morse_f(r2, R.ma, R.mD, R.mr0, &r);
+                    Fx -= f * dx[q8];
+                    Fy -= f * dy[q8];
+                    Fz -= f * dz[q8];
+                    if (obs) {
+                        const double e1 = exp(-(double)R.ma * ((double)r - (double)R.mr0));
+                        pe += 0.5 * ((double)R.mD * (e1 * e1 - 2.0 * e1) - (double)R.Vc);
+                    }
+                }
+            }
+        }
+        T vx = R.vx[i], vy = R.vy[i], vz = R.vz[i];
+        if (phase == PHASE_STEP) {
+            const T k = R.hdtm[sp];
+            vx += k * Fx;
+            vy += k * Fy;
+            vz += k * Fz;
+            if (R.ttm_mode == 1) {
+                const int c = V.cell[i];
+                const double Te = V.Te[c];
+                const int canon = ((si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
+                const Normals3<T> eta = normals3<T>(R.seed, R.run_id, (uint32_t)canon, step, 1u);
+                const T amp = R.ou_amp[sp] * (T)sqrt(Te);
+                const T nx = R.ou_c1 * vx + amp * eta.a;
+                const T ny = R.ou_c1 * vy + amp * eta.b;
+                const T nz = R.ou_c1 * vz + amp * eta.c;
+                // mean energy the step hands to this atom given its velocity
+                const double ke = 0.5 * (double)R.m_e[sp] *
+                                  ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+                const double dE = R.ou_1mc2 * (1.5 * kKB * Te - ke);
+                if (fabs(dE) < 1.0e3) {
+                    const long long fixp = llrint(dE * kFIX);
+                    atomicAdd(&acc[c], (unsigned long long)fixp);
+                } else {
+                    atomicOr(&R.st->err, ERR_DE);
+                }
+                vx = nx;
+                vy = ny;
+                vz = nz;
+            }
+            R.vx[i] = vx;
+            R.vy[i] = vy;
+            R.vz[i] = vz;
+        }
+        R.fx[i] = Fx;
+        R.fy[i] = Fy;
+        R.fz[i] = Fz;
+        if (obs) {
+            q[14] = 0.5 * (double)R.m_e[sp] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+            q[15] = pe;
+        }
+    }
+    if (obs) {
+        const double s0 = V.sx[i], s1 = V.sy[i], s2 = V.sz[i];
+        const V3<T> h = exchange_sum(R, V, si.x, si.y, si.z, si.b, sp);
+        const double h0 = h.x, h1 = h.y, h2 = h.z;
+        q[12] = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
+        q[13] = -R.mumb[sp] * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
+        const double t0 = h0 + R.mumb[sp] * R.Bd[0];
+        const double t1 = h1 + R.mumb[sp] * R.Bd[1];
+        const double t2 = h2 + R.mumb[sp] * R.Bd[2];
+        const double c0 = s1 * t2 - s2 * t1, c1 = s2 * t0 - s0 * t2, c2 = s0 * t1 - s1 * t0;
+        const double num = c0 * c0 + c1 * c1 + c2 * c2;
+        const double den = s0 * t0 + s1 * t1 + s2 * t2;
+        // per-species slots with compile-time indices (kept in registers)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bool me = sp == t;
+            q[3 * t + 0] = me ? s0 : 0.0;
+            q[3 * t + 1] = me ? s1 : 0.0;
+            q[3 * t + 2] = me ? s2 : 0.0;
+            q[16 + t] = me ? num : 0.0;
+            q[20 + t] = me ? den : 0.0;
+        }
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
-                                                       const int2* __restrict__ work, int phase)
+// Fixed-order wave reduction of NQ doubles; lane 0 writes the row of the
+// wave's 64 consecutive atoms (row = first atom / 64), so samples do not
+// depend on the block size.
+__device__ inline void wave_reduce_row(double* q, double* partial, int i_first, int n)
 {
-    __shared__ unsigned long long cacc[kLdsCells];
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    int64_t step = R.st->step;
-    if (phase == PHASE_STEP) {
-        if (!run_active(R, &step)) return;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        double x = q[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        q[k] = x;
     }
-    const bool obs = R.obs_every > 0 &&
-                     (phase == PHASE_INIT || ((step + 1) % R.obs_every) == 0);
-    if (!R.live && !obs) return;
-    // electron-phonon energy per cell: first summed in LDS (fixed point, so
-    // the order does not matter), then one global atomic per touched cell
-    const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
-    const bool lds_acc = eph && R.ncell <= kLdsCells;
-    if (lds_acc) {
-        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
-        __syncthreads();
-    }
-    const int i = w.y + (int)threadIdx.x;
-    const bool valid = i < R.n;
-    double q[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) q[k] = 0.0;
-    if (valid) {
-        const Site si = decode_site(R.g, (uint32_t)i);
-        const int sp = species_of(R, i);
-        if (R.live) {
-            const Pos4<T> pi = R.pos[i];
-            T Fx = T(0), Fy = T(0), Fz = T(0);
-            double pe = 0.0;
-            const int nn = R.nbr_n[i];
-            const size_t n = (size_t)R.n;
-            // neighbours in chunks of 8: all index loads, then all position
-            // loads, then the arithmetic (two memory round trips per chunk)
-            for (int k0 = 0; k0 < nn; k0 += 8) {
-                int jj[8];
-                T dx[8], dy[8], dz[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) jj[q] = k0 + q < nn ? R.nbr[(size_t)(k0 + q) * n + i] : i;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const V3<T> d = separation(R, pi, jj[q]);
-                    dx[q] = d.x;
-                    dy[q] = d.y;
-                    dz[q] = d.z;
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const T r2 = dx[q] * dx[q] + dy[q] * dy[q] + dz[q] * dz[q];
-                    if (k0 + q < nn && r2 < R.rc2) {
-                        T r;
-                        // -dV/dr along +d pushes j; the force on i is its opposite
-                        const T f = morse_f(r2, R.ma, R.mD, R.mr0, &r);
-                        Fx -= f * dx[q];
-                        Fy -= f * dy[q];
-                        Fz -= f * dz[q];
-                        if (obs) {
-                            const double e1 = exp(-(double)R.ma * ((double)r - (double)R.mr0));
-                            pe += 0.5 * ((double)R.mD * (e1 * e1 - 2.0 * e1) - (double)R.Vc);
-                        }
-                    }
-                }
-            }
-            T vx = R.vx[i], vy = R.vy[i], vz = R.vz[i];
-            if (phase == PHASE_STEP) {
-                const T k = R.hdtm[sp];
-                vx += k * Fx;
-                vy += k * Fy;
-                vz += k * Fz;
-                if (R.ttm_mode == 1) {
-                    const int c = R.cell[i];
-                    const double Te = R.Te[c];
-                    const int canon = ((si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
-                    const Normals3<T> eta =
-                        normals3<T>(R.seed, R.run_id, (uint32_t)canon, step, 1u);
-                    const T amp = R.ou_amp[sp] * (T)sqrt(Te);
-                    const T nx = R.ou_c1 * vx + amp * eta.a;
-                    const T ny = R.ou_c1 * vy + amp * eta.b;
-                    const T nz = R.ou_c1 * vz + amp * eta.c;
-                    // mean energy the step hands to this atom given its velocity
-                    const double ke = 0.5 * (double)R.m_e[sp] *
-                                      ((double)vx * vx + (double)vy * vy + (double)vz * vz);
-                    const double dE = R.ou_1mc2 * (1.5 * kKB * Te - ke);
-                    if (fabs(dE) < 1.0e3) {
-                        const long long fixp = llrint(dE * kFIX);
-                        if (lds_acc)
-                            atomicAdd(&cacc[c], (unsigned long long)fixp);
-                        else
-                            atomicAdd(&R.dE[c], (unsigned long long)fixp);
-                    } else {
-                        atomicOr(&R.st->err, ERR_DE);
-                    }
-                    vx = nx;
-                    vy = ny;
-                    vz = nz;
-                }
-                R.vx[i] = vx;
-                R.vy[i] = vy;
-                R.vz[i] = vz;
-            }
-            R.fx[i] = Fx;
-            R.fy[i] = Fy;
-            R.fz[i] = Fz;
-            if (obs) {
-                q[14] = 0.5 * (double)R.m_e[sp] *
-                        ((double)vx * vx + (double)vy * vy + (double)vz * vz);
-                q[15] = pe;
-            }
-        }
-        if (obs) {
-            const double s0 = R.sx[i], s1 = R.sy[i], s2 = R.sz[i];
-            const V3<T> h = exchange_sum(R, si.x, si.y, si.z, si.b, sp);
-            const double h0 = h.x, h1 = h.y, h2 = h.z;
-            q[12] = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
-            q[13] = -R.mumb[sp] * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
-            const double t0 = h0 + R.mumb[sp] * R.Bd[0];
-            const double t1 = h1 + R.mumb[sp] * R.Bd[1];
-            const double t2 = h2 + R.mumb[sp] * R.Bd[2];
-            const double c0 = s1 * t2 - s2 * t1, c1 = s2 * t0 - s0 * t2, c2 = s0 * t1 - s1 * t0;
-            const double num = c0 * c0 + c1 * c1 + c2 * c2;
-            const double den = s0 * t0 + s1 * t1 + s2 * t2;
-            // per-species slots with compile-time indices (kept in registers)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const bool me = sp == t;
-                q[3 * t + 0] = me ? s0 : 0.0;
-                q[3 * t + 1] = me ? s1 : 0.0;
-                q[3 * t + 2] = me ? s2 : 0.0;
-                q[16 + t] = me ? num : 0.0;
-                q[20 + t] = me ? den : 0.0;
-            }
-        }
-    }
-    if (lds_acc) {
-        __syncthreads();
-        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
-            if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
-    }
-    if (!obs) return;
-    // one row of partial sums per 64 consecutive atoms (a wave), so the
-    // sample does not depend on the block size
-    wave_reduce_nq(q);
-    if ((threadIdx.x & 63) == 0 && i < R.n) {
-        double* row = R.partial + (size_t)(i >> 6) * NQ;
+    if ((threadIdx.x & 63) == 0 && i_first < n) {
+        double* row = partial + (size_t)(i_first >> 6) * NQ;
 #pragma unroll
         for (int k = 0; k < NQ; ++k) row[k] = q[k];
     }
@@ -631,22 +578,12 @@ template <typename T> __device__ inline double laser_power(const RunDev<T>& R, d
     return R.S0 * exp(-4.0 * 0.69314718055994530942 * d * d / (R.fwhm * R.fwhm));
 }
 
-// One explicit diffusion sub-step of e = gamma_e T^2 / 2 with the periodic
-// 7-point Laplacian: reads T from one buffer, writes the next.  The first
-// sub-step of a step starts e from the current T.
+// One explicit diffusion sub-step of cell c of e = gamma_e T^2 / 2 with the
+// periodic 7-point Laplacian of src, written to dst.  The first sub-step
+// of a step starts e from the current T.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ttm_diffuse(const RunDev<T>* __restrict__ runs,
-                                                        const int2* __restrict__ work, int sub)
+__device__ inline void diffuse_cell(const RunDev<T>& R, const double* src, double* dst, int c, int sub)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    int64_t step;
-    if (!run_active(R, &step)) return;
-    if (R.ttm_mode != 1 || R.kappa_e == 0.0 || sub >= R.n_sub) return;
-    const int c = w.y + (int)threadIdx.x;
-    if (c >= R.ncell) return;
-    const double* src = (sub & 1) ? R.Te_alt : R.Te;
-    double* dst = (sub & 1) ? R.Te : R.Te_alt;
     const int n0 = R.tn[0], n1 = R.tn[1], n2 = R.tn[2];
     const int i = c % n0, j = (c / n0) % n1, k = c / (n0 * n1);
     const int ip = (i + 1) % n0, im = (i + n0 - 1) % n0;
@@ -668,25 +605,218 @@ __global__ __launch_bounds__(kBlock) void k_ttm_diffuse(const RunDev<T>* __restr
 
 // Laser source and electron-phonon energy of one cell (two-temperature
 // mode): e = (after diffusion, or gamma_e T^2 / 2) + dt S(z, t + dt/2)
-// - dE / V, T_e = sqrt(2 e / gamma_e).
-template <typename T> __device__ inline void cell_update(const RunDev<T>& R, int c, int64_t step)
+// - dE / V, T_e = sqrt(2 e / gamma_e).  dE is the cell's fixed-point sum.
+template <typename T>
+__device__ inline void cell_update(const RunDev<T>& R, double* Te, unsigned long long* dEsum, int c,
+                                   int64_t step)
 {
     const double ge = R.gamma_e;
-    const double T0 = R.Te[c];
+    const double T0 = Te[c];
     const double e0 = R.kappa_e != 0.0 ? R.ee[c] : 0.5 * ge * T0 * T0;
     const int k = c / (R.tn[0] * R.tn[1]);
     const double tmid = ((double)step + 0.5) * R.dtd;
     const double src = laser_power(R, (k + 0.5) * R.th[2], tmid);
-    const double de = (double)(long long)R.dE[c] / kFIX;
-    R.dE[c] = 0ull;
+    const double de = (double)(long long)dEsum[c] / kFIX;
+    dEsum[c] = 0ull;
     const double e = e0 + R.dtd * src - de / R.Vcell;
     R.ee[c] = e;
     if (e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
-    R.Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
+    Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
 }
 
-// Cell-parallel update of large electron grids (ncell > kSmallGrid).
-constexpr int kSmallGrid = 4096;
+constexpr int kSmallGrid = 4096;   // larger electron grids update cell-parallel
+
+// The observable sample of a run, computed by threads 0..255 of one block
+// (the others idle): per-wave partial rows in order, electron-grid sums in
+// a fixed-shape tree.  `step_of_sample` is the step the sample describes.
+struct SampleScratch {
+    double red[3][kBlock];
+    double tot[NQ];
+};
+
+template <typename T>
+__device__ inline void write_sample(const RunDev<T>& R, const View<T>& V, SampleScratch& S,
+                                    int64_t step_of_sample)
+{
+    const int tid = threadIdx.x;
+    const int nc = R.ncell;
+    if (tid < NQ) {
+        double acc = 0.0;
+        for (int bk = 0; bk < R.n_part; ++bk) acc += V.partial[(size_t)bk * NQ + tid];
+        S.tot[tid] = acc;
+    }
+    if (tid < kBlock) {
+        double eacc = 0.0, tacc = 0.0, tmax = 0.0;
+        for (int c = tid; c < nc; c += kBlock) {
+            const double Tc = V.Te[c];
+            eacc += 0.5 * R.gamma_e * Tc * Tc * R.Vcell;
+            tacc += Tc;
+            tmax = Tc > tmax ? Tc : tmax;
+        }
+        S.red[0][tid] = eacc;
+        S.red[1][tid] = tacc;
+        S.red[2][tid] = tmax;
+    }
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            S.red[0][tid] += S.red[0][tid + off];
+            S.red[1][tid] += S.red[1][tid + off];
+            S.red[2][tid] = S.red[2][tid] > S.red[2][tid + off] ? S.red[2][tid] : S.red[2][tid + off];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        RunState* st = R.st;
+        const int64_t ns = st->n_samples;
+        sl_obs* o = &R.ring[ns % R.obs_cap];
+        o->t = (double)step_of_sample * R.dtd;
+        o->step = step_of_sample;
+        double m[3] = {0.0, 0.0, 0.0};
+        for (int sp = 0; sp < 4; ++sp)
+            for (int k = 0; k < 3; ++k) {
+                m[k] += S.tot[3 * sp + k];
+                o->M[sp][k] = R.cnt[sp] > 0.0 ? S.tot[3 * sp + k] / R.cnt[sp] : 0.0;
+            }
+        for (int k = 0; k < 3; ++k) o->m[k] = m[k] / (double)R.n;
+        o->m_abs = sqrt(o->m[0] * o->m[0] + o->m[1] * o->m[1] + o->m[2] * o->m[2]);
+        o->E_ex = S.tot[12];
+        o->E_z = S.tot[13];
+        o->KE = S.tot[14];
+        o->PE = S.tot[15];
+        o->E_e = S.red[0][0];
+        o->Te_mean = S.red[1][0] / (double)nc;
+        o->Te_max = S.red[2][0];
+        o->Tl = 2.0 * S.tot[14] / (3.0 * (double)R.n * kKB);
+        for (int sp = 0; sp < 4; ++sp)
+            o->Tspin[sp] = S.tot[20 + sp] != 0.0 ? S.tot[16 + sp] / (2.0 * kKB * S.tot[20 + sp]) : 0.0;
+        st->n_samples = ns + 1;
+    }
+    __syncthreads();
+}
+
+template <typename T> __device__ inline bool sample_due(const RunDev<T>& R, int phase, int64_t step)
+{
+    return R.obs_every > 0 && (phase == PHASE_INIT || ((step + 1) % R.obs_every) == 0);
+}
+
+// ==================================================== multi-kernel step
+template <typename T, int SPT>
+__global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
+                                                      const int2* __restrict__ work, int pass)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (!run_active(R, &step)) return;
+    if (pass >= 2 * R.g.C - 1) return;
+    int colour;
+    T tau;
+    pass_colour(R, pass, &colour, &tau);
+    const View<T> V = global_view(R);
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int l = w.y + k * (int)blockDim.x + (int)threadIdx.x;
+        if (l < R.g.H) spin_site(R, V, colour, tau, l, step);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kick_drift(const RunDev<T>* __restrict__ runs,
+                                                       const int2* __restrict__ work, int phase)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (phase == PHASE_STEP) {
+        if (!run_active(R, &step) || !R.live) return;
+    }
+    const int i = w.y + (int)threadIdx.x;
+    if (i >= R.n) return;
+    if (kick_drift_atom(R, global_view(R), i, phase)) atomicOr(&R.st->rebuild, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict__ runs,
+                                                    const int2* __restrict__ work)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
+    const int i = w.y + (int)threadIdx.x;
+    if (i < R.n) nbr_bin_atom(R, global_view(R), i);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict__ runs,
+                                                     const int2* __restrict__ work)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
+    const int bin = w.y + (int)threadIdx.x;
+    if (bin < R.nbins) nbr_sort_bin(R, bin);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restrict__ runs,
+                                                      const int2* __restrict__ work)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
+    const int i = w.y + (int)threadIdx.x;
+    if (i < R.n) nbr_build_atom(R, global_view(R), i);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
+                                                       const int2* __restrict__ work, int phase)
+{
+    __shared__ unsigned long long cacc[kLdsCells];
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step = R.st->step;
+    if (phase == PHASE_STEP) {
+        if (!run_active(R, &step)) return;
+    }
+    const bool obs = sample_due(R, phase, step);
+    if (!R.live && !obs) return;
+    // electron-phonon energy per cell: first summed in LDS (fixed point, so
+    // the order does not matter), then one global atomic per touched cell
+    const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
+    const bool lds_acc = eph && R.ncell <= kLdsCells;
+    if (lds_acc) {
+        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
+        __syncthreads();
+    }
+    const int i = w.y + (int)threadIdx.x;
+    double q[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+    if (i < R.n)
+        atom_final_atom(R, global_view(R), i, phase, step, obs, lds_acc ? cacc : R.dE, q);
+    if (lds_acc) {
+        __syncthreads();
+        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
+            if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
+    }
+    if (obs) wave_reduce_row(q, R.partial, i - (int)(threadIdx.x & 63), R.n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ttm_diffuse(const RunDev<T>* __restrict__ runs,
+                                                        const int2* __restrict__ work, int sub)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    int64_t step;
+    if (!run_active(R, &step)) return;
+    if (R.ttm_mode != 1 || R.kappa_e == 0.0 || sub >= R.n_sub) return;
+    const int c = w.y + (int)threadIdx.x;
+    if (c >= R.ncell) return;
+    diffuse_cell(R, (sub & 1) ? R.Te_alt : R.Te, (sub & 1) ? R.Te : R.Te_alt, c, sub);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ runs,
@@ -697,88 +827,196 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     int64_t step;
     if (!run_active(R, &step) || R.ttm_mode != 1 || R.ncell <= kSmallGrid) return;
     const int c = w.y + (int)threadIdx.x;
-    if (c < R.ncell) cell_update(R, c, step);
+    if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step);
 }
 
-// One block per run: small electron grids, the observable sample (fixed
-// order over blocks and cells), bins emptied after a rebuild, step + 1.
+// One block per run: small electron grids, the observable sample, bins
+// emptied after a rebuild, step + 1.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
                                                      const int* __restrict__ run_list, int phase)
 {
-    __shared__ double red[3][kBlock];
-    __shared__ double tot[NQ];
+    __shared__ SampleScratch S;
     const RunDev<T>& R = runs[run_list[blockIdx.x]];
     RunState* st = R.st;
     const int64_t step = st->step;
     if (phase == PHASE_STEP && (st->err != 0 || step >= st->target)) return;
     const int tid = threadIdx.x;
-    const int nc = R.ncell;
-    if (phase == PHASE_STEP && R.ttm_mode == 1 && nc <= kSmallGrid) {
-        for (int c = tid; c < nc; c += kBlock) cell_update(R, c, step);
+    if (phase == PHASE_STEP && R.ttm_mode == 1 && R.ncell <= kSmallGrid) {
+        for (int c = tid; c < R.ncell; c += blockDim.x) cell_update(R, R.Te, R.dE, c, step);
         __syncthreads();
     }
-    const bool obs = R.obs_every > 0 &&
-                     (phase == PHASE_INIT || ((step + 1) % R.obs_every) == 0);
-    if (obs) {
-        if (tid < NQ) {
-            double acc = 0.0;
-            for (int bk = 0; bk < R.n_part; ++bk) acc += R.partial[(size_t)bk * NQ + tid];
-            tot[tid] = acc;
-        }
-        double eacc = 0.0, tacc = 0.0, tmax = 0.0;
-        for (int c = tid; c < nc; c += kBlock) {
-            const double Tc = R.Te[c];
-            eacc += 0.5 * R.gamma_e * Tc * Tc * R.Vcell;
-            tacc += Tc;
-            tmax = Tc > tmax ? Tc : tmax;
-        }
-        red[0][tid] = eacc;
-        red[1][tid] = tacc;
-        red[2][tid] = tmax;
-        __syncthreads();
-        for (int off = kBlock / 2; off > 0; off >>= 1) {
-            if (tid < off) {
-                red[0][tid] += red[0][tid + off];
-                red[1][tid] += red[1][tid + off];
-                red[2][tid] = red[2][tid] > red[2][tid + off] ? red[2][tid] : red[2][tid + off];
-            }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            const int64_t sample_step = phase == PHASE_INIT ? step : step + 1;
-            const int64_t ns = st->n_samples;
-            sl_obs* o = &R.ring[ns % R.obs_cap];
-            o->t = (double)sample_step * R.dtd;
-            o->step = sample_step;
-            double m[3] = {0.0, 0.0, 0.0};
-            for (int sp = 0; sp < 4; ++sp)
-                for (int k = 0; k < 3; ++k) {
-                    m[k] += tot[3 * sp + k];
-                    o->M[sp][k] = R.cnt[sp] > 0.0 ? tot[3 * sp + k] / R.cnt[sp] : 0.0;
-                }
-            for (int k = 0; k < 3; ++k) o->m[k] = m[k] / (double)R.n;
-            o->m_abs = sqrt(o->m[0] * o->m[0] + o->m[1] * o->m[1] + o->m[2] * o->m[2]);
-            o->E_ex = tot[12];
-            o->E_z = tot[13];
-            o->KE = tot[14];
-            o->PE = tot[15];
-            o->E_e = red[0][0];
-            o->Te_mean = red[1][0] / (double)nc;
-            o->Te_max = red[2][0];
-            o->Tl = 2.0 * tot[14] / (3.0 * (double)R.n * kKB);
-            for (int sp = 0; sp < 4; ++sp)
-                o->Tspin[sp] = tot[20 + sp] != 0.0 ? tot[16 + sp] / (2.0 * kKB * tot[20 + sp]) : 0.0;
-            st->n_samples = ns + 1;
-        }
-    }
+    if (sample_due(R, phase, step))
+        write_sample(R, global_view(R), S, phase == PHASE_INIT ? step : step + 1);
     // neighbour bins are emptied after a rebuild, ready for the next one
     if (R.live && st->rebuild != 0) {
-        for (int b = tid; b < R.nbins; b += kBlock) R.bin_n[b] = 0;
+        for (int b = tid; b < R.nbins; b += blockDim.x) R.bin_n[b] = 0;
         __syncthreads();
         if (tid == 0) st->rebuild = 0;
     }
     if (tid == 0 && phase == PHASE_STEP) st->step = step + 1;
+}
+
+// ==================================================== persistent kernel
+// One block advances one run by up to `nsteps` steps in a single launch.
+// Spins, species, electron-cell ids, the electron grid, the per-cell
+// electron-phonon sums and the observable rows live in LDS (positions too
+// when they fit); phases are separated by block barriers only.  The
+// arithmetic of every site, atom and cell is that of the multi-kernel step,
+// so a run gives the same bits on either executor.
+struct PersistLayout {
+    uint32_t off_s, off_species, off_cell, off_pos, off_Te, off_Te2, off_acc, off_part, bytes;
+    int32_t pos_in_lds;
+};
+
+template <typename T>
+__host__ __device__ inline PersistLayout persist_layout(int n, int ncell, int n_part, bool live,
+                                                        int n_species, uint32_t lds_max)
+{
+    PersistLayout L{};
+    uint32_t o = 0;
+    auto take = [&](uint32_t bytes) {
+        const uint32_t at = o;
+        o += (bytes + 15u) & ~15u;
+        return at;
+    };
+    L.off_s = take(3u * (uint32_t)n * (uint32_t)sizeof(T));
+    L.off_species = n_species > 1 ? take((uint32_t)n) : 0u;
+    L.off_cell = take(2u * (uint32_t)n);
+    L.off_Te = take(8u * (uint32_t)ncell);
+    L.off_Te2 = take(8u * (uint32_t)ncell);
+    L.off_acc = take(8u * (uint32_t)ncell);
+    L.off_part = take(8u * NQ * (uint32_t)n_part);
+    L.pos_in_lds = 0;
+    L.off_pos = 0;
+    if (live && o + (uint32_t)n * (uint32_t)sizeof(Pos4<T>) <= lds_max) {
+        L.off_pos = take((uint32_t)n * (uint32_t)sizeof(Pos4<T>));
+        L.pos_in_lds = 1;
+    }
+    L.bytes = o;
+    return L;
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_persist(const RunDev<T>* __restrict__ runs,
+                                                  const int* __restrict__ run_list, int nsteps,
+                                                  uint32_t lds_max)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ SampleScratch S;
+    __shared__ int flag_rebuild;
+    __shared__ int flag_stop;
+    const RunDev<T>& R = runs[run_list[blockIdx.x]];
+    RunState* st = R.st;
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int n = R.n, nc = R.ncell;
+    const PersistLayout L = persist_layout<T>(n, nc, R.n_part, R.live != 0, R.n_species, lds_max);
+    View<T> V;
+    V.sx = reinterpret_cast<T*>(smem + L.off_s);
+    V.sy = V.sx + n;
+    V.sz = V.sy + n;
+    V.species = R.n_species > 1 ? reinterpret_cast<const int8_t*>(smem + L.off_species) : R.species;
+    V.cell = reinterpret_cast<uint16_t*>(smem + L.off_cell);
+    V.pos = L.pos_in_lds ? reinterpret_cast<Pos4<T>*>(smem + L.off_pos) : R.pos;
+    V.Te = reinterpret_cast<double*>(smem + L.off_Te);
+    double* Te2 = reinterpret_cast<double*>(smem + L.off_Te2);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.off_acc);
+    V.partial = reinterpret_cast<double*>(smem + L.off_part);
+    // load the run into LDS
+    for (int i = tid; i < n; i += B) {
+        V.sx[i] = R.sx[i];
+        V.sy[i] = R.sy[i];
+        V.sz[i] = R.sz[i];
+        V.cell[i] = R.cell[i];
+        if (R.n_species > 1) const_cast<int8_t*>(V.species)[i] = R.species[i];
+        if (L.pos_in_lds) V.pos[i] = R.pos[i];
+    }
+    for (int c = tid; c < nc; c += B) {
+        V.Te[c] = R.Te[c];
+        acc[c] = 0ull;
+    }
+    for (int k = tid; k < R.n_part * NQ; k += B) V.partial[k] = 0.0;
+    int64_t step = st->step;
+    const int64_t target = st->target;
+    // A step that raises an error is abandoned where the multi-kernel step
+    // would abandon it: the rest of the step is skipped and the step
+    // counter keeps the step's number.
+    auto error_raised = [&]() {
+        __syncthreads();
+        if (tid == 0) flag_stop = st->err != 0 ? 1 : 0;
+        __syncthreads();
+        return flag_stop != 0;
+    };
+    const bool run = !error_raised() && step < target;
+    for (int it = 0; run && it < nsteps && step < target; ++it) {
+        if (tid == 0) flag_rebuild = 0;
+        // spins: the colour sweep
+        for (int pass = 0; pass < 2 * R.g.C - 1; ++pass) {
+            __syncthreads();
+            int colour;
+            T tau;
+            pass_colour(R, pass, &colour, &tau);
+            for (int l = tid; l < R.g.H; l += B) spin_site(R, V, colour, tau, l, step);
+        }
+        __syncthreads();
+        // lattice: kick and drift, list rebuild when flagged
+        if (R.live) {
+            for (int i = tid; i < n; i += B)
+                if (kick_drift_atom(R, V, i, PHASE_STEP)) atomicOr(&flag_rebuild, 1);
+            if (tid == 0) st->step = step;   // read by the overflow diagnostics
+            __syncthreads();
+            if (flag_rebuild) {
+                for (int i = tid; i < n; i += B) nbr_bin_atom(R, V, i);
+                if (error_raised()) break;
+                for (int b = tid; b < R.nbins; b += B) nbr_sort_bin(R, b);
+                __syncthreads();
+                for (int i = tid; i < n; i += B) nbr_build_atom(R, V, i);
+                if (error_raised()) break;
+                for (int b = tid; b < R.nbins; b += B) R.bin_n[b] = 0;
+            }
+        }
+        // forces, electron-phonon step, observable rows
+        const bool obs = sample_due(R, PHASE_STEP, step);
+        if (R.live || obs) {
+            for (int base = 0; base < n; base += B) {
+                const int i = base + tid;
+                double q[NQ];
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+                if (i < n) atom_final_atom(R, V, i, PHASE_STEP, step, obs, acc, q);
+                if (obs) wave_reduce_row(q, V.partial, i - (tid & 63), n);
+            }
+        }
+        if (error_raised()) break;
+        // electron grid
+        if (R.ttm_mode == 1) {
+            if (R.kappa_e != 0.0) {
+                for (int sub = 0; sub < R.n_sub; ++sub) {
+                    for (int c = tid; c < nc; c += B)
+                        diffuse_cell(R, (sub & 1) ? Te2 : V.Te, (sub & 1) ? V.Te : Te2, c, sub);
+                    __syncthreads();
+                }
+            }
+            for (int c = tid; c < nc; c += B) cell_update(R, V.Te, acc, c, step);
+            if (error_raised()) break;
+        }
+        if (obs) write_sample(R, V, S, step + 1);
+        ++step;
+    }
+    __syncthreads();
+    // write the run back
+    for (int i = tid; i < n; i += B) {
+        R.sx[i] = V.sx[i];
+        R.sy[i] = V.sy[i];
+        R.sz[i] = V.sz[i];
+        R.cell[i] = V.cell[i];
+        if (L.pos_in_lds) R.pos[i] = V.pos[i];
+    }
+    for (int c = tid; c < nc; c += B) R.Te[c] = V.Te[c];
+    if (tid == 0) {
+        st->step = step;
+        st->rebuild = 0;
+    }
 }
 
 }  // namespace sl

@@ -60,6 +60,8 @@ struct DevAlloc {
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+constexpr int64_t kPersistChunk = 4096;   // steps per persistent launch
+
 // Carves typed sub-arrays out of one allocation.
 struct Carver {
     size_t off = 0;
@@ -260,7 +262,7 @@ public:
                           int64_t max_samples, int64_t* n_obs) = 0;
     virtual sl_status remove(int slot) = 0;
     virtual sl_status sync() = 0;
-    virtual sl_status profiled(int64_t n, double avg[4], int64_t cnt[4]) = 0;
+    virtual sl_status profiled(int64_t n, double avg[5], int64_t cnt[5]) = 0;
     std::vector<Run> runs;
     DevAlloc alloc;
     hipStream_t stream = nullptr;
@@ -271,6 +273,7 @@ public:
     int precision = SL_FP64;
     // launch shape (every choice gives bitwise-identical results)
     int spin_block = 256, spin_spt = 1, atom_block = 256;
+    int persist_block = 0;          // 0: every run on the multi-kernel step
     virtual sl_status retune() = 0;
 };
 
@@ -288,6 +291,9 @@ public:
         for (void* p : tables) alloc.put(p);
         alloc.put(d_runs);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (side_stream) (void)hipStreamDestroy(side_stream);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 
@@ -297,6 +303,18 @@ public:
         if (!d_runs) return fail(SL_ENOMEM, "device allocation of the run table failed");
         SL_HIP(hipMemset(d_runs, 0, sizeof(RD) * runs.size()));
         SL_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        SL_HIP(hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking));
+        SL_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        SL_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+        // LDS available to the persistent kernel's dynamic buffer
+        int dev = 0, per_block = 0;
+        SL_HIP(hipGetDevice(&dev));
+        SL_HIP(hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        hipFuncAttributes fa{};
+        SL_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sl::k_persist<T>)));
+        lds_max = per_block > (int)fa.sharedSizeBytes ? (uint32_t)(per_block - (int)fa.sharedSizeBytes) : 0u;
+        SL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sl::k_persist<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
         return SL_OK;
     }
 
@@ -378,8 +396,21 @@ public:
             sl_status st = rebuild_tables();
             if (st != SL_OK) return st;
         }
-        if (active_blocks_atom == 0) return SL_OK;
-        int64_t left = n;
+        if (active_blocks_atom == 0 && persist_runs == 0) return SL_OK;
+        // the runs that live in LDS advance in persistent launches on a side
+        // stream, concurrently with the multi-kernel step of the others
+        if (persist_runs > 0) {
+            SL_HIP(hipEventRecord(ev_fork, stream));
+            SL_HIP(hipStreamWaitEvent(side_stream, ev_fork, 0));
+            for (int64_t done = 0; done < n; done += kPersistChunk) {
+                const int k = (int)std::min<int64_t>(kPersistChunk, n - done);
+                sl::k_persist<T><<<persist_runs, persist_block, persist_bytes, side_stream>>>(
+                    d_runs, d_persist_list, k, lds_max);
+            }
+            SL_HIP(hipGetLastError());
+            SL_HIP(hipEventRecord(ev_join, side_stream));
+        }
+        int64_t left = active_blocks_atom > 0 ? n : 0;
         if (graph_steps > 1 && left >= graph_steps) {
             if (!graph_ok) {
                 sl_status st = capture();
@@ -392,13 +423,15 @@ public:
         }
         for (int64_t k = 0; k < left; ++k) enqueue_step(stream, nullptr);
         SL_HIP(hipGetLastError());
+        if (persist_runs > 0) SL_HIP(hipStreamWaitEvent(stream, ev_join, 0));
         for (auto& r : runs)
             if (r.used) r.steps = std::min(r.target, r.steps + n);
         return SL_OK;
     }
 
-    sl_status profiled(int64_t n, double avg[4], int64_t cnt[4]) override
+    sl_status profiled(int64_t n, double avg[5], int64_t cnt[5]) override
     {
+        if (n > kPersistChunk) return fail(SL_EINVAL, "profile at most 4096 steps per call");
         if (tables_dirty) {
             sl_status st = rebuild_tables();
             if (st != SL_OK) return st;
@@ -406,13 +439,20 @@ public:
         std::vector<hipEvent_t> ev;
         std::vector<int> cls;
         Prof p{&ev, &cls};
-        for (int64_t k = 0; k < n; ++k) {
+        if (persist_runs > 0) {
+            sl_status st = timed(stream, &p, 4, [&] {
+                sl::k_persist<T><<<persist_runs, persist_block, persist_bytes, stream>>>(
+                    d_runs, d_persist_list, (int)n, lds_max);
+            });
+            if (st != SL_OK) return st;
+        }
+        for (int64_t k = 0; k < n && active_blocks_atom > 0; ++k) {
             sl_status st = enqueue_step(stream, &p);
             if (st != SL_OK) return st;
         }
         SL_HIP(hipStreamSynchronize(stream));
-        double tot[4] = {0, 0, 0, 0};
-        int64_t c[4] = {0, 0, 0, 0};
+        double tot[5] = {0, 0, 0, 0, 0};
+        int64_t c[5] = {0, 0, 0, 0, 0};
         for (size_t k = 0; k + 1 < ev.size(); k += 2) {
             float ms = 0.f;
             SL_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
@@ -420,7 +460,7 @@ public:
             c[cls[k / 2]] += 1;
         }
         for (auto e : ev) (void)hipEventDestroy(e);
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 5; ++k) {
             avg[k] = c[k] ? tot[k] / c[k] : 0.0;
             cnt[k] = c[k];
         }
@@ -554,6 +594,13 @@ private:
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
     bool tables_dirty = true;
+    // persistent executor: runs that fit in LDS, one block each
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    uint32_t lds_max = 0;
+    int* d_persist_list = nullptr;
+    int persist_runs = 0;
+    uint32_t persist_bytes = 0;
 
     sl_status numeric_error(int s, int err)
     {
@@ -843,9 +890,20 @@ private:
         std::vector<int> rl;
         any_live = false;
         max_sub = 0;
+        std::vector<int> pl;
+        persist_bytes = 0;
         for (size_t s = 0; s < runs.size(); ++s) {
             if (!runs[s].used) continue;
             const RD& R = host_rd[s];
+            if (persist_block > 0) {
+                const sl::PersistLayout L = sl::persist_layout<T>(R.n, R.ncell, R.n_part, R.live != 0,
+                                                                  R.n_species, lds_max);
+                if (L.bytes <= lds_max) {
+                    pl.push_back((int)s);
+                    persist_bytes = std::max(persist_bytes, L.bytes);
+                    continue;
+                }
+            }
             for (int st = 0; st < R.g.H; st += spin_block * spin_spt) ws.push_back(make_int2((int)s, st));
             for (int st = 0; st < R.n; st += atom_block) wa.push_back(make_int2((int)s, st));
             for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2((int)s, st));
@@ -868,6 +926,8 @@ private:
         active_blocks_diff = (int)wd.size();
         active_runs = (int)rl.size();
         d_run_list = nullptr;
+        persist_runs = (int)pl.size();
+        d_persist_list = nullptr;
         auto up = [&](const void* src, size_t bytes, void** dst) -> sl_status {
             if (bytes == 0) return SL_OK;
             void* p = alloc.get(bytes);
@@ -884,6 +944,7 @@ private:
         if ((st = up(wc.data(), sizeof(int2) * wc.size(), (void**)&d_work_cell)) != SL_OK) return st;
         if ((st = up(wd.data(), sizeof(int2) * wd.size(), (void**)&d_work_diff)) != SL_OK) return st;
         if ((st = up(rl.data(), sizeof(int) * rl.size(), (void**)&d_run_list)) != SL_OK) return st;
+        if ((st = up(pl.data(), sizeof(int) * pl.size(), (void**)&d_persist_list)) != SL_OK) return st;
         SL_HIP(hipStreamSynchronize(stream));
         return SL_OK;
     }
@@ -1066,7 +1127,7 @@ sl_status sl_step(sl_system h, int64_t n_steps)
     return h->eng->advance(n_steps);
 }
 
-sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[4], int64_t launches[4])
+sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5])
 {
     if (!h || !avg_ms || !launches) return fail(SL_EINVAL, "null argument");
     return h->eng->profiled(n_steps, avg_ms, launches);
@@ -1108,10 +1169,13 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     if (!blk_ok) return fail(SL_EINVAL, "block sizes must be 64, 128 or 256");
     if (t->spin_spt != 1 && t->spin_spt != 2 && t->spin_spt != 4) return fail(SL_EINVAL, "spin_spt must be 1, 2 or 4");
     if (t->graph_steps < 1 || t->graph_steps > 256) return fail(SL_EINVAL, "graph_steps must be 1..256");
+    if (t->persist_block != 0 && t->persist_block != 256 && t->persist_block != 512)
+        return fail(SL_EINVAL, "persist_block must be 0, 256 or 512");
     e->spin_block = t->spin_block;
     e->spin_spt = t->spin_spt;
     e->atom_block = t->atom_block;
     e->graph_steps = t->graph_steps;
+    e->persist_block = t->persist_block;
     return e->retune();
 }
 
@@ -1121,6 +1185,7 @@ static void get_tuning(const Engine* e, sl_tuning* t)
     t->spin_spt = e->spin_spt;
     t->atom_block = e->atom_block;
     t->graph_steps = e->graph_steps;
+    t->persist_block = e->persist_block;
 }
 
 sl_status sl_set_tuning(sl_system h, const sl_tuning* t)
@@ -1162,6 +1227,7 @@ sl_status sl_batch_create(const sl_batch_desc* desc, sl_batch* out)
     sl_status st = setup_engine(b->eng.get(), desc->precision, desc->stream, desc->alloc,
                                 desc->mem_budget, desc->graph_steps);
     if (st != SL_OK) return st;
+    b->eng->persist_block = 512;
     *out = b.release();
     return SL_OK;
 }
@@ -1186,7 +1252,7 @@ sl_status sl_batch_advance(sl_batch b, int64_t n_steps)
     return b->eng->advance(n_steps);
 }
 
-sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[4], int64_t launches[4])
+sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[5], int64_t launches[5])
 {
     if (!b || !avg_ms || !launches) return fail(SL_EINVAL, "null argument");
     return b->eng->profiled(n_steps, avg_ms, launches);

@@ -79,7 +79,7 @@ class sl_batch_desc(C.Structure):
 
 class sl_tuning(C.Structure):
     _fields_ = [("spin_block", C.c_int32), ("spin_spt", C.c_int32), ("atom_block", C.c_int32),
-                ("graph_steps", C.c_int32)]
+                ("graph_steps", C.c_int32), ("persist_block", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -329,8 +329,8 @@ class System:
         return a.value, b.value, c.value
 
     def step_profiled(self, n: int):
-        avg = (C.c_double * 4)()
-        cnt = (C.c_int64 * 4)()
+        avg = (C.c_double * 5)()
+        cnt = (C.c_int64 * 5)()
         check(lib().sl_step_profiled(self._h, int(n), avg, cnt))
         return list(avg), list(cnt)
 
@@ -418,8 +418,8 @@ class Batch:
         return t.to_dict()
 
     def advance_profiled(self, n: int):
-        avg = (C.c_double * 4)()
-        cnt = (C.c_int64 * 4)()
+        avg = (C.c_double * 5)()
+        cnt = (C.c_int64 * 5)()
         check(lib().sl_batch_advance_profiled(self._h, int(n), avg, cnt))
         return list(avg), list(cnt)
 
