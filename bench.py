@@ -24,7 +24,41 @@ if ROOT not in sys.path:
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["spin_pass", "atom_final", "kick_drift", "grid"]
+KERNELS = ["spin_pass", "atom_final", "kick_drift", "grid", "persist"]
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_digest() -> str:
+    """SHA-256 over the kernel sources and the C header, the key under which
+    counter-derived traffic figures are stored."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2608_18541_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "spinlattice.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    copy-kernel calibration), or None when there is none or the kernels
+    changed since the counters were taken."""
+    path = os.path.join(PROFILES, "%s_%s_traffic.txt" % (kernel, workload))
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != source_digest():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def bytes_per_unit(kernel: str, fp: int, n_species: int, z_list: float) -> float:
@@ -142,7 +176,8 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
     one-request-at-a-time plain FP64 baseline on the same trace."""
     trace = W.request_trace(n=n_req, rate=50.0, seed=7, steps_scale=steps_scale)
     batch = N.Batch(precision=N.SL_FP32, max_runs=512, mem_budget=24 << 30)
-    srv = S.Server(batch, chunk=500, obs_every=100)
+    srv = S.Server(batch, chunk=500, obs_every=100,
+                   progress=lambda m: print("bench: serving: " + m, file=sys.stderr, flush=True))
     res = srv.run(trace)
     st = S.summarize(res, srv.makespan)
     batch.close()
@@ -201,6 +236,39 @@ def large_run(N, I, steps: int) -> dict:
                                                               np.sqrt((g64["v"] ** 2).mean()))}}
 
 
+def field_llg_scale(N, I, L: int = 256) -> dict:
+    """The field + LLG colour pass alone (frozen lattice, constant bath) on
+    bcc Fe L^3 in FP32, large enough (2 L^3 sites) that the spins do not fit
+    in the 256 MB last-level cache: achieved algorithmic bandwidth of one
+    pass and, when committed counters match these kernels, its measured HBM
+    traffic."""
+    spec = I.fe_bcc_spec(L=L, lattice_mode=0)
+    st = I.initial_state(spec, "tilt")
+    s = N.System(spec, st, precision=N.SL_FP32, obs_every=0)
+    del st
+    s.step(4)
+    s.synchronize()
+    from paper_2608_18541_amd.autotune import autotune
+    tuning = autotune(s, steps=8, rounds=2, use_cache=False)
+    avg, cnt = s.step_profiled(10)
+    s.close()
+    H = spec.n_sites / 4
+    bpu = bytes_per_unit("spin_pass", 1, spec.n_species, 0)
+    us = avg[0] * 1e3
+    ach = bpu * H / (us * 1e-6) / 1e9
+    traffic = measured_traffic("spin_pass", "fe%d_fp32" % L)
+    out = {"workload": "bcc Fe %d^3 (%d sites) FP32, frozen lattice, 300 K bath, field + LLG "
+                       "colour pass" % (L, spec.n_sites),
+           "avg_launch_us": round(us, 3), "sites_per_launch": int(H),
+           "site_passes_per_s": H / (us * 1e-6),
+           "achieved_GBs": round(ach, 1), "peak_GBs": HBM_PEAK_GBS,
+           "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_site": bpu, "tuning": tuning,
+           "traffic_bytes_per_launch": None if traffic is None else int(traffic)}
+    if traffic is not None:
+        out["traffic_GBs"] = round(traffic / (us * 1e-6) / 1e9, 1)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,7 +278,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, served and large-run measurements")
-    ap.add_argument("--extras", default="batched,serving,large",
+    ap.add_argument("--extras", default="batched,serving,large,scale",
                     help="comma list of extra measurements")
     ap.add_argument("--pd-steps", type=int, default=20000)
     ap.add_argument("--pd-seeds", type=int, default=20)
@@ -255,8 +323,10 @@ def main() -> int:
     units = units_per_launch(dom, spec.n_sites, 2)
     alg_bytes = bpu * units
     achieved = alg_bytes / (avg[di] * 1e-3) / 1e9 if avg[di] > 0 else 0.0
+    traffic = measured_traffic(dom, "alloy32_fp64")
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None if traffic is None else int(traffic),
             "avg_launch_us": round(avg[di] * 1e3, 3), "bytes_per_launch": int(alg_bytes),
             "per_step_us": {k: round(v * 1e3, 3) for k, v in per_step.items()}}
     sys_.close()
@@ -283,6 +353,8 @@ def main() -> int:
         out["serving"] = serving(N, W, S, args.serve_requests, args.serve_steps_scale)
     if "large" in extras:
         out["large"] = large_run(N, I, args.large_steps)
+    if "scale" in extras:
+        out["field_llg_scale"] = field_llg_scale(N, I)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, st)

@@ -197,6 +197,9 @@ typedef struct sl_tuning {
                                  runs that fit in LDS advance in a persistent kernel,
                                  one block of this many threads per run (batches
                                  default to 512, single systems to 0)               */
+    int32_t xcd_order;        /* 1: work tables ordered so that each of the 8 XCDs
+                                 receives one contiguous range of tiles (its L2
+                                 then holds their neighbours); 0: round-robin    */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of

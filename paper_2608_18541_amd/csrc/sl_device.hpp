@@ -70,9 +70,11 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a = 0xD2511F53u, b = 0xCD9E8D57u;
-        uint32_t hi0 = mulhi32(a, c.x), lo0 = a * c.x;
-        uint32_t hi1 = mulhi32(b, c.z), lo1 = b * c.z;
+        // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32 on gfx950)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         U4 n;
         n.x = hi1 ^ c.y ^ k0;
         n.y = lo1;
@@ -122,10 +124,11 @@ __device__ inline Normals3<float> normals3_f32(uint32_t seed, uint32_t run, uint
     float u1 = ((float)(w.y >> 8) + 0.5f) * 5.9604644775390625e-8f;
     float u2 = ((float)(w.z >> 8) + 0.5f) * 5.9604644775390625e-8f;
     float u3 = ((float)(w.w >> 8) + 0.5f) * 5.9604644775390625e-8f;
-    // hardware log / sin / cos (a few ulp): the single-precision path is
-    // compared with double precision statistically, not per trajectory
-    float r0 = sqrtf(-2.0f * __logf(u0));
-    float r1 = sqrtf(-2.0f * __logf(u2));
+    // hardware log2 / sqrt / sin / cos (a few ulp): the single-precision
+    // path is compared with double precision statistically, not per
+    // trajectory.  -2 ln u = -2 ln(2) log2(u); u >= 2^-25 is never denormal.
+    float r0 = __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u0));
+    float r1 = __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u2));
     float s1, c1;
     __sincosf(6.28318530717958648f * u1, &s1, &c1);
     float c3 = __cosf(6.28318530717958648f * u3);
@@ -190,6 +193,41 @@ __device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2)
     double oz = (double)(ct * e.z + f * (cs * p.z + sn * ex.z));
     double inv = 1.0 / sqrt(ox * ox + oy * oy + oz * oz);
     return {(T)(ox * inv), (T)(oy * inv), (T)(oz * inv)};
+}
+
+// Single precision: the same flow with the hardware reciprocal, reciprocal
+// square root, exponential and sine/cosine (about 1 ulp each).  The result
+// is renormalised in double: its squared norm is 1 + eps with |eps| of a
+// few float ulps, so 1/sqrt(1 + eps) = 1 - eps/2 + 3 eps^2/8 to within
+// 5|eps|^3/16 (below 1e-15 for |eps| < 1e-5); larger eps takes the exact
+// reciprocal square root.
+__device__ inline V3<float> llg_flow(V3<float> s, V3<float> w, float alpha, float tau,
+                                     float inv1pa2)
+{
+    const float wn2 = w.x * w.x + w.y * w.y + w.z * w.z;
+    if (!(wn2 > 0.0f)) return s;
+    const float iw = __builtin_amdgcn_rsqf(wn2);
+    const float wn = wn2 * iw;
+    const V3<float> e{w.x * iw, w.y * iw, w.z * iw};
+    const float u = s.x * e.x + s.y * e.y + s.z * e.z;
+    const V3<float> p{s.x - u * e.x, s.y - u * e.y, s.z - u * e.z};
+    const float phi = wn * tau * inv1pa2;
+    const float E = __expf(-alpha * phi);
+    const float E2 = E * E;
+    const float D = (1.0f + u) + (1.0f - u) * E2;
+    const float iD = __builtin_amdgcn_rcpf(D);
+    const float ct = ((1.0f + u) - (1.0f - u) * E2) * iD;
+    const float f = 2.0f * E * iD;
+    float sn, cs;
+    __sincosf(phi, &sn, &cs);
+    const V3<float> ex{e.y * p.z - e.z * p.y, e.z * p.x - e.x * p.z, e.x * p.y - e.y * p.x};
+    const double ox = (double)(ct * e.x + f * (cs * p.x + sn * ex.x));
+    const double oy = (double)(ct * e.y + f * (cs * p.y + sn * ex.y));
+    const double oz = (double)(ct * e.z + f * (cs * p.z + sn * ex.z));
+    const double eps = (ox * ox + oy * oy + oz * oz) - 1.0;
+    const double inv = fabs(eps) < 1.0e-5 ? 1.0 + eps * (-0.5 + 0.375 * eps)
+                                          : 1.0 / sqrt(1.0 + eps);
+    return {(float)(ox * inv), (float)(oy * inv), (float)(oz * inv)};
 }
 
 // ------------------------------------------------------------- lattice

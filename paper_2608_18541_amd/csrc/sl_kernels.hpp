@@ -56,6 +56,8 @@ template <typename T> struct alignas(4 * sizeof(T)) Pos4 {
 template <typename T> struct RunDev {
     Geom g;
     int32_t lattice, n, n_species, n_shells, live, ttm_mode, obs_every, obs_cap;
+    int32_t noisy;       // some species has a thermal field (sig > 0)
+    int32_t pad0;
     uint32_t seed, run_id;
     T a, box[3], half_box[3];
     T alpha, dt, tau_half, inv1pa2, gam;
@@ -93,12 +95,90 @@ template <typename T> struct RunDev {
     RunState* st;
 };
 
+// ------------------------------------------------------- memory access
+// Element i of a global array through its base pointer and a 32-bit byte
+// offset: with a wave-uniform base the load or store is issued with the base
+// in scalar registers and one 32-bit vector offset per lane.  Every array
+// read this way is below 4 GiB (the host limits the atom count).
+#define SL_GLOBAL __attribute__((address_space(1)))
+#define SL_LDS __attribute__((address_space(3)))
+
+template <typename X> __device__ __forceinline__ X gld(const X* base, uint32_t i)
+{
+    return *(const SL_GLOBAL X*)((const SL_GLOBAL char*)base + i * (uint32_t)sizeof(X));
+}
+template <typename X> __device__ __forceinline__ void gst(X* base, uint32_t i, X v)
+{
+    *(SL_GLOBAL X*)((SL_GLOBAL char*)base + i * (uint32_t)sizeof(X)) = v;
+}
+
+// positions move as one 16- or 32-byte vector
+template <typename T> struct Vec4 {
+    typedef T type __attribute__((ext_vector_type(4)));
+};
+template <typename T> __device__ __forceinline__ Pos4<T> gld(const Pos4<T>* base, uint32_t i)
+{
+    typedef typename Vec4<T>::type V4;
+    const V4 v = *(const SL_GLOBAL V4*)((const SL_GLOBAL char*)base + i * (uint32_t)sizeof(Pos4<T>));
+    return Pos4<T>{v.x, v.y, v.z, v.w};
+}
+template <typename T> __device__ __forceinline__ void gst(Pos4<T>* base, uint32_t i, Pos4<T> p)
+{
+    typedef typename Vec4<T>::type V4;
+    V4 v = {p.x, p.y, p.z, p.w};
+    *(SL_GLOBAL V4*)((SL_GLOBAL char*)base + i * (uint32_t)sizeof(Pos4<T>)) = v;
+}
+template <typename T> __device__ __forceinline__ Pos4<T> sld(const Pos4<T>* base, uint32_t i)
+{
+    typedef typename Vec4<T>::type V4;
+    const V4 v = ((const SL_LDS V4*)base)[i];
+    return Pos4<T>{v.x, v.y, v.z, v.w};
+}
+template <typename T> __device__ __forceinline__ void sst(Pos4<T>* base, uint32_t i, Pos4<T> p)
+{
+    typedef typename Vec4<T>::type V4;
+    V4 v = {p.x, p.y, p.z, p.w};
+    ((SL_LDS V4*)base)[i] = v;
+}
+template <typename X> __device__ __forceinline__ X sld(const X* base, uint32_t i)
+{
+    return ((const SL_LDS X*)base)[i];
+}
+template <typename X> __device__ __forceinline__ void sst(X* base, uint32_t i, X v)
+{
+    ((SL_LDS X*)base)[i] = v;
+}
+
+struct InGlobal {
+    template <typename X> static __device__ __forceinline__ X ld(const X* b, uint32_t i)
+    {
+        return gld(b, i);
+    }
+    template <typename X> static __device__ __forceinline__ void st(X* b, uint32_t i, X v)
+    {
+        gst(b, i, v);
+    }
+};
+struct InLds {
+    template <typename X> static __device__ __forceinline__ X ld(const X* b, uint32_t i)
+    {
+        return sld(b, i);
+    }
+    template <typename X> static __device__ __forceinline__ void st(X* b, uint32_t i, X v)
+    {
+        sst(b, i, v);
+    }
+};
+
 // ----------------------------------------------------------- views
 // Where the hot arrays of a run live while a kernel works on it: the run's
 // global arrays (the multi-kernel step) or copies in LDS (the persistent
-// per-run kernel).  Every per-site, per-atom and per-cell computation below
-// takes a view, so both executors run literally the same arithmetic.
-template <typename T> struct View {
+// per-run kernel; positions there too when they fit).  Every per-site,
+// per-atom and per-cell computation below takes a view, so both executors
+// run literally the same arithmetic.
+template <typename T, typename M, typename P> struct View {
+    using Mem = M;      // spins, species, cell ids, T_e, observable rows
+    using PosMem = P;   // wrapped positions
     T *sx, *sy, *sz;
     const int8_t* species;
     uint16_t* cell;
@@ -107,56 +187,134 @@ template <typename T> struct View {
     double* partial;
 };
 
-template <typename T> __device__ inline View<T> global_view(const RunDev<T>& R)
+template <typename T> using GView = View<T, InGlobal, InGlobal>;
+
+template <typename T> __device__ inline GView<T> global_view(const RunDev<T>& R)
 {
-    return View<T>{R.sx, R.sy, R.sz, R.species, R.cell, R.pos, R.Te, R.partial};
+    return GView<T>{R.sx, R.sy, R.sz, R.species, R.cell, R.pos, R.Te, R.partial};
 }
 
-template <typename T>
-__device__ inline int species_of(const RunDev<T>& R, const View<T>& V, int idx)
+template <typename T, typename VW>
+__device__ __forceinline__ int species_of(const RunDev<T>& R, const VW& V, uint32_t idx)
 {
-    return R.n_species > 1 ? (int)V.species[idx] : 0;
+    return R.n_species > 1 ? (int)VW::Mem::ld(V.species, idx) : 0;
 }
 
-// Exchange sum h = sum_j J_ij s_j (eV) over the neighbour shells of site
-// (x, y, z, b), read from the colour-major spin arrays.  All neighbour
-// indices are formed first and all their loads issued together; the
-// coupling J[shell][sp][sj] is selected in registers from the run's table.
-template <typename T> __device__ inline T select4(int k, T a, T b, T c, T d)
+// One of four per-species values by the bits of k (0..3): two levels of
+// register selects, no branches.
+template <typename T> __device__ __forceinline__ T select4(int k, T a, T b, T c, T d)
 {
-    return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+    const T ab = (k & 1) ? b : a;
+    const T cd = (k & 1) ? d : c;
+    return (k & 2) ? cd : ab;
 }
 
-template <typename T, int NN>
-__device__ __forceinline__ V3<T> exchange_gather(const RunDev<T>& R, const View<T>& V,
-                                                 const int (&j)[NN], const int (&sh)[NN], int nn,
-                                                 int sp)
+// Offsets, inside one colour block, of the sites around cell (x, y, z):
+// the half-x index of x-1, x, x+1 and the row (y) and plane (z) offsets of
+// the three neighbouring rows and planes, periodic.  A neighbour at
+// (x', y', z') of colour k' sits at k' H + xh(x') + row(y') + plane(z').
+struct Around {
+    uint32_t xm, x0, xp, ym, y0, yp, zm, z0, zp;
+};
+
+__device__ __forceinline__ Around around(const Geom& g, uint32_t x, uint32_t xh, uint32_t y,
+                                         uint32_t z)
 {
+    const uint32_t Lxh = (uint32_t)g.Lxh, Ly = (uint32_t)g.Ly, Lz = (uint32_t)g.Lz;
+    const uint32_t row = Lxh, plane = Lxh * Ly;
+    Around a;
+    a.x0 = xh;
+    // x = 2 xh + parity: x - 1 leaves the pair when x is even, x + 1 when odd
+    a.xm = (x & 1u) ? xh : (xh == 0 ? Lxh - 1 : xh - 1);
+    a.xp = (x & 1u) ? (xh == Lxh - 1 ? 0 : xh + 1) : xh;
+    a.y0 = __umul24(y, row);
+    a.ym = y == 0 ? __umul24(Ly - 1, row) : a.y0 - row;
+    a.yp = y == Ly - 1 ? 0 : a.y0 + row;
+    a.z0 = __umul24(z, plane);
+    a.zm = z == 0 ? __umul24(Lz - 1, plane) : a.z0 - plane;
+    a.zp = z == Lz - 1 ? 0 : a.z0 + plane;
+    return a;
+}
+
+// Exchange sum h = sum_j J_ij s_j (eV) over the neighbour shells of the
+// site of colour k at (x, y, z).  Neighbour colours follow from k alone
+// (uniform over a colour pass), so each neighbour is one offset into the
+// spin arrays of its colour.  All loads are issued before the arithmetic;
+// the coupling J[shell][sp][sj] is selected in registers.
+//   simple cubic: the 6 sites at +-a along an axis;
+//   bcc: first shell the 8 sites of the other basis at (+-a/2)^3 in the
+//   order (x0|x1, y0|y1, z0|z1) with x fastest, then the 6 second-shell
+//   sites of the same basis at -x, +x, -y, +y, -z, +z.
+template <typename T, typename VW, int LAT, bool MULTI>
+__device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V, int k, const Around& a,
+                                                int sp)
+{
+    using M = typename VW::Mem;
+    constexpr int NN = LAT == SL_LATTICE_SC ? 6 : 14;
+    const uint32_t H = (uint32_t)R.g.H;
+    uint32_t col[NN], off[NN];
+    int sh[NN];
+    int nn;
+    const int p = k & 1;
+    if (LAT == SL_LATTICE_SC) {
+        nn = 6;
+        const uint32_t o[6] = {a.xm + a.y0 + a.z0, a.xp + a.y0 + a.z0, a.x0 + a.ym + a.z0,
+                               a.x0 + a.yp + a.z0, a.x0 + a.y0 + a.zm, a.x0 + a.y0 + a.zp};
+#pragma unroll
+        for (int q = 0; q < NN; ++q) {
+            col[q] = (uint32_t)(1 - p);
+            off[q] = o[q];
+            sh[q] = 0;
+        }
+    } else {
+        nn = R.n_shells > 1 ? 14 : 8;
+        const int b = k >> 1;
+        const uint32_t X[2] = {b == 0 ? a.xm : a.x0, b == 0 ? a.x0 : a.xp};
+        const uint32_t Y[2] = {b == 0 ? a.ym : a.y0, b == 0 ? a.y0 : a.yp};
+        const uint32_t Z[2] = {b == 0 ? a.zm : a.z0, b == 0 ? a.z0 : a.zp};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int mx = q & 1, my = (q >> 1) & 1, mz = q >> 2;
+            // cell shift sum is mx+my+mz (b = 1) or that minus 3 (b = 0)
+            col[q] = (uint32_t)(2 * (1 - b) + ((p + mx + my + mz + (1 - b)) & 1));
+            off[q] = X[mx] + Y[my] + Z[mz];
+            sh[q] = 0;
+        }
+        const uint32_t o2[6] = {a.xm + a.y0 + a.z0, a.xp + a.y0 + a.z0, a.x0 + a.ym + a.z0,
+                                a.x0 + a.yp + a.z0, a.x0 + a.y0 + a.zm, a.x0 + a.y0 + a.zp};
+#pragma unroll
+        for (int q = 8; q < NN; ++q) {
+            col[q] = (uint32_t)(2 * b + (1 - p));
+            off[q] = o2[(q - 8) % 6];
+            sh[q] = 1;
+        }
+    }
     T ax[NN], ay[NN], az[NN];
     int sj[NN];
-    const bool multi = R.n_species > 1;
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
         if (q < nn) {
-            ax[q] = V.sx[j[q]];
-            ay[q] = V.sy[j[q]];
-            az[q] = V.sz[j[q]];
-            sj[q] = multi ? (int)V.species[j[q]] : 0;
+            const uint32_t cb = col[q] * H;
+            ax[q] = M::ld(V.sx + cb, off[q]);
+            ay[q] = M::ld(V.sy + cb, off[q]);
+            az[q] = M::ld(V.sz + cb, off[q]);
+            sj[q] = MULTI ? (int)M::ld(V.species + cb, off[q]) : 0;
         }
     }
-    // couplings of this site's species to each species, per shell
     T row[2][4];
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-            row[s2][t] = select4(sp, R.J[s2][0][t], R.J[s2][1][t], R.J[s2][2][t], R.J[s2][3][t]);
+            row[s2][t] = MULTI ? select4(sp, R.J[s2][0][t], R.J[s2][1][t], R.J[s2][2][t], R.J[s2][3][t])
+                               : R.J[s2][0][0];
     V3<T> h{T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
         if (q < nn) {
-            const T Jv = sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
-                                    : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
+            const T Jv = !MULTI ? row[sh[q]][0]
+                         : sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
+                                      : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
             h.x += Jv * ax[q];
             h.y += Jv * ay[q];
             h.z += Jv * az[q];
@@ -165,36 +323,35 @@ __device__ __forceinline__ V3<T> exchange_gather(const RunDev<T>& R, const View<
     return h;
 }
 
-template <typename T>
-__device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, const View<T>& V, int x, int y,
-                                              int z, int b, int sp)
+// Dispatch on the run's lattice and species count (uniform per run).
+template <typename T, typename VW>
+__device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, const VW& V, int k, const Around& a,
+                                              int sp)
 {
-    const Geom& g = R.g;
-    const int xm = x == 0 ? g.Lx - 1 : x - 1, xp = x == g.Lx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? g.Ly - 1 : y - 1, yp = y == g.Ly - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? g.Lz - 1 : z - 1, zp = z == g.Lz - 1 ? 0 : z + 1;
-    if (R.lattice == SL_LATTICE_SC) {
-        const int j[6] = {encode_site(g, xm, y, z, 0), encode_site(g, xp, y, z, 0),
-                          encode_site(g, x, ym, z, 0), encode_site(g, x, yp, z, 0),
-                          encode_site(g, x, y, zm, 0), encode_site(g, x, y, zp, 0)};
-        const int sh[6] = {0, 0, 0, 0, 0, 0};
-        return exchange_gather<T, 6>(R, V, j, sh, 6, sp);
-    }
-    // first shell: the 8 sites of the other basis at (+-a/2, +-a/2, +-a/2);
-    // second shell: the 6 sites of the same basis at +-a along an axis
-    const int ob = 1 - b;
-    const int x0 = b == 0 ? xm : x, x1 = b == 0 ? x : xp;
-    const int y0 = b == 0 ? ym : y, y1 = b == 0 ? y : yp;
-    const int z0 = b == 0 ? zm : z, z1 = b == 0 ? z : zp;
-    const int j[14] = {encode_site(g, x0, y0, z0, ob), encode_site(g, x1, y0, z0, ob),
-                       encode_site(g, x0, y1, z0, ob), encode_site(g, x1, y1, z0, ob),
-                       encode_site(g, x0, y0, z1, ob), encode_site(g, x1, y0, z1, ob),
-                       encode_site(g, x0, y1, z1, ob), encode_site(g, x1, y1, z1, ob),
-                       encode_site(g, xm, y, z, b),    encode_site(g, xp, y, z, b),
-                       encode_site(g, x, ym, z, b),    encode_site(g, x, yp, z, b),
-                       encode_site(g, x, y, zm, b),    encode_site(g, x, y, zp, b)};
-    const int sh[14] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
-    return exchange_gather<T, 14>(R, V, j, sh, R.n_shells > 1 ? 14 : 8, sp);
+    if (R.lattice == SL_LATTICE_SC)
+        return R.n_species > 1 ? exchange_sum_t<T, VW, SL_LATTICE_SC, true>(R, V, k, a, sp)
+                               : exchange_sum_t<T, VW, SL_LATTICE_SC, false>(R, V, k, a, sp);
+    return R.n_species > 1 ? exchange_sum_t<T, VW, SL_LATTICE_BCC, true>(R, V, k, a, sp)
+                           : exchange_sum_t<T, VW, SL_LATTICE_BCC, false>(R, V, k, a, sp);
+}
+
+// sqrt of a cell temperature in the storage precision
+__device__ __forceinline__ double sqrt_te(double Te, double) { return sqrt(Te); }
+__device__ __forceinline__ float sqrt_te(double Te, float) { return __builtin_amdgcn_sqrtf((float)Te); }
+
+// Cell coordinates of offset l inside a colour block.
+struct Cell3 {
+    uint32_t x, xh, y, z;
+};
+__device__ __forceinline__ Cell3 cell_of(const Geom& g, int k, uint32_t l)
+{
+    Cell3 c;
+    const uint32_t r = fdiv(l, g.divLxh);
+    c.xh = l - __umul24(r, (uint32_t)g.Lxh);
+    c.z = fdiv(r, g.divLy);
+    c.y = r - __umul24(c.z, (uint32_t)g.Ly);
+    c.x = 2 * c.xh + (((uint32_t)k + c.y + c.z) & 1u);
+    return c;
 }
 
 template <typename T> __device__ inline V3<T> ideal_site(const RunDev<T>& R, const Site& s)
@@ -209,10 +366,11 @@ template <typename T> __device__ inline T min_image(T d, T box, T half)
 }
 
 // Separation x_j - x_i (minimum image) from the wrapped positions.
-template <typename T>
-__device__ inline V3<T> separation(const RunDev<T>& R, const View<T>& V, const Pos4<T>& pi, int j)
+template <typename T, typename VW>
+__device__ __forceinline__ V3<T> separation(const RunDev<T>& R, const VW& V, const Pos4<T>& pi,
+                                            uint32_t j)
 {
-    const Pos4<T> pj = V.pos[j];
+    const Pos4<T> pj = VW::PosMem::ld(V.pos, j);
     V3<T> d{pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
     d.x = min_image(d.x, R.box[0], R.half_box[0]);
     d.y = min_image(d.y, R.box[1], R.half_box[1]);
@@ -225,7 +383,7 @@ __device__ inline V3<T> separation(const RunDev<T>& R, const View<T>& V, const P
 // correctly rounded.
 __device__ inline float morse_f(float r2, float a, float D, float r0, float* r_out)
 {
-    const float ir = rsqrtf(r2);
+    const float ir = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ir;
     *r_out = r;
     const float e1 = __expf(-a * (r - r0));
@@ -245,11 +403,11 @@ template <typename T> __device__ inline T wrap_box(T x, T L)
 }
 
 // Wrapped position of atom idx from its ideal site and displacement.
-template <typename T> __device__ inline V3<T> position(const RunDev<T>& R, const Site& s, int idx)
+template <typename T> __device__ inline V3<T> position(const RunDev<T>& R, const Site& s, uint32_t idx)
 {
     V3<T> r = ideal_site(R, s);
-    return {wrap_box(r.x + R.ux[idx], R.box[0]), wrap_box(r.y + R.uy[idx], R.box[1]),
-            wrap_box(r.z + R.uz[idx], R.box[2])};
+    return {wrap_box(r.x + gld(R.ux, idx), R.box[0]), wrap_box(r.y + gld(R.uy, idx), R.box[1]),
+            wrap_box(r.z + gld(R.uz, idx), R.box[2])};
 }
 
 template <typename T> __device__ inline int electron_cell(const RunDev<T>& R, const V3<T>& p)
@@ -284,38 +442,57 @@ template <typename T> __device__ inline bool run_active(const RunDev<T>& R, int6
 
 // ------------------------------------------------------------ spins
 // Update of site l of a colour: field from the current neighbours, thermal
-// field from the step's Philox block, exact flow over tau.
-template <typename T>
-__device__ __forceinline__ void spin_site(const RunDev<T>& R, const View<T>& V, int colour, T tau,
-                                          int l, int64_t step)
+// field from the step's Philox block (drawn whenever the run has a thermal
+// field; its amplitude is zero in cells at T_e = 0), exact flow over tau.
+template <typename T, typename VW, int LAT, bool MULTI>
+__device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int colour, T tau,
+                                            uint32_t l, int64_t step)
 {
-    const int idx = colour * R.g.H + l;
-    const uint32_t r = fdiv((uint32_t)l, R.g.divLxh);
-    const int xh = l - (int)r * R.g.Lxh;
-    const int z = (int)fdiv(r, R.g.divLy);
-    const int y = (int)r - z * R.g.Ly;
-    const int x = 2 * xh + ((colour + y + z) & 1);
-    const int b = R.g.nb == 2 ? (colour >> 1) : 0;
-    const int sp = species_of(R, V, idx);
-    const V3<T> h = exchange_sum(R, V, x, y, z, b, sp);
-    T Hx = h.x * R.inv_mumb[sp] + R.B[0];
-    T Hy = h.y * R.inv_mumb[sp] + R.B[1];
-    T Hz = h.z * R.inv_mumb[sp] + R.B[2];
-    const double Te = V.Te[V.cell[idx]];
-    if (Te > 0.0 && R.sig[sp] > T(0)) {
-        const int canon = ((z * R.g.Ly + y) * R.g.Lx + x) * R.g.nb + b;
-        const Normals3<T> nu = normals3<T>(R.seed, R.run_id, (uint32_t)canon, step, 0u);
-        const T amp = R.sig[sp] * (T)sqrt(Te);
+    using M = typename VW::Mem;
+    const Cell3 c = cell_of(R.g, colour, l);
+    const Around a = around(R.g, c.x, c.xh, c.y, c.z);
+    const uint32_t kH = (uint32_t)colour * (uint32_t)R.g.H;
+    const uint32_t idx = kH + l;
+    const int sp = MULTI ? (int)M::ld(V.species, idx) : 0;
+    const V3<T> h = exchange_sum_t<T, VW, LAT, MULTI>(R, V, colour, a, sp);
+    const T imu = MULTI ? select4(sp, R.inv_mumb[0], R.inv_mumb[1], R.inv_mumb[2], R.inv_mumb[3])
+                        : R.inv_mumb[0];
+    T Hx = h.x * imu + R.B[0];
+    T Hy = h.y * imu + R.B[1];
+    T Hz = h.z * imu + R.B[2];
+    if (R.noisy) {
+        const double Te = M::ld(V.Te, (uint32_t)M::ld(V.cell, idx));
+        const int b = LAT == SL_LATTICE_BCC ? (colour >> 1) : 0;
+        const uint32_t canon =
+            __umul24(__umul24(c.z, (uint32_t)R.g.Ly) + c.y, (uint32_t)R.g.Lx) * (uint32_t)R.g.nb +
+            c.x * (uint32_t)R.g.nb + (uint32_t)b;
+        const Normals3<T> nu = normals3<T>(R.seed, R.run_id, canon, step, 0u);
+        const T sg = MULTI ? select4(sp, R.sig[0], R.sig[1], R.sig[2], R.sig[3]) : R.sig[0];
+        const T amp = Te > 0.0 ? sg * sqrt_te(Te, T(0)) : T(0);
         Hx += amp * nu.a;
         Hy += amp * nu.b;
         Hz += amp * nu.c;
     }
-    V3<T> s{V.sx[idx], V.sy[idx], V.sz[idx]};
+    V3<T> s{M::ld(V.sx + kH, l), M::ld(V.sy + kH, l), M::ld(V.sz + kH, l)};
     const V3<T> wv{R.gam * Hx, R.gam * Hy, R.gam * Hz};
     s = llg_flow(s, wv, R.alpha, tau, R.inv1pa2);
-    V.sx[idx] = s.x;
-    V.sy[idx] = s.y;
-    V.sz[idx] = s.z;
+    M::st(V.sx + kH, l, s.x);
+    M::st(V.sy + kH, l, s.y);
+    M::st(V.sz + kH, l, s.z);
+}
+
+// Dispatch on the run's lattice and species count (uniform per run).
+template <typename T, typename VW>
+__device__ __forceinline__ void spin_site(const RunDev<T>& R, const VW& V, int colour, T tau,
+                                          uint32_t l, int64_t step)
+{
+    if (R.lattice == SL_LATTICE_SC) {
+        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true>(R, V, colour, tau, l, step);
+        else spin_site_t<T, VW, SL_LATTICE_SC, false>(R, V, colour, tau, l, step);
+    } else {
+        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true>(R, V, colour, tau, l, step);
+        else spin_site_t<T, VW, SL_LATTICE_BCC, false>(R, V, colour, tau, l, step);
+    }
 }
 
 template <typename T> __device__ inline void pass_colour(const RunDev<T>& R, int pass, int* colour, T* tau)
@@ -329,41 +506,42 @@ template <typename T> __device__ inline void pass_colour(const RunDev<T>& R, int
 // Half kick and drift of atom i (step phase), then its electron cell and
 // wrapped position; returns whether it moved more than half the skin since
 // its list was built.
-template <typename T>
-__device__ __forceinline__ bool kick_drift_atom(const RunDev<T>& R, const View<T>& V, int i, int phase)
+template <typename T, typename VW>
+__device__ __forceinline__ bool kick_drift_atom(const RunDev<T>& R, const VW& V, uint32_t i, int phase)
 {
-    const Site s = decode_site(R.g, (uint32_t)i);
+    const Site s = decode_site(R.g, i);
     bool far = false;
     if (phase == PHASE_STEP) {
         const int sp = species_of(R, V, i);
-        const T k = R.hdtm[sp];
-        T vx = R.vx[i] + k * R.fx[i];
-        T vy = R.vy[i] + k * R.fy[i];
-        T vz = R.vz[i] + k * R.fz[i];
-        T ux = R.ux[i] + R.dt * vx;
-        T uy = R.uy[i] + R.dt * vy;
-        T uz = R.uz[i] + R.dt * vz;
-        R.vx[i] = vx; R.vy[i] = vy; R.vz[i] = vz;
-        R.ux[i] = ux; R.uy[i] = uy; R.uz[i] = uz;
-        const T dx = ux - R.rx[i], dy = uy - R.ry[i], dz = uz - R.rz[i];
+        const T k = select4(sp, R.hdtm[0], R.hdtm[1], R.hdtm[2], R.hdtm[3]);
+        T vx = gld(R.vx, i) + k * gld(R.fx, i);
+        T vy = gld(R.vy, i) + k * gld(R.fy, i);
+        T vz = gld(R.vz, i) + k * gld(R.fz, i);
+        T ux = gld(R.ux, i) + R.dt * vx;
+        T uy = gld(R.uy, i) + R.dt * vy;
+        T uz = gld(R.uz, i) + R.dt * vz;
+        gst(R.vx, i, vx); gst(R.vy, i, vy); gst(R.vz, i, vz);
+        gst(R.ux, i, ux); gst(R.uy, i, uy); gst(R.uz, i, uz);
+        const T dx = ux - gld(R.rx, i), dy = uy - gld(R.ry, i), dz = uz - gld(R.rz, i);
         far = dx * dx + dy * dy + dz * dz > R.skin_half2;
     }
     const V3<T> p = position(R, s, i);
-    V.cell[i] = (uint16_t)electron_cell(R, p);
-    if (R.live) V.pos[i] = Pos4<T>{p.x, p.y, p.z, T(0)};
+    VW::Mem::st(V.cell, i, (uint16_t)electron_cell(R, p));
+    if (R.live) VW::PosMem::st(V.pos, i, Pos4<T>{p.x, p.y, p.z, T(0)});
     return far;
 }
 
-template <typename T> __device__ inline void nbr_bin_atom(const RunDev<T>& R, const View<T>& V, int i)
+template <typename T, typename VW>
+__device__ inline void nbr_bin_atom(const RunDev<T>& R, const VW& V, uint32_t i)
 {
-    const Pos4<T> pi = V.pos[i];
+    const Pos4<T> pi = VW::PosMem::ld(V.pos, i);
     int b3[3];
     const int bin = bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     const int slot = atomicAdd(&R.bin_n[bin], 1);
     if (slot < R.bin_cap) {
-        R.bin_atoms[(size_t)bin * R.bin_cap + slot] = i;
+        R.bin_atoms[(size_t)bin * R.bin_cap + slot] = (int32_t)i;
     } else {
-        if (atomicCAS(&R.st->bad_atom, 0, i + 1) == 0) {
+        if (atomicCAS(&R.st->bad_atom, 0, (int)i + 1) == 0) {
             R.st->bad_count = slot + 1;
             R.st->bad_step = R.st->step;
         }
@@ -390,11 +568,13 @@ template <typename T> __device__ inline void nbr_sort_bin(const RunDev<T>& R, in
 }
 
 // Verlet list of atom i: every atom within rc + skin in its own and the 26
-// surrounding bins, in bin order and ascending index within a bin.
-template <typename T> __device__ inline void nbr_build_atom(const RunDev<T>& R, const View<T>& V, int i)
+// surrounding bins, in bin order and ascending index within a bin.  The
+// list is stored column-major, entry q of atom i at nbr[q n + i].
+template <typename T, typename VW>
+__device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t i)
 {
-    const V3<T> ui{R.ux[i], R.uy[i], R.uz[i]};
-    const Pos4<T> pi = V.pos[i];
+    const V3<T> ui{gld(R.ux, i), gld(R.uy, i), gld(R.uz, i)};
+    const Pos4<T> pi = VW::PosMem::ld(V.pos, i);
     int b3[3];
     bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     int count = 0;
@@ -411,8 +591,8 @@ template <typename T> __device__ inline void nbr_build_atom(const RunDev<T>& R, 
                 const int32_t* a = R.bin_atoms + (size_t)bin * R.bin_cap;
                 for (int q = 0; q < cnt; ++q) {
                     const int j = a[q];
-                    if (j == i) continue;
-                    const V3<T> d = separation(R, V, pi, j);
+                    if (j == (int)i) continue;
+                    const V3<T> d = separation(R, V, pi, (uint32_t)j);
                     if (d.x * d.x + d.y * d.y + d.z * d.z < R.rlist2) {
                         if (count < R.max_nbr) R.nbr[(size_t)count * n + i] = j;
                         ++count;
@@ -422,44 +602,46 @@ template <typename T> __device__ inline void nbr_build_atom(const RunDev<T>& R, 
         }
     }
     if (count > R.max_nbr) {
-        if (atomicCAS(&R.st->bad_atom, 0, i + 1) == 0) {
+        if (atomicCAS(&R.st->bad_atom, 0, (int)i + 1) == 0) {
             R.st->bad_count = count;
             R.st->bad_step = R.st->step;
         }
         atomicOr(&R.st->err, ERR_NBR);
         count = R.max_nbr;
     }
-    R.nbr_n[i] = count;
-    R.rx[i] = ui.x;
-    R.ry[i] = ui.y;
-    R.rz[i] = ui.z;
+    gst(R.nbr_n, i, (int32_t)count);
+    gst(R.rx, i, ui.x);
+    gst(R.ry, i, ui.y);
+    gst(R.rz, i, ui.z);
 }
 
 // Forces on atom i at the new positions, the second half kick, the
 // electron-phonon Ornstein-Uhlenbeck step (its mean energy added to `acc`
 // of the atom's cell, fixed point) and, on sample steps, the atom's
 // observable terms q[NQ].
-template <typename T>
-__device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const View<T>& V, int i,
+template <typename T, typename VW>
+__device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V, uint32_t i,
                                                 int phase, int64_t step, bool obs,
                                                 unsigned long long* acc, double* q)
 {
-    const Site si = decode_site(R.g, (uint32_t)i);
+    using M = typename VW::Mem;
+    const Site si = decode_site(R.g, i);
     const int sp = species_of(R, V, i);
     if (R.live) {
-        const Pos4<T> pi = V.pos[i];
+        const Pos4<T> pi = VW::PosMem::ld(V.pos, i);
         T Fx = T(0), Fy = T(0), Fz = T(0);
         double pe = 0.0;
-        const int nn = R.nbr_n[i];
+        const int nn = gld(R.nbr_n, i);
         const size_t n = (size_t)R.n;
         // neighbours in chunks of 8: all index loads, then all position
-        // loads, then the arithmetic (two memory round trips per chunk)
+        // loads, then the arithmetic (two memory round trips per chunk);
+        // column q of the list starts at nbr + q n (uniform per wave)
         for (int k0 = 0; k0 < nn; k0 += 8) {
-            int jj[8];
-            T dx[8], dy[8], dz[8];
+            uint32_t jj[8];
 #pragma unroll
             for (int q8 = 0; q8 < 8; ++q8)
-                jj[q8] = k0 + q8 < nn ? R.nbr[(size_t)(k0 + q8) * n + i] : i;
+                jj[q8] = k0 + q8 < nn ? (uint32_t)gld(R.nbr + (size_t)(k0 + q8) * n, i) : i;
+            T dx[8], dy[8], dz[8];
 #pragma unroll
             for (int q8 = 0; q8 < 8; ++q8) {
                 const V3<T> d = separation(R, V, pi, jj[q8]);
@@ -484,23 +666,26 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const View<T
                 }
             }
         }
-        T vx = R.vx[i], vy = R.vy[i], vz = R.vz[i];
+        T vx = gld(R.vx, i), vy = gld(R.vy, i), vz = gld(R.vz, i);
+        const T me = select4(sp, R.m_e[0], R.m_e[1], R.m_e[2], R.m_e[3]);
         if (phase == PHASE_STEP) {
-            const T k = R.hdtm[sp];
+            const T k = select4(sp, R.hdtm[0], R.hdtm[1], R.hdtm[2], R.hdtm[3]);
             vx += k * Fx;
             vy += k * Fy;
             vz += k * Fz;
             if (R.ttm_mode == 1) {
-                const int c = V.cell[i];
-                const double Te = V.Te[c];
-                const int canon = ((si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
-                const Normals3<T> eta = normals3<T>(R.seed, R.run_id, (uint32_t)canon, step, 1u);
-                const T amp = R.ou_amp[sp] * (T)sqrt(Te);
+                const uint32_t c = M::ld(V.cell, i);
+                const double Te = M::ld(V.Te, c);
+                const uint32_t canon =
+                    (((uint32_t)si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
+                const Normals3<T> eta = normals3<T>(R.seed, R.run_id, canon, step, 1u);
+                const T oa = select4(sp, R.ou_amp[0], R.ou_amp[1], R.ou_amp[2], R.ou_amp[3]);
+                const T amp = oa * sqrt_te(Te, T(0));
                 const T nx = R.ou_c1 * vx + amp * eta.a;
                 const T ny = R.ou_c1 * vy + amp * eta.b;
                 const T nz = R.ou_c1 * vz + amp * eta.c;
                 // mean energy the step hands to this atom given its velocity
-                const double ke = 0.5 * (double)R.m_e[sp] *
+                const double ke = 0.5 * (double)me *
                                   ((double)vx * vx + (double)vy * vy + (double)vz * vz);
                 const double dE = R.ou_1mc2 * (1.5 * kKB * Te - ke);
                 if (fabs(dE) < 1.0e3) {
@@ -513,39 +698,43 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const View<T
                 vy = ny;
                 vz = nz;
             }
-            R.vx[i] = vx;
-            R.vy[i] = vy;
-            R.vz[i] = vz;
+            gst(R.vx, i, vx);
+            gst(R.vy, i, vy);
+            gst(R.vz, i, vz);
         }
-        R.fx[i] = Fx;
-        R.fy[i] = Fy;
-        R.fz[i] = Fz;
+        gst(R.fx, i, Fx);
+        gst(R.fy, i, Fy);
+        gst(R.fz, i, Fz);
         if (obs) {
-            q[14] = 0.5 * (double)R.m_e[sp] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+            q[14] = 0.5 * (double)me * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
             q[15] = pe;
         }
     }
     if (obs) {
-        const double s0 = V.sx[i], s1 = V.sy[i], s2 = V.sz[i];
-        const V3<T> h = exchange_sum(R, V, si.x, si.y, si.z, si.b, sp);
+        const double s0 = M::ld(V.sx, i), s1 = M::ld(V.sy, i), s2 = M::ld(V.sz, i);
+        const uint32_t l = i - (uint32_t)si.k * (uint32_t)R.g.H;
+        const Around a = around(R.g, (uint32_t)si.x, l - __umul24(fdiv(l, R.g.divLxh), (uint32_t)R.g.Lxh),
+                                (uint32_t)si.y, (uint32_t)si.z);
+        const V3<T> h = exchange_sum(R, V, si.k, a, sp);
         const double h0 = h.x, h1 = h.y, h2 = h.z;
+        const double mb = select4(sp, R.mumb[0], R.mumb[1], R.mumb[2], R.mumb[3]);
         q[12] = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
-        q[13] = -R.mumb[sp] * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
-        const double t0 = h0 + R.mumb[sp] * R.Bd[0];
-        const double t1 = h1 + R.mumb[sp] * R.Bd[1];
-        const double t2 = h2 + R.mumb[sp] * R.Bd[2];
+        q[13] = -mb * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
+        const double t0 = h0 + mb * R.Bd[0];
+        const double t1 = h1 + mb * R.Bd[1];
+        const double t2 = h2 + mb * R.Bd[2];
         const double c0 = s1 * t2 - s2 * t1, c1 = s2 * t0 - s0 * t2, c2 = s0 * t1 - s1 * t0;
         const double num = c0 * c0 + c1 * c1 + c2 * c2;
         const double den = s0 * t0 + s1 * t1 + s2 * t2;
         // per-species slots with compile-time indices (kept in registers)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const bool me = sp == t;
-            q[3 * t + 0] = me ? s0 : 0.0;
-            q[3 * t + 1] = me ? s1 : 0.0;
-            q[3 * t + 2] = me ? s2 : 0.0;
-            q[16 + t] = me ? num : 0.0;
-            q[20 + t] = me ? den : 0.0;
+            const bool me2 = sp == t;
+            q[3 * t + 0] = me2 ? s0 : 0.0;
+            q[3 * t + 1] = me2 ? s1 : 0.0;
+            q[3 * t + 2] = me2 ? s2 : 0.0;
+            q[16 + t] = me2 ? num : 0.0;
+            q[20 + t] = me2 ? den : 0.0;
         }
     }
 }
@@ -634,8 +823,8 @@ struct SampleScratch {
     double tot[NQ];
 };
 
-template <typename T>
-__device__ inline void write_sample(const RunDev<T>& R, const View<T>& V, SampleScratch& S,
+template <typename T, typename VW>
+__device__ inline void write_sample(const RunDev<T>& R, const VW& V, SampleScratch& S,
                                     int64_t step_of_sample)
 {
     const int tid = threadIdx.x;
@@ -713,11 +902,11 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     int colour;
     T tau;
     pass_colour(R, pass, &colour, &tau);
-    const View<T> V = global_view(R);
+    const GView<T> V = global_view(R);
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
-        const int l = w.y + k * (int)blockDim.x + (int)threadIdx.x;
-        if (l < R.g.H) spin_site(R, V, colour, tau, l, step);
+        const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
+        if (l < (uint32_t)R.g.H) spin_site(R, V, colour, tau, l, step);
     }
 }
 
@@ -897,42 +1086,32 @@ __host__ __device__ inline PersistLayout persist_layout(int n, int ncell, int n_
     return L;
 }
 
-template <typename T>
-__global__ __launch_bounds__(512) void k_persist(const RunDev<T>* __restrict__ runs,
-                                                  const int* __restrict__ run_list, int nsteps,
-                                                  uint32_t lds_max)
+struct PersistShared {
+    SampleScratch S;
+    int flag_rebuild;
+    int flag_stop;
+};
+
+// The run's steps inside one block: load the LDS copies, step, write back.
+template <typename T, typename VW>
+__device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, double* Te2,
+                                            unsigned long long* acc, PersistShared& P, int nsteps,
+                                            bool pos_in_lds)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ SampleScratch S;
-    __shared__ int flag_rebuild;
-    __shared__ int flag_stop;
-    const RunDev<T>& R = runs[run_list[blockIdx.x]];
     RunState* st = R.st;
     const int tid = threadIdx.x, B = blockDim.x;
     const int n = R.n, nc = R.ncell;
-    const PersistLayout L = persist_layout<T>(n, nc, R.n_part, R.live != 0, R.n_species, lds_max);
-    View<T> V;
-    V.sx = reinterpret_cast<T*>(smem + L.off_s);
-    V.sy = V.sx + n;
-    V.sz = V.sy + n;
-    V.species = R.n_species > 1 ? reinterpret_cast<const int8_t*>(smem + L.off_species) : R.species;
-    V.cell = reinterpret_cast<uint16_t*>(smem + L.off_cell);
-    V.pos = L.pos_in_lds ? reinterpret_cast<Pos4<T>*>(smem + L.off_pos) : R.pos;
-    V.Te = reinterpret_cast<double*>(smem + L.off_Te);
-    double* Te2 = reinterpret_cast<double*>(smem + L.off_Te2);
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.off_acc);
-    V.partial = reinterpret_cast<double*>(smem + L.off_part);
     // load the run into LDS
     for (int i = tid; i < n; i += B) {
-        V.sx[i] = R.sx[i];
-        V.sy[i] = R.sy[i];
-        V.sz[i] = R.sz[i];
-        V.cell[i] = R.cell[i];
-        if (R.n_species > 1) const_cast<int8_t*>(V.species)[i] = R.species[i];
-        if (L.pos_in_lds) V.pos[i] = R.pos[i];
+        V.sx[i] = gld(R.sx, i);
+        V.sy[i] = gld(R.sy, i);
+        V.sz[i] = gld(R.sz, i);
+        V.cell[i] = gld(R.cell, i);
+        if (R.n_species > 1) const_cast<int8_t*>(V.species)[i] = gld(R.species, i);
+        if (pos_in_lds) V.pos[i] = gld(R.pos, i);
     }
     for (int c = tid; c < nc; c += B) {
-        V.Te[c] = R.Te[c];
+        V.Te[c] = gld(R.Te, c);
         acc[c] = 0ull;
     }
     for (int k = tid; k < R.n_part * NQ; k += B) V.partial[k] = 0.0;
@@ -943,34 +1122,34 @@ __global__ __launch_bounds__(512) void k_persist(const RunDev<T>* __restrict__ r
     // counter keeps the step's number.
     auto error_raised = [&]() {
         __syncthreads();
-        if (tid == 0) flag_stop = st->err != 0 ? 1 : 0;
+        if (tid == 0) P.flag_stop = st->err != 0 ? 1 : 0;
         __syncthreads();
-        return flag_stop != 0;
+        return P.flag_stop != 0;
     };
     const bool run = !error_raised() && step < target;
     for (int it = 0; run && it < nsteps && step < target; ++it) {
-        if (tid == 0) flag_rebuild = 0;
+        if (tid == 0) P.flag_rebuild = 0;
         // spins: the colour sweep
         for (int pass = 0; pass < 2 * R.g.C - 1; ++pass) {
             __syncthreads();
             int colour;
             T tau;
             pass_colour(R, pass, &colour, &tau);
-            for (int l = tid; l < R.g.H; l += B) spin_site(R, V, colour, tau, l, step);
+            for (int l = tid; l < R.g.H; l += B) spin_site(R, V, colour, tau, (uint32_t)l, step);
         }
         __syncthreads();
         // lattice: kick and drift, list rebuild when flagged
         if (R.live) {
             for (int i = tid; i < n; i += B)
-                if (kick_drift_atom(R, V, i, PHASE_STEP)) atomicOr(&flag_rebuild, 1);
+                if (kick_drift_atom(R, V, (uint32_t)i, PHASE_STEP)) atomicOr(&P.flag_rebuild, 1);
             if (tid == 0) st->step = step;   // read by the overflow diagnostics
             __syncthreads();
-            if (flag_rebuild) {
-                for (int i = tid; i < n; i += B) nbr_bin_atom(R, V, i);
+            if (P.flag_rebuild) {
+                for (int i = tid; i < n; i += B) nbr_bin_atom(R, V, (uint32_t)i);
                 if (error_raised()) break;
                 for (int b = tid; b < R.nbins; b += B) nbr_sort_bin(R, b);
                 __syncthreads();
-                for (int i = tid; i < n; i += B) nbr_build_atom(R, V, i);
+                for (int i = tid; i < n; i += B) nbr_build_atom(R, V, (uint32_t)i);
                 if (error_raised()) break;
                 for (int b = tid; b < R.nbins; b += B) R.bin_n[b] = 0;
             }
@@ -983,7 +1162,7 @@ __global__ __launch_bounds__(512) void k_persist(const RunDev<T>* __restrict__ r
                 double q[NQ];
 #pragma unroll
                 for (int k = 0; k < NQ; ++k) q[k] = 0.0;
-                if (i < n) atom_final_atom(R, V, i, PHASE_STEP, step, obs, acc, q);
+                if (i < n) atom_final_atom(R, V, (uint32_t)i, PHASE_STEP, step, obs, acc, q);
                 if (obs) wave_reduce_row(q, V.partial, i - (tid & 63), n);
             }
         }
@@ -1000,22 +1179,50 @@ __global__ __launch_bounds__(512) void k_persist(const RunDev<T>* __restrict__ r
             for (int c = tid; c < nc; c += B) cell_update(R, V.Te, acc, c, step);
             if (error_raised()) break;
         }
-        if (obs) write_sample(R, V, S, step + 1);
+        if (obs) write_sample(R, V, P.S, step + 1);
         ++step;
     }
     __syncthreads();
     // write the run back
     for (int i = tid; i < n; i += B) {
-        R.sx[i] = V.sx[i];
-        R.sy[i] = V.sy[i];
-        R.sz[i] = V.sz[i];
-        R.cell[i] = V.cell[i];
-        if (L.pos_in_lds) R.pos[i] = V.pos[i];
+        gst(R.sx, i, V.sx[i]);
+        gst(R.sy, i, V.sy[i]);
+        gst(R.sz, i, V.sz[i]);
+        gst(R.cell, i, V.cell[i]);
+        if (pos_in_lds) gst(R.pos, i, V.pos[i]);
     }
-    for (int c = tid; c < nc; c += B) R.Te[c] = V.Te[c];
+    for (int c = tid; c < nc; c += B) gst(R.Te, c, V.Te[c]);
     if (tid == 0) {
         st->step = step;
         st->rebuild = 0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_persist(const RunDev<T>* __restrict__ runs,
+                                                  const int* __restrict__ run_list, int nsteps,
+                                                  uint32_t lds_max)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ PersistShared P;
+    const RunDev<T>& R = runs[run_list[blockIdx.x]];
+    const int n = R.n;
+    const PersistLayout L = persist_layout<T>(n, R.ncell, R.n_part, R.live != 0, R.n_species, lds_max);
+    T* sx = reinterpret_cast<T*>(smem + L.off_s);
+    const int8_t* species =
+        R.n_species > 1 ? reinterpret_cast<const int8_t*>(smem + L.off_species) : R.species;
+    uint16_t* cell = reinterpret_cast<uint16_t*>(smem + L.off_cell);
+    double* Te = reinterpret_cast<double*>(smem + L.off_Te);
+    double* Te2 = reinterpret_cast<double*>(smem + L.off_Te2);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.off_acc);
+    double* partial = reinterpret_cast<double*>(smem + L.off_part);
+    if (L.pos_in_lds) {
+        const View<T, InLds, InLds> V{sx, sx + n, sx + 2 * n, species, cell,
+                                      reinterpret_cast<Pos4<T>*>(smem + L.off_pos), Te, partial};
+        persist_run(R, V, Te2, acc, P, nsteps, true);
+    } else {
+        const View<T, InLds, InGlobal> V{sx, sx + n, sx + 2 * n, species, cell, R.pos, Te, partial};
+        persist_run(R, V, Te2, acc, P, nsteps, false);
     }
 }
 

@@ -62,6 +62,27 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 constexpr int64_t kPersistChunk = 4096;   // steps per persistent launch
 
+// Workgroups are dispatched round-robin over the accelerator's 8 XCDs
+// (block b runs on XCD b mod 8), each with its own L2.  Reordering a work
+// table so that every XCD receives one contiguous range of tiles keeps the
+// neighbouring rows and planes of a tile in the same L2.  Any order gives the
+// same results; only the cache traffic changes.
+constexpr size_t kXcds = 8;
+inline void xcd_order(std::vector<int2>& t)
+{
+    const size_t m = t.size();
+    if (m < 2 * kXcds) return;
+    const size_t per = (m + kXcds - 1) / kXcds;
+    std::vector<int2> o;
+    o.reserve(m);
+    for (size_t j = 0; j < per; ++j)
+        for (size_t x = 0; x < kXcds; ++x) {
+            const size_t src = x * per + j;   // only the last j can run past the end
+            if (src < m) o.push_back(t[src]);
+        }
+    t.swap(o);
+}
+
 // Carves typed sub-arrays out of one allocation.
 struct Carver {
     size_t off = 0;
@@ -83,7 +104,9 @@ std::string validate_desc(const sl_system_desc* d)
         if (d->ncell[k] < 2 || (d->ncell[k] & 1)) return "every ncell must be even and >= 2";
     const int64_t nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
     const int64_t n = nb * (int64_t)d->ncell[0] * d->ncell[1] * d->ncell[2];
-    if (n > (1ll << 30)) return "too many sites";
+    // per-atom arrays are addressed with 32-bit byte offsets (32 B per atom
+    // at most)
+    if (n >= (1ll << 27)) return "too many sites (at most 2^27 - 1)";
     if (d->ncell[0] > 1024 || d->ncell[1] > 1024 || d->ncell[2] > 1024) return "ncell above 1024";
     if (!(d->a > 0.0)) return "lattice constant must be positive";
     if (d->n_species < 1 || d->n_species > 4) return "n_species must be 1..4";
@@ -274,6 +297,7 @@ public:
     // launch shape (every choice gives bitwise-identical results)
     int spin_block = 256, spin_spt = 1, atom_block = 256;
     int persist_block = 0;          // 0: every run on the multi-kernel step
+    int xcd_ord = 0;                // 1: XCD-contiguous work tables
     virtual sl_status retune() = 0;
 };
 
@@ -692,6 +716,9 @@ private:
             R.m_e[sp] = (T)(m * sl::kMVV2E);
             R.cnt[sp] = cnt[sp];
         }
+        R.noisy = 0;
+        for (int sp = 0; sp < d->n_species; ++sp)
+            if (R.sig[sp] > T(0)) R.noisy = 1;
         for (int sh = 0; sh < 2; ++sh)
             for (int a = 0; a < 4; ++a)
                 for (int b = 0; b < 4; ++b) R.J[sh][a][b] = (T)d->J[sh][a][b];
@@ -915,6 +942,10 @@ private:
                 max_sub = std::max(max_sub, R.n_sub);
             }
             any_live = any_live || R.live;
+        }
+        if (xcd_ord) {
+            xcd_order(ws);
+            xcd_order(wa);
         }
         for (void* p : tables) alloc.put(p);
         tables.clear();
@@ -1171,11 +1202,13 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     if (t->graph_steps < 1 || t->graph_steps > 256) return fail(SL_EINVAL, "graph_steps must be 1..256");
     if (t->persist_block != 0 && t->persist_block != 256 && t->persist_block != 512)
         return fail(SL_EINVAL, "persist_block must be 0, 256 or 512");
+    if (t->xcd_order != 0 && t->xcd_order != 1) return fail(SL_EINVAL, "xcd_order must be 0 or 1");
     e->spin_block = t->spin_block;
     e->spin_spt = t->spin_spt;
     e->atom_block = t->atom_block;
     e->graph_steps = t->graph_steps;
     e->persist_block = t->persist_block;
+    e->xcd_ord = t->xcd_order;
     return e->retune();
 }
 
@@ -1186,6 +1219,7 @@ static void get_tuning(const Engine* e, sl_tuning* t)
     t->atom_block = e->atom_block;
     t->graph_steps = e->graph_steps;
     t->persist_block = e->persist_block;
+    t->xcd_order = e->xcd_ord;
 }
 
 sl_status sl_set_tuning(sl_system h, const sl_tuning* t)

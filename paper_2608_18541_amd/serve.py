@@ -72,8 +72,11 @@ def summarize(results: List[Result], makespan: float) -> ServeStats:
 class Server:
     def __init__(self, executor, chunk: int = 500, obs_every: int = 100,
                  keep_state: bool = False, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep,
+                 progress: Optional[Callable[[str], None]] = None, progress_every: float = 20.0):
         self.ex = executor
+        self.progress = progress
+        self.progress_every = progress_every
         self.chunk = chunk
         self.obs_every = obs_every
         self.keep_state = keep_state
@@ -87,8 +90,13 @@ class Server:
         active: Dict[int, tuple] = {}
         done: List[Result] = []
         t0 = self.clock()
+        next_report = self.progress_every
         while pending or waiting or active:
             now = self.clock() - t0
+            if self.progress is not None and now >= next_report:
+                self.progress("served %d, active %d, waiting %d, pending %d at %.0f s"
+                              % (len(done), len(active), len(waiting), len(pending), now))
+                next_report = now + self.progress_every
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             # admission: first come first served, by slot and HBM footprint
