@@ -42,7 +42,7 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, tuning=None):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
     copy-kernel calibration), or None when there is none or the kernels
@@ -55,6 +55,8 @@ def measured_traffic(kernel: str, workload: str):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
         if kv.get("source_sha256") != source_digest():
+            return None
+        if tuning is not None and json.loads(kv.get("tuning", "null")) != dict(tuning):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -122,6 +124,7 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     runs = W.phase_diagram(L=16, n_seeds=n_seeds, n_steps=n_steps)
     res = {}
     flags = {}
+    mz_mean = {}
     for prec in (N.SL_FP32, N.SL_FP64):
         b = N.Batch(precision=prec, max_runs=len(runs))
         slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
@@ -134,15 +137,18 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
         except N.SLError:
             pass                    # runs that stopped are counted below
         el = time.perf_counter() - t0
-        fl, failed = [], 0
+        fl, failed, series = [], 0, []
         for s in slots:
             try:
                 mz = [o["M"][1][2] for o in b.get(s, max_samples=n_steps // 20 + 2)["obs"]]
                 fl.append(switched(mz))
+                series.append(mz)
             except N.SLError:
                 failed += 1
                 fl.append(False)
         flags[prec] = np.array(fl).reshape(8, 8, n_seeds)
+        m = min(len(x) for x in series) if series else 0
+        mz_mean[prec] = np.mean([x[:m] for x in series], axis=0) if m else np.zeros(0)
         res["fp32" if prec else "fp64"] = {"seconds": round(el, 3),
                                            "runs_per_s": round(len(runs) / el, 3),
                                            "atom_steps_per_s": len(runs) * 4096 * n_steps / el,
@@ -156,6 +162,32 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     agree = float((flags[N.SL_FP32] == flags[N.SL_FP64]).mean())
     k = flags[N.SL_FP32].sum(axis=2)
     ci = [wilson_ci(int(v), n_seeds) for v in k.ravel()]
+    # homogeneity of the FP32 and FP64 switching counts over the 64 cells:
+    # sum of squared two-proportion z statistics over cells with 0 < p < 1
+    k64 = flags[N.SL_FP64].sum(axis=2)
+    chi2, dof = 0.0, 0
+    for a, c in zip(k.ravel(), k64.ravel()):
+        pp = (a + c) / (2.0 * n_seeds)
+        if 0.0 < pp < 1.0:
+            chi2 += (a - c) ** 2 / (2.0 * n_seeds * pp * (1.0 - pp))
+            dof += 1
+    # upper tail of chi^2 with dof degrees of freedom by the Wilson-Hilferty
+    # cube-root normal approximation (about 1e-3 absolute at dof >= 10)
+    if dof:
+        wz = ((chi2 / dof) ** (1.0 / 3.0) - (1.0 - 2.0 / (9.0 * dof))) / math.sqrt(2.0 / (9.0 * dof))
+        pval = 0.5 * math.erfc(wz / math.sqrt(2.0))
+    else:
+        pval = 1.0
+    m = min(len(mz_mean[N.SL_FP32]), len(mz_mean[N.SL_FP64]))
+    dM = np.abs(mz_mean[N.SL_FP32][:m] - mz_mean[N.SL_FP64][:m])
+    # the FP64 oracle on one core for a few steps of one 16^3 run
+    from oracle import oracle as O
+    r0 = runs[0]
+    orc = O.Oracle(r0.spec, r0.state.species, r0.state.spins, r0.state.vel)
+    orc.step(1)
+    t0 = time.perf_counter()
+    orc.step(3)
+    t_orc = (time.perf_counter() - t0) / 3
     res.update({
         "workload": "Gd25(FeCo)75 sc 16^3 x (8 alpha 0.005-0.04 log) x (8 peak T_e 800-2400 K)"
                     " x %d seeds = %d runs, %d steps" % (n_seeds, len(runs), n_steps),
@@ -167,6 +199,11 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
         "max_abs_dP_fp32_fp64": float(np.abs(p32 - p64).max()),
         "paired_flag_agreement": agree,
         "wilson_halfwidth_max": float(max(h - l for l, h in ci) / 2),
+        "chi2_fp32_vs_fp64": round(chi2, 2), "chi2_dof": dof, "chi2_p_value": round(pval, 4),
+        "max_abs_dMz_gd_ensemble_fp32_fp64": float(dM.max()) if m else None,
+        "cpu_oracle_runs_per_s_per_core": 1.0 / (t_orc * n_steps),
+        "cpu_oracle_note": "FP64 oracle, one thread, 3 steps of one 16^3 run timed "
+                           "(%.1f ms per step), scaled to %d steps" % (t_orc * 1e3, n_steps),
     })
     return res
 
@@ -218,13 +255,16 @@ def large_run(N, I, steps: int) -> dict:
     H = spec.n_sites / 4
     bpu = bytes_per_unit("spin_pass", 1, spec.n_species, 0)
     ach = bpu * H / (avg[0] * 1e-3) / 1e9
-    a32 = N.System(spec, st, precision=N.SL_FP32)
-    a64 = N.System(spec, st, precision=N.SL_FP64)
+    a32 = N.System(spec, st, precision=N.SL_FP32, obs_every=1, obs_capacity=16)
+    a64 = N.System(spec, st, precision=N.SL_FP64, obs_every=1, obs_capacity=16)
     a32.step(10)
     a64.step(10)
     g32, g64 = a32.state(), a64.state()
+    m32 = np.array([o["m"] for o in a32.observables()])
+    m64 = np.array([o["m"] for o in a64.observables()])
     a32.close()
     a64.close()
+    e32, e64 = strain_profile(spec, g32["x"]), strain_profile(spec, g64["x"])
     return {"workload": "bcc Fe 64^3 (524288 atoms) FP32, 32^3 grid, kappa_e 80 W/m/K, "
                         "100 fs top-10 nm pulse",
             "atom_steps_per_s": spec.n_sites * steps / el, "ms_per_step": el / steps * 1e3,
@@ -233,10 +273,32 @@ def large_run(N, I, steps: int) -> dict:
             "per_step_us": {k: round(avg[i] * cnt[i] / 20 * 1e3, 2) for i, k in enumerate(KERNELS)},
             "fp32_vs_fp64_10_steps": {"max_abs_ds": float(np.abs(g32["s"] - g64["s"]).max()),
                                       "max_abs_dv_rel": float(np.abs(g32["v"] - g64["v"]).max() /
-                                                              np.sqrt((g64["v"] ** 2).mean()))}}
+                                                              np.sqrt((g64["v"] ** 2).mean())),
+                                      "max_abs_dm": float(np.abs(m32 - m64).max()),
+                                      "max_abs_d_strain_zz": float(np.abs(e32 - e64).max()),
+                                      "max_abs_strain_zz": float(np.abs(e64).max())},
+            "note": "FP64 reference is the GPU FP64 path (pinned to the oracle at 1e-10 on "
+                    "smaller systems); the all-pairs oracle is too slow at 524288 atoms"}
 
 
-def field_llg_scale(N, I, L: int = 256) -> dict:
+def strain_profile(spec, x) -> np.ndarray:
+    """eps_zz(z): per z layer of unit cells the mean displacement along z from
+    the ideal sites, differentiated along z (periodic central difference)."""
+    Lx, Ly, Lz = spec.ncell
+    nb = 2 if spec.lattice == 1 else 1
+    idx = np.arange(spec.n_sites)
+    b = idx % nb
+    cell = idx // nb
+    z = cell // (Lx * Ly)
+    ideal = (z + 0.25 + 0.5 * b) * spec.a
+    box = Lz * spec.a
+    d = x[:, 2] - ideal
+    d -= box * np.round(d / box)
+    uz = np.bincount(z, weights=d, minlength=Lz) / np.bincount(z, minlength=Lz)
+    return (np.roll(uz, -1) - np.roll(uz, 1)) / (2.0 * spec.a)
+
+
+def field_llg_scale(N, I, L: int = 256, tuning=None) -> dict:
     """The field + LLG colour pass alone (frozen lattice, constant bath) on
     bcc Fe L^3 in FP32, large enough (2 L^3 sites) that the spins do not fit
     in the 256 MB last-level cache: achieved algorithmic bandwidth of one
@@ -248,15 +310,19 @@ def field_llg_scale(N, I, L: int = 256) -> dict:
     del st
     s.step(4)
     s.synchronize()
-    from paper_2608_18541_amd.autotune import autotune
-    tuning = autotune(s, steps=8, rounds=2, use_cache=False)
+    if tuning:
+        s.set_tuning(**tuning)
+    else:
+        from paper_2608_18541_amd.autotune import autotune
+        autotune(s, steps=8, rounds=2, use_cache=False)
+    tuning = s.tuning()
     avg, cnt = s.step_profiled(10)
     s.close()
     H = spec.n_sites / 4
     bpu = bytes_per_unit("spin_pass", 1, spec.n_species, 0)
     us = avg[0] * 1e3
     ach = bpu * H / (us * 1e-6) / 1e9
-    traffic = measured_traffic("spin_pass", "fe%d_fp32" % L)
+    traffic = measured_traffic("spin_pass", "fe%d_fp32" % L, tuning)
     out = {"workload": "bcc Fe %d^3 (%d sites) FP32, frozen lattice, 300 K bath, field + LLG "
                        "colour pass" % (L, spec.n_sites),
            "avg_launch_us": round(us, 3), "sites_per_launch": int(H),
@@ -285,6 +351,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
     ap.add_argument("--large-steps", type=int, default=500)
+    ap.add_argument("--scale-tuning", default="",
+                    help="JSON launch shape for the 256^3 field+LLG row (default: autotuned)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported "
@@ -299,7 +367,10 @@ def main() -> int:
     torch.cuda.set_device(0)
     spec = I.gdfeco_sc_spec(L=32, tn=8, S0=I.cfg1_S0(), alpha=0.01)
     st = I.initial_state(spec, "afm")
+    t_up = time.perf_counter()
     sys_ = N.System(spec, st, precision=N.SL_FP64, obs_every=100)
+    sys_.synchronize()
+    t_up = time.perf_counter() - t_up
     print("bench: workload built, warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
     sys_.step(args.warmup)
     sys_.synchronize()
@@ -311,6 +382,9 @@ def main() -> int:
     el = time.perf_counter() - t0
     value = spec.n_sites * args.steps / el
     print("bench: timed %d steps in %.3f s" % (args.steps, el), file=sys.stderr, flush=True)
+    t_dn = time.perf_counter()
+    sys_.state()
+    t_dn = time.perf_counter() - t_dn
 
     # per-kernel device time of the same path, HIP events on the run's stream
     avg, cnt = sys_.step_profiled(args.profile_steps)
@@ -343,6 +417,11 @@ def main() -> int:
                    "n_sites": spec.n_sites, "seq_len": None, "global_batch": 1,
                    "parallelism": "single run"},
         "roofline": roof,
+        "pcie_inclusive": {"value": round(spec.n_sites * args.steps / (el + t_up + t_dn), 1),
+                           "init_upload_s": round(t_up, 4), "state_download_s": round(t_dn, 4),
+                           "note": "host-buffer boundary: system creation (upload, initial "
+                                   "lists and forces) and one state read-back added to the "
+                                   "timed steps"},
     }
     extras = [] if args.no_extras else [e for e in args.extras.split(",") if e]
     from paper_2608_18541_amd import serve as S
@@ -354,7 +433,13 @@ def main() -> int:
     if "large" in extras:
         out["large"] = large_run(N, I, args.large_steps)
     if "scale" in extras:
-        out["field_llg_scale"] = field_llg_scale(N, I)
+        row = field_llg_scale(N, I, tuning=json.loads(args.scale_tuning) if args.scale_tuning else None)
+        sweep = []
+        for L in (128, 192):
+            r = field_llg_scale(N, I, L=L, tuning=row["tuning"])
+            sweep.append({k: r[k] for k in ("workload", "avg_launch_us", "achieved_GBs", "frac")})
+        row["sweep_same_tuning"] = sweep
+        out["field_llg_scale"] = row
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, st)

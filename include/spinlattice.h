@@ -171,6 +171,21 @@ sl_status sl_observables(sl_system h, sl_obs* out, int64_t max_samples, int64_t*
  * [n][3], spins [n][3], electron temperatures [cells]. */
 sl_status sl_get_state(sl_system h, double* x, double* v, double* s, double* Te);
 
+/* Waits, then replaces parts of the state from host arrays in canonical
+ * order (checkpoint restore; any pointer may be NULL to keep the current
+ * values): positions [n][3] in A (any periodic image; stored as the
+ * minimum-image displacement from the ideal site), velocities [n][3] in A/ps
+ * (ignored for a frozen lattice), spins [n][3] (unit vectors within 1e-6),
+ * electron temperatures [cells] in K.  Species, parameters, the step counter
+ * (so the Philox noise continues) and the returned samples are kept.
+ * Electron-cell ids, neighbour lists and forces are recomputed for the new
+ * positions exactly as at initialisation, and with obs_every > 0 one sample
+ * of the new state is recorded at the current step.  Synchronous.
+ * SL_EINVAL, with the state unchanged, for a non-unit spin, a non-finite
+ * position or velocity, or a negative or non-finite temperature. */
+sl_status sl_set_state(sl_system h, const double* x, const double* v, const double* s,
+                       const double* Te);
+
 /* Number of sites, electron cells and completed steps (host view). */
 sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* steps);
 

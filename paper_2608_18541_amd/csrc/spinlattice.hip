@@ -7,6 +7,7 @@
 // launch cover all active runs.  A single system is an engine with one run.
 // Steps are replayed from a captured HIP graph of graph_steps steps.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -61,6 +62,24 @@ struct DevAlloc {
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 constexpr int64_t kPersistChunk = 4096;   // steps per persistent launch
+
+template <typename X> struct ident {
+    using type = X;
+};
+
+// Kernel launch; when profiling, through HIP's extended launch, whose start
+// and stop events are stamped by the dispatch itself (the kernel's own
+// duration, as a kernel trace reports it, without the queue overhead that
+// events recorded around the launch would add).
+template <typename... KA>
+void launch(void (*k)(KA...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t st, hipEvent_t e0,
+            hipEvent_t e1, typename ident<KA>::type... args)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(k, grid, block, shmem, st, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(k, grid, block, shmem, st, args...);
+}
 
 // Workgroups are dispatched round-robin over the accelerator's 8 XCDs
 // (block b runs on XCD b mod 8), each with its own L2.  Reordering a work
@@ -283,6 +302,8 @@ public:
     virtual sl_status advance(int64_t n) = 0;
     virtual sl_status get(int slot, double* x, double* v, double* s, double* Te, sl_obs* obs,
                           int64_t max_samples, int64_t* n_obs) = 0;
+    virtual sl_status set_state(int slot, const double* x, const double* v, const double* s,
+                                const double* Te) = 0;
     virtual sl_status remove(int slot) = 0;
     virtual sl_status sync() = 0;
     virtual sl_status profiled(int64_t n, double avg[5], int64_t cnt[5]) = 0;
@@ -464,9 +485,9 @@ public:
         std::vector<int> cls;
         Prof p{&ev, &cls};
         if (persist_runs > 0) {
-            sl_status st = timed(stream, &p, 4, [&] {
-                sl::k_persist<T><<<persist_runs, persist_block, persist_bytes, stream>>>(
-                    d_runs, d_persist_list, (int)n, lds_max);
+            sl_status st = timed(stream, &p, 4, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_persist<T>, dim3(persist_runs), dim3(persist_block), persist_bytes, stream,
+                       a, b, d_runs, d_persist_list, (int)n, lds_max);
             });
             if (st != SL_OK) return st;
         }
@@ -567,6 +588,88 @@ public:
         }
         if (rs.err) return numeric_error(s, rs.err);
         return SL_OK;
+    }
+
+    // Replaces positions, velocities, spins and/or the electron grid of a run
+    // (canonical host order, NULL keeps the current values), then recomputes
+    // electron cells, neighbour lists and forces as at initialisation.
+    sl_status set_state(int s, const double* x, const double* v, const double* sp,
+                        const double* Te) override
+    {
+        if (s < 0 || s >= (int)runs.size() || !runs[s].used) return fail(SL_EINVAL, "bad slot");
+        Run& r = runs[s];
+        RD& R = host_rd[s];
+        const size_t n = (size_t)r.z.n;
+        for (size_t i = 0; sp && i < n; ++i) {
+            const double nn = std::sqrt(sp[3 * i] * sp[3 * i] + sp[3 * i + 1] * sp[3 * i + 1] +
+                                        sp[3 * i + 2] * sp[3 * i + 2]);
+            if (!(std::fabs(nn - 1.0) <= 1e-6)) return fail(SL_EINVAL, "spins must be unit vectors");
+        }
+        for (size_t i = 0; x && i < 3 * n; ++i)
+            if (!std::isfinite(x[i])) return fail(SL_EINVAL, "positions must be finite");
+        for (size_t i = 0; v && i < 3 * n; ++i)
+            if (!std::isfinite(v[i])) return fail(SL_EINVAL, "velocities must be finite");
+        for (int c = 0; Te && c < r.z.ncell; ++c)
+            if (!(Te[c] >= 0.0) || !std::isfinite(Te[c])) return fail(SL_EINVAL, "temperatures must be >= 0");
+        SL_HIP(hipStreamSynchronize(stream));
+        std::vector<T> a(n), b(n), c(n);
+        auto put3 = [&](T* dx, T* dy, T* dz) -> sl_status {
+            SL_HIP(hipMemcpyAsync(dx, a.data(), n * sizeof(T), hipMemcpyHostToDevice, stream));
+            SL_HIP(hipMemcpyAsync(dy, b.data(), n * sizeof(T), hipMemcpyHostToDevice, stream));
+            SL_HIP(hipMemcpyAsync(dz, c.data(), n * sizeof(T), hipMemcpyHostToDevice, stream));
+            SL_HIP(hipStreamSynchronize(stream));
+            return SL_OK;
+        };
+        sl_status st;
+        if (sp) {
+            for (size_t i = 0; i < n; ++i) {
+                const size_t ci = (size_t)r.canon[i];
+                a[i] = (T)sp[3 * ci];
+                b[i] = (T)sp[3 * ci + 1];
+                c[i] = (T)sp[3 * ci + 2];
+            }
+            if ((st = put3(R.sx, R.sy, R.sz)) != SL_OK) return st;
+        }
+        if (x) {
+            // displacement from the ideal site, minimum image
+            T* out[3] = {a.data(), b.data(), c.data()};
+            for (size_t i = 0; i < n; ++i) {
+                const sl::Site site = sl::decode_site(R.g, (uint32_t)i);
+                const double off = 0.25 + 0.5 * site.b;
+                const double r0[3] = {(site.x + off) * r.d.a, (site.y + off) * r.d.a,
+                                      (site.z + off) * r.d.a};
+                const size_t ci = (size_t)r.canon[i];
+                for (int k = 0; k < 3; ++k) {
+                    const double L = r.d.ncell[k] * r.d.a;
+                    double d = x[3 * ci + k] - r0[k];
+                    d -= L * std::nearbyint(d / L);
+                    out[k][i] = (T)d;
+                }
+            }
+            if ((st = put3(R.ux, R.uy, R.uz)) != SL_OK) return st;
+        }
+        if (v && R.live) {
+            for (size_t i = 0; i < n; ++i) {
+                const size_t ci = (size_t)r.canon[i];
+                a[i] = (T)v[3 * ci];
+                b[i] = (T)v[3 * ci + 1];
+                c[i] = (T)v[3 * ci + 2];
+            }
+            if ((st = put3(R.vx, R.vy, R.vz)) != SL_OK) return st;
+        }
+        if (Te) {
+            r.te_init.assign(Te, Te + r.z.ncell);
+        } else {
+            r.te_init.resize(r.z.ncell);
+            SL_HIP(hipMemcpy(r.te_init.data(), R.Te, sizeof(double) * r.z.ncell, hipMemcpyDeviceToHost));
+        }
+        if (R.live) {
+            sl::RunState rs;
+            SL_HIP(hipMemcpy(&rs, R.st, sizeof(rs), hipMemcpyDeviceToHost));
+            rs.rebuild = 1;
+            SL_HIP(hipMemcpy(R.st, &rs, sizeof(rs), hipMemcpyHostToDevice));
+        }
+        return commit_and_init(s);
     }
 
     sl_status remove(int s) override
@@ -991,15 +1094,14 @@ private:
     template <typename F> sl_status timed(hipStream_t st, Prof* p, int cls, F&& launch)
     {
         if (!p) {
-            launch();
+            launch(nullptr, nullptr);
             return SL_OK;
         }
         hipEvent_t a, b;
         SL_HIP(hipEventCreate(&a));
         SL_HIP(hipEventCreate(&b));
-        SL_HIP(hipEventRecord(a, st));
-        launch();
-        SL_HIP(hipEventRecord(b, st));
+        launch(a, b);
+        SL_HIP(hipGetLastError());
         p->ev->push_back(a);
         p->ev->push_back(b);
         p->cls->push_back(cls);
@@ -1009,47 +1111,51 @@ private:
     sl_status enqueue_step(hipStream_t st, Prof* p)
     {
         const int C = max_colours();
+        const dim3 bs(spin_block), ba(atom_block), bk(sl::kBlock);
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
-            sl_status e = timed(st, p, 0, [&] {
+            sl_status e = timed(st, p, 0, [&](hipEvent_t a, hipEvent_t b) {
+                const dim3 g(active_blocks_spin);
                 if (spin_spt == 4)
-                    sl::k_spin_pass<T, 4><<<active_blocks_spin, spin_block, 0, st>>>(d_runs, d_work_spin, pass);
+                    launch(sl::k_spin_pass<T, 4>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass);
                 else if (spin_spt == 2)
-                    sl::k_spin_pass<T, 2><<<active_blocks_spin, spin_block, 0, st>>>(d_runs, d_work_spin, pass);
+                    launch(sl::k_spin_pass<T, 2>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass);
                 else
-                    sl::k_spin_pass<T, 1><<<active_blocks_spin, spin_block, 0, st>>>(d_runs, d_work_spin, pass);
+                    launch(sl::k_spin_pass<T, 1>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass);
             });
             if (e != SL_OK) return e;
         }
+        const dim3 ga(active_blocks_atom);
         if (any_live) {
-            sl_status e = timed(st, p, 2, [&] {
-                sl::k_kick_drift<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom,
-                                                                              sl::PHASE_STEP);
+            sl_status e = timed(st, p, 2, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_kick_drift<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                       (int)sl::PHASE_STEP);
             });
             if (e != SL_OK) return e;
-            sl::k_nbr_bin<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom);
+            sl::k_nbr_bin<T><<<ga, ba, 0, st>>>(d_runs, d_work_atom);
             if (active_blocks_bin > 0)
-                sl::k_nbr_sort<T><<<active_blocks_bin, sl::kBlock, 0, st>>>(d_runs, d_work_bin);
-            sl::k_nbr_build<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom);
+                sl::k_nbr_sort<T><<<active_blocks_bin, bk, 0, st>>>(d_runs, d_work_bin);
+            sl::k_nbr_build<T><<<ga, ba, 0, st>>>(d_runs, d_work_atom);
         }
-        sl_status e = timed(st, p, 1, [&] {
-            sl::k_atom_final<T><<<active_blocks_atom, atom_block, 0, st>>>(d_runs, d_work_atom,
-                                                                          sl::PHASE_STEP);
+        sl_status e = timed(st, p, 1, [&](hipEvent_t a, hipEvent_t b) {
+            launch(sl::k_atom_final<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
         });
         if (e != SL_OK) return e;
         for (int sub = 0; sub < max_sub; ++sub) {
-            e = timed(st, p, 3, [&] {
-                sl::k_ttm_diffuse<T><<<active_blocks_diff, sl::kBlock, 0, st>>>(d_runs, d_work_diff, sub);
+            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_ttm_diffuse<T>, dim3(active_blocks_diff), bk, 0, st, a, b, d_runs,
+                       d_work_diff, sub);
             });
             if (e != SL_OK) return e;
         }
         if (active_blocks_cell > 0) {
-            e = timed(st, p, 3, [&] {
-                sl::k_grid<T><<<active_blocks_cell, sl::kBlock, 0, st>>>(d_runs, d_work_cell);
+            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_grid<T>, dim3(active_blocks_cell), bk, 0, st, a, b, d_runs, d_work_cell);
             });
             if (e != SL_OK) return e;
         }
-        e = timed(st, p, 3, [&] {
-            sl::k_finalize<T><<<active_runs, sl::kBlock, 0, st>>>(d_runs, d_run_list, sl::PHASE_STEP);
+        e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+            launch(sl::k_finalize<T>, dim3(active_runs), bk, 0, st, a, b, d_runs, d_run_list,
+                   (int)sl::PHASE_STEP);
         });
         return e;
     }
@@ -1180,6 +1286,13 @@ sl_status sl_get_state(sl_system h, double* x, double* v, double* s, double* Te)
 {
     if (!h) return fail(SL_EINVAL, "null handle");
     return h->eng->get(0, x, v, s, Te, nullptr, 0, nullptr);
+}
+
+sl_status sl_set_state(sl_system h, const double* x, const double* v, const double* s,
+                       const double* Te)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    return h->eng->set_state(0, x, v, s, Te);
 }
 
 sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* steps)

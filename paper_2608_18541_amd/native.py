@@ -102,6 +102,7 @@ EXPORTS = {
     "sl_observables": (C.c_int32, [C.c_void_p, C.POINTER(sl_obs), C.c_int64,
                                    C.POINTER(C.c_int64)]),
     "sl_get_state": (C.c_int32, [C.c_void_p] + [C.POINTER(C.c_double)] * 4),
+    "sl_set_state": (C.c_int32, [C.c_void_p] + [C.POINTER(C.c_double)] * 4),
     "sl_info": (C.c_int32, [C.c_void_p] + [C.POINTER(C.c_int64)] * 3),
     "sl_footprint_bytes": (C.c_int32, [C.POINTER(sl_system_desc), C.POINTER(sl_ttm_desc),
                                        C.POINTER(C.c_size_t)]),
@@ -317,6 +318,21 @@ class System:
         Te = np.zeros(self.spec.n_tcells)
         check(lib().sl_get_state(self._h, _dp(x), _dp(v), _dp(s), _dp(Te)))
         return {"x": x, "v": v, "s": s, "Te": Te}
+
+    def set_state(self, x=None, v=None, s=None, Te=None) -> None:
+        """Replaces any of positions, velocities, spins and the electron grid
+        (canonical order); the step counter and the noise stream continue."""
+        def arr(a, shape):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            if a.shape != shape:
+                raise ValueError("expected shape %s, got %s" % (shape, a.shape))
+            return a
+        n = self.n
+        bufs = [arr(x, (n, 3)), arr(v, (n, 3)), arr(s, (n, 3)), arr(Te, (self.spec.n_tcells,))]
+        ptrs = [None if b is None else _dp(b) for b in bufs]
+        check(lib().sl_set_state(self._h, *ptrs))
 
     def observables(self, max_samples: int = 1 << 20) -> list:
         buf = (sl_obs * max_samples)()

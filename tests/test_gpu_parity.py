@@ -11,7 +11,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2608_18541_amd import inputs as I
-from tests.gpu_util import compare_states, rel_err
+from tests.gpu_util import compare_states, min_image, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -197,3 +197,36 @@ def test_invalid_inputs_rejected(N):
     with pytest.raises(N.SLError) as e:
         N.System(hot, sth)
     assert e.value.code == N.SL_EINVAL
+
+
+def test_set_state_restores_a_checkpoint(N):
+    """A checkpoint (positions, velocities, spins, T_e) taken from one run and
+    written into a system that started elsewhere (same noise key, same step
+    count) continues like the original, to the FP64 parity tolerance; the
+    state reads back exactly; invalid states are rejected unchanged."""
+    spec = I.gdfeco_sc_spec(L=8, tn=2, S0=0.3, t0=0.002, fwhm=0.002, seed=41, run_id=3)
+    a = N.System(spec, I.initial_state(spec, "afm"), precision=0)
+    a.step(37)
+    ck = a.state()
+    a.step(20)
+    fa = a.state()
+    # same species and noise key, different spins and velocities
+    b = N.System(spec, I.initial_state(spec, "random", T_lattice=900.0), precision=0)
+    b.step(37)
+    b.set_state(x=ck["x"], v=ck["v"], s=ck["s"], Te=ck["Te"])
+    rb = b.state()
+    assert np.array_equal(rb["s"], ck["s"]) and np.array_equal(rb["v"], ck["v"])
+    assert np.array_equal(rb["Te"], ck["Te"])
+    assert np.abs(min_image(rb["x"] - ck["x"], spec.box)).max() < 1e-12
+    b.step(20)
+    errs, bad = compare_states(b.state(), fa, spec.box, 1e-10)
+    assert not bad, errs
+    bad_s = ck["s"].copy()
+    bad_s[5] *= 1.01
+    with pytest.raises(N.SLError) as e:
+        b.set_state(s=bad_s)
+    assert e.value.code == N.SL_EINVAL
+    with pytest.raises(N.SLError):
+        b.set_state(Te=-np.ones_like(ck["Te"]))
+    a.close()
+    b.close()
