@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["spin_pass", "atom_final", "kick_drift", "grid", "persist"]
+KERNELS = ["spin_pass", "atom_final", "spin_kick", "end_step", "persist"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -64,24 +64,31 @@ def measured_traffic(kernel: str, workload: str, tuning=None):
 
 
 def bytes_per_unit(kernel: str, fp: int, n_species: int, z_list: float) -> float:
-    """Algorithmic bytes per processed unit of each kernel:
-    spin_pass per updated site, atom_final / kick_drift per atom."""
+    """Algorithmic bytes per processed unit of each kernel class:
+    spin_pass per updated site, atom_final and kick per atom."""
     t = 8 if fp == 0 else 4
     sp = 1 if n_species > 1 else 0
     if kernel == "spin_pass":
         return 6 * t + sp + 2                  # own spin read + write, species, cell id
     if kernel == "atom_final":
         return 3 * t + 6 * t + 3 * t + 4 * z_list + 4 + sp + 2
-    if kernel == "kick_drift":
-        return 3 * t + 6 * t + 6 * t + 3 * t + sp + 2
+    if kernel == "kick":
+        # F read, v r+w, u r+w, reference u read, species, cell id, bin count + slot
+        return 3 * t + 6 * t + 6 * t + 3 * t + sp + 2 + 8
     return 0.0
 
 
-def units_per_launch(kernel: str, n_sites: int, colours: int) -> float:
+def launch_bytes(kernel: str, fp: int, n_species: int, z_list: float, n_sites: int,
+                 colours: int) -> float:
+    """Algorithmic bytes of one launch of a kernel class on one run."""
+    H = n_sites / colours
     if kernel == "spin_pass":
-        return n_sites / colours
-    if kernel in ("atom_final", "kick_drift"):
-        return float(n_sites)
+        return bytes_per_unit("spin_pass", fp, n_species, z_list) * H
+    if kernel == "spin_kick":              # colour pass 0 carrying the lattice kick
+        return (bytes_per_unit("spin_pass", fp, n_species, z_list) * H +
+                bytes_per_unit("kick", fp, n_species, z_list) * n_sites)
+    if kernel == "atom_final":
+        return bytes_per_unit("atom_final", fp, n_species, z_list) * n_sites
     return 0.0
 
 
@@ -393,9 +400,7 @@ def main() -> int:
     di = KERNELS.index(dom)
     # mean neighbour-list length of the Morse list at this density
     z_list = 18.0
-    bpu = bytes_per_unit(dom, 0, spec.n_species, z_list)
-    units = units_per_launch(dom, spec.n_sites, 2)
-    alg_bytes = bpu * units
+    alg_bytes = launch_bytes(dom, 0, spec.n_species, z_list, spec.n_sites, 2)
     achieved = alg_bytes / (avg[di] * 1e-3) / 1e9 if avg[di] > 0 else 0.0
     traffic = measured_traffic(dom, "alloy32_fp64")
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

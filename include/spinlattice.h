@@ -186,6 +186,19 @@ sl_status sl_get_state(sl_system h, double* x, double* v, double* s, double* Te)
 sl_status sl_set_state(sl_system h, const double* x, const double* v, const double* s,
                        const double* Te);
 
+/* Device-side counters of one run. */
+typedef struct {
+    int64_t steps;            /* completed steps                                     */
+    int64_t samples;          /* observable samples recorded (returned or not)       */
+    int64_t list_rebuilds;    /* Verlet-list builds, the initial one included
+                                 (0 for a frozen lattice)                            */
+    int32_t max_list;         /* longest neighbour list built so far                 */
+    int32_t list_capacity;    /* entries per atom the list holds (0: frozen lattice) */
+} sl_run_stats;
+
+/* Waits, then reads the run's counters.  SL_EINVAL for a null output. */
+sl_status sl_stats(sl_system h, sl_run_stats* out);
+
 /* Number of sites, electron cells and completed steps (host view). */
 sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* steps);
 
@@ -193,11 +206,13 @@ sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* step
 sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
                              size_t* bytes);
 
-/* Runs n_steps (at most 4096) launching every kernel directly with HIP
- * events around each; returns the average device time (ms) per launch of
- * each kernel class and the launch counts: 0 spin colour pass, 1 lattice
- * force and electron-phonon step, 2 kick-drift, 3 electron grid and
- * end-of-step reductions, 4 persistent kernel (one launch for all steps). */
+/* Runs n_steps (at most 4096) launching every kernel directly, each timed
+ * by HIP events stamped by its own dispatch; returns the average device time
+ * (ms) per launch of each kernel class and the launch counts: 0 spin colour
+ * pass, 1 lattice force and electron-phonon step, 2 colour pass 0 carrying
+ * the lattice's kick, drift and binning (live lattices), 3 neighbour-list
+ * build, electron grid and end-of-step reductions, 4 persistent kernel (one
+ * launch for all steps). */
 sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5]);
 
 /* Launch shape of the step kernels.  Every choice performs the same
@@ -215,6 +230,9 @@ typedef struct sl_tuning {
     int32_t xcd_order;        /* 1: work tables ordered so that each of the 8 XCDs
                                  receives one contiguous range of tiles (its L2
                                  then holds their neighbours); 0: round-robin    */
+    int32_t bin_mode;         /* neighbour binning: 1 by the kick every step, 2 by a
+                                 separate launch only when a list is rebuilt, 0
+                                 automatic (1 up to 2^20 live atoms)             */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of
@@ -262,6 +280,10 @@ sl_status sl_batch_add(sl_batch b, const sl_system_desc* desc, const sl_ttm_desc
 /* Enqueues up to n_steps steps for every active run (a run stops at its
  * target).  Asynchronous. */
 sl_status sl_batch_advance(sl_batch b, int64_t n_steps);
+
+/* Waits, then reads the counters of the run in a slot (as sl_stats).
+ * SL_EINVAL for a slot not in use. */
+sl_status sl_batch_stats(sl_batch b, int32_t slot, sl_run_stats* out);
 
 /* Host view of the slots in use (no wait): fills up to cap entries. */
 sl_status sl_batch_runs(sl_batch b, sl_run_info* info, int32_t cap, int32_t* n_out);

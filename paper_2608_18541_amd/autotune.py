@@ -3,7 +3,8 @@
 The knobs are the colour-pass block size and sites per thread, the lattice
 kernels' block size, the number of steps captured per HIP graph replay and
 the block size of the persistent per-run kernel (0 keeps every run on the
-multi-kernel step) and the order of the work tables over the XCDs.
+multi-kernel step), the order of the work tables over the XCDs and where
+neighbours are binned.
 Every setting performs the same arithmetic for every site, atom and cell,
 so the tuner times real steps of the run being tuned: a coordinate search
 (one knob at a time, the others held) keeps the fastest setting, and the
@@ -23,6 +24,7 @@ KNOBS = {
     "spin_block": (64, 128, 256),
     "atom_block": (64, 128, 256),
     "xcd_order": (0, 1),
+    "bin_mode": (0, 1, 2),
 }
 
 _CACHE_FILE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2608_18541_amd",

@@ -7,9 +7,12 @@
 //
 // Per step, in stream order:
 //   k_spin_pass  x (2C-1)  colour sweep 0..C-1 (half steps), C-2..0, the
-//                          middle colour taking one full step
-//   k_kick_drift           half kick + drift, electron-cell id, skin check
-//   k_nbr_bin/sort/build   Verlet-list rebuild (exit at once unless flagged)
+//                          middle colour taking one full step; the launch of
+//                          pass 0 also carries the lattice's half kick +
+//                          drift, electron-cell id, skin check and binning
+//                          (they read no spin, and the cell ids of the new
+//                          positions go to the other of two buffers)
+//   k_nbr_build            Verlet-list rebuild (exits at once unless flagged)
 //   k_atom_final           Morse forces, half kick, electron-phonon
 //                          Ornstein-Uhlenbeck step and its mean energy per
 //                          electron cell, observable partials
@@ -30,6 +33,7 @@ namespace sl {
 
 constexpr int kBlock = 256;
 constexpr int NQ = 24;      // observable partial sums per wave of 64 atoms
+static_assert(NQ % 3 == 0, "samples reduce three quantities at a time");
 constexpr int kLdsCells = 2048;   // electron grids up to this size are summed in LDS
 
 enum { ERR_NEG_E = 1, ERR_BIN = 2, ERR_NBR = 4, ERR_DE = 8 };
@@ -44,7 +48,9 @@ struct RunState {
     int32_t bad_atom;    // first atom that overflowed a neighbour table (+1), for diagnostics
     int32_t bad_count;
     int64_t bad_step;
-    int64_t pad;
+    int64_t n_rebuild;   // Verlet-list builds so far, the initial one included
+    int32_t max_list;    // longest list built so far
+    int32_t bin_over;    // a bin overflowed while binning this step
 };
 
 // Wrapped absolute position of an atom, padded to a 16/32-byte vector so a
@@ -57,7 +63,7 @@ template <typename T> struct RunDev {
     Geom g;
     int32_t lattice, n, n_species, n_shells, live, ttm_mode, obs_every, obs_cap;
     int32_t noisy;       // some species has a thermal field (sig > 0)
-    int32_t pad0;
+    int32_t bin_step;    // 1: atoms are binned by the kick every step, 0: only for a rebuild
     uint32_t seed, run_id;
     T a, box[3], half_box[3];
     T alpha, dt, tau_half, inv1pa2, gam;
@@ -84,7 +90,7 @@ template <typename T> struct RunDev {
     T *sx, *sy, *sz, *ux, *uy, *uz, *vx, *vy, *vz, *fx, *fy, *fz, *rx, *ry, *rz;
     Pos4<T>* pos;                    // wrap(ideal site + u), refreshed by k_kick_drift
     int8_t* species;
-    uint16_t* cell;
+    uint16_t* cellb[2];              // electron-cell id of x^n in cellb[n & 1]
     int32_t *nbr, *nbr_n;
     int32_t *bin_n, *bin_atoms;      // [nbins], [nbins][bin_cap]
     double *Te, *ee, *Te_alt;        // T_e, energy density, diffusion ping-pong buffer
@@ -189,9 +195,11 @@ template <typename T, typename M, typename P> struct View {
 
 template <typename T> using GView = View<T, InGlobal, InGlobal>;
 
-template <typename T> __device__ inline GView<T> global_view(const RunDev<T>& R)
+// View of the run's global arrays with the electron-cell ids of x^n,
+// n & 1 == parity.
+template <typename T> __device__ inline GView<T> global_view(const RunDev<T>& R, int64_t parity)
 {
-    return GView<T>{R.sx, R.sy, R.sz, R.species, R.cell, R.pos, R.Te, R.partial};
+    return GView<T>{R.sx, R.sy, R.sz, R.species, R.cellb[parity & 1], R.pos, R.Te, R.partial};
 }
 
 template <typename T, typename VW>
@@ -531,6 +539,9 @@ __device__ __forceinline__ bool kick_drift_atom(const RunDev<T>& R, const VW& V,
     return far;
 }
 
+// Atom i into the bin of its wrapped position (any order within a bin).  An
+// overflow is only flagged: it is an error if the list is rebuilt from
+// these bins.
 template <typename T, typename VW>
 __device__ inline void nbr_bin_atom(const RunDev<T>& R, const VW& V, uint32_t i)
 {
@@ -538,19 +549,14 @@ __device__ inline void nbr_bin_atom(const RunDev<T>& R, const VW& V, uint32_t i)
     int b3[3];
     const int bin = bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     const int slot = atomicAdd(&R.bin_n[bin], 1);
-    if (slot < R.bin_cap) {
+    if (slot < R.bin_cap)
         R.bin_atoms[(size_t)bin * R.bin_cap + slot] = (int32_t)i;
-    } else {
-        if (atomicCAS(&R.st->bad_atom, 0, (int)i + 1) == 0) {
-            R.st->bad_count = slot + 1;
-            R.st->bad_step = R.st->step;
-        }
-        atomicOr(&R.st->err, ERR_BIN);
-    }
+    else
+        atomicOr(&R.st->bin_over, 1);
 }
 
-// Sorts a bin's atoms so that the neighbour order does not depend on the
-// order in which atoms were binned.
+// Sorts a bin's atoms by index (insertion sort of a short list); with every
+// bin sorted the list build takes each bin in order.
 template <typename T> __device__ inline void nbr_sort_bin(const RunDev<T>& R, int bin)
 {
     int cnt = R.bin_n[bin];
@@ -567,10 +573,22 @@ template <typename T> __device__ inline void nbr_sort_bin(const RunDev<T>& R, in
     }
 }
 
+// Raised by the list build when it finds an overflowed bin.
+template <typename T> __device__ inline void raise_bin_overflow(const RunDev<T>& R)
+{
+    if (atomicCAS(&R.st->bad_atom, 0, -1) == 0) {
+        R.st->bad_count = R.bin_cap;
+        R.st->bad_step = R.st->step;
+    }
+    atomicOr(&R.st->err, ERR_BIN);
+}
+
 // Verlet list of atom i: every atom within rc + skin in its own and the 26
-// surrounding bins, in bin order and ascending index within a bin.  The
-// list is stored column-major, entry q of atom i at nbr[q n + i].
-template <typename T, typename VW>
+// surrounding bins, bins in a fixed order and atoms in ascending index
+// within a bin (so the list, and the order of the force sum, do not depend
+// on the order in which atoms were binned).  The list is stored
+// column-major, entry q of atom i at nbr[q n + i].
+template <typename T, typename VW, bool SORTED_BINS = false>
 __device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t i)
 {
     const V3<T> ui{gld(R.ux, i), gld(R.uy, i), gld(R.uz, i)};
@@ -579,6 +597,7 @@ __device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t 
     bin_of(R, V3<T>{pi.x, pi.y, pi.z}, b3);
     int count = 0;
     const size_t n = (size_t)R.n;
+    int32_t* col = R.nbr + i;
     for (int dz = -1; dz <= 1; ++dz) {
         const int bz = wrapi(b3[2] + dz, R.nbin[2]);
         for (int dy = -1; dy <= 1; ++dy) {
@@ -589,18 +608,46 @@ __device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t 
                 int cnt = R.bin_n[bin];
                 cnt = cnt < R.bin_cap ? cnt : R.bin_cap;
                 const int32_t* a = R.bin_atoms + (size_t)bin * R.bin_cap;
-                for (int q = 0; q < cnt; ++q) {
-                    const int j = a[q];
-                    if (j == (int)i) continue;
-                    const V3<T> d = separation(R, V, pi, (uint32_t)j);
-                    if (d.x * d.x + d.y * d.y + d.z * d.z < R.rlist2) {
-                        if (count < R.max_nbr) R.nbr[(size_t)count * n + i] = j;
-                        ++count;
+                // the bin's atoms in ascending index (each chosen as the
+                // smallest entry above the last one taken; bins are filled in
+                // any order), four at a time: indices, then positions, then
+                // the distance tests (padding slots repeat atom i itself)
+                int last = -1;
+                for (int q0 = 0; q0 < cnt; q0 += 4) {
+                    int jj[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool ok = q0 + u < cnt;
+                        if (SORTED_BINS) {
+                            jj[u] = ok ? a[q0 + u] : (int)i;
+                            continue;
+                        }
+                        int best = 0x7fffffff;
+                        for (int q = 0; q < cnt; ++q) {
+                            const int v = a[q];
+                            best = (v > last && v < best) ? v : best;
+                        }
+                        jj[u] = ok ? best : (int)i;
+                        last = ok ? best : last;
+                    }
+                    V3<T> d[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) d[u] = separation(R, V, pi, (uint32_t)jj[u]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const T r2 = d[u].x * d[u].x + d[u].y * d[u].y + d[u].z * d[u].z;
+                        if (jj[u] != (int)i && r2 < R.rlist2) {
+                            if (count < R.max_nbr) col[(size_t)count * n] = jj[u];
+                            ++count;
+                        }
                     }
                 }
             }
         }
     }
+    // one address for all atoms: only counts above the value already seen
+    // reach the atomic (the maximum does not depend on which do)
+    if (count > *(volatile int32_t*)&R.st->max_list) atomicMax(&R.st->max_list, count);
     if (count > R.max_nbr) {
         if (atomicCAS(&R.st->bad_atom, 0, (int)i + 1) == 0) {
             R.st->bad_count = count;
@@ -829,10 +876,36 @@ __device__ inline void write_sample(const RunDev<T>& R, const VW& V, SampleScrat
 {
     const int tid = threadIdx.x;
     const int nc = R.ncell;
-    if (tid < NQ) {
-        double acc = 0.0;
-        for (int bk = 0; bk < R.n_part; ++bk) acc += V.partial[(size_t)bk * NQ + tid];
-        S.tot[tid] = acc;
+    // the per-wave rows: thread t sums rows t, t + 256, ... in order, then a
+    // fixed-shape tree over the threads, three quantities at a time
+    for (int q0 = 0; q0 < NQ; q0 += 3) {
+        if (tid < kBlock) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int bk = tid; bk < R.n_part; bk += kBlock) {
+                const double* row = V.partial + (size_t)bk * NQ + q0;
+                a0 += row[0];
+                a1 += row[1];
+                a2 += row[2];
+            }
+            S.red[0][tid] = a0;
+            S.red[1][tid] = a1;
+            S.red[2][tid] = a2;
+        }
+        __syncthreads();
+        for (int off = kBlock / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                S.red[0][tid] += S.red[0][tid + off];
+                S.red[1][tid] += S.red[1][tid + off];
+                S.red[2][tid] += S.red[2][tid + off];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            S.tot[q0] = S.red[0][0];
+            S.tot[q0 + 1] = S.red[1][0];
+            S.tot[q0 + 2] = S.red[2][0];
+        }
+        __syncthreads();
     }
     if (tid < kBlock) {
         double eacc = 0.0, tacc = 0.0, tmax = 0.0;
@@ -890,10 +963,31 @@ template <typename T> __device__ inline bool sample_due(const RunDev<T>& R, int 
 }
 
 // ==================================================== multi-kernel step
+// Colour pass `pass` over the sites of every active run.  Blocks from
+// n_spin_blocks on (the launch of pass 0 carries them when lattices are
+// live) take atoms instead: half kick, drift, the electron cell of the new
+// position (into the other cell buffer, so the spin blocks of this launch
+// still see the cells of x^n), the skin check and binning.  They read no
+// spin and the spin blocks read no lattice array.
 template <typename T, int SPT>
 __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
-                                                      const int2* __restrict__ work, int pass)
+                                                      const int2* __restrict__ work, int pass,
+                                                      const int2* __restrict__ work_kick,
+                                                      int n_spin_blocks)
 {
+    if ((int)blockIdx.x >= n_spin_blocks) {
+        const int2 w = work_kick[blockIdx.x - n_spin_blocks];
+        const RunDev<T>& R = runs[w.x];
+        int64_t step;
+        if (!run_active(R, &step) || !R.live) return;
+        const uint32_t i = (uint32_t)w.y + threadIdx.x;
+        if (i >= (uint32_t)R.n) return;
+        const GView<T> V = global_view(R, step + 1);
+        if (kick_drift_atom(R, V, i, PHASE_STEP) && *(volatile int32_t*)&R.st->rebuild == 0)
+            atomicOr(&R.st->rebuild, 1);
+        if (R.bin_step) nbr_bin_atom(R, V, i);
+        return;
+    }
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     int64_t step;
@@ -902,7 +996,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     int colour;
     T tau;
     pass_colour(R, pass, &colour, &tau);
-    const GView<T> V = global_view(R);
+    const GView<T> V = global_view(R, step);
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
@@ -910,52 +1004,80 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     }
 }
 
+// Kick and drift on their own: the initialisation phase (electron cells
+// and wrapped positions of the current positions).  At initialisation the
+// cell ids go to both buffers: a frozen lattice never rewrites them.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work, int phase)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
-    int64_t step;
+    int64_t step = R.st->step;
     if (phase == PHASE_STEP) {
         if (!run_active(R, &step) || !R.live) return;
     }
-    const int i = w.y + (int)threadIdx.x;
-    if (i >= R.n) return;
-    if (kick_drift_atom(R, global_view(R), i, phase)) atomicOr(&R.st->rebuild, 1);
+    const uint32_t i = (uint32_t)w.y + threadIdx.x;
+    if (i >= (uint32_t)R.n) return;
+    const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
+    if (kick_drift_atom(R, V, i, phase) && *(volatile int32_t*)&R.st->rebuild == 0)
+        atomicOr(&R.st->rebuild, 1);
+    if (phase == PHASE_INIT) gst(R.cellb[(step + 1) & 1], i, gld(R.cellb[step & 1], i));
 }
 
+// Binning on its own, for a rebuild: at initialisation, and every step for
+// runs whose kick does not bin (exits at once unless a rebuild is flagged).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict__ runs,
-                                                    const int2* __restrict__ work)
+                                                    const int2* __restrict__ work, int phase)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    const int i = w.y + (int)threadIdx.x;
-    if (i < R.n) nbr_bin_atom(R, global_view(R), i);
+    if (phase == PHASE_STEP && (R.bin_step || R.st->step >= R.st->target)) return;
+    const uint32_t i = (uint32_t)w.y + threadIdx.x;
+    if (i < (uint32_t)R.n) nbr_bin_atom(R, global_view(R, 0), i);
 }
 
+// Sorts the bins filled by k_nbr_bin for a rebuild (thread i of a run takes
+// bins i, i + n, ...): at initialisation, and in steps of runs whose kick
+// does not bin.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict__ runs,
-                                                     const int2* __restrict__ work)
+                                                     const int2* __restrict__ work, int phase)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    const int bin = w.y + (int)threadIdx.x;
-    if (bin < R.nbins) nbr_sort_bin(R, bin);
+    if (phase == PHASE_STEP && (R.bin_step || R.st->step >= R.st->target)) return;
+    for (uint32_t b = (uint32_t)w.y + threadIdx.x; b < (uint32_t)R.nbins; b += (uint32_t)R.n)
+        nbr_sort_bin(R, (int)b);
 }
 
+// The Verlet-list rebuild, when some atom moved more than half the skin
+// since its list was built.  Unsorted bins (filled by the kick) are read in
+// ascending order by selection, bins sorted by k_nbr_sort in turn: the same
+// list either way.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restrict__ runs,
-                                                      const int2* __restrict__ work)
+                                                      const int2* __restrict__ work,
+                                                      int sorted_bins)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    const int i = w.y + (int)threadIdx.x;
-    if (i < R.n) nbr_build_atom(R, global_view(R), i);
+    const bool first = w.y == 0 && threadIdx.x == 0;
+    if (R.st->bin_over) {
+        if (first) raise_bin_overflow(R);
+        return;
+    }
+    if (first) R.st->n_rebuild += 1;
+    const uint32_t i = (uint32_t)w.y + threadIdx.x;
+    if (i >= (uint32_t)R.n) return;
+    if (sorted_bins)
+        nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), i);
+    else
+        nbr_build_atom<T, GView<T>, false>(R, global_view(R, 0), i);
 }
 
 template <typename T>
@@ -969,6 +1091,13 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
     if (phase == PHASE_STEP) {
         if (!run_active(R, &step)) return;
     }
+    const uint32_t i = (uint32_t)w.y + threadIdx.x;
+    // the bins filled this step were read by the list build: empty them for
+    // the next binning
+    if (R.live && (R.bin_step || R.st->rebuild != 0 || phase == PHASE_INIT)) {
+        for (uint32_t b = i; b < (uint32_t)R.nbins; b += (uint32_t)R.n) R.bin_n[b] = 0;
+        if (i == 0) R.st->bin_over = 0;
+    }
     const bool obs = sample_due(R, phase, step);
     if (!R.live && !obs) return;
     // electron-phonon energy per cell: first summed in LDS (fixed point, so
@@ -979,18 +1108,17 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
         __syncthreads();
     }
-    const int i = w.y + (int)threadIdx.x;
     double q[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) q[k] = 0.0;
-    if (i < R.n)
-        atom_final_atom(R, global_view(R), i, phase, step, obs, lds_acc ? cacc : R.dE, q);
+    const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
+    if (i < (uint32_t)R.n) atom_final_atom(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, q);
     if (lds_acc) {
         __syncthreads();
         for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
             if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
     }
-    if (obs) wave_reduce_row(q, R.partial, i - (int)(threadIdx.x & 63), R.n);
+    if (obs) wave_reduce_row(q, R.partial, (int)i - (int)(threadIdx.x & 63), R.n);
 }
 
 template <typename T>
@@ -1019,8 +1147,8 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step);
 }
 
-// One block per run: small electron grids, the observable sample, bins
-// emptied after a rebuild, step + 1.
+// One block per run: small electron grids, the observable sample, the
+// rebuild flag cleared, step + 1.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
                                                      const int* __restrict__ run_list, int phase)
@@ -1036,14 +1164,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict
         __syncthreads();
     }
     if (sample_due(R, phase, step))
-        write_sample(R, global_view(R), S, phase == PHASE_INIT ? step : step + 1);
-    // neighbour bins are emptied after a rebuild, ready for the next one
-    if (R.live && st->rebuild != 0) {
-        for (int b = tid; b < R.nbins; b += blockDim.x) R.bin_n[b] = 0;
-        __syncthreads();
-        if (tid == 0) st->rebuild = 0;
+        write_sample(R, global_view(R, step), S, phase == PHASE_INIT ? step : step + 1);
+    if (tid == 0) {
+        if (R.live && st->rebuild != 0) st->rebuild = 0;
+        if (phase == PHASE_STEP) st->step = step + 1;
     }
-    if (tid == 0 && phase == PHASE_STEP) st->step = step + 1;
 }
 
 // ==================================================== persistent kernel
@@ -1102,11 +1227,12 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
     const int tid = threadIdx.x, B = blockDim.x;
     const int n = R.n, nc = R.ncell;
     // load the run into LDS
+    const uint16_t* cell_in = R.cellb[st->step & 1];
     for (int i = tid; i < n; i += B) {
         V.sx[i] = gld(R.sx, i);
         V.sy[i] = gld(R.sy, i);
         V.sz[i] = gld(R.sz, i);
-        V.cell[i] = gld(R.cell, i);
+        V.cell[i] = gld(cell_in, i);
         if (R.n_species > 1) const_cast<int8_t*>(V.species)[i] = gld(R.species, i);
         if (pos_in_lds) V.pos[i] = gld(R.pos, i);
     }
@@ -1146,10 +1272,14 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
             __syncthreads();
             if (P.flag_rebuild) {
                 for (int i = tid; i < n; i += B) nbr_bin_atom(R, V, (uint32_t)i);
+                __syncthreads();
+                if (tid == 0 && st->bin_over) raise_bin_overflow(R);
                 if (error_raised()) break;
+                if (tid == 0) st->n_rebuild += 1;
                 for (int b = tid; b < R.nbins; b += B) nbr_sort_bin(R, b);
                 __syncthreads();
-                for (int i = tid; i < n; i += B) nbr_build_atom(R, V, (uint32_t)i);
+                for (int i = tid; i < n; i += B)
+                    nbr_build_atom<T, VW, true>(R, V, (uint32_t)i);
                 if (error_raised()) break;
                 for (int b = tid; b < R.nbins; b += B) R.bin_n[b] = 0;
             }
@@ -1183,12 +1313,14 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
         ++step;
     }
     __syncthreads();
-    // write the run back
+    // write the run back (cell ids of the current positions to the buffer
+    // of the current step's parity)
+    uint16_t* cell_out = R.cellb[step & 1];
     for (int i = tid; i < n; i += B) {
         gst(R.sx, i, V.sx[i]);
         gst(R.sy, i, V.sy[i]);
         gst(R.sz, i, V.sz[i]);
-        gst(R.cell, i, V.cell[i]);
+        gst(cell_out, i, V.cell[i]);
         if (pos_in_lds) gst(R.pos, i, V.pos[i]);
     }
     for (int c = tid; c < nc; c += B) gst(R.Te, c, V.Te[c]);

@@ -263,6 +263,7 @@ template <typename T> size_t main_bytes(const sl_system_desc* d, const Sizes& z)
     }
     if (live) c.take<sl::Pos4<T>>(n);
     c.take<int8_t>(n);
+    c.take<uint16_t>(n);                                            // cell ids, two buffers
     c.take<uint16_t>(n);
     c.take<double>((size_t)z.n_part * sl::NQ);
     c.take<sl_obs>((size_t)std::max(1, d->obs_capacity));
@@ -305,6 +306,7 @@ public:
     virtual sl_status set_state(int slot, const double* x, const double* v, const double* s,
                                 const double* Te) = 0;
     virtual sl_status remove(int slot) = 0;
+    virtual sl_status stats(int slot, sl_run_stats* out) = 0;
     virtual sl_status sync() = 0;
     virtual sl_status profiled(int64_t n, double avg[5], int64_t cnt[5]) = 0;
     std::vector<Run> runs;
@@ -319,6 +321,7 @@ public:
     int spin_block = 256, spin_spt = 1, atom_block = 256;
     int persist_block = 0;          // 0: every run on the multi-kernel step
     int xcd_ord = 0;                // 1: XCD-contiguous work tables
+    int bin_mode = 0;               // 0 automatic, 1 kick bins every step, 2 rebuild only
     virtual sl_status retune() = 0;
 };
 
@@ -672,6 +675,21 @@ public:
         return commit_and_init(s);
     }
 
+    sl_status stats(int s, sl_run_stats* out) override
+    {
+        if (s < 0 || s >= (int)runs.size() || !runs[s].used) return fail(SL_EINVAL, "bad slot");
+        if (!out) return fail(SL_EINVAL, "null output");
+        SL_HIP(hipStreamSynchronize(stream));
+        sl::RunState rs;
+        SL_HIP(hipMemcpy(&rs, host_rd[s].st, sizeof(rs), hipMemcpyDeviceToHost));
+        out->steps = rs.step;
+        out->samples = rs.n_samples;
+        out->list_rebuilds = rs.n_rebuild;
+        out->max_list = rs.max_list;
+        out->list_capacity = host_rd[s].live ? host_rd[s].max_nbr : 0;
+        return SL_OK;
+    }
+
     sl_status remove(int s) override
     {
         if (s < 0 || s >= (int)runs.size() || !runs[s].used) return fail(SL_EINVAL, "bad slot");
@@ -709,12 +727,12 @@ private:
     std::vector<void*> tables;
     int2* d_work_spin = nullptr;
     int2* d_work_atom = nullptr;
-    int2* d_work_bin = nullptr;
+    int2* d_work_kick = nullptr;     // atoms of live runs, in tiles of spin_block
     int2* d_work_cell = nullptr;
     int2* d_work_diff = nullptr;
     int* d_run_list = nullptr;
     int active_runs = 0;
-    int active_blocks_spin = 0, active_blocks_atom = 0, active_blocks_bin = 0, active_blocks_cell = 0,
+    int active_blocks_spin = 0, active_blocks_atom = 0, active_blocks_kick = 0, active_blocks_cell = 0,
         active_blocks_diff = 0;
     int max_sub = 0;
     bool any_live = false;
@@ -727,6 +745,11 @@ private:
     uint32_t lds_max = 0;
     int* d_persist_list = nullptr;
     int persist_runs = 0;
+    // the kick bins every step while the engine's live atoms are few (one
+    // atomic per atom costs less than a launch); above that a separate
+    // binning launch works only when a list is rebuilt
+    static constexpr int64_t kBinEachStepMaxAtoms = int64_t(1) << 20;
+    bool bin_each_step = true;
     uint32_t persist_bytes = 0;
 
     sl_status numeric_error(int s, int err)
@@ -857,7 +880,8 @@ private:
         }
         if (R.live) R.pos = c.take<sl::Pos4<T>>(n);
         R.species = c.take<int8_t>(n);
-        R.cell = c.take<uint16_t>(n);
+        R.cellb[0] = c.take<uint16_t>(n);
+        R.cellb[1] = c.take<uint16_t>(n);
         R.n_part = r.z.n_part;
         R.partial = c.take<double>((size_t)r.z.n_part * sl::NQ);
         R.ring = c.take<sl_obs>((size_t)R.obs_cap);
@@ -978,26 +1002,21 @@ private:
         SL_HIP(hipMemsetAsync(R.dE, 0, sizeof(unsigned long long) * r.z.ncell, stream));
         SL_HIP(hipMemcpyAsync(d_runs + s, &R, sizeof(RD), hipMemcpyHostToDevice, stream));
         // single-run work tables for the initialisation launches
-        std::vector<int2> wa, wb, wc;
+        std::vector<int2> wa;
         for (int st = 0; st < R.n; st += sl::kBlock) wa.push_back(make_int2(s, st));
-        for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2(s, st));
-        void* tmp = alloc.get(sizeof(int2) * (wa.size() + wb.size() + wc.size()) + 512);
+        void* tmp = alloc.get(sizeof(int2) * wa.size() + 512);
         if (!tmp) return fail(SL_ENOMEM, "device allocation failed");
         int2* dwa = static_cast<int2*>(tmp);
-        int2* dwb = dwa + wa.size();
-        int2* dwc = dwb + wb.size();
-        int* drl = reinterpret_cast<int*>(dwc + wc.size());
+        int* drl = reinterpret_cast<int*>(dwa + wa.size());
         const int one = s;
         SL_HIP(hipMemcpyAsync(drl, &one, sizeof(int), hipMemcpyHostToDevice, stream));
         SL_HIP(hipMemcpyAsync(dwa, wa.data(), sizeof(int2) * wa.size(), hipMemcpyHostToDevice, stream));
-        if (!wb.empty())
-            SL_HIP(hipMemcpyAsync(dwb, wb.data(), sizeof(int2) * wb.size(), hipMemcpyHostToDevice, stream));
         const int ga = (int)wa.size();
         sl::k_kick_drift<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
         if (R.live) {
-            sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
-            sl::k_nbr_sort<T><<<(R.nbins + sl::kBlock - 1) / sl::kBlock, sl::kBlock, 0, stream>>>(d_runs, dwb);
-            sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
+            sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
+            sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
+            sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, 1);
         }
         sl::k_atom_final<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
         sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
@@ -1016,7 +1035,7 @@ private:
     {
         drop_graph();
         tables_dirty = false;
-        std::vector<int2> ws, wa, wb, wc, wd;
+        std::vector<int2> ws, wa, wk, wc, wd;
         std::vector<int> rl;
         any_live = false;
         max_sub = 0;
@@ -1036,7 +1055,8 @@ private:
             }
             for (int st = 0; st < R.g.H; st += spin_block * spin_spt) ws.push_back(make_int2((int)s, st));
             for (int st = 0; st < R.n; st += atom_block) wa.push_back(make_int2((int)s, st));
-            for (int st = 0; st < R.nbins; st += sl::kBlock) wb.push_back(make_int2((int)s, st));
+            if (R.live)
+                for (int st = 0; st < R.n; st += spin_block) wk.push_back(make_int2((int)s, st));
             if (R.ttm_mode == 1 && R.ncell > sl::kSmallGrid)
                 for (int st = 0; st < R.ncell; st += sl::kBlock) wc.push_back(make_int2((int)s, st));
             rl.push_back((int)s);
@@ -1049,13 +1069,25 @@ private:
         if (xcd_ord) {
             xcd_order(ws);
             xcd_order(wa);
+            xcd_order(wk);
+        }
+        int64_t live_atoms = 0;
+        for (int2 t : wk) live_atoms += std::min<int64_t>(spin_block, host_rd[t.x].n - t.y);
+        bin_each_step = bin_mode == 1 || (bin_mode == 0 && live_atoms <= kBinEachStepMaxAtoms);
+        for (size_t s = 0; s < runs.size(); ++s) {
+            if (!runs[s].used) continue;
+            const int32_t want = bin_each_step ? 1 : 0;
+            if (host_rd[s].bin_step != want) {
+                host_rd[s].bin_step = want;
+                SL_HIP(hipMemcpyAsync(d_runs + s, &host_rd[s], sizeof(RD), hipMemcpyHostToDevice, stream));
+            }
         }
         for (void* p : tables) alloc.put(p);
         tables.clear();
-        d_work_spin = d_work_atom = d_work_bin = d_work_cell = d_work_diff = nullptr;
+        d_work_spin = d_work_atom = d_work_kick = d_work_cell = d_work_diff = nullptr;
         active_blocks_spin = (int)ws.size();
         active_blocks_atom = (int)wa.size();
-        active_blocks_bin = (int)wb.size();
+        active_blocks_kick = (int)wk.size();
         active_blocks_cell = (int)wc.size();
         active_blocks_diff = (int)wd.size();
         active_runs = (int)rl.size();
@@ -1074,7 +1106,7 @@ private:
         sl_status st;
         if ((st = up(ws.data(), sizeof(int2) * ws.size(), (void**)&d_work_spin)) != SL_OK) return st;
         if ((st = up(wa.data(), sizeof(int2) * wa.size(), (void**)&d_work_atom)) != SL_OK) return st;
-        if ((st = up(wb.data(), sizeof(int2) * wb.size(), (void**)&d_work_bin)) != SL_OK) return st;
+        if ((st = up(wk.data(), sizeof(int2) * wk.size(), (void**)&d_work_kick)) != SL_OK) return st;
         if ((st = up(wc.data(), sizeof(int2) * wc.size(), (void**)&d_work_cell)) != SL_OK) return st;
         if ((st = up(wd.data(), sizeof(int2) * wd.size(), (void**)&d_work_diff)) != SL_OK) return st;
         if ((st = up(rl.data(), sizeof(int) * rl.size(), (void**)&d_run_list)) != SL_OK) return st;
@@ -1108,35 +1140,50 @@ private:
         return SL_OK;
     }
 
+    // One step of every run on the multi-kernel path.  Profiling classes:
+    // 0 colour pass, 1 force / e-ph kernel, 2 colour pass 0 carrying the
+    // lattice kick and drift, 3 list build, electron grid and end of step.
     sl_status enqueue_step(hipStream_t st, Prof* p)
     {
         const int C = max_colours();
         const dim3 bs(spin_block), ba(atom_block), bk(sl::kBlock);
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
-            sl_status e = timed(st, p, 0, [&](hipEvent_t a, hipEvent_t b) {
-                const dim3 g(active_blocks_spin);
+            const bool fused = pass == 0 && active_blocks_kick > 0;
+            const int nk = fused ? active_blocks_kick : 0;
+            sl_status e = timed(st, p, fused ? 2 : 0, [&](hipEvent_t a, hipEvent_t b) {
+                const dim3 g(active_blocks_spin + nk);
                 if (spin_spt == 4)
-                    launch(sl::k_spin_pass<T, 4>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass);
+                    launch(sl::k_spin_pass<T, 4>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
+                           d_work_kick, active_blocks_spin);
                 else if (spin_spt == 2)
-                    launch(sl::k_spin_pass<T, 2>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass);
+                    launch(sl::k_spin_pass<T, 2>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
+                           d_work_kick, active_blocks_spin);
                 else
-                    launch(sl::k_spin_pass<T, 1>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass);
+                    launch(sl::k_spin_pass<T, 1>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
+                           d_work_kick, active_blocks_spin);
             });
             if (e != SL_OK) return e;
         }
         const dim3 ga(active_blocks_atom);
-        if (any_live) {
-            sl_status e = timed(st, p, 2, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_kick_drift<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       (int)sl::PHASE_STEP);
+        sl_status e;
+        if (active_blocks_kick > 0 && !bin_each_step) {
+            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_nbr_bin<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
             });
             if (e != SL_OK) return e;
-            sl::k_nbr_bin<T><<<ga, ba, 0, st>>>(d_runs, d_work_atom);
-            if (active_blocks_bin > 0)
-                sl::k_nbr_sort<T><<<active_blocks_bin, bk, 0, st>>>(d_runs, d_work_bin);
-            sl::k_nbr_build<T><<<ga, ba, 0, st>>>(d_runs, d_work_atom);
+            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_nbr_sort<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
+            });
+            if (e != SL_OK) return e;
         }
-        sl_status e = timed(st, p, 1, [&](hipEvent_t a, hipEvent_t b) {
+        if (active_blocks_kick > 0) {
+            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_nbr_build<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                       bin_each_step ? 0 : 1);
+            });
+            if (e != SL_OK) return e;
+        }
+        e = timed(st, p, 1, [&](hipEvent_t a, hipEvent_t b) {
             launch(sl::k_atom_final<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
         });
         if (e != SL_OK) return e;
@@ -1295,6 +1342,12 @@ sl_status sl_set_state(sl_system h, const double* x, const double* v, const doub
     return h->eng->set_state(0, x, v, s, Te);
 }
 
+sl_status sl_stats(sl_system h, sl_run_stats* out)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    return h->eng->stats(0, out);
+}
+
 sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* steps)
 {
     if (!h) return fail(SL_EINVAL, "null handle");
@@ -1316,12 +1369,14 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     if (t->persist_block != 0 && t->persist_block != 256 && t->persist_block != 512)
         return fail(SL_EINVAL, "persist_block must be 0, 256 or 512");
     if (t->xcd_order != 0 && t->xcd_order != 1) return fail(SL_EINVAL, "xcd_order must be 0 or 1");
+    if (t->bin_mode < 0 || t->bin_mode > 2) return fail(SL_EINVAL, "bin_mode must be 0, 1 or 2");
     e->spin_block = t->spin_block;
     e->spin_spt = t->spin_spt;
     e->atom_block = t->atom_block;
     e->graph_steps = t->graph_steps;
     e->persist_block = t->persist_block;
     e->xcd_ord = t->xcd_order;
+    e->bin_mode = t->bin_mode;
     return e->retune();
 }
 
@@ -1333,6 +1388,7 @@ static void get_tuning(const Engine* e, sl_tuning* t)
     t->graph_steps = e->graph_steps;
     t->persist_block = e->persist_block;
     t->xcd_order = e->xcd_ord;
+    t->bin_mode = e->bin_mode;
 }
 
 sl_status sl_set_tuning(sl_system h, const sl_tuning* t)
@@ -1436,6 +1492,12 @@ sl_status sl_batch_remove(sl_batch b, int32_t slot)
 {
     if (!b) return fail(SL_EINVAL, "null handle");
     return b->eng->remove(slot);
+}
+
+sl_status sl_batch_stats(sl_batch b, int32_t slot, sl_run_stats* out)
+{
+    if (!b) return fail(SL_EINVAL, "null handle");
+    return b->eng->stats(slot, out);
 }
 
 sl_status sl_batch_memory(sl_batch b, size_t* used, size_t* budget)

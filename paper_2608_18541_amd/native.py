@@ -80,7 +80,15 @@ class sl_batch_desc(C.Structure):
 class sl_tuning(C.Structure):
     _fields_ = [("spin_block", C.c_int32), ("spin_spt", C.c_int32), ("atom_block", C.c_int32),
                 ("graph_steps", C.c_int32), ("persist_block", C.c_int32),
-                ("xcd_order", C.c_int32)]
+                ("xcd_order", C.c_int32), ("bin_mode", C.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class sl_run_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("samples", C.c_int64), ("list_rebuilds", C.c_int64),
+                ("max_list", C.c_int32), ("list_capacity", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -103,6 +111,8 @@ EXPORTS = {
                                    C.POINTER(C.c_int64)]),
     "sl_get_state": (C.c_int32, [C.c_void_p] + [C.POINTER(C.c_double)] * 4),
     "sl_set_state": (C.c_int32, [C.c_void_p] + [C.POINTER(C.c_double)] * 4),
+    "sl_stats": (C.c_int32, [C.c_void_p, C.POINTER(sl_run_stats)]),
+    "sl_batch_stats": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(sl_run_stats)]),
     "sl_info": (C.c_int32, [C.c_void_p] + [C.POINTER(C.c_int64)] * 3),
     "sl_footprint_bytes": (C.c_int32, [C.POINTER(sl_system_desc), C.POINTER(sl_ttm_desc),
                                        C.POINTER(C.c_size_t)]),
@@ -319,6 +329,12 @@ class System:
         check(lib().sl_get_state(self._h, _dp(x), _dp(v), _dp(s), _dp(Te)))
         return {"x": x, "v": v, "s": s, "Te": Te}
 
+    def stats(self) -> dict:
+        """Device-side counters: steps, samples, list rebuilds, longest list."""
+        out = sl_run_stats()
+        check(lib().sl_stats(self._h, C.byref(out)))
+        return out.to_dict()
+
     def set_state(self, x=None, v=None, s=None, Te=None) -> None:
         """Replaces any of positions, velocities, spins and the electron grid
         (canonical order); the step counter and the noise stream continue."""
@@ -433,6 +449,11 @@ class Batch:
         t = sl_tuning()
         check(lib().sl_batch_get_tuning(self._h, C.byref(t)))
         return t.to_dict()
+
+    def stats(self, slot: int) -> dict:
+        out = sl_run_stats()
+        check(lib().sl_batch_stats(self._h, int(slot), C.byref(out)))
+        return out.to_dict()
 
     def advance_profiled(self, n: int):
         avg = (C.c_double * 5)()

@@ -192,17 +192,19 @@ def test_launch_shapes_are_bitwise_identical(N):
         b = N.Batch(precision=prec, max_runs=4)
         slots = [b.add(sp, st, 10_000) for sp, st in runs]
         shapes = [dict(spin_block=64, spin_spt=4, atom_block=128, graph_steps=8, persist_block=0,
-                       xcd_order=1),
+                       xcd_order=1, bin_mode=2),
                   dict(spin_block=128, spin_spt=2, atom_block=64, graph_steps=32,
-                       persist_block=512, xcd_order=0),
+                       persist_block=512, xcd_order=0, bin_mode=1),
                   dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=1,
-                       persist_block=256, xcd_order=1)]
+                       persist_block=0, xcd_order=1, bin_mode=2),
+                  dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=16,
+                       persist_block=256, xcd_order=0, bin_mode=0)]
         for sh in shapes:
             b.set_tuning(**sh)
             b.advance(17)
         best = autotune(b, steps=8, use_cache=False)
         assert set(best) == {"spin_block", "spin_spt", "atom_block", "graph_steps",
-                             "persist_block", "xcd_order"}
+                             "persist_block", "xcd_order", "bin_mode"}
         info = {r["slot"]: r["steps_done"] for r in b.runs()}
         for (sp, st), s in zip(runs, slots):
             alone = N.System(sp, st, precision=prec)

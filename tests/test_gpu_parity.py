@@ -230,3 +230,28 @@ def test_set_state_restores_a_checkpoint(N):
         b.set_state(Te=-np.ones_like(ck["Te"]))
     a.close()
     b.close()
+
+
+def test_run_stats_counters(N):
+    """Device counters: steps, samples, list builds (the initial one
+    included), the longest list within capacity; a frozen lattice builds no
+    list.  The same counters through a batch slot."""
+    spec = I.gdfeco_sc_spec(L=8, tn=2, S0=0.3, t0=0.002, fwhm=0.002, seed=5, run_id=1)
+    g = N.System(spec, I.initial_state(spec, "afm"), precision=0, obs_every=10)
+    g.step(55)
+    st = g.stats()
+    assert st["steps"] == 55 and st["samples"] == 1 + 5
+    assert st["list_rebuilds"] >= 1 and 0 < st["max_list"] <= st["list_capacity"]
+    g.close()
+    fz = I.fe_bcc_spec(L=4, lattice_mode=0, seed=8, run_id=10)
+    f = N.System(fz, I.initial_state(fz, "tilt"), precision=1)
+    f.step(7)
+    sf = f.stats()
+    assert sf["steps"] == 7 and sf["list_rebuilds"] == 0 and sf["list_capacity"] == 0
+    f.close()
+    b = N.Batch(precision=1, max_runs=2)
+    slot = b.add(spec, I.initial_state(spec, "afm"), 30)
+    b.advance(40)
+    sb = b.stats(slot)
+    assert sb["steps"] == 30 and sb["list_rebuilds"] >= 1
+    b.close()

@@ -74,7 +74,9 @@ int main(void) {
   printf("sl_batch_desc size %zu\n", sizeof(sl_batch_desc));
   P(sl_batch_desc, mem_budget) P(sl_batch_desc, alloc)
   printf("sl_tuning size %zu\n", sizeof(sl_tuning));
-  P(sl_tuning, graph_steps) P(sl_tuning, persist_block) P(sl_tuning, xcd_order)
+  P(sl_tuning, graph_steps) P(sl_tuning, persist_block) P(sl_tuning, xcd_order) P(sl_tuning, bin_mode)
+  printf("sl_run_stats size %zu\n", sizeof(sl_run_stats));
+  P(sl_run_stats, list_rebuilds) P(sl_run_stats, max_list) P(sl_run_stats, list_capacity)
   printf("sl_run_info size %zu\n", sizeof(sl_run_info));
   P(sl_run_info, steps_done) P(sl_run_info, n_samples)
   return 0;
@@ -92,7 +94,8 @@ def test_ctypes_layout_matches_c():
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
     types = {"sl_system_desc": N.sl_system_desc, "sl_ttm_desc": N.sl_ttm_desc,
              "sl_obs": N.sl_obs, "sl_batch_desc": N.sl_batch_desc,
-             "sl_run_info": N.sl_run_info, "sl_tuning": N.sl_tuning}
+             "sl_run_info": N.sl_run_info, "sl_tuning": N.sl_tuning,
+             "sl_run_stats": N.sl_run_stats}
     for line in out.strip().splitlines():
         t, f, v = line.split()
         if f == "size":
