@@ -209,10 +209,11 @@ sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
 /* Runs n_steps (at most 4096) launching every kernel directly, each timed
  * by HIP events stamped by its own dispatch; returns the average device time
  * (ms) per launch of each kernel class and the launch counts: 0 spin colour
- * pass, 1 lattice force and electron-phonon step, 2 colour pass 0 carrying
- * the lattice's kick, drift and binning (live lattices), 3 neighbour-list
- * build, electron grid and end-of-step reductions, 4 persistent kernel (one
- * launch for all steps). */
+ * pass, 1 neighbour-list rebuild (when due), lattice forces and
+ * electron-phonon step, 2 colour pass 0 carrying the lattice's kick, drift
+ * and binning (live lattices), 3 binning for a rebuild (large engines),
+ * electron grid and end-of-step reductions, 4 persistent kernel (one launch
+ * for all steps). */
 sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5]);
 
 /* Launch shape of the step kernels.  Every choice performs the same

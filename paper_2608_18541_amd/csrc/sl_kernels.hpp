@@ -12,8 +12,10 @@
 //                          drift, electron-cell id, skin check and binning
 //                          (they read no spin, and the cell ids of the new
 //                          positions go to the other of two buffers)
-//   k_nbr_build            Verlet-list rebuild (exits at once unless flagged)
-//   k_atom_final           Morse forces, half kick, electron-phonon
+//   k_nbr_bin, k_nbr_sort  binning for a rebuild (large engines; exit at
+//                          once unless a rebuild is flagged)
+//   k_atom_final           Verlet-list rebuild of its own atoms when flagged,
+//                          Morse forces, half kick, electron-phonon
 //                          Ornstein-Uhlenbeck step and its mean energy per
 //                          electron cell, observable partials
 //   k_ttm_diffuse x n_sub  explicit electron diffusion sub-steps (runs with
@@ -1080,9 +1082,15 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
         nbr_build_atom<T, GView<T>, false>(R, global_view(R, 0), i);
 }
 
+// Forces, the second half kick, the electron-phonon step and the
+// observable rows.  In a step whose kick flagged a rebuild, each block first
+// rebuilds the lists of its own atoms: positions and bins are final after
+// the kick, and an atom's forces read only its own list.  `sorted_bins`
+// tells how the bins were filled (unsorted by the kick, or sorted).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
-                                                       const int2* __restrict__ work, int phase)
+                                                       const int2* __restrict__ work, int phase,
+                                                       int sorted_bins)
 {
     __shared__ unsigned long long cacc[kLdsCells];
     const int2 w = work[blockIdx.x];
@@ -1092,11 +1100,19 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         if (!run_active(R, &step)) return;
     }
     const uint32_t i = (uint32_t)w.y + threadIdx.x;
-    // the bins filled this step were read by the list build: empty them for
-    // the next binning
-    if (R.live && (R.bin_step || R.st->rebuild != 0 || phase == PHASE_INIT)) {
-        for (uint32_t b = i; b < (uint32_t)R.nbins; b += (uint32_t)R.n) R.bin_n[b] = 0;
-        if (i == 0) R.st->bin_over = 0;
+    if (phase == PHASE_STEP && R.live && R.st->rebuild != 0) {
+        const bool first = w.y == 0 && threadIdx.x == 0;
+        if (R.st->bin_over) {
+            if (first) raise_bin_overflow(R);
+            return;
+        }
+        if (first) R.st->n_rebuild += 1;
+        if (i < (uint32_t)R.n) {
+            if (sorted_bins)
+                nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), i);
+            else
+                nbr_build_atom<T, GView<T>, false>(R, global_view(R, 0), i);
+        }
     }
     const bool obs = sample_due(R, phase, step);
     if (!R.live && !obs) return;
@@ -1147,8 +1163,8 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step);
 }
 
-// One block per run: small electron grids, the observable sample, the
-// rebuild flag cleared, step + 1.
+// One block per run: small electron grids, the observable sample, the bins
+// emptied and the rebuild flag cleared, step + 1.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
                                                      const int* __restrict__ run_list, int phase)
@@ -1165,8 +1181,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict
     }
     if (sample_due(R, phase, step))
         write_sample(R, global_view(R, step), S, phase == PHASE_INIT ? step : step + 1);
+    // the bins filled this step have been read by the list build: empty them
+    // for the next binning
+    if (R.live && (R.bin_step || st->rebuild != 0 || phase == PHASE_INIT))
+        for (int b = tid; b < R.nbins; b += blockDim.x) R.bin_n[b] = 0;
     if (tid == 0) {
-        if (R.live && st->rebuild != 0) st->rebuild = 0;
+        if (R.live) {
+            st->bin_over = 0;
+            st->rebuild = 0;
+        }
         if (phase == PHASE_STEP) st->step = step + 1;
     }
 }

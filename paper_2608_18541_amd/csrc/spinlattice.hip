@@ -1018,7 +1018,7 @@ private:
             sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
             sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, 1);
         }
-        sl::k_atom_final<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
+        sl::k_atom_final<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1);
         sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
         SL_HIP(hipGetLastError());
         SL_HIP(hipStreamSynchronize(stream));
@@ -1141,8 +1141,9 @@ private:
     }
 
     // One step of every run on the multi-kernel path.  Profiling classes:
-    // 0 colour pass, 1 force / e-ph kernel, 2 colour pass 0 carrying the
-    // lattice kick and drift, 3 list build, electron grid and end of step.
+    // 0 colour pass, 1 list rebuild (when flagged) and force / e-ph kernel,
+    // 2 colour pass 0 carrying the lattice kick and drift, 3 binning for a
+    // rebuild, electron grid and end of step.
     sl_status enqueue_step(hipStream_t st, Prof* p)
     {
         const int C = max_colours();
@@ -1176,15 +1177,9 @@ private:
             });
             if (e != SL_OK) return e;
         }
-        if (active_blocks_kick > 0) {
-            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_build<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       bin_each_step ? 0 : 1);
-            });
-            if (e != SL_OK) return e;
-        }
         e = timed(st, p, 1, [&](hipEvent_t a, hipEvent_t b) {
-            launch(sl::k_atom_final<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
+            launch(sl::k_atom_final<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
+                   bin_each_step ? 0 : 1);
         });
         if (e != SL_OK) return e;
         for (int sub = 0; sub < max_sub; ++sub) {

@@ -215,3 +215,59 @@ def test_launch_shapes_are_bitwise_identical(N):
                 assert np.array_equal(a[k], g[k]), (prec, s, k)
             alone.close()
         b.close()
+
+
+def test_full_phase_diagram_batch_sampled_runs(N):
+    """The full 1280-run phase-diagram batch (16^3 alloys, the bench's launch
+    configuration: persistent executor, FP32) for 60 steps: sampled runs
+    from corners and the middle of the grid equal the same runs alone, bit
+    for bit, and every run advanced exactly 60 steps."""
+    from paper_2608_18541_amd import workloads as W
+    runs = W.phase_diagram(L=16, n_seeds=20, n_steps=60)
+    b = N.Batch(precision=1, max_runs=len(runs))
+    slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=8) for r in runs]
+    _log("full batch: %d runs" % len(runs))
+    b.advance(60)
+    info = b.runs()
+    assert len(info) == 1280 and all(r["steps_done"] == 60 for r in info)
+    for k in (0, 639, 1279):
+        g = b.get(slots[k])
+        alone = N.System(runs[k].spec, runs[k].state, precision=1, obs_every=20, obs_capacity=8)
+        alone.step(60)
+        a = alone.state()
+        for key in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[key], g[key]), (k, key)
+        oa = alone.observables()
+        assert [o["E_ex"] for o in oa] == [o["E_ex"] for o in g["obs"]]
+        alone.close()
+    b.close()
+
+
+def test_large_bcc_fp32_invariants(N):
+    """bcc Fe 64^3 (524288 atoms) with surface heating, FP32 as the bench
+    runs it, through at least one list rebuild: unit spins, finite state,
+    counters, and FP32 tracking FP64 over the first 20 steps."""
+    spec = I.fe_large_spec()
+    st = I.initial_state(spec, "tilt")
+    g32 = N.System(spec, st, precision=1, obs_every=10, obs_capacity=64)
+    g64 = N.System(spec, st, precision=0, obs_every=10, obs_capacity=64)
+    g32.step(20)
+    g64.step(20)
+    a, c = g32.state(), g64.state()
+    assert np.abs(np.linalg.norm(a["s"], axis=1) - 1.0).max() < 1e-6
+    # FP32 vs FP64 is a statistical comparison: the typical site differs by
+    # float rounding (about 1e-7 after 20 steps); a few sites amplify it
+    ds = np.abs(a["s"] - c["s"])
+    assert np.sqrt((ds ** 2).mean()) < 1e-5 and ds.max() < 1e-2
+    vr = np.sqrt((c["v"] ** 2).mean())
+    dv = np.abs(a["v"] - c["v"])
+    assert np.sqrt((dv ** 2).mean()) < 1e-5 * vr and dv.max() < 1e-2 * vr
+    g32.step(480)
+    s = g32.stats()
+    assert s["steps"] == 500 and s["list_rebuilds"] >= 1
+    assert 0 < s["max_list"] <= s["list_capacity"]
+    fin = g32.state()
+    assert np.all(np.isfinite(fin["x"])) and np.all(np.isfinite(fin["v"]))
+    assert np.abs(np.linalg.norm(fin["s"], axis=1) - 1.0).max() < 1e-6
+    g32.close()
+    g64.close()
