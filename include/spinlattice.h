@@ -224,10 +224,11 @@ typedef struct sl_tuning {
     int32_t spin_spt;         /* sites per thread in a colour pass: 1, 2, 4          */
     int32_t atom_block;       /* threads per block of the lattice kernels: 64..256   */
     int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256         */
-    int32_t persist_block;    /* 0: all runs on the multi-kernel step; 256 or 512:
-                                 runs that fit in LDS advance in a persistent kernel,
-                                 one block of this many threads per run (batches
-                                 default to 512, single systems to 0)               */
+    int32_t persist_block;    /* 0: all runs on the multi-kernel step; 256, 512 or
+                                 1024: runs that fit in LDS advance in a persistent
+                                 kernel, one block of this many threads per run
+                                 (batches default to 1024 in FP32 and 512 in FP64,
+                                 single systems to 0)                               */
     int32_t xcd_order;        /* 1: work tables ordered so that each of the 8 XCDs
                                  receives one contiguous range of tiles (its L2
                                  then holds their neighbours); 0: round-robin    */

@@ -18,7 +18,7 @@ import time
 from typing import Dict, List, Optional
 
 KNOBS = {
-    "persist_block": (0, 256, 512),
+    "persist_block": (0, 256, 512, 1024),
     "graph_steps": (8, 16, 32, 64),
     "spin_spt": (1, 2, 4),
     "spin_block": (64, 128, 256),

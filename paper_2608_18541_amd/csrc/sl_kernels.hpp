@@ -664,14 +664,38 @@ __device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t 
     gst(R.rz, i, ui.z);
 }
 
+// An atom's contribution to an observable sample.  The NQ slots of a row are
+// derived from it one at a time (obs_slot), so a wave never holds all of
+// them at once.
+struct ObsTerms {
+    double s0, s1, s2;   // spin
+    double eex, ez;      // exchange (bonds once) and Zeeman energy, eV
+    double ke, pe;       // kinetic and Morse energy, eV
+    double num, den;     // |s x h_tot|^2 and s . h_tot of the spin temperature
+    int sp;              // species
+};
+
+// Slot k of a row: species-resolved spin sums (0-11), energies (12-15),
+// spin-temperature numerators (16-19) and denominators (20-23).
+__device__ __forceinline__ double obs_slot(const ObsTerms& o, int k)
+{
+    if (k < 12) return o.sp == k / 3 ? (k % 3 == 0 ? o.s0 : (k % 3 == 1 ? o.s1 : o.s2)) : 0.0;
+    if (k == 12) return o.eex;
+    if (k == 13) return o.ez;
+    if (k == 14) return o.ke;
+    if (k == 15) return o.pe;
+    if (k < 20) return o.sp == k - 16 ? o.num : 0.0;
+    return o.sp == k - 20 ? o.den : 0.0;
+}
+
 // Forces on atom i at the new positions, the second half kick, the
 // electron-phonon Ornstein-Uhlenbeck step (its mean energy added to `acc`
 // of the atom's cell, fixed point) and, on sample steps, the atom's
-// observable terms q[NQ].
+// observable terms.
 template <typename T, typename VW>
 __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V, uint32_t i,
                                                 int phase, int64_t step, bool obs,
-                                                unsigned long long* acc, double* q)
+                                                unsigned long long* acc, ObsTerms& o)
 {
     using M = typename VW::Mem;
     const Site si = decode_site(R.g, i);
@@ -755,8 +779,8 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
         gst(R.fy, i, Fy);
         gst(R.fz, i, Fz);
         if (obs) {
-            q[14] = 0.5 * (double)me * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
-            q[15] = pe;
+            o.ke = 0.5 * (double)me * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+            o.pe = pe;
         }
     }
     if (obs) {
@@ -767,43 +791,34 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
         const V3<T> h = exchange_sum(R, V, si.k, a, sp);
         const double h0 = h.x, h1 = h.y, h2 = h.z;
         const double mb = select4(sp, R.mumb[0], R.mumb[1], R.mumb[2], R.mumb[3]);
-        q[12] = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
-        q[13] = -mb * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
+        o.eex = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
+        o.ez = -mb * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
         const double t0 = h0 + mb * R.Bd[0];
         const double t1 = h1 + mb * R.Bd[1];
         const double t2 = h2 + mb * R.Bd[2];
         const double c0 = s1 * t2 - s2 * t1, c1 = s2 * t0 - s0 * t2, c2 = s0 * t1 - s1 * t0;
-        const double num = c0 * c0 + c1 * c1 + c2 * c2;
-        const double den = s0 * t0 + s1 * t1 + s2 * t2;
-        // per-species slots with compile-time indices (kept in registers)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const bool me2 = sp == t;
-            q[3 * t + 0] = me2 ? s0 : 0.0;
-            q[3 * t + 1] = me2 ? s1 : 0.0;
-            q[3 * t + 2] = me2 ? s2 : 0.0;
-            q[16 + t] = me2 ? num : 0.0;
-            q[20 + t] = me2 ? den : 0.0;
-        }
+        o.num = c0 * c0 + c1 * c1 + c2 * c2;
+        o.den = s0 * t0 + s1 * t1 + s2 * t2;
+        o.s0 = s0;
+        o.s1 = s1;
+        o.s2 = s2;
+        o.sp = sp;
     }
 }
 
-// Fixed-order wave reduction of NQ doubles; lane 0 writes the row of the
-// wave's 64 consecutive atoms (row = first atom / 64), so samples do not
-// depend on the block size.
-__device__ inline void wave_reduce_row(double* q, double* partial, int i_first, int n)
+// Fixed-order wave reduction of the row slots, one slot at a time; lane 0
+// writes the row of the wave's 64 consecutive atoms (row = first atom / 64),
+// so samples do not depend on the block size.
+__device__ inline void wave_write_row(const ObsTerms& o, double* partial, int i_first, int n)
 {
+    double* row = partial + (size_t)(i_first >> 6) * NQ;
+    const bool writer = (threadIdx.x & 63) == 0 && i_first < n;
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-        double x = q[k];
+        double x = obs_slot(o, k);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-        q[k] = x;
-    }
-    if ((threadIdx.x & 63) == 0 && i_first < n) {
-        double* row = partial + (size_t)(i_first >> 6) * NQ;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) row[k] = q[k];
+        if (writer) row[k] = x;
     }
 }
 
@@ -1124,17 +1139,15 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
         __syncthreads();
     }
-    double q[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+    ObsTerms o{};
     const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
-    if (i < (uint32_t)R.n) atom_final_atom(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, q);
+    if (i < (uint32_t)R.n) atom_final_atom(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, o);
     if (lds_acc) {
         __syncthreads();
         for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
             if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
     }
-    if (obs) wave_reduce_row(q, R.partial, (int)i - (int)(threadIdx.x & 63), R.n);
+    if (obs) wave_write_row(o, R.partial, (int)i - (int)(threadIdx.x & 63), R.n);
 }
 
 template <typename T>
@@ -1312,11 +1325,9 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
         if (R.live || obs) {
             for (int base = 0; base < n; base += B) {
                 const int i = base + tid;
-                double q[NQ];
-#pragma unroll
-                for (int k = 0; k < NQ; ++k) q[k] = 0.0;
-                if (i < n) atom_final_atom(R, V, (uint32_t)i, PHASE_STEP, step, obs, acc, q);
-                if (obs) wave_reduce_row(q, V.partial, i - (tid & 63), n);
+                ObsTerms o{};
+                if (i < n) atom_final_atom(R, V, (uint32_t)i, PHASE_STEP, step, obs, acc, o);
+                if (obs) wave_write_row(o, V.partial, i - (tid & 63), n);
             }
         }
         if (error_raised()) break;
@@ -1353,10 +1364,12 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(512) void k_persist(const RunDev<T>* __restrict__ runs,
-                                                  const int* __restrict__ run_list, int nsteps,
-                                                  uint32_t lds_max)
+// MAXT: the largest block the instantiation is compiled for (512: up to 256
+// registers per lane; 1024: up to 128, with some spilling).
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_persist(const RunDev<T>* __restrict__ runs,
+                                                   const int* __restrict__ run_list, int nsteps,
+                                                   uint32_t lds_max)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ PersistShared P;

@@ -358,11 +358,17 @@ public:
         int dev = 0, per_block = 0;
         SL_HIP(hipGetDevice(&dev));
         SL_HIP(hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        hipFuncAttributes fa{};
-        SL_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&sl::k_persist<T>)));
-        lds_max = per_block > (int)fa.sharedSizeBytes ? (uint32_t)(per_block - (int)fa.sharedSizeBytes) : 0u;
-        SL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&sl::k_persist<T>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
+        const void* pk[2] = {reinterpret_cast<const void*>(&sl::k_persist<T, 512>),
+                             reinterpret_cast<const void*>(&sl::k_persist<T, 1024>)};
+        int static_lds = 0;
+        for (const void* f : pk) {
+            hipFuncAttributes fa{};
+            SL_HIP(hipFuncGetAttributes(&fa, f));
+            static_lds = std::max(static_lds, (int)fa.sharedSizeBytes);
+        }
+        lds_max = per_block > static_lds ? (uint32_t)(per_block - static_lds) : 0u;
+        for (const void* f : pk)
+            SL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
         return SL_OK;
     }
 
@@ -452,8 +458,12 @@ public:
             SL_HIP(hipStreamWaitEvent(side_stream, ev_fork, 0));
             for (int64_t done = 0; done < n; done += kPersistChunk) {
                 const int k = (int)std::min<int64_t>(kPersistChunk, n - done);
-                sl::k_persist<T><<<persist_runs, persist_block, persist_bytes, side_stream>>>(
-                    d_runs, d_persist_list, k, lds_max);
+                if (persist_block > 512)
+                    sl::k_persist<T, 1024><<<persist_runs, persist_block, persist_bytes, side_stream>>>(
+                        d_runs, d_persist_list, k, lds_max);
+                else
+                    sl::k_persist<T, 512><<<persist_runs, persist_block, persist_bytes, side_stream>>>(
+                        d_runs, d_persist_list, k, lds_max);
             }
             SL_HIP(hipGetLastError());
             SL_HIP(hipEventRecord(ev_join, side_stream));
@@ -489,8 +499,12 @@ public:
         Prof p{&ev, &cls};
         if (persist_runs > 0) {
             sl_status st = timed(stream, &p, 4, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_persist<T>, dim3(persist_runs), dim3(persist_block), persist_bytes, stream,
-                       a, b, d_runs, d_persist_list, (int)n, lds_max);
+                if (persist_block > 512)
+                    launch(sl::k_persist<T, 1024>, dim3(persist_runs), dim3(persist_block), persist_bytes,
+                           stream, a, b, d_runs, d_persist_list, (int)n, lds_max);
+                else
+                    launch(sl::k_persist<T, 512>, dim3(persist_runs), dim3(persist_block), persist_bytes,
+                           stream, a, b, d_runs, d_persist_list, (int)n, lds_max);
             });
             if (st != SL_OK) return st;
         }
@@ -1361,8 +1375,9 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     if (!blk_ok) return fail(SL_EINVAL, "block sizes must be 64, 128 or 256");
     if (t->spin_spt != 1 && t->spin_spt != 2 && t->spin_spt != 4) return fail(SL_EINVAL, "spin_spt must be 1, 2 or 4");
     if (t->graph_steps < 1 || t->graph_steps > 256) return fail(SL_EINVAL, "graph_steps must be 1..256");
-    if (t->persist_block != 0 && t->persist_block != 256 && t->persist_block != 512)
-        return fail(SL_EINVAL, "persist_block must be 0, 256 or 512");
+    if (t->persist_block != 0 && t->persist_block != 256 && t->persist_block != 512 &&
+        t->persist_block != 1024)
+        return fail(SL_EINVAL, "persist_block must be 0, 256, 512 or 1024");
     if (t->xcd_order != 0 && t->xcd_order != 1) return fail(SL_EINVAL, "xcd_order must be 0 or 1");
     if (t->bin_mode < 0 || t->bin_mode > 2) return fail(SL_EINVAL, "bin_mode must be 0, 1 or 2");
     e->spin_block = t->spin_block;
@@ -1425,7 +1440,7 @@ sl_status sl_batch_create(const sl_batch_desc* desc, sl_batch* out)
     sl_status st = setup_engine(b->eng.get(), desc->precision, desc->stream, desc->alloc,
                                 desc->mem_budget, desc->graph_steps);
     if (st != SL_OK) return st;
-    b->eng->persist_block = 512;
+    b->eng->persist_block = desc->precision == SL_FP32 ? 1024 : 512;
     *out = b.release();
     return SL_OK;
 }

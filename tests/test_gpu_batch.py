@@ -198,7 +198,9 @@ def test_launch_shapes_are_bitwise_identical(N):
                   dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=1,
                        persist_block=0, xcd_order=1, bin_mode=2),
                   dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=16,
-                       persist_block=256, xcd_order=0, bin_mode=0)]
+                       persist_block=256, xcd_order=0, bin_mode=0),
+                  dict(spin_block=128, spin_spt=1, atom_block=128, graph_steps=8,
+                       persist_block=1024, xcd_order=0, bin_mode=0)]
         for sh in shapes:
             b.set_tuning(**sh)
             b.advance(17)
