@@ -1,9 +1,9 @@
 // sl_kernels.hpp -- HIP kernels of one spin-lattice timestep (gfx950).
 //
 // Every launch covers all active runs of an engine: block b reads
-// work[b] = {run, first item} and works on 256 consecutive items of that
-// run, so one run alone and the same run inside a batch execute identical
-// arithmetic in identical order (bitwise-equal trajectories).
+// work[b] = {run, first item} and works on a tile of consecutive items of
+// that run, so one run alone and the same run inside a batch execute
+// identical arithmetic in identical order (bitwise-equal trajectories).
 //
 // Per step, in stream order:
 //   k_spin_pass  x (2C-1)  colour sweep 0..C-1 (half steps), C-2..0, the
@@ -25,7 +25,9 @@
 //   k_finalize             one block per run: small grids, the observable
 //                          sample, the step counter
 // or, for runs small enough to live in LDS, k_persist: one block per run
-// advancing many steps in one launch.
+// advancing many steps in one launch.  A run is initialised (and restored
+// from a checkpoint) by k_init_lattice, k_nbr_bin, k_nbr_sort, k_nbr_build,
+// k_atom_final and k_finalize in their initialisation phase.
 #pragma once
 
 #include "sl_device.hpp"
@@ -1021,25 +1023,21 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     }
 }
 
-// Kick and drift on their own: the initialisation phase (electron cells
-// and wrapped positions of the current positions).  At initialisation the
-// cell ids go to both buffers: a frozen lattice never rewrites them.
+// Initialisation of the lattice arrays of one run: electron cells and
+// wrapped positions of the current positions, the cell ids into both
+// buffers (a frozen lattice never rewrites them).  In steps the kick is
+// carried by colour pass 0.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_kick_drift(const RunDev<T>* __restrict__ runs,
-                                                       const int2* __restrict__ work, int phase)
+__global__ __launch_bounds__(kBlock) void k_init_lattice(const RunDev<T>* __restrict__ runs,
+                                                         const int2* __restrict__ work)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
-    int64_t step = R.st->step;
-    if (phase == PHASE_STEP) {
-        if (!run_active(R, &step) || !R.live) return;
-    }
+    const int64_t step = R.st->step;
     const uint32_t i = (uint32_t)w.y + threadIdx.x;
     if (i >= (uint32_t)R.n) return;
-    const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
-    if (kick_drift_atom(R, V, i, phase) && *(volatile int32_t*)&R.st->rebuild == 0)
-        atomicOr(&R.st->rebuild, 1);
-    if (phase == PHASE_INIT) gst(R.cellb[(step + 1) & 1], i, gld(R.cellb[step & 1], i));
+    kick_drift_atom(R, global_view(R, step), i, PHASE_INIT);
+    gst(R.cellb[(step + 1) & 1], i, gld(R.cellb[step & 1], i));
 }
 
 // Binning on its own, for a rebuild: at initialisation, and every step for
@@ -1071,14 +1069,11 @@ __global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict
         nbr_sort_bin(R, (int)b);
 }
 
-// The Verlet-list rebuild, when some atom moved more than half the skin
-// since its list was built.  Unsorted bins (filled by the kick) are read in
-// ascending order by selection, bins sorted by k_nbr_sort in turn: the same
-// list either way.
+// The initial Verlet-list build (from bins sorted by k_nbr_sort); in steps
+// the lists are rebuilt by k_atom_final.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restrict__ runs,
-                                                      const int2* __restrict__ work,
-                                                      int sorted_bins)
+                                                      const int2* __restrict__ work)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
@@ -1090,11 +1085,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
     }
     if (first) R.st->n_rebuild += 1;
     const uint32_t i = (uint32_t)w.y + threadIdx.x;
-    if (i >= (uint32_t)R.n) return;
-    if (sorted_bins)
-        nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), i);
-    else
-        nbr_build_atom<T, GView<T>, false>(R, global_view(R, 0), i);
+    if (i < (uint32_t)R.n) nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), i);
 }
 
 // Forces, the second half kick, the electron-phonon step and the

@@ -1026,11 +1026,11 @@ private:
         SL_HIP(hipMemcpyAsync(drl, &one, sizeof(int), hipMemcpyHostToDevice, stream));
         SL_HIP(hipMemcpyAsync(dwa, wa.data(), sizeof(int2) * wa.size(), hipMemcpyHostToDevice, stream));
         const int ga = (int)wa.size();
-        sl::k_kick_drift<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT);
+        sl::k_init_lattice<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         if (R.live) {
             sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
             sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
-            sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, 1);
+            sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         }
         sl::k_atom_final<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1);
         sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
