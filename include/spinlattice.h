@@ -220,7 +220,9 @@ sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64
  * arithmetic in the same order for each site, atom and cell, so results are
  * bitwise identical; only the speed changes (an autotuner picks it). */
 typedef struct sl_tuning {
-    int32_t spin_block;       /* threads per block of the colour passes: 64, 128, 256 */
+    int32_t spin_block;       /* threads per block of the colour passes: 64, 128,
+                                 256, or 0 automatic (the largest giving at least
+                                 256 blocks per pass)                          */
     int32_t spin_spt;         /* sites per thread in a colour pass: 1, 2, 4          */
     int32_t atom_block;       /* threads per block of the lattice kernels: 64..256   */
     int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256         */
@@ -235,6 +237,13 @@ typedef struct sl_tuning {
     int32_t bin_mode;         /* neighbour binning: 1 by the kick every step, 2 by a
                                  separate launch only when a list is rebuilt, 0
                                  automatic (1 up to 2^20 live atoms)             */
+    int32_t atom_lanes;       /* lanes sharing one atom's neighbour list in the
+                                 force kernel: 1, 2 or 4 (atom_block / atom_lanes
+                                 atoms per block, at least 64), 0 automatic (4 up
+                                 to 2^16 atoms on the multi-kernel step, 2 up to
+                                 2^17, then 1).  The pair sums are four
+                                 interleaved partial sums over the list in every
+                                 case, hence the same bits                   */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of

@@ -3,8 +3,8 @@
 The knobs are the colour-pass block size and sites per thread, the lattice
 kernels' block size, the number of steps captured per HIP graph replay and
 the block size of the persistent per-run kernel (0 keeps every run on the
-multi-kernel step), the order of the work tables over the XCDs and where
-neighbours are binned.
+multi-kernel step), the order of the work tables over the XCDs, where
+neighbours are binned and how many lanes share an atom's neighbour list.
 Every setting performs the same arithmetic for every site, atom and cell,
 so the tuner times real steps of the run being tuned: a coordinate search
 (one knob at a time, the others held) keeps the fastest setting, and the
@@ -21,8 +21,9 @@ KNOBS = {
     "persist_block": (0, 256, 512, 1024),
     "graph_steps": (8, 16, 32, 64),
     "spin_spt": (1, 2, 4),
-    "spin_block": (64, 128, 256),
+    "spin_block": (0, 64, 128, 256),
     "atom_block": (64, 128, 256),
+    "atom_lanes": (0, 1, 2, 4),
     "xcd_order": (0, 1),
     "bin_mode": (0, 1, 2),
 }
@@ -57,6 +58,13 @@ def _time_steps(target, steps: int) -> float:
     return (time.perf_counter() - t0) / steps
 
 
+def valid(t: dict) -> bool:
+    """Whether a setting is accepted by the library (a block of the force
+    kernel covers at least 64 atoms)."""
+    lanes = t.get("atom_lanes", 0)
+    return lanes == 0 or t.get("atom_block", 256) // lanes >= 64
+
+
 def _steps_for(t: dict, steps: int) -> int:
     g = t["graph_steps"]
     return (max(steps, g) + g - 1) // g * g
@@ -82,6 +90,10 @@ def autotune(target, key: Optional[str] = None, steps: int = 64, rounds: int = 2
                 continue
             trial = dict(best)
             trial[knob] = v
+            if knob == "atom_lanes" and not valid(trial):
+                trial["atom_block"] = 64 * v
+            if not valid(trial):
+                continue
             tb, tt = [], []
             for _ in range(rounds):
                 for cfg, acc in ((best, tb), (trial, tt)):

@@ -592,8 +592,19 @@ template <typename T> __device__ inline void raise_bin_overflow(const RunDev<T>&
 // within a bin (so the list, and the order of the force sum, do not depend
 // on the order in which atoms were binned).  The list is stored
 // column-major, entry q of atom i at nbr[q n + i].
+// Verlet list of atom i: the 27 bins around it in a fixed order, each bin's
+// atoms within r_list in ascending index, so the list does not depend on
+// the order in which atoms entered the bins.  From sorted bins the atoms
+// are appended as scanned; from unsorted bins (binned by atomics) a bin's
+// accepted atoms are kept sorted in a small per-thread LDS buffer and
+// appended when the bin is done (in windows of kBinKeep when it holds more).
+// `keep` (unsorted bins only) is the thread's buffer in LDS: slot t at
+// keep[t * kBlock], so the threads of a wave touch consecutive words.
+constexpr int kBinKeep = 16;
+
 template <typename T, typename VW, bool SORTED_BINS = false>
-__device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t i)
+__device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t i,
+                                      int* keep = nullptr)
 {
     const V3<T> ui{gld(R.ux, i), gld(R.uy, i), gld(R.uz, i)};
     const Pos4<T> pi = VW::PosMem::ld(V.pos, i);
@@ -602,6 +613,10 @@ __device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t 
     int count = 0;
     const size_t n = (size_t)R.n;
     int32_t* col = R.nbr + i;
+    auto append = [&](int jv) {
+        if (count < R.max_nbr) col[(size_t)count * n] = jv;
+        ++count;
+    };
     for (int dz = -1; dz <= 1; ++dz) {
         const int bz = wrapi(b3[2] + dz, R.nbin[2]);
         for (int dy = -1; dy <= 1; ++dy) {
@@ -612,39 +627,50 @@ __device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t 
                 int cnt = R.bin_n[bin];
                 cnt = cnt < R.bin_cap ? cnt : R.bin_cap;
                 const int32_t* a = R.bin_atoms + (size_t)bin * R.bin_cap;
-                // the bin's atoms in ascending index (each chosen as the
-                // smallest entry above the last one taken; bins are filled in
-                // any order), four at a time: indices, then positions, then
-                // the distance tests (padding slots repeat atom i itself)
-                int last = -1;
-                for (int q0 = 0; q0 < cnt; q0 += 4) {
-                    int jj[4];
+                // candidates four at a time: indices, then positions, then the
+                // distance tests (padding slots repeat atom i itself).  Unsorted:
+                // a pass keeps the kBinKeep smallest accepted indices above
+                // `lo` in ascending order and appends them; a bin with more
+                // accepted atoms is scanned again above the last one appended.
+                int lo = -1;
+                for (bool more = true; more;) {
+                    int m = 0, mtot = 0;
+                    for (int q0 = 0; q0 < cnt; q0 += 4) {
+                        int jj[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const bool ok = q0 + u < cnt;
-                        if (SORTED_BINS) {
-                            jj[u] = ok ? a[q0 + u] : (int)i;
-                            continue;
+                        for (int u = 0; u < 4; ++u) jj[u] = q0 + u < cnt ? a[q0 + u] : (int)i;
+                        V3<T> d[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) d[u] = separation(R, V, pi, (uint32_t)jj[u]);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const T r2 = d[u].x * d[u].x + d[u].y * d[u].y + d[u].z * d[u].z;
+                            if (jj[u] == (int)i || !(r2 < R.rlist2)) continue;
+                            if (SORTED_BINS) {
+                                append(jj[u]);
+                                continue;
+                            }
+                            if (jj[u] <= lo) continue;
+                            ++mtot;
+                            if (m == kBinKeep &&
+                                jj[u] > sld(keep, (uint32_t)(kBinKeep - 1) * kBlock))
+                                continue;
+                            // insertion into the ascending keep[0..m); when
+                            // full, the largest entry drops out
+                            int t = m < kBinKeep ? m : kBinKeep - 1;
+                            for (; t > 0; --t) {
+                                const int prev = sld(keep, (uint32_t)(t - 1) * kBlock);
+                                if (prev < jj[u]) break;
+                                sst(keep, (uint32_t)t * kBlock, prev);
+                            }
+                            sst(keep, (uint32_t)t * kBlock, jj[u]);
+                            m += m < kBinKeep ? 1 : 0;
                         }
-                        int best = 0x7fffffff;
-                        for (int q = 0; q < cnt; ++q) {
-                            const int v = a[q];
-                            best = (v > last && v < best) ? v : best;
-                        }
-                        jj[u] = ok ? best : (int)i;
-                        last = ok ? best : last;
                     }
-                    V3<T> d[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) d[u] = separation(R, V, pi, (uint32_t)jj[u]);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const T r2 = d[u].x * d[u].x + d[u].y * d[u].y + d[u].z * d[u].z;
-                        if (jj[u] != (int)i && r2 < R.rlist2) {
-                            if (count < R.max_nbr) col[(size_t)count * n] = jj[u];
-                            ++count;
-                        }
-                    }
+                    if (SORTED_BINS) break;
+                    for (int t = 0; t < m; ++t) append(sld(keep, (uint32_t)t * kBlock));
+                    more = mtot > kBinKeep;
+                    if (more) lo = sld(keep, (uint32_t)(kBinKeep - 1) * kBlock);
                 }
             }
         }
@@ -690,32 +716,87 @@ __device__ __forceinline__ double obs_slot(const ObsTerms& o, int k)
     return o.sp == k - 20 ? o.den : 0.0;
 }
 
+// Lane exchange inside aligned groups of four lanes (DPP quad permutation:
+// MASK 1 swaps neighbours, MASK 2 swaps pairs).
+template <int MASK> __device__ __forceinline__ uint32_t quad_xor_u32(uint32_t v)
+{
+    static_assert(MASK == 1 || MASK == 2, "quad lane masks");
+    constexpr int ctrl = MASK == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+}
+template <int MASK> __device__ __forceinline__ float quad_xor(float v)
+{
+    return __builtin_bit_cast(float, quad_xor_u32<MASK>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int MASK> __device__ __forceinline__ double quad_xor(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = quad_xor_u32<MASK>((uint32_t)b);
+    const uint64_t hi = quad_xor_u32<MASK>((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
+// Pair sums over an atom's Verlet list are defined as four interleaved
+// partial sums -- entry k goes to partial k mod 4, in ascending k -- folded
+// as (p0 + p1) + (p2 + p3).  One lane may hold all four partials, or LPA
+// lanes of a quad hold 4/LPA each (lane j of the group: partials j, j + LPA,
+// ...): the sums, and so every result, are bitwise the same for LPA = 1, 2
+// and 4.  `p` holds this lane's partials; every lane of the group returns
+// the folded sum.
+template <int LPA, typename X> __device__ __forceinline__ X fold_partials(const X (&p)[4 / LPA])
+{
+    if constexpr (LPA == 1) {
+        return (p[0] + p[1]) + (p[2] + p[3]);
+    } else if constexpr (LPA == 2) {
+        // lane 0 holds p0, p2 and lane 1 holds p1, p3 (addition commutes, so
+        // both lanes form the same bits)
+        return (p[0] + quad_xor<1>(p[0])) + (p[1] + quad_xor<1>(p[1]));
+    } else {
+        const X s = p[0] + quad_xor<1>(p[0]);   // p0 + p1 on lanes 0, 1; p2 + p3 on 2, 3
+        return s + quad_xor<2>(s);
+    }
+}
+
 // Forces on atom i at the new positions, the second half kick, the
 // electron-phonon Ornstein-Uhlenbeck step (its mean energy added to `acc`
 // of the atom's cell, fixed point) and, on sample steps, the atom's
-// observable terms.
-template <typename T, typename VW>
+// observable terms.  LPA lanes of a quad share the atom (lane `j` of the
+// group): they split its neighbour list, fold the pair sums, and then all
+// compute the rest while only lane 0 stores.
+template <typename T, typename VW, int LPA = 1>
 __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V, uint32_t i,
                                                 int phase, int64_t step, bool obs,
-                                                unsigned long long* acc, ObsTerms& o)
+                                                unsigned long long* acc, ObsTerms& o, int j = 0)
 {
+    static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    constexpr int NA = 4 / LPA;   // partial sums held by one lane
     using M = typename VW::Mem;
+    const bool lead = j == 0;
     const Site si = decode_site(R.g, i);
     const int sp = species_of(R, V, i);
     if (R.live) {
         const Pos4<T> pi = VW::PosMem::ld(V.pos, i);
-        T Fx = T(0), Fy = T(0), Fz = T(0);
-        double pe = 0.0;
+        T px[NA], py[NA], pz[NA];
+        double ppe[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            px[a] = py[a] = pz[a] = T(0);
+            ppe[a] = 0.0;
+        }
         const int nn = gld(R.nbr_n, i);
         const size_t n = (size_t)R.n;
-        // neighbours in chunks of 8: all index loads, then all position
-        // loads, then the arithmetic (two memory round trips per chunk);
-        // column q of the list starts at nbr + q n (uniform per wave)
-        for (int k0 = 0; k0 < nn; k0 += 8) {
+        // this lane's entries k = j, j + LPA, ... in chunks of 8: all index
+        // loads, then all position loads, then the arithmetic (two memory
+        // round trips per chunk); column k of the list starts at nbr + k n.
+        // Entry q of a chunk goes to partial (k mod 4), which is this lane's
+        // slot q mod NA.
+        for (int k0 = j; k0 < nn; k0 += 8 * LPA) {
             uint32_t jj[8];
 #pragma unroll
-            for (int q8 = 0; q8 < 8; ++q8)
-                jj[q8] = k0 + q8 < nn ? (uint32_t)gld(R.nbr + (size_t)(k0 + q8) * n, i) : i;
+            for (int q8 = 0; q8 < 8; ++q8) {
+                const int k = k0 + q8 * LPA;
+                jj[q8] = k < nn ? (uint32_t)gld(R.nbr + (size_t)k * n, i) : i;
+            }
             T dx[8], dy[8], dz[8];
 #pragma unroll
             for (int q8 = 0; q8 < 8; ++q8) {
@@ -726,21 +807,24 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
             }
 #pragma unroll
             for (int q8 = 0; q8 < 8; ++q8) {
+                const int a = q8 % NA;
                 const T r2 = dx[q8] * dx[q8] + dy[q8] * dy[q8] + dz[q8] * dz[q8];
-                if (k0 + q8 < nn && r2 < R.rc2) {
+                if (k0 + q8 * LPA < nn && r2 < R.rc2) {
                     T r;
                     // -dV/dr along +d pushes j; the force on i is its opposite
                     const T f = morse_f(r2, R.ma, R.mD, R.mr0, &r);
-                    Fx -= f * dx[q8];
-                    Fy -= f * dy[q8];
-                    Fz -= f * dz[q8];
+                    px[a] -= f * dx[q8];
+                    py[a] -= f * dy[q8];
+                    pz[a] -= f * dz[q8];
                     if (obs) {
                         const double e1 = exp(-(double)R.ma * ((double)r - (double)R.mr0));
-                        pe += 0.5 * ((double)R.mD * (e1 * e1 - 2.0 * e1) - (double)R.Vc);
+                        ppe[a] += 0.5 * ((double)R.mD * (e1 * e1 - 2.0 * e1) - (double)R.Vc);
                     }
                 }
             }
         }
+        const T Fx = fold_partials<LPA>(px), Fy = fold_partials<LPA>(py), Fz = fold_partials<LPA>(pz);
+        const double pe = obs ? fold_partials<LPA>(ppe) : 0.0;
         T vx = gld(R.vx, i), vy = gld(R.vy, i), vz = gld(R.vz, i);
         const T me = select4(sp, R.m_e[0], R.m_e[1], R.m_e[2], R.m_e[3]);
         if (phase == PHASE_STEP) {
@@ -765,21 +849,25 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
                 const double dE = R.ou_1mc2 * (1.5 * kKB * Te - ke);
                 if (fabs(dE) < 1.0e3) {
                     const long long fixp = llrint(dE * kFIX);
-                    atomicAdd(&acc[c], (unsigned long long)fixp);
-                } else {
+                    if (lead) atomicAdd(&acc[c], (unsigned long long)fixp);
+                } else if (lead) {
                     atomicOr(&R.st->err, ERR_DE);
                 }
                 vx = nx;
                 vy = ny;
                 vz = nz;
             }
-            gst(R.vx, i, vx);
-            gst(R.vy, i, vy);
-            gst(R.vz, i, vz);
+            if (lead) {
+                gst(R.vx, i, vx);
+                gst(R.vy, i, vy);
+                gst(R.vz, i, vz);
+            }
         }
-        gst(R.fx, i, Fx);
-        gst(R.fy, i, Fy);
-        gst(R.fz, i, Fz);
+        if (lead) {
+            gst(R.fx, i, Fx);
+            gst(R.fy, i, Fy);
+            gst(R.fz, i, Fz);
+        }
         if (obs) {
             o.ke = 0.5 * (double)me * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
             o.pe = pe;
@@ -879,43 +967,50 @@ __device__ inline void cell_update(const RunDev<T>& R, double* Te, unsigned long
     Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
 }
 
+
 constexpr int kSmallGrid = 4096;   // larger electron grids update cell-parallel
 
-// The observable sample of a run, computed by threads 0..255 of one block
-// (the others idle): per-wave partial rows in order, electron-grid sums in
-// a fixed-shape tree.  `step_of_sample` is the step the sample describes.
+// The observable sample of a run, computed by one block of any size: per-wave
+// partial rows in order, electron-grid sums in a fixed-shape tree.
+// `step_of_sample` is the step the sample describes.  `go` and `step` carry
+// the run's state read once for the whole block.
 struct SampleScratch {
     double red[3][kBlock];
     double tot[NQ];
+    int64_t step;
+    int32_t go, rebuild;
 };
 
 template <typename T, typename VW>
 __device__ inline void write_sample(const RunDev<T>& R, const VW& V, SampleScratch& S,
                                     int64_t step_of_sample)
 {
-    const int tid = threadIdx.x;
+    // kBlock virtual threads whatever the block size (vt = tid, tid + B, ...),
+    // so the order of every sum is that of a 256-thread block
+    const int tid = threadIdx.x, B = blockDim.x;
     const int nc = R.ncell;
-    // the per-wave rows: thread t sums rows t, t + 256, ... in order, then a
-    // fixed-shape tree over the threads, three quantities at a time
+    // the per-wave rows: virtual thread t sums rows t, t + 256, ... in order,
+    // then a fixed-shape tree over the virtual threads, three quantities at
+    // a time
     for (int q0 = 0; q0 < NQ; q0 += 3) {
-        if (tid < kBlock) {
+        for (int vt = tid; vt < kBlock; vt += B) {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            for (int bk = tid; bk < R.n_part; bk += kBlock) {
+            for (int bk = vt; bk < R.n_part; bk += kBlock) {
                 const double* row = V.partial + (size_t)bk * NQ + q0;
                 a0 += row[0];
                 a1 += row[1];
                 a2 += row[2];
             }
-            S.red[0][tid] = a0;
-            S.red[1][tid] = a1;
-            S.red[2][tid] = a2;
+            S.red[0][vt] = a0;
+            S.red[1][vt] = a1;
+            S.red[2][vt] = a2;
         }
         __syncthreads();
         for (int off = kBlock / 2; off > 0; off >>= 1) {
-            if (tid < off) {
-                S.red[0][tid] += S.red[0][tid + off];
-                S.red[1][tid] += S.red[1][tid + off];
-                S.red[2][tid] += S.red[2][tid + off];
+            for (int vt = tid; vt < off; vt += B) {
+                S.red[0][vt] += S.red[0][vt + off];
+                S.red[1][vt] += S.red[1][vt + off];
+                S.red[2][vt] += S.red[2][vt + off];
             }
             __syncthreads();
         }
@@ -926,24 +1021,24 @@ __device__ inline void write_sample(const RunDev<T>& R, const VW& V, SampleScrat
         }
         __syncthreads();
     }
-    if (tid < kBlock) {
+    for (int vt = tid; vt < kBlock; vt += B) {
         double eacc = 0.0, tacc = 0.0, tmax = 0.0;
-        for (int c = tid; c < nc; c += kBlock) {
+        for (int c = vt; c < nc; c += kBlock) {
             const double Tc = V.Te[c];
             eacc += 0.5 * R.gamma_e * Tc * Tc * R.Vcell;
             tacc += Tc;
             tmax = Tc > tmax ? Tc : tmax;
         }
-        S.red[0][tid] = eacc;
-        S.red[1][tid] = tacc;
-        S.red[2][tid] = tmax;
+        S.red[0][vt] = eacc;
+        S.red[1][vt] = tacc;
+        S.red[2][vt] = tmax;
     }
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (tid < off) {
-            S.red[0][tid] += S.red[0][tid + off];
-            S.red[1][tid] += S.red[1][tid + off];
-            S.red[2][tid] = S.red[2][tid] > S.red[2][tid + off] ? S.red[2][tid] : S.red[2][tid + off];
+        for (int vt = tid; vt < off; vt += B) {
+            S.red[0][vt] += S.red[0][vt + off];
+            S.red[1][vt] += S.red[1][vt + off];
+            S.red[2][vt] = S.red[2][vt] > S.red[2][vt + off] ? S.red[2][vt] : S.red[2][vt + off];
         }
         __syncthreads();
     }
@@ -1093,52 +1188,85 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
 // rebuilds the lists of its own atoms: positions and bins are final after
 // the kick, and an atom's forces read only its own list.  `sorted_bins`
 // tells how the bins were filled (unsorted by the kick, or sorted).
-template <typename T>
+// LPA lanes per atom: a block of B threads takes B / LPA consecutive atoms
+// (a multiple of 64, so observable rows of 64 atoms never straddle blocks).
+// The run's state is read once for the block, so every wave takes the same
+// branch at the barriers even when another block raises an error meanwhile.
+template <typename T, int LPA>
 __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work, int phase,
                                                        int sorted_bins)
 {
     __shared__ unsigned long long cacc[kLdsCells];
+    __shared__ ObsTerms ostage[LPA > 1 ? kBlock / LPA : 1];
+    __shared__ int keep[kBinKeep * kBlock];   // per-thread bin buffers of the unsorted build
+    __shared__ int64_t b_step;
+    __shared__ int32_t b_go, b_rebuild;
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
-    int64_t step = R.st->step;
-    if (phase == PHASE_STEP) {
-        if (!run_active(R, &step)) return;
+    RunState* st = R.st;
+    // the run's state, read once for the block
+    if (threadIdx.x == 0) {
+        b_step = st->step;
+        b_go = phase != PHASE_STEP || (st->err == 0 && b_step < st->target);
+        b_rebuild = phase == PHASE_STEP && R.live && st->rebuild != 0 ? (st->bin_over ? 2 : 1) : 0;
     }
-    const uint32_t i = (uint32_t)w.y + threadIdx.x;
-    if (phase == PHASE_STEP && R.live && R.st->rebuild != 0) {
-        const bool first = w.y == 0 && threadIdx.x == 0;
-        if (R.st->bin_over) {
-            if (first) raise_bin_overflow(R);
-            return;
-        }
-        if (first) R.st->n_rebuild += 1;
-        if (i < (uint32_t)R.n) {
-            if (sorted_bins)
-                nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), i);
-            else
-                nbr_build_atom<T, GView<T>, false>(R, global_view(R, 0), i);
-        }
-    }
+    __syncthreads();
+    const int64_t step = b_step;
+    const uint32_t apb = blockDim.x / LPA;              // atoms of this block
+    const uint32_t la = threadIdx.x / LPA;              // the thread's atom in the block
+    const int lj = (int)(threadIdx.x % LPA);            // its lane in the atom's group
+    const uint32_t i = (uint32_t)w.y + la;
     const bool obs = sample_due(R, phase, step);
-    if (!R.live && !obs) return;
-    // electron-phonon energy per cell: first summed in LDS (fixed point, so
-    // the order does not matter), then one global atomic per touched cell
-    const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
-    const bool lds_acc = eph && R.ncell <= kLdsCells;
-    if (lds_acc) {
-        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
-        __syncthreads();
+    if (b_go && b_rebuild == 2) {
+        if (w.y == 0 && threadIdx.x == 0) raise_bin_overflow(R);
+    } else if (b_go && (R.live || obs)) {
+        if (b_rebuild) {
+            if (w.y == 0 && threadIdx.x == 0) st->n_rebuild += 1;
+            // one thread per atom builds the lists of the block's atoms
+            const uint32_t ib = (uint32_t)w.y + threadIdx.x;
+            if (threadIdx.x < apb && ib < (uint32_t)R.n) {
+                if (sorted_bins)
+                    nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), ib);
+                else
+                    nbr_build_atom<T, GView<T>, false>(R, global_view(R, 0), ib,
+                                                       keep + threadIdx.x);
+            }
+            __syncthreads();
+        }
+        // electron-phonon energy per cell: first summed in LDS (fixed point,
+        // so the order does not matter), then one global atomic per touched
+        // cell
+        const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
+        const bool lds_acc = eph && R.ncell <= kLdsCells;
+        if (lds_acc) {
+            for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
+            __syncthreads();
+        }
+        ObsTerms o{};
+        const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
+        if (i < (uint32_t)R.n)
+            atom_final_atom<T, GView<T>, LPA>(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, o, lj);
+        if (lds_acc) {
+            __syncthreads();
+            for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
+                if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
+        }
+        if (obs) {
+            if constexpr (LPA == 1) {
+                wave_write_row(o, R.partial, (int)i - (int)(threadIdx.x & 63), R.n);
+            } else {
+                // a wave holds 64 / LPA atoms: stage the terms so that rows of
+                // 64 atoms are reduced by one wave each, as with one lane per
+                // atom
+                if (lj == 0) ostage[la] = o;
+                __syncthreads();
+                if (threadIdx.x < apb)
+                    wave_write_row(ostage[threadIdx.x], R.partial,
+                                   w.y + (int)(threadIdx.x & ~63u), R.n);
+            }
+        }
     }
-    ObsTerms o{};
-    const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
-    if (i < (uint32_t)R.n) atom_final_atom(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, o);
-    if (lds_acc) {
-        __syncthreads();
-        for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
-            if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
-    }
-    if (obs) wave_write_row(o, R.partial, (int)i - (int)(threadIdx.x & 63), R.n);
 }
 
 template <typename T>
@@ -1167,18 +1295,24 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step);
 }
 
-// One block per run: small electron grids, the observable sample, the bins
-// emptied and the rebuild flag cleared, step + 1.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
-                                                     const int* __restrict__ run_list, int phase)
+
+// End of a step of one run, by one block: small electron grids, the
+// observable sample, the bins emptied and the rebuild flag cleared,
+// step + 1.  The run's state is read once for the block (the grid update
+// may raise an error while other waves have yet to look, and every wave
+// must take the same branch at the barriers).
+template <typename T> __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase)
 {
-    __shared__ SampleScratch S;
-    const RunDev<T>& R = runs[run_list[blockIdx.x]];
     RunState* st = R.st;
-    const int64_t step = st->step;
-    if (phase == PHASE_STEP && (st->err != 0 || step >= st->target)) return;
     const int tid = threadIdx.x;
+    if (tid == 0) {
+        S.step = st->step;
+        S.go = phase != PHASE_STEP || (st->err == 0 && S.step < st->target);
+        S.rebuild = st->rebuild;
+    }
+    __syncthreads();
+    if (!S.go) return;
+    const int64_t step = S.step;
     if (phase == PHASE_STEP && R.ttm_mode == 1 && R.ncell <= kSmallGrid) {
         for (int c = tid; c < R.ncell; c += blockDim.x) cell_update(R, R.Te, R.dE, c, step);
         __syncthreads();
@@ -1187,8 +1321,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict
         write_sample(R, global_view(R, step), S, phase == PHASE_INIT ? step : step + 1);
     // the bins filled this step have been read by the list build: empty them
     // for the next binning
-    if (R.live && (R.bin_step || st->rebuild != 0 || phase == PHASE_INIT))
+    if (R.live && (R.bin_step || S.rebuild != 0 || phase == PHASE_INIT))
         for (int b = tid; b < R.nbins; b += blockDim.x) R.bin_n[b] = 0;
+    __syncthreads();
     if (tid == 0) {
         if (R.live) {
             st->bin_over = 0;
@@ -1196,6 +1331,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict
         }
         if (phase == PHASE_STEP) st->step = step + 1;
     }
+}
+
+// One block per run.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
+                                                     const int* __restrict__ run_list, int phase)
+{
+    __shared__ SampleScratch S;
+    end_step(runs[run_list[blockIdx.x]], S, phase);
 }
 
 // ==================================================== persistent kernel

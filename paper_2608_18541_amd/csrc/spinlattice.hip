@@ -318,10 +318,13 @@ public:
     int graph_steps = 16;
     int precision = SL_FP64;
     // launch shape (every choice gives bitwise-identical results)
-    int spin_block = 256, spin_spt = 1, atom_block = 256;
+    int spin_block = 0, spin_spt = 1, atom_block = 256;   // spin_block 0: by the site count
+    int spin_eff = 256;             // the colour-pass block size in use
     int persist_block = 0;          // 0: every run on the multi-kernel step
     int xcd_ord = 0;                // 1: XCD-contiguous work tables
     int bin_mode = 0;               // 0 automatic, 1 kick bins every step, 2 rebuild only
+    int atom_lanes = 0;             // lanes per atom in k_atom_final (0: by the atom count)
+    int lanes_eff = 1;              // the lanes in use (tables are built for it)
     virtual sl_status retune() = 0;
 };
 
@@ -741,7 +744,7 @@ private:
     std::vector<void*> tables;
     int2* d_work_spin = nullptr;
     int2* d_work_atom = nullptr;
-    int2* d_work_kick = nullptr;     // atoms of live runs, in tiles of spin_block
+    int2* d_work_kick = nullptr;     // atoms of live runs, in tiles of the colour-pass block
     int2* d_work_cell = nullptr;
     int2* d_work_diff = nullptr;
     int* d_run_list = nullptr;
@@ -1032,7 +1035,7 @@ private:
             sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
             sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         }
-        sl::k_atom_final<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1);
+        sl::k_atom_final<T, 1><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1);
         sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
         SL_HIP(hipGetLastError());
         SL_HIP(hipStreamSynchronize(stream));
@@ -1055,6 +1058,34 @@ private:
         max_sub = 0;
         std::vector<int> pl;
         persist_bytes = 0;
+        // automatic launch shapes for the runs on the multi-kernel step: the
+        // colour-pass block is the largest of 256, 128, 64 threads that still
+        // gives at least one block per CU (256); lanes per atom give the force
+        // launch about two waves per SIMD (4 lanes up to 64k atoms, 2 up to
+        // 128k, then 1), within what the block size allows
+        int64_t multi_atoms = 0, multi_sites = 0;
+        for (size_t s = 0; s < runs.size(); ++s) {
+            if (!runs[s].used) continue;
+            const RD& R = host_rd[s];
+            const bool fits =
+                persist_block > 0 &&
+                sl::persist_layout<T>(R.n, R.ncell, R.n_part, R.live != 0, R.n_species, lds_max)
+                        .bytes <= lds_max;
+            if (!fits) {
+                multi_atoms += R.n;
+                multi_sites += R.g.H;
+            }
+        }
+        spin_eff = spin_block;
+        if (spin_eff == 0) {
+            spin_eff = 256;
+            while (spin_eff > 64 && multi_sites < (int64_t)256 * spin_eff * spin_spt) spin_eff /= 2;
+        }
+        lanes_eff = atom_lanes;
+        if (lanes_eff == 0) {
+            lanes_eff = multi_atoms <= (int64_t(1) << 16) ? 4 : (multi_atoms <= (int64_t(1) << 17) ? 2 : 1);
+            while (atom_block / lanes_eff < 64) lanes_eff /= 2;
+        }
         for (size_t s = 0; s < runs.size(); ++s) {
             if (!runs[s].used) continue;
             const RD& R = host_rd[s];
@@ -1067,10 +1098,11 @@ private:
                     continue;
                 }
             }
-            for (int st = 0; st < R.g.H; st += spin_block * spin_spt) ws.push_back(make_int2((int)s, st));
-            for (int st = 0; st < R.n; st += atom_block) wa.push_back(make_int2((int)s, st));
+            for (int st = 0; st < R.g.H; st += spin_eff * spin_spt) ws.push_back(make_int2((int)s, st));
+            const int atile = atom_block / lanes_eff;
+            for (int st = 0; st < R.n; st += atile) wa.push_back(make_int2((int)s, st));
             if (R.live)
-                for (int st = 0; st < R.n; st += spin_block) wk.push_back(make_int2((int)s, st));
+                for (int st = 0; st < R.n; st += spin_eff) wk.push_back(make_int2((int)s, st));
             if (R.ttm_mode == 1 && R.ncell > sl::kSmallGrid)
                 for (int st = 0; st < R.ncell; st += sl::kBlock) wc.push_back(make_int2((int)s, st));
             rl.push_back((int)s);
@@ -1086,7 +1118,7 @@ private:
             xcd_order(wk);
         }
         int64_t live_atoms = 0;
-        for (int2 t : wk) live_atoms += std::min<int64_t>(spin_block, host_rd[t.x].n - t.y);
+        for (int2 t : wk) live_atoms += std::min<int64_t>(spin_eff, host_rd[t.x].n - t.y);
         bin_each_step = bin_mode == 1 || (bin_mode == 0 && live_atoms <= kBinEachStepMaxAtoms);
         for (size_t s = 0; s < runs.size(); ++s) {
             if (!runs[s].used) continue;
@@ -1161,7 +1193,9 @@ private:
     sl_status enqueue_step(hipStream_t st, Prof* p)
     {
         const int C = max_colours();
-        const dim3 bs(spin_block), ba(atom_block), bk(sl::kBlock);
+        // the atom table's tiles hold atom_block / atom_lanes atoms: the
+        // binning launches take one thread per atom, k_atom_final atom_lanes
+        const dim3 bs(spin_eff), ba(atom_block), bt(atom_block / lanes_eff), bk(sl::kBlock);
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
             const bool fused = pass == 0 && active_blocks_kick > 0;
             const int nk = fused ? active_blocks_kick : 0;
@@ -1183,17 +1217,25 @@ private:
         sl_status e;
         if (active_blocks_kick > 0 && !bin_each_step) {
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_bin<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
+                launch(sl::k_nbr_bin<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
             });
             if (e != SL_OK) return e;
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_sort<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
+                launch(sl::k_nbr_sort<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
             });
             if (e != SL_OK) return e;
         }
         e = timed(st, p, 1, [&](hipEvent_t a, hipEvent_t b) {
-            launch(sl::k_atom_final<T>, ga, ba, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
-                   bin_each_step ? 0 : 1);
+            const int sorted = bin_each_step ? 0 : 1;
+            if (lanes_eff == 4)
+                launch(sl::k_atom_final<T, 4>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                       (int)sl::PHASE_STEP, sorted);
+            else if (lanes_eff == 2)
+                launch(sl::k_atom_final<T, 2>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                       (int)sl::PHASE_STEP, sorted);
+            else
+                launch(sl::k_atom_final<T, 1>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                       (int)sl::PHASE_STEP, sorted);
         });
         if (e != SL_OK) return e;
         for (int sub = 0; sub < max_sub; ++sub) {
@@ -1370,9 +1412,9 @@ sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* step
 static sl_status set_tuning(Engine* e, const sl_tuning* t)
 {
     if (!t) return fail(SL_EINVAL, "null tuning");
-    const bool blk_ok = [](int b) { return b == 64 || b == 128 || b == 256; }(t->spin_block) &&
+    const bool blk_ok = [](int b) { return b == 0 || b == 64 || b == 128 || b == 256; }(t->spin_block) &&
                         [](int b) { return b == 64 || b == 128 || b == 256; }(t->atom_block);
-    if (!blk_ok) return fail(SL_EINVAL, "block sizes must be 64, 128 or 256");
+    if (!blk_ok) return fail(SL_EINVAL, "block sizes must be 64, 128 or 256 (spin_block also 0)");
     if (t->spin_spt != 1 && t->spin_spt != 2 && t->spin_spt != 4) return fail(SL_EINVAL, "spin_spt must be 1, 2 or 4");
     if (t->graph_steps < 1 || t->graph_steps > 256) return fail(SL_EINVAL, "graph_steps must be 1..256");
     if (t->persist_block != 0 && t->persist_block != 256 && t->persist_block != 512 &&
@@ -1380,6 +1422,10 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
         return fail(SL_EINVAL, "persist_block must be 0, 256, 512 or 1024");
     if (t->xcd_order != 0 && t->xcd_order != 1) return fail(SL_EINVAL, "xcd_order must be 0 or 1");
     if (t->bin_mode < 0 || t->bin_mode > 2) return fail(SL_EINVAL, "bin_mode must be 0, 1 or 2");
+    if (t->atom_lanes != 0 && t->atom_lanes != 1 && t->atom_lanes != 2 && t->atom_lanes != 4)
+        return fail(SL_EINVAL, "atom_lanes must be 0, 1, 2 or 4");
+    if (t->atom_lanes > 0 && t->atom_block / t->atom_lanes < 64)
+        return fail(SL_EINVAL, "atom_block / atom_lanes must be at least 64");
     e->spin_block = t->spin_block;
     e->spin_spt = t->spin_spt;
     e->atom_block = t->atom_block;
@@ -1387,6 +1433,7 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     e->persist_block = t->persist_block;
     e->xcd_ord = t->xcd_order;
     e->bin_mode = t->bin_mode;
+    e->atom_lanes = t->atom_lanes;
     return e->retune();
 }
 
@@ -1399,6 +1446,7 @@ static void get_tuning(const Engine* e, sl_tuning* t)
     t->persist_block = e->persist_block;
     t->xcd_order = e->xcd_ord;
     t->bin_mode = e->bin_mode;
+    t->atom_lanes = e->atom_lanes;
 }
 
 sl_status sl_set_tuning(sl_system h, const sl_tuning* t)

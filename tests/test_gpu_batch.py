@@ -47,13 +47,19 @@ def _mixed_runs():
     runs.append((spec, I.initial_state(spec, "tilt")))
     spec = I.fe_bcc_spec(L=4, lattice_mode=0, seed=8, run_id=10, Te0=500.0)
     runs.append((spec, I.initial_state(spec, "random")))
+    # diffusing electrons: this run's step ends in its own launches, the
+    # others' in the force kernel
+    spec = replace(I.gdfeco_sc_spec(L=12, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005,
+                                    kappa_e=I.w_per_mk_to_metal(80.0), n_sub=4, profile=1,
+                                    depth=10.0, seed=12, run_id=11), tn=(3, 3, 6))
+    runs.append((spec, I.initial_state(spec, "afm")))
     return runs
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_equals_alone_bitwise(N, prec):
     runs = _mixed_runs()
-    targets = [37, 50, 64, 45, 70]
+    targets = [37, 50, 64, 45, 70, 55]
     _log("batch: %d runs prec=%d" % (len(runs), prec))
     b = N.Batch(precision=prec, max_runs=8)
     slots = [b.add(sp, st, t, obs_every=5) for (sp, st), t in zip(runs, targets)]
@@ -192,21 +198,23 @@ def test_launch_shapes_are_bitwise_identical(N):
         b = N.Batch(precision=prec, max_runs=4)
         slots = [b.add(sp, st, 10_000) for sp, st in runs]
         shapes = [dict(spin_block=64, spin_spt=4, atom_block=128, graph_steps=8, persist_block=0,
-                       xcd_order=1, bin_mode=2),
+                       xcd_order=1, bin_mode=2, atom_lanes=2),
                   dict(spin_block=128, spin_spt=2, atom_block=64, graph_steps=32,
-                       persist_block=512, xcd_order=0, bin_mode=1),
+                       persist_block=512, xcd_order=0, bin_mode=1, atom_lanes=1),
                   dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=1,
-                       persist_block=0, xcd_order=1, bin_mode=2),
+                       persist_block=0, xcd_order=1, bin_mode=2, atom_lanes=4),
                   dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=16,
-                       persist_block=256, xcd_order=0, bin_mode=0),
+                       persist_block=256, xcd_order=0, bin_mode=0, atom_lanes=1),
                   dict(spin_block=128, spin_spt=1, atom_block=128, graph_steps=8,
-                       persist_block=1024, xcd_order=0, bin_mode=0)]
+                       persist_block=1024, xcd_order=0, bin_mode=0, atom_lanes=2),
+                  dict(spin_block=256, spin_spt=1, atom_block=256, graph_steps=4,
+                       persist_block=0, xcd_order=0, bin_mode=1, atom_lanes=4)]
         for sh in shapes:
             b.set_tuning(**sh)
             b.advance(17)
         best = autotune(b, steps=8, use_cache=False)
         assert set(best) == {"spin_block", "spin_spt", "atom_block", "graph_steps",
-                             "persist_block", "xcd_order", "bin_mode"}
+                             "persist_block", "xcd_order", "bin_mode", "atom_lanes"}
         info = {r["slot"]: r["steps_done"] for r in b.runs()}
         for (sp, st), s in zip(runs, slots):
             alone = N.System(sp, st, precision=prec)
