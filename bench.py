@@ -11,6 +11,8 @@ phonon step, electron grid).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import math
 import os
@@ -104,28 +106,45 @@ def cpu_baseline(spec, st, budget_s: float = 20.0) -> dict:
     from oracle import oracle as O
     orc = O.Oracle(spec, st.species, st.spins, st.vel)
     steps = 0
-    t0 = time.perf_counter()
-    while True:
-        orc.step(1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s * 0.5 or steps >= 50:
-            break
+    with host_quiet():
+        t0 = time.perf_counter()
+        while True:
+            orc.step(1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget_s * 0.5 or steps >= 50:
+                break
     return {"value": spec.n_sites * steps / el, "unit": "atom-steps/s", "cores": 1,
             "kind": "oracle",
             "sample": "%d full steps of the 32^3 alloy (all-pairs Morse, FP64, one thread), "
                       "%.1f s" % (steps, el)}
 
 
-def plain_step_time(N, run, steps: int = 1000) -> float:
+@contextlib.contextmanager
+def host_quiet():
+    """A host-timed region with no Python garbage collection inside it (a
+    full collection over the millions of objects the ensemble rows hold
+    takes a tenth of a second and would land in a 25 ms window)."""
+    gc.collect()
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
+
+def plain_step_time(N, run, steps: int = 2000) -> float:
     """Seconds per step of one run alone on the plain FP64 path."""
     s = N.System(run.spec, run.state, precision=N.SL_FP64, obs_every=100)
     s.step(50)
     s.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps)
-    s.synchronize()
-    el = (time.perf_counter() - t0) / steps
+    with host_quiet():
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.synchronize()
+        el = (time.perf_counter() - t0) / steps
     s.close()
     return el
 
@@ -133,7 +152,7 @@ def plain_step_time(N, run, steps: int = 1000) -> float:
 def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     """The alloy phase diagram (8 alpha x 8 peak T_e x seeds, 16^3 runs) in
     one batch, FP32 and FP64; switching probabilities per cell."""
-    from paper_2608_18541_amd.stats import switched, wilson_ci
+    from paper_2608_18541_amd.stats import homogeneity_chi2, switched, wilson_ci
     runs = W.phase_diagram(L=16, n_seeds=n_seeds, n_steps=n_steps)
     res = {}
     flags = {}
@@ -143,13 +162,14 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
         slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
                  for r in runs]
         b.synchronize()
-        t0 = time.perf_counter()
-        b.advance(n_steps)
-        try:
-            b.synchronize()
-        except N.SLError:
-            pass                    # runs that stopped are counted below
-        el = time.perf_counter() - t0
+        with host_quiet():
+            t0 = time.perf_counter()
+            b.advance(n_steps)
+            try:
+                b.synchronize()
+            except N.SLError:
+                pass                # runs that stopped are counted below
+            el = time.perf_counter() - t0
         fl, failed, series = [], 0, []
         for s in slots:
             try:
@@ -168,29 +188,16 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
                                            "failed_runs": failed}
         print("bench: phase diagram prec %d: %.2f s" % (prec, el), file=sys.stderr, flush=True)
         b.close()
-    t_plain = plain_step_time(N, runs[0], 1000)
+    t_plain = plain_step_time(N, runs[0])
     plain_rps = 1.0 / (t_plain * n_steps)
     p32 = flags[N.SL_FP32].mean(axis=2)
     p64 = flags[N.SL_FP64].mean(axis=2)
     agree = float((flags[N.SL_FP32] == flags[N.SL_FP64]).mean())
     k = flags[N.SL_FP32].sum(axis=2)
     ci = [wilson_ci(int(v), n_seeds) for v in k.ravel()]
-    # homogeneity of the FP32 and FP64 switching counts over the 64 cells:
-    # sum of squared two-proportion z statistics over cells with 0 < p < 1
+    # homogeneity of the FP32 and FP64 switching counts over the 64 cells
     k64 = flags[N.SL_FP64].sum(axis=2)
-    chi2, dof = 0.0, 0
-    for a, c in zip(k.ravel(), k64.ravel()):
-        pp = (a + c) / (2.0 * n_seeds)
-        if 0.0 < pp < 1.0:
-            chi2 += (a - c) ** 2 / (2.0 * n_seeds * pp * (1.0 - pp))
-            dof += 1
-    # upper tail of chi^2 with dof degrees of freedom by the Wilson-Hilferty
-    # cube-root normal approximation (about 1e-3 absolute at dof >= 10)
-    if dof:
-        wz = ((chi2 / dof) ** (1.0 / 3.0) - (1.0 - 2.0 / (9.0 * dof))) / math.sqrt(2.0 / (9.0 * dof))
-        pval = 0.5 * math.erfc(wz / math.sqrt(2.0))
-    else:
-        pval = 1.0
+    chi2, dof, pval = homogeneity_chi2(k, k64, n_seeds)
     m = min(len(mz_mean[N.SL_FP32]), len(mz_mean[N.SL_FP64]))
     dM = np.abs(mz_mean[N.SL_FP32][:m] - mz_mean[N.SL_FP64][:m])
     # the FP64 oracle on one core for a few steps of one 16^3 run
@@ -198,9 +205,10 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     r0 = runs[0]
     orc = O.Oracle(r0.spec, r0.state.species, r0.state.spins, r0.state.vel)
     orc.step(1)
-    t0 = time.perf_counter()
-    orc.step(3)
-    t_orc = (time.perf_counter() - t0) / 3
+    with host_quiet():
+        t0 = time.perf_counter()
+        orc.step(3)
+        t_orc = (time.perf_counter() - t0) / 3
     res.update({
         "workload": "Gd25(FeCo)75 sc 16^3 x (8 alpha 0.005-0.04 log) x (8 peak T_e 800-2400 K)"
                     " x %d seeds = %d runs, %d steps" % (n_seeds, len(runs), n_steps),
@@ -235,7 +243,7 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
     per_size = {}
     for L in sorted(set(r.run.spec.ncell[0] for r in trace)):
         rr = next(r for r in trace if r.run.spec.ncell[0] == L)
-        per_size[L] = plain_step_time(N, rr.run, 500)
+        per_size[L] = plain_step_time(N, rr.run)
     base = S.fifo_baseline(trace, lambda r: per_size[r.run.spec.ncell[0]] * r.run.n_steps)
     bst = S.summarize(base, max(r.finished for r in base))
     return {"requests": st.n, "trace": "Poisson 50/s, sizes {8,16,24,32,48}^3, x U(0.18,0.32),"
@@ -247,6 +255,8 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
             "plain_req_per_s": round(bst.throughput, 4), "plain_makespan_s": round(bst.makespan, 1),
             "plain_p50_s": round(bst.p50, 2), "plain_p99_s": round(bst.p99, 2),
             "plain_us_per_step": {str(k): round(v * 1e6, 2) for k, v in per_size.items()},
+            "served_wall_s_by_activity": {k: round(v, 2) for k, v in srv.time_in.items()},
+            "served_chunks": len(srv.log),
             "plain_latency_method": "FIFO replay of measured plain FP64 per-step times"}
 
 
@@ -259,10 +269,11 @@ def large_run(N, I, steps: int) -> dict:
     s32 = N.System(spec, st, precision=N.SL_FP32, obs_every=100)
     s32.step(20)
     s32.synchronize()
-    t0 = time.perf_counter()
-    s32.step(steps)
-    s32.synchronize()
-    el = time.perf_counter() - t0
+    with host_quiet():
+        t0 = time.perf_counter()
+        s32.step(steps)
+        s32.synchronize()
+        el = time.perf_counter() - t0
     avg, cnt = s32.step_profiled(20)
     s32.close()
     H = spec.n_sites / 4
@@ -405,11 +416,12 @@ def main() -> int:
     sys_.step(args.warmup)
     sys_.synchronize()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sys_.step(args.steps)
-    sys_.synchronize()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    with host_quiet():
+        t0 = time.perf_counter()
+        sys_.step(args.steps)
+        sys_.synchronize()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     value = spec.n_sites * args.steps / el
     print("bench: timed %d steps in %.3f s" % (args.steps, el), file=sys.stderr, flush=True)
     t_dn = time.perf_counter()

@@ -69,7 +69,7 @@ template <typename T> struct RunDev {
     int32_t noisy;       // some species has a thermal field (sig > 0)
     int32_t bin_step;    // 1: atoms are binned by the kick every step, 0: only for a rebuild
     uint32_t seed, run_id;
-    T a, box[3], half_box[3];
+    T a, box[3], inv_box[3];
     T alpha, dt, tau_half, inv1pa2, gam;
     T B[3];
     T inv_mumb[4];       // 1 / (mu mu_B), T/eV
@@ -80,6 +80,7 @@ template <typename T> struct RunDev {
     double ou_1mc2;      // 1 - c1^2
     T m_e[4];            // m in eV ps^2 / A^2
     T mD, ma, mr0, rc2, Vc;
+    T mk1, mk0;          // single precision: exp(-a (r - r0)) = exp2(mk1 r + mk0)
     T skin_half2, rlist2;
     double mumb[4];      // mu mu_B, eV/T
     double Bd[3];
@@ -372,9 +373,16 @@ template <typename T> __device__ inline V3<T> ideal_site(const RunDev<T>& R, con
     return {((T)s.x + off) * R.a, ((T)s.y + off) * R.a, ((T)s.z + off) * R.a};
 }
 
-template <typename T> __device__ inline T min_image(T d, T box, T half)
+// Minimum image of a separation |d| < 1.5 box: the nearest lattice
+// translate, d - box rint(d / box) (one product, one rounding, one fused
+// multiply-add; d itself whenever |d| < box / 2).
+__device__ inline float min_image(float d, float box, float inv_box)
 {
-    return d > half ? d - box : (d < -half ? d + box : d);
+    return __builtin_fmaf(-box, __builtin_rintf(d * inv_box), d);
+}
+__device__ inline double min_image(double d, double box, double inv_box)
+{
+    return __builtin_fma(-box, __builtin_rint(d * inv_box), d);
 }
 
 // Separation x_j - x_i (minimum image) from the wrapped positions.
@@ -384,29 +392,30 @@ __device__ __forceinline__ V3<T> separation(const RunDev<T>& R, const VW& V, con
 {
     const Pos4<T> pj = VW::PosMem::ld(V.pos, j);
     V3<T> d{pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
-    d.x = min_image(d.x, R.box[0], R.half_box[0]);
-    d.y = min_image(d.y, R.box[1], R.half_box[1]);
-    d.z = min_image(d.z, R.box[2], R.half_box[2]);
+    d.x = min_image(d.x, R.box[0], R.inv_box[0]);
+    d.y = min_image(d.y, R.box[1], R.inv_box[1]);
+    d.z = min_image(d.z, R.box[2], R.inv_box[2]);
     return d;
 }
 
-// Morse force factor f = -dV/dr / r.  The single-precision path uses the
-// hardware exponential and reciprocal square root; double precision stays
+// Morse force factor f = -dV/dr / r at separation^2 r2 (and r).  The
+// single-precision path uses the hardware reciprocal square root and
+// exponential (exp2 of one fused multiply-add); double precision stays
 // correctly rounded.
-__device__ inline float morse_f(float r2, float a, float D, float r0, float* r_out)
+__device__ inline float morse_f(const RunDev<float>& R, float r2, float* r_out)
 {
     const float ir = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ir;
     *r_out = r;
-    const float e1 = __expf(-a * (r - r0));
-    return 2.0f * a * D * (e1 * e1 - e1) * ir;
+    const float e1 = __builtin_amdgcn_exp2f(__builtin_fmaf(r, R.mk1, R.mk0));
+    return 2.0f * R.ma * R.mD * (e1 * e1 - e1) * ir;
 }
-__device__ inline double morse_f(double r2, double a, double D, double r0, double* r_out)
+__device__ inline double morse_f(const RunDev<double>& R, double r2, double* r_out)
 {
     const double r = sqrt(r2);
     *r_out = r;
-    const double e1 = exp(-a * (r - r0));
-    return 2.0 * a * D * (e1 * e1 - e1) / r;
+    const double e1 = exp(-R.ma * (r - R.mr0));
+    return 2.0 * R.ma * R.mD * (e1 * e1 - e1) / r;
 }
 
 template <typename T> __device__ inline T wrap_box(T x, T L)
@@ -757,16 +766,54 @@ template <int LPA, typename X> __device__ __forceinline__ X fold_partials(const 
     }
 }
 
+// Walks this lane's share of atom i's Verlet list within the Morse cutoff:
+// entries k = j, j + LPA, ... in chunks of CH (all index loads, then all
+// position loads, then the arithmetic: two memory round trips per chunk;
+// column k of the list starts at nbr + k n).  With CH LPA a multiple of 4,
+// entry q of a chunk belongs to partial (k mod 4), which is this lane's
+// slot q mod (4 / LPA), whatever the chunk: f(slot, r^2, d), d = x_j - x_i.
+template <typename T, typename VW, int LPA, int CH = 8, typename F>
+__device__ __forceinline__ void walk_list(const RunDev<T>& R, const VW& V, uint32_t i, int j,
+                                          const Pos4<T>& pi, F&& f)
+{
+    constexpr int NA = 4 / LPA;
+    static_assert((CH * LPA) % 4 == 0, "chunks must keep the partial of each entry");
+    const int nn = gld(R.nbr_n, i);
+    const size_t n = (size_t)R.n;
+    for (int k0 = j; k0 < nn; k0 += CH * LPA) {
+        uint32_t jj[CH];
+#pragma unroll
+        for (int q8 = 0; q8 < CH; ++q8) {
+            const int k = k0 + q8 * LPA;
+            jj[q8] = k < nn ? (uint32_t)gld(R.nbr + (size_t)k * n, i) : i;
+        }
+        T dx[CH], dy[CH], dz[CH];
+#pragma unroll
+        for (int q8 = 0; q8 < CH; ++q8) {
+            const V3<T> d = separation(R, V, pi, jj[q8]);
+            dx[q8] = d.x;
+            dy[q8] = d.y;
+            dz[q8] = d.z;
+        }
+#pragma unroll
+        for (int q8 = 0; q8 < CH; ++q8) {
+            const T r2 = dx[q8] * dx[q8] + dy[q8] * dy[q8] + dz[q8] * dz[q8];
+            if (k0 + q8 * LPA < nn && r2 < R.rc2) f(q8 % NA, r2, dx[q8], dy[q8], dz[q8]);
+        }
+    }
+}
+
 // Forces on atom i at the new positions, the second half kick, the
-// electron-phonon Ornstein-Uhlenbeck step (its mean energy added to `acc`
-// of the atom's cell, fixed point) and, on sample steps, the atom's
+// electron-phonon Ornstein-Uhlenbeck step (its mean energy added to
+// acc[cell - acc_first], fixed point) and, on sample steps, the atom's
 // observable terms.  LPA lanes of a quad share the atom (lane `j` of the
 // group): they split its neighbour list, fold the pair sums, and then all
 // compute the rest while only lane 0 stores.
 template <typename T, typename VW, int LPA = 1>
 __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V, uint32_t i,
                                                 int phase, int64_t step, bool obs,
-                                                unsigned long long* acc, ObsTerms& o, int j = 0)
+                                                unsigned long long* acc, ObsTerms& o, int j = 0,
+                                                uint32_t acc_first = 0)
 {
     static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
     constexpr int NA = 4 / LPA;   // partial sums held by one lane
@@ -777,54 +824,32 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
     if (R.live) {
         const Pos4<T> pi = VW::PosMem::ld(V.pos, i);
         T px[NA], py[NA], pz[NA];
-        double ppe[NA];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            px[a] = py[a] = pz[a] = T(0);
-            ppe[a] = 0.0;
-        }
-        const int nn = gld(R.nbr_n, i);
-        const size_t n = (size_t)R.n;
-        // this lane's entries k = j, j + LPA, ... in chunks of 8: all index
-        // loads, then all position loads, then the arithmetic (two memory
-        // round trips per chunk); column k of the list starts at nbr + k n.
-        // Entry q of a chunk goes to partial (k mod 4), which is this lane's
-        // slot q mod NA.
-        for (int k0 = j; k0 < nn; k0 += 8 * LPA) {
-            uint32_t jj[8];
-#pragma unroll
-            for (int q8 = 0; q8 < 8; ++q8) {
-                const int k = k0 + q8 * LPA;
-                jj[q8] = k < nn ? (uint32_t)gld(R.nbr + (size_t)k * n, i) : i;
-            }
-            T dx[8], dy[8], dz[8];
-#pragma unroll
-            for (int q8 = 0; q8 < 8; ++q8) {
-                const V3<T> d = separation(R, V, pi, jj[q8]);
-                dx[q8] = d.x;
-                dy[q8] = d.y;
-                dz[q8] = d.z;
-            }
-#pragma unroll
-            for (int q8 = 0; q8 < 8; ++q8) {
-                const int a = q8 % NA;
-                const T r2 = dx[q8] * dx[q8] + dy[q8] * dy[q8] + dz[q8] * dz[q8];
-                if (k0 + q8 * LPA < nn && r2 < R.rc2) {
-                    T r;
-                    // -dV/dr along +d pushes j; the force on i is its opposite
-                    const T f = morse_f(r2, R.ma, R.mD, R.mr0, &r);
-                    px[a] -= f * dx[q8];
-                    py[a] -= f * dy[q8];
-                    pz[a] -= f * dz[q8];
-                    if (obs) {
-                        const double e1 = exp(-(double)R.ma * ((double)r - (double)R.mr0));
-                        ppe[a] += 0.5 * ((double)R.mD * (e1 * e1 - 2.0 * e1) - (double)R.Vc);
-                    }
-                }
-            }
-        }
+        for (int a = 0; a < NA; ++a) px[a] = py[a] = pz[a] = T(0);
+        walk_list<T, VW, LPA>(R, V, i, j, pi, [&](int a, T r2, T dx, T dy, T dz) {
+            T r;
+            // -dV/dr along +d pushes j; the force on i is its opposite
+            const T f = morse_f(R, r2, &r);
+            px[a] -= f * dx;
+            py[a] -= f * dy;
+            pz[a] -= f * dz;
+        });
         const T Fx = fold_partials<LPA>(px), Fy = fold_partials<LPA>(py), Fz = fold_partials<LPA>(pz);
-        const double pe = obs ? fold_partials<LPA>(ppe) : 0.0;
+        double pe = 0.0;
+        if (obs) {
+            // the Morse energy (sample steps only: a second walk keeps the
+            // force loop's registers free of it), bonds counted once
+            double ppe[NA];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) ppe[a] = 0.0;
+            walk_list<T, VW, LPA, 4>(R, V, i, j, pi, [&](int a, T r2, T, T, T) {
+                T r;
+                (void)morse_f(R, r2, &r);
+                const double e1 = exp(-(double)R.ma * ((double)r - (double)R.mr0));
+                ppe[a] += 0.5 * ((double)R.mD * (e1 * e1 - 2.0 * e1) - (double)R.Vc);
+            });
+            pe = fold_partials<LPA>(ppe);
+        }
         T vx = gld(R.vx, i), vy = gld(R.vy, i), vz = gld(R.vz, i);
         const T me = select4(sp, R.m_e[0], R.m_e[1], R.m_e[2], R.m_e[3]);
         if (phase == PHASE_STEP) {
@@ -849,7 +874,7 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
                 const double dE = R.ou_1mc2 * (1.5 * kKB * Te - ke);
                 if (fabs(dE) < 1.0e3) {
                     const long long fixp = llrint(dE * kFIX);
-                    if (lead) atomicAdd(&acc[c], (unsigned long long)fixp);
+                    if (lead) atomicAdd(&acc[c - acc_first], (unsigned long long)fixp);
                 } else if (lead) {
                     atomicOr(&R.st->err, ERR_DE);
                 }
@@ -1197,11 +1222,19 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
                                                        const int2* __restrict__ work, int phase,
                                                        int sorted_bins)
 {
-    __shared__ unsigned long long cacc[kLdsCells];
     __shared__ ObsTerms ostage[LPA > 1 ? kBlock / LPA : 1];
-    __shared__ int keep[kBinKeep * kBlock];   // per-thread bin buffers of the unsorted build
+    // the list build's per-thread bin buffers and the per-cell sums are never
+    // live together (a barrier separates them): one region, 16 KB, so five
+    // 256-thread blocks fit a CU
+    __shared__ union {
+        int keep[kBinKeep * kBlock];
+        unsigned long long cacc[kLdsCells];
+    } lds;
+    unsigned long long* const cacc = lds.cacc;
+    int* const keep = lds.keep;
     __shared__ int64_t b_step;
     __shared__ int32_t b_go, b_rebuild;
+    __shared__ uint32_t b_lo[kBlock / 64], b_hi[kBlock / 64];   // per-wave cell ranges
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     RunState* st = R.st;
@@ -1227,30 +1260,56 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
             const uint32_t ib = (uint32_t)w.y + threadIdx.x;
             if (threadIdx.x < apb && ib < (uint32_t)R.n) {
                 if (sorted_bins)
-                    nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), ib);
+                    [[clang::always_inline]] nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), ib);
                 else
-                    nbr_build_atom<T, GView<T>, false>(R, global_view(R, 0), ib,
-                                                       keep + threadIdx.x);
+                    [[clang::always_inline]] nbr_build_atom<T, GView<T>, false>(
+                        R, global_view(R, 0), ib, keep + threadIdx.x);
             }
             __syncthreads();
         }
-        // electron-phonon energy per cell: first summed in LDS (fixed point,
-        // so the order does not matter), then one global atomic per touched
-        // cell
+        // electron-phonon energy per cell: first summed in LDS over the span
+        // of cells the block's atoms occupy (fixed point, so the order does
+        // not matter), then one global atomic per touched cell; a block whose
+        // span exceeds the LDS table adds to the global sums directly
         const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
-        const bool lds_acc = eph && R.ncell <= kLdsCells;
+        const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
+        uint32_t c_lo = 0, c_span = 0;
+        if (eph) {
+            const bool mine = i < (uint32_t)R.n;
+            const uint32_t c = mine ? (uint32_t)gld(V.cell, i) : 0u;
+            uint32_t lo = mine ? c : 0xFFFFFFFFu, hi = mine ? c : 0u;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+                hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                b_lo[threadIdx.x >> 6] = lo;
+                b_hi[threadIdx.x >> 6] = hi;
+            }
+            __syncthreads();
+            lo = b_lo[0];
+            hi = b_hi[0];
+            for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) {
+                lo = min(lo, b_lo[wv]);
+                hi = max(hi, b_hi[wv]);
+            }
+            c_lo = lo;
+            c_span = hi >= lo ? hi - lo + 1 : 0;
+        }
+        const bool lds_acc = eph && c_span <= (uint32_t)kLdsCells;
         if (lds_acc) {
-            for (int c = threadIdx.x; c < R.ncell; c += blockDim.x) cacc[c] = 0ull;
+            for (uint32_t c = threadIdx.x; c < c_span; c += blockDim.x) cacc[c] = 0ull;
             __syncthreads();
         }
         ObsTerms o{};
-        const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
         if (i < (uint32_t)R.n)
-            atom_final_atom<T, GView<T>, LPA>(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, o, lj);
+            atom_final_atom<T, GView<T>, LPA>(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, o, lj,
+                                              lds_acc ? c_lo : 0u);
         if (lds_acc) {
             __syncthreads();
-            for (int c = threadIdx.x; c < R.ncell; c += blockDim.x)
-                if (cacc[c] != 0ull) atomicAdd(&R.dE[c], cacc[c]);
+            for (uint32_t c = threadIdx.x; c < c_span; c += blockDim.x)
+                if (cacc[c] != 0ull) atomicAdd(&R.dE[c_lo + c], cacc[c]);
         }
         if (obs) {
             if constexpr (LPA == 1) {

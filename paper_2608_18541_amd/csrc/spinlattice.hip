@@ -833,7 +833,7 @@ private:
         R.a = (T)d->a;
         for (int k = 0; k < 3; ++k) {
             R.box[k] = (T)(d->ncell[k] * d->a);
-            R.half_box[k] = (T)(0.5 * d->ncell[k] * d->a);
+            R.inv_box[k] = (T)(1.0 / (d->ncell[k] * d->a));
             R.B[k] = (T)d->B[k];
             R.Bd[k] = d->B[k];
         }
@@ -868,6 +868,8 @@ private:
         R.mD = (T)d->morse[0];
         R.ma = (T)d->morse[1];
         R.mr0 = (T)d->morse[2];
+        R.mk1 = (T)(-d->morse[1] * 1.4426950408889634);                 // -a log2(e)
+        R.mk0 = (T)(d->morse[1] * d->morse[2] * 1.4426950408889634);    // a r0 log2(e)
         R.rc2 = (T)(d->morse[3] * d->morse[3]);
         R.Vc = (T)(d->morse[0] * (std::exp(-2.0 * d->morse[1] * (d->morse[3] - d->morse[2])) -
                                   2.0 * std::exp(-d->morse[1] * (d->morse[3] - d->morse[2]))));

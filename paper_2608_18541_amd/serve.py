@@ -83,6 +83,10 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.log: List[tuple] = []
+        # wall time by activity: advancing the batch (device work and its
+        # wait), admitting requests, collecting finished runs, idle waiting
+        # for arrivals
+        self.time_in = {"advance": 0.0, "admit": 0.0, "collect": 0.0, "idle": 0.0}
 
     def run(self, requests) -> List[Result]:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -100,6 +104,7 @@ class Server:
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             # admission: first come first served, by slot and HBM footprint
+            ta = self.clock()
             while waiting:
                 req = waiting[0]
                 spec = req.run.spec
@@ -112,16 +117,21 @@ class Server:
                     break
                 waiting.popleft()
                 active[slot] = (req, self.clock() - t0)
+            tb = self.clock()
+            self.time_in["admit"] += tb - ta
             if not active:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
+                self.time_in["idle"] += self.clock() - tb
                 continue
             self.ex.advance(self.chunk)
             try:
                 self.ex.synchronize()
             except RuntimeError:
                 pass                             # reported per run when collected
-            self.log.append((self.clock() - t0, len(active), len(waiting)))
+            tc = self.clock()
+            self.time_in["advance"] += tc - tb
+            self.log.append((tc - t0, len(active), len(waiting)))
             for info in self.ex.runs():
                 s = info["slot"]
                 if s not in active or info["steps_done"] < info["steps_target"]:
@@ -140,6 +150,7 @@ class Server:
                              state=out if self.keep_state else None, error=err)
                 done.append(res)
                 self.ex.remove(s)
+            self.time_in["collect"] += self.clock() - tc
         self.makespan = self.clock() - t0
         return sorted(done, key=lambda r: r.rid)
 

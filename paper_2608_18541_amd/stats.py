@@ -34,3 +34,23 @@ def switched(mz_gd: Sequence[float], tail_fraction: float = 0.1) -> bool:
     k = max(1, int(math.ceil(tail_fraction * (m.size - 1))))
     tail = m[-k:]
     return bool(np.all(tail * m[0] < 0.0))
+
+
+def homogeneity_chi2(k_a: Sequence[int], k_b: Sequence[int], n: int) -> Tuple[float, int, float]:
+    """Whether two sets of switching counts (k_a[c], k_b[c] successes out of
+    n each, per cell c) share their probabilities: the sum over cells with
+    a pooled probability strictly between 0 and 1 of the squared
+    two-proportion z statistic, its degrees of freedom (those cells) and the
+    upper-tail p value of chi^2 with that many degrees of freedom by the
+    Wilson-Hilferty cube-root normal approximation (about 1e-3 absolute at
+    dof >= 10)."""
+    chi2, dof = 0.0, 0
+    for a, c in zip(np.ravel(k_a), np.ravel(k_b)):
+        pp = (a + c) / (2.0 * n)
+        if 0.0 < pp < 1.0:
+            chi2 += (a - c) ** 2 / (2.0 * n * pp * (1.0 - pp))
+            dof += 1
+    if dof == 0:
+        return 0.0, 0, 1.0
+    wz = ((chi2 / dof) ** (1.0 / 3.0) - (1.0 - 2.0 / (9.0 * dof))) / math.sqrt(2.0 / (9.0 * dof))
+    return chi2, dof, 0.5 * math.erfc(wz / math.sqrt(2.0))

@@ -1,0 +1,114 @@
+"""Host-side helpers of bench.py and the ensemble statistics (CPU only)."""
+import gc
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+from paper_2608_18541_amd import inputs as I
+from paper_2608_18541_amd.stats import homogeneity_chi2
+
+
+def test_host_quiet_suspends_collection():
+    assert gc.isenabled()
+    with bench.host_quiet():
+        assert not gc.isenabled()
+    assert gc.isenabled()
+    with pytest.raises(RuntimeError):
+        with bench.host_quiet():
+            raise RuntimeError("inside")
+    assert gc.isenabled()
+
+
+def test_algorithmic_bytes_per_unit():
+    # own spin read + write, species, electron-cell id
+    assert bench.bytes_per_unit("spin_pass", 0, 2, 0) == 51
+    assert bench.bytes_per_unit("spin_pass", 1, 2, 0) == 27
+    assert bench.bytes_per_unit("spin_pass", 0, 1, 0) == 50
+    # u read, v read + write, F write, list 4 z, count, species, cell (sc, z = 18)
+    assert bench.bytes_per_unit("atom_final", 0, 2, 18.0) == 175
+    assert bench.bytes_per_unit("atom_final", 1, 2, 18.0) == 127
+
+
+def _write_profile(tmp_path, name, digest, tuning=None, value=12345.0):
+    lines = ["# test", "traffic_bytes_per_launch: %.0f" % value, "source_sha256: %s" % digest]
+    if tuning is not None:
+        lines.append("tuning: %s" % json.dumps(tuning))
+    (tmp_path / name).write_text("\n".join(lines) + "\n")
+
+
+def test_measured_traffic_only_for_current_kernels(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    digest = bench.source_digest()
+    tun = {"spin_block": 256, "spin_spt": 2}
+    _write_profile(tmp_path, "spin_pass_w1_traffic.txt", digest, tun, 627e6)
+    _write_profile(tmp_path, "atom_final_w2_traffic.txt", "0" * 64, None, 7e6)
+    assert bench.measured_traffic("spin_pass", "w1", tun) == 627e6
+    assert bench.measured_traffic("spin_pass", "w1") == 627e6
+    assert bench.measured_traffic("spin_pass", "w1", {"spin_block": 128, "spin_spt": 2}) is None
+    assert bench.measured_traffic("atom_final", "w2") is None        # kernels changed since
+    assert bench.measured_traffic("atom_final", "missing") is None
+
+
+def test_committed_profiles_match_the_kernels():
+    """The committed counter summaries were taken on the current kernels
+    (otherwise the bench line would report traffic null)."""
+    assert bench.measured_traffic("atom_final", "alloy32_fp64") is not None
+    assert bench.measured_traffic("spin_pass", "fe256_fp32", json.loads(bench.SCALE_TUNING)) is not None
+
+
+def _positions(spec, uz_of_layer):
+    Lx, Ly, Lz = spec.ncell
+    nb = 2 if spec.lattice == 1 else 1
+    out = np.zeros((spec.n_sites, 3))
+    for i in range(spec.n_sites):
+        b, cell = i % nb, i // nb
+        x, y, z = cell % Lx, (cell // Lx) % Ly, cell // (Lx * Ly)
+        off = 0.25 + 0.5 * b
+        out[i] = [(x + off) * spec.a, (y + off) * spec.a, (z + off) * spec.a + uz_of_layer[z]]
+    out[:, 2] %= Lz * spec.a
+    return out
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_strain_profile_of_a_standing_wave(lattice):
+    """u_z = A sin(2 pi k / Lz) per layer k gives the central-difference
+    strain A cos(2 pi k / Lz) sin(2 pi / Lz) / a; the ideal lattice none."""
+    spec = I.fe_bcc_spec(L=6) if lattice == 1 else I.gdfeco_sc_spec(L=6, tn=2)
+    Lz = spec.ncell[2]
+    assert np.allclose(bench.strain_profile(spec, _positions(spec, np.zeros(Lz))), 0.0, atol=1e-15)
+    A = 0.05
+    k = np.arange(Lz)
+    eps = bench.strain_profile(spec, _positions(spec, A * np.sin(2 * np.pi * k / Lz)))
+    want = A * np.cos(2 * np.pi * k / Lz) * np.sin(2 * np.pi / Lz) / spec.a
+    np.testing.assert_allclose(eps, want, atol=1e-12)
+
+
+def test_homogeneity_chi2_against_the_exact_tail():
+    scipy_stats = pytest.importorskip("scipy.stats")
+    rng = np.random.default_rng(3)
+    for cells, n in ((64, 20), (40, 50), (16, 200)):
+        p = rng.uniform(0.1, 0.9, cells)
+        ka, kb = rng.binomial(n, p), rng.binomial(n, p)
+        chi2, dof, pval = homogeneity_chi2(ka, kb, n)
+        # the statistic written out directly
+        pp = (ka + kb) / (2.0 * n)
+        m = (pp > 0) & (pp < 1)
+        direct = np.sum((ka - kb)[m] ** 2 / (2.0 * n * pp[m] * (1 - pp[m])))
+        assert math.isclose(chi2, direct, rel_tol=1e-12) and dof == int(m.sum())
+        # Wilson-Hilferty tail within its stated accuracy at dof >= 10
+        assert abs(pval - scipy_stats.chi2.sf(chi2, dof)) < 2e-3
+    # cells at p = 0 or 1 carry no information; identical counts give chi2 0
+    chi2, dof, pval = homogeneity_chi2([0, 20, 5], [0, 20, 5], 20)
+    assert chi2 == 0.0 and dof == 1 and pval > 0.3
+    assert homogeneity_chi2([0, 20], [0, 20], 20) == (0.0, 0, 1.0)
+
+
+def test_more_than_one_gpu_is_refused(monkeypatch, capsys):
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
+    assert bench.main() == 2
+    assert "one GPU" in capsys.readouterr().err
