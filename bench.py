@@ -92,7 +92,7 @@ def launch_bytes(kernel: str, fp: int, n_species: int, z_list: float, n_sites: i
     H = n_sites / colours
     if kernel == "spin_pass":
         return bytes_per_unit("spin_pass", fp, n_species, z_list) * H
-    if kernel == "spin_kick":              # colour pass 0 carrying the lattice kick
+    if kernel == "spin_kick":              # colour pass 1 carrying the lattice kick
         return (bytes_per_unit("spin_pass", fp, n_species, z_list) * H +
                 bytes_per_unit("kick", fp, n_species, z_list) * n_sites)
     if kernel == "atom_final":

@@ -210,7 +210,7 @@ sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
  * by HIP events stamped by its own dispatch; returns the average device time
  * (ms) per launch of each kernel class and the launch counts: 0 spin colour
  * pass, 1 neighbour-list rebuild (when due), lattice forces and
- * electron-phonon step, 2 colour pass 0 carrying the lattice's kick, drift
+ * electron-phonon step, 2 colour pass 1 carrying the lattice's kick, drift
  * and binning (live lattices), 3 binning for a rebuild (large engines),
  * electron grid and end-of-step reductions, 4 persistent kernel (one launch
  * for all steps). */

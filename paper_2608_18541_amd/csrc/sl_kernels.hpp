@@ -8,10 +8,13 @@
 // Per step, in stream order:
 //   k_spin_pass  x (2C-1)  colour sweep 0..C-1 (half steps), C-2..0, the
 //                          middle colour taking one full step; the launch of
-//                          pass 0 also carries the lattice's half kick +
+//                          pass 1 also carries the lattice's half kick +
 //                          drift, electron-cell id, skin check and binning
 //                          (they read no spin, and the cell ids of the new
-//                          positions go to the other of two buffers)
+//                          positions go to the other of two buffers).  In a
+//                          merged chunk a step leaves its last pass (colour
+//                          0, half step) to the next step's pass 0, which
+//                          applies it before its own: 2C-2 passes per step
 //   k_nbr_bin, k_nbr_sort  binning for a rebuild (large engines; exit at
 //                          once unless a rebuild is flagged)
 //   k_atom_final           Verlet-list rebuild of its own atoms when flagged,
@@ -55,6 +58,9 @@ struct RunState {
     int64_t n_rebuild;   // Verlet-list builds so far, the initial one included
     int32_t max_list;    // longest list built so far
     int32_t bin_over;    // a bin overflowed while binning this step
+    int32_t pending;     // the last half step (colour 0) of step `step - 1` is deferred
+                         // to the next colour pass 0, which applies it first
+    int32_t pad_;
 };
 
 // Wrapped absolute position of an atom, padded to a 16/32-byte vector so a
@@ -465,9 +471,19 @@ template <typename T> __device__ inline bool run_active(const RunDev<T>& R, int6
 // Update of site l of a colour: field from the current neighbours, thermal
 // field from the step's Philox block (drawn whenever the run has a thermal
 // field; its amplitude is zero in cells at T_e = 0), exact flow over tau.
+// With `has_prev` (colour pass 0 only), the deferred last half step of the
+// previous step comes first: the same neighbours, hence the same exchange
+// field, with that step's noise, T_e and electron cells.  Two rotations in
+// one pass give the same bits as the two passes they replace.
+struct PrevHalf {
+    const uint16_t* cell;    // electron cells of the previous step's positions
+    const double* Te;        // the previous step's electron temperatures
+};
+
 template <typename T, typename VW, int LAT, bool MULTI>
 __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int colour, T tau,
-                                            uint32_t l, int64_t step)
+                                            uint32_t l, int64_t step, bool cur = true,
+                                            bool has_prev = false, PrevHalf prev = {})
 {
     using M = typename VW::Mem;
     const Cell3 c = cell_of(R.g, colour, l);
@@ -478,25 +494,36 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
     const V3<T> h = exchange_sum_t<T, VW, LAT, MULTI>(R, V, colour, a, sp);
     const T imu = MULTI ? select4(sp, R.inv_mumb[0], R.inv_mumb[1], R.inv_mumb[2], R.inv_mumb[3])
                         : R.inv_mumb[0];
-    T Hx = h.x * imu + R.B[0];
-    T Hy = h.y * imu + R.B[1];
-    T Hz = h.z * imu + R.B[2];
-    if (R.noisy) {
-        const double Te = M::ld(V.Te, (uint32_t)M::ld(V.cell, idx));
-        const int b = LAT == SL_LATTICE_BCC ? (colour >> 1) : 0;
-        const uint32_t canon =
-            __umul24(__umul24(c.z, (uint32_t)R.g.Ly) + c.y, (uint32_t)R.g.Lx) * (uint32_t)R.g.nb +
-            c.x * (uint32_t)R.g.nb + (uint32_t)b;
-        const Normals3<T> nu = normals3<T>(R.seed, R.run_id, canon, step, 0u);
-        const T sg = MULTI ? select4(sp, R.sig[0], R.sig[1], R.sig[2], R.sig[3]) : R.sig[0];
-        const T amp = Te > 0.0 ? sg * sqrt_te(Te, T(0)) : T(0);
-        Hx += amp * nu.a;
-        Hy += amp * nu.b;
-        Hz += amp * nu.c;
-    }
+    const T H0x = h.x * imu + R.B[0];
+    const T H0y = h.y * imu + R.B[1];
+    const T H0z = h.z * imu + R.B[2];
+    const int b = LAT == SL_LATTICE_BCC ? (colour >> 1) : 0;
+    const uint32_t canon =
+        __umul24(__umul24(c.z, (uint32_t)R.g.Ly) + c.y, (uint32_t)R.g.Lx) * (uint32_t)R.g.nb +
+        c.x * (uint32_t)R.g.nb + (uint32_t)b;
+    // one exact rotation over tau_ with the thermal field of step stp at T_e
+    auto rotate = [&](V3<T> s0, int64_t stp, double Te, T tau_) {
+        T Hx = H0x, Hy = H0y, Hz = H0z;
+        if (R.noisy) {
+            const Normals3<T> nu = normals3<T>(R.seed, R.run_id, canon, stp, 0u);
+            const T sg = MULTI ? select4(sp, R.sig[0], R.sig[1], R.sig[2], R.sig[3]) : R.sig[0];
+            const T amp = Te > 0.0 ? sg * sqrt_te(Te, T(0)) : T(0);
+            Hx += amp * nu.a;
+            Hy += amp * nu.b;
+            Hz += amp * nu.c;
+        }
+        const V3<T> wv{R.gam * Hx, R.gam * Hy, R.gam * Hz};
+        return llg_flow(s0, wv, R.alpha, tau_, R.inv1pa2);
+    };
     V3<T> s{M::ld(V.sx + kH, l), M::ld(V.sy + kH, l), M::ld(V.sz + kH, l)};
-    const V3<T> wv{R.gam * Hx, R.gam * Hy, R.gam * Hz};
-    s = llg_flow(s, wv, R.alpha, tau, R.inv1pa2);
+    if (has_prev) {
+        const double Te = R.noisy ? gld(prev.Te, (uint32_t)gld(prev.cell, idx)) : 0.0;
+        s = rotate(s, step - 1, Te, R.tau_half);
+    }
+    if (cur) {
+        const double Te = R.noisy ? M::ld(V.Te, (uint32_t)M::ld(V.cell, idx)) : 0.0;
+        s = rotate(s, step, Te, tau);
+    }
     M::st(V.sx + kH, l, s.x);
     M::st(V.sy + kH, l, s.y);
     M::st(V.sz + kH, l, s.z);
@@ -505,14 +532,15 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
 // Dispatch on the run's lattice and species count (uniform per run).
 template <typename T, typename VW>
 __device__ __forceinline__ void spin_site(const RunDev<T>& R, const VW& V, int colour, T tau,
-                                          uint32_t l, int64_t step)
+                                          uint32_t l, int64_t step, bool cur = true,
+                                          bool has_prev = false, PrevHalf prev = {})
 {
     if (R.lattice == SL_LATTICE_SC) {
-        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true>(R, V, colour, tau, l, step);
-        else spin_site_t<T, VW, SL_LATTICE_SC, false>(R, V, colour, tau, l, step);
+        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else spin_site_t<T, VW, SL_LATTICE_SC, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     } else {
-        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true>(R, V, colour, tau, l, step);
-        else spin_site_t<T, VW, SL_LATTICE_BCC, false>(R, V, colour, tau, l, step);
+        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else spin_site_t<T, VW, SL_LATTICE_BCC, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     }
 }
 
@@ -976,10 +1004,11 @@ __device__ inline void diffuse_cell(const RunDev<T>& R, const double* src, doubl
 // - dE / V, T_e = sqrt(2 e / gamma_e).  dE is the cell's fixed-point sum.
 template <typename T>
 __device__ inline void cell_update(const RunDev<T>& R, double* Te, unsigned long long* dEsum, int c,
-                                   int64_t step)
+                                   int64_t step, double* Te_prev = nullptr)
 {
     const double ge = R.gamma_e;
     const double T0 = Te[c];
+    if (Te_prev != nullptr) Te_prev[c] = T0;   // kept for a deferred spin half step
     const double e0 = R.kappa_e != 0.0 ? R.ee[c] : 0.5 * ge * T0 * T0;
     const int k = c / (R.tn[0] * R.tn[1]);
     const double tmid = ((double)step + 0.5) * R.dtd;
@@ -1112,7 +1141,7 @@ template <typename T, int SPT>
 __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
                                                       const int2* __restrict__ work, int pass,
                                                       const int2* __restrict__ work_kick,
-                                                      int n_spin_blocks)
+                                                      int n_spin_blocks, int merge)
 {
     if ((int)blockIdx.x >= n_spin_blocks) {
         const int2 w = work_kick[blockIdx.x - n_spin_blocks];
@@ -1130,23 +1159,30 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     int64_t step;
-    if (!run_active(R, &step)) return;
+    const bool cur = run_active(R, &step);
+    // colour pass 0 of a merged step first applies the previous step's
+    // deferred last half step (also when the run has just reached its target)
+    const bool prev = merge && pass == 0 && R.st->pending != 0;
+    if (!cur && !prev) return;
     if (pass >= 2 * R.g.C - 1) return;
     int colour;
     T tau;
     pass_colour(R, pass, &colour, &tau);
     const GView<T> V = global_view(R, step);
+    // T_e of the previous step: kept by the grid update in the diffusion
+    // buffer (runs that merge do not diffuse); a fixed grid never changes
+    const PrevHalf ph{R.cellb[(step - 1) & 1], R.ttm_mode == 1 ? R.Te_alt : R.Te};
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
-        if (l < (uint32_t)R.g.H) spin_site(R, V, colour, tau, l, step);
+        if (l < (uint32_t)R.g.H) spin_site(R, V, colour, tau, l, step, cur, prev, ph);
     }
 }
 
 // Initialisation of the lattice arrays of one run: electron cells and
 // wrapped positions of the current positions, the cell ids into both
 // buffers (a frozen lattice never rewrites them).  In steps the kick is
-// carried by colour pass 0.
+// carried by colour pass 1.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_lattice(const RunDev<T>* __restrict__ runs,
                                                          const int2* __restrict__ work)
@@ -1351,7 +1387,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     int64_t step;
     if (!run_active(R, &step) || R.ttm_mode != 1 || R.ncell <= kSmallGrid) return;
     const int c = w.y + (int)threadIdx.x;
-    if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step);
+    if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step, R.kappa_e == 0.0 ? R.Te_alt : nullptr);
 }
 
 
@@ -1360,7 +1396,10 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
 // step + 1.  The run's state is read once for the block (the grid update
 // may raise an error while other waves have yet to look, and every wave
 // must take the same branch at the barriers).
-template <typename T> __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase)
+// `deferred`: this step's last colour half step is left to the next step's
+// colour pass 0 (recorded in the run state for it).
+template <typename T>
+__device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase, int deferred = 0)
 {
     RunState* st = R.st;
     const int tid = threadIdx.x;
@@ -1370,10 +1409,14 @@ template <typename T> __device__ inline void end_step(const RunDev<T>& R, Sample
         S.rebuild = st->rebuild;
     }
     __syncthreads();
-    if (!S.go) return;
+    if (!S.go) {
+        if (tid == 0 && phase == PHASE_STEP) st->pending = 0;
+        return;
+    }
     const int64_t step = S.step;
     if (phase == PHASE_STEP && R.ttm_mode == 1 && R.ncell <= kSmallGrid) {
-        for (int c = tid; c < R.ncell; c += blockDim.x) cell_update(R, R.Te, R.dE, c, step);
+        for (int c = tid; c < R.ncell; c += blockDim.x)
+            cell_update(R, R.Te, R.dE, c, step, R.kappa_e == 0.0 ? R.Te_alt : nullptr);
         __syncthreads();
     }
     if (sample_due(R, phase, step))
@@ -1388,17 +1431,21 @@ template <typename T> __device__ inline void end_step(const RunDev<T>& R, Sample
             st->bin_over = 0;
             st->rebuild = 0;
         }
-        if (phase == PHASE_STEP) st->step = step + 1;
+        if (phase == PHASE_STEP) {
+            st->pending = deferred;
+            st->step = step + 1;
+        }
     }
 }
 
 // One block per run.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
-                                                     const int* __restrict__ run_list, int phase)
+                                                     const int* __restrict__ run_list, int phase,
+                                                     int deferred)
 {
     __shared__ SampleScratch S;
-    end_step(runs[run_list[blockIdx.x]], S, phase);
+    end_step(runs[run_list[blockIdx.x]], S, phase, deferred);
 }
 
 // ==================================================== persistent kernel

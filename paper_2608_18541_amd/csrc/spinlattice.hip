@@ -5,7 +5,10 @@
 // forces, neighbour tables, electron grid, observable ring); a device table
 // of run descriptors plus block->(run, offset) work tables let every kernel
 // launch cover all active runs.  A single system is an engine with one run.
-// Steps are replayed from a captured HIP graph of graph_steps steps.
+// Steps are replayed from a captured HIP graph of graph_steps steps, or, for
+// a single run on the multi-kernel step, of chunks of steps whose adjacent
+// colour-0 half steps share one pass (chunk length dividing the sample
+// interval, so that every sample sees complete sweeps).
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
@@ -324,6 +327,8 @@ public:
     int xcd_ord = 0;                // 1: XCD-contiguous work tables
     int bin_mode = 0;               // 0 automatic, 1 kick bins every step, 2 rebuild only
     int atom_lanes = 0;             // lanes per atom in k_atom_final (0: by the atom count)
+    int merge_g = 0;                // >= 2: steps per merged chunk (one multi-kernel run)
+    int merge_run = -1;             // that run's slot
     int lanes_eff = 1;              // the lanes in use (tables are built for it)
     virtual sl_status retune() = 0;
 };
@@ -472,14 +477,23 @@ public:
             SL_HIP(hipEventRecord(ev_join, side_stream));
         }
         int64_t left = active_blocks_atom > 0 ? n : 0;
-        if (graph_steps > 1 && left >= graph_steps) {
+        const int G = graph_len();
+        if (merge_g >= 2 && left > 0) {
+            // single steps up to the next multiple of the chunk length
+            const int64_t s0 = runs[merge_run].steps;
+            int64_t head = (merge_g - s0 % merge_g) % merge_g;
+            head = std::min<int64_t>(head, left);
+            for (int64_t k = 0; k < head; ++k) enqueue_step(stream, nullptr);
+            left -= head;
+        }
+        if (G > 1 && left >= G) {
             if (!graph_ok) {
                 sl_status st = capture();
                 if (st != SL_OK) return st;
             }
-            while (left >= graph_steps) {
+            while (left >= G) {
                 SL_HIP(hipGraphLaunch(exec, stream));
-                left -= graph_steps;
+                left -= G;
             }
         }
         for (int64_t k = 0; k < left; ++k) enqueue_step(stream, nullptr);
@@ -511,7 +525,23 @@ public:
             });
             if (st != SL_OK) return st;
         }
-        for (int64_t k = 0; k < n && active_blocks_atom > 0; ++k) {
+        // the schedule advance() uses: single steps up to a chunk boundary,
+        // then merged chunks, then single steps
+        int64_t left = active_blocks_atom > 0 ? n : 0;
+        if (merge_g >= 2 && left > 0) {
+            const int64_t s0 = runs[merge_run].steps;
+            int64_t head = std::min<int64_t>((merge_g - s0 % merge_g) % merge_g, left);
+            for (int64_t k = 0; k < head; ++k) {
+                sl_status st = enqueue_step(stream, &p);
+                if (st != SL_OK) return st;
+            }
+            left -= head;
+            for (; left >= merge_g; left -= merge_g) {
+                sl_status st = enqueue_chunk(stream, &p);
+                if (st != SL_OK) return st;
+            }
+        }
+        for (int64_t k = 0; k < left; ++k) {
             sl_status st = enqueue_step(stream, &p);
             if (st != SL_OK) return st;
         }
@@ -1038,7 +1068,7 @@ private:
             sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         }
         sl::k_atom_final<T, 1><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1);
-        sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT);
+        sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT, 0);
         SL_HIP(hipGetLastError());
         SL_HIP(hipStreamSynchronize(stream));
         alloc.put(tmp);
@@ -1130,6 +1160,30 @@ private:
                 SL_HIP(hipMemcpyAsync(d_runs + s, &host_rd[s], sizeof(RD), hipMemcpyHostToDevice, stream));
             }
         }
+        // adjacent colour-0 half steps of consecutive steps merge into one pass
+        // when a single run is on the multi-kernel step, its electrons do not
+        // diffuse (the deferred half step reads the previous step's T_e kept
+        // in the diffusion buffer) and chunks of merge_g steps can end on
+        // every sample step (merge_g divides obs_every); chunks start at
+        // multiples of merge_g
+        merge_g = 0;
+        merge_run = -1;
+        if (rl.size() == 1) {
+            const RD& R = host_rd[rl[0]];
+            if (!(R.ttm_mode == 1 && R.kappa_e != 0.0)) {
+                int g = 0;
+                if (R.obs_every > 0) {
+                    for (int d = 2; d <= 64; ++d)
+                        if (R.obs_every % d == 0) g = d;
+                } else {
+                    g = graph_steps;
+                }
+                if (g >= 2) {
+                    merge_g = g;
+                    merge_run = rl[0];
+                }
+            }
+        }
         for (void* p : tables) alloc.put(p);
         tables.clear();
         d_work_spin = d_work_atom = d_work_kick = d_work_cell = d_work_diff = nullptr;
@@ -1190,28 +1244,33 @@ private:
 
     // One step of every run on the multi-kernel path.  Profiling classes:
     // 0 colour pass, 1 list rebuild (when flagged) and force / e-ph kernel,
-    // 2 colour pass 0 carrying the lattice kick and drift, 3 binning for a
+    // 2 colour pass 1 carrying the lattice kick and drift, 3 binning for a
     // rebuild, electron grid and end of step.
-    sl_status enqueue_step(hipStream_t st, Prof* p)
+    // merge_first: colour pass 0 applies the previous step's deferred last
+    // half step first; defer_last: this step's last colour pass is left to
+    // the next step's pass 0.  The lattice kick rides on colour pass 1.
+    sl_status enqueue_step(hipStream_t st, Prof* p, bool merge_first = false, bool defer_last = false)
     {
         const int C = max_colours();
         // the atom table's tiles hold atom_block / atom_lanes atoms: the
         // binning launches take one thread per atom, k_atom_final atom_lanes
         const dim3 bs(spin_eff), ba(atom_block), bt(atom_block / lanes_eff), bk(sl::kBlock);
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
-            const bool fused = pass == 0 && active_blocks_kick > 0;
+            if (defer_last && pass == 2 * C - 2) break;
+            const int merge = merge_first && pass == 0 ? 1 : 0;
+            const bool fused = pass == 1 && active_blocks_kick > 0;
             const int nk = fused ? active_blocks_kick : 0;
             sl_status e = timed(st, p, fused ? 2 : 0, [&](hipEvent_t a, hipEvent_t b) {
                 const dim3 g(active_blocks_spin + nk);
                 if (spin_spt == 4)
                     launch(sl::k_spin_pass<T, 4>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin);
+                           d_work_kick, active_blocks_spin, merge);
                 else if (spin_spt == 2)
                     launch(sl::k_spin_pass<T, 2>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin);
+                           d_work_kick, active_blocks_spin, merge);
                 else
                     launch(sl::k_spin_pass<T, 1>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin);
+                           d_work_kick, active_blocks_spin, merge);
             });
             if (e != SL_OK) return e;
         }
@@ -1255,17 +1314,35 @@ private:
         }
         e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
             launch(sl::k_finalize<T>, dim3(active_runs), bk, 0, st, a, b, d_runs, d_run_list,
-                   (int)sl::PHASE_STEP);
+                   (int)sl::PHASE_STEP, defer_last ? 1 : 0);
         });
         return e;
     }
+
+    // One chunk of merge_g steps: every step but the last defers its last
+    // colour half step, every step but the first applies the one deferred
+    // before it, so the chunk ends with complete sweeps.
+    sl_status enqueue_chunk(hipStream_t st, Prof* p)
+    {
+        for (int k = 0; k < merge_g; ++k) {
+            sl_status e = enqueue_step(st, p, k > 0, k < merge_g - 1);
+            if (e != SL_OK) return e;
+        }
+        return SL_OK;
+    }
+
+    // steps per graph replay
+    int graph_len() const { return merge_g >= 2 ? merge_g : graph_steps; }
 
     sl_status capture()
     {
         drop_graph();
         hipGraph_t graph = nullptr;
         SL_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < graph_steps; ++k) enqueue_step(cap_stream, nullptr);
+        if (merge_g >= 2)
+            enqueue_chunk(cap_stream, nullptr);
+        else
+            for (int k = 0; k < graph_steps; ++k) enqueue_step(cap_stream, nullptr);
         hipError_t e = hipStreamEndCapture(cap_stream, &graph);
         if (e != hipSuccess) return fail(SL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

@@ -1,0 +1,91 @@
+"""Merged colour sweeps: a step that leaves its last colour-0 half step to the
+next step's colour pass 0 (two rotations in one pass, same neighbours) must
+give the bits of the unmerged schedule.
+
+A run sampled every step cannot merge (no chunk length in 2..64 divides 1),
+so it is the unmerged reference; the same run sampled every 10 steps merges
+in chunks of 10.  Advances of uneven length start and stop inside chunks,
+and a batch run reaches its target inside a chunk.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2608_18541_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_18541_amd import native
+    native.lib()
+    return native
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    # bcc Fe, fixed 300 K electrons (the deferred half step reads T_e itself)
+    yield "bcc_fixed_Te", I.fe_bcc_spec(L=6), "tilt"
+    # laser-heated sc alloy, live lattice, electron grid updated every step
+    # (the deferred half step reads the previous step's T_e)
+    yield "alloy_laser_live", I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005,
+                                               fwhm=0.005), "afm"
+
+
+def _samples(sysobj, every):
+    return {o["step"]: o for o in sysobj.observables() if (o["step"] % every) == 0}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["bcc_fixed_Te", "alloy_laser_live"])
+def test_merged_sweep_equals_unmerged(N, case, prec):
+    name, spec, init = next(c for c in _cases() if c[0] == case)
+    st = I.initial_state(spec, init)
+    _log("case: %s prec=%d" % (name, prec))
+    ref = N.System(spec, st, precision=prec, obs_every=1)
+    mrg = N.System(spec, st, precision=prec, obs_every=10)
+    for chunk in (7, 23, 15, 40, 1, 34):
+        ref.step(chunk)
+        mrg.step(chunk)
+        a, b = ref.state(), mrg.state()
+        for k in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[k], b[k]), (name, chunk, k)
+    # samples at steps 10, 20, ...: the merged run's samples see complete sweeps
+    sa, sb = _samples(ref, 10), _samples(mrg, 10)
+    assert sorted(sb) == list(range(0, 121, 10))
+    for stp, o in sb.items():
+        r = sa[stp]
+        for k in ("E_ex", "E_z", "KE", "PE", "m_abs", "Te_mean"):
+            assert r[k] == o[k], (name, stp, k)
+        assert np.array_equal(np.array(r["M"]), np.array(o["M"])), (name, stp)
+    ref.close()
+    mrg.close()
+
+
+def test_run_ending_inside_a_chunk(N):
+    """A batch's only multi-kernel run reaches its target at step 37 while the
+    engine steps chunks of 10: the half step deferred by step 36 is applied
+    by the next pass 0 although the run no longer steps."""
+    spec = I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005, seed=3, run_id=2)
+    st = I.initial_state(spec, "afm")
+    b = N.Batch(precision=0, max_runs=1)
+    slot = b.add(spec, st, 37, obs_every=10)
+    b.advance(60)
+    g = b.get(slot)
+    ref = N.System(spec, st, precision=0, obs_every=1)
+    ref.step(37)
+    a = ref.state()
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(a[k], g[k]), k
+    assert [o["step"] for o in g["obs"]] == [0, 10, 20, 30]
+    b.close()
+    ref.close()
