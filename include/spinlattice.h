@@ -225,7 +225,11 @@ typedef struct sl_tuning {
                                  256 blocks per pass)                          */
     int32_t spin_spt;         /* sites per thread in a colour pass: 1, 2, 4          */
     int32_t atom_block;       /* threads per block of the lattice kernels: 64..256   */
-    int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256         */
+    int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256; a
+                                 single run on the multi-kernel step replays
+                                 chunks of merged sweeps instead (the largest
+                                 divisor of its sample interval up to 64, or
+                                 graph_steps when it takes no samples)        */
     int32_t persist_block;    /* 0: all runs on the multi-kernel step; 256, 512 or
                                  1024: runs that fit in LDS advance in a persistent
                                  kernel, one block of this many threads per run
