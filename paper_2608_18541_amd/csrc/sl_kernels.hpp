@@ -1003,22 +1003,29 @@ __device__ inline void diffuse_cell(const RunDev<T>& R, const double* src, doubl
 // mode): e = (after diffusion, or gamma_e T^2 / 2) + dt S(z, t + dt/2)
 // - dE / V, T_e = sqrt(2 e / gamma_e).  dE is the cell's fixed-point sum.
 template <typename T>
-__device__ inline void cell_update(const RunDev<T>& R, double* Te, unsigned long long* dEsum, int c,
-                                   int64_t step, double* Te_prev = nullptr)
+__device__ inline void cell_update_from(const RunDev<T>& R, double T0, unsigned long long raw, double* Te,
+                                        unsigned long long* dEsum, int c, int64_t step,
+                                        double* Te_prev = nullptr)
 {
     const double ge = R.gamma_e;
-    const double T0 = Te[c];
     if (Te_prev != nullptr) Te_prev[c] = T0;   // kept for a deferred spin half step
     const double e0 = R.kappa_e != 0.0 ? R.ee[c] : 0.5 * ge * T0 * T0;
     const int k = c / (R.tn[0] * R.tn[1]);
     const double tmid = ((double)step + 0.5) * R.dtd;
     const double src = laser_power(R, (k + 0.5) * R.th[2], tmid);
-    const double de = (double)(long long)dEsum[c] / kFIX;
+    const double de = (double)(long long)raw / kFIX;
     dEsum[c] = 0ull;
     const double e = e0 + R.dtd * src - de / R.Vcell;
     R.ee[c] = e;
     if (e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
     Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
+}
+
+template <typename T>
+__device__ inline void cell_update(const RunDev<T>& R, double* Te, unsigned long long* dEsum, int c,
+                                   int64_t step, double* Te_prev = nullptr)
+{
+    cell_update_from(R, Te[c], dEsum[c], Te, dEsum, c, step, Te_prev);
 }
 
 
@@ -1403,6 +1410,20 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
 {
     RunState* st = R.st;
     const int tid = threadIdx.x;
+    // this thread's first two cells of a small grid, loaded before the state
+    // is known (they were written by earlier launches) so that the two
+    // memory round trips overlap
+    const bool grid = phase == PHASE_STEP && R.ttm_mode == 1 && R.ncell <= kSmallGrid;
+    double pT[2] = {0.0, 0.0};
+    unsigned long long pE[2] = {0ull, 0ull};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = tid + q * (int)blockDim.x;
+        if (grid && c < R.ncell) {
+            pT[q] = R.Te[c];
+            pE[q] = R.dE[c];
+        }
+    }
     if (tid == 0) {
         S.step = st->step;
         S.go = phase != PHASE_STEP || (st->err == 0 && S.step < st->target);
@@ -1414,9 +1435,15 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
         return;
     }
     const int64_t step = S.step;
-    if (phase == PHASE_STEP && R.ttm_mode == 1 && R.ncell <= kSmallGrid) {
-        for (int c = tid; c < R.ncell; c += blockDim.x)
-            cell_update(R, R.Te, R.dE, c, step, R.kappa_e == 0.0 ? R.Te_alt : nullptr);
+    if (grid) {
+        double* const keep_prev = R.kappa_e == 0.0 ? R.Te_alt : nullptr;
+        int q = 0;
+        for (int c = tid; c < R.ncell; c += blockDim.x, ++q) {
+            if (q < 2)
+                cell_update_from(R, pT[q & 1], pE[q & 1], R.Te, R.dE, c, step, keep_prev);
+            else
+                cell_update(R, R.Te, R.dE, c, step, keep_prev);
+        }
         __syncthreads();
     }
     if (sample_due(R, phase, step))
