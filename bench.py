@@ -45,9 +45,11 @@ def source_digest() -> str:
 
 
 # launch shape of the 256^3 field + LLG row: 2 sites per thread in 256-thread
-# blocks, round-robin over the XCDs (the autotuner's choice for that workload)
+# blocks, round-robin over the XCDs (the autotuner's choice for that workload),
+# one launch per colour pass (every timed pass updates its sites once)
 SCALE_TUNING = json.dumps({"spin_block": 256, "spin_spt": 2, "atom_block": 256, "graph_steps": 16,
-                           "persist_block": 0, "xcd_order": 0, "bin_mode": 0, "atom_lanes": 0})
+                           "persist_block": 0, "xcd_order": 0, "bin_mode": 0, "atom_lanes": 0,
+                           "merge_sweeps": 0})
 
 
 def measured_traffic(kernel: str, workload: str, tuning=None):

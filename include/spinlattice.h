@@ -248,6 +248,11 @@ typedef struct sl_tuning {
                                  2^17, then 1).  The pair sums are four
                                  interleaved partial sums over the list in every
                                  case, hence the same bits                   */
+    int32_t merge_sweeps;     /* 1 (default): a single run on the multi-kernel
+                                 step applies the last colour half step of a
+                                 step together with the next step's first, in
+                                 chunks ending on every sample step; 0: one
+                                 launch per colour pass.  Same bits either way */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of

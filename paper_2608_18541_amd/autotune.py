@@ -26,6 +26,7 @@ KNOBS = {
     "atom_lanes": (0, 1, 2, 4),
     "xcd_order": (0, 1),
     "bin_mode": (0, 1, 2),
+    "merge_sweeps": (1, 0),
 }
 
 _CACHE_FILE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2608_18541_amd",

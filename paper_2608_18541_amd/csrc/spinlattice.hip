@@ -327,6 +327,7 @@ public:
     int xcd_ord = 0;                // 1: XCD-contiguous work tables
     int bin_mode = 0;               // 0 automatic, 1 kick bins every step, 2 rebuild only
     int atom_lanes = 0;             // lanes per atom in k_atom_final (0: by the atom count)
+    int merge_sweeps = 1;           // 1: merge adjacent colour half steps when possible
     int merge_g = 0;                // >= 2: steps per merged chunk (one multi-kernel run)
     int merge_run = -1;             // that run's slot
     int lanes_eff = 1;              // the lanes in use (tables are built for it)
@@ -1168,7 +1169,7 @@ private:
         // multiples of merge_g
         merge_g = 0;
         merge_run = -1;
-        if (rl.size() == 1) {
+        if (merge_sweeps && rl.size() == 1) {
             const RD& R = host_rd[rl[0]];
             if (!(R.ttm_mode == 1 && R.kappa_e != 0.0)) {
                 int g = 0;
@@ -1505,6 +1506,7 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
         return fail(SL_EINVAL, "atom_lanes must be 0, 1, 2 or 4");
     if (t->atom_lanes > 0 && t->atom_block / t->atom_lanes < 64)
         return fail(SL_EINVAL, "atom_block / atom_lanes must be at least 64");
+    if (t->merge_sweeps != 0 && t->merge_sweeps != 1) return fail(SL_EINVAL, "merge_sweeps must be 0 or 1");
     e->spin_block = t->spin_block;
     e->spin_spt = t->spin_spt;
     e->atom_block = t->atom_block;
@@ -1513,6 +1515,7 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     e->xcd_ord = t->xcd_order;
     e->bin_mode = t->bin_mode;
     e->atom_lanes = t->atom_lanes;
+    e->merge_sweeps = t->merge_sweeps;
     return e->retune();
 }
 
@@ -1526,6 +1529,7 @@ static void get_tuning(const Engine* e, sl_tuning* t)
     t->xcd_order = e->xcd_ord;
     t->bin_mode = e->bin_mode;
     t->atom_lanes = e->atom_lanes;
+    t->merge_sweeps = e->merge_sweeps;
 }
 
 sl_status sl_set_tuning(sl_system h, const sl_tuning* t)

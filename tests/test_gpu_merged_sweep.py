@@ -89,3 +89,28 @@ def test_run_ending_inside_a_chunk(N):
     assert [o["step"] for o in g["obs"]] == [0, 10, 20, 30]
     b.close()
     ref.close()
+
+
+def test_merge_knob_same_bits(N):
+    """merge_sweeps 0 (one launch per colour pass) and 1 at the same sample
+    interval: identical trajectories and samples; other values rejected."""
+    spec = I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005, seed=5, run_id=4)
+    st = I.initial_state(spec, "afm")
+    out = []
+    for m in (0, 1):
+        g = N.System(spec, st, precision=1, obs_every=20)
+        g.set_tuning(merge_sweeps=m)
+        g.step(13)
+        g.step(90)
+        out.append((g.state(), g.observables()))
+        if m == 1:
+            before = g.tuning()
+            with pytest.raises(N.SLError) as e:
+                g.set_tuning(merge_sweeps=2)
+            assert e.value.code == N.SL_EINVAL and g.tuning() == before
+        g.close()
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    assert [o["step"] for o in out[0][1]] == [o["step"] for o in out[1][1]]
+    for a, b in zip(out[0][1], out[1][1]):
+        assert a["E_ex"] == b["E_ex"] and a["m_abs"] == b["m_abs"] and a["Te_mean"] == b["Te_mean"]
