@@ -248,6 +248,24 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
         per_size[L] = plain_step_time(N, rr.run)
     base = S.fifo_baseline(trace, lambda r: per_size[r.run.spec.ncell[0]] * r.run.n_steps)
     bst = S.summarize(base, max(r.finished for r in base))
+    # FP32 served results against the same requests on the plain FP64 path
+    # (every 60th request): M_Gd,z(t) at the server's sampling and the flags
+    from paper_2608_18541_amd.stats import switched
+    by_rid = {r.rid: r for r in res}
+    cmp_ids = [q.rid for q in trace][::60]
+    dmz, agree = [], 0
+    for q in trace:
+        if q.rid not in cmp_ids:
+            continue
+        s64 = N.System(q.run.spec, q.run.state, precision=N.SL_FP64, obs_every=100,
+                       obs_capacity=q.run.n_steps // 100 + 2)
+        s64.step(q.run.n_steps)
+        mz64 = np.array([o["M"][1][2] for o in s64.observables()])
+        s64.close()
+        mz32 = by_rid[q.rid].mz_gd
+        m = min(len(mz32), len(mz64))
+        dmz.append(float(np.abs(mz32[:m] - mz64[:m]).max()))
+        agree += int(switched(mz32) == switched(mz64))
     return {"requests": st.n, "trace": "Poisson 50/s, sizes {8,16,24,32,48}^3, x U(0.18,0.32),"
                                        " T_peak U(1000,2200) K, steps U{5000..30000} x %g"
                                        % steps_scale,
@@ -258,6 +276,12 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
             "plain_p50_s": round(bst.p50, 2), "plain_p99_s": round(bst.p99, 2),
             "plain_us_per_step": {str(k): round(v * 1e6, 2) for k, v in per_size.items()},
             "served_wall_s_by_activity": {k: round(v, 2) for k, v in srv.time_in.items()},
+            "fp32_vs_fp64_sample": {"requests": len(dmz), "max_abs_dMz_gd": max(dmz) if dmz else None,
+                                    "median_abs_dMz_gd": float(np.median(dmz)) if dmz else None,
+                                    "switch_flag_agreement": agree / len(dmz) if dmz else None,
+                                    "note": "every 60th request re-run alone on the plain FP64 "
+                                            "path; single trajectories, so FP32 and FP64 diverge "
+                                            "chaotically and agree only statistically"},
             "served_chunks": len(srv.log),
             "plain_latency_method": "FIFO replay of measured plain FP64 per-step times"}
 
