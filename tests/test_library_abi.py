@@ -173,3 +173,42 @@ def test_device_integer_logic_on_host():
     assert lines[-1] == "OK", lines[-3:]
     for c, line in zip(cases, lines[:-1]):
         assert list(map(int, line.split())) == list(O.philox(c[:4], c[4:])), c
+
+
+def test_footprint_and_site_limit(libpath):
+    """Host-only calls: the HBM footprint grows with the site count and is
+    smaller in FP32; runs of 2^27 sites or more are rejected before any
+    array is read (per-atom arrays use 32-bit byte offsets)."""
+    from paper_2608_18541_amd import inputs as I
+    from paper_2608_18541_amd import native
+    L = native.lib()
+    sizes = {}
+    for Lc in (8, 16):
+        spec = I.gdfeco_sc_spec(L=Lc, tn=2)
+        st = I.initial_state(spec, "afm")
+        for prec in (native.SL_FP64, native.SL_FP32):
+            d, keep = native.system_desc(spec, st, prec)
+            t, keep2 = native.ttm_desc(spec)
+            out = C.c_size_t()
+            assert L.sl_footprint_bytes(C.byref(d), C.byref(t), C.byref(out)) == native.SL_OK
+            sizes[(Lc, prec)] = out.value
+    for prec in (native.SL_FP64, native.SL_FP32):
+        ratio = sizes[(16, prec)] / sizes[(8, prec)]
+        assert 7.0 < ratio < 8.5, ratio                # per-site arrays dominate
+    # FP32 halves the 15 real per-atom arrays (spins, displacements,
+    # velocities, forces, reference displacements) and the padded position
+    # vector: 15 x 4 + 16 bytes per atom less; lists, bins, ids and samples
+    # keep their size
+    for Lc in (8, 16):
+        n = Lc ** 3
+        assert sizes[(Lc, native.SL_FP64)] - sizes[(Lc, native.SL_FP32)] == (15 * 4 + 16) * n
+    # 2^27 sites: bcc 512 x 512 x 256 cells, with the small run's arrays
+    spec = I.gdfeco_sc_spec(L=8, tn=2)
+    st = I.initial_state(spec, "afm")
+    d, keep = native.system_desc(spec, st, native.SL_FP32)
+    t, keep2 = native.ttm_desc(spec)
+    d.lattice = 1
+    d.ncell = (C.c_int32 * 3)(512, 512, 256)
+    out = C.c_size_t()
+    assert L.sl_footprint_bytes(C.byref(d), C.byref(t), C.byref(out)) == native.SL_EINVAL
+    assert b"too many sites" in L.sl_last_error()
