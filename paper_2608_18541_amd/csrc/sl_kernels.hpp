@@ -1139,11 +1139,12 @@ template <typename T> __device__ inline bool sample_due(const RunDev<T>& R, int 
 
 // ==================================================== multi-kernel step
 // Colour pass `pass` over the sites of every active run.  Blocks from
-// n_spin_blocks on (the launch of pass 0 carries them when lattices are
+// n_spin_blocks on (the launch of pass 1 carries them when lattices are
 // live) take atoms instead: half kick, drift, the electron cell of the new
 // position (into the other cell buffer, so the spin blocks of this launch
 // still see the cells of x^n), the skin check and binning.  They read no
-// spin and the spin blocks read no lattice array.
+// spin and the spin blocks read no lattice array.  `merge` (pass 0): apply
+// the previous step's deferred last half step first.
 template <typename T, int SPT>
 __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
                                                       const int2* __restrict__ work, int pass,
