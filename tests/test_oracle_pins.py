@@ -346,6 +346,76 @@ def test_boltzmann_average_sc222_against_metropolis():
     assert abs(M_ld - M_mc) < 0.02, (M_ld, M_mc)
 
 
+def _metropolis_bcc222(J1v, J2v, T, nchain=2048, nsweep=1200, burn=300, seed=2):
+    """Independent Metropolis sampler on the 16-spin periodic 2x2x2 bcc cell
+    with two exchange shells: a site's 8 first neighbours are the other
+    sublattice in the 8 cells around it (all distinct at L = 2), its 6 second
+    neighbours the same sublattice one cell away along each axis (each of the
+    3 distinct ones reached through two images, so counted twice)."""
+    rng = np.random.default_rng(seed)
+    L, nb = 2, 2
+    idx = lambda x, y, z, b: ((z * L + y) * L + x) * nb + b
+    nbr = np.zeros((16, 14), dtype=np.int64)
+    Jn = np.zeros(14)
+    Jn[:8], Jn[8:] = J1v, J2v
+    axes = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    for z in range(L):
+        for y in range(L):
+            for x in range(L):
+                for b in range(nb):
+                    i = idx(x, y, z, b)
+                    d = (-1, 0) if b == 0 else (0, 1)
+                    first = [idx((x + dx) % L, (y + dy) % L, (z + dz) % L, 1 - b)
+                             for dz in d for dy in d for dx in d]
+                    second = [idx((x + ax) % L, (y + ay) % L, (z + az) % L, b) for ax, ay, az in axes]
+                    nbr[i] = first + second
+    s = rng.standard_normal((nchain, 16, 3))
+    s /= np.linalg.norm(s, axis=2, keepdims=True)
+    beta = 1.0 / (KB * T)
+    field = lambda i: np.einsum("k,ckd->cd", Jn, s[:, nbr[i], :])
+    Es, Ms = [], []
+    for sweep in range(nsweep):
+        for i in range(16):
+            h = field(i)
+            new = rng.standard_normal((nchain, 3))
+            new /= np.linalg.norm(new, axis=1, keepdims=True)
+            dE = -np.sum((new - s[:, i, :]) * h, axis=1)
+            acc = rng.random(nchain) < np.exp(np.minimum(0.0, -beta * dE))
+            s[acc, i, :] = new[acc]
+        if sweep >= burn and sweep % 5 == 0:
+            E = 0.0
+            for i in range(16):
+                E = E - 0.5 * np.sum(s[:, i, :] * field(i), axis=1)
+            Es.append(E.mean())
+            Ms.append(np.linalg.norm(s.mean(axis=1), axis=1).mean())
+    return float(np.mean(Es)), float(np.mean(Ms))
+
+
+def test_boltzmann_average_bcc222_two_shells_against_metropolis():
+    """The 16-spin periodic bcc cell with first- and second-shell exchange:
+    Langevin time averages of the oracle equal Metropolis ensemble averages of
+    the same Hamiltonian (the second shell's doubled images included)."""
+    J1v, J2v = 0.01, 0.005
+    T = 2.5 * J1v / KB
+    E_mc, M_mc = _metropolis_bcc222(J1v, J2v, T)
+    Jm = lambda j: (tuple([j, j, 0, 0]), tuple([j, j, 0, 0]), (0,) * 4, (0,) * 4)
+    Es, Ms = [], []
+    for run in range(16):
+        spec = spin_only_spec(lattice=1, n_shells=2, J=(Jm(J1v), Jm(J2v)), alpha=0.5, dt=1e-3,
+                              Te0=T, seed=78, run_id=run)
+        st = I.spins_random(16, 10, run)
+        orc = O.Oracle(spec, [0] * 16, st)
+        orc.step(800)
+        for _ in range(60):
+            orc.step(25)
+            o = orc.observables()
+            Es.append(o["E_ex"])
+            Ms.append(o["m_abs"])
+    E_ld, M_ld = float(np.mean(Es)), float(np.mean(Ms))
+    assert abs(E_ld - E_mc) < 0.03 * abs(E_mc), (E_ld, E_mc)
+    assert abs(M_ld - M_mc) < 0.02, (M_ld, M_mc)
+
+
 def test_two_species_fdt_equilibrium():
     """Two moments (1.92 and 7.63 mu_B) in one ferromagnetic lattice at one
     bath temperature: with the 1/sqrt(mu) noise both spin temperatures equal
