@@ -251,8 +251,14 @@ typedef struct sl_tuning {
     int32_t merge_sweeps;     /* 1 (default): a single run on the multi-kernel
                                  step applies the last colour half step of a
                                  step together with the next step's first, in
-                                 chunks ending on every sample step; 0: one
-                                 launch per colour pass.  Same bits either way */
+                                 chunks ending on every sample step, and (with
+                                 at most 4096 electron cells) ends each step of
+                                 a chunk inside the next step's first colour
+                                 pass; 0: one launch per colour pass and a step
+                                 end per step.  Same bits either way, except
+                                 that a negative electron energy met at a step
+                                 end inside a chunk stops the run one step
+                                 later (SL_ENUMERIC either way)               */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of

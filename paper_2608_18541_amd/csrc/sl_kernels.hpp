@@ -14,7 +14,11 @@
 //                          positions go to the other of two buffers).  In a
 //                          merged chunk a step leaves its last pass (colour
 //                          0, half step) to the next step's pass 0, which
-//                          applies it before its own: 2C-2 passes per step
+//                          applies it before its own: 2C-2 passes per step;
+//                          when the chunk is folded, extra blocks of pass 0
+//                          also end the previous step (small electron grid,
+//                          bins, flags) while its spin blocks compute the
+//                          new T_e of their cells from the same inputs
 //   k_nbr_bin, k_nbr_sort  binning for a rebuild (large engines; exit at
 //                          once unless a rebuild is flagged)
 //   k_atom_final           Verlet-list rebuild of its own atoms when flagged,
@@ -26,7 +30,8 @@
 //   k_grid                 laser source and electron-phonon energy per
 //                          cell of large grids
 //   k_finalize             one block per run: small grids, the observable
-//                          sample, the step counter
+//                          sample, the step counter (in a folded chunk only
+//                          after its last step)
 // or, for runs small enough to live in LDS, k_persist: one block per run
 // advancing many steps in one launch.  A run is initialised (and restored
 // from a checkpoint) by k_init_lattice, k_nbr_bin, k_nbr_sort, k_nbr_build,
@@ -60,7 +65,9 @@ struct RunState {
     int32_t bin_over;    // a bin overflowed while binning this step
     int32_t pending;     // the last half step (colour 0) of step `step - 1` is deferred
                          // to the next colour pass 0, which applies it first
-    int32_t pad_;
+    int32_t chunk_done;  // steps of the current folded chunk that have ended
+    int32_t neg_at;      // 1 + position in the current folded chunk of the first step
+                         // end that met a negative electron energy (0: none)
 };
 
 // Wrapped absolute position of an atom, padded to a 16/32-byte vector so a
@@ -106,6 +113,7 @@ template <typename T> struct RunDev {
     int32_t *bin_n, *bin_atoms;      // [nbins], [nbins][bin_cap]
     double *Te, *ee, *Te_alt;        // T_e, energy density, diffusion ping-pong buffer
     unsigned long long* dE;
+    unsigned long long* dE_alt;      // second electron-phonon sum buffer (folded chunks)
     double* partial;
     int32_t n_part;
     sl_obs* ring;
@@ -467,6 +475,43 @@ template <typename T> __device__ inline bool run_active(const RunDev<T>& R, int6
     return st->err == 0 && st->step < st->target;
 }
 
+// Folded chunks (a single run on the multi-kernel step): the run's step
+// counter holds the chunk's first step until the chunk ends, and a kernel
+// at position k of the chunk works on step counter + k.  The electron
+// temperatures and electron-phonon sums of position k live in the first or
+// second buffer by the parity of k (a fixed grid keeps one buffer).
+template <typename T> __device__ inline int64_t step_at(const RunDev<T>& R, int fold_k)
+{
+    return R.st->step + (fold_k > 0 ? fold_k : 0);
+}
+// Whether no error stops the run at position k of a folded chunk (k < 0:
+// outside one).  The end of step k - 1 runs in the same launch as the first
+// colour pass of step k, so a negative electron energy it meets is recorded
+// with its position and stops the run from step k + 1 on: every kernel of
+// step k reads the same answer whenever the record is written.
+__device__ inline bool fold_ok(const RunState* st, int k)
+{
+    if (st->err != 0) return false;
+    if (k < 0) return true;
+    const int32_t neg = st->neg_at;
+    return neg == 0 || neg > k;
+}
+// End of a folded chunk: a recorded negative energy becomes the run's error.
+__device__ inline void fold_close(RunState* st)
+{
+    if (st->neg_at != 0) st->err |= ERR_NEG_E;
+    st->neg_at = 0;
+    st->chunk_done = 0;
+}
+template <typename T> __device__ inline double* te_buf(const RunDev<T>& R, int fold_k)
+{
+    return (R.ttm_mode == 1 && fold_k > 0 && (fold_k & 1)) ? R.Te_alt : R.Te;
+}
+template <typename T> __device__ inline unsigned long long* de_buf(const RunDev<T>& R, int fold_k)
+{
+    return (fold_k > 0 && (fold_k & 1)) ? R.dE_alt : R.dE;
+}
+
 // ------------------------------------------------------------ spins
 // Update of site l of a colour: field from the current neighbours, thermal
 // field from the step's Philox block (drawn whenever the run has a thermal
@@ -478,7 +523,17 @@ template <typename T> __device__ inline bool run_active(const RunDev<T>& R, int6
 struct PrevHalf {
     const uint16_t* cell;    // electron cells of the previous step's positions
     const double* Te;        // the previous step's electron temperatures
+    // folded chunks: this step's T_e is not written yet (the end of the
+    // previous step runs in the same launch), so a site computes its cell's
+    // value from the previous step's T_e and electron-phonon sum
+    const unsigned long long* dE;   // non-null: compute T_e of this step
 };
+
+template <typename T>
+__device__ inline double cell_energy(const RunDev<T>& R, double e0, unsigned long long raw, int c,
+                                     int64_t step);
+template <typename T> __device__ inline double cell_e0(const RunDev<T>& R, double T0);
+__device__ inline double cell_temp(double e, double ge);
 
 template <typename T, typename VW, int LAT, bool MULTI>
 __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int colour, T tau,
@@ -521,7 +576,16 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
         s = rotate(s, step - 1, Te, R.tau_half);
     }
     if (cur) {
-        const double Te = R.noisy ? M::ld(V.Te, (uint32_t)M::ld(V.cell, idx)) : 0.0;
+        double Te = 0.0;
+        if (R.noisy) {
+            const uint32_t cc = (uint32_t)M::ld(V.cell, idx);
+            if (prev.dE != nullptr)
+                Te = cell_temp(cell_energy(R, cell_e0(R, gld(prev.Te, cc)), gld(prev.dE, cc), (int)cc,
+                                           step - 1),
+                               R.gamma_e);
+            else
+                Te = M::ld(V.Te, cc);
+        }
         s = rotate(s, step, Te, tau);
     }
     M::st(V.sx + kH, l, s.x);
@@ -1002,23 +1066,46 @@ __device__ inline void diffuse_cell(const RunDev<T>& R, const double* src, doubl
 // Laser source and electron-phonon energy of one cell (two-temperature
 // mode): e = (after diffusion, or gamma_e T^2 / 2) + dt S(z, t + dt/2)
 // - dE / V, T_e = sqrt(2 e / gamma_e).  dE is the cell's fixed-point sum.
+// Electron energy density of cell c after step `step`, from the density e0
+// before it (gamma_e T^2 / 2 when the electrons do not diffuse), the laser
+// source at mid-step and the cell's electron-phonon sum (fixed point).
 template <typename T>
-__device__ inline void cell_update_from(const RunDev<T>& R, double T0, unsigned long long raw, double* Te,
-                                        unsigned long long* dEsum, int c, int64_t step,
-                                        double* Te_prev = nullptr)
+__device__ inline double cell_energy(const RunDev<T>& R, double e0, unsigned long long raw, int c,
+                                     int64_t step)
 {
-    const double ge = R.gamma_e;
-    if (Te_prev != nullptr) Te_prev[c] = T0;   // kept for a deferred spin half step
-    const double e0 = R.kappa_e != 0.0 ? R.ee[c] : 0.5 * ge * T0 * T0;
     const int k = c / (R.tn[0] * R.tn[1]);
     const double tmid = ((double)step + 0.5) * R.dtd;
     const double src = laser_power(R, (k + 0.5) * R.th[2], tmid);
     const double de = (double)(long long)raw / kFIX;
-    dEsum[c] = 0ull;
-    const double e = e0 + R.dtd * src - de / R.Vcell;
+    return e0 + R.dtd * src - de / R.Vcell;
+}
+template <typename T> __device__ inline double cell_e0(const RunDev<T>& R, double T0)
+{
+    return 0.5 * R.gamma_e * T0 * T0;
+}
+__device__ inline double cell_temp(double e, double ge)
+{
+    return sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
+}
+
+// neg_k >= 0: the update ends a step inside a folded chunk at position
+// neg_k, where a negative energy is recorded by position (fold_ok).
+template <typename T>
+__device__ inline void cell_update_from(const RunDev<T>& R, double T0, unsigned long long raw, double* Te,
+                                        unsigned long long* dEsum, int c, int64_t step,
+                                        double* Te_prev = nullptr, int neg_k = -1)
+{
+    const double ge = R.gamma_e;
+    if (Te_prev != nullptr) Te_prev[c] = T0;   // kept for a deferred spin half step
+    const double e0 = R.kappa_e != 0.0 ? R.ee[c] : cell_e0(R, T0);
+    if (dEsum != nullptr) dEsum[c] = 0ull;
+    const double e = cell_energy(R, e0, raw, c, step);
     R.ee[c] = e;
-    if (e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
-    Te[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / ge);
+    if (e < 0.0) {
+        if (neg_k >= 0) atomicCAS(&R.st->neg_at, 0, neg_k + 1);
+        else atomicOr(&R.st->err, ERR_NEG_E);
+    }
+    Te[c] = cell_temp(e, ge);
 }
 
 template <typename T>
@@ -1039,7 +1126,7 @@ struct SampleScratch {
     double red[3][kBlock];
     double tot[NQ];
     int64_t step;
-    int32_t go, rebuild;
+    int32_t go, rebuild, done;
 };
 
 template <typename T, typename VW>
@@ -1145,17 +1232,57 @@ template <typename T> __device__ inline bool sample_due(const RunDev<T>& R, int 
 // still see the cells of x^n), the skin check and binning.  They read no
 // spin and the spin blocks read no lattice array.  `merge` (pass 0): apply
 // the previous step's deferred last half step first.
+// The end of step k - 1 of a folded chunk, by the nf extra blocks of colour
+// pass 0 of step k (k >= 1; this is block f of them, one thread per cell):
+// the small electron grid from the buffers of position k - 1 into those of
+// position k (the sums of position k - 1 are read by this pass's spin
+// blocks and cleared by the force kernel of step k), the bins emptied (when
+// no binning has filled them since they were last emptied they are empty
+// already, so no block needs the rebuild flag that the first block clears)
+// and the flags cleared.  Chunks end on sample steps, so no sample falls
+// here; the step counter moves at the chunk's end.
+template <typename T> __device__ inline void fold_end_step(const RunDev<T>& R, int k, int f, int nf)
+{
+    RunState* st = R.st;
+    const int64_t step = st->step + k - 1;
+    if (!fold_ok(st, k - 1) || step >= st->target) return;
+    const int t = f * (int)blockDim.x + (int)threadIdx.x, nt = nf * (int)blockDim.x;
+    if (R.ttm_mode == 1) {
+        const double* Tp = te_buf(R, k - 1);
+        const unsigned long long* Ep = de_buf(R, k - 1);
+        double* Tn = te_buf(R, k);
+        for (int c = t; c < R.ncell; c += nt)
+            cell_update_from(R, Tp[c], Ep[c], Tn, (unsigned long long*)nullptr, c, step, nullptr, k);
+    }
+    if (R.live)
+        for (int b = t; b < R.nbins; b += nt) R.bin_n[b] = 0;
+    if (t == 0) {
+        if (R.live) {
+            st->bin_over = 0;
+            st->rebuild = 0;
+        }
+        st->chunk_done = k;
+    }
+}
+
 template <typename T, int SPT>
 __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
                                                       const int2* __restrict__ work, int pass,
                                                       const int2* __restrict__ work_kick,
-                                                      int n_spin_blocks, int merge)
+                                                      int n_spin_blocks, int merge, int fold_k)
 {
     if ((int)blockIdx.x >= n_spin_blocks) {
+        // colour pass 0 at position k >= 1 of a folded chunk: the extra
+        // blocks end step k - 1
+        if (fold_k >= 1 && pass == 0) {
+            fold_end_step(runs[work[0].x], fold_k, (int)blockIdx.x - n_spin_blocks,
+                          (int)gridDim.x - n_spin_blocks);
+            return;
+        }
         const int2 w = work_kick[blockIdx.x - n_spin_blocks];
         const RunDev<T>& R = runs[w.x];
-        int64_t step;
-        if (!run_active(R, &step) || !R.live) return;
+        const int64_t step = step_at(R, fold_k);
+        if (!fold_ok(R.st, fold_k) || step >= R.st->target || !R.live) return;
         const uint32_t i = (uint32_t)w.y + threadIdx.x;
         if (i >= (uint32_t)R.n) return;
         const GView<T> V = global_view(R, step + 1);
@@ -1166,20 +1293,31 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     }
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
-    int64_t step;
-    const bool cur = run_active(R, &step);
+    const RunState* st = R.st;
+    const int64_t step = step_at(R, fold_k);
+    const bool cur = fold_ok(st, fold_k) && step < st->target;
     // colour pass 0 of a merged step first applies the previous step's
-    // deferred last half step (also when the run has just reached its target)
-    const bool prev = merge && pass == 0 && R.st->pending != 0;
+    // deferred last half step (also when the run has just reached its
+    // target): in a folded chunk whenever the previous step ran, otherwise
+    // as recorded by the previous step's end
+    const bool prev = merge && pass == 0 &&
+                      (fold_k >= 0 ? fold_k >= 1 && fold_ok(st, fold_k - 1) && step - 1 < st->target
+                                   : st->pending != 0);
     if (!cur && !prev) return;
     if (pass >= 2 * R.g.C - 1) return;
     int colour;
     T tau;
     pass_colour(R, pass, &colour, &tau);
-    const GView<T> V = global_view(R, step);
-    // T_e of the previous step: kept by the grid update in the diffusion
+    GView<T> V = global_view(R, step);
+    if (fold_k >= 0) V.Te = te_buf(R, fold_k);
+    // T_e of the previous step: in a folded chunk the previous position's
+    // buffer (and this step's T_e is computed from it, its end running in
+    // this launch); otherwise kept by the grid update in the diffusion
     // buffer (runs that merge do not diffuse); a fixed grid never changes
-    const PrevHalf ph{R.cellb[(step - 1) & 1], R.ttm_mode == 1 ? R.Te_alt : R.Te};
+    PrevHalf ph{R.cellb[(step - 1) & 1], R.ttm_mode == 1 ? R.Te_alt : R.Te, nullptr};
+    if (fold_k >= 1 && pass == 0)
+        ph = PrevHalf{R.cellb[(step - 1) & 1], te_buf(R, fold_k - 1),
+                      R.ttm_mode == 1 ? de_buf(R, fold_k - 1) : nullptr};
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
@@ -1208,12 +1346,13 @@ __global__ __launch_bounds__(kBlock) void k_init_lattice(const RunDev<T>* __rest
 // runs whose kick does not bin (exits at once unless a rebuild is flagged).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict__ runs,
-                                                    const int2* __restrict__ work, int phase)
+                                                    const int2* __restrict__ work, int phase,
+                                                    int fold_k)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
-    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    if (phase == PHASE_STEP && (R.bin_step || R.st->step >= R.st->target)) return;
+    if (!R.live || R.st->rebuild == 0 || !fold_ok(R.st, fold_k)) return;
+    if (phase == PHASE_STEP && (R.bin_step || step_at(R, fold_k) >= R.st->target)) return;
     const uint32_t i = (uint32_t)w.y + threadIdx.x;
     if (i < (uint32_t)R.n) nbr_bin_atom(R, global_view(R, 0), i);
 }
@@ -1223,12 +1362,13 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict_
 // does not bin.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict__ runs,
-                                                     const int2* __restrict__ work, int phase)
+                                                     const int2* __restrict__ work, int phase,
+                                                     int fold_k)
 {
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
-    if (!R.live || R.st->rebuild == 0 || R.st->err != 0) return;
-    if (phase == PHASE_STEP && (R.bin_step || R.st->step >= R.st->target)) return;
+    if (!R.live || R.st->rebuild == 0 || !fold_ok(R.st, fold_k)) return;
+    if (phase == PHASE_STEP && (R.bin_step || step_at(R, fold_k) >= R.st->target)) return;
     for (uint32_t b = (uint32_t)w.y + threadIdx.x; b < (uint32_t)R.nbins; b += (uint32_t)R.n)
         nbr_sort_bin(R, (int)b);
 }
@@ -1264,7 +1404,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
 template <typename T, int LPA>
 __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work, int phase,
-                                                       int sorted_bins)
+                                                       int sorted_bins, int fold_k)
 {
     __shared__ ObsTerms ostage[LPA > 1 ? kBlock / LPA : 1];
     // the list build's per-thread bin buffers and the per-cell sums are never
@@ -1284,8 +1424,8 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
     RunState* st = R.st;
     // the run's state, read once for the block
     if (threadIdx.x == 0) {
-        b_step = st->step;
-        b_go = phase != PHASE_STEP || (st->err == 0 && b_step < st->target);
+        b_step = step_at(R, fold_k);
+        b_go = phase != PHASE_STEP || (fold_ok(st, fold_k) && b_step < st->target);
         b_rebuild = phase == PHASE_STEP && R.live && st->rebuild != 0 ? (st->bin_over ? 2 : 1) : 0;
     }
     __syncthreads();
@@ -1316,7 +1456,18 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         // not matter), then one global atomic per touched cell; a block whose
         // span exceeds the LDS table adds to the global sums directly
         const bool eph = phase == PHASE_STEP && R.live && R.ttm_mode == 1;
-        const GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
+        GView<T> V = global_view(R, phase == PHASE_INIT ? step : step + 1);
+        unsigned long long* const dE = fold_k >= 0 ? de_buf(R, fold_k) : R.dE;
+        if (fold_k >= 0) V.Te = te_buf(R, fold_k);
+        if (eph && fold_k >= 1) {
+            // the previous position's sums, read by this step's colour pass
+            // 0, are cleared for position k + 1
+            unsigned long long* const old = de_buf(R, fold_k - 1);
+            const uint32_t nb = ((uint32_t)R.n + apb - 1) / apb;
+            for (uint32_t c = (uint32_t)w.y / apb * blockDim.x + threadIdx.x; c < (uint32_t)R.ncell;
+                 c += nb * blockDim.x)
+                old[c] = 0ull;
+        }
         uint32_t c_lo = 0, c_span = 0;
         if (eph) {
             const bool mine = i < (uint32_t)R.n;
@@ -1348,12 +1499,12 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         }
         ObsTerms o{};
         if (i < (uint32_t)R.n)
-            atom_final_atom<T, GView<T>, LPA>(R, V, i, phase, step, obs, lds_acc ? cacc : R.dE, o, lj,
+            atom_final_atom<T, GView<T>, LPA>(R, V, i, phase, step, obs, lds_acc ? cacc : dE, o, lj,
                                               lds_acc ? c_lo : 0u);
         if (lds_acc) {
             __syncthreads();
             for (uint32_t c = threadIdx.x; c < c_span; c += blockDim.x)
-                if (cacc[c] != 0ull) atomicAdd(&R.dE[c_lo + c], cacc[c]);
+                if (cacc[c] != 0ull) atomicAdd(&dE[c_lo + c], cacc[c]);
         }
         if (obs) {
             if constexpr (LPA == 1) {
@@ -1406,33 +1557,57 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
 // must take the same branch at the barriers).
 // `deferred`: this step's last colour half step is left to the next step's
 // colour pass 0 (recorded in the run state for it).
+// fold_k >= 0: the last step (position fold_k) of a folded chunk, whose
+// electron temperatures and sums are in that position's buffers; the step
+// counter moves to the end of the chunk, or, when the run stopped inside
+// it, past the last step that ended, whose temperatures are moved to the
+// first buffer.
 template <typename T>
-__device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase, int deferred = 0)
+__device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase, int deferred = 0,
+                                int fold_k = -1)
 {
     RunState* st = R.st;
     const int tid = threadIdx.x;
+    const bool grid = phase == PHASE_STEP && R.ttm_mode == 1 && R.ncell <= kSmallGrid;
+    const double* const srcT = fold_k >= 0 ? te_buf(R, fold_k) : R.Te;
+    unsigned long long* const srcE = fold_k >= 0 ? de_buf(R, fold_k) : R.dE;
     // this thread's first two cells of a small grid, loaded before the state
     // is known (they were written by earlier launches) so that the two
     // memory round trips overlap
-    const bool grid = phase == PHASE_STEP && R.ttm_mode == 1 && R.ncell <= kSmallGrid;
     double pT[2] = {0.0, 0.0};
     unsigned long long pE[2] = {0ull, 0ull};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int c = tid + q * (int)blockDim.x;
         if (grid && c < R.ncell) {
-            pT[q] = R.Te[c];
-            pE[q] = R.dE[c];
+            pT[q] = srcT[c];
+            pE[q] = srcE[c];
         }
     }
     if (tid == 0) {
-        S.step = st->step;
-        S.go = phase != PHASE_STEP || (st->err == 0 && S.step < st->target);
+        S.step = phase == PHASE_STEP ? step_at(R, fold_k) : st->step;
+        S.go = phase != PHASE_STEP || (fold_ok(st, fold_k) && S.step < st->target);
         S.rebuild = st->rebuild;
+        S.done = st->chunk_done;
     }
     __syncthreads();
     if (!S.go) {
-        if (tid == 0 && phase == PHASE_STEP) st->pending = 0;
+        if (phase != PHASE_STEP) return;
+        if (fold_k >= 0 && R.ttm_mode == 1) {
+            // stopped inside a folded chunk after S.done steps
+            for (int c = tid; c < R.ncell; c += blockDim.x) {
+                if (S.done & 1) R.Te[c] = R.Te_alt[c];
+                R.dE[c] = 0ull;
+                R.dE_alt[c] = 0ull;
+            }
+        }
+        if (tid == 0) {
+            st->pending = 0;
+            if (fold_k >= 0) {
+                st->step += S.done;
+                fold_close(st);
+            }
+        }
         return;
     }
     const int64_t step = S.step;
@@ -1441,9 +1616,9 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
         int q = 0;
         for (int c = tid; c < R.ncell; c += blockDim.x, ++q) {
             if (q < 2)
-                cell_update_from(R, pT[q & 1], pE[q & 1], R.Te, R.dE, c, step, keep_prev);
+                cell_update_from(R, pT[q & 1], pE[q & 1], R.Te, srcE, c, step, keep_prev);
             else
-                cell_update(R, R.Te, R.dE, c, step, keep_prev);
+                cell_update_from(R, srcT[c], srcE[c], R.Te, srcE, c, step, keep_prev);
         }
         __syncthreads();
     }
@@ -1462,6 +1637,7 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
         if (phase == PHASE_STEP) {
             st->pending = deferred;
             st->step = step + 1;
+            if (fold_k >= 0) fold_close(st);
         }
     }
 }
@@ -1470,10 +1646,10 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict__ runs,
                                                      const int* __restrict__ run_list, int phase,
-                                                     int deferred)
+                                                     int deferred, int fold_k)
 {
     __shared__ SampleScratch S;
-    end_step(runs[run_list[blockIdx.x]], S, phase, deferred);
+    end_step(runs[run_list[blockIdx.x]], S, phase, deferred, fold_k);
 }
 
 // ==================================================== persistent kernel

@@ -279,6 +279,7 @@ size_t grid_bytes(const Sizes& z)
     Carver c;
     c.take<double>(z.ncell); c.take<double>(z.ncell); c.take<double>(z.ncell);
     c.take<unsigned long long>(z.ncell);
+    c.take<unsigned long long>(z.ncell);
     return c.off;
 }
 
@@ -330,6 +331,8 @@ public:
     int merge_sweeps = 1;           // 1: merge adjacent colour half steps when possible
     int merge_g = 0;                // >= 2: steps per merged chunk (one multi-kernel run)
     int merge_run = -1;             // that run's slot
+    bool fold = false;              // chunks end each step inside the next one's colour pass 0
+    int fold_blocks = 0;            // the blocks of colour pass 0 that end the previous step
     int lanes_eff = 1;              // the lanes in use (tables are built for it)
     virtual sl_status retune() = 0;
 };
@@ -977,6 +980,7 @@ private:
         R.ee = c.take<double>(r.z.ncell);
         R.Te_alt = c.take<double>(r.z.ncell);
         R.dE = c.take<unsigned long long>(r.z.ncell);
+        R.dE_alt = c.take<unsigned long long>(r.z.ncell);
 
         std::vector<double> te(r.z.ncell, t->Te0);
         if (t->Te_init) std::copy(t->Te_init, t->Te_init + r.z.ncell, te.begin());
@@ -1050,6 +1054,7 @@ private:
         SL_HIP(hipMemcpyAsync(R.Te, r.te_init.data(), sizeof(double) * r.z.ncell,
                               hipMemcpyHostToDevice, stream));
         SL_HIP(hipMemsetAsync(R.dE, 0, sizeof(unsigned long long) * r.z.ncell, stream));
+        SL_HIP(hipMemsetAsync(R.dE_alt, 0, sizeof(unsigned long long) * r.z.ncell, stream));
         SL_HIP(hipMemcpyAsync(d_runs + s, &R, sizeof(RD), hipMemcpyHostToDevice, stream));
         // single-run work tables for the initialisation launches
         std::vector<int2> wa;
@@ -1064,12 +1069,12 @@ private:
         const int ga = (int)wa.size();
         sl::k_init_lattice<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         if (R.live) {
-            sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
-            sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT);
+            sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT, -1);
+            sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT, -1);
             sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         }
-        sl::k_atom_final<T, 1><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1);
-        sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT, 0);
+        sl::k_atom_final<T, 1><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1, -1);
+        sl::k_finalize<T><<<1, sl::kBlock, 0, stream>>>(d_runs, drl, sl::PHASE_INIT, 0, -1);
         SL_HIP(hipGetLastError());
         SL_HIP(hipStreamSynchronize(stream));
         alloc.put(tmp);
@@ -1167,8 +1172,14 @@ private:
         // in the diffusion buffer) and chunks of merge_g steps can end on
         // every sample step (merge_g divides obs_every); chunks start at
         // multiples of merge_g
+        // Within a chunk each step's end (small electron grid, bins, flags)
+        // also runs as one extra block of the next step's colour pass 0,
+        // which computes the new T_e of its sites from the same inputs; the
+        // chunk's last step ends in k_finalize.  Larger grids keep their
+        // cell-parallel update.
         merge_g = 0;
         merge_run = -1;
+        fold = false;
         if (merge_sweeps && rl.size() == 1) {
             const RD& R = host_rd[rl[0]];
             if (!(R.ttm_mode == 1 && R.kappa_e != 0.0)) {
@@ -1182,6 +1193,11 @@ private:
                 if (g >= 2) {
                     merge_g = g;
                     merge_run = rl[0];
+                    fold = !(R.ttm_mode == 1 && R.ncell > sl::kSmallGrid);
+                    // one thread per electron cell, four bins per thread
+                    const int cells = R.ttm_mode == 1 ? R.ncell : 0;
+                    const int bins = R.live ? (R.nbins + 3) / 4 : 0;
+                    fold_blocks = std::max(1, (std::max(cells, bins) + spin_eff - 1) / spin_eff);
                 }
             }
         }
@@ -1250,7 +1266,10 @@ private:
     // merge_first: colour pass 0 applies the previous step's deferred last
     // half step first; defer_last: this step's last colour pass is left to
     // the next step's pass 0.  The lattice kick rides on colour pass 1.
-    sl_status enqueue_step(hipStream_t st, Prof* p, bool merge_first = false, bool defer_last = false)
+    // fold_k >= 0: position of the step in a folded chunk (its pass 0 ends
+    // the previous step, and only the chunk's last step has a k_finalize).
+    sl_status enqueue_step(hipStream_t st, Prof* p, bool merge_first = false, bool defer_last = false,
+                           int fold_k = -1)
     {
         const int C = max_colours();
         // the atom table's tiles hold atom_block / atom_lanes atoms: the
@@ -1260,18 +1279,18 @@ private:
             if (defer_last && pass == 2 * C - 2) break;
             const int merge = merge_first && pass == 0 ? 1 : 0;
             const bool fused = pass == 1 && active_blocks_kick > 0;
-            const int nk = fused ? active_blocks_kick : 0;
+            const int nk = fused ? active_blocks_kick : (pass == 0 && fold_k >= 1 ? fold_blocks : 0);
             sl_status e = timed(st, p, fused ? 2 : 0, [&](hipEvent_t a, hipEvent_t b) {
                 const dim3 g(active_blocks_spin + nk);
                 if (spin_spt == 4)
                     launch(sl::k_spin_pass<T, 4>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin, merge);
+                           d_work_kick, active_blocks_spin, merge, fold_k);
                 else if (spin_spt == 2)
                     launch(sl::k_spin_pass<T, 2>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin, merge);
+                           d_work_kick, active_blocks_spin, merge, fold_k);
                 else
                     launch(sl::k_spin_pass<T, 1>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin, merge);
+                           d_work_kick, active_blocks_spin, merge, fold_k);
             });
             if (e != SL_OK) return e;
         }
@@ -1279,11 +1298,13 @@ private:
         sl_status e;
         if (active_blocks_kick > 0 && !bin_each_step) {
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_bin<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
+                launch(sl::k_nbr_bin<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
+                       fold_k);
             });
             if (e != SL_OK) return e;
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_sort<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP);
+                launch(sl::k_nbr_sort<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
+                       fold_k);
             });
             if (e != SL_OK) return e;
         }
@@ -1291,13 +1312,13 @@ private:
             const int sorted = bin_each_step ? 0 : 1;
             if (lanes_eff == 4)
                 launch(sl::k_atom_final<T, 4>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       (int)sl::PHASE_STEP, sorted);
+                       (int)sl::PHASE_STEP, sorted, fold_k);
             else if (lanes_eff == 2)
                 launch(sl::k_atom_final<T, 2>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       (int)sl::PHASE_STEP, sorted);
+                       (int)sl::PHASE_STEP, sorted, fold_k);
             else
                 launch(sl::k_atom_final<T, 1>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       (int)sl::PHASE_STEP, sorted);
+                       (int)sl::PHASE_STEP, sorted, fold_k);
         });
         if (e != SL_OK) return e;
         for (int sub = 0; sub < max_sub; ++sub) {
@@ -1313,9 +1334,10 @@ private:
             });
             if (e != SL_OK) return e;
         }
+        if (fold_k >= 0 && fold_k < merge_g - 1) return SL_OK;
         e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
             launch(sl::k_finalize<T>, dim3(active_runs), bk, 0, st, a, b, d_runs, d_run_list,
-                   (int)sl::PHASE_STEP, defer_last ? 1 : 0);
+                   (int)sl::PHASE_STEP, defer_last ? 1 : 0, fold_k);
         });
         return e;
     }
@@ -1326,7 +1348,7 @@ private:
     sl_status enqueue_chunk(hipStream_t st, Prof* p)
     {
         for (int k = 0; k < merge_g; ++k) {
-            sl_status e = enqueue_step(st, p, k > 0, k < merge_g - 1);
+            sl_status e = enqueue_step(st, p, k > 0, k < merge_g - 1, fold ? k : -1);
             if (e != SL_OK) return e;
         }
         return SL_OK;

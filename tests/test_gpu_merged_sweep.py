@@ -114,3 +114,30 @@ def test_merge_knob_same_bits(N):
     assert [o["step"] for o in out[0][1]] == [o["step"] for o in out[1][1]]
     for a, b in zip(out[0][1], out[1][1]):
         assert a["E_ex"] == b["E_ex"] and a["m_abs"] == b["m_abs"] and a["Te_mean"] == b["Te_mean"]
+
+
+def test_negative_electron_energy_inside_a_chunk(N):
+    """Electrons at 600 K with a hundredth of the alloy's heat capacity over
+    a lattice at 0 K give their energy away within about twenty steps (the
+    oracle meets a negative energy density after 18), until one step's
+    transfer exceeds what is left: the run stops with a negative electron
+    energy.  Stepped one by one (samples every step) it stops at the step
+    whose end met it.  In chunks of ten, where a step's end runs with the
+    next step's first colour pass, an end inside the chunk stops the run
+    one step later; the chunk's own last end stops it at once."""
+    spec = I.gdfeco_sc_spec(L=6, tn=2, gamma_e=I.j_per_m3k2_to_metal(2.25), Te0=600.0, seed=9,
+                           run_id=1)
+    st = I.initial_state(spec, "afm", T_lattice=0.0)
+    steps = []
+    for every in (1, 10):
+        _log("case: negative energy, obs_every=%d" % every)
+        g = N.System(spec, st, precision=0, obs_every=every)
+        with pytest.raises(N.SLError) as e:
+            g.step(200)
+            g.synchronize()
+        assert e.value.code == N.SL_ENUMERIC and "negative electron energy" in str(e.value)
+        steps.append(g.stats()["steps"])
+        g.close()
+    u, f = steps
+    assert 10 < u < 40, steps
+    assert f == u + (1 if u % 10 else 0), steps
