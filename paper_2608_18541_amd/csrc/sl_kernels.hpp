@@ -1225,13 +1225,6 @@ template <typename T> __device__ inline bool sample_due(const RunDev<T>& R, int 
 }
 
 // ==================================================== multi-kernel step
-// Colour pass `pass` over the sites of every active run.  Blocks from
-// n_spin_blocks on (the launch of pass 1 carries them when lattices are
-// live) take atoms instead: half kick, drift, the electron cell of the new
-// position (into the other cell buffer, so the spin blocks of this launch
-// still see the cells of x^n), the skin check and binning.  They read no
-// spin and the spin blocks read no lattice array.  `merge` (pass 0): apply
-// the previous step's deferred last half step first.
 // The end of step k - 1 of a folded chunk, by the nf extra blocks of colour
 // pass 0 of step k (k >= 1; this is block f of them, one thread per cell):
 // the small electron grid from the buffers of position k - 1 into those of
@@ -1265,6 +1258,14 @@ template <typename T> __device__ inline void fold_end_step(const RunDev<T>& R, i
     }
 }
 
+// Colour pass `pass` over the sites of every active run.  Blocks from
+// n_spin_blocks on (the launch of pass 1 carries them when lattices are
+// live) take atoms instead: half kick, drift, the electron cell of the new
+// position (into the other cell buffer, so the spin blocks of this launch
+// still see the cells of x^n), the skin check and binning.  They read no
+// spin and the spin blocks read no lattice array.  In a folded chunk the
+// extra blocks of pass 0 end the previous step instead (fold_end_step).
+// `merge` (pass 0): apply the previous step's deferred last half step first.
 template <typename T, int SPT>
 __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
                                                       const int2* __restrict__ work, int pass,
