@@ -25,8 +25,11 @@
 //                          Morse forces, half kick, electron-phonon
 //                          Ornstein-Uhlenbeck step and its mean energy per
 //                          electron cell, observable partials
-//   k_ttm_diffuse x n_sub  explicit electron diffusion sub-steps (runs with
-//                          kappa_e > 0 only)
+//   k_ttm_tile             all explicit electron diffusion sub-steps of a
+//                          step in one launch, tiled with halos in LDS (runs
+//                          with kappa_e > 0), or
+//   k_ttm_diffuse x n_sub  one launch per sub-step when a tile and its halo
+//                          do not fit
 //   k_grid                 laser source and electron-phonon energy per
 //                          cell of large grids
 //   k_finalize             one block per run: small grids, the observable
@@ -100,7 +103,11 @@ template <typename T> struct RunDev {
     double cnt[4];       // sites per species
     // electron grid
     int32_t tn[3], ncell, n_sub, profile;
+    int32_t dtile[3], dntile[3];     // diffusion tiles (cells per axis, tiles per axis);
+                                     // dtile[0] == 0: one launch per sub-step instead
     double th[3], gamma_e, kappa_e, S0, t0, fwhm, Vcell, depth, dtd;
+    double dcoef[3];     // (dt / n_sub) kappa_e / h_d^2 per axis
+    double two_ge;       // 2 / gamma_e
     // neighbour bins
     int32_t nbin[3], nbins, bin_cap, max_nbr;
     T binw[3];
@@ -510,6 +517,12 @@ template <typename T> __device__ inline double* te_buf(const RunDev<T>& R, int f
 template <typename T> __device__ inline unsigned long long* de_buf(const RunDev<T>& R, int fold_k)
 {
     return (fold_k > 0 && (fold_k & 1)) ? R.dE_alt : R.dE;
+}
+// Whether the grid update keeps the step's T_e in the second buffer for a
+// deferred spin half step: unless sub-step launches use it for diffusion.
+template <typename T> __device__ inline bool keeps_prev_te(const RunDev<T>& R)
+{
+    return R.kappa_e == 0.0 || R.dtile[0] > 0;
 }
 
 // ------------------------------------------------------------ spins
@@ -1038,9 +1051,30 @@ template <typename T> __device__ inline double laser_power(const RunDev<T>& R, d
     return R.S0 * exp(-4.0 * 0.69314718055994530942 * d * d / (R.fwhm * R.fwhm));
 }
 
-// One explicit diffusion sub-step of cell c of e = gamma_e T^2 / 2 with the
-// periodic 7-point Laplacian of src, written to dst.  The first sub-step
-// of a step starts e from the current T.
+// Electron energy density of a cell after one explicit diffusion sub-step:
+// e0 + (dt / n_sub) kappa_e times the 7-point Laplacian of T at the cell
+// (its temperature Tc and its six neighbours'), with the per-axis factors
+// (dt / n_sub) kappa_e / h^2 precomputed.  The first sub-step of a step
+// starts from e0 = gamma_e Tc^2 / 2 (diffuse_e0); the cell's temperature
+// after it is sqrt(2 e / gamma_e) (diffuse_temp).
+template <typename T>
+__device__ inline double diffuse_energy(const RunDev<T>& R, double Tc, double xp, double xm, double yp,
+                                     double ym, double zp, double zm, double e0)
+{
+    return e0 + R.dcoef[0] * (xp - 2.0 * Tc + xm) + R.dcoef[1] * (yp - 2.0 * Tc + ym) +
+           R.dcoef[2] * (zp - 2.0 * Tc + zm);
+}
+template <typename T> __device__ inline double diffuse_temp(const RunDev<T>& R, double e)
+{
+    return sqrt(R.two_ge * (e > 0.0 ? e : 0.0));
+}
+template <typename T>
+__device__ inline double diffuse_e0(const RunDev<T>& R, double Tc)
+{
+    return 0.5 * R.gamma_e * Tc * Tc;
+}
+
+// One sub-step of cell c with the periodic Laplacian of src, written to dst.
 template <typename T>
 __device__ inline void diffuse_cell(const RunDev<T>& R, const double* src, double* dst, int c, int sub)
 {
@@ -1051,22 +1085,19 @@ __device__ inline void diffuse_cell(const RunDev<T>& R, const double* src, doubl
     const int kp = (k + 1) % n2, km = (k + n2 - 1) % n2;
     const int row = (k * n1 + j) * n0;
     const double Tc = src[c];
-    const double lap = (src[row + ip] - 2.0 * Tc + src[row + im]) / (R.th[0] * R.th[0]) +
-                       (src[(k * n1 + jp) * n0 + i] - 2.0 * Tc + src[(k * n1 + jm) * n0 + i]) /
-                           (R.th[1] * R.th[1]) +
-                       (src[(kp * n1 + j) * n0 + i] - 2.0 * Tc + src[(km * n1 + j) * n0 + i]) /
-                           (R.th[2] * R.th[2]);
-    const double e0 = sub == 0 ? 0.5 * R.gamma_e * Tc * Tc : R.ee[c];
-    const double e = e0 + (R.dtd / (double)R.n_sub) * R.kappa_e * lap;
+    const double e0 = sub == 0 ? diffuse_e0(R, Tc) : R.ee[c];
+    const double e = diffuse_energy(R, Tc, src[row + ip], src[row + im], src[(k * n1 + jp) * n0 + i],
+                                    src[(k * n1 + jm) * n0 + i], src[(kp * n1 + j) * n0 + i],
+                                    src[(km * n1 + j) * n0 + i], e0);
     R.ee[c] = e;
     if (e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
-    dst[c] = sqrt(2.0 * (e > 0.0 ? e : 0.0) / R.gamma_e);
+    dst[c] = diffuse_temp(R, e);
 }
 
 // Laser source and electron-phonon energy of one cell (two-temperature
 // mode): e = (after diffusion, or gamma_e T^2 / 2) + dt S(z, t + dt/2)
 // - dE / V, T_e = sqrt(2 e / gamma_e).  dE is the cell's fixed-point sum.
-// Electron energy density of cell c after step `step`, from the density e0
+// cell_energy: the electron energy density of cell c after step `step`, from the density e0
 // before it (gamma_e T^2 / 2 when the electrons do not diffuse), the laser
 // source at mid-step and the cell's electron-phonon sum (fixed point).
 template <typename T>
@@ -1538,6 +1569,85 @@ __global__ __launch_bounds__(kBlock) void k_ttm_diffuse(const RunDev<T>* __restr
     diffuse_cell(R, (sub & 1) ? R.Te_alt : R.Te, (sub & 1) ? R.Te : R.Te_alt, c, sub);
 }
 
+// All diffusion sub-steps of one tile of a run's electron grid in one launch
+// (temporal blocking).  The temperatures of the tile and of a halo n_sub
+// cells deep (periodic images included) are staged in LDS.  Sub-step s
+// updates the region that is still exact after it, one cell per side
+// smaller each sub-step, so a halo cell is recomputed by every tile that
+// needs it with the arithmetic of the tile that owns it.  Only the tile's
+// own cells are written: their diffused energy density, which the grid
+// update then takes.  No block writes the temperatures during the launch,
+// so every halo reads the same grid.
+// The region is at most kTileSide cells along x and y (tile + 2 n_sub), laid
+// out padded to kTileSide so that a thread's cell column is (x, y) =
+// (thread mod 16, thread / 16 mod 16); the block's kTileBlock / 256 thread
+// layers split the z range.
+constexpr int kTileSide = 16;
+constexpr int kTileBlock = 1024;
+template <typename T>
+__global__ __launch_bounds__(kTileBlock) void k_ttm_tile(const RunDev<T>* __restrict__ runs,
+                                                         const int2* __restrict__ work)
+{
+    extern __shared__ double tl[];
+    __shared__ int32_t b_go;
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    if (threadIdx.x == 0) {
+        int64_t step;
+        b_go = run_active(R, &step) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!b_go) return;
+    const int h = R.n_sub;
+    const int n0 = R.tn[0], n1 = R.tn[1], n2 = R.tn[2];
+    const int t0 = R.dtile[0], t1 = R.dtile[1], t2 = R.dtile[2];
+    const int a0 = w.y % R.dntile[0], a1 = (w.y / R.dntile[0]) % R.dntile[1],
+              a2 = w.y / (R.dntile[0] * R.dntile[1]);
+    const int D0 = t0 + 2 * h, D1 = t1 + 2 * h, D2 = t2 + 2 * h;
+    constexpr int S = kTileSide, P = kTileSide * kTileSide;
+    const int vol = P * D2;
+    // grid coordinates of region cell (0, 0, 0), and the tile's own extent
+    // (the last tile along an axis may be cut by the grid's edge)
+    const int o0 = a0 * t0 - h, o1 = a1 * t1 - h, o2 = a2 * t2 - h;
+    const int w0 = min(t0, n0 - a0 * t0), w1 = min(t1, n1 - a1 * t1), w2 = min(t2, n2 - a2 * t2);
+    double* A = tl;
+    double* B = tl + vol;
+    double* const E = tl + 2 * vol;
+    const int x = (int)threadIdx.x & (S - 1), y = ((int)threadIdx.x / S) & (S - 1);
+    const int zg = (int)threadIdx.x / P, nz = (int)blockDim.x / P;
+    if (x < D0 && y < D1) {
+        const int gx = ((o0 + x) % n0 + n0) % n0, gy = ((o1 + y) % n1 + n1) % n1;
+        for (int z = zg; z < D2; z += nz) {
+            const int gz = ((o2 + z) % n2 + n2) % n2;
+            A[z * P + y * S + x] = R.Te[(gz * n1 + gy) * n0 + gx];
+        }
+    }
+    __syncthreads();
+    const bool own_col = x >= h && x < h + w0 && y >= h && y < h + w1;
+    for (int sub = 0; sub < h; ++sub) {
+        const int lo = sub + 1;
+        if (x >= lo && x < D0 - lo && y >= lo && y < D1 - lo) {
+            for (int z = lo + zg; z < D2 - lo; z += nz) {
+                const int r = z * P + y * S + x;
+                const double Tc = A[r];
+                const double e0 = sub == 0 ? diffuse_e0(R, Tc) : E[r];
+                const double e = diffuse_energy(R, Tc, A[r + 1], A[r - 1], A[r + S], A[r - S], A[r + P],
+                                                A[r - P], e0);
+                E[r] = e;
+                B[r] = diffuse_temp(R, e);
+                if (own_col && z >= h && z < h + w2 && e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
+            }
+        }
+        __syncthreads();
+        double* const t = A;
+        A = B;
+        B = t;
+    }
+    if (own_col)
+        for (int z = h + zg; z < h + w2; z += nz)
+            R.ee[((a2 * t2 + z - h) * n1 + (a1 * t1 + y - h)) * n0 + (a0 * t0 + x - h)] = E[z * P + y * S + x];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ runs,
                                                  const int2* __restrict__ work)
@@ -1547,7 +1657,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     int64_t step;
     if (!run_active(R, &step) || R.ttm_mode != 1 || R.ncell <= kSmallGrid) return;
     const int c = w.y + (int)threadIdx.x;
-    if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step, R.kappa_e == 0.0 ? R.Te_alt : nullptr);
+    if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step, keeps_prev_te(R) ? R.Te_alt : nullptr);
 }
 
 
@@ -1613,7 +1723,7 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
     }
     const int64_t step = S.step;
     if (grid) {
-        double* const keep_prev = R.kappa_e == 0.0 ? R.Te_alt : nullptr;
+        double* const keep_prev = keeps_prev_te(R) ? R.Te_alt : nullptr;
         int q = 0;
         for (int c = tid; c < R.ncell; c += blockDim.x, ++q) {
             if (q < 2)

@@ -381,6 +381,11 @@ public:
         lds_max = per_block > static_lds ? (uint32_t)(per_block - static_lds) : 0u;
         for (const void* f : pk)
             SL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
+        const void* tk = reinterpret_cast<const void*>(&sl::k_ttm_tile<T>);
+        hipFuncAttributes ta{};
+        SL_HIP(hipFuncGetAttributes(&ta, tk));
+        tile_lds_max = per_block > (int)ta.sharedSizeBytes ? (uint32_t)(per_block - (int)ta.sharedSizeBytes) : 0u;
+        SL_HIP(hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds_max));
         return SL_OK;
     }
 
@@ -781,10 +786,11 @@ private:
     int2* d_work_kick = nullptr;     // atoms of live runs, in tiles of the colour-pass block
     int2* d_work_cell = nullptr;
     int2* d_work_diff = nullptr;
+    int2* d_work_tile = nullptr;
     int* d_run_list = nullptr;
     int active_runs = 0;
     int active_blocks_spin = 0, active_blocks_atom = 0, active_blocks_kick = 0, active_blocks_cell = 0,
-        active_blocks_diff = 0;
+        active_blocks_diff = 0, active_blocks_tile = 0;
     int max_sub = 0;
     bool any_live = false;
     hipGraphExec_t exec = nullptr;
@@ -794,6 +800,8 @@ private:
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint32_t lds_max = 0;
+    uint32_t tile_lds_max = 0;      // dynamic LDS available to k_ttm_tile
+    uint32_t tile_bytes = 0;        // the LDS its launch takes (largest tile of the table)
     int* d_persist_list = nullptr;
     int persist_runs = 0;
     // the kick bins every step while the engine's live atoms are few (one
@@ -964,6 +972,34 @@ private:
         R.depth = t->depth;
         R.Vcell = R.th[0] * R.th[1] * R.th[2];
         R.dtd = d->dt;
+        for (int k = 0; k < 3; ++k) R.dcoef[k] = d->dt / (double)R.n_sub * R.kappa_e / (R.th[k] * R.th[k]);
+        R.two_ge = 2.0 / R.gamma_e;
+        // diffusion tiles: the tile plus its halo of n_sub cells spans at most
+        // 16 cells along every axis (k_ttm_tile's layout), and its three LDS
+        // arrays must fit one block; otherwise one launch per sub-step.  The
+        // tile's depth is halved (down to 2 cells) while the grid has fewer
+        // than 256 tiles: more blocks and shorter columns per thread against
+        // more recomputed halo
+        for (int k = 0; k < 3; ++k) R.dtile[k] = R.dntile[k] = 0;
+        if (t->mode == 1 && t->kappa_e != 0.0 && 2 * R.n_sub < sl::kTileSide) {
+            int tt[3];
+            for (int k = 0; k < 3; ++k) tt[k] = std::min(sl::kTileSide - 2 * R.n_sub, t->n[k]);
+            auto bytes = [&]() {
+                return 3.0 * 8.0 * sl::kTileSide * sl::kTileSide * (tt[2] + 2.0 * R.n_sub);
+            };
+            auto tiles = [&]() {
+                int64_t m = 1;
+                for (int k = 0; k < 3; ++k) m *= (t->n[k] + tt[k] - 1) / tt[k];
+                return m;
+            };
+            while (tiles() < 256 && tt[2] > 2) tt[2] = (tt[2] + 1) / 2;
+            while (bytes() > (double)tile_lds_max && tt[2] > 1) tt[2] = (tt[2] + 1) / 2;
+            if (bytes() <= (double)tile_lds_max)
+                for (int k = 0; k < 3; ++k) {
+                    R.dtile[k] = tt[k];
+                    R.dntile[k] = (t->n[k] + tt[k] - 1) / tt[k];
+                }
+        }
         // electron-phonon Ornstein-Uhlenbeck coefficients
         const double vol = (double)d->ncell[0] * d->ncell[1] * d->ncell[2] * std::pow(d->a, 3);
         const double Gamma = t->mode == 1 ? t->G_el / (3.0 * ((double)r.z.n / vol) * sl::kKB) : 0.0;
@@ -1090,10 +1126,11 @@ private:
     {
         drop_graph();
         tables_dirty = false;
-        std::vector<int2> ws, wa, wk, wc, wd;
+        std::vector<int2> ws, wa, wk, wc, wd, wt;
         std::vector<int> rl;
         any_live = false;
         max_sub = 0;
+        tile_bytes = 0;
         std::vector<int> pl;
         persist_bytes = 0;
         // automatic launch shapes for the runs on the multi-kernel step: the
@@ -1144,7 +1181,13 @@ private:
             if (R.ttm_mode == 1 && R.ncell > sl::kSmallGrid)
                 for (int st = 0; st < R.ncell; st += sl::kBlock) wc.push_back(make_int2((int)s, st));
             rl.push_back((int)s);
-            if (R.ttm_mode == 1 && R.kappa_e != 0.0) {
+            if (R.ttm_mode == 1 && R.kappa_e != 0.0 && R.dtile[0] > 0) {
+                const int nt = R.dntile[0] * R.dntile[1] * R.dntile[2];
+                for (int k = 0; k < nt; ++k) wt.push_back(make_int2((int)s, k));
+                const uint32_t b = (uint32_t)(3 * 8 * sl::kTileSide * sl::kTileSide *
+                                              (R.dtile[2] + 2 * R.n_sub));
+                tile_bytes = std::max(tile_bytes, b);
+            } else if (R.ttm_mode == 1 && R.kappa_e != 0.0) {
                 for (int st = 0; st < R.ncell; st += sl::kBlock) wd.push_back(make_int2((int)s, st));
                 max_sub = std::max(max_sub, R.n_sub);
             }
@@ -1167,22 +1210,24 @@ private:
             }
         }
         // adjacent colour-0 half steps of consecutive steps merge into one pass
-        // when a single run is on the multi-kernel step, its electrons do not
-        // diffuse (the deferred half step reads the previous step's T_e kept
-        // in the diffusion buffer) and chunks of merge_g steps can end on
-        // every sample step (merge_g divides obs_every); chunks start at
-        // multiples of merge_g
+        // when a single run is on the multi-kernel step, the grid update can
+        // keep the previous step's T_e in the second buffer for the deferred
+        // half step (not when diffusion runs as sub-step launches, which use
+        // that buffer) and chunks of merge_g steps can end on every sample
+        // step (merge_g divides obs_every); chunks start at multiples of
+        // merge_g
         // Within a chunk each step's end (small electron grid, bins, flags)
-        // also runs as one extra block of the next step's colour pass 0,
-        // which computes the new T_e of its sites from the same inputs; the
-        // chunk's last step ends in k_finalize.  Larger grids keep their
-        // cell-parallel update.
+        // also runs as extra blocks of the next step's colour pass 0, whose
+        // spin blocks compute the new T_e of their sites from the same
+        // inputs; the chunk's last step ends in k_finalize.  Larger grids
+        // keep their cell-parallel update, and diffusing electrons (whose
+        // new T_e depends on the neighbour cells) their own launches.
         merge_g = 0;
         merge_run = -1;
         fold = false;
         if (merge_sweeps && rl.size() == 1) {
             const RD& R = host_rd[rl[0]];
-            if (!(R.ttm_mode == 1 && R.kappa_e != 0.0)) {
+            if (!(R.ttm_mode == 1 && R.kappa_e != 0.0 && R.dtile[0] == 0)) {
                 int g = 0;
                 if (R.obs_every > 0) {
                     for (int d = 2; d <= 64; ++d)
@@ -1193,7 +1238,7 @@ private:
                 if (g >= 2) {
                     merge_g = g;
                     merge_run = rl[0];
-                    fold = !(R.ttm_mode == 1 && R.ncell > sl::kSmallGrid);
+                    fold = !(R.ttm_mode == 1 && (R.ncell > sl::kSmallGrid || R.kappa_e != 0.0));
                     // one thread per electron cell, four bins per thread
                     const int cells = R.ttm_mode == 1 ? R.ncell : 0;
                     const int bins = R.live ? (R.nbins + 3) / 4 : 0;
@@ -1203,12 +1248,13 @@ private:
         }
         for (void* p : tables) alloc.put(p);
         tables.clear();
-        d_work_spin = d_work_atom = d_work_kick = d_work_cell = d_work_diff = nullptr;
+        d_work_spin = d_work_atom = d_work_kick = d_work_cell = d_work_diff = d_work_tile = nullptr;
         active_blocks_spin = (int)ws.size();
         active_blocks_atom = (int)wa.size();
         active_blocks_kick = (int)wk.size();
         active_blocks_cell = (int)wc.size();
         active_blocks_diff = (int)wd.size();
+        active_blocks_tile = (int)wt.size();
         active_runs = (int)rl.size();
         d_run_list = nullptr;
         persist_runs = (int)pl.size();
@@ -1228,6 +1274,7 @@ private:
         if ((st = up(wk.data(), sizeof(int2) * wk.size(), (void**)&d_work_kick)) != SL_OK) return st;
         if ((st = up(wc.data(), sizeof(int2) * wc.size(), (void**)&d_work_cell)) != SL_OK) return st;
         if ((st = up(wd.data(), sizeof(int2) * wd.size(), (void**)&d_work_diff)) != SL_OK) return st;
+        if ((st = up(wt.data(), sizeof(int2) * wt.size(), (void**)&d_work_tile)) != SL_OK) return st;
         if ((st = up(rl.data(), sizeof(int) * rl.size(), (void**)&d_run_list)) != SL_OK) return st;
         if ((st = up(pl.data(), sizeof(int) * pl.size(), (void**)&d_persist_list)) != SL_OK) return st;
         SL_HIP(hipStreamSynchronize(stream));
@@ -1321,6 +1368,13 @@ private:
                        (int)sl::PHASE_STEP, sorted, fold_k);
         });
         if (e != SL_OK) return e;
+        if (active_blocks_tile > 0) {
+            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_ttm_tile<T>, dim3(active_blocks_tile), dim3(sl::kTileBlock), tile_bytes, st, a,
+                       b, d_runs, d_work_tile);
+            });
+            if (e != SL_OK) return e;
+        }
         for (int sub = 0; sub < max_sub; ++sub) {
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
                 launch(sl::k_ttm_diffuse<T>, dim3(active_blocks_diff), bk, 0, st, a, b, d_runs,

@@ -8,6 +8,7 @@ in chunks of 10.  Advances of uneven length start and stop inside chunks,
 and a batch run reaches its target inside a chunk.
 """
 import sys
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -39,6 +40,12 @@ def _cases():
     # (the deferred half step reads the previous step's T_e)
     yield "alloy_laser_live", I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005,
                                                fwhm=0.005), "afm"
+    # diffusing electrons heated in a top slab: four diffusion sub-steps per
+    # step in one tiled launch, the previous step's T_e kept by the grid update
+    yield "alloy_diffusing", replace(
+        I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005,
+                         kappa_e=I.w_per_mk_to_metal(80.0), n_sub=4, profile=1, depth=10.0),
+        tn=(3, 3, 6)), "afm"
 
 
 def _samples(sysobj, every):
@@ -46,7 +53,7 @@ def _samples(sysobj, every):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("case", ["bcc_fixed_Te", "alloy_laser_live"])
+@pytest.mark.parametrize("case", ["bcc_fixed_Te", "alloy_laser_live", "alloy_diffusing"])
 def test_merged_sweep_equals_unmerged(N, case, prec):
     name, spec, init = next(c for c in _cases() if c[0] == case)
     st = I.initial_state(spec, init)

@@ -114,6 +114,23 @@ def test_diffusion_surface_heating_window(N):
     assert Te[-1].mean() > Te[0].mean() + 10.0
 
 
+def test_many_diffusion_substeps_window(N):
+    """Forty diffusion sub-steps per step: a tile with a halo forty cells deep
+    does not fit in LDS, so the sub-steps run as one launch each (the tiled
+    launch covers the other diffusion tests)."""
+    spec = _alloy_window(L=8, tn=2, kappa=I.w_per_mk_to_metal(80.0), n_sub=40, profile=1,
+                         depth=8.0)
+    spec = replace(spec, tn=(2, 2, 4))
+    st = I.initial_state(spec, "afm")
+    g, o = run_pair(N, spec, st, 60)
+    g.step(60)
+    o.step(60)
+    errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+    assert not bad, errs
+    Te = o.state()["Te"].reshape(4, 2, 2)
+    assert Te[-1].mean() > Te[0].mean() + 1.0
+
+
 def test_full_size_alloy_32cubed_frozen_graph(N):
     """The full 32^3 alloy (32768 sites, 8^3 grid, laser on) in the launch
     configuration the benchmark times (16-step graph replays), lattice
