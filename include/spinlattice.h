@@ -225,11 +225,11 @@ typedef struct sl_tuning {
                                  256 blocks per pass)                          */
     int32_t spin_spt;         /* sites per thread in a colour pass: 1, 2, 4          */
     int32_t atom_block;       /* threads per block of the lattice kernels: 64..256   */
-    int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256; a
-                                 single run on the multi-kernel step replays
-                                 chunks of merged sweeps instead (the largest
-                                 divisor of its sample interval up to 64, or
-                                 graph_steps when it takes no samples)        */
+    int32_t graph_steps;      /* steps captured per HIP graph replay: 1..256;
+                                 runs that merge their sweeps replay chunks
+                                 instead (the largest common divisor of their
+                                 sample intervals up to 64, or graph_steps when
+                                 none takes samples)                          */
     int32_t persist_block;    /* 0: all runs on the multi-kernel step; 256, 512 or
                                  1024: runs that fit in LDS advance in a persistent
                                  kernel, one block of this many threads per run
@@ -248,17 +248,19 @@ typedef struct sl_tuning {
                                  2^17, then 1).  The pair sums are four
                                  interleaved partial sums over the list in every
                                  case, hence the same bits                   */
-    int32_t merge_sweeps;     /* 1 (default): a single run on the multi-kernel
-                                 step applies the last colour half step of a
-                                 step together with the next step's first, in
-                                 chunks ending on every sample step, and (with
-                                 at most 4096 electron cells) ends each step of
-                                 a chunk inside the next step's first colour
-                                 pass; 0: one launch per colour pass and a step
-                                 end per step.  Same bits either way, except
-                                 that a negative electron energy met at a step
-                                 end inside a chunk stops the run one step
-                                 later (SL_ENUMERIC either way)               */
+    int32_t merge_sweeps;     /* 1 (default): the runs on the multi-kernel step
+                                 (a system, or batch runs with one colour count
+                                 at the same step modulo the chunk length)
+                                 apply the last colour half step of a step
+                                 together with the next step's first, in chunks
+                                 ending on every sample step; a single run with
+                                 at most 4096 non-diffusing electron cells also
+                                 ends each step of a chunk inside the next
+                                 step's first colour pass.  0: one launch per
+                                 colour pass and a step end per step.  Same bits
+                                 either way, except that a negative electron
+                                 energy met at a folded step end stops the run
+                                 one step later (SL_ENUMERIC either way)      */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of

@@ -329,8 +329,9 @@ public:
     int bin_mode = 0;               // 0 automatic, 1 kick bins every step, 2 rebuild only
     int atom_lanes = 0;             // lanes per atom in k_atom_final (0: by the atom count)
     int merge_sweeps = 1;           // 1: merge adjacent colour half steps when possible
-    int merge_g = 0;                // >= 2: steps per merged chunk (one multi-kernel run)
-    int merge_run = -1;             // that run's slot
+    int merge_g = 0;                // >= 2: steps per merged chunk of the multi-kernel runs
+    int merge_run = -1;             // a stepping run among them (its step gives the chunk phase)
+    std::vector<int> mk_runs;       // the runs on the multi-kernel step
     bool fold = false;              // chunks end each step inside the next one's colour pass 0
     int fold_blocks = 0;            // the blocks of colour pass 0 that end the previous step
     int lanes_eff = 1;              // the lanes in use (tables are built for it)
@@ -489,9 +490,7 @@ public:
         const int G = graph_len();
         if (merge_g >= 2 && left > 0) {
             // single steps up to the next multiple of the chunk length
-            const int64_t s0 = runs[merge_run].steps;
-            int64_t head = (merge_g - s0 % merge_g) % merge_g;
-            head = std::min<int64_t>(head, left);
+            const int64_t head = std::min<int64_t>(chunk_head(), left);
             for (int64_t k = 0; k < head; ++k) enqueue_step(stream, nullptr);
             left -= head;
         }
@@ -538,8 +537,7 @@ public:
         // then merged chunks, then single steps
         int64_t left = active_blocks_atom > 0 ? n : 0;
         if (merge_g >= 2 && left > 0) {
-            const int64_t s0 = runs[merge_run].steps;
-            int64_t head = std::min<int64_t>((merge_g - s0 % merge_g) % merge_g, left);
+            const int64_t head = std::min<int64_t>(chunk_head(), left);
             for (int64_t k = 0; k < head; ++k) {
                 sl_status st = enqueue_step(stream, &p);
                 if (st != SL_OK) return st;
@@ -1210,12 +1208,11 @@ private:
             }
         }
         // adjacent colour-0 half steps of consecutive steps merge into one pass
-        // when a single run is on the multi-kernel step, the grid update can
-        // keep the previous step's T_e in the second buffer for the deferred
-        // half step (not when diffusion runs as sub-step launches, which use
-        // that buffer) and chunks of merge_g steps can end on every sample
-        // step (merge_g divides obs_every); chunks start at multiples of
-        // merge_g
+        // when the grid update can keep each run's previous T_e in the second
+        // buffer for the deferred half step (not when diffusion runs as
+        // sub-step launches, which use that buffer) and chunks of merge_g
+        // steps can end on every sample step (merge_g divides every obs_every);
+        // chunks start at multiples of merge_g
         // Within a chunk each step's end (small electron grid, bins, flags)
         // also runs as extra blocks of the next step's colour pass 0, whose
         // spin blocks compute the new T_e of their sites from the same
@@ -1225,19 +1222,40 @@ private:
         merge_g = 0;
         merge_run = -1;
         fold = false;
-        if (merge_sweeps && rl.size() == 1) {
-            const RD& R = host_rd[rl[0]];
-            if (!(R.ttm_mode == 1 && R.kappa_e != 0.0 && R.dtile[0] == 0)) {
-                int g = 0;
-                if (R.obs_every > 0) {
-                    for (int d = 2; d <= 64; ++d)
-                        if (R.obs_every % d == 0) g = d;
-                } else {
-                    g = graph_steps;
+        mk_runs = rl;
+        if (merge_sweeps && !rl.empty()) {
+            // several runs merge together when they have the same colour count
+            // (they defer the same pass), a common chunk length divides every
+            // sample interval, and the runs still stepping are at the same
+            // step modulo it (runs added together, advanced in whole chunks)
+            bool ok = true, sampled = false;
+            for (int s : rl) {
+                const RD& R = host_rd[s];
+                if ((R.ttm_mode == 1 && R.kappa_e != 0.0 && R.dtile[0] == 0) ||
+                    R.g.C != host_rd[rl[0]].g.C)
+                    ok = false;
+                sampled = sampled || R.obs_every > 0;
+            }
+            int g = sampled ? 0 : graph_steps;
+            for (int d = 64; sampled && d >= 2 && g == 0; --d) {
+                bool all = true;
+                for (int s : rl) all = all && (host_rd[s].obs_every <= 0 || host_rd[s].obs_every % d == 0);
+                if (all) g = d;
+            }
+            int64_t phase = -1;
+            for (int s : rl) {
+                if (!ok || g < 2 || runs[s].steps >= runs[s].target) continue;
+                if (phase < 0) {
+                    phase = runs[s].steps % g;
+                    merge_run = s;
+                } else if (runs[s].steps % g != phase) {
+                    ok = false;
                 }
-                if (g >= 2) {
-                    merge_g = g;
-                    merge_run = rl[0];
+            }
+            if (ok && g >= 2 && merge_run >= 0) {
+                merge_g = g;
+                const RD& R = host_rd[merge_run];
+                if (rl.size() == 1) {
                     fold = !(R.ttm_mode == 1 && (R.ncell > sl::kSmallGrid || R.kappa_e != 0.0));
                     // one thread per electron cell, four bins per thread
                     const int cells = R.ttm_mode == 1 ? R.ncell : 0;
@@ -1410,6 +1428,16 @@ private:
 
     // steps per graph replay
     int graph_len() const { return merge_g >= 2 ? merge_g : graph_steps; }
+
+    // single steps before the next chunk boundary of the merged runs, from
+    // one that still steps (all that step share the phase; one that reached
+    // its target keeps its final count)
+    int64_t chunk_head() const
+    {
+        for (int s : mk_runs)
+            if (runs[s].steps < runs[s].target) return (merge_g - runs[s].steps % merge_g) % merge_g;
+        return 0;
+    }
 
     sl_status capture()
     {

@@ -148,3 +148,36 @@ def test_negative_electron_energy_inside_a_chunk(N):
     u, f = steps
     assert 10 < u < 40, steps
     assert f == u + (1 if u % 10 else 0), steps
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_runs_merge_together(N, prec):
+    """Three sc alloys added together to a batch on the multi-kernel step
+    (same colour count, sample interval 10) advance in merged chunks: one
+    colour pass without the kick per step instead of two, except at a
+    chunk's last step.  Each run keeps the bits it has alone stepped one by
+    one; two of them reach their targets inside a chunk."""
+    specs = [I.gdfeco_sc_spec(L=L, tn=2, alpha=0.02 * (k + 1), S0=0.6, t0=0.005, fwhm=0.005,
+                              seed=20 + k, run_id=k) for k, L in enumerate((8, 10, 12))]
+    states = [I.initial_state(sp, "afm") for sp in specs]
+    targets = [37, 50, 44]
+    _log("case: batch of 3 sc alloys, prec=%d" % prec)
+    b = N.Batch(precision=prec, max_runs=4)
+    b.set_tuning(persist_block=0)
+    slots = [b.add(sp, st, t, obs_every=10) for sp, st, t in zip(specs, states, targets)]
+    b.advance(23)
+    avg, cnt = b.advance_profiled(27)      # 7 single steps, then two chunks of 10
+    assert cnt[0] == 7 * 2 + 2 * 11, cnt
+    for sp, st, t, s in zip(specs, states, targets, slots):
+        g = b.get(s)
+        ref = N.System(sp, st, precision=prec, obs_every=1)
+        ref.step(t)
+        a = ref.state()
+        for k in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[k], g[k]), (t, k)
+        want = [o for o in ref.observables() if o["step"] % 10 == 0]
+        assert [o["step"] for o in g["obs"]] == [o["step"] for o in want]
+        for o, r in zip(g["obs"], want):
+            assert o["E_ex"] == r["E_ex"] and o["m_abs"] == r["m_abs"] and o["Te_mean"] == r["Te_mean"]
+        ref.close()
+    b.close()
