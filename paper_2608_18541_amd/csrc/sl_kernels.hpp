@@ -125,6 +125,7 @@ template <typename T> struct RunDev {
     int32_t n_part;
     sl_obs* ring;
     RunState* st;
+    int32_t* any_rebuild;            // engine-wide: a run flagged a list rebuild this step
 };
 
 // ------------------------------------------------------- memory access
@@ -1286,6 +1287,7 @@ template <typename T> __device__ inline void fold_end_step(const RunDev<T>& R, i
             st->rebuild = 0;
         }
         st->chunk_done = k;
+        *R.any_rebuild = 0;
     }
 }
 
@@ -1318,8 +1320,10 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
         const uint32_t i = (uint32_t)w.y + threadIdx.x;
         if (i >= (uint32_t)R.n) return;
         const GView<T> V = global_view(R, step + 1);
-        if (kick_drift_atom(R, V, i, PHASE_STEP) && *(volatile int32_t*)&R.st->rebuild == 0)
+        if (kick_drift_atom(R, V, i, PHASE_STEP) && *(volatile int32_t*)&R.st->rebuild == 0) {
             atomicOr(&R.st->rebuild, 1);
+            atomicOr(R.any_rebuild, 1);
+        }
         if (R.bin_step) nbr_bin_atom(R, V, i);
         return;
     }
@@ -1375,18 +1379,24 @@ __global__ __launch_bounds__(kBlock) void k_init_lattice(const RunDev<T>* __rest
 }
 
 // Binning on its own, for a rebuild: at initialisation, and every step for
-// runs whose kick does not bin (exits at once unless a rebuild is flagged).
+// runs whose kick does not bin.  Blocks stride over the n_work entries of
+// the atom table; in steps (any_rebuild given) the launch is capped and
+// exits at once unless some run flagged a rebuild.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict__ runs,
                                                     const int2* __restrict__ work, int phase,
-                                                    int fold_k)
+                                                    int fold_k, int n_work,
+                                                    const int32_t* __restrict__ any_rebuild)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    if (!R.live || R.st->rebuild == 0 || !fold_ok(R.st, fold_k)) return;
-    if (phase == PHASE_STEP && (R.bin_step || step_at(R, fold_k) >= R.st->target)) return;
-    const uint32_t i = (uint32_t)w.y + threadIdx.x;
-    if (i < (uint32_t)R.n) nbr_bin_atom(R, global_view(R, 0), i);
+    if (any_rebuild != nullptr && *any_rebuild == 0) return;
+    for (int e = (int)blockIdx.x; e < n_work; e += (int)gridDim.x) {
+        const int2 w = work[e];
+        const RunDev<T>& R = runs[w.x];
+        if (!R.live || R.st->rebuild == 0 || !fold_ok(R.st, fold_k)) continue;
+        if (phase == PHASE_STEP && (R.bin_step || step_at(R, fold_k) >= R.st->target)) continue;
+        const uint32_t i = (uint32_t)w.y + threadIdx.x;
+        if (i < (uint32_t)R.n) nbr_bin_atom(R, global_view(R, 0), i);
+    }
 }
 
 // Sorts the bins filled by k_nbr_bin for a rebuild (thread i of a run takes
@@ -1395,14 +1405,18 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bin(const RunDev<T>* __restrict_
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_sort(const RunDev<T>* __restrict__ runs,
                                                      const int2* __restrict__ work, int phase,
-                                                     int fold_k)
+                                                     int fold_k, int n_work,
+                                                     const int32_t* __restrict__ any_rebuild)
 {
-    const int2 w = work[blockIdx.x];
-    const RunDev<T>& R = runs[w.x];
-    if (!R.live || R.st->rebuild == 0 || !fold_ok(R.st, fold_k)) return;
-    if (phase == PHASE_STEP && (R.bin_step || step_at(R, fold_k) >= R.st->target)) return;
-    for (uint32_t b = (uint32_t)w.y + threadIdx.x; b < (uint32_t)R.nbins; b += (uint32_t)R.n)
-        nbr_sort_bin(R, (int)b);
+    if (any_rebuild != nullptr && *any_rebuild == 0) return;
+    for (int e = (int)blockIdx.x; e < n_work; e += (int)gridDim.x) {
+        const int2 w = work[e];
+        const RunDev<T>& R = runs[w.x];
+        if (!R.live || R.st->rebuild == 0 || !fold_ok(R.st, fold_k)) continue;
+        if (phase == PHASE_STEP && (R.bin_step || step_at(R, fold_k) >= R.st->target)) continue;
+        for (uint32_t b = (uint32_t)w.y + threadIdx.x; b < (uint32_t)R.nbins; b += (uint32_t)R.n)
+            nbr_sort_bin(R, (int)b);
+    }
 }
 
 // The initial Verlet-list build (from bins sorted by k_nbr_sort); in steps
@@ -1695,6 +1709,8 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
             pE[q] = srcE[c];
         }
     }
+    // the binning launches of this step have read the engine's rebuild word
+    if (blockIdx.x == 0 && tid == 0) *R.any_rebuild = 0;
     if (tid == 0) {
         S.step = phase == PHASE_STEP ? step_at(R, fold_k) : st->step;
         S.go = phase != PHASE_STEP || (fold_ok(st, fold_k) && S.step < st->target);

@@ -351,6 +351,7 @@ public:
         for (size_t s = 0; s < runs.size(); ++s) release(s);
         for (void* p : tables) alloc.put(p);
         alloc.put(d_runs);
+        if (d_any_rebuild) alloc.put(d_any_rebuild);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (side_stream) (void)hipStreamDestroy(side_stream);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -363,6 +364,9 @@ public:
         d_runs = static_cast<RD*>(alloc.get(sizeof(RD) * runs.size()));
         if (!d_runs) return fail(SL_ENOMEM, "device allocation of the run table failed");
         SL_HIP(hipMemset(d_runs, 0, sizeof(RD) * runs.size()));
+        d_any_rebuild = static_cast<int32_t*>(alloc.get(256));
+        if (!d_any_rebuild) return fail(SL_ENOMEM, "device allocation failed");
+        SL_HIP(hipMemset(d_any_rebuild, 0, 256));
         SL_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
         SL_HIP(hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking));
         SL_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
@@ -785,6 +789,8 @@ private:
     int2* d_work_cell = nullptr;
     int2* d_work_diff = nullptr;
     int2* d_work_tile = nullptr;
+    int32_t* d_any_rebuild = nullptr;   // a run flagged a list rebuild this step (device word)
+    static constexpr int kBinGrid = 2048;   // blocks of a step's binning launches
     int* d_run_list = nullptr;
     int active_runs = 0;
     int active_blocks_spin = 0, active_blocks_atom = 0, active_blocks_kick = 0, active_blocks_cell = 0,
@@ -945,6 +951,7 @@ private:
         R.partial = c.take<double>((size_t)r.z.n_part * sl::NQ);
         R.ring = c.take<sl_obs>((size_t)R.obs_cap);
         R.st = c.take<sl::RunState>(1);
+        R.any_rebuild = d_any_rebuild;
         host_rd[s] = R;
     }
 
@@ -1103,8 +1110,10 @@ private:
         const int ga = (int)wa.size();
         sl::k_init_lattice<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         if (R.live) {
-            sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT, -1);
-            sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT, -1);
+            sl::k_nbr_bin<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT, -1,
+                                                             (int)wa.size(), nullptr);
+            sl::k_nbr_sort<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, (int)sl::PHASE_INIT, -1,
+                                                              (int)wa.size(), nullptr);
             sl::k_nbr_build<T><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa);
         }
         sl::k_atom_final<T, 1><<<ga, sl::kBlock, 0, stream>>>(d_runs, dwa, sl::PHASE_INIT, 1, -1);
@@ -1362,14 +1371,17 @@ private:
         const dim3 ga(active_blocks_atom);
         sl_status e;
         if (active_blocks_kick > 0 && !bin_each_step) {
+            // capped grids striding over the atom table, which exit at once
+            // unless a run flagged a rebuild
+            const dim3 gb(std::min(active_blocks_atom, kBinGrid));
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_bin<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
-                       fold_k);
+                launch(sl::k_nbr_bin<T>, gb, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
+                       fold_k, active_blocks_atom, (const int32_t*)d_any_rebuild);
             });
             if (e != SL_OK) return e;
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_sort<T>, ga, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
-                       fold_k);
+                launch(sl::k_nbr_sort<T>, gb, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
+                       fold_k, active_blocks_atom, (const int32_t*)d_any_rebuild);
             });
             if (e != SL_OK) return e;
         }
