@@ -84,6 +84,8 @@ template <typename T> struct RunDev {
     int32_t lattice, n, n_species, n_shells, live, ttm_mode, obs_every, obs_cap;
     int32_t noisy;       // some species has a thermal field (sig > 0)
     int32_t bin_step;    // 1: atoms are binned by the kick every step, 0: only for a rebuild
+    int32_t eta_drawn;   // 1: the kick draws the electron-phonon normals into eta for the
+                         // force kernel (which then gives an atom several lanes)
     uint32_t seed, run_id;
     T a, box[3], inv_box[3];
     T alpha, dt, tau_half, inv1pa2, gam;
@@ -126,6 +128,8 @@ template <typename T> struct RunDev {
     sl_obs* ring;
     RunState* st;
     int32_t* any_rebuild;            // engine-wide: a run flagged a list rebuild this step
+    T* eta;                          // [3][n]: the step's electron-phonon normals (live
+                                     // runs), drawn by the kick for the force kernel
 };
 
 // ------------------------------------------------------- memory access
@@ -919,12 +923,17 @@ template <typename T, typename VW, int LPA = 1>
 __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V, uint32_t i,
                                                 int phase, int64_t step, bool obs,
                                                 unsigned long long* acc, ObsTerms& o, int j = 0,
-                                                uint32_t acc_first = 0)
+                                                uint32_t acc_first = 0, const T* drawn = nullptr)
 {
     static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
     constexpr int NA = 4 / LPA;   // partial sums held by one lane
     using M = typename VW::Mem;
     const bool lead = j == 0;
+    // drawn: the step's electron-phonon normals, already drawn by the kick
+    // (loaded first, so that their latency overlaps the list walk)
+    const bool pre = drawn != nullptr && phase == PHASE_STEP && R.ttm_mode == 1 && R.live;
+    Normals3<T> kept{T(0), T(0), T(0)};
+    if (pre) kept = Normals3<T>{gld(drawn, i), gld(drawn + R.n, i), gld(drawn + 2 * R.n, i)};
     const Site si = decode_site(R.g, i);
     const int sp = species_of(R, V, i);
     if (R.live) {
@@ -968,7 +977,7 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
                 const double Te = M::ld(V.Te, c);
                 const uint32_t canon =
                     (((uint32_t)si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
-                const Normals3<T> eta = normals3<T>(R.seed, R.run_id, canon, step, 1u);
+                const Normals3<T> eta = pre ? kept : normals3<T>(R.seed, R.run_id, canon, step, 1u);
                 const T oa = select4(sp, R.ou_amp[0], R.ou_amp[1], R.ou_amp[2], R.ou_amp[3]);
                 const T amp = oa * sqrt_te(Te, T(0));
                 const T nx = R.ou_c1 * vx + amp * eta.a;
@@ -1325,6 +1334,16 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
             atomicOr(R.any_rebuild, 1);
         }
         if (R.bin_step) nbr_bin_atom(R, V, i);
+        if (R.ttm_mode == 1 && R.eta_drawn) {
+            // this step's electron-phonon normals for the force kernel, one
+            // atom per lane (the force kernel gives an atom several)
+            const Site si = decode_site(R.g, i);
+            const uint32_t canon = (((uint32_t)si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
+            const Normals3<T> eta = normals3<T>(R.seed, R.run_id, canon, step, 1u);
+            gst(R.eta, i, eta.a);
+            gst(R.eta + R.n, i, eta.b);
+            gst(R.eta + 2 * R.n, i, eta.c);
+        }
         return;
     }
     const int2 w = work[blockIdx.x];
@@ -1546,7 +1565,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         ObsTerms o{};
         if (i < (uint32_t)R.n)
             atom_final_atom<T, GView<T>, LPA>(R, V, i, phase, step, obs, lds_acc ? cacc : dE, o, lj,
-                                              lds_acc ? c_lo : 0u);
+                                              lds_acc ? c_lo : 0u, R.eta_drawn ? R.eta : nullptr);
         if (lds_acc) {
             __syncthreads();
             for (uint32_t c = threadIdx.x; c < c_span; c += blockDim.x)

@@ -271,6 +271,7 @@ template <typename T> size_t main_bytes(const sl_system_desc* d, const Sizes& z)
     c.take<double>((size_t)z.n_part * sl::NQ);
     c.take<sl_obs>((size_t)std::max(1, d->obs_capacity));
     c.take<sl::RunState>(1);
+    if (live) c.take<T>(3 * n);                                     // electron-phonon normals
     return c.off;
 }
 
@@ -951,6 +952,7 @@ private:
         R.partial = c.take<double>((size_t)r.z.n_part * sl::NQ);
         R.ring = c.take<sl_obs>((size_t)R.obs_cap);
         R.st = c.take<sl::RunState>(1);
+        R.eta = R.live ? c.take<T>(3 * n) : nullptr;
         R.any_rebuild = d_any_rebuild;
         host_rd[s] = R;
     }
@@ -1211,8 +1213,12 @@ private:
         for (size_t s = 0; s < runs.size(); ++s) {
             if (!runs[s].used) continue;
             const int32_t want = bin_each_step ? 1 : 0;
-            if (host_rd[s].bin_step != want) {
+            // with several lanes per atom in the force kernel, the kick draws
+            // the electron-phonon normals once per atom for it
+            const int32_t draw = lanes_eff > 1 ? 1 : 0;
+            if (host_rd[s].bin_step != want || host_rd[s].eta_drawn != draw) {
                 host_rd[s].bin_step = want;
+                host_rd[s].eta_drawn = draw;
                 SL_HIP(hipMemcpyAsync(d_runs + s, &host_rd[s], sizeof(RD), hipMemcpyHostToDevice, stream));
             }
         }

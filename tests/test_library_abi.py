@@ -196,12 +196,13 @@ def test_footprint_and_site_limit(libpath):
         ratio = sizes[(16, prec)] / sizes[(8, prec)]
         assert 7.0 < ratio < 8.5, ratio                # per-site arrays dominate
     # FP32 halves the 15 real per-atom arrays (spins, displacements,
-    # velocities, forces, reference displacements) and the padded position
-    # vector: 15 x 4 + 16 bytes per atom less; lists, bins, ids and samples
+    # velocities, forces, reference displacements), the padded position
+    # vector and the three electron-phonon normals drawn per atom:
+    # 15 x 4 + 16 + 3 x 4 bytes per atom less; lists, bins, ids and samples
     # keep their size
     for Lc in (8, 16):
         n = Lc ** 3
-        assert sizes[(Lc, native.SL_FP64)] - sizes[(Lc, native.SL_FP32)] == (15 * 4 + 16) * n
+        assert sizes[(Lc, native.SL_FP64)] - sizes[(Lc, native.SL_FP32)] == (15 * 4 + 16 + 12) * n
     # 2^27 sites: bcc 512 x 512 x 256 cells, with the small run's arrays
     spec = I.gdfeco_sc_spec(L=8, tn=2)
     st = I.initial_state(spec, "afm")
