@@ -50,6 +50,7 @@ constexpr int kBlock = 256;
 constexpr int NQ = 24;      // observable partial sums per wave of 64 atoms
 static_assert(NQ % 3 == 0, "samples reduce three quantities at a time");
 constexpr int kLdsCells = 2048;   // electron grids up to this size are summed in LDS
+constexpr int kSmallGrid = 4096;  // larger electron grids update cell-parallel (k_grid)
 
 enum { ERR_NEG_E = 1, ERR_BIN = 2, ERR_NBR = 4, ERR_DE = 8 };
 enum { PHASE_STEP = 0, PHASE_INIT = 1 };
@@ -522,6 +523,12 @@ template <typename T> __device__ inline double* te_buf(const RunDev<T>& R, int f
 template <typename T> __device__ inline unsigned long long* de_buf(const RunDev<T>& R, int fold_k)
 {
     return (fold_k > 0 && (fold_k & 1)) ? R.dE_alt : R.dE;
+}
+// Whether the bins of a run are emptied by the cell-parallel grid update
+// (live runs with a large electron grid) instead of the step end.
+template <typename T> __device__ inline bool empties_bins_in_grid(const RunDev<T>& R)
+{
+    return R.live && R.ttm_mode == 1 && R.ncell > kSmallGrid;
 }
 // Whether the grid update keeps the step's T_e in the second buffer for a
 // deferred spin half step: unless sub-step launches use it for diffusion.
@@ -1157,7 +1164,6 @@ __device__ inline void cell_update(const RunDev<T>& R, double* Te, unsigned long
 }
 
 
-constexpr int kSmallGrid = 4096;   // larger electron grids update cell-parallel
 
 // The observable sample of a run, computed by one block of any size: per-wave
 // partial rows in order, electron-grid sums in a fixed-shape tree.
@@ -1691,6 +1697,12 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     if (!run_active(R, &step) || R.ttm_mode != 1 || R.ncell <= kSmallGrid) return;
     const int c = w.y + (int)threadIdx.x;
     if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step, keeps_prev_te(R) ? R.Te_alt : nullptr);
+    // the bins filled this step, emptied here for such runs (spread over the
+    // grid's blocks rather than by the one block of the step end)
+    if (empties_bins_in_grid(R) && (R.bin_step || R.st->rebuild != 0)) {
+        const int span = (R.ncell + kBlock - 1) / kBlock * kBlock;
+        for (int b = c; b < R.nbins; b += span) R.bin_n[b] = 0;
+    }
 }
 
 
@@ -1771,8 +1783,9 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
     if (sample_due(R, phase, step))
         write_sample(R, global_view(R, step), S, phase == PHASE_INIT ? step : step + 1);
     // the bins filled this step have been read by the list build: empty them
-    // for the next binning
-    if (R.live && (R.bin_step || S.rebuild != 0 || phase == PHASE_INIT))
+    // for the next binning (runs with a large grid: emptied by k_grid)
+    if (R.live && (R.bin_step || S.rebuild != 0 || phase == PHASE_INIT) &&
+        (phase == PHASE_INIT || !empties_bins_in_grid(R)))
         for (int b = tid; b < R.nbins; b += blockDim.x) R.bin_n[b] = 0;
     __syncthreads();
     if (tid == 0) {

@@ -110,3 +110,32 @@ def test_overfull_bins_against_oracle(N):
     o.step(30)
     errs, bad = compare_states(out[0], o.state(), spec.box, 1e-10)
     assert not bad, errs
+
+
+def test_large_grid_bins_emptied_by_the_grid_update(N):
+    """A live run whose electron grid is updated cell-parallel (17^3 = 4913
+    cells) has its bins emptied by that launch.  Binning by the kick every
+    step and binning only for a rebuild must build the same lists (stale
+    bins would add wrong candidates or overflow), with a skin thin enough
+    to rebuild every few steps; the first steps against the oracle."""
+    spec = replace(I.gdfeco_sc_spec(L=18, tn=17, S0=0.3, t0=0.002, fwhm=0.002, seed=13, run_id=5),
+                   skin=0.05)
+    st = I.initial_state(spec, "afm")
+    out = []
+    for mode in (1, 2):
+        _log("case: sc 18^3, 17^3 grid, bin_mode=%d" % mode)
+        g = N.System(spec, st, precision=0, obs_every=10)
+        g.set_tuning(bin_mode=mode)
+        g.step(15)
+        out.append(g.state())
+        g.step(105)
+        out.append(g.state())
+        stats = g.stats()
+        assert stats["list_rebuilds"] >= 4, stats
+        g.close()
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(out[1][k], out[3][k]), k
+    o = O.Oracle(spec, st.species, st.spins, st.vel, disp=st.disp)
+    o.step(15)
+    errs, bad = compare_states(out[0], o.state(), spec.box, 1e-10)
+    assert not bad, errs
