@@ -175,7 +175,7 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
         fl, failed, series = [], 0, []
         for s in slots:
             try:
-                mz = [o["M"][1][2] for o in b.get(s, max_samples=n_steps // 20 + 2)["obs"]]
+                mz = [o["M"][1][2] for o in b.get(s, max_samples=n_steps // 20 + 2, state=False)["obs"]]
                 fl.append(switched(mz))
                 series.append(mz)
             except N.SLError:

@@ -406,6 +406,7 @@ class Batch:
         self._h = h
         self.precision = precision
         self.specs = {}
+        self.caps = {}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -425,6 +426,7 @@ class Batch:
         slot = C.c_int32()
         check(lib().sl_batch_add(self._h, C.byref(d), C.byref(t), int(n_steps), C.byref(slot)))
         self.specs[slot.value] = spec
+        self.caps[slot.value] = max(1, int(obs_capacity))
         return slot.value
 
     def try_add(self, *a, **k) -> Optional[int]:
@@ -470,21 +472,31 @@ class Batch:
         return [{"slot": buf[k].slot, "steps_done": buf[k].steps_done,
                  "steps_target": buf[k].steps_target} for k in range(min(cap, n.value))]
 
-    def get(self, slot: int, max_samples: int = 1 << 16) -> dict:
+    def get(self, slot: int, max_samples: Optional[int] = None, state: bool = True) -> dict:
+        """The run's samples (up to its ring capacity unless max_samples is
+        given) and, with state=True, its positions, velocities, spins and
+        electron grid."""
         spec = self.specs[slot]
         n = spec.n_sites
-        x = np.zeros((n, 3)); v = np.zeros((n, 3)); s = np.zeros((n, 3))
-        Te = np.zeros(spec.n_tcells)
+        if max_samples is None:
+            max_samples = self.caps.get(slot, 1 << 16)
+        x = v = s = Te = None
+        if state:
+            x = np.zeros((n, 3)); v = np.zeros((n, 3)); s = np.zeros((n, 3))
+            Te = np.zeros(spec.n_tcells)
         buf = (sl_obs * max_samples)()
         k = C.c_int64()
         check(lib().sl_batch_get(self._h, slot, _dp(x), _dp(v), _dp(s), _dp(Te), buf,
                                  max_samples, C.byref(k)))
-        return {"x": x, "v": v, "s": s, "Te": Te,
-                "obs": [obs_to_dict(buf[q]) for q in range(k.value)]}
+        out = {"obs": [obs_to_dict(buf[q]) for q in range(k.value)]}
+        if state:
+            out.update({"x": x, "v": v, "s": s, "Te": Te})
+        return out
 
     def remove(self, slot: int) -> None:
         check(lib().sl_batch_remove(self._h, slot))
         self.specs.pop(slot, None)
+        self.caps.pop(slot, None)
 
     def memory(self) -> tuple:
         u, b = C.c_size_t(), C.c_size_t()

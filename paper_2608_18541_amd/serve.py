@@ -11,7 +11,8 @@ as that run alone.
 
 The executor is anything with ``try_add(spec, state, n_steps, obs_every=,
 obs_capacity=)``, ``advance(n)``, ``synchronize()``, ``runs()``,
-``get(slot)`` and ``remove(slot)`` (``native.Batch`` on the GPU; the tests
+``get(slot, state=)`` (the run's samples, and its state when asked) and
+``remove(slot)`` (``native.Batch`` on the GPU; the tests
 also drive it with a host-side stand-in).
 """
 from __future__ import annotations
@@ -139,7 +140,7 @@ class Server:
                 req, t_adm = active.pop(s)
                 err = None
                 try:
-                    out = self.ex.get(s)
+                    out = self.ex.get(s, state=self.keep_state)
                 except RuntimeError as e:       # the run stopped on a numerical error
                     out, err = {}, str(e)
                 fin = self.clock() - t0

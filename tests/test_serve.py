@@ -62,7 +62,7 @@ class FakeExecutor:
         return [{"slot": s, "steps_done": r["done"], "steps_target": r["target"]}
                 for s, r in self.runs_.items()]
 
-    def get(self, slot):
+    def get(self, slot, state=True):
         r = self.runs_[slot]
         k = r["done"] // r["every"] + 1
         return {"obs": [{"M": np.array([[0, 0, -1.0]] * 2 + [[0, 0, 0]] * 2) if q else
