@@ -74,7 +74,8 @@ def measured_traffic(kernel: str, workload: str, tuning=None):
 
 
 def bytes_per_unit(kernel: str, fp: int, n_species: int, z_list: float) -> float:
-    """Algorithmic bytes per processed unit of each kernel class:
+    """Algorithmic bytes per processed unit of each kernel class, each array
+    the kernel must touch counted once (neighbour gathers are cache traffic):
     spin_pass per updated site, atom_final and kick per atom."""
     t = 8 if fp == 0 else 4
     sp = 1 if n_species > 1 else 0
