@@ -152,6 +152,39 @@ def plain_step_time(N, run, steps: int = 2000) -> float:
     return el
 
 
+def sublattice_analysis(runs, traj, flags) -> dict:
+    """The paper's trajectory readings over an ensemble: single-exponential
+    collapse times of the TM and Gd projections (fitted from the laser
+    peak), and the transient ferromagnetic-like interval of the switched
+    runs."""
+    from paper_2608_18541_amd import analysis as A
+    tau_tm, tau_gd, tfls = [], [], []
+    n_sw = 0
+    for r, tr, sw in zip(runs, traj, flags):
+        if tr is None:
+            continue
+        t, mz_tm, mz_gd = tr
+        for series, out in ((mz_tm, tau_tm), (mz_gd, tau_gd)):
+            try:
+                tau, _ = A.collapse_time(t, series, t_on=r.spec.t0)
+                if 0.0 < tau < t[-1]:
+                    out.append(tau)
+            except (RuntimeError, ValueError):
+                pass
+        if sw:
+            n_sw += 1
+            st = A.transient_ferromagnetic_state(t, mz_tm, mz_gd)
+            if st is not None:
+                tfls.append(st[2])
+
+    def med(x):
+        return round(float(np.median(x)), 4) if x else None
+    return {"tau_tm_median_ps": med(tau_tm), "tau_gd_median_ps": med(tau_gd),
+            "tau_fits": [len(tau_tm), len(tau_gd)],
+            "switched_runs": n_sw, "tfls_in_switched": len(tfls),
+            "tfls_median_ps": med(tfls)}
+
+
 def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     """The alloy phase diagram (8 alpha x 8 peak T_e x seeds, 16^3 runs) in
     one batch, FP32 and FP64; switching probabilities per cell."""
@@ -173,15 +206,19 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
             except N.SLError:
                 pass                # runs that stopped are counted below
             el = time.perf_counter() - t0
-        fl, failed, series = [], 0, []
+        fl, failed, series, traj = [], 0, [], []
         for s in slots:
             try:
-                mz = [o["M"][1][2] for o in b.get(s, max_samples=n_steps // 20 + 2, state=False)["obs"]]
+                obs = b.get(s, max_samples=n_steps // 20 + 2, state=False)["obs"]
+                mz = [o["M"][1][2] for o in obs]
                 fl.append(switched(mz))
                 series.append(mz)
+                traj.append((np.array([o["t"] for o in obs]), np.array([o["M"][0][2] for o in obs]),
+                             np.array(mz)))
             except N.SLError:
                 failed += 1
                 fl.append(False)
+                traj.append(None)
         flags[prec] = np.array(fl).reshape(8, 8, n_seeds)
         m = min(len(x) for x in series) if series else 0
         mz_mean[prec] = np.mean([x[:m] for x in series], axis=0) if m else np.zeros(0)
@@ -189,6 +226,7 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
                                            "runs_per_s": round(len(runs) / el, 3),
                                            "atom_steps_per_s": len(runs) * 4096 * n_steps / el,
                                            "failed_runs": failed}
+        res["fp32" if prec else "fp64"].update(sublattice_analysis(runs, traj, fl))
         print("bench: phase diagram prec %d: %.2f s" % (prec, el), file=sys.stderr, flush=True)
         b.close()
     t_plain = plain_step_time(N, runs[0])
@@ -285,6 +323,49 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
                                             "chaotically and agree only statistically"},
             "served_chunks": len(srv.log),
             "plain_latency_method": "FIFO replay of measured plain FP64 per-step times"}
+
+
+def three_temperature_run(N, I, steps: int = 80000) -> dict:
+    """The three-temperature benchmark: bcc Fe (2000 atoms, live lattice at
+    300 K), electrons set to 1500 K at t = 0 and left to cool with no source
+    term, exchanging energy with the lattice (electron-phonon) and the spins
+    (the bath at T_e); FP64, 8 ps.  Coupling constants are SI values typical
+    of Fe (gamma_e 700 J m^-3 K^-2, G 1e18 W m^-3 K^-1), not the paper's
+    friction constant, which has no SI equivalent, so the times are this
+    model's own."""
+    from paper_2608_18541_amd import analysis as A
+    spec = I.fe_bcc_spec(L=10, tn=(2, 2, 2), ttm_mode=1, Te0=1500.0, B=(0.0, 0.0, 0.0), alpha=0.05,
+                         gamma_e=I.j_per_m3k2_to_metal(700.0), G_el=I.w_per_m3k_to_metal(1.0e18),
+                         kappa_e=0.0, S0=0.0)
+    st = I.initial_state(spec, "tilt")
+    s = N.System(spec, st, precision=N.SL_FP64, obs_every=100, obs_capacity=steps // 100 + 2)
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    el = time.perf_counter() - t0
+    obs = s.observables()
+    s.close()
+    t = np.array([o["t"] for o in obs])
+    Te = np.array([o["Te_mean"] for o in obs])
+    Tl = np.array([o["Tl"] for o in obs])
+    Ts = np.array([o["Tspin"][0] for o in obs])
+    n_tail = max(1, len(t) // 10)
+    T_end = [float(x[-n_tail:].mean()) for x in (Te, Tl, Ts)]
+    T_common = float(np.mean(T_end))
+    # the spin-temperature estimator of 2000 spins is noisy: the convergence
+    # test takes 0.2 ps running means (21 samples)
+    def smooth(x, w=21):
+        k = np.ones(w) / w
+        return np.convolve(np.pad(x, w // 2, mode="edge"), k, mode="valid")
+    t_conv = A.convergence_time(t, [smooth(Te), smooth(Tl), smooth(Ts)], tol=0.05 * T_common)
+    return {"workload": "bcc Fe 10^3 (2000 atoms) FP64, live lattice at 300 K, T_e(0) = 1500 K, "
+                        "no source, %d steps of %.2g ps" % (steps, spec.dt),
+            "seconds": round(el, 3),
+            "lattice_90pct_ps": round(A.equilibration_time(t, Tl, 0.9), 4),
+            "converged_within_5pct_ps": round(t_conv, 4) if t_conv is not None else None,
+            "convergence_note": "spread of 0.2 ps running means within 5% of the common final value",
+            "final_Te_Tl_Tspin_K": [round(x, 1) for x in T_end],
+            "Te_Tl_Tspin_at_1ps_K": [round(float(np.interp(1.0, t, x)), 1) for x in (Te, Tl, Ts)]}
 
 
 def large_run(N, I, steps: int) -> dict:
@@ -398,7 +479,7 @@ def main() -> int:
                          "automatic shape)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, served and large-run measurements")
-    ap.add_argument("--extras", default="batched,serving,large,scale",
+    ap.add_argument("--extras", default="batched,serving,large,three_temp,scale",
                     help="comma list of extra measurements")
     ap.add_argument("--pd-steps", type=int, default=20000)
     ap.add_argument("--pd-seeds", type=int, default=20)
@@ -499,6 +580,8 @@ def main() -> int:
         out["serving"] = serving(N, W, S, args.serve_requests, args.serve_steps_scale)
     if "large" in extras:
         out["large"] = large_run(N, I, args.large_steps)
+    if "three_temp" in extras:
+        out["three_temperature"] = three_temperature_run(N, I)
     if "scale" in extras:
         row = field_llg_scale(N, I, tuning=json.loads(args.scale_tuning) if args.scale_tuning else None)
         sweep = []
