@@ -181,3 +181,30 @@ def test_batch_runs_merge_together(N, prec):
             assert o["E_ex"] == r["E_ex"] and o["m_abs"] == r["m_abs"] and o["Te_mean"] == r["Te_mean"]
         ref.close()
     b.close()
+
+
+def test_batch_run_added_out_of_phase_steps_unmerged(N):
+    """A run added to a merging batch at a step that is not a chunk boundary
+    of the others: the batch steps unmerged (two colour passes without the
+    kick per step) and every run keeps its bits alone."""
+    specs = [I.gdfeco_sc_spec(L=8, tn=2, alpha=0.03, S0=0.6, t0=0.005, fwhm=0.005,
+                              seed=40 + k, run_id=k) for k in range(3)]
+    states = [I.initial_state(sp, "afm") for sp in specs]
+    _log("case: batch, third run added after 25 steps")
+    b = N.Batch(precision=0, max_runs=4)
+    b.set_tuning(persist_block=0)
+    slots = [b.add(specs[k], states[k], 60, obs_every=10) for k in range(2)]
+    b.advance(25)
+    slots.append(b.add(specs[2], states[2], 40, obs_every=10))
+    avg, cnt = b.advance_profiled(20)      # phases 5 and 0 modulo 10: no chunk fits
+    assert cnt[0] == 2 * 20, cnt
+    b.advance(20)
+    for sp, st, t, s in zip(specs, states, (60, 60, 40), slots):
+        g = b.get(s)
+        ref = N.System(sp, st, precision=0, obs_every=1)
+        ref.step(t)
+        a = ref.state()
+        for k in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[k], g[k]), (t, k)
+        ref.close()
+    b.close()
