@@ -85,6 +85,8 @@ typedef struct sl_system_desc {
     int32_t n_shells;         /* 1 or 2                                           */
     double J[2][4][4];        /* eV                                               */
     double B[3];              /* applied field, T                                 */
+    double K[4];              /* uniaxial anisotropy per species along z, eV per
+                                 atom: energy -K s_z^2, field 2 K s_z / (mu mu_B) */
     double alpha;             /* Gilbert damping (>= 0)                           */
     int32_t noise_mode;       /* 0: FDT noise ~ 1/sqrt(mu);
                                  1: control ~ 1/mu (equal at mu_ref)             */
@@ -130,7 +132,8 @@ typedef struct sl_obs {
     double M[4][3];           /* mean spin per species                            */
     double m[3];              /* mean spin of all sites                           */
     double m_abs;
-    double E_ex, E_z;         /* exchange and Zeeman energy, eV                   */
+    double E_ex, E_z;         /* exchange energy; single-site energy (Zeeman and
+                                 uniaxial anisotropy), eV                        */
     double KE, PE;            /* lattice kinetic and Morse energy, eV             */
     double E_e;               /* electron energy sum gamma_e T_e^2/2 V_cell, eV    */
     double Te_mean, Te_max;   /* K                                                */

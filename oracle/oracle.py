@@ -58,7 +58,7 @@ class OrDesc(C.Structure):
         ("Te0", C.POINTER(C.c_double)), ("gamma_e", C.c_double), ("G_el", C.c_double),
         ("kappa_e", C.c_double), ("n_sub", C.c_int32), ("S0", C.c_double),
         ("t0", C.c_double), ("fwhm", C.c_double), ("profile", C.c_int32),
-        ("depth", C.c_double),
+        ("depth", C.c_double), ("K_s", C.POINTER(C.c_double)),
     ]
 
 
@@ -244,6 +244,7 @@ class Oracle:
         k["species"] = sp
         k["mu"] = np.ascontiguousarray(np.asarray(spec.mu, dtype=np.float64))
         k["mass"] = np.ascontiguousarray(np.asarray(spec.mass, dtype=np.float64))
+        k["K"] = np.ascontiguousarray(np.asarray(getattr(spec, "K", (0.0,) * 4), dtype=np.float64))
         k["nbr_off"] = np.ascontiguousarray(t.nbr_off, dtype=np.int32)
         k["nbr_j"] = np.ascontiguousarray(t.nbr_j, dtype=np.int32)
         k["nbr_J"] = np.ascontiguousarray(nbr_J, dtype=np.float64)
@@ -267,6 +268,7 @@ class Oracle:
         d.n_species = spec.n_species
         d.mu_s = _p(k["mu"], C.c_double)
         d.mass_s = _p(k["mass"], C.c_double)
+        d.K_s = _p(k["K"], C.c_double)
         d.nbr_off = _p(k["nbr_off"], C.c_int32)
         d.nbr_j = _p(k["nbr_j"], C.c_int32)
         d.nbr_J = _p(k["nbr_J"], C.c_double)

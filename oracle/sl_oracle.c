@@ -126,6 +126,8 @@ typedef struct {
     double S0, t0, fwhm;     /* laser: peak power density eV/(ps A^3), centre and FWHM (ps) */
     int32_t profile;         /* 0: uniform; 1: cells with centre z > box_z - depth */
     double depth;            /* Angstrom                                       */
+    const double* K_s;       /* [n_species] uniaxial anisotropy along z, eV per atom
+                                (energy -K s_z^2), or NULL for none           */
 } or_desc;
 
 typedef struct {
@@ -144,6 +146,7 @@ typedef struct {
     int32_t n, ncell;
     double *s, *x, *v, *F;   /* [n][3]                                         */
     double *mu, *mass;       /* [n]                                            */
+    double* K;               /* [n] anisotropy constant, eV                    */
     int32_t *colour, *ctr_id, *species, *nbr_off, *nbr_j;
     double* nbr_J;
     double *Te, *dE;         /* [ncell]                                        */
@@ -321,6 +324,9 @@ static void or_spin_step(or_system* S)
             if (S->colour[i] != colour) continue;
             double h[3];
             or_exchange_sum(S, i, h);
+            /* uniaxial anisotropy: -dE/ds of E = -K s_z^2 is 2 K s_z along z,
+             * from the spin this update starts from */
+            h[2] += 2.0 * S->K[i] * S->s[3 * i + 2];
             double w[3];
             for (int k = 0; k < 3; ++k) {
                 double H = h[k] / (S->mu[i] * OR_MUB) + S->d.B[k];   /* Tesla */
@@ -473,9 +479,11 @@ or_system* or_create(const or_desc* d)
     S->nbr_J = (double*)or_copy(d->nbr_J, sizeof(double) * nnz);
     S->mu = (double*)malloc(sizeof(double) * n);
     S->mass = (double*)malloc(sizeof(double) * n);
+    S->K = (double*)malloc(sizeof(double) * n);
     for (int32_t i = 0; i < n; ++i) {
         S->mu[i] = d->mu_s[S->species[i]];
         S->mass[i] = d->mass_s[S->species[i]];
+        S->K[i] = d->K_s != NULL ? d->K_s[S->species[i]] : 0.0;
         for (int k = 0; k < 3; ++k) S->x[3 * i + k] = or_wrap(S->x[3 * i + k], d->box[k]);
     }
     S->Te = (double*)or_copy(d->Te0, sizeof(double) * S->ncell);
@@ -491,7 +499,7 @@ or_system* or_create(const or_desc* d)
 void or_destroy(or_system* S)
 {
     if (!S) return;
-    free(S->s); free(S->x); free(S->v); free(S->F); free(S->mu); free(S->mass);
+    free(S->s); free(S->x); free(S->v); free(S->F); free(S->mu); free(S->mass); free(S->K);
     free(S->colour); free(S->ctr_id); free(S->species); free(S->nbr_off); free(S->nbr_j);
     free(S->nbr_J); free(S->Te); free(S->dE);
     free(S);
@@ -550,9 +558,11 @@ void or_observables(const or_system* S, or_obs* o)
             o->m[k] += s[k];
         }
         o->E_ex += -0.5 * (s[0] * h[0] + s[1] * h[1] + s[2] * h[2]);
-        o->E_z += -S->mu[i] * OR_MUB * (S->d.B[0] * s[0] + S->d.B[1] * s[1] + S->d.B[2] * s[2]);
+        o->E_z += -S->mu[i] * OR_MUB * (S->d.B[0] * s[0] + S->d.B[1] * s[1] + S->d.B[2] * s[2]) -
+                  S->K[i] * s[2] * s[2];
         double ht[3];
         for (int k = 0; k < 3; ++k) ht[k] = h[k] + S->mu[i] * OR_MUB * S->d.B[k];
+        ht[2] += 2.0 * S->K[i] * s[2];
         double cr[3] = {s[1] * ht[2] - s[2] * ht[1], s[2] * ht[0] - s[0] * ht[2],
                         s[0] * ht[1] - s[1] * ht[0]};
         num[sp] += cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];

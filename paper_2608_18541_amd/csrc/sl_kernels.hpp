@@ -83,6 +83,7 @@ template <typename T> struct alignas(4 * sizeof(T)) Pos4 {
 template <typename T> struct RunDev {
     Geom g;
     int32_t lattice, n, n_species, n_shells, live, ttm_mode, obs_every, obs_cap;
+    int32_t aniso;       // some species has a uniaxial anisotropy (Kd, kan below)
     int32_t noisy;       // some species has a thermal field (sig > 0)
     int32_t bin_step;    // 1: atoms are binned by the kick every step, 0: only for a rebuild
     int32_t eta_drawn;   // 1: the kick draws the electron-phonon normals into eta for the
@@ -131,6 +132,10 @@ template <typename T> struct RunDev {
     int32_t* any_rebuild;            // engine-wide: a run flagged a list rebuild this step
     T* eta;                          // [3][n]: the step's electron-phonon normals (live
                                      // runs), drawn by the kick for the force kernel
+    // uniaxial anisotropy along z per species (energy -K s_z^2), kept last so
+    // that the fields every kernel reads keep their places
+    double Kd[4];                    // K, eV
+    T kan[4];                        // its field per unit s_z, 2 K / (mu mu_B), T
 };
 
 // ------------------------------------------------------- memory access
@@ -560,7 +565,7 @@ __device__ inline double cell_energy(const RunDev<T>& R, double e0, unsigned lon
 template <typename T> __device__ inline double cell_e0(const RunDev<T>& R, double T0);
 __device__ inline double cell_temp(double e, double ge);
 
-template <typename T, typename VW, int LAT, bool MULTI>
+template <typename T, typename VW, int LAT, bool MULTI, bool ANISO>
 __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int colour, T tau,
                                             uint32_t l, int64_t step, bool cur = true,
                                             bool has_prev = false, PrevHalf prev = {})
@@ -584,6 +589,11 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
     // one exact rotation over tau_ with the thermal field of step stp at T_e
     auto rotate = [&](V3<T> s0, int64_t stp, double Te, T tau_) {
         T Hx = H0x, Hy = H0y, Hz = H0z;
+        // uniaxial anisotropy: 2 K s_z / (mu mu_B) along z, from the spin
+        // this rotation starts from (a merged pass's second rotation sees the
+        // first one's result)
+        if constexpr (ANISO)
+            Hz += (MULTI ? select4(sp, R.kan[0], R.kan[1], R.kan[2], R.kan[3]) : R.kan[0]) * s0.z;
         if (R.noisy) {
             const Normals3<T> nu = normals3<T>(R.seed, R.run_id, canon, stp, 0u);
             const T sg = MULTI ? select4(sp, R.sig[0], R.sig[1], R.sig[2], R.sig[3]) : R.sig[0];
@@ -624,12 +634,24 @@ __device__ __forceinline__ void spin_site(const RunDev<T>& R, const VW& V, int c
                                           uint32_t l, int64_t step, bool cur = true,
                                           bool has_prev = false, PrevHalf prev = {})
 {
+    // runs with anisotropy take their own instantiation, so those without
+    // keep the site update's code unchanged
+    if (R.aniso) {
+        if (R.lattice == SL_LATTICE_SC) {
+            if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+            else spin_site_t<T, VW, SL_LATTICE_SC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        } else {
+            if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+            else spin_site_t<T, VW, SL_LATTICE_BCC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        }
+        return;
+    }
     if (R.lattice == SL_LATTICE_SC) {
-        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        else spin_site_t<T, VW, SL_LATTICE_SC, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else spin_site_t<T, VW, SL_LATTICE_SC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     } else {
-        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        else spin_site_t<T, VW, SL_LATTICE_BCC, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else spin_site_t<T, VW, SL_LATTICE_BCC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     }
 }
 
@@ -1029,10 +1051,12 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
         const double h0 = h.x, h1 = h.y, h2 = h.z;
         const double mb = select4(sp, R.mumb[0], R.mumb[1], R.mumb[2], R.mumb[3]);
         o.eex = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
-        o.ez = -mb * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2);
+        // single-site energy and field: Zeeman and uniaxial anisotropy
+        const double kk = select4(sp, R.Kd[0], R.Kd[1], R.Kd[2], R.Kd[3]);
+        o.ez = -mb * (R.Bd[0] * s0 + R.Bd[1] * s1 + R.Bd[2] * s2) - kk * s2 * s2;
         const double t0 = h0 + mb * R.Bd[0];
         const double t1 = h1 + mb * R.Bd[1];
-        const double t2 = h2 + mb * R.Bd[2];
+        const double t2 = h2 + mb * R.Bd[2] + 2.0 * kk * s2;
         const double c0 = s1 * t2 - s2 * t1, c1 = s2 * t0 - s0 * t2, c2 = s0 * t1 - s1 * t0;
         o.num = c0 * c0 + c1 * c1 + c2 * c2;
         o.den = s0 * t0 + s1 * t1 + s2 * t2;

@@ -899,6 +899,10 @@ private:
             const double m = sp < d->n_species && d->mass[sp] > 0 ? d->mass[sp] : 1.0;
             R.inv_mumb[sp] = (T)(1.0 / (mu * sl::kMUB));
             R.mumb[sp] = mu * sl::kMUB;
+            const double K = sp < d->n_species ? d->K[sp] : 0.0;
+            R.Kd[sp] = K;
+            R.kan[sp] = (T)(2.0 * K / (mu * sl::kMUB));
+            if (K != 0.0) R.aniso = 1;
             double sig = std::sqrt(2.0 * d->alpha * sl::kKB / (sl::kGAMMA * mu * sl::kMUB * d->dt));
             if (d->noise_mode == 1) sig *= std::sqrt(d->mu_ref / mu);
             R.sig[sp] = (T)sig;

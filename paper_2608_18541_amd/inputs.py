@@ -71,6 +71,7 @@ class SystemSpec:
     J: tuple = (((0.022, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0)),
                 ((0.011, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0)))
     B: tuple = (0.0, 0.0, 1.0)
+    K: tuple = (0.0, 0.0, 0.0, 0.0)             # uniaxial anisotropy along z, eV/atom
     alpha: float = 0.1
     noise_mode: int = 0
     mu_ref: float = 0.0

@@ -40,7 +40,8 @@ class sl_system_desc(C.Structure):
         ("lattice", C.c_int32), ("ncell", C.c_int32 * 3), ("a", C.c_double),
         ("n_species", C.c_int32), ("species", C.POINTER(C.c_int8)), ("mu", C.c_double * 4),
         ("mass", C.c_double * 4), ("n_shells", C.c_int32), ("J", ((C.c_double * 4) * 4) * 2),
-        ("B", C.c_double * 3), ("alpha", C.c_double), ("noise_mode", C.c_int32),
+        ("B", C.c_double * 3), ("K", C.c_double * 4), ("alpha", C.c_double),
+        ("noise_mode", C.c_int32),
         ("mu_ref", C.c_double), ("lattice_mode", C.c_int32), ("morse", C.c_double * 4),
         ("skin", C.c_double), ("dt", C.c_double), ("seed", C.c_uint32), ("run_id", C.c_uint32),
         ("precision", C.c_int32), ("obs_every", C.c_int32), ("obs_capacity", C.c_int32),
@@ -225,6 +226,7 @@ def system_desc(spec: I.SystemSpec, state: I.InitialState, precision: int = SL_F
             for b in range(4):
                 d.J[sh][a][b] = float(J[sh, a, b])
     d.B = (C.c_double * 3)(*spec.B)
+    d.K = (C.c_double * 4)(*spec.K)
     d.alpha = spec.alpha
     d.noise_mode = spec.noise_mode
     d.mu_ref = spec.mu_ref

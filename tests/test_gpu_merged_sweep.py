@@ -40,6 +40,11 @@ def _cases():
     # (the deferred half step reads the previous step's T_e)
     yield "alloy_laser_live", I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005,
                                                fwhm=0.005), "afm"
+    # uniaxial anisotropy: the field depends on the site's own spin, so the
+    # merged pass's second rotation takes it from the first one's result
+    yield "alloy_anisotropy", replace(
+        I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005),
+        K=(2.0e-3, 1.0e-3, 0.0, 0.0)), "afm"
     # diffusing electrons heated in a top slab: four diffusion sub-steps per
     # step in one tiled launch, the previous step's T_e kept by the grid update
     yield "alloy_diffusing", replace(
@@ -53,7 +58,8 @@ def _samples(sysobj, every):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("case", ["bcc_fixed_Te", "alloy_laser_live", "alloy_diffusing"])
+@pytest.mark.parametrize("case", ["bcc_fixed_Te", "alloy_laser_live", "alloy_anisotropy",
+                                  "alloy_diffusing"])
 def test_merged_sweep_equals_unmerged(N, case, prec):
     name, spec, init = next(c for c in _cases() if c[0] == case)
     st = I.initial_state(spec, init)

@@ -114,6 +114,26 @@ def test_diffusion_surface_heating_window(N):
     assert Te[-1].mean() > Te[0].mean() + 10.0
 
 
+def test_uniaxial_anisotropy_window(N):
+    """Uniaxial anisotropy along z per species (energy -K s_z^2): the
+    laser-heated sc alloy with a frozen lattice (the paper's production
+    runs freeze it) and live bcc Fe, 100 steps against the oracle, and the
+    single-site energy of the last sample.  K is 20-60 times the literature
+    value so that the term matters within the window."""
+    cases = ((replace(_alloy_window(), lattice_mode=0, K=(2.0e-3, 1.0e-3, 0.0, 0.0)), "afm"),
+             (replace(I.fe_bcc_spec(L=6), K=(3.0e-3, 0.0, 0.0, 0.0)), "tilt"))
+    for spec, init in cases:
+        st = I.initial_state(spec, init)
+        g, o = run_pair(N, spec, st, 100, obs_every=100)
+        g.step(100)
+        o.step(100)
+        errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+        assert not bad, errs
+        ez_g = g.observables()[-1]["E_z"]
+        ez_o = o.observables()["E_z"]
+        assert abs(ez_g - ez_o) <= 1e-10 * max(1.0, abs(ez_o)), (ez_g, ez_o)
+
+
 def test_many_diffusion_substeps_window(N):
     """Forty diffusion sub-steps per step: a tile with a halo forty cells deep
     does not fit in LDS, so the sub-steps run as one launch each (the tiled

@@ -128,6 +128,48 @@ def test_larmor_closed_form(alpha, dt, mu):
     np.testing.assert_allclose(s, ref, atol=2e-12 * max(1.0, phi))
 
 
+@pytest.mark.parametrize("K, mu", [(2.0e-3, 2.2), (-1.5e-3, 7.63), (5.0384e-5, 1.92)])
+def test_uniaxial_anisotropy_precession_closed_form(K, mu):
+    """Single spin with uniaxial anisotropy K along z (energy -K s_z^2) and a
+    field B_z, no damping, no noise: the anisotropy field 2 K s_z / (mu mu_B)
+    stays along z with s_z fixed, so the spin precesses about z at
+    gamma (B_z + 2 K cos(theta) / (mu mu_B)), and the single-site energy
+    -mu mu_B B_z cos(theta) - K cos^2(theta) stays constant.  An easy plane
+    (K < 0) reverses the anisotropy term's sense."""
+    Bz = 0.7
+    th0 = math.radians(35.0)
+    s0 = np.array([[math.sin(th0), 0.0, math.cos(th0)]])
+    top = O.generic_topology(1, [], [0])
+    spec = spin_only_spec(B=(0.0, 0.0, Bz), alpha=0.0, dt=2e-4, mu=(mu, 0, 0, 0),
+                          K=(K, 0.0, 0.0, 0.0))
+    orc = O.Oracle(spec, [0], s0, topology=top)
+    nsteps = 53
+    orc.step(nsteps)
+    s = orc.state()["s"][0]
+    w = GAMMA * (Bz + 2.0 * K * math.cos(th0) / (mu * MUB))
+    phi = w * nsteps * spec.dt
+    ref = np.array([math.sin(th0) * math.cos(phi), math.sin(th0) * math.sin(phi), math.cos(th0)])
+    np.testing.assert_allclose(s, ref, atol=2e-12 * max(1.0, abs(phi)))
+    E = orc.observables()["E_z"]
+    assert abs(E - (-mu * MUB * Bz * math.cos(th0) - K * math.cos(th0) ** 2)) < 1e-15
+
+
+def test_uniaxial_anisotropy_damping_toward_the_easy_axis():
+    """With damping and no field, an easy axis (K > 0) pulls a tilted spin to
+    the nearer pole and an easy plane (K < 0) to the equator, each with the
+    single-site energy -K s_z^2 falling at every step."""
+    for K, sz0, goal in ((3.0e-3, 0.6, 1.0), (3.0e-3, -0.6, -1.0), (-3.0e-3, 0.6, 0.0)):
+        s0 = np.array([[math.sqrt(1.0 - sz0 ** 2), 0.0, sz0]])
+        spec = spin_only_spec(alpha=0.3, dt=2e-4, K=(K, 0.0, 0.0, 0.0))
+        orc = O.Oracle(spec, [0], s0, topology=O.generic_topology(1, [], [0]))
+        energies = []
+        for _ in range(60):                  # 4.8 ps, relaxation rate about 2.3 / ps
+            orc.step(400)
+            energies.append(orc.observables()["E_z"])
+        assert all(b < a for a, b in zip(energies, energies[1:])), (K, sz0)
+        assert abs(orc.state()["s"][0][2] - goal) < 1e-3, (K, sz0, orc.state()["s"][0])
+
+
 def test_flow_field_axis_any_direction():
     """Rotation sense and damping direction for a field not along z: damping
     turns the spin toward the field, precession is right-handed about it."""
