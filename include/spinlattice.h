@@ -109,7 +109,11 @@ typedef struct sl_system_desc {
 /* Electron-temperature grid over the periodic box, cell (i,j,k) at index
  * (k*n1 + j)*n0 + i; cell c holds the atoms whose wrapped position p has
  * floor(p_d / (box_d / n_d)) = c_d.  mode 0 keeps T_e fixed (no
- * electron-phonon step); mode 1 runs the two-temperature update. */
+ * electron-phonon step); mode 1 runs the two-temperature update; mode 2
+ * prescribes a uniform stepped T_e(t): step_T[0] before step_end[0],
+ * step_T[1] before step_end[1], step_T[2] after (the heat-pulse profile of
+ * the production runs; no electron-phonon step), step n using
+ * T_e(n dt). */
 typedef struct sl_ttm_desc {
     int32_t n[3];             /* cells per dimension (product <= 65535)           */
     int32_t mode;             /* 0 fixed field, 1 two-temperature                 */
@@ -123,6 +127,8 @@ typedef struct sl_ttm_desc {
     double t0, fwhm;          /* pulse centre and FWHM, ps                        */
     int32_t profile;          /* 0 uniform; 1 cells whose centre z > box_z - depth */
     double depth;             /* A                                                */
+    double step_T[3];         /* mode 2: T_e of the three stages, K (>= 0)        */
+    double step_end[2];       /* mode 2: ends of stages 1 and 2, ps (ascending)   */
 } sl_ttm_desc;
 
 /* One observable sample, taken after a step (and once at step 0). */

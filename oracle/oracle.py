@@ -59,6 +59,7 @@ class OrDesc(C.Structure):
         ("kappa_e", C.c_double), ("n_sub", C.c_int32), ("S0", C.c_double),
         ("t0", C.c_double), ("fwhm", C.c_double), ("profile", C.c_int32),
         ("depth", C.c_double), ("K_s", C.POINTER(C.c_double)),
+        ("step_T", C.c_double * 3), ("step_end", C.c_double * 2),
     ]
 
 
@@ -257,7 +258,11 @@ class Oracle:
         k["s0"] = np.ascontiguousarray(np.asarray(spins, dtype=np.float64).reshape(n, 3))
         ncell = int(np.prod(spec.tn))
         if Te is None:
-            Te = np.full(ncell, float(spec.Te0))
+            T0 = float(spec.Te0)
+            if getattr(spec, "ttm_mode", 0) == 2:       # a stepped profile starts at its t = 0 value
+                T0 = float(spec.step_T[0] if 0.0 < spec.step_end[0] else
+                           (spec.step_T[1] if 0.0 < spec.step_end[1] else spec.step_T[2]))
+            Te = np.full(ncell, T0)
         k["Te0"] = np.ascontiguousarray(np.asarray(Te, dtype=np.float64).reshape(ncell))
         d = OrDesc()
         d.n = n
@@ -269,6 +274,8 @@ class Oracle:
         d.mu_s = _p(k["mu"], C.c_double)
         d.mass_s = _p(k["mass"], C.c_double)
         d.K_s = _p(k["K"], C.c_double)
+        d.step_T = (C.c_double * 3)(*getattr(spec, "step_T", (0.0, 0.0, 0.0)))
+        d.step_end = (C.c_double * 2)(*getattr(spec, "step_end", (0.0, 0.0)))
         d.nbr_off = _p(k["nbr_off"], C.c_int32)
         d.nbr_j = _p(k["nbr_j"], C.c_int32)
         d.nbr_J = _p(k["nbr_J"], C.c_double)

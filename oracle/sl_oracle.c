@@ -117,7 +117,8 @@ typedef struct {
     int32_t lattice_live;    /* 0: positions frozen; 1: velocity Verlet        */
     double morse[4];         /* D (eV), a (1/Angstrom), r0 (A), cutoff rc (A)   */
     int32_t tn[3];           /* electron-temperature grid cells per dimension   */
-    int32_t ttm_mode;        /* 0: fixed T_e field; 1: two-temperature update  */
+    int32_t ttm_mode;        /* 0: fixed T_e field; 1: two-temperature update;
+                                2: prescribed stepped T_e(t)                   */
     const double* Te0;       /* [tn0*tn1*tn2] initial T_e, K, x fastest        */
     double gamma_e;          /* C_e = gamma_e T_e, eV / (Angstrom^3 K^2)        */
     double G_el;             /* electron-phonon coupling, eV/(ps Angstrom^3 K)  */
@@ -128,6 +129,8 @@ typedef struct {
     double depth;            /* Angstrom                                       */
     const double* K_s;       /* [n_species] uniaxial anisotropy along z, eV per atom
                                 (energy -K s_z^2), or NULL for none           */
+    double step_T[3];        /* ttm_mode 2: stage temperatures, K              */
+    double step_end[2];      /* ttm_mode 2: ends of stages 1 and 2, ps         */
 } or_desc;
 
 typedef struct {
@@ -518,6 +521,12 @@ int or_step(or_system* S, int64_t nsteps)
             memset(S->dE, 0, sizeof(double) * S->ncell);
             if (S->d.lattice_live) or_eph_step(S);
             if (or_ttm_step(S) != 0) { S->err = 1; return -1; }
+        } else if (S->d.ttm_mode == 2) {
+            /* prescribed stepped profile: every cell at T_e(t_{n+1}) */
+            double t = (double)(S->step + 1) * S->d.dt;
+            double T = t < S->d.step_end[0] ? S->d.step_T[0]
+                     : (t < S->d.step_end[1] ? S->d.step_T[1] : S->d.step_T[2]);
+            for (int32_t c = 0; c < S->ncell; ++c) S->Te[c] = T;
         }
         S->step += 1;
     }

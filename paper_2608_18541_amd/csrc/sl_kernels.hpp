@@ -136,6 +136,7 @@ template <typename T> struct RunDev {
     // that the fields every kernel reads keep their places
     double Kd[4];                    // K, eV
     T kan[4];                        // its field per unit s_z, 2 K / (mu mu_B), T
+    double stT[3], stEnd[2];         // stepped T_e profile (grid mode 2): K, ps
 };
 
 // ------------------------------------------------------- memory access
@@ -540,6 +541,12 @@ template <typename T> __device__ inline bool empties_bins_in_grid(const RunDev<T
 template <typename T> __device__ inline bool keeps_prev_te(const RunDev<T>& R)
 {
     return R.kappa_e == 0.0 || R.dtile[0] > 0;
+}
+// Grid mode 2: the prescribed stepped T_e of step n, at t = n dt.
+template <typename T> __device__ inline double te_stepped(const RunDev<T>& R, int64_t n)
+{
+    const double t = (double)n * R.dtd;
+    return t < R.stEnd[0] ? R.stT[0] : (t < R.stEnd[1] ? R.stT[1] : R.stT[2]);
 }
 
 // ------------------------------------------------------------ spins
@@ -1397,9 +1404,9 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     if (fold_k >= 0) V.Te = te_buf(R, fold_k);
     // T_e of the previous step: in a folded chunk the previous position's
     // buffer (and this step's T_e is computed from it, its end running in
-    // this launch); otherwise kept by the grid update in the diffusion
-    // buffer (runs that merge do not diffuse); a fixed grid never changes
-    PrevHalf ph{R.cellb[(step - 1) & 1], R.ttm_mode == 1 ? R.Te_alt : R.Te, nullptr};
+    // this launch); otherwise kept by the grid update (two-temperature or
+    // prescribed) in the second buffer; a fixed grid never changes
+    PrevHalf ph{R.cellb[(step - 1) & 1], R.ttm_mode != 0 ? R.Te_alt : R.Te, nullptr};
     if (fold_k >= 1 && pass == 0)
         ph = PrevHalf{R.cellb[(step - 1) & 1], te_buf(R, fold_k - 1),
                       R.ttm_mode == 1 ? de_buf(R, fold_k - 1) : nullptr};
@@ -1718,9 +1725,18 @@ __global__ __launch_bounds__(kBlock) void k_grid(const RunDev<T>* __restrict__ r
     const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     int64_t step;
-    if (!run_active(R, &step) || R.ttm_mode != 1 || R.ncell <= kSmallGrid) return;
+    if (!run_active(R, &step) || R.ttm_mode == 0 || R.ncell <= kSmallGrid) return;
     const int c = w.y + (int)threadIdx.x;
-    if (c < R.ncell) cell_update(R, R.Te, R.dE, c, step, keeps_prev_te(R) ? R.Te_alt : nullptr);
+    if (c < R.ncell) {
+        if (R.ttm_mode == 2) {
+            // the prescribed profile (the previous step's value kept for a
+            // deferred spin half step)
+            R.Te_alt[c] = R.Te[c];
+            R.Te[c] = te_stepped(R, step + 1);
+        } else {
+            cell_update(R, R.Te, R.dE, c, step, keeps_prev_te(R) ? R.Te_alt : nullptr);
+        }
+    }
     // the bins filled this step, emptied here for such runs (spread over the
     // grid's blocks rather than by the one block of the step end)
     if (empties_bins_in_grid(R) && (R.bin_step || R.st->rebuild != 0)) {
@@ -1793,6 +1809,16 @@ __device__ inline void end_step(const RunDev<T>& R, SampleScratch& S, int phase,
         return;
     }
     const int64_t step = S.step;
+    if (phase == PHASE_STEP && R.ttm_mode == 2 && R.ncell <= kSmallGrid) {
+        // the prescribed profile (the previous step's value kept for a
+        // deferred spin half step)
+        const double Tn = te_stepped(R, step + 1);
+        for (int c = tid; c < R.ncell; c += blockDim.x) {
+            R.Te_alt[c] = R.Te[c];
+            R.Te[c] = Tn;
+        }
+        __syncthreads();
+    }
     if (grid) {
         double* const keep_prev = keeps_prev_te(R) ? R.Te_alt : nullptr;
         int q = 0;
@@ -1970,6 +1996,10 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
             }
             for (int c = tid; c < nc; c += B) cell_update(R, V.Te, acc, c, step);
             if (error_raised()) break;
+        } else if (R.ttm_mode == 2) {
+            const double Tn = te_stepped(R, step + 1);
+            for (int c = tid; c < nc; c += B) V.Te[c] = Tn;
+            __syncthreads();
         }
         if (obs) write_sample(R, V, P.S, step + 1);
         ++step;

@@ -173,7 +173,12 @@ std::string validate_ttm(const sl_ttm_desc* t, const sl_system_desc* d)
         nc *= t->n[k];
     }
     if (nc > 65535) return "at most 65535 electron cells";
-    if (t->mode != 0 && t->mode != 1) return "grid mode must be 0 or 1";
+    if (t->mode < 0 || t->mode > 2) return "grid mode must be 0, 1 or 2";
+    if (t->mode == 2) {
+        for (int k = 0; k < 3; ++k)
+            if (!(t->step_T[k] >= 0.0)) return "stepped temperatures must be >= 0";
+        if (!(t->step_end[0] <= t->step_end[1])) return "stage ends must be ascending";
+    }
     double tmin = t->Te0;
     if (t->Te_init) {
         tmin = t->Te_init[0];
@@ -985,6 +990,8 @@ private:
         R.dtd = d->dt;
         for (int k = 0; k < 3; ++k) R.dcoef[k] = d->dt / (double)R.n_sub * R.kappa_e / (R.th[k] * R.th[k]);
         R.two_ge = 2.0 / R.gamma_e;
+        for (int k = 0; k < 3; ++k) R.stT[k] = t->step_T[k];
+        for (int k = 0; k < 2; ++k) R.stEnd[k] = t->step_end[k];
         // diffusion tiles: the tile plus its halo of n_sub cells spans at most
         // 16 cells along every axis (k_ttm_tile's layout), and its three LDS
         // arrays must fit one block; otherwise one launch per sub-step.  The
@@ -1029,7 +1036,12 @@ private:
         R.dE = c.take<unsigned long long>(r.z.ncell);
         R.dE_alt = c.take<unsigned long long>(r.z.ncell);
 
-        std::vector<double> te(r.z.ncell, t->Te0);
+        // a stepped profile starts the grid at its value at t = 0
+        const double te0 = t->mode != 2 ? t->Te0
+                                         : (0.0 < t->step_end[0] ? t->step_T[0]
+                                                                 : (0.0 < t->step_end[1] ? t->step_T[1]
+                                                                                         : t->step_T[2]));
+        std::vector<double> te(r.z.ncell, te0);
         if (t->Te_init) std::copy(t->Te_init, t->Te_init + r.z.ncell, te.begin());
         r.te_init = te;
         r.t.Te_init = nullptr;
@@ -1191,7 +1203,7 @@ private:
             for (int st = 0; st < R.n; st += atile) wa.push_back(make_int2((int)s, st));
             if (R.live)
                 for (int st = 0; st < R.n; st += spin_eff) wk.push_back(make_int2((int)s, st));
-            if (R.ttm_mode == 1 && R.ncell > sl::kSmallGrid)
+            if (R.ttm_mode != 0 && R.ncell > sl::kSmallGrid)
                 for (int st = 0; st < R.ncell; st += sl::kBlock) wc.push_back(make_int2((int)s, st));
             rl.push_back((int)s);
             if (R.ttm_mode == 1 && R.kappa_e != 0.0 && R.dtile[0] > 0) {
@@ -1275,7 +1287,10 @@ private:
                 merge_g = g;
                 const RD& R = host_rd[merge_run];
                 if (rl.size() == 1) {
-                    fold = !(R.ttm_mode == 1 && (R.ncell > sl::kSmallGrid || R.kappa_e != 0.0));
+                    // (a prescribed profile is written at the step end in
+                    // place, so it does not fold)
+                    fold = R.ttm_mode != 2 &&
+                           !(R.ttm_mode == 1 && (R.ncell > sl::kSmallGrid || R.kappa_e != 0.0));
                     // one thread per electron cell, four bins per thread
                     const int cells = R.ttm_mode == 1 ? R.ncell : 0;
                     const int bins = R.live ? (R.nbins + 3) / 4 : 0;

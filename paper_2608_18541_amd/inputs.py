@@ -94,6 +94,9 @@ class SystemSpec:
     fwhm: float = 0.0
     profile: int = 0
     depth: float = 0.0
+    # ttm_mode 2: stepped T_e(t), stage temperatures (K) and ends of stages 1, 2 (ps)
+    step_T: tuple = (0.0, 0.0, 0.0)
+    step_end: tuple = (0.0, 0.0)
 
     @property
     def nbasis(self) -> int:

@@ -57,6 +57,7 @@ class sl_ttm_desc(C.Structure):
         ("Te_init", C.POINTER(C.c_double)), ("gamma_e", C.c_double), ("G_el", C.c_double),
         ("kappa_e", C.c_double), ("n_sub", C.c_int32), ("S0", C.c_double), ("t0", C.c_double),
         ("fwhm", C.c_double), ("profile", C.c_int32), ("depth", C.c_double),
+        ("step_T", C.c_double * 3), ("step_end", C.c_double * 2),
     ]
 
 
@@ -276,6 +277,8 @@ def ttm_desc(spec: I.SystemSpec, Te: Optional[np.ndarray] = None):
     t.fwhm = spec.fwhm
     t.profile = spec.profile
     t.depth = spec.depth
+    t.step_T = (C.c_double * 3)(*spec.step_T)
+    t.step_end = (C.c_double * 2)(*spec.step_end)
     return t, keep
 
 

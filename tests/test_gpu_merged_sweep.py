@@ -45,6 +45,11 @@ def _cases():
     yield "alloy_anisotropy", replace(
         I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005),
         K=(2.0e-3, 1.0e-3, 0.0, 0.0)), "afm"
+    # the stepped T_e profile on a frozen lattice (the production runs):
+    # the deferred half step reads the stage of its own step
+    yield "alloy_stepped_profile", replace(
+        I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, lattice_mode=0, K=(2.0e-3, 1.0e-3, 0.0, 0.0)),
+        ttm_mode=2, step_T=(1100.0, 550.0, 300.0), step_end=(0.0042, 0.0097)), "afm"
     # diffusing electrons heated in a top slab: four diffusion sub-steps per
     # step in one tiled launch, the previous step's T_e kept by the grid update
     yield "alloy_diffusing", replace(
@@ -59,7 +64,7 @@ def _samples(sysobj, every):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("case", ["bcc_fixed_Te", "alloy_laser_live", "alloy_anisotropy",
-                                  "alloy_diffusing"])
+                                  "alloy_stepped_profile", "alloy_diffusing"])
 def test_merged_sweep_equals_unmerged(N, case, prec):
     name, spec, init = next(c for c in _cases() if c[0] == case)
     st = I.initial_state(spec, init)

@@ -134,6 +134,22 @@ def test_uniaxial_anisotropy_window(N):
         assert abs(ez_g - ez_o) <= 1e-10 * max(1.0, abs(ez_o)), (ez_g, ez_o)
 
 
+def test_stepped_profile_frozen_alloy_window(N):
+    """The production runs' set-up: frozen lattice, the alloy's exchange and
+    moments, uniaxial anisotropy, and the three-stage stepped T_e profile
+    (grid mode 2), with both stage ends inside 150 steps; against the
+    oracle, and the grid at the end."""
+    spec = replace(I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, lattice_mode=0, K=(2.0e-3, 1.0e-3, 0.0, 0.0)),
+                   ttm_mode=2, step_T=(1100.0, 550.0, 300.0), step_end=(0.0042, 0.0097))
+    st = I.initial_state(spec, "afm")
+    g, o = run_pair(N, spec, st, 150)
+    g.step(150)
+    o.step(150)
+    errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+    assert not bad, errs
+    assert np.all(g.state()["Te"] == 300.0)
+
+
 def test_many_diffusion_substeps_window(N):
     """Forty diffusion sub-steps per step: a tile with a halo forty cells deep
     does not fit in LDS, so the sub-steps run as one launch each (the tiled

@@ -170,6 +170,28 @@ def test_uniaxial_anisotropy_damping_toward_the_easy_axis():
         assert abs(orc.state()["s"][0][2] - goal) < 1e-3, (K, sz0, orc.state()["s"][0])
 
 
+def test_stepped_electron_temperature_profile():
+    """Grid mode 2 prescribes the production runs' heat pulse: T_e^0, then a
+    second level, then the base temperature, switching when t = n dt
+    reaches each stage end; the electrons neither diffuse nor exchange
+    energy with the lattice."""
+    dt = 1e-4
+    spec = replace(spin_only_spec(alpha=0.05, dt=dt, B=(0.0, 0.0, 1.0), ncell=(2, 2, 2), tn=(2, 1, 1)),
+                   ttm_mode=2, step_T=(1100.0, 550.0, 300.0), step_end=(0.0025, 0.0061))
+    s0 = np.tile([0.0, 0.0, 1.0], (8, 1))
+    orc = O.Oracle(spec, [0] * 8, s0, topology=O.generic_topology(8, [], [0] * 8))
+    seen = [orc.state()["Te"].copy()]
+    for _ in range(80):
+        orc.step(1)
+        seen.append(orc.state()["Te"].copy())
+    for n, Te in enumerate(seen):
+        t = n * dt
+        want = 1100.0 if t < 0.0025 else (550.0 if t < 0.0061 else 300.0)
+        assert np.all(Te == want), (n, Te)
+    # the boundaries fall on whole steps of t = n dt: 25 and 61
+    assert seen[24][0] == 1100.0 and seen[25][0] == 550.0 and seen[61][0] == 300.0
+
+
 def test_flow_field_axis_any_direction():
     """Rotation sense and damping direction for a field not along z: damping
     turns the spin toward the field, precession is right-handed about it."""
