@@ -155,7 +155,7 @@ def plain_step_time(N, run, steps: int = 2000) -> float:
 def sublattice_analysis(runs, traj, flags) -> dict:
     """The paper's trajectory readings over an ensemble: single-exponential
     collapse times of the TM and Gd projections (fitted from the laser
-    peak), and the transient ferromagnetic-like interval of the switched
+    peak, or from t = 0 under a stepped profile), and the transient ferromagnetic-like interval of the switched
     runs."""
     from paper_2608_18541_amd import analysis as A
     tau_tm, tau_gd, tfls = [], [], []
@@ -166,7 +166,8 @@ def sublattice_analysis(runs, traj, flags) -> dict:
         t, mz_tm, mz_gd = tr
         for series, out in ((mz_tm, tau_tm), (mz_gd, tau_gd)):
             try:
-                tau, _ = A.collapse_time(t, series, t_on=r.spec.t0)
+                t_on = None if r.spec.ttm_mode == 2 else r.spec.t0
+                tau, _ = A.collapse_time(t, series, t_on=t_on)
                 if 0.0 < tau < t[-1]:
                     out.append(tau)
             except (RuntimeError, ValueError):
@@ -269,6 +270,66 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     })
     return res
 
+
+
+def production_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
+    """The production phase diagram: 8 peak T_e (800-2900 K) x 8 cooling
+    multipliers (d = 1-8) x seeds, 16^3 sc alloy runs on a frozen lattice
+    with the literature anisotropy, alpha 0.01, B = 0 and the stepped T_e
+    profile, in one FP32 batch; switching probabilities per cell and the
+    rate of one run on the plain FP64 path."""
+    from paper_2608_18541_amd.stats import switched, wilson_ci
+    base_ends = (0.1, 0.5)
+    runs = W.production_diagram(L=16, n_seeds=n_seeds, n_steps=n_steps, base_ends=base_ends)
+    b = N.Batch(precision=N.SL_FP32, max_runs=len(runs))
+    slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
+             for r in runs]
+    b.synchronize()
+    with host_quiet():
+        t0 = time.perf_counter()
+        b.advance(n_steps)
+        try:
+            b.synchronize()
+        except N.SLError:
+            pass
+        el = time.perf_counter() - t0
+    fl, failed, traj = [], 0, []
+    for s in slots:
+        try:
+            obs = b.get(s, max_samples=n_steps // 20 + 2, state=False)["obs"]
+            mz = [o["M"][1][2] for o in obs]
+            fl.append(switched(mz))
+            traj.append((np.array([o["t"] for o in obs]), np.array([o["M"][0][2] for o in obs]),
+                         np.array(mz)))
+        except N.SLError:
+            failed += 1
+            fl.append(False)
+            traj.append(None)
+    b.close()
+    print("bench: production diagram: %.2f s" % el, file=sys.stderr, flush=True)
+    flags = np.array(fl).reshape(8, 8, n_seeds)
+    k = flags.sum(axis=2)
+    ci = [wilson_ci(int(v), n_seeds) for v in k.ravel()]
+    t_plain = plain_step_time(N, runs[0])
+    plain_rps = 1.0 / (t_plain * n_steps)
+    res = {
+        "workload": "Gd25(FeCo)75 sc 16^3 frozen lattice, K %.4g eV, alpha 0.01, B = 0, stepped "
+                    "T_e (T0, T0/2, 300 K; stage ends d x %g, d x %g ps) x (8 T0 800-2900 K) x "
+                    "(8 d 1-8) x %d seeds = %d runs, %d steps"
+                    % (runs[0].spec.K[0], base_ends[0], base_ends[1], n_seeds, len(runs), n_steps),
+        "seconds": round(el, 3), "runs_per_s": round(len(runs) / el, 3),
+        "atom_steps_per_s": len(runs) * 4096 * n_steps / el, "failed_runs": failed,
+        "plain_fp64_runs_per_s": round(plain_rps, 4),
+        "plain_us_per_step": round(t_plain * 1e6, 2),
+        "speedup_vs_plain": round(len(runs) / el / plain_rps, 1),
+        "P": np.round(k / n_seeds, 3).tolist(),
+        "P_rows_T0_cols_d_note": "rows T0 = 800, 1100, ..., 2900 K; columns d = 1, ..., 8",
+        "wilson_halfwidth_max": float(max(h - l for l, h in ci) / 2),
+        "stage_note": "the paper gives the stage temperatures and that d scales the durations, "
+                      "not the base durations: %g ps and %g ps here" % base_ends,
+    }
+    res.update(sublattice_analysis(runs, traj, fl))
+    return res
 
 def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
     """Poisson request stream served with continuous batching (FP32), and a
@@ -479,10 +540,12 @@ def main() -> int:
                          "automatic shape)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, served and large-run measurements")
-    ap.add_argument("--extras", default="batched,serving,large,three_temp,scale",
+    ap.add_argument("--extras", default="batched,production,serving,large,three_temp,scale",
                     help="comma list of extra measurements")
     ap.add_argument("--pd-steps", type=int, default=20000)
     ap.add_argument("--pd-seeds", type=int, default=20)
+    ap.add_argument("--prod-steps", type=int, default=50000)
+    ap.add_argument("--prod-seeds", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
     ap.add_argument("--large-steps", type=int, default=500)
@@ -576,6 +639,8 @@ def main() -> int:
     from paper_2608_18541_amd import workloads as W
     if "batched" in extras:
         out["batched"] = batched_phase_diagram(N, W, args.pd_steps, args.pd_seeds)
+    if "production" in extras:
+        out["production"] = production_phase_diagram(N, W, args.prod_steps, args.prod_seeds)
     if "serving" in extras:
         out["serving"] = serving(N, W, S, args.serve_requests, args.serve_steps_scale)
     if "large" in extras:

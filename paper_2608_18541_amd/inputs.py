@@ -194,6 +194,8 @@ def fe_bcc_spec(L: int = 6, **kw) -> SystemSpec:
 GDFECO_J_TMTM = joule_to_ev(2.835e-21)
 GDFECO_J_GDGD = joule_to_ev(1.26e-21)
 GDFECO_J_TMGD = joule_to_ev(-1.09e-21)
+# uniaxial easy-axis anisotropy of both species, eV per atom (parameter table)
+GDFECO_K = 5.0384e-5
 
 
 def gdfeco_sc_spec(L: int = 32, alpha: float = 0.01, S0: float = 0.0, tn: int = 8,

@@ -5,6 +5,10 @@
   temperatures x seeds (Methods F: replicas share nothing; Methods G: n
   realizations per condition with an independent alloy and noise seed
   each).
+* ``production_diagram``: the production runs (Results, phase diagram):
+  frozen alloy lattice, literature anisotropy, zero field, and the
+  three-stage stepped electron temperature, over a grid of peak
+  temperatures x cooling-duration multipliers d x seeds.
 * ``request_trace``: a Poisson stream of alloy simulations of mixed size,
   composition, peak temperature and length.
 """
@@ -64,6 +68,39 @@ def phase_diagram(L: int = 16, n_alpha: int = 8, n_temp: int = 8, n_seeds: int =
                 rid += 1
     return out
 
+
+
+def production_run(L: int, T0: float, d: float, seed: int, run_id: int, n_steps: int,
+                   alpha: float = 0.01, base_ends=(0.1, 0.5), p_gd: float = 0.25) -> RunSpec:
+    """One production realization: sc alloy L^3 on a frozen lattice, the
+    literature anisotropy on both species, B = 0, electrons held at T0 until
+    d * base_ends[0] ps, at T0 / 2 until d * base_ends[1] ps, then at 300 K.
+    The paper scales the stage durations by d but does not give the base
+    durations; base_ends is this workload's choice."""
+    spec = I.gdfeco_sc_spec(L=L, tn=max(1, L // 4), alpha=alpha, lattice_mode=0,
+                            K=(I.GDFECO_K, I.GDFECO_K, 0.0, 0.0), seed=seed, run_id=run_id)
+    spec = replace(spec, ttm_mode=2, step_T=(T0, 0.5 * T0, 300.0),
+                   step_end=(d * base_ends[0], d * base_ends[1]))
+    return RunSpec(spec, n_steps, (T0, d), "afm", p_gd)
+
+
+def production_diagram(L: int = 16, n_temp: int = 8, n_d: int = 8, n_seeds: int = 20,
+                       n_steps: int = 50000, seed: int = 2027, temp_range=(800.0, 2900.0),
+                       d_range=(1.0, 8.0), base_ends=(0.1, 0.5)) -> List[RunSpec]:
+    """Peak T_e linearly spaced x d linearly spaced x seeds (the paper's
+    8 x 8 x 20 grid: 800-2900 K, d = 1-8); run_id enumerates the runs."""
+    t0, t1 = temp_range
+    temps = [t0 + k * (t1 - t0) / max(1, n_temp - 1) for k in range(n_temp)]
+    d0, d1 = d_range
+    ds = [d0 + k * (d1 - d0) / max(1, n_d - 1) for k in range(n_d)]
+    out = []
+    rid = 0
+    for T in temps:
+        for d in ds:
+            for s in range(n_seeds):
+                out.append(production_run(L, T, d, seed, rid, n_steps, base_ends=base_ends))
+                rid += 1
+    return out
 
 @dataclass
 class Request:

@@ -112,3 +112,37 @@ def test_more_than_one_gpu_is_refused(monkeypatch, capsys):
     monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
     assert bench.main() == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_production_diagram_grid():
+    """The production grid: T0 800-2900 K in steps of 300 K (rows), d = 1-8
+    (columns), seeds innermost; frozen lattice, literature anisotropy, zero
+    field, stage ends scaling with d; every run its own run_id."""
+    from paper_2608_18541_amd import workloads as W
+    runs = W.production_diagram(L=4, n_seeds=2, n_steps=100, base_ends=(0.05, 0.15))
+    assert len(runs) == 128
+    assert len({r.spec.run_id for r in runs}) == 128
+    for k, r in enumerate(runs):
+        T0 = 800.0 + 300.0 * (k // 16)
+        d = 1.0 + (k // 2) % 8
+        sp = r.spec
+        assert sp.step_T == (T0, T0 / 2, 300.0) and r.tag == (T0, d)
+        assert np.allclose(sp.step_end, (0.05 * d, 0.15 * d), rtol=0, atol=1e-15)
+        assert sp.ttm_mode == 2 and sp.lattice_mode == 0 and sp.alpha == 0.01
+        assert sp.K[:2] == (5.0384e-5, 5.0384e-5) and tuple(sp.B) == (0.0, 0.0, 0.0)
+
+
+def test_production_run_follows_its_profile_in_the_oracle():
+    """A production spec with stage ends at steps 4 and 10: the oracle's grid
+    holds T0, then T0 / 2, then 300 K."""
+    from oracle import oracle as O
+    from paper_2608_18541_amd import workloads as W
+    r = W.production_run(L=4, T0=1400.0, d=2.0, seed=5, run_id=3, n_steps=12,
+                         base_ends=(0.0002, 0.0005))
+    st = r.state
+    orc = O.Oracle(r.spec, st.species, st.spins, st.vel)
+    seen = []
+    for _ in range(12):
+        orc.step(1)
+        seen.append(float(orc.state()["Te"][0]))
+    assert seen[:3] == [1400.0] * 3 and seen[4:9] == [700.0] * 5 and seen[10:] == [300.0] * 2

@@ -53,13 +53,19 @@ def _mixed_runs():
                                     kappa_e=I.w_per_mk_to_metal(80.0), n_sub=4, profile=1,
                                     depth=10.0, seed=12, run_id=11), tn=(3, 3, 6))
     runs.append((spec, I.initial_state(spec, "afm")))
+    # a production run (frozen lattice, anisotropy, stepped T_e with both
+    # stage ends inside the window): it advances in the persistent executor
+    spec = replace(I.gdfeco_sc_spec(L=8, tn=2, alpha=0.05, lattice_mode=0, seed=13, run_id=12,
+                                    K=(2.0e-3, 1.0e-3, 0.0, 0.0)),
+                   ttm_mode=2, step_T=(1100.0, 550.0, 300.0), step_end=(0.0021, 0.0047))
+    runs.append((spec, I.initial_state(spec, "afm")))
     return runs
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_equals_alone_bitwise(N, prec):
     runs = _mixed_runs()
-    targets = [37, 50, 64, 45, 70, 55]
+    targets = [37, 50, 64, 45, 70, 55, 66]
     _log("batch: %d runs prec=%d" % (len(runs), prec))
     b = N.Batch(precision=prec, max_runs=8)
     slots = [b.add(sp, st, t, obs_every=5) for (sp, st), t in zip(runs, targets)]
