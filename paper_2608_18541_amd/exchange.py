@@ -73,3 +73,31 @@ def nearest_neighbour_distance(lattice: str, a: float) -> float:
     if lattice not in f:
         raise ValueError("lattice must be sc, bcc or fcc")
     return a * f[lattice]
+
+
+def shell_distances(lattice: str, a: float) -> Tuple[float, float]:
+    """Distances of the first two neighbour shells: sc a, a sqrt(2); bcc
+    a sqrt(3)/2, a; fcc a / sqrt(2), a."""
+    r1 = nearest_neighbour_distance(lattice, a)
+    r2 = {"sc": a * math.sqrt(2.0), "bcc": a, "fcc": a}[lattice]
+    return r1, r2
+
+
+def shell_exchange_table(lattice: str, a: float, J1_pairs, J2: float, J3: float,
+                         cutoff: float, n_shells: int):
+    """Per-shell, per-species-pair exchange constants (eV) of J(r) on an
+    ideal lattice, in the layout of the system description: n_shells 4 x 4
+    tables, shell k holding J(r_k) for every pair (zero beyond the cutoff).
+    On a frozen lattice every pair of a shell keeps its ideal distance, so
+    these constants reproduce J(r) exactly.  J1_pairs is a 4 x 4 table of
+    amplitudes (eV); J2 and J3 are shared by all pairs."""
+    J1_pairs = np.asarray(J1_pairs, dtype=np.float64)
+    if J1_pairs.shape != (4, 4) or not np.array_equal(J1_pairs, J1_pairs.T):
+        raise ValueError("J1_pairs must be a symmetric 4 x 4 table")
+    if not 1 <= n_shells <= 2:
+        raise ValueError("one or two shells")
+    out = []
+    for r in shell_distances(lattice, a)[:n_shells]:
+        f = float(radial_exchange(r, 1.0, J2, J3)) if r < cutoff else 0.0
+        out.append(tuple(tuple(float(f * v) for v in row) for row in J1_pairs))
+    return tuple(out)

@@ -82,3 +82,49 @@ def test_bad_arguments():
         X.rederive_radial_exchange(0.0)
     with pytest.raises(ValueError):
         X.nearest_neighbour_distance("hcp", 3.0)
+
+
+def test_shell_table_of_the_frozen_lattice():
+    """With the re-derived shape every nearest-neighbour pair gets exactly its
+    amplitude, a shell beyond the cutoff gets zero, and a shell inside it
+    gets J(r2) for every pair, in proportion to the amplitudes."""
+    J1 = np.zeros((4, 4))
+    J1[0, 0], J1[0, 1], J1[1, 0], J1[1, 1] = 0.01762, -0.006803, -0.006803, 0.007864
+    a = 2.8665
+    r1, r2 = X.shell_distances("bcc", a)
+    assert abs(r1 - a * math.sqrt(3) / 2) < 1e-15 and r2 == a
+    _, J2, J3 = X.rederive_radial_exchange(r1)
+    t1, t2 = X.shell_exchange_table("bcc", a, J1, J2, J3, cutoff=0.5 * (r1 + r2), n_shells=2)
+    assert np.allclose(np.array(t1), J1, rtol=1e-15, atol=0)
+    assert np.all(np.array(t2) == 0.0)
+    _, u2 = X.shell_exchange_table("bcc", a, J1, J2, J3, cutoff=3.0, n_shells=2)
+    f2 = float(X.radial_exchange(r2, 1.0, J2, J3))
+    assert 0.0 < f2 < 1.0
+    assert np.allclose(np.array(u2), f2 * J1, rtol=1e-15, atol=0)
+    with pytest.raises(ValueError):
+        X.shell_exchange_table("bcc", a, np.ones((3, 3)), J2, J3, 3.0, 1)
+    bad = J1.copy()
+    bad[0, 1] = 0.0
+    with pytest.raises(ValueError):
+        X.shell_exchange_table("bcc", a, bad, J2, J3, 3.0, 1)
+
+
+def test_shell_table_drives_the_oracle_like_the_direct_constants():
+    """A sc alloy whose exchange comes from J(r) with the re-derived shape
+    takes the same steps in the oracle as the alloy with its constants
+    given directly."""
+    from dataclasses import replace
+    from oracle import oracle as O
+    from paper_2608_18541_amd import inputs as I
+    spec = I.gdfeco_sc_spec(L=4, tn=1, alpha=0.05, lattice_mode=0)
+    J1 = np.array(spec.J[0], dtype=np.float64)
+    _, J2, J3 = X.rederive_radial_exchange(spec.a)
+    (t1,) = X.shell_exchange_table("sc", spec.a, J1, J2, J3, cutoff=0.5 * (1 + math.sqrt(2)) * spec.a,
+                                   n_shells=1)
+    spec_r = replace(spec, J=(t1, spec.J[1]))
+    st = I.initial_state(spec, "afm")
+    a = O.Oracle(spec, st.species, st.spins, st.vel)
+    b = O.Oracle(spec_r, st.species, st.spins, st.vel)
+    a.step(5)
+    b.step(5)
+    assert np.allclose(a.state()["s"], b.state()["s"], rtol=0, atol=1e-12)
