@@ -136,6 +136,18 @@ def species_bernoulli(n: int, p: float, seed: int, run_id: int) -> np.ndarray:
     return (rng.random(n) < p).astype(np.int8)
 
 
+def species_exact(n: int, n_gd: int, seed: int, run_id: int) -> np.ndarray:
+    """Random binary alloy with exactly n_gd Gd sites, drawn uniformly without
+    replacement (every set of n_gd sites equally likely), as the production
+    alloys are placed."""
+    if not 0 <= n_gd <= n:
+        raise ValueError("n_gd must lie in [0, n]")
+    rng = _rng(seed, run_id, 4)
+    out = np.zeros(n, dtype=np.int8)
+    out[rng.choice(n, size=n_gd, replace=False)] = 1
+    return out
+
+
 def spins_tilted(n: int, max_deg: float, seed: int, run_id: int) -> np.ndarray:
     """Unit spins uniform on the spherical cap within max_deg of +z."""
     rng = _rng(seed, run_id, 2)
@@ -219,11 +231,14 @@ def gdfeco_sc_spec(L: int = 32, alpha: float = 0.01, S0: float = 0.0, tn: int = 
 
 
 def initial_state(spec: SystemSpec, kind: str = "tilt", p_gd: float = 0.25,
-                  T_lattice: float = 300.0) -> InitialState:
+                  T_lattice: float = 300.0, exact_count: bool = False) -> InitialState:
     """Seeded initial state for a spec.  kind: 'tilt' (within 10 degrees of
-    +z), 'afm' (Gd +z, TM -z) or 'random'."""
+    +z), 'afm' (Gd +z, TM -z) or 'random'.  An alloy has each site Gd with
+    probability p_gd, or, with exact_count, exactly round(p_gd n) Gd sites."""
     n = spec.n_sites
-    if spec.n_species > 1:
+    if spec.n_species > 1 and exact_count:
+        species = species_exact(n, int(round(p_gd * n)), spec.seed, spec.run_id)
+    elif spec.n_species > 1:
         species = species_bernoulli(n, p_gd, spec.seed, spec.run_id)
     else:
         species = np.zeros(n, dtype=np.int8)

@@ -31,10 +31,11 @@ class RunSpec:
     tag: tuple = ()
     kind: str = "afm"
     p_gd: float = 0.25
+    exact_count: bool = False
 
     @property
     def state(self) -> I.InitialState:
-        return I.initial_state(self.spec, self.kind, p_gd=self.p_gd)
+        return I.initial_state(self.spec, self.kind, p_gd=self.p_gd, exact_count=self.exact_count)
 
 
 def alloy_run(L: int, alpha: float, T_peak: float, seed: int, run_id: int, n_steps: int,
@@ -72,8 +73,9 @@ def phase_diagram(L: int = 16, n_alpha: int = 8, n_temp: int = 8, n_seeds: int =
 
 def production_run(L: int, T0: float, d: float, seed: int, run_id: int, n_steps: int,
                    alpha: float = 0.01, base_ends=(0.1, 0.5), p_gd: float = 0.25) -> RunSpec:
-    """One production realization: sc alloy L^3 on a frozen lattice, the
-    literature anisotropy on both species, B = 0, electrons held at T0 until
+    """One production realization: sc alloy L^3 with exactly round(p_gd L^3)
+    Gd sites on a frozen lattice, the literature anisotropy on both species,
+    B = 0, electrons held at T0 until
     d * base_ends[0] ps, at T0 / 2 until d * base_ends[1] ps, then at 300 K.
     The paper scales the stage durations by d but does not give the base
     durations; base_ends is this workload's choice."""
@@ -81,7 +83,7 @@ def production_run(L: int, T0: float, d: float, seed: int, run_id: int, n_steps:
                             K=(I.GDFECO_K, I.GDFECO_K, 0.0, 0.0), seed=seed, run_id=run_id)
     spec = replace(spec, ttm_mode=2, step_T=(T0, 0.5 * T0, 300.0),
                    step_end=(d * base_ends[0], d * base_ends[1]))
-    return RunSpec(spec, n_steps, (T0, d), "afm", p_gd)
+    return RunSpec(spec, n_steps, (T0, d), "afm", p_gd, exact_count=True)
 
 
 def production_diagram(L: int = 16, n_temp: int = 8, n_d: int = 8, n_seeds: int = 20,

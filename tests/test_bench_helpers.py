@@ -146,3 +146,39 @@ def test_production_run_follows_its_profile_in_the_oracle():
         orc.step(1)
         seen.append(float(orc.state()["Te"][0]))
     assert seen[:3] == [1400.0] * 3 and seen[4:9] == [700.0] * 5 and seen[10:] == [300.0] * 2
+
+
+def test_exact_count_alloy_matches_the_random_occupancy_prediction():
+    """Exactly k Gd of N sites, drawn without replacement: the expected
+    number of Gd-Gd nearest-neighbour bonds on a periodic sc L^3 lattice is
+    3N k(k-1) / (N(N-1)), below the independent-site value 3N (k/N)^2; the
+    mean over 3000 alloys lies within four standard errors of it (and more
+    than four from the independent-site value), and every site is Gd with
+    frequency near k/N."""
+    L = 4
+    M = 3000
+    N = L ** 3
+    k = int(round(0.25 * N))
+    counts, freq = [], np.zeros(N)
+    for r in range(M):
+        sp = I.species_exact(N, k, seed=11, run_id=r).reshape(L, L, L)
+        assert int(sp.sum()) == k
+        freq += sp.ravel()
+        g = sp.astype(np.int64)
+        counts.append(int(sum((g * np.roll(g, 1, axis=ax)).sum() for ax in range(3))))
+    counts = np.array(counts, dtype=np.float64)
+    expect = 3 * N * k * (k - 1) / (N * (N - 1))
+    se = counts.std(ddof=1) / math.sqrt(len(counts))
+    assert abs(counts.mean() - expect) < 4 * se
+    assert 3 * N * (k / N) ** 2 - expect > 4 * se       # the test tells the two apart
+    f = freq / M
+    assert abs(f.mean() - k / N) < 1e-12
+    assert np.abs(f - k / N).max() < 0.04                  # binomial(3000, 1/4): sd 0.008
+    with pytest.raises(ValueError):
+        I.species_exact(10, 11, 1, 1)
+
+
+def test_production_runs_have_exact_counts():
+    from paper_2608_18541_amd import workloads as W
+    r = W.production_run(L=6, T0=1100.0, d=6.0, seed=3, run_id=4, n_steps=10)
+    assert int(r.state.species.sum()) == round(0.25 * 216)
