@@ -331,6 +331,43 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     res.update(sublattice_analysis(runs, traj, fl))
     return res
 
+
+def field_dependence(N, W, n_steps: int, n_seeds: int, T0: float = 2900.0, d: float = 7.0) -> dict:
+    """Switching probability of the production runs at one condition under
+    0, 0.5 T and 10 T (+z, opposing the reversal), one FP32 batch, with
+    Wilson intervals.  The condition is the one where this model switches
+    most often in the production grid, not the paper's 1100 K, d = 6, where
+    it does not switch."""
+    from paper_2608_18541_amd.stats import switched, wilson_ci
+    fields = (0.0, 0.5, 10.0)
+    runs = W.field_runs(T0, d, n_seeds, n_steps=n_steps, fields=fields)
+    b = N.Batch(precision=N.SL_FP32, max_runs=len(runs))
+    slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
+             for r in runs]
+    b.synchronize()
+    with host_quiet():
+        t0 = time.perf_counter()
+        b.advance(n_steps)
+        b.synchronize()
+        el = time.perf_counter() - t0
+    fl = []
+    for s in slots:
+        obs = b.get(s, max_samples=n_steps // 20 + 2, state=False)["obs"]
+        fl.append(switched([o["M"][1][2] for o in obs]))
+    b.close()
+    print("bench: field dependence: %.2f s" % el, file=sys.stderr, flush=True)
+    fl = np.array(fl).reshape(len(fields), n_seeds)
+    rows = []
+    for B, f in zip(fields, fl):
+        k = int(f.sum())
+        lo, hi = wilson_ci(k, n_seeds)
+        rows.append({"B_T": B, "switched": k, "n": n_seeds, "P": round(k / n_seeds, 3),
+                     "wilson95": [round(lo, 3), round(hi, 3)]})
+    return {"workload": "production runs (16^3 sc, frozen, K, alpha 0.01, stepped T_e) at T0 = %g K, "
+                        "d = %g, B along +z (opposing the reversal) x %d seeds per field, %d steps"
+                        % (T0, d, n_seeds, n_steps),
+            "seconds": round(el, 3), "fields": rows}
+
 def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
     """Poisson request stream served with continuous batching (FP32), and a
     one-request-at-a-time plain FP64 baseline on the same trace."""
@@ -540,12 +577,13 @@ def main() -> int:
                          "automatic shape)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, served and large-run measurements")
-    ap.add_argument("--extras", default="batched,production,serving,large,three_temp,scale",
+    ap.add_argument("--extras", default="batched,production,field,serving,large,three_temp,scale",
                     help="comma list of extra measurements")
     ap.add_argument("--pd-steps", type=int, default=20000)
     ap.add_argument("--pd-seeds", type=int, default=20)
     ap.add_argument("--prod-steps", type=int, default=50000)
     ap.add_argument("--prod-seeds", type=int, default=20)
+    ap.add_argument("--field-seeds", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
     ap.add_argument("--large-steps", type=int, default=500)
@@ -641,6 +679,8 @@ def main() -> int:
         out["batched"] = batched_phase_diagram(N, W, args.pd_steps, args.pd_seeds)
     if "production" in extras:
         out["production"] = production_phase_diagram(N, W, args.prod_steps, args.prod_seeds)
+    if "field" in extras:
+        out["field_dependence"] = field_dependence(N, W, args.prod_steps, args.field_seeds)
     if "serving" in extras:
         out["serving"] = serving(N, W, S, args.serve_requests, args.serve_steps_scale)
     if "large" in extras:

@@ -9,6 +9,9 @@
   frozen alloy lattice, literature anisotropy, zero field, and the
   three-stage stepped electron temperature, over a grid of peak
   temperatures x cooling-duration multipliers d x seeds.
+* ``field_runs``: production runs at one condition under zero field, a
+  0.5 T bias and a 10 T field opposing the reversal (Results, field
+  (in)dependence of thermal switching).
 * ``request_trace``: a Poisson stream of alloy simulations of mixed size,
   composition, peak temperature and length.
 """
@@ -102,6 +105,24 @@ def production_diagram(L: int = 16, n_temp: int = 8, n_d: int = 8, n_seeds: int 
             for s in range(n_seeds):
                 out.append(production_run(L, T, d, seed, rid, n_steps, base_ends=base_ends))
                 rid += 1
+    return out
+
+
+def field_runs(T0: float, d: float, n_seeds: int, L: int = 16, n_steps: int = 50000,
+               seed: int = 2028, fields=(0.0, 0.5, 10.0)) -> List[RunSpec]:
+    """Production runs at (T0, d) under each field magnitude, seeds
+    innermost.  The field points along +z: the Gd sublattice and the net
+    moment start along +z and reverse to -z, so +z opposes the reversal
+    (the paper's 10 T check); the 0.5 T bias is given the same direction."""
+    out = []
+    rid = 0
+    for B in fields:
+        for s in range(n_seeds):
+            r = production_run(L, T0, d, seed, rid, n_steps)
+            r.spec = replace(r.spec, B=(0.0, 0.0, float(B)))
+            r.tag = (T0, d, B)
+            out.append(r)
+            rid += 1
     return out
 
 @dataclass

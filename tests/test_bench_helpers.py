@@ -182,3 +182,19 @@ def test_production_runs_have_exact_counts():
     from paper_2608_18541_amd import workloads as W
     r = W.production_run(L=6, T0=1100.0, d=6.0, seed=3, run_id=4, n_steps=10)
     assert int(r.state.species.sum()) == round(0.25 * 216)
+
+
+def test_field_runs_layout():
+    from paper_2608_18541_amd import workloads as W
+    runs = W.field_runs(2900.0, 7.0, n_seeds=3, L=4, n_steps=10)
+    assert [r.spec.B for r in runs] == [(0.0, 0.0, B) for B in (0.0, 0.5, 10.0) for _ in range(3)]
+    assert len({r.spec.run_id for r in runs}) == 9
+    r = runs[4]
+    assert r.spec.ttm_mode == 2 and r.spec.lattice_mode == 0 and r.exact_count
+    assert r.spec.step_T == (2900.0, 1450.0, 300.0) and r.tag == (2900.0, 7.0, 0.5)
+    # the field opposes the reversal: Gd (and the net moment) start along +z
+    st = r.state
+    gd = st.species == 1
+    assert np.all(st.spins[gd, 2] == 1.0) and np.all(st.spins[~gd, 2] == -1.0)
+    mu = np.where(gd, 7.63, 1.92)
+    assert (mu * st.spins[:, 2]).sum() > 0
