@@ -278,6 +278,7 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     with the literature anisotropy, alpha 0.01, B = 0 and the stepped T_e
     profile, in one FP32 batch; switching probabilities per cell and the
     rate of one run on the plain FP64 path."""
+    from paper_2608_18541_amd import analysis as A
     from paper_2608_18541_amd.stats import switched, wilson_ci
     base_ends = (0.1, 0.5)
     runs = W.production_diagram(L=16, n_seeds=n_seeds, n_steps=n_steps, base_ends=base_ends)
@@ -324,6 +325,8 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
         "speedup_vs_plain": round(len(runs) / el / plain_rps, 1),
         "P": np.round(k / n_seeds, 3).tolist(),
         "P_rows_T0_cols_d_note": "rows T0 = 800, 1100, ..., 2900 K; columns d = 1, ..., 8",
+        "d_c_per_T0": [A.critical_cooling_duration(range(1, 9), row) for row in k / n_seeds],
+        "d_c_note": "smallest d from which P >= 0.5 for every larger d; null: none up to d = 8",
         "wilson_halfwidth_max": float(max(h - l for l, h in ci) / 2),
         "stage_note": "the paper gives the stage temperatures and that d scales the durations, "
                       "not the base durations: %g ps and %g ps here" % base_ends,

@@ -10,7 +10,9 @@ dynamics and the three-temperature benchmark):
   m_z, before the slower one completes its reversal;
 * the lattice's equilibration time (when it has covered 90% of its range)
   and the time at which the electron, lattice and spin temperatures come
-  together.
+  together;
+* the critical cooling-duration multiplier of each peak temperature in a
+  T_e^0 x d phase diagram.
 
 Readings where the paper gives no procedure (fit window, interpolation of
 crossings, the equilibrium level and the convergence tolerance) are stated
@@ -141,3 +143,22 @@ def convergence_time(t: Sequence[float], temps: Sequence[Sequence[float]], tol: 
         return float(t[0])
     k = int(bad[-1]) + 1
     return float(t[k]) if k < len(t) else None
+
+
+def critical_cooling_duration(ds: Sequence[float], P: Sequence[float],
+                              level: float = 0.5) -> Optional[float]:
+    """Critical cooling-duration multiplier d_c of one peak temperature, read
+    from switching probabilities P at increasing multipliers ds.  Reading:
+    the smallest d from which P stays at or above `level` for every larger
+    d of the grid; None when the largest d is below it (no d_c in range)."""
+    ds = np.asarray(ds, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    if ds.shape != P.shape or ds.size == 0 or np.any(np.diff(ds) <= 0):
+        raise ValueError("ds must increase and match P")
+    ok = P >= level
+    if not ok[-1]:
+        return None
+    k = len(ok) - 1
+    while k > 0 and ok[k - 1]:
+        k -= 1
+    return float(ds[k])

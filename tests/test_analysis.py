@@ -86,3 +86,17 @@ def test_convergence_time_of_three_relaxing_temperatures():
     assert abs(tc - tau * math.log((A_ + B_) / 20.0)) < 2e-4
     assert A.convergence_time(t, [Te, Tl], tol=1e-9) is None
     assert A.convergence_time(t, [Tl, Tl], tol=1.0) == 0.0
+
+
+def test_critical_cooling_duration():
+    ds = [1, 2, 3, 4, 5, 6, 7, 8]
+    # the paper's kind of rows: switching from d = 5 on; from d = 7 on; never
+    assert A.critical_cooling_duration(ds, [0, 0, 0, 0.1, 0.85, 1.0, 0.95, 1.0]) == 5.0
+    assert A.critical_cooling_duration(ds, [0, 0, 0.6, 0.2, 0.4, 0.45, 1.0, 0.9]) == 7.0
+    assert A.critical_cooling_duration(ds, [0, 0, 0, 0, 0, 0, 0.1, 0.3]) is None
+    # a dip below the level after a first rise moves d_c past the dip
+    assert A.critical_cooling_duration(ds, [0, 0.7, 0.8, 0.3, 0.6, 0.7, 0.8, 0.9]) == 5.0
+    assert A.critical_cooling_duration(ds, [1.0] * 8) == 1.0
+    assert A.critical_cooling_duration(ds, [0.5] * 8, level=0.5) == 1.0
+    with pytest.raises(ValueError):
+        A.critical_cooling_duration([2, 1], [0, 1])
