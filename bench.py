@@ -272,7 +272,7 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
 
 
 
-def production_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
+def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int = 2000) -> dict:
     """The production phase diagram: 8 peak T_e (800-2900 K) x 8 cooling
     multipliers (d = 1-8) x seeds, 16^3 sc alloy runs on a frozen lattice
     with the literature anisotropy, alpha 0.01, B = 0 and the stepped T_e
@@ -311,7 +311,7 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     flags = np.array(fl).reshape(8, 8, n_seeds)
     k = flags.sum(axis=2)
     ci = [wilson_ci(int(v), n_seeds) for v in k.ravel()]
-    t_plain = plain_step_time(N, runs[0])
+    t_plain = plain_step_time(N, runs[0], plain_steps)
     plain_rps = 1.0 / (t_plain * n_steps)
     res = {
         "workload": "Gd25(FeCo)75 sc 16^3 frozen lattice, K %.4g eV, alpha 0.01, B = 0, stepped "
@@ -587,6 +587,8 @@ def main() -> int:
     ap.add_argument("--prod-steps", type=int, default=50000)
     ap.add_argument("--prod-seeds", type=int, default=20)
     ap.add_argument("--field-seeds", type=int, default=100)
+    ap.add_argument("--prod-plain-steps", type=int, default=2000,
+                    help="steps of the plain-path timing of one production run")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
     ap.add_argument("--large-steps", type=int, default=500)
@@ -681,7 +683,8 @@ def main() -> int:
     if "batched" in extras:
         out["batched"] = batched_phase_diagram(N, W, args.pd_steps, args.pd_seeds)
     if "production" in extras:
-        out["production"] = production_phase_diagram(N, W, args.prod_steps, args.prod_seeds)
+        out["production"] = production_phase_diagram(N, W, args.prod_steps, args.prod_seeds,
+                                                     args.prod_plain_steps)
     if "field" in extras:
         out["field_dependence"] = field_dependence(N, W, args.prod_steps, args.field_seeds)
     if "serving" in extras:
