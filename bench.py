@@ -73,6 +73,24 @@ def measured_traffic(kernel: str, workload: str, tuning=None):
         return None
 
 
+
+def measured_valu_per_site_step(workload: str = "production16_fp32"):
+    """VALU wave instructions per site-step of the persistent kernel on
+    `workload`, from the committed rocprofv3 counter summary, or None when
+    there is none or the kernels changed since the counters were taken."""
+    path = os.path.join(PROFILES, "persist_%s_valu.txt" % workload)
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != source_digest():
+            return None
+        return float(kv["valu_wave_instructions_per_site_step"])
+    except (OSError, KeyError, ValueError):
+        return None
+
 def bytes_per_unit(kernel: str, fp: int, n_species: int, z_list: float) -> float:
     """Algorithmic bytes per processed unit of each kernel class, each array
     the kernel must touch counted once (neighbour gathers are cache traffic):
@@ -331,6 +349,16 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int 
         "stage_note": "the paper gives the stage temperatures and that d scales the durations, "
                       "not the base durations: %g ps and %g ps here" % base_ends,
     }
+    # the batch is bound by VALU issue: 256 CUs x 2.4 GHz, one wave64
+    # instruction per CU per cycle (four SIMDs, four cycles each)
+    valu = measured_valu_per_site_step()
+    rate = len(runs) * 4096 * n_steps / el
+    peak = 256 * 2.4e9
+    res["alu_roofline"] = None if valu is None else {
+        "bound": "alu", "achieved": rate * valu, "peak": peak,
+        "unit": "VALU wave instructions/s", "frac": rate * valu / peak,
+        "note": "host-timed site-steps/s x %.3f VALU wave instructions per site-step "
+                "(rocprofv3 SQ_INSTS_VALU)" % valu}
     res.update(sublattice_analysis(runs, traj, fl))
     return res
 

@@ -59,6 +59,8 @@ def test_committed_profiles_match_the_kernels():
     (otherwise the bench line would report traffic null)."""
     assert bench.measured_traffic("atom_final", "alloy32_fp64") is not None
     assert bench.measured_traffic("spin_pass", "fe256_fp32", json.loads(bench.SCALE_TUNING)) is not None
+    v = bench.measured_valu_per_site_step()
+    assert v is not None and 5.0 < v < 20.0
 
 
 def _positions(spec, uz_of_layer):
