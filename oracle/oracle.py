@@ -8,11 +8,12 @@ every lattice vector within two unit cells, the ideal distance decides the
 exchange shell, so a small periodic box that reaches the same neighbour
 through several images counts each image as its own bond.  Sites are
 numbered canonically, ((z*Ly + y)*Lx + x)*nb + b, with basis b = 0 at the
-cell corner and b = 1 at the body centre (bcc), all sites shifted by a
-quarter of the lattice constant so that none lies on an electron-grid face.
-The spin update order uses the checkerboard colouring
-colour = 2b + (x + y + z) mod 2 (bcc, four colours) or (x + y + z) mod 2
-(simple cubic, two colours); the builder asserts that no bond joins two
+cell corner and b = 1 at the body centre (bcc), or b = 1, 2, 3 at the
+centres of the xy, xz and yz faces (fcc), all sites shifted by a quarter of
+the lattice constant so that none lies on an electron-grid face.  The spin
+update order uses the checkerboard colouring colour = 2b + (x + y + z) mod 2
+(bcc, four colours) or (x + y + z) mod 2 (simple cubic, two colours), and the
+basis site on fcc (four colours); the builder asserts that no bond joins two
 spins of one colour.
 """
 from __future__ import annotations
@@ -31,11 +32,12 @@ _LIB = os.path.join(_HERE, "_build", "libsl_oracle.so")
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    """Compile the oracle with gcc (-O3, no fast-math, no contraction of
+    multiply-adds)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         os.makedirs(os.path.dirname(_LIB), exist_ok=True)
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
                                "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -106,6 +108,9 @@ def lib():
                                   C.POINTER(C.c_double)]
         L.or_llg_exact_flow.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.c_double, C.c_double]
+        L.or_pair_forces.restype = C.c_double
+        L.or_pair_forces.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -128,6 +133,18 @@ def normals3(seed: int, run: int, cid: int, step: int, stream: int) -> np.ndarra
     out = np.zeros(3)
     lib().or_normals3(seed, run, cid, step, stream, _p(out, C.c_double))
     return out
+
+
+def pair_forces(x, box, morse, method: int):
+    """Morse forces [n, 3] and shifted pair energy of positions x: method 0
+    over all pairs, 1 through the cell list the oracle steps with."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, 3))
+    b = np.ascontiguousarray(np.asarray(box, dtype=np.float64))
+    m = np.ascontiguousarray(np.asarray(morse, dtype=np.float64))
+    F = np.zeros_like(x)
+    pe = lib().or_pair_forces(_p(x, C.c_double), x.shape[0], _p(b, C.c_double),
+                              _p(m, C.c_double), int(method), _p(F, C.c_double))
+    return F, pe
 
 
 def llg_exact_flow(s, w, alpha: float, tau: float) -> np.ndarray:
@@ -153,8 +170,10 @@ class Topology:
 
 
 def lattice_topology(lattice: int, ncell, a: float, n_shells: int) -> Topology:
-    """Sites, colours and exchange neighbours of a periodic sc (0) or bcc (1)
-    lattice by enumeration of lattice vectors."""
+    """Sites, colours and exchange neighbours of a periodic sc (0), bcc (1) or
+    fcc (2) lattice by enumeration of lattice vectors.  fcc has the basis
+    sites at the cell corner and the centres of the xy, xz and yz faces, its
+    nearest neighbours at a / sqrt(2), and is coloured by basis site."""
     Lx, Ly, Lz = (int(v) for v in ncell)
     if lattice == 0:
         basis = np.array([[0.0, 0.0, 0.0]])
@@ -162,6 +181,9 @@ def lattice_topology(lattice: int, ncell, a: float, n_shells: int) -> Topology:
     elif lattice == 1:
         basis = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])
         shells = [np.sqrt(3.0) / 2.0, 1.0]
+    elif lattice == 2:
+        basis = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+        shells = [np.sqrt(0.5), 1.0]
     else:
         raise ValueError("lattice")
     nb = basis.shape[0]
@@ -174,7 +196,7 @@ def lattice_topology(lattice: int, ncell, a: float, n_shells: int) -> Topology:
     cell = np.stack([x, y, z], axis=1).astype(np.float64)
     pos = (cell + 0.25 + basis[b]) * a
     parity = (x + y + z) % 2
-    colour = (2 * b + parity) if nb == 2 else parity
+    colour = (2 * b + parity) if nb == 2 else (b if nb == 4 else parity)
     # every (basis b, lattice-vector offset, basis b2) with an ideal distance
     # on one of the first n_shells shells
     nbrs = [[] for _ in range(nb)]
@@ -208,7 +230,7 @@ def lattice_topology(lattice: int, ncell, a: float, n_shells: int) -> Topology:
     # proper colouring: no bond inside a colour
     own = np.repeat(np.arange(n), zmax)
     assert not np.any(colour[own] == colour[nbr_j]), "improper colouring"
-    return Topology(n=n, n_colours=2 * nb, colour=colour.astype(np.int32),
+    return Topology(n=n, n_colours=4 if nb == 4 else 2 * nb, colour=colour.astype(np.int32),
                     ctr_id=np.arange(n, dtype=np.int32), pos=pos,
                     box=(a * Lx, a * Ly, a * Lz), nbr_off=nbr_off, nbr_j=nbr_j,
                     nbr_shell=nbr_shell)

@@ -8,8 +8,10 @@
  * HIP path.  It shares no code, header, table or constant with the product
  * library; only the test-suite, the smoke check and the CPU-baseline leg of
  * the benchmark may load it.  Every routine is written for clarity, not
- * speed: pair forces loop over all pairs with the minimum image, every spin
- * is updated one at a time, and all arithmetic is double precision.
+ * speed: pair forces take every pair closer than the cutoff (minimum image),
+ * found through a cell list rebuilt at every evaluation and pinned against
+ * the loop over all pairs; every spin is updated one at a time, and all
+ * arithmetic is double precision.
  *
  * Units (LAMMPS "metal"): Angstrom, picosecond, eV, amu, Kelvin, Tesla.
  *
@@ -209,38 +211,119 @@ static double or_morse_force(const double* m, double r)
     return 2.0 * a * D * (exp(-2.0 * a * (r - r0)) - exp(-a * (r - r0)));
 }
 
-static void or_compute_forces(or_system* S)
+/* The interacting pairs: every unordered pair {i, j}, i < j, whose
+ * minimum-image distance is below the cutoff, as (i, j) entries of `pairs`
+ * (2 * count ints, malloc'd; the caller frees).  method 0 tests all pairs;
+ * method 1 finds the same set with a cell list built for this call: the box
+ * is cut into floor(L_d / rc) >= 3 bins per axis (bins at least rc wide), so
+ * the two atoms of a pair closer than rc sit in the same or adjacent bins,
+ * and the 27 bins around an atom are distinct; with fewer than 3 bins along
+ * an axis, all pairs are tested. */
+static int64_t or_pairs(const double* x, int32_t n, const double* box, double rc, int method,
+                        int32_t** pairs)
 {
-    int32_t n = S->n;
-    memset(S->F, 0, sizeof(double) * 3 * n);
-    for (int32_t i = 0; i < n; ++i) {
-        for (int32_t j = i + 1; j < n; ++j) {
-            double d[3];
-            or_min_image(&S->x[3 * i], &S->x[3 * j], S->d.box, d);
-            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (r >= S->d.morse[3]) continue;
-            double f = or_morse_force(S->d.morse, r);   /* force on j along d/r */
-            for (int k = 0; k < 3; ++k) {
-                double fk = f * d[k] / r;
-                S->F[3 * j + k] += fk;
-                S->F[3 * i + k] -= fk;
+    int32_t nb[3];
+    int use_bins = method == 1;
+    for (int k = 0; k < 3; ++k) {
+        nb[k] = (int32_t)floor(box[k] / rc);
+        if (nb[k] < 3) use_bins = 0;
+    }
+    int64_t cap = 1024, cnt = 0;
+    int32_t* out = (int32_t*)malloc(sizeof(int32_t) * 2 * cap);
+    if (!use_bins) {
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t j = i + 1; j < n; ++j) {
+                double d[3];
+                or_min_image(&x[3 * i], &x[3 * j], box, d);
+                if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= rc) continue;
+                if (cnt == cap) { cap *= 2; out = (int32_t*)realloc(out, sizeof(int32_t) * 2 * cap); }
+                out[2 * cnt] = i; out[2 * cnt + 1] = j; ++cnt;
             }
+        *pairs = out;
+        return cnt;
+    }
+    /* bin of every atom, then the atoms of each bin in ascending index */
+    int64_t nbins = (int64_t)nb[0] * nb[1] * nb[2];
+    int32_t* bin = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t* start = (int32_t*)calloc((size_t)nbins + 1, sizeof(int32_t));
+    int32_t* list = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t c[3];
+        for (int k = 0; k < 3; ++k) {
+            c[k] = (int32_t)floor(or_wrap(x[3 * i + k], box[k]) / (box[k] / nb[k]));
+            if (c[k] >= nb[k]) c[k] = nb[k] - 1;
+            if (c[k] < 0) c[k] = 0;
+        }
+        bin[i] = (c[2] * nb[1] + c[1]) * nb[0] + c[0];
+        start[bin[i] + 1] += 1;
+    }
+    for (int64_t b = 0; b < nbins; ++b) start[b + 1] += start[b];
+    int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nbins > 0 ? nbins : 1));
+    for (int64_t b = 0; b < nbins; ++b) fill[b] = start[b];
+    for (int32_t i = 0; i < n; ++i) list[fill[bin[i]]++] = i;
+    free(fill);
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t bx = bin[i] % nb[0], by = (bin[i] / nb[0]) % nb[1], bz = bin[i] / (nb[0] * nb[1]);
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int32_t ox = (bx + dx + nb[0]) % nb[0], oy = (by + dy + nb[1]) % nb[1];
+                    int32_t oz = (bz + dz + nb[2]) % nb[2];
+                    int32_t b = (oz * nb[1] + oy) * nb[0] + ox;
+                    for (int32_t q = start[b]; q < start[b + 1]; ++q) {
+                        int32_t j = list[q];
+                        if (j <= i) continue;
+                        double d[3];
+                        or_min_image(&x[3 * i], &x[3 * j], box, d);
+                        if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= rc) continue;
+                        if (cnt == cap) { cap *= 2; out = (int32_t*)realloc(out, sizeof(int32_t) * 2 * cap); }
+                        out[2 * cnt] = i; out[2 * cnt + 1] = j; ++cnt;
+                    }
+                }
+    }
+    free(bin); free(start); free(list);
+    *pairs = out;
+    return cnt;
+}
+
+/* Morse forces (into F, [n][3]) and the shifted pair energy of positions x,
+ * over the pairs found by `method` (see or_pairs).  Pure function of its
+ * arguments: also the test hook that pins the cell list to all pairs. */
+double or_pair_forces(const double* x, int32_t n, const double* box, const double* morse, int method,
+                      double* F)
+{
+    int32_t* pairs = NULL;
+    int64_t np = or_pairs(x, n, box, morse[3], method, &pairs);
+    double pe = 0.0;
+    if (F) memset(F, 0, sizeof(double) * 3 * n);
+    for (int64_t q = 0; q < np; ++q) {
+        int32_t i = pairs[2 * q], j = pairs[2 * q + 1];
+        double d[3];
+        or_min_image(&x[3 * i], &x[3 * j], box, d);
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        pe += or_morse_energy(morse, r);
+        if (!F) continue;
+        double f = or_morse_force(morse, r);   /* force on j along d/r */
+        for (int k = 0; k < 3; ++k) {
+            double fk = f * d[k] / r;
+            F[3 * j + k] += fk;
+            F[3 * i + k] -= fk;
         }
     }
+    free(pairs);
+    return pe;
+}
+
+/* The system's forces use the cell list (the same pair set as all pairs). */
+static void or_compute_forces(or_system* S)
+{
+    (void)or_pair_forces(S->x, S->n, S->d.box, S->d.morse, 1, S->F);
 }
 
 /* Total pair energy of the current positions (eV). */
 static double or_potential_energy(const or_system* S)
 {
-    double pe = 0.0;
-    for (int32_t i = 0; i < S->n; ++i)
-        for (int32_t j = i + 1; j < S->n; ++j) {
-            double d[3];
-            or_min_image(&S->x[3 * i], &S->x[3 * j], S->d.box, d);
-            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (r < S->d.morse[3]) pe += or_morse_energy(S->d.morse, r);
-        }
-    return pe;
+    return or_pair_forces(S->x, S->n, S->d.box, S->d.morse, 1, NULL);
 }
 
 /* ------------------------------------------------------------- spin update */

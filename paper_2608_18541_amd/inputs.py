@@ -28,6 +28,7 @@ MVV2E = AMU_KG * 1.0e4 / EV
 
 LATTICE_SC = 0
 LATTICE_BCC = 1
+LATTICE_FCC = 2
 
 SPECIES_TM = 0                  # transition metal (Fe/Co merged)
 SPECIES_GD = 1
@@ -100,7 +101,7 @@ class SystemSpec:
 
     @property
     def nbasis(self) -> int:
-        return 1 if self.lattice == LATTICE_SC else 2
+        return {LATTICE_SC: 1, LATTICE_BCC: 2, LATTICE_FCC: 4}[self.lattice]
 
     @property
     def n_sites(self) -> int:
@@ -227,6 +228,34 @@ def gdfeco_sc_spec(L: int = 32, alpha: float = 0.01, S0: float = 0.0, tn: int = 
                    gamma_e=j_per_m3k2_to_metal(225.0),
                    G_el=w_per_m3k_to_metal(6.6e17), kappa_e=0.0, n_sub=1,
                    S0=S0, t0=0.1, fwhm=0.05, profile=0)
+    return replace(s, **kw)
+
+
+# the production GdFeCo model's literature exchange amplitudes (eV, the
+# parameter table): nearest neighbours of the fcc lattice
+GDFECO_FCC_J_FEFE = 0.01762
+GDFECO_FCC_J_GDGD = 0.007864
+GDFECO_FCC_J_FEGD = -0.006803
+
+
+def gdfeco_fcc_spec(L: int = 13, alpha: float = 0.01, **kw) -> SystemSpec:
+    """The production Gd25(FeCo)75 model (Methods, GdFeCo model; the
+    parameter table): random binary alloy on an fcc lattice, a = 3.6 A,
+    L^3 cells (13^3: 8788 sites), moments 1.92 / 7.63 mu_B, nearest-neighbour
+    exchange Fe-Fe 17.62 meV, Gd-Gd 7.864 meV, Fe-Gd -6.803 meV (the radial
+    exchange function re-derived to equal J_1 at the nearest-neighbour
+    distance, so on the frozen lattice each bond is one constant), uniaxial
+    anisotropy 5.0384e-5 eV on both species, damping 0.01, no field, frozen
+    lattice, one electron cell.  The temperature profile is set by the
+    caller (production_spec in workloads)."""
+    J1 = ((GDFECO_FCC_J_FEFE, GDFECO_FCC_J_FEGD, 0, 0), (GDFECO_FCC_J_FEGD, GDFECO_FCC_J_GDGD, 0, 0),
+          (0,) * 4, (0,) * 4)
+    s = SystemSpec(lattice=LATTICE_FCC, ncell=(L, L, L), a=3.6, n_species=2,
+                   mu=(1.92, 7.63, 0, 0), mass=(55.845, 55.845, 0, 0), n_shells=1,
+                   J=(J1, ((0,) * 4,) * 4), B=(0.0, 0.0, 0.0),
+                   K=(GDFECO_K, GDFECO_K, 0.0, 0.0), alpha=alpha, lattice_mode=0,
+                   morse=(0.4174, 1.3885, 2.845, 5.0), skin=0.5, dt=1.0e-4, tn=(1, 1, 1),
+                   ttm_mode=0, Te0=300.0)
     return replace(s, **kw)
 
 

@@ -480,6 +480,99 @@ def test_boltzmann_average_bcc222_two_shells_against_metropolis():
     assert abs(M_ld - M_mc) < 0.02, (M_ld, M_mc)
 
 
+def _metropolis_fcc222(Jv, T, nchain=1024, nsweep=900, burn=200, seed=3):
+    """Independent Metropolis sampler on the 32-spin periodic 2x2x2 fcc cell
+    with nearest-neighbour exchange.  The neighbours are found by position:
+    each site plus each of the 12 vectors (+-1/2, +-1/2, 0) and their
+    permutations (in lattice constants), wrapped into the box, is matched to
+    the site at that point (all 12 distinct at L = 2)."""
+    rng = np.random.default_rng(seed)
+    L = 2
+    basis = [(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]          # in half constants
+    where = {}
+    sites = []
+    for z in range(L):
+        for y in range(L):
+            for x in range(L):
+                for b, f in enumerate(basis):
+                    p = ((2 * x + f[0]) % (2 * L), (2 * y + f[1]) % (2 * L), (2 * z + f[2]) % (2 * L))
+                    where[p] = len(sites)
+                    sites.append(p)
+    vecs = set()
+    for a in (-1, 1):
+        for c in (-1, 1):
+            vecs |= {(a, c, 0), (a, 0, c), (0, a, c)}
+    n = len(sites)
+    nbr = np.zeros((n, 12), dtype=np.int64)
+    for i, p in enumerate(sites):
+        q = [where[((p[0] + v[0]) % (2 * L), (p[1] + v[1]) % (2 * L), (p[2] + v[2]) % (2 * L))]
+             for v in sorted(vecs)]
+        assert len(set(q)) == 12
+        nbr[i] = q
+    s = rng.standard_normal((nchain, n, 3))
+    s /= np.linalg.norm(s, axis=2, keepdims=True)
+    beta = 1.0 / (KB * T)
+    field = lambda i: Jv * s[:, nbr[i], :].sum(axis=1)
+    Es, Ms = [], []
+    for sweep in range(nsweep):
+        for i in range(n):
+            h = field(i)
+            new = rng.standard_normal((nchain, 3))
+            new /= np.linalg.norm(new, axis=1, keepdims=True)
+            dE = -np.sum((new - s[:, i, :]) * h, axis=1)
+            acc = rng.random(nchain) < np.exp(np.minimum(0.0, -beta * dE))
+            s[acc, i, :] = new[acc]
+        if sweep >= burn and sweep % 5 == 0:
+            E = 0.0
+            for i in range(n):
+                E = E - 0.5 * np.sum(s[:, i, :] * field(i), axis=1)
+            Es.append(E)
+            Ms.append(np.linalg.norm(s.mean(axis=1), axis=1))
+    # per-chain time averages: independent estimates
+    Ec, Mc = np.mean(Es, axis=0), np.mean(Ms, axis=0)
+    return (float(Ec.mean()), float(Ec.std(ddof=1) / math.sqrt(nchain)), float(Mc.mean()),
+            float(Mc.std(ddof=1) / math.sqrt(nchain)))
+
+
+@pytest.mark.parametrize("tfac,dt", [(2.0, 5e-4), (4.0, 2.5e-4)])
+def test_boltzmann_average_fcc222_against_metropolis(tfac, dt):
+    """The 32-spin periodic fcc cell (twelve nearest neighbours, coloured by
+    basis site): Langevin time averages of the oracle equal Metropolis
+    ensemble averages of the same Hamiltonian, in the ordered (2 J / k_B) and
+    the disordered (4 J / k_B) regime, within four combined standard errors
+    (per-run and per-chain averages are independent) and 3% (5% for |m|).
+    The splitting's weak error is first order in the step (reading R5): in
+    the disordered cell a 1 fs step biases the energy by about 7% (0.25 fs:
+    within the error bars), so that case steps at 0.25 fs."""
+    Jv = 0.01
+    T = tfac * Jv / KB
+    E_mc, se_E_mc, M_mc, se_M_mc = _metropolis_fcc222(Jv, T)
+    Er, Mr = [], []
+    every = int(round(0.025 / dt))
+    for run in range(24):
+        spec = spin_only_spec(lattice=2, ncell=(2, 2, 2), a=3.6, n_shells=1, J=J1(Jv), alpha=0.5,
+                              dt=dt, Te0=T, seed=79, run_id=run)
+        st = I.spins_random(32, 11, run)
+        orc = O.Oracle(spec, [0] * 32, st)
+        assert orc.topology.n_colours == 4
+        orc.step(int(round(0.8 / dt)))
+        e, m = [], []
+        for _ in range(60):
+            orc.step(every)
+            o = orc.observables()
+            e.append(o["E_ex"])
+            m.append(o["m_abs"])
+        Er.append(np.mean(e))
+        Mr.append(np.mean(m))
+    E_ld, M_ld = float(np.mean(Er)), float(np.mean(Mr))
+    se_E = math.hypot(np.std(Er, ddof=1) / math.sqrt(len(Er)), se_E_mc)
+    se_M = math.hypot(np.std(Mr, ddof=1) / math.sqrt(len(Mr)), se_M_mc)
+    assert abs(E_ld - E_mc) < max(4.0 * se_E, 0.01 * abs(E_mc)), (E_ld, E_mc, se_E)
+    assert abs(E_ld - E_mc) < 0.03 * abs(E_mc), (E_ld, E_mc, se_E)
+    assert abs(M_ld - M_mc) < max(4.0 * se_M, 0.005), (M_ld, M_mc, se_M)
+    assert abs(M_ld - M_mc) < 0.05 * M_mc, (M_ld, M_mc)
+
+
 def test_two_species_fdt_equilibrium():
     """Two moments (1.92 and 7.63 mu_B) in one ferromagnetic lattice at one
     bath temperature: with the 1/sqrt(mu) noise both spin temperatures equal
@@ -735,3 +828,133 @@ def test_switch_flag():
     assert switched([0.8, 0.2, -0.3, -0.5, -0.6, -0.7, -0.6, -0.5, -0.55, -0.6, -0.5])
     assert not switched([0.8, 0.2, -0.3, -0.5, -0.6, -0.7, -0.6, -0.5, -0.55, -0.6, 0.1])
     assert not switched([0.8, 0.7, 0.6])
+
+
+# ------------------------------------------- pair search, Morse cut, energies
+
+MORSE = (0.4174, 1.3885, 2.845, 5.0)
+
+
+@pytest.mark.parametrize("box", [(15.0, 15.0, 15.0), (17.2, 26.3, 40.1), (15.0001, 30.0, 15.0),
+                                 (12.0, 12.0, 12.0)])
+def test_cell_list_pairs_equal_all_pairs(box):
+    """The oracle steps with a cell list; its forces and pair energy equal
+    the loop over all pairs (to rounding, the sums running in another order)
+    on random and on thermally displaced lattice configurations, including a
+    box exactly three cutoffs wide (three bins of width rc per axis) and one
+    too small for bins (all pairs)."""
+    rng = np.random.default_rng(int(sum(box) * 1000))
+    box = np.array(box)
+    configs = [rng.random((300, 3)) * box]
+    # a bcc-like lattice with 0.2 A displacements
+    a = 2.8665
+    cells = [np.arange(int(b // a)) for b in box]
+    g = np.stack(np.meshgrid(*cells, indexing="ij"), -1).reshape(-1, 3) * a
+    lat = np.concatenate([g, g + a / 2]) + 0.2 * rng.standard_normal((2 * len(g), 3))
+    configs.append(lat)
+    for x in configs:
+        F0, pe0 = O.pair_forces(x, box, MORSE, 0)
+        F1, pe1 = O.pair_forces(x, box, MORSE, 1)
+        scale = np.abs(F0).max()
+        assert np.abs(F1 - F0).max() <= 1e-13 * scale, np.abs(F1 - F0).max() / scale
+        assert abs(pe1 - pe0) <= 1e-13 * max(abs(pe0), 1.0)
+        assert abs(pe0) > 0
+
+
+def test_morse_cut_is_energy_shifted():
+    """Reading R9: the pair energy is shifted so that it vanishes at the
+    cutoff.  The pair force has the textbook Morse well: zero at r0 and, with
+    a cutoff far out, work D from r0 to infinity (Simpson quadrature of the
+    force).  With the 5 A cut the dimer's energy is continuous at rc (0 from
+    there on, tending to 0 from below) and equals the work of the force from
+    the separation out to rc, so the shift is the constant that makes the
+    energy vanish at the cut; the force is minus the energy's slope."""
+    D, a, r0, rc = MORSE
+    from scipy.integrate import simpson
+
+    def dimer(r, morse=MORSE, box=(40.0, 40.0, 40.0)):
+        x = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+        F, pe = O.pair_forces(x, box, morse, 1)
+        return F[1, 0], pe
+    far = (D, a, r0, 50.0)
+    rr = np.linspace(r0, 49.0, 40001)
+    work = simpson([dimer(r, far, (120.0, 120.0, 120.0))[0] for r in rr], x=rr)
+    assert abs(work + D) < 1e-9, work           # the force pulls back: work -D
+    assert abs(dimer(r0)[0]) < 1e-14
+    f_rc, pe_below = dimer(rc - 1e-9)
+    assert abs(pe_below) < 1e-9 * abs(f_rc) + 1e-15, pe_below
+    assert dimer(rc)[1] == 0.0 and dimer(rc + 0.3)[1] == 0.0 and dimer(rc + 0.3)[0] == 0.0
+    for r in (2.2, 2.6, r0, 3.3, 4.2, 4.9):
+        rr = np.linspace(r, rc - 1e-12, 4001)
+        w = simpson([dimer(q)[0] for q in rr], x=rr)
+        assert abs(dimer(r)[1] - w) < 1e-9 * max(1.0, abs(w)), (r, dimer(r)[1], w)
+        h = 1e-5
+        slope = (dimer(r + h)[1] - dimer(r - h)[1]) / (2 * h)
+        assert abs(dimer(r)[0] + slope) < 1e-8 * max(1.0, abs(slope)), r
+
+
+def _grid_system(tn, Te, **kw):
+    spec = replace(I.gdfeco_sc_spec(L=4, tn=1, lattice_mode=0, alpha=0.0, dt=1e-4, **kw),
+                   tn=tuple(tn))
+    return spec, O.Oracle(spec, np.zeros(spec.n_sites, dtype=np.int8),
+                          np.tile([0, 0, 1.0], (spec.n_sites, 1)), Te=Te)
+
+
+def test_electron_energy_on_a_nonuniform_grid():
+    """E_e is the electrons' energy: on a non-uniform 4 x 3 x 5 grid the
+    explicit conservative diffusion keeps it to rounding (no source, no
+    coupling), and with the Gaussian source it grows by exactly the box
+    volume times the time integral of S (error-function closed form;
+    midpoint sampling), diffusing or not.  Te_max and Te_mean describe the
+    grid's temperatures."""
+    tn = (4, 3, 5)
+    rng = np.random.default_rng(5)
+    Te = 300.0 + 1200.0 * rng.random(int(np.prod(tn)))
+    kappa = I.w_per_mk_to_metal(80.0)
+    spec, orc = _grid_system(tn, Te, kappa_e=kappa, n_sub=4)
+    o0 = orc.observables()
+    assert o0["Te_max"] == Te.max() and abs(o0["Te_mean"] - Te.mean()) < 1e-12 * Te.mean()
+    orc.step(60)
+    o1 = orc.observables()
+    assert abs(o1["E_e"] / o0["E_e"] - 1.0) < 1e-12, (o1["E_e"], o0["E_e"])
+    assert np.abs(orc.state()["Te"] - Te).max() > 1.0          # heat did flow
+    S0, t0, fwhm = 4.89e-2, 0.004, 0.002
+    sig = fwhm / math.sqrt(8.0 * math.log(2.0))
+    vol = float(np.prod(spec.box))
+    for kap in (0.0, kappa):
+        spec, orc = _grid_system(tn, Te, kappa_e=kap, n_sub=4, S0=S0, t0=t0, fwhm=fwhm)
+        E0 = orc.observables()["E_e"]
+        orc.step(80)
+        t = 80 * spec.dt
+        integral = S0 * sig * math.sqrt(math.pi / 2.0) * (
+            math.erf((t - t0) / (math.sqrt(2.0) * sig)) + math.erf(t0 / (math.sqrt(2.0) * sig)))
+        gained = orc.observables()["E_e"] - E0
+        assert abs(gained / (vol * integral) - 1.0) < 2e-4, (gained, vol * integral)
+
+
+def test_eph_bookkeeping_conserves_energy_on_average():
+    """Reading R11: the electrons of a cell lose the energy the Ornstein-
+    Uhlenbeck step hands to its atoms on average given their velocities, so
+    E_e + KE + PE is conserved in the ensemble mean (each run's total takes
+    a zero-mean random walk from the noise), while the electrons lose a
+    large, significant amount of heat to the colder lattice.  Hot electrons
+    (1200 K) over a 300 K live bcc lattice, 48 realizations of 0.2 ps."""
+    dE_tot, dE_e = [], []
+    for run in range(48):
+        spec = I.fe_bcc_spec(L=4, alpha=0.0, B=(0, 0, 0), dt=1e-3, run_id=run, seed=77,
+                             J=(((0.0,) * 4,) * 4, ((0.0,) * 4,) * 4),
+                             ttm_mode=1, Te0=1200.0, tn=(1, 1, 1), gamma_e=1.84e-8,
+                             G_el=3.0 * (2.0 / 2.8665 ** 3) * KB * 5.0, n_sub=1)
+        st = I.initial_state(spec, "tilt", T_lattice=300.0)
+        orc = O.Oracle(spec, st.species, st.spins, st.vel)
+        o0 = orc.observables()
+        orc.step(200)
+        o1 = orc.observables()
+        dE_tot.append((o1["E_e"] + o1["KE"] + o1["PE"]) - (o0["E_e"] + o0["KE"] + o0["PE"]))
+        dE_e.append(o1["E_e"] - o0["E_e"])
+    dE_tot, dE_e = np.array(dE_tot), np.array(dE_e)
+    se_tot = dE_tot.std(ddof=1) / math.sqrt(len(dE_tot))
+    se_e = dE_e.std(ddof=1) / math.sqrt(len(dE_e))
+    assert abs(dE_tot.mean()) < 4.0 * se_tot, (dE_tot.mean(), se_tot)
+    assert dE_e.mean() < -10.0 * se_e and dE_e.mean() < -10.0 * se_tot, (dE_e.mean(), se_e, se_tot)
+    assert dE_tot.std() > 0.05                     # each run's total does walk
