@@ -28,7 +28,7 @@
  *
  * Units: Angstrom, ps, eV, amu, K, Tesla, Bohr magnetons.
  * Arrays exchanged with the caller are host memory in canonical site order
- * ((z*Ly + y)*Lx + x)*nb + b, b = 0 cell corner, b = 1 body centre (bcc);
+ * ((z*Ly + y)*Lx + x)*nb + b (nb = 1 sc, 2 bcc, 4 fcc; see sl_system_desc);
  * vectors are [n][3] row-major doubles.  Host pointers are borrowed for the
  * duration of the call.  The library owns all device memory, obtained from
  * the caller's allocator when one is given (else hipMalloc).  Streams are
@@ -53,12 +53,21 @@ enum {
     SL_EINVAL = -1,    /* invalid argument; nothing was changed            */
     SL_ENOMEM = -2,    /* device memory or the batch memory budget exceeded */
     SL_EHIP = -3,      /* a HIP runtime call failed                         */
-    SL_ENUMERIC = -4,  /* a run hit a numerical error (negative electron
-                          energy, neighbour-table overflow); it is frozen   */
+    SL_ENUMERIC = -4,  /* a run hit a numerical error; it is frozen and the
+                          other runs of a batch go on.  Detected on the
+                          device: a negative or non-finite electron energy,
+                          a neighbour-table overflow, an electron-phonon
+                          energy out of range, and the watchdog -- a spin
+                          that is not a finite unit vector when it is
+                          updated (|s|^2 off by more than about 1e-4 before
+                          the renormalisation of the update), or a kick
+                          that leaves a non-finite velocity or
+                          displacement.  Reported by the next call that
+                          waits (sl_synchronize, sl_get_state, ...)        */
     SL_EBUSY = -5      /* no free slot in a batch                           */
 };
 
-enum { SL_LATTICE_SC = 0, SL_LATTICE_BCC = 1 };
+enum { SL_LATTICE_SC = 0, SL_LATTICE_BCC = 1, SL_LATTICE_FCC = 2 };
 enum { SL_FP64 = 0, SL_FP32 = 1 };
 
 /* Device-memory provider (e.g. PyTorch's caching allocator).  alloc returns
@@ -73,9 +82,14 @@ typedef struct sl_allocator {
  * ideal lattice with J[k][species_i][species_j] (eV, H = -sum_bonds J s_i.s_j,
  * negative J antiferromagnetic).  Supported: sc with 1 shell, bcc with 1 or
  * 2 shells (the shells the checkerboard colouring keeps bond-free inside a
- * colour).  Every ncell[d] must be even and >= 2. */
+ * colour), fcc with 1 shell (the 12 nearest neighbours; coloured by basis
+ * site, so no two neighbours share a colour).  Every ncell[d] must be
+ * >= 2, and even for sc and bcc.  Basis sites: bcc b = 0 corner, 1 body
+ * centre; fcc b = 0 corner, 1, 2, 3 the centres of the xy, xz and yz faces;
+ * every site sits a quarter lattice constant above its ideal point along
+ * each axis. */
 typedef struct sl_system_desc {
-    int32_t lattice;          /* SL_LATTICE_SC or SL_LATTICE_BCC                  */
+    int32_t lattice;          /* SL_LATTICE_SC, SL_LATTICE_BCC or SL_LATTICE_FCC   */
     int32_t ncell[3];         /* unit cells per dimension                         */
     double a;                 /* lattice constant, Angstrom                       */
     int32_t n_species;        /* 1..4                                             */
@@ -164,7 +178,10 @@ sl_status sl_init_system(const sl_system_desc* desc, sl_system* out);
  * kappa_e / (gamma_e T_e)). */
 sl_status sl_set_ttm_grid(sl_system h, const sl_ttm_desc* ttm);
 
-/* Enqueues n_steps timesteps on the run's stream and returns (asynchronous). */
+/* Enqueues n_steps timesteps on the run's stream and returns (asynchronous).
+ * The first call after creation, a checkpoint restore or a tuning change
+ * allocates the launch tables (through the system's allocator) and captures
+ * a HIP graph of the steps. */
 sl_status sl_step(sl_system h, int64_t n_steps);
 
 /* Waits for the run's stream.  SL_ENUMERIC if the run hit a numerical error. */
@@ -203,6 +220,9 @@ typedef struct {
                                  (0 for a frozen lattice)                            */
     int32_t max_list;         /* longest neighbour list built so far                 */
     int32_t list_capacity;    /* entries per atom the list holds (0: frozen lattice) */
+    int32_t list_rescans;     /* bins scanned a second time by list builds from
+                                 unsorted bins (more than 16 accepted atoms)        */
+    int32_t error;            /* the run's error bits (0: none; nonzero: frozen)     */
 } sl_run_stats;
 
 /* Waits, then reads the run's counters.  SL_EINVAL for a null output. */

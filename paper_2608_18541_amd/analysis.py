@@ -162,3 +162,23 @@ def critical_cooling_duration(ds: Sequence[float], P: Sequence[float],
     while k > 0 and ok[k - 1]:
         k -= 1
     return float(ds[k])
+
+
+def strain_zz_profile(ncell, lattice: int, a: float, x) -> np.ndarray:
+    """eps_zz(z) of the acoustic strain pulse (Results A): per z layer of unit
+    cells, the mean displacement along z of the layer's atoms from their ideal
+    sites (canonical site order, sites offset by a/4), differentiated along z
+    by the periodic central difference."""
+    Lx, Ly, Lz = (int(v) for v in ncell)
+    nb = 2 if lattice == 1 else 1
+    x = np.asarray(x, dtype=np.float64)
+    idx = np.arange(x.shape[0])
+    b = idx % nb
+    z = (idx // nb) // (Lx * Ly)
+    ideal = (z + 0.25 + 0.5 * b) * a
+    box = Lz * a
+    d = x[:, 2] - ideal
+    d -= box * np.round(d / box)
+    uz = np.bincount(z, weights=d, minlength=Lz) / np.bincount(z, minlength=Lz)
+    return (np.roll(uz, -1) - np.roll(uz, 1)) / (2.0 * a)
+

@@ -159,9 +159,15 @@ template <> __device__ inline Normals3<float> normals3<float>(uint32_t s, uint32
 //   D = (1+u) + (1-u) E^2,
 // the new spin is cos(theta') e + (2E/D) R_phi(s_perp) with no division by
 // |s_perp| (finite for s along +e or -e).  Renormalised in double.
+// For a unit input the squared length before the renormalisation is 1 up to
+// rounding; an input that is not finite, or whose length is off by more than
+// a few 1e-5, moves it by more than kNormTol and sets `bad` (the run's
+// numeric watchdog).
 template <typename T> struct V3 {
     T x, y, z;
 };
+
+constexpr double kNormTol = 1.0e-4;
 
 __device__ inline void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ inline void sin_cos(float x, float* s, float* c) { __sincosf(x, s, c); }
@@ -169,10 +175,13 @@ __device__ inline double expo(double x) { return exp(x); }
 __device__ inline float expo(float x) { return __expf(x); }
 
 template <typename T>
-__device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2)
+__device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2, bool& bad)
 {
     T wn2 = w.x * w.x + w.y * w.y + w.z * w.z;
-    if (!(wn2 > T(0))) return s;
+    if (!(wn2 > T(0))) {
+        bad |= !(s.x * s.x + s.y * s.y + s.z * s.z < T(2));
+        return s;
+    }
     T wn = sqrt(wn2);
     T iw = T(1) / wn;
     V3<T> e{w.x * iw, w.y * iw, w.z * iw};
@@ -191,7 +200,9 @@ __device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2)
     double ox = (double)(ct * e.x + f * (cs * p.x + sn * ex.x));
     double oy = (double)(ct * e.y + f * (cs * p.y + sn * ex.y));
     double oz = (double)(ct * e.z + f * (cs * p.z + sn * ex.z));
-    double inv = 1.0 / sqrt(ox * ox + oy * oy + oz * oz);
+    const double n2 = ox * ox + oy * oy + oz * oz;
+    bad |= !(fabs(n2 - 1.0) < kNormTol);
+    double inv = 1.0 / sqrt(n2);
     return {(T)(ox * inv), (T)(oy * inv), (T)(oz * inv)};
 }
 
@@ -202,10 +213,13 @@ __device__ inline V3<T> llg_flow(V3<T> s, V3<T> w, T alpha, T tau, T inv1pa2)
 // 5|eps|^3/16 (below 1e-15 for |eps| < 1e-5); larger eps takes the exact
 // reciprocal square root.
 __device__ inline V3<float> llg_flow(V3<float> s, V3<float> w, float alpha, float tau,
-                                     float inv1pa2)
+                                     float inv1pa2, bool& bad)
 {
     const float wn2 = w.x * w.x + w.y * w.y + w.z * w.z;
-    if (!(wn2 > 0.0f)) return s;
+    if (!(wn2 > 0.0f)) {
+        bad |= !(s.x * s.x + s.y * s.y + s.z * s.z < 2.0f);
+        return s;
+    }
     const float iw = __builtin_amdgcn_rsqf(wn2);
     const float wn = wn2 * iw;
     const V3<float> e{w.x * iw, w.y * iw, w.z * iw};
@@ -225,6 +239,7 @@ __device__ inline V3<float> llg_flow(V3<float> s, V3<float> w, float alpha, floa
     const double oy = (double)(ct * e.y + f * (cs * p.y + sn * ex.y));
     const double oz = (double)(ct * e.z + f * (cs * p.z + sn * ex.z));
     const double eps = (ox * ox + oy * oy + oz * oz) - 1.0;
+    bad |= !(fabs(eps) < kNormTol);
     const double inv = fabs(eps) < 1.0e-5 ? 1.0 + eps * (-0.5 + 0.375 * eps)
                                           : 1.0 / sqrt(1.0 + eps);
     return {(float)(ox * inv), (float)(oy * inv), (float)(oz * inv)};
@@ -232,23 +247,39 @@ __device__ inline V3<float> llg_flow(V3<float> s, V3<float> w, float alpha, floa
 
 // ------------------------------------------------------------- lattice
 // Site numbering.  Colour k of a site is (x+y+z) mod 2 on the simple-cubic
-// lattice and 2b + (x+y+z) mod 2 on bcc (b = 0 corner, 1 body centre).
-// Inside the device arrays the sites of one colour are contiguous:
-//   internal = k * H + xh + (Lx/2) * (y + Ly * z),  x = 2 xh + ((k + y + z) & 1),
-// with H = Lx Ly Lz / 2, so one colour pass streams one contiguous block.
-// The canonical (public) number is ((z Ly + y) Lx + x) nb + b.
+// lattice, 2b + (x+y+z) mod 2 on bcc (b = 0 corner, 1 body centre), and the
+// basis site b itself on fcc (b = 0 corner, 1..3 the face centres of the xy,
+// xz and yz faces: no two nearest neighbours share a sublattice).  Inside the
+// device arrays the sites of one colour are contiguous, in rows along x:
+//   sc, bcc (checkerboard, par = 1): internal = k H + xh + (Lx/2)(y + Ly z),
+//     x = 2 xh + ((k + y + z) & 1), H = Lx Ly Lz / 2;
+//   fcc (par = 0): internal = k H + x + Lx (y + Ly z), H = Lx Ly Lz,
+// so one colour pass streams one contiguous block.  `Lxh` is the length of a
+// row of one colour (Lx / 2 or Lx).  The canonical (public) number is
+// ((z Ly + y) Lx + x) nb + b.
 struct Geom {
-    int32_t Lx, Ly, Lz;   // unit cells per dimension (all even)
-    int32_t Lxh;          // Lx / 2
-    int32_t H;            // Lx Ly Lz / 2 = sites per colour
-    int32_t nb;           // basis atoms per cell (1 sc, 2 bcc)
-    int32_t C;            // colours (2 sc, 4 bcc)
+    int32_t Lx, Ly, Lz;   // unit cells per dimension (even for the checkerboard)
+    int32_t Lxh;          // sites of one colour per row: Lx / 2 (par) or Lx
+    int32_t H;            // sites per colour
+    int32_t nb;           // basis atoms per cell (1 sc, 2 bcc, 4 fcc)
+    int32_t C;            // colours (2 sc, 4 bcc, 4 fcc)
+    int32_t par;          // 1: checkerboard rows of half length; 0: full rows
     FastDiv divH, divLxh, divLy;
 };
 
 struct Site {
     int32_t x, y, z, b, k;
 };
+
+// Axes along which basis site b is shifted by half a lattice constant from
+// the cell corner (bit 0 x, bit 1 y, bit 2 z): bcc body centre all three;
+// fcc face centres (xy), (xz), (yz).
+__host__ __device__ inline uint32_t basis_half_bits(int32_t nb, int32_t b)
+{
+    if (nb == 2) return b ? 7u : 0u;
+    if (nb == 4) return b == 0 ? 0u : (b == 1 ? 3u : (b == 2 ? 5u : 6u));
+    return 0u;
+}
 
 __host__ __device__ inline Site decode_site(const Geom& g, uint32_t idx)
 {
@@ -260,10 +291,10 @@ __host__ __device__ inline Site decode_site(const Geom& g, uint32_t idx)
     uint32_t z = fdiv(r, g.divLy);
     uint32_t y = r - z * (uint32_t)g.Ly;
     s.k = (int32_t)k;
-    s.b = (g.nb == 2) ? (int32_t)(k >> 1) : 0;
+    s.b = g.nb == 2 ? (int32_t)(k >> 1) : (g.nb == 4 ? (int32_t)k : 0);
     s.y = (int32_t)y;
     s.z = (int32_t)z;
-    s.x = 2 * (int32_t)xh + (int32_t)((k + y + z) & 1u);
+    s.x = g.par ? 2 * (int32_t)xh + (int32_t)((k + y + z) & 1u) : (int32_t)xh;
     return s;
 }
 
@@ -271,6 +302,7 @@ __host__ __device__ inline Site decode_site(const Geom& g, uint32_t idx)
 __host__ __device__ inline int32_t encode_site(const Geom& g, int32_t x, int32_t y, int32_t z,
                                                int32_t b)
 {
+    if (!g.par) return b * g.H + x + g.Lxh * (y + g.Ly * z);
     int32_t par = (x + y + z) & 1;
     int32_t k = (g.nb == 2) ? (2 * b + par) : par;
     return k * g.H + (x >> 1) + g.Lxh * (y + g.Ly * z);
@@ -285,5 +317,8 @@ __host__ __device__ inline int32_t wrapi(int32_t v, int32_t L)
 {
     return v < 0 ? v + L : (v >= L ? v - L : v);
 }
+
+// XCDs of the accelerator: workgroup b runs on XCD b mod 8
+constexpr int kXcdCount = 8;
 
 }  // namespace sl

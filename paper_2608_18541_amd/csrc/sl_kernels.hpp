@@ -52,7 +52,10 @@ static_assert(NQ % 3 == 0, "samples reduce three quantities at a time");
 constexpr int kLdsCells = 2048;   // electron grids up to this size are summed in LDS
 constexpr int kSmallGrid = 4096;  // larger electron grids update cell-parallel (k_grid)
 
-enum { ERR_NEG_E = 1, ERR_BIN = 2, ERR_NBR = 4, ERR_DE = 8 };
+// Numerical errors of a run (RunState.err).  ERR_NUMERIC is the watchdog: a
+// spin update whose input was not a finite unit vector, or a kick that left a
+// non-finite velocity or displacement.  A run with an error stops stepping.
+enum { ERR_NEG_E = 1, ERR_BIN = 2, ERR_NBR = 4, ERR_DE = 8, ERR_NUMERIC = 16 };
 enum { PHASE_STEP = 0, PHASE_INIT = 1 };
 
 struct RunState {
@@ -72,6 +75,8 @@ struct RunState {
     int32_t chunk_done;  // steps of the current folded chunk that have ended
     int32_t neg_at;      // 1 + position in the current folded chunk of the first step
                          // end that met a negative electron energy (0: none)
+    int32_t n_rescan;    // bins scanned again by a list build from unsorted bins
+                         // (more than kBinKeep accepted atoms)
 };
 
 // Wrapped absolute position of an atom, padded to a 16/32-byte vector so a
@@ -270,9 +275,15 @@ __device__ __forceinline__ Around around(const Geom& g, uint32_t x, uint32_t xh,
     const uint32_t row = Lxh, plane = Lxh * Ly;
     Around a;
     a.x0 = xh;
-    // x = 2 xh + parity: x - 1 leaves the pair when x is even, x + 1 when odd
-    a.xm = (x & 1u) ? xh : (xh == 0 ? Lxh - 1 : xh - 1);
-    a.xp = (x & 1u) ? (xh == Lxh - 1 ? 0 : xh + 1) : xh;
+    if (g.par) {
+        // x = 2 xh + parity: x - 1 leaves the pair when x is even, x + 1 when odd
+        a.xm = (x & 1u) ? xh : (xh == 0 ? Lxh - 1 : xh - 1);
+        a.xp = (x & 1u) ? (xh == Lxh - 1 ? 0 : xh + 1) : xh;
+    } else {
+        // full rows (fcc): x itself
+        a.xm = xh == 0 ? Lxh - 1 : xh - 1;
+        a.xp = xh == Lxh - 1 ? 0 : xh + 1;
+    }
     a.y0 = __umul24(y, row);
     a.ym = y == 0 ? __umul24(Ly - 1, row) : a.y0 - row;
     a.yp = y == Ly - 1 ? 0 : a.y0 + row;
@@ -290,13 +301,18 @@ __device__ __forceinline__ Around around(const Geom& g, uint32_t x, uint32_t xh,
 //   simple cubic: the 6 sites at +-a along an axis;
 //   bcc: first shell the 8 sites of the other basis at (+-a/2)^3 in the
 //   order (x0|x1, y0|y1, z0|z1) with x fastest, then the 6 second-shell
-//   sites of the same basis at -x, +x, -y, +y, -z, +z.
+//   sites of the same basis at -x, +x, -y, +y, -z, +z;
+//   fcc: the 12 sites at (+-a/2, +-a/2, 0) and its permutations, four in
+//   each other sublattice b': along the two axes on which b and b' differ in
+//   their half shifts the neighbour lies half a constant either way (the
+//   same cell and the one below when b is not shifted there, the same cell
+//   and the one above when it is), on the third axis in the same cell.
 template <typename T, typename VW, int LAT, bool MULTI>
 __device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V, int k, const Around& a,
                                                 int sp)
 {
     using M = typename VW::Mem;
-    constexpr int NN = LAT == SL_LATTICE_SC ? 6 : 14;
+    constexpr int NN = LAT == SL_LATTICE_SC ? 6 : (LAT == SL_LATTICE_FCC ? 12 : 14);
     const uint32_t H = (uint32_t)R.g.H;
     uint32_t col[NN], off[NN];
     int sh[NN];
@@ -310,6 +326,26 @@ __device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V,
         for (int q = 0; q < NN; ++q) {
             col[q] = (uint32_t)(1 - p);
             off[q] = o[q];
+            sh[q] = 0;
+        }
+    } else if (LAT == SL_LATTICE_FCC) {
+        nn = 12;
+        const uint32_t hb = basis_half_bits(4, k);
+        // per axis: [0] and [1] the two cells of a shifted axis, [2] the same cell
+        const uint32_t X[3] = {(hb & 1u) ? a.x0 : a.xm, (hb & 1u) ? a.xp : a.x0, a.x0};
+        const uint32_t Y[3] = {(hb & 2u) ? a.y0 : a.ym, (hb & 2u) ? a.yp : a.y0, a.y0};
+        const uint32_t Z[3] = {(hb & 4u) ? a.z0 : a.zm, (hb & 4u) ? a.zp : a.z0, a.z0};
+#pragma unroll
+        for (int q = 0; q < NN; ++q) {
+            const int t = q >> 2, u = q & 3;
+            const int bp = t < k ? t : t + 1;                 // the other sublattice
+            const uint32_t d = hb ^ basis_half_bits(4, bp);   // its two shifted axes
+            const int ax = d & 1u, ay = (d >> 1) & 1u, az = (d >> 2) & 1u;
+            const int sx = ax ? (u & 1) : 2;
+            const int sy = ay ? (ax ? (u >> 1) & 1 : u & 1) : 2;
+            const int sz = az ? (u >> 1) & 1 : 2;
+            col[q] = (uint32_t)bp;
+            off[q] = X[sx] + Y[sy] + Z[sz];
             sh[q] = 0;
         }
     } else {
@@ -377,6 +413,9 @@ __device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, const VW& V, i
     if (R.lattice == SL_LATTICE_SC)
         return R.n_species > 1 ? exchange_sum_t<T, VW, SL_LATTICE_SC, true>(R, V, k, a, sp)
                                : exchange_sum_t<T, VW, SL_LATTICE_SC, false>(R, V, k, a, sp);
+    if (R.lattice == SL_LATTICE_FCC)
+        return R.n_species > 1 ? exchange_sum_t<T, VW, SL_LATTICE_FCC, true>(R, V, k, a, sp)
+                               : exchange_sum_t<T, VW, SL_LATTICE_FCC, false>(R, V, k, a, sp);
     return R.n_species > 1 ? exchange_sum_t<T, VW, SL_LATTICE_BCC, true>(R, V, k, a, sp)
                            : exchange_sum_t<T, VW, SL_LATTICE_BCC, false>(R, V, k, a, sp);
 }
@@ -396,14 +435,20 @@ __device__ __forceinline__ Cell3 cell_of(const Geom& g, int k, uint32_t l)
     c.xh = l - __umul24(r, (uint32_t)g.Lxh);
     c.z = fdiv(r, g.divLy);
     c.y = r - __umul24(c.z, (uint32_t)g.Ly);
-    c.x = 2 * c.xh + (((uint32_t)k + c.y + c.z) & 1u);
+    c.x = g.par ? 2 * c.xh + (((uint32_t)k + c.y + c.z) & 1u) : c.xh;
     return c;
 }
 
+// Ideal position of a site: its cell corner, the basis shift and a quarter
+// lattice constant along each axis (so that no ideal site lies on a face of
+// the electron grid).
 template <typename T> __device__ inline V3<T> ideal_site(const RunDev<T>& R, const Site& s)
 {
-    const T off = T(0.25) + T(0.5) * (T)s.b;
-    return {((T)s.x + off) * R.a, ((T)s.y + off) * R.a, ((T)s.z + off) * R.a};
+    const uint32_t hb = basis_half_bits(R.g.nb, s.b);
+    const T ox = (hb & 1u) ? T(0.75) : T(0.25);
+    const T oy = (hb & 2u) ? T(0.75) : T(0.25);
+    const T oz = (hb & 4u) ? T(0.75) : T(0.25);
+    return {((T)s.x + ox) * R.a, ((T)s.y + oy) * R.a, ((T)s.z + oz) * R.a};
 }
 
 // Minimum image of a separation |d| < 1.5 box: the nearest lattice
@@ -589,10 +634,11 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
     const T H0x = h.x * imu + R.B[0];
     const T H0y = h.y * imu + R.B[1];
     const T H0z = h.z * imu + R.B[2];
-    const int b = LAT == SL_LATTICE_BCC ? (colour >> 1) : 0;
+    const int b = LAT == SL_LATTICE_BCC ? (colour >> 1) : (LAT == SL_LATTICE_FCC ? colour : 0);
     const uint32_t canon =
         __umul24(__umul24(c.z, (uint32_t)R.g.Ly) + c.y, (uint32_t)R.g.Lx) * (uint32_t)R.g.nb +
         c.x * (uint32_t)R.g.nb + (uint32_t)b;
+    bool bad = false;   // the watchdog: a spin that was not a finite unit vector
     // one exact rotation over tau_ with the thermal field of step stp at T_e
     auto rotate = [&](V3<T> s0, int64_t stp, double Te, T tau_) {
         T Hx = H0x, Hy = H0y, Hz = H0z;
@@ -610,7 +656,7 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
             Hz += amp * nu.c;
         }
         const V3<T> wv{R.gam * Hx, R.gam * Hy, R.gam * Hz};
-        return llg_flow(s0, wv, R.alpha, tau_, R.inv1pa2);
+        return llg_flow(s0, wv, R.alpha, tau_, R.inv1pa2, bad);
     };
     V3<T> s{M::ld(V.sx + kH, l), M::ld(V.sy + kH, l), M::ld(V.sz + kH, l)};
     if (has_prev) {
@@ -633,6 +679,7 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
     M::st(V.sx + kH, l, s.x);
     M::st(V.sy + kH, l, s.y);
     M::st(V.sz + kH, l, s.z);
+    if (bad) atomicOr(&R.st->err, ERR_NUMERIC);
 }
 
 // Dispatch on the run's lattice and species count (uniform per run).
@@ -647,6 +694,9 @@ __device__ __forceinline__ void spin_site(const RunDev<T>& R, const VW& V, int c
         if (R.lattice == SL_LATTICE_SC) {
             if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
             else spin_site_t<T, VW, SL_LATTICE_SC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        } else if (R.lattice == SL_LATTICE_FCC) {
+            if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_FCC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+            else spin_site_t<T, VW, SL_LATTICE_FCC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
         } else {
             if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
             else spin_site_t<T, VW, SL_LATTICE_BCC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
@@ -656,6 +706,9 @@ __device__ __forceinline__ void spin_site(const RunDev<T>& R, const VW& V, int c
     if (R.lattice == SL_LATTICE_SC) {
         if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
         else spin_site_t<T, VW, SL_LATTICE_SC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+    } else if (R.lattice == SL_LATTICE_FCC) {
+        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_FCC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else spin_site_t<T, VW, SL_LATTICE_FCC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     } else {
         if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
         else spin_site_t<T, VW, SL_LATTICE_BCC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
@@ -689,6 +742,10 @@ __device__ __forceinline__ bool kick_drift_atom(const RunDev<T>& R, const VW& V,
         T uz = gld(R.uz, i) + R.dt * vz;
         gst(R.vx, i, vx); gst(R.vy, i, vy); gst(R.vz, i, vz);
         gst(R.ux, i, ux); gst(R.uy, i, uy); gst(R.uz, i, uz);
+        // watchdog: a non-finite velocity or displacement (from a non-finite
+        // force) stops the run
+        if (!(fabs(vx) + fabs(vy) + fabs(vz) + fabs(ux) + fabs(uy) + fabs(uz) < T(1.0e30)))
+            atomicOr(&R.st->err, ERR_NUMERIC);
         const T dx = ux - gld(R.rx, i), dy = uy - gld(R.ry, i), dz = uz - gld(R.rz, i);
         far = dx * dx + dy * dy + dz * dz > R.skin_half2;
     }
@@ -825,7 +882,10 @@ __device__ inline void nbr_build_atom(const RunDev<T>& R, const VW& V, uint32_t 
                     if (SORTED_BINS) break;
                     for (int t = 0; t < m; ++t) append(sld(keep, (uint32_t)t * kBlock));
                     more = mtot > kBinKeep;
-                    if (more) lo = sld(keep, (uint32_t)(kBinKeep - 1) * kBlock);
+                    if (more) {
+                        lo = sld(keep, (uint32_t)(kBinKeep - 1) * kBlock);
+                        atomicAdd(&R.st->n_rescan, 1);
+                    }
                 }
             }
         }
@@ -1138,7 +1198,7 @@ __device__ inline void diffuse_cell(const RunDev<T>& R, const double* src, doubl
                                     src[(k * n1 + jm) * n0 + i], src[(kp * n1 + j) * n0 + i],
                                     src[(km * n1 + j) * n0 + i], e0);
     R.ee[c] = e;
-    if (e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
+    if (!(e >= 0.0)) atomicOr(&R.st->err, ERR_NEG_E);   // negative or not a number
     dst[c] = diffuse_temp(R, e);
 }
 
@@ -1180,7 +1240,7 @@ __device__ inline void cell_update_from(const RunDev<T>& R, double T0, unsigned 
     if (dEsum != nullptr) dEsum[c] = 0ull;
     const double e = cell_energy(R, e0, raw, c, step);
     R.ee[c] = e;
-    if (e < 0.0) {
+    if (!(e >= 0.0)) {   // negative or not a number
         if (neg_k >= 0) atomicCAS(&R.st->neg_at, 0, neg_k + 1);
         else atomicOr(&R.st->err, ERR_NEG_E);
     }
@@ -1705,7 +1765,7 @@ __global__ __launch_bounds__(kTileBlock) void k_ttm_tile(const RunDev<T>* __rest
                                                 A[r - P], e0);
                 E[r] = e;
                 B[r] = diffuse_temp(R, e);
-                if (own_col && z >= h && z < h + w2 && e < 0.0) atomicOr(&R.st->err, ERR_NEG_E);
+                if (own_col && z >= h && z < h + w2 && !(e >= 0.0)) atomicOr(&R.st->err, ERR_NEG_E);
             }
         }
         __syncthreads();
@@ -1871,6 +1931,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict
 struct PersistLayout {
     uint32_t off_s, off_species, off_cell, off_pos, off_Te, off_Te2, off_acc, off_part, bytes;
     int32_t pos_in_lds;
+    int32_t part_in_lds;   // the observable rows (else the run's global rows: they are
+                           // written and read on sample steps only)
 };
 
 template <typename T>
@@ -1890,10 +1952,16 @@ __host__ __device__ inline PersistLayout persist_layout(int n, int ncell, int n_
     L.off_Te = take(8u * (uint32_t)ncell);
     L.off_Te2 = take(8u * (uint32_t)ncell);
     L.off_acc = take(8u * (uint32_t)ncell);
-    L.off_part = take(8u * NQ * (uint32_t)n_part);
+    L.part_in_lds = 0;
+    L.off_part = 0;
+    const uint32_t part_bytes = 8u * NQ * (uint32_t)n_part;
+    if (o + part_bytes <= lds_max) {
+        L.off_part = take(part_bytes);
+        L.part_in_lds = 1;
+    }
     L.pos_in_lds = 0;
     L.off_pos = 0;
-    if (live && o + (uint32_t)n * (uint32_t)sizeof(Pos4<T>) <= lds_max) {
+    if (live && L.part_in_lds && o + (uint32_t)n * (uint32_t)sizeof(Pos4<T>) <= lds_max) {
         L.off_pos = take((uint32_t)n * (uint32_t)sizeof(Pos4<T>));
         L.pos_in_lds = 1;
     }
@@ -2041,7 +2109,7 @@ __global__ __launch_bounds__(MAXT) void k_persist(const RunDev<T>* __restrict__ 
     double* Te = reinterpret_cast<double*>(smem + L.off_Te);
     double* Te2 = reinterpret_cast<double*>(smem + L.off_Te2);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.off_acc);
-    double* partial = reinterpret_cast<double*>(smem + L.off_part);
+    double* partial = L.part_in_lds ? reinterpret_cast<double*>(smem + L.off_part) : R.partial;
     if (L.pos_in_lds) {
         const View<T, InLds, InLds> V{sx, sx + n, sx + 2 * n, species, cell,
                                       reinterpret_cast<Pos4<T>*>(smem + L.off_pos), Te, partial};

@@ -89,7 +89,7 @@ void launch(void (*k)(KA...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t
 // table so that every XCD receives one contiguous range of tiles keeps the
 // neighbouring rows and planes of a tile in the same L2.  Any order gives the
 // same results; only the cache traffic changes.
-constexpr size_t kXcds = 8;
+constexpr size_t kXcds = sl::kXcdCount;
 inline void xcd_order(std::vector<int2>& t)
 {
     const size_t m = t.size();
@@ -118,13 +118,32 @@ struct Carver {
 };
 
 // ------------------------------------------------------------ validation
+// Ideal position of a site (as the kernels place it): cell corner, basis
+// shift and a quarter lattice constant along each axis.
+inline void ideal_position(const sl::Geom& g, const sl::Site& s, double a, double r0[3])
+{
+    const uint32_t hb = sl::basis_half_bits(g.nb, s.b);
+    const int c[3] = {s.x, s.y, s.z};
+    for (int k = 0; k < 3; ++k) r0[k] = (c[k] + ((hb >> k) & 1u ? 0.75 : 0.25)) * a;
+}
+
+// basis sites per cubic cell
+inline int basis_count(int lattice)
+{
+    return lattice == SL_LATTICE_BCC ? 2 : (lattice == SL_LATTICE_FCC ? 4 : 1);
+}
+
 std::string validate_desc(const sl_system_desc* d)
 {
     if (!d) return "null description";
-    if (d->lattice != SL_LATTICE_SC && d->lattice != SL_LATTICE_BCC) return "lattice must be 0 (sc) or 1 (bcc)";
-    for (int k = 0; k < 3; ++k)
-        if (d->ncell[k] < 2 || (d->ncell[k] & 1)) return "every ncell must be even and >= 2";
-    const int64_t nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
+    if (d->lattice != SL_LATTICE_SC && d->lattice != SL_LATTICE_BCC && d->lattice != SL_LATTICE_FCC)
+        return "lattice must be 0 (sc), 1 (bcc) or 2 (fcc)";
+    for (int k = 0; k < 3; ++k) {
+        if (d->ncell[k] < 2) return "every ncell must be >= 2";
+        // the checkerboard colourings need even counts; fcc colours by basis
+        if (d->lattice != SL_LATTICE_FCC && (d->ncell[k] & 1)) return "every ncell must be even (sc, bcc)";
+    }
+    const int64_t nb = basis_count(d->lattice);
     const int64_t n = nb * (int64_t)d->ncell[0] * d->ncell[1] * d->ncell[2];
     // per-atom arrays are addressed with 32-bit byte offsets (32 B per atom
     // at most)
@@ -137,6 +156,7 @@ std::string validate_desc(const sl_system_desc* d)
         if (d->lattice_mode == 1 && !(d->mass[s] > 0.0)) return "every mass must be positive";
     }
     if (d->lattice == SL_LATTICE_SC && d->n_shells != 1) return "sc supports one exchange shell";
+    if (d->lattice == SL_LATTICE_FCC && d->n_shells != 1) return "fcc supports one exchange shell";
     if (d->lattice == SL_LATTICE_BCC && (d->n_shells < 1 || d->n_shells > 2)) return "bcc supports one or two shells";
     if (!(d->alpha >= 0.0)) return "alpha must be >= 0";
     if (d->noise_mode != 0 && d->noise_mode != 1) return "noise_mode must be 0 or 1";
@@ -226,7 +246,7 @@ struct Sizes {
 Sizes run_sizes(const sl_system_desc* d, const sl_ttm_desc* t)
 {
     Sizes z{};
-    const int nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
+    const int nb = basis_count(d->lattice);
     z.n = (int64_t)nb * d->ncell[0] * d->ncell[1] * d->ncell[2];
     z.ncell = t->n[0] * t->n[1] * t->n[2];
     z.n_part = (int)((z.n + 63) / 64);   // one row of observable partials per wave
@@ -478,6 +498,13 @@ public:
             sl_status st = rebuild_tables();
             if (st != SL_OK) return st;
         }
+        return advance_core(n, true);
+    }
+
+    // The steps themselves, the tables being in place; with_graph: replay the
+    // captured graph for whole chunks (capturing it first if needed).
+    sl_status advance_core(int64_t n, bool with_graph)
+    {
         if (active_blocks_atom == 0 && persist_runs == 0) return SL_OK;
         // the runs that live in LDS advance in persistent launches on a side
         // stream, concurrently with the multi-kernel step of the others
@@ -498,13 +525,27 @@ public:
         }
         int64_t left = active_blocks_atom > 0 ? n : 0;
         const int G = graph_len();
+        // a merged chunk shorter than the chunk length: replayed from a graph
+        // kept per length, or launched directly
+        auto short_chunk = [&](int len) -> sl_status {
+            if (!with_graph) return enqueue_chunk(stream, nullptr, len);
+            hipGraphExec_t ex = nullptr;
+            sl_status st = chunk_graph(len, &ex);
+            if (st != SL_OK) return st;
+            SL_HIP(hipGraphLaunch(ex, stream));
+            return SL_OK;
+        };
         if (merge_g >= 2 && left > 0) {
-            // single steps up to the next multiple of the chunk length
+            // a shorter merged chunk up to the next multiple of the chunk
+            // length (it ends on no sample step: those are multiples of it)
             const int64_t head = std::min<int64_t>(chunk_head(), left);
-            for (int64_t k = 0; k < head; ++k) enqueue_step(stream, nullptr);
+            if (head > 0) {
+                sl_status st = short_chunk((int)head);
+                if (st != SL_OK) return st;
+            }
             left -= head;
         }
-        if (G > 1 && left >= G) {
+        if (G > 1 && left >= G && with_graph) {
             if (!graph_ok) {
                 sl_status st = capture();
                 if (st != SL_OK) return st;
@@ -513,6 +554,17 @@ public:
                 SL_HIP(hipGraphLaunch(exec, stream));
                 left -= G;
             }
+        } else if (G > 1 && merge_g >= 2) {
+            for (; left >= G; left -= G) {
+                sl_status st = enqueue_chunk(stream, nullptr);
+                if (st != SL_OK) return st;
+            }
+        }
+        if (merge_g >= 2 && left > 0) {
+            // the rest as one shorter merged chunk from a chunk boundary
+            sl_status st = short_chunk((int)left);
+            if (st != SL_OK) return st;
+            left = 0;
         }
         for (int64_t k = 0; k < left; ++k) enqueue_step(stream, nullptr);
         SL_HIP(hipGetLastError());
@@ -543,19 +595,24 @@ public:
             });
             if (st != SL_OK) return st;
         }
-        // the schedule advance() uses: single steps up to a chunk boundary,
-        // then merged chunks, then single steps
+        // the schedule advance() uses: a shorter merged chunk up to a chunk
+        // boundary, whole chunks, a shorter chunk for the rest
         int64_t left = active_blocks_atom > 0 ? n : 0;
         if (merge_g >= 2 && left > 0) {
             const int64_t head = std::min<int64_t>(chunk_head(), left);
-            for (int64_t k = 0; k < head; ++k) {
-                sl_status st = enqueue_step(stream, &p);
+            if (head > 0) {
+                sl_status st = enqueue_chunk(stream, &p, (int)head);
                 if (st != SL_OK) return st;
             }
             left -= head;
             for (; left >= merge_g; left -= merge_g) {
                 sl_status st = enqueue_chunk(stream, &p);
                 if (st != SL_OK) return st;
+            }
+            if (left > 0) {
+                sl_status st = enqueue_chunk(stream, &p, (int)left);
+                if (st != SL_OK) return st;
+                left = 0;
             }
         }
         for (int64_t k = 0; k < left; ++k) {
@@ -618,9 +675,8 @@ public:
             if ((st = fetch3(R.ux, R.uy, R.uz)) != SL_OK) return st;
             for (size_t i = 0; i < n; ++i) {
                 sl::Site site = sl::decode_site(R.g, (uint32_t)i);
-                const double off = 0.25 + 0.5 * site.b;
-                const double r0[3] = {(site.x + off) * r.d.a, (site.y + off) * r.d.a,
-                                      (site.z + off) * r.d.a};
+                double r0[3];
+                ideal_position(R.g, site, r.d.a, r0);
                 for (int k = 0; k < 3; ++k) {
                     const double L = r.d.ncell[k] * r.d.a;
                     double p = r0[k] + (double)buf[k * n + i];
@@ -702,9 +758,8 @@ public:
             T* out[3] = {a.data(), b.data(), c.data()};
             for (size_t i = 0; i < n; ++i) {
                 const sl::Site site = sl::decode_site(R.g, (uint32_t)i);
-                const double off = 0.25 + 0.5 * site.b;
-                const double r0[3] = {(site.x + off) * r.d.a, (site.y + off) * r.d.a,
-                                      (site.z + off) * r.d.a};
+                double r0[3];
+                ideal_position(R.g, site, r.d.a, r0);
                 const size_t ci = (size_t)r.canon[i];
                 for (int k = 0; k < 3; ++k) {
                     const double L = r.d.ncell[k] * r.d.a;
@@ -751,6 +806,8 @@ public:
         out->list_rebuilds = rs.n_rebuild;
         out->max_list = rs.max_list;
         out->list_capacity = host_rd[s].live ? host_rd[s].max_nbr : 0;
+        out->list_rescans = rs.n_rescan;
+        out->error = rs.err;
         return SL_OK;
     }
 
@@ -805,6 +862,10 @@ private:
     bool any_live = false;
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
+    // graphs of merged chunks shorter than merge_g, by length (a chunk's
+    // launches depend on its length only; every kernel reads the steps from
+    // the run state)
+    std::vector<std::pair<int, hipGraphExec_t>> short_exec;
     bool tables_dirty = true;
     // persistent executor: runs that fit in LDS, one block each
     hipStream_t side_stream = nullptr;
@@ -831,7 +892,9 @@ private:
                  std::to_string(rs.bad_count) + " at step " + std::to_string(rs.bad_step) +
                  ", list capacity " + std::to_string(host_rd[s].max_nbr) + ", bin capacity " +
                  std::to_string(host_rd[s].bin_cap) + "]";
-        if (err & sl::ERR_NEG_E) m += " negative electron energy density;";
+        if (err & sl::ERR_NEG_E) m += " negative electron energy density (or not a number);";
+        if (err & sl::ERR_NUMERIC)
+            m += " non-finite or non-unit spin, or non-finite velocity or position;";
         if (err & sl::ERR_BIN) m += " neighbour bin overflow;";
         if (err & sl::ERR_NBR) m += " neighbour list overflow;";
         if (err & sl::ERR_DE) m += " electron-phonon energy out of range;";
@@ -843,6 +906,8 @@ private:
         if (exec) (void)hipGraphExecDestroy(exec);
         exec = nullptr;
         graph_ok = false;
+        for (auto& e : short_exec) (void)hipGraphExecDestroy(e.second);
+        short_exec.clear();
     }
 
     void release(size_t s)
@@ -862,14 +927,16 @@ private:
         Run& r = runs[s];
         const sl_system_desc* d = &r.d;
         RD R{};
-        const int nb = d->lattice == SL_LATTICE_BCC ? 2 : 1;
+        const int nb = basis_count(d->lattice);
+        const bool fcc = d->lattice == SL_LATTICE_FCC;
         R.g.Lx = d->ncell[0];
         R.g.Ly = d->ncell[1];
         R.g.Lz = d->ncell[2];
-        R.g.Lxh = d->ncell[0] / 2;
-        R.g.H = d->ncell[0] * d->ncell[1] * d->ncell[2] / 2;
+        R.g.par = fcc ? 0 : 1;
+        R.g.Lxh = fcc ? d->ncell[0] : d->ncell[0] / 2;
+        R.g.H = fcc ? d->ncell[0] * d->ncell[1] * d->ncell[2] : d->ncell[0] * d->ncell[1] * d->ncell[2] / 2;
         R.g.nb = nb;
-        R.g.C = 2 * nb;
+        R.g.C = fcc ? 4 : 2 * nb;
         R.g.divH = sl::make_fastdiv((uint32_t)R.g.H);
         R.g.divLxh = sl::make_fastdiv((uint32_t)R.g.Lxh);
         R.g.divLy = sl::make_fastdiv((uint32_t)R.g.Ly);
@@ -1147,16 +1214,46 @@ private:
         return SL_OK;
     }
 
+    // The launch tables of the current runs, as host arrays: block -> (run,
+    // first item) of the colour passes (ws), the force kernel (wa), the kick
+    // (wk), the cell-parallel grid update (wc), the diffusion sub-step
+    // launches (wd) and tiles (wt); the runs on the multi-kernel step (rl) and
+    // in the persistent kernel (pl).
+    struct Tables {
+        std::vector<int2> ws, wa, wk, wc, wd, wt;
+        std::vector<int> rl, pl;
+    };
+
     sl_status rebuild_tables()
     {
         drop_graph();
         tables_dirty = false;
-        std::vector<int2> ws, wa, wk, wc, wd, wt;
-        std::vector<int> rl;
+        Tables tb;
+        std::vector<int> changed;
+        plan_tables(tb, changed);
+        for (int s : changed)
+            SL_HIP(hipMemcpyAsync(d_runs + s, &host_rd[s], sizeof(RD), hipMemcpyHostToDevice, stream));
+        return upload_tables(tb);
+    }
+
+    // Host part of a table rebuild: the launch plan (block sizes, lanes,
+    // binning mode, merged chunks, block counts) and the tables.  Runs whose
+    // per-run flags (binning by the kick, normals drawn by the kick) changed
+    // are listed in `changed`: their host descriptors are updated here, their
+    // device copies by the caller.
+    void plan_tables(Tables& tb, std::vector<int>& changed)
+    {
+        std::vector<int2>& ws = tb.ws;
+        std::vector<int2>& wa = tb.wa;
+        std::vector<int2>& wk = tb.wk;
+        std::vector<int2>& wc = tb.wc;
+        std::vector<int2>& wd = tb.wd;
+        std::vector<int2>& wt = tb.wt;
+        std::vector<int>& rl = tb.rl;
+        std::vector<int>& pl = tb.pl;
         any_live = false;
         max_sub = 0;
         tile_bytes = 0;
-        std::vector<int> pl;
         persist_bytes = 0;
         // automatic launch shapes for the runs on the multi-kernel step: the
         // colour-pass block is the largest of 256, 128, 64 threads that still
@@ -1235,7 +1332,7 @@ private:
             if (host_rd[s].bin_step != want || host_rd[s].eta_drawn != draw) {
                 host_rd[s].bin_step = want;
                 host_rd[s].eta_drawn = draw;
-                SL_HIP(hipMemcpyAsync(d_runs + s, &host_rd[s], sizeof(RD), hipMemcpyHostToDevice, stream));
+                changed.push_back((int)s);
             }
         }
         // adjacent colour-0 half steps of consecutive steps merge into one pass
@@ -1298,9 +1395,6 @@ private:
                 }
             }
         }
-        for (void* p : tables) alloc.put(p);
-        tables.clear();
-        d_work_spin = d_work_atom = d_work_kick = d_work_cell = d_work_diff = d_work_tile = nullptr;
         active_blocks_spin = (int)ws.size();
         active_blocks_atom = (int)wa.size();
         active_blocks_kick = (int)wk.size();
@@ -1308,8 +1402,16 @@ private:
         active_blocks_diff = (int)wd.size();
         active_blocks_tile = (int)wt.size();
         active_runs = (int)rl.size();
-        d_run_list = nullptr;
         persist_runs = (int)pl.size();
+    }
+
+    // Device copies of the tables, in memory from the engine's allocator.
+    sl_status upload_tables(const Tables& tb)
+    {
+        for (void* p : tables) alloc.put(p);
+        tables.clear();
+        d_work_spin = d_work_atom = d_work_kick = d_work_cell = d_work_diff = d_work_tile = nullptr;
+        d_run_list = nullptr;
         d_persist_list = nullptr;
         auto up = [&](const void* src, size_t bytes, void** dst) -> sl_status {
             if (bytes == 0) return SL_OK;
@@ -1321,14 +1423,14 @@ private:
             return SL_OK;
         };
         sl_status st;
-        if ((st = up(ws.data(), sizeof(int2) * ws.size(), (void**)&d_work_spin)) != SL_OK) return st;
-        if ((st = up(wa.data(), sizeof(int2) * wa.size(), (void**)&d_work_atom)) != SL_OK) return st;
-        if ((st = up(wk.data(), sizeof(int2) * wk.size(), (void**)&d_work_kick)) != SL_OK) return st;
-        if ((st = up(wc.data(), sizeof(int2) * wc.size(), (void**)&d_work_cell)) != SL_OK) return st;
-        if ((st = up(wd.data(), sizeof(int2) * wd.size(), (void**)&d_work_diff)) != SL_OK) return st;
-        if ((st = up(wt.data(), sizeof(int2) * wt.size(), (void**)&d_work_tile)) != SL_OK) return st;
-        if ((st = up(rl.data(), sizeof(int) * rl.size(), (void**)&d_run_list)) != SL_OK) return st;
-        if ((st = up(pl.data(), sizeof(int) * pl.size(), (void**)&d_persist_list)) != SL_OK) return st;
+        if ((st = up(tb.ws.data(), sizeof(int2) * tb.ws.size(), (void**)&d_work_spin)) != SL_OK) return st;
+        if ((st = up(tb.wa.data(), sizeof(int2) * tb.wa.size(), (void**)&d_work_atom)) != SL_OK) return st;
+        if ((st = up(tb.wk.data(), sizeof(int2) * tb.wk.size(), (void**)&d_work_kick)) != SL_OK) return st;
+        if ((st = up(tb.wc.data(), sizeof(int2) * tb.wc.size(), (void**)&d_work_cell)) != SL_OK) return st;
+        if ((st = up(tb.wd.data(), sizeof(int2) * tb.wd.size(), (void**)&d_work_diff)) != SL_OK) return st;
+        if ((st = up(tb.wt.data(), sizeof(int2) * tb.wt.size(), (void**)&d_work_tile)) != SL_OK) return st;
+        if ((st = up(tb.rl.data(), sizeof(int) * tb.rl.size(), (void**)&d_run_list)) != SL_OK) return st;
+        if ((st = up(tb.pl.data(), sizeof(int) * tb.pl.size(), (void**)&d_persist_list)) != SL_OK) return st;
         SL_HIP(hipStreamSynchronize(stream));
         return SL_OK;
     }
@@ -1365,10 +1467,11 @@ private:
     // merge_first: colour pass 0 applies the previous step's deferred last
     // half step first; defer_last: this step's last colour pass is left to
     // the next step's pass 0.  The lattice kick rides on colour pass 1.
-    // fold_k >= 0: position of the step in a folded chunk (its pass 0 ends
-    // the previous step, and only the chunk's last step has a k_finalize).
+    // fold_k >= 0: position of the step in a folded chunk of chunk_len steps
+    // (its pass 0 ends the previous step, and only the chunk's last step has
+    // a k_finalize).
     sl_status enqueue_step(hipStream_t st, Prof* p, bool merge_first = false, bool defer_last = false,
-                           int fold_k = -1)
+                           int fold_k = -1, int chunk_len = 0)
     {
         const int C = max_colours();
         // the atom table's tiles hold atom_block / atom_lanes atoms: the
@@ -1443,7 +1546,7 @@ private:
             });
             if (e != SL_OK) return e;
         }
-        if (fold_k >= 0 && fold_k < merge_g - 1) return SL_OK;
+        if (fold_k >= 0 && fold_k < (chunk_len > 0 ? chunk_len : merge_g) - 1) return SL_OK;
         e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
             launch(sl::k_finalize<T>, dim3(active_runs), bk, 0, st, a, b, d_runs, d_run_list,
                    (int)sl::PHASE_STEP, defer_last ? 1 : 0, fold_k);
@@ -1451,13 +1554,16 @@ private:
         return e;
     }
 
-    // One chunk of merge_g steps: every step but the last defers its last
-    // colour half step, every step but the first applies the one deferred
-    // before it, so the chunk ends with complete sweeps.
-    sl_status enqueue_chunk(hipStream_t st, Prof* p)
+    // One chunk of merge_g steps (or len < merge_g steps, which end before
+    // the next multiple of merge_g and so on no sample step): every step but
+    // the last defers its last colour half step, every step but the first
+    // applies the one deferred before it, so the chunk ends with complete
+    // sweeps.
+    sl_status enqueue_chunk(hipStream_t st, Prof* p, int len = 0)
     {
-        for (int k = 0; k < merge_g; ++k) {
-            sl_status e = enqueue_step(st, p, k > 0, k < merge_g - 1, fold ? k : -1);
+        if (len <= 0) len = merge_g;
+        for (int k = 0; k < len; ++k) {
+            sl_status e = enqueue_step(st, p, k > 0, k < len - 1, fold ? k : -1, len);
             if (e != SL_OK) return e;
         }
         return SL_OK;
@@ -1474,6 +1580,28 @@ private:
         for (int s : mk_runs)
             if (runs[s].steps < runs[s].target) return (merge_g - runs[s].steps % merge_g) % merge_g;
         return 0;
+    }
+
+    // The graph of a merged chunk of len < merge_g steps (captured on first use).
+    sl_status chunk_graph(int len, hipGraphExec_t* out)
+    {
+        for (auto& e : short_exec)
+            if (e.first == len) {
+                *out = e.second;
+                return SL_OK;
+            }
+        hipGraph_t graph = nullptr;
+        SL_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_chunk(cap_stream, nullptr, len);
+        hipError_t e = hipStreamEndCapture(cap_stream, &graph);
+        if (e != hipSuccess) return fail(SL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(SL_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        short_exec.emplace_back(len, ex);
+        *out = ex;
+        return SL_OK;
     }
 
     sl_status capture()

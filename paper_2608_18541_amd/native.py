@@ -91,7 +91,8 @@ class sl_tuning(C.Structure):
 
 class sl_run_stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("samples", C.c_int64), ("list_rebuilds", C.c_int64),
-                ("max_list", C.c_int32), ("list_capacity", C.c_int32)]
+                ("max_list", C.c_int32), ("list_capacity", C.c_int32),
+                ("list_rescans", C.c_int32), ("error", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -182,6 +183,8 @@ class TorchAllocator:
         import torch
         self._torch = torch
         self._live = {}
+        self.n_allocs = 0
+        self.history = []          # (device address, bytes) of every allocation, in order
         self._alloc = ALLOC_FN(self._do_alloc)
         self._free = FREE_FN(self._do_free)
         self.struct = sl_allocator(None, self._alloc, self._free)
@@ -191,6 +194,8 @@ class TorchAllocator:
         p = t.data_ptr()
         aligned = (p + 255) & ~255
         self._live[aligned] = t
+        self.n_allocs += 1
+        self.history.append((aligned, int(nbytes)))
         return aligned
 
     def _do_free(self, ctx, ptr):

@@ -75,15 +75,21 @@ def phase_diagram(L: int = 16, n_alpha: int = 8, n_temp: int = 8, n_seeds: int =
 
 
 def production_run(L: int, T0: float, d: float, seed: int, run_id: int, n_steps: int,
-                   alpha: float = 0.01, base_ends=(0.1, 0.5), p_gd: float = 0.25) -> RunSpec:
-    """One production realization: sc alloy L^3 with exactly round(p_gd L^3)
-    Gd sites on a frozen lattice, the literature anisotropy on both species,
-    B = 0, electrons held at T0 until
-    d * base_ends[0] ps, at T0 / 2 until d * base_ends[1] ps, then at 300 K.
-    The paper scales the stage durations by d but does not give the base
-    durations; base_ends is this workload's choice."""
-    spec = I.gdfeco_sc_spec(L=L, tn=max(1, L // 4), alpha=alpha, lattice_mode=0,
-                            K=(I.GDFECO_K, I.GDFECO_K, 0.0, 0.0), seed=seed, run_id=run_id)
+                   alpha: float = 0.01, base_ends=(0.1, 0.5), p_gd: float = 0.25,
+                   lattice: str = "sc") -> RunSpec:
+    """One production realization: an alloy with exactly round(p_gd N) Gd
+    sites on a frozen lattice, the literature anisotropy on both species,
+    B = 0, electrons held at T0 until d * base_ends[0] ps, at T0 / 2 until
+    d * base_ends[1] ps, then at 300 K.  lattice "fcc": the paper's model
+    (L^3 fcc cells, a = 3.6 A, the literature exchange, one electron cell);
+    "sc": the 32^3 workload's alloy on L^3 simple-cubic cells.  The paper
+    scales the stage durations by d but does not give the base durations;
+    base_ends is this workload's choice."""
+    if lattice == "fcc":
+        spec = I.gdfeco_fcc_spec(L=L, alpha=alpha, seed=seed, run_id=run_id)
+    else:
+        spec = I.gdfeco_sc_spec(L=L, tn=max(1, L // 4), alpha=alpha, lattice_mode=0,
+                                K=(I.GDFECO_K, I.GDFECO_K, 0.0, 0.0), seed=seed, run_id=run_id)
     spec = replace(spec, ttm_mode=2, step_T=(T0, 0.5 * T0, 300.0),
                    step_end=(d * base_ends[0], d * base_ends[1]))
     return RunSpec(spec, n_steps, (T0, d), "afm", p_gd, exact_count=True)
@@ -91,7 +97,8 @@ def production_run(L: int, T0: float, d: float, seed: int, run_id: int, n_steps:
 
 def production_diagram(L: int = 16, n_temp: int = 8, n_d: int = 8, n_seeds: int = 20,
                        n_steps: int = 50000, seed: int = 2027, temp_range=(800.0, 2900.0),
-                       d_range=(1.0, 8.0), base_ends=(0.1, 0.5)) -> List[RunSpec]:
+                       d_range=(1.0, 8.0), base_ends=(0.1, 0.5),
+                       lattice: str = "sc") -> List[RunSpec]:
     """Peak T_e linearly spaced x d linearly spaced x seeds (the paper's
     8 x 8 x 20 grid: 800-2900 K, d = 1-8); run_id enumerates the runs."""
     t0, t1 = temp_range
@@ -103,7 +110,8 @@ def production_diagram(L: int = 16, n_temp: int = 8, n_d: int = 8, n_seeds: int 
     for T in temps:
         for d in ds:
             for s in range(n_seeds):
-                out.append(production_run(L, T, d, seed, rid, n_steps, base_ends=base_ends))
+                out.append(production_run(L, T, d, seed, rid, n_steps, base_ends=base_ends,
+                                          lattice=lattice))
                 rid += 1
     return out
 

@@ -6,8 +6,8 @@ bin's atoms in ascending index.  So one, two or four lanes per atom, bins
 filled by the kick (unsorted) or sorted by a separate launch, and the
 persistent executor must all give the same bits; with a skin this thin the
 lists are rebuilt every few steps.  A wide skin overfills the per-bin
-register buffer of the unsorted build, whose selection fallback is checked
-against the oracle.
+buffer of the unsorted build, whose second scan of a bin is counted and
+checked against the oracle.
 """
 import sys
 from dataclasses import replace
@@ -89,25 +89,30 @@ def test_invalid_lane_split_rejected(N):
 
 
 def test_overfull_bins_against_oracle(N):
-    """bcc Fe with a 2 A skin: bins at least 7 A wide hold about 30 atoms,
-    more than the unsorted build keeps sorted in registers per bin, so its
-    selection fallback builds those bins.  FP64 against the oracle over 30
-    steps, and bitwise against the sorted-bin build."""
-    spec = replace(I.fe_bcc_spec(L=8), skin=2.0)
-    st = I.initial_state(spec, "tilt")
+    """bcc Fe 8^3 with a 1 A skin: 7.6 A bins hold about 38 atoms, more than
+    the 16 accepted atoms per bin the unsorted build keeps sorted, so a
+    rebuild from unsorted bins scans such bins a second time.  3000 K
+    velocities at a 1 fs step trigger rebuilds inside the 100-step window;
+    the rescans are counted on the device.  FP64 against the oracle, and
+    bitwise against the sorted-bin build."""
+    spec = replace(I.fe_bcc_spec(L=8), skin=1.0, dt=1e-3)
+    st = I.initial_state(spec, "tilt", T_lattice=3000.0)
     out = []
     for sh in (dict(bin_mode=1, atom_lanes=1), dict(bin_mode=2, atom_lanes=4, atom_block=256)):
-        _log("case: bcc L=8 skin=2 shape=%s" % sh)
+        _log("case: bcc L=8 skin=1 3000 K shape=%s" % sh)
         g = N.System(spec, st, precision=0)
         g.set_tuning(**sh)
-        g.step(30)
+        g.step(100)
         out.append(g.state())
-        assert g.stats()["max_list"] > 16
+        stats = g.stats()
+        assert stats["list_rebuilds"] >= 3 and stats["max_list"] > 16, stats
+        if sh["bin_mode"] == 1:
+            assert stats["list_rescans"] > 0, stats
         g.close()
     for k in ("s", "x", "v", "Te"):
         assert np.array_equal(out[0][k], out[1][k]), k
     o = O.Oracle(spec, st.species, st.spins, st.vel, disp=st.disp)
-    o.step(30)
+    o.step(100)
     errs, bad = compare_states(out[0], o.state(), spec.box, 1e-10)
     assert not bad, errs
 

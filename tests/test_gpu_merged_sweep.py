@@ -56,6 +56,10 @@ def _cases():
         I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005,
                          kappa_e=I.w_per_mk_to_metal(80.0), n_sub=4, profile=1, depth=10.0),
         tn=(3, 3, 6)), "afm"
+    # the fcc production model (coloured by basis site, odd cell counts)
+    yield "fcc_production", replace(
+        I.gdfeco_fcc_spec(L=5, alpha=0.05, K=(2.0e-3, 1.0e-3, 0.0, 0.0)),
+        ttm_mode=2, step_T=(1100.0, 550.0, 300.0), step_end=(0.0042, 0.0097)), "afm"
 
 
 def _samples(sysobj, every):
@@ -64,7 +68,7 @@ def _samples(sysobj, every):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("case", ["bcc_fixed_Te", "alloy_laser_live", "alloy_anisotropy",
-                                  "alloy_stepped_profile", "alloy_diffusing"])
+                                  "alloy_stepped_profile", "alloy_diffusing", "fcc_production"])
 def test_merged_sweep_equals_unmerged(N, case, prec):
     name, spec, init = next(c for c in _cases() if c[0] == case)
     st = I.initial_state(spec, init)
@@ -177,8 +181,11 @@ def test_batch_runs_merge_together(N, prec):
     b.set_tuning(persist_block=0)
     slots = [b.add(sp, st, t, obs_every=10) for sp, st, t in zip(specs, states, targets)]
     b.advance(23)
-    avg, cnt = b.advance_profiled(27)      # 7 single steps, then two chunks of 10
-    assert cnt[0] == 7 * 2 + 2 * 11, cnt
+    # a shorter merged chunk of 7 steps up to step 30, then two chunks of 10:
+    # one colour pass without the kick per step, plus the last step's
+    # closing pass in each chunk
+    avg, cnt = b.advance_profiled(27)
+    assert cnt[0] == (7 + 1) + 2 * 11, cnt
     for sp, st, t, s in zip(specs, states, targets, slots):
         g = b.get(s)
         ref = N.System(sp, st, precision=prec, obs_every=1)

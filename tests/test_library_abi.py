@@ -77,6 +77,7 @@ int main(void) {
   P(sl_tuning, graph_steps) P(sl_tuning, persist_block) P(sl_tuning, xcd_order) P(sl_tuning, bin_mode) P(sl_tuning, atom_lanes) P(sl_tuning, merge_sweeps)
   printf("sl_run_stats size %zu\n", sizeof(sl_run_stats));
   P(sl_run_stats, list_rebuilds) P(sl_run_stats, max_list) P(sl_run_stats, list_capacity)
+  P(sl_run_stats, list_rescans) P(sl_run_stats, error)
   printf("sl_run_info size %zu\n", sizeof(sl_run_info));
   P(sl_run_info, steps_done) P(sl_run_info, n_samples)
   return 0;
@@ -119,11 +120,15 @@ int main() {
     if (sl::fdiv(top, f) != top / d) { printf("FAIL div top %u\n", d); return 1; }
   }
   // site numbering: internal <-> (x, y, z, b) is a bijection and colours are proper
-  int dims[][4] = {{2, 2, 2, 1}, {4, 6, 2, 1}, {6, 6, 6, 2}, {8, 4, 10, 2}, {2, 2, 2, 2}};
+  int dims[][4] = {{2, 2, 2, 1}, {4, 6, 2, 1}, {6, 6, 6, 2}, {8, 4, 10, 2}, {2, 2, 2, 2},
+                   {2, 2, 2, 4}, {3, 5, 4, 4}, {13, 13, 13, 4}};
   for (auto& dm : dims) {
     sl::Geom g;
     g.Lx = dm[0]; g.Ly = dm[1]; g.Lz = dm[2]; g.nb = dm[3];
-    g.Lxh = g.Lx / 2; g.H = g.Lx * g.Ly * g.Lz / 2; g.C = 2 * g.nb;
+    g.par = g.nb == 4 ? 0 : 1;
+    g.Lxh = g.par ? g.Lx / 2 : g.Lx;
+    g.H = g.par ? g.Lx * g.Ly * g.Lz / 2 : g.Lx * g.Ly * g.Lz;
+    g.C = g.nb == 4 ? 4 : 2 * g.nb;
     g.divH = sl::make_fastdiv(g.H); g.divLxh = sl::make_fastdiv(g.Lxh);
     g.divLy = sl::make_fastdiv(g.Ly);
     int n = g.nb * g.Lx * g.Ly * g.Lz;
@@ -135,7 +140,8 @@ int main() {
       if (c < 0 || c >= n || seen[c]) { printf("FAIL canon %d\n", i); return 1; }
       seen[c] = 1;
       int par = (s.x + s.y + s.z) & 1;
-      if (s.k != (g.nb == 2 ? 2 * s.b + par : par)) { printf("FAIL colour %d\n", i); return 1; }
+      int want = g.nb == 4 ? s.b : (g.nb == 2 ? 2 * s.b + par : par);
+      if (s.k != want || s.x >= g.Lx || s.y >= g.Ly || s.z >= g.Lz) { printf("FAIL colour %d\n", i); return 1; }
     }
     free(seen);
   }
