@@ -184,6 +184,22 @@ sl_status sl_set_ttm_grid(sl_system h, const sl_ttm_desc* ttm);
  * a HIP graph of the steps. */
 sl_status sl_step(sl_system h, int64_t n_steps);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation: enqueues
+ * n_steps timesteps exactly as sl_step does (the same kernels in the same
+ * order, so the same results bit for bit), but allocates and frees nothing.
+ * The launch tables are written, by a kernel on the run's stream, into a
+ * static device buffer of SL_NOALLOC_SCRATCH_BYTES that every GPU the
+ * library runs on holds until the process ends, and every step is launched
+ * directly instead of through a HIP graph.  SL_EINVAL, with nothing
+ * enqueued, when the system's tables exceed the buffer (about half a million
+ * thread blocks: a few 10^7 sites) or for n_steps < 0.  Every call on a GPU
+ * rewrites that GPU's one buffer, so calls whose work overlaps on one GPU
+ * (systems stepped on different streams, other host threads) race: the
+ * caller serialises them, e.g. on one stream.  Asynchronous like sl_step. */
+#define SL_NOALLOC_SCRATCH_BYTES (4u << 20)
+sl_status sl_step_noalloc(sl_system h, int64_t n_steps);
+
 /* Waits for the run's stream.  SL_ENUMERIC if the run hit a numerical error. */
 sl_status sl_synchronize(sl_system h);
 

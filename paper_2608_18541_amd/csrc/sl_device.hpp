@@ -318,7 +318,42 @@ __host__ __device__ inline int32_t wrapi(int32_t v, int32_t L)
     return v < 0 ? v + L : (v >= L ? v - L : v);
 }
 
-// XCDs of the accelerator: workgroup b runs on XCD b mod 8
+// -------------------------------------------------------- launch tables
+// A single run's launch tables are arithmetic: entry q of a table is (run,
+// q * tile), or, ordered for the XCDs (block b runs on XCD b mod 8), the
+// entries of the m tiles dealt so that XCD x receives the contiguous range
+// x * per .. x * per + per - 1 (per = ceil(m / 8)) in order: with a = the
+// number of full ranges and r the length of the partial one, output q takes
+// tile x * per + j where (j, x) enumerates j = 0, 1, ... with x over the
+// ranges still holding a tile at j.  Tables shorter than 16 keep their order.
 constexpr int kXcdCount = 8;
+
+struct TableFill {
+    int32_t off[6], m[6], tile[6], xcd[6];   // six int2 tables, offsets in entries
+    int32_t n_int2;                           // entries of the six tables together
+    int32_t slot;                             // the run
+    int32_t rl_n, pl_n;                       // run list and persistent list (0 or 1 each)
+};
+
+__host__ __device__ inline int2 fill_entry(const TableFill& f, int k, int32_t q, int32_t slot)
+{
+    const int32_t m = f.m[k];
+    int32_t src = q;
+    if (f.xcd[k] && m >= 2 * kXcdCount) {
+        const int32_t per = (m + kXcdCount - 1) / kXcdCount;
+        const int32_t a = m / per, r = m - a * per;
+        int32_t j, x;
+        if (q < r * (a + 1)) {
+            j = q / (a + 1);
+            x = q - j * (a + 1);
+        } else {
+            const int32_t q2 = q - r * (a + 1);
+            j = r + q2 / a;
+            x = q2 - (q2 / a) * a;
+        }
+        src = x * per + j;
+    }
+    return make_int2(slot, src * f.tile[k]);
+}
 
 }  // namespace sl

@@ -1921,6 +1921,33 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict
     end_step(runs[run_list[blockIdx.x]], S, phase, deferred, fold_k);
 }
 
+// ======================================================= launch tables
+// Writes a single run's launch tables into `base` (then the run list and
+// the persistent list, one int each, at `ints`).
+__global__ __launch_bounds__(kBlock) void k_fill_tables(int2* __restrict__ base, int* __restrict__ ints,
+                                                        TableFill f)
+{
+    for (int32_t e = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); e < f.n_int2;
+         e += (int32_t)(gridDim.x * blockDim.x)) {
+        int k = 0;
+        while (k < 5 && e >= f.off[k] + f.m[k]) ++k;
+        base[e] = fill_entry(f, k, e - f.off[k], f.slot);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ints[0] = f.rl_n > 0 ? f.slot : 0;
+        ints[1] = f.pl_n > 0 ? f.slot : 0;
+    }
+}
+
+// The per-run launch flags of a run's device descriptor (kick binning,
+// normals drawn by the kick), written without a host copy.
+template <typename T>
+__global__ void k_set_run_flags(RunDev<T>* runs, int slot, int32_t bin_step, int32_t eta_drawn)
+{
+    runs[slot].bin_step = bin_step;
+    runs[slot].eta_drawn = eta_drawn;
+}
+
 // ==================================================== persistent kernel
 // One block advances one run by up to `nsteps` steps in a single launch.
 // Spins, species, electron-cell ids, the electron grid, the per-cell

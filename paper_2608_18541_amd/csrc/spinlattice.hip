@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -331,6 +332,7 @@ public:
     virtual sl_status add(const sl_system_desc* d, const sl_ttm_desc* t, int64_t target, int* slot) = 0;
     virtual sl_status set_grid(int slot, const sl_ttm_desc* t) = 0;
     virtual sl_status advance(int64_t n) = 0;
+    virtual sl_status advance_noalloc(int64_t n, char* scratch, size_t cap) = 0;
     virtual sl_status get(int slot, double* x, double* v, double* s, double* Te, sl_obs* obs,
                           int64_t max_samples, int64_t* n_obs) = 0;
     virtual sl_status set_state(int slot, const double* x, const double* v, const double* s,
@@ -367,6 +369,7 @@ public:
 template <typename T> class EngineT final : public Engine {
 public:
     using RD = sl::RunDev<T>;
+    using T_ = T;
 
     EngineT(int max_runs) { runs.resize(max_runs); host_rd.resize(max_runs); }
 
@@ -499,6 +502,88 @@ public:
             if (st != SL_OK) return st;
         }
         return advance_core(n, true);
+    }
+
+    // As advance(), with the launch tables in `scratch` (cap bytes of device
+    // memory the engine does not own) and every step launched directly: no
+    // device memory is allocated or freed and no graph is instantiated.  The
+    // tables are written by a kernel from their closed form (a single run's
+    // tables are arithmetic sequences, XCD-ordered or not), so the call holds
+    // no host buffer that a captured graph would have to keep.  The engine's
+    // own tables and graph, if any, are left as they were.
+    sl_status advance_noalloc(int64_t n, char* scratch, size_t cap) override
+    {
+        if (n < 0) return fail(SL_EINVAL, "negative step count");
+        Tables tb;
+        std::vector<int> changed;
+        plan_tables(tb, changed);
+        sl::TableFill f{};
+        const std::vector<int2>* tabs[6] = {&tb.ws, &tb.wa, &tb.wk, &tb.wc, &tb.wd, &tb.wt};
+        const int xcd[6] = {xcd_ord, xcd_ord, xcd_ord, 0, 0, 0};
+        // items per block of each table (the diffusion tiles are numbered)
+        const int tiles[6] = {spin_eff * spin_spt, atom_block / lanes_eff, spin_eff, sl::kBlock,
+                              sl::kBlock, 1};
+        size_t off = 0;
+        for (int k = 0; k < 6; ++k) {
+            const std::vector<int2>& t = *tabs[k];
+            f.off[k] = (int32_t)off;
+            f.m[k] = (int32_t)t.size();
+            f.xcd[k] = xcd[k];
+            f.tile[k] = tiles[k];
+            for (size_t q = 0; q < t.size(); ++q) {
+                const int2 e = sl::fill_entry(f, k, (int32_t)q, t[q].x);
+                if (e.x != t[q].x || e.y != t[q].y || (q > 0 && t[q].x != t[0].x))
+                    return fail(SL_EINVAL, "sl_step_noalloc: only a single system's tables are built "
+                                           "without allocation");
+            }
+            off += t.size();
+        }
+        f.slot = tb.rl.empty() ? (tb.pl.empty() ? 0 : tb.pl[0]) : tb.rl[0];
+        f.n_int2 = (int32_t)off;
+        if (tb.rl.size() > 1 || tb.pl.size() > 1)
+            return fail(SL_EINVAL, "sl_step_noalloc: only a single system's tables are built "
+                                   "without allocation");
+        f.rl_n = (int32_t)tb.rl.size();
+        f.pl_n = (int32_t)tb.pl.size();
+        const size_t bytes = off * sizeof(int2) + 2 * sizeof(int);
+        if (bytes > cap)
+            return fail(SL_EINVAL, "sl_step_noalloc: the system's launch tables take " +
+                                       std::to_string(bytes) + " bytes, more than the " +
+                                       std::to_string(cap) + "-byte static buffer");
+        if (n == 0) return SL_OK;
+        int2* base = reinterpret_cast<int2*>(scratch);
+        int* ints = reinterpret_cast<int*>(base + off);
+        for (int s : changed)
+            sl::k_set_run_flags<T_><<<1, 1, 0, stream>>>(d_runs, s, host_rd[s].bin_step,
+                                                          host_rd[s].eta_drawn);
+        const int fill_blocks = (int)std::min<size_t>((off + 2 + 255) / 256, 1024);
+        sl::k_fill_tables<<<fill_blocks, 256, 0, stream>>>(base, ints, f);
+        SL_HIP(hipGetLastError());
+        // the launches below read the tables from the scratch buffer
+        int2* keep_w[6] = {d_work_spin, d_work_atom, d_work_kick, d_work_cell, d_work_diff, d_work_tile};
+        int* keep_rl = d_run_list;
+        int* keep_pl = d_persist_list;
+        const bool keep_graph = graph_ok;
+        d_work_spin = base + f.off[0];
+        d_work_atom = base + f.off[1];
+        d_work_kick = base + f.off[2];
+        d_work_cell = base + f.off[3];
+        d_work_diff = base + f.off[4];
+        d_work_tile = base + f.off[5];
+        d_run_list = ints;
+        d_persist_list = ints + 1;
+        graph_ok = false;
+        const sl_status st = advance_core(n, false);
+        d_work_spin = keep_w[0];
+        d_work_atom = keep_w[1];
+        d_work_kick = keep_w[2];
+        d_work_cell = keep_w[3];
+        d_work_diff = keep_w[4];
+        d_work_tile = keep_w[5];
+        d_run_list = keep_rl;
+        d_persist_list = keep_pl;
+        graph_ok = keep_graph;
+        return st;
     }
 
     // The steps themselves, the tables being in place; with_graph: replay the
@@ -1657,6 +1742,40 @@ sl_status setup_engine(Engine* e, int precision, void* stream, const sl_allocato
 
 }  // namespace
 
+// ======================================================= static scratch
+// The device buffer of sl_step_noalloc: the launch tables of a system
+// stepped without allocation.  Every GPU the library runs on holds its own
+// copy for the life of the process.  In host code `scratch` names a host-side
+// stand-in, not device memory: the buffer's device address is taken once per
+// device with hipGetSymbolAddress and only that address is used.
+static __device__ __align__(256) unsigned char scratch[SL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch buffer (looked up on the
+// first call on that device).
+sl_status scratch_address(char** out)
+{
+    int dev = 0;
+    SL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SL_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        SL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SL_EHIP, "hipGetSymbolAddress returned no address for the scratch buffer");
+        g_scratch_dev[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SL_OK;
+}
+
+}  // namespace
+
 // ==================================================================== C ABI
 struct sl_system_s {
     std::unique_ptr<Engine> eng;
@@ -1709,6 +1828,15 @@ sl_status sl_step(sl_system h, int64_t n_steps)
 {
     if (!h) return fail(SL_EINVAL, "null handle");
     return h->eng->advance(n_steps);
+}
+
+sl_status sl_step_noalloc(sl_system h, int64_t n_steps)
+{
+    if (!h) return fail(SL_EINVAL, "null handle");
+    char* p = nullptr;
+    sl_status st = scratch_address(&p);
+    if (st != SL_OK) return st;
+    return h->eng->advance_noalloc(n_steps, p, SL_NOALLOC_SCRATCH_BYTES);
 }
 
 sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5])

@@ -110,6 +110,7 @@ EXPORTS = {
     "sl_init_system": (C.c_int32, [C.POINTER(sl_system_desc), C.POINTER(C.c_void_p)]),
     "sl_set_ttm_grid": (C.c_int32, [C.c_void_p, C.POINTER(sl_ttm_desc)]),
     "sl_step": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "sl_step_noalloc": (C.c_int32, [C.c_void_p, C.c_int64]),
     "sl_synchronize": (C.c_int32, [C.c_void_p]),
     "sl_observables": (C.c_int32, [C.c_void_p, C.POINTER(sl_obs), C.c_int64,
                                    C.POINTER(C.c_int64)]),
@@ -329,6 +330,10 @@ class System:
 
     def step(self, n: int = 1) -> None:
         check(lib().sl_step(self._h, int(n)))
+
+    def step_noalloc(self, n: int = 1) -> None:
+        """As step, through the allocation-free entry point."""
+        check(lib().sl_step_noalloc(self._h, int(n)))
 
     def synchronize(self) -> None:
         check(lib().sl_synchronize(self._h))

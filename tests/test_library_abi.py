@@ -145,6 +145,32 @@ int main() {
     }
     free(seen);
   }
+  // launch tables: the closed-form entries of a single run's tables equal the
+  // explicit deal of the tiles over the 8 XCDs (the order the multi-run
+  // tables are built in), natural order below 16 tiles
+  for (int m = 1; m < 3000; m += (m < 200 ? 1 : 7)) {
+    sl::TableFill f{};
+    f.m[2] = m; f.tile[2] = 3; f.xcd[2] = 1;
+    int* deal = (int*)malloc(sizeof(int) * m);
+    int k = 0;
+    if (m < 16) {
+      for (int q = 0; q < m; ++q) deal[k++] = q;
+    } else {
+      int per = (m + 7) / 8;
+      for (int j = 0; j < per; ++j)
+        for (int x = 0; x < 8; ++x)
+          if (x * per + j < m) deal[k++] = x * per + j;
+    }
+    if (k != m) { printf("FAIL deal count %d\n", m); return 1; }
+    for (int q = 0; q < m; ++q) {
+      int2 e = sl::fill_entry(f, 2, q, 5);
+      if (e.x != 5 || e.y != 3 * deal[q]) { printf("FAIL table %d %d\n", m, q); return 1; }
+    }
+    f.xcd[2] = 0;
+    for (int q = 0; q < m; ++q)
+      if (sl::fill_entry(f, 2, q, 5).y != 3 * q) { printf("FAIL natural %d\n", m); return 1; }
+    free(deal);
+  }
   // Philox words for a few counters (compared with the oracle by the test)
   unsigned v[6];
   while (scanf("%u %u %u %u %u %u", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6) {
