@@ -341,16 +341,19 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
 
 
 
-def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int = 2000) -> dict:
+def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int = 2000,
+                             lattice: str = "fcc", L: int = 13) -> dict:
     """The production phase diagram: 8 peak T_e (800-2900 K) x 8 cooling
-    multipliers (d = 1-8) x seeds, 16^3 sc alloy runs on a frozen lattice
-    with the literature anisotropy, alpha 0.01, B = 0 and the stepped T_e
-    profile, in one FP32 batch; switching probabilities per cell and the
-    rate of one run on the plain FP64 path."""
-    from paper_2608_18541_amd import analysis as A
+    multipliers (d = 1-8) x seeds of the paper's production model (fcc
+    13^3, 8788 sites, exactly 2197 Gd, the literature exchange, moments and
+    anisotropy, alpha 0.01, B = 0, frozen lattice, the stepped T_e profile),
+    in one FP32 batch; switching probabilities per cell and the rate of one
+    run on the plain FP64 path."""
     from paper_2608_18541_amd.stats import switched, wilson_ci
     base_ends = (0.1, 0.5)
-    runs = W.production_diagram(L=16, n_seeds=n_seeds, n_steps=n_steps, base_ends=base_ends)
+    runs = W.production_diagram(L=L, n_seeds=n_seeds, n_steps=n_steps, base_ends=base_ends,
+                                lattice=lattice)
+    n_sites = runs[0].spec.n_sites
     b = N.Batch(precision=N.SL_FP32, max_runs=len(runs))
     slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
              for r in runs]
@@ -383,27 +386,26 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int 
     t_plain = plain_step_time(N, runs[0], plain_steps)
     plain_rps = 1.0 / (t_plain * n_steps)
     res = {
-        "workload": "Gd25(FeCo)75 sc 16^3 frozen lattice, K %.4g eV, alpha 0.01, B = 0, stepped "
-                    "T_e (T0, T0/2, 300 K; stage ends d x %g, d x %g ps) x (8 T0 800-2900 K) x "
-                    "(8 d 1-8) x %d seeds = %d runs, %d steps"
-                    % (runs[0].spec.K[0], base_ends[0], base_ends[1], n_seeds, len(runs), n_steps),
+        "workload": "Gd25(FeCo)75 %s %d^3 (%d sites, %d Gd), frozen lattice, K %.4g eV, alpha 0.01, "
+                    "B = 0, stepped T_e (T0, T0/2, 300 K; stage ends d x %g, d x %g ps) x (8 T0 "
+                    "800-2900 K) x (8 d 1-8) x %d seeds = %d runs, %d steps"
+                    % (lattice, L, n_sites, int(runs[0].state.species.sum()), runs[0].spec.K[0],
+                       base_ends[0], base_ends[1], n_seeds, len(runs), n_steps),
         "seconds": round(el, 3), "runs_per_s": round(len(runs) / el, 3),
-        "atom_steps_per_s": len(runs) * 4096 * n_steps / el, "failed_runs": failed,
+        "atom_steps_per_s": len(runs) * n_sites * n_steps / el, "failed_runs": failed,
         "plain_fp64_runs_per_s": round(plain_rps, 4),
         "plain_us_per_step": round(t_plain * 1e6, 2),
         "speedup_vs_plain": round(len(runs) / el / plain_rps, 1),
         "P": np.round(k / n_seeds, 3).tolist(),
         "P_rows_T0_cols_d_note": "rows T0 = 800, 1100, ..., 2900 K; columns d = 1, ..., 8",
-        "d_c_per_T0": [A.critical_cooling_duration(range(1, 9), row) for row in k / n_seeds],
-        "d_c_note": "smallest d from which P >= 0.5 for every larger d; null: none up to d = 8",
         "wilson_halfwidth_max": float(max(h - l for l, h in ci) / 2),
         "stage_note": "the paper gives the stage temperatures and that d scales the durations, "
                       "not the base durations: %g ps and %g ps here" % base_ends,
     }
     # the batch is bound by VALU issue: 256 CUs x 2.4 GHz, one wave64
     # instruction per CU per cycle (four SIMDs, four cycles each)
-    valu = measured_valu_per_site_step()
-    rate = len(runs) * 4096 * n_steps / el
+    valu = measured_valu_per_site_step("production%d%s_fp32" % (L, lattice))
+    rate = len(runs) * n_sites * n_steps / el
     peak = 256 * 2.4e9
     res["alu_roofline"] = None if valu is None else {
         "bound": "alu", "achieved": rate * valu, "peak": peak,
@@ -414,15 +416,14 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int 
     return res
 
 
-def field_dependence(N, W, n_steps: int, n_seeds: int, T0: float = 2900.0, d: float = 7.0) -> dict:
-    """Switching probability of the production runs at one condition under
-    0, 0.5 T and 10 T (+z, opposing the reversal), one FP32 batch, with
-    Wilson intervals.  The condition is the one where this model switches
-    most often in the production grid, not the paper's 1100 K, d = 6, where
-    it does not switch."""
+def field_dependence(N, W, n_steps: int, n_seeds: int, T0: float = 1100.0, d: float = 6.0,
+                     lattice: str = "fcc", L: int = 13) -> dict:
+    """Switching probability of the production runs at one condition (the
+    paper's headline T0 = 1100 K, d = 6 by default) under 0, 0.5 T and 10 T
+    (+z, opposing the reversal), one FP32 batch, with Wilson intervals."""
     from paper_2608_18541_amd.stats import switched, wilson_ci
     fields = (0.0, 0.5, 10.0)
-    runs = W.field_runs(T0, d, n_seeds, n_steps=n_steps, fields=fields)
+    runs = W.field_runs(T0, d, n_seeds, L=L, n_steps=n_steps, fields=fields, lattice=lattice)
     b = N.Batch(precision=N.SL_FP32, max_runs=len(runs))
     slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
              for r in runs]
@@ -445,9 +446,9 @@ def field_dependence(N, W, n_steps: int, n_seeds: int, T0: float = 2900.0, d: fl
         lo, hi = wilson_ci(k, n_seeds)
         rows.append({"B_T": B, "switched": k, "n": n_seeds, "P": round(k / n_seeds, 3),
                      "wilson95": [round(lo, 3), round(hi, 3)]})
-    return {"workload": "production runs (16^3 sc, frozen, K, alpha 0.01, stepped T_e) at T0 = %g K, "
+    return {"workload": "production runs (%s %d^3, frozen, K, alpha 0.01, stepped T_e) at T0 = %g K, "
                         "d = %g, B along +z (opposing the reversal) x %d seeds per field, %d steps"
-                        % (T0, d, n_seeds, n_steps),
+                        % (lattice, L, T0, d, n_seeds, n_steps),
             "seconds": round(el, 3), "fields": rows}
 
 def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
@@ -653,7 +654,11 @@ def main() -> int:
     ap.add_argument("--pd-seeds", type=int, default=20)
     ap.add_argument("--prod-steps", type=int, default=50000)
     ap.add_argument("--prod-seeds", type=int, default=20)
+    ap.add_argument("--prod-lattice", default="fcc", help="lattice of the production rows (fcc, sc)")
+    ap.add_argument("--prod-L", type=int, default=13, help="cells per side of the production runs")
     ap.add_argument("--field-seeds", type=int, default=100)
+    ap.add_argument("--field-T0", type=float, default=1100.0)
+    ap.add_argument("--field-d", type=float, default=6.0)
     ap.add_argument("--prod-plain-steps", type=int, default=2000,
                     help="steps of the plain-path timing of one production run")
     ap.add_argument("--serve-requests", type=int, default=600)
@@ -761,9 +766,12 @@ def main() -> int:
         out["batched"] = batched_phase_diagram(N, W, args.pd_steps, args.pd_seeds)
     if "production" in extras:
         out["production"] = production_phase_diagram(N, W, args.prod_steps, args.prod_seeds,
-                                                     args.prod_plain_steps)
+                                                     args.prod_plain_steps, args.prod_lattice,
+                                                     args.prod_L)
     if "field" in extras:
-        out["field_dependence"] = field_dependence(N, W, args.prod_steps, args.field_seeds)
+        out["field_dependence"] = field_dependence(N, W, args.prod_steps, args.field_seeds,
+                                                   args.field_T0, args.field_d, args.prod_lattice,
+                                                   args.prod_L)
     if "serving" in extras:
         out["serving"] = serving(N, W, S, args.serve_requests, args.serve_steps_scale)
     if "large" in extras:

@@ -117,7 +117,7 @@ def production_diagram(L: int = 16, n_temp: int = 8, n_d: int = 8, n_seeds: int 
 
 
 def field_runs(T0: float, d: float, n_seeds: int, L: int = 16, n_steps: int = 50000,
-               seed: int = 2028, fields=(0.0, 0.5, 10.0)) -> List[RunSpec]:
+               seed: int = 2028, fields=(0.0, 0.5, 10.0), lattice: str = "sc") -> List[RunSpec]:
     """Production runs at (T0, d) under each field magnitude, seeds
     innermost.  The field points along +z: the Gd sublattice and the net
     moment start along +z and reverse to -z, so +z opposes the reversal
@@ -126,7 +126,7 @@ def field_runs(T0: float, d: float, n_seeds: int, L: int = 16, n_steps: int = 50
     rid = 0
     for B in fields:
         for s in range(n_seeds):
-            r = production_run(L, T0, d, seed, rid, n_steps)
+            r = production_run(L, T0, d, seed, rid, n_steps, lattice=lattice)
             r.spec = replace(r.spec, B=(0.0, 0.0, float(B)))
             r.tag = (T0, d, B)
             out.append(r)
