@@ -118,6 +118,17 @@ typedef struct sl_system_desc {
     const double* disp0;      /* [n][3] displacement from the ideal site, A, or NULL */
     void* stream;             /* hipStream_t to run on, or NULL (library stream)  */
     const sl_allocator* alloc;/* or NULL (hipMalloc)                              */
+    /* Radial exchange (Methods A; the re-derivation of the radial exchange
+     * function), live lattices only.  0: J[k] are the bonds' constants.  1:
+     * J[k][a][b] is the amplitude J1 of J(r) = 4 J1 x (1 - J2 x) e^{-x},
+     * x = (r / J3)^2, evaluated at a bond's current (minimum-image) length,
+     * and the bond exerts the force -dJ/dr (s_i . s_j) on its two atoms.  The
+     * bonds stay those of the ideal lattice's shells (the radial function
+     * sets their strength).  A step then applies the first half kick (pair
+     * and exchange forces at the old positions with the swept spins) after
+     * the whole colour sweep; such runs do not merge colour sweeps. */
+    int32_t exch_radial;      /* 0 or 1                                           */
+    double exch_r[2][2];      /* per shell: J2 (dimensionless), J3 (A, > 0)       */
 } sl_system_desc;
 
 /* Electron-temperature grid over the periodic box, cell (i,j,k) at index

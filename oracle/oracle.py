@@ -62,6 +62,8 @@ class OrDesc(C.Structure):
         ("t0", C.c_double), ("fwhm", C.c_double), ("profile", C.c_int32),
         ("depth", C.c_double), ("K_s", C.POINTER(C.c_double)),
         ("step_T", C.c_double * 3), ("step_end", C.c_double * 2),
+        ("exch_radial", C.c_int32), ("exch_r", (C.c_double * 2) * 2),
+        ("nbr_sh", C.POINTER(C.c_int32)),
     ]
 
 
@@ -108,6 +110,8 @@ def lib():
                                   C.POINTER(C.c_double)]
         L.or_llg_exact_flow.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.c_double, C.c_double]
+        L.or_get_exchange_forces.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.or_set_positions.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.or_pair_forces.restype = C.c_double
         L.or_pair_forces.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]
@@ -271,6 +275,7 @@ class Oracle:
         k["nbr_off"] = np.ascontiguousarray(t.nbr_off, dtype=np.int32)
         k["nbr_j"] = np.ascontiguousarray(t.nbr_j, dtype=np.int32)
         k["nbr_J"] = np.ascontiguousarray(nbr_J, dtype=np.float64)
+        k["nbr_sh"] = np.ascontiguousarray(t.nbr_shell, dtype=np.int32)
         x0 = np.array(t.pos, dtype=np.float64)
         if disp is not None:
             x0 = x0 + np.asarray(disp, dtype=np.float64).reshape(n, 3)
@@ -301,6 +306,12 @@ class Oracle:
         d.nbr_off = _p(k["nbr_off"], C.c_int32)
         d.nbr_j = _p(k["nbr_j"], C.c_int32)
         d.nbr_J = _p(k["nbr_J"], C.c_double)
+        d.nbr_sh = _p(k["nbr_sh"], C.c_int32)
+        d.exch_radial = int(getattr(spec, "exch_radial", 0))
+        er = getattr(spec, "exch_r", ((0.0, 0.0), (0.0, 0.0)))
+        for sh in range(2):
+            for q in range(2):
+                d.exch_r[sh][q] = float(er[sh][q])
         d.x0 = _p(k["x0"], C.c_double)
         d.v0 = _p(k["v0"], C.c_double)
         d.s0 = _p(k["s0"], C.c_double)
@@ -354,6 +365,15 @@ class Oracle:
         lib().or_get_state(self._h, _p(x, C.c_double), _p(v, C.c_double), _p(s, C.c_double),
                            _p(F, C.c_double), _p(Te, C.c_double))
         return {"x": x, "v": v, "s": s, "F": F, "Te": Te}
+
+    def exchange_forces(self) -> np.ndarray:
+        F = np.zeros((self.n, 3))
+        lib().or_get_exchange_forces(self._h, _p(F, C.c_double))
+        return F
+
+    def set_positions(self, x) -> None:
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(self.n, 3))
+        lib().or_set_positions(self._h, _p(a, C.c_double))
 
     def set_spins(self, s) -> None:
         a = np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(self.n, 3))

@@ -133,6 +133,11 @@ typedef struct {
                                 (energy -K s_z^2), or NULL for none           */
     double step_T[3];        /* ttm_mode 2: stage temperatures, K              */
     double step_end[2];      /* ttm_mode 2: ends of stages 1 and 2, ps         */
+    int32_t exch_radial;     /* 1: nbr_J holds amplitudes J1 of the radial
+                                exchange J(r) = 4 J1 x (1 - J2 x) e^{-x},
+                                x = (r / J3)^2, at the bond's current length  */
+    double exch_r[2][2];     /* per shell: J2, J3 (Angstrom)                   */
+    const int32_t* nbr_sh;   /* [nnz] shell of each neighbour entry (or NULL)  */
 } or_desc;
 
 typedef struct {
@@ -152,7 +157,7 @@ typedef struct {
     double *s, *x, *v, *F;   /* [n][3]                                         */
     double *mu, *mass;       /* [n]                                            */
     double* K;               /* [n] anisotropy constant, eV                    */
-    int32_t *colour, *ctr_id, *species, *nbr_off, *nbr_j;
+    int32_t *colour, *ctr_id, *species, *nbr_off, *nbr_j, *nbr_sh;
     double* nbr_J;
     double *Te, *dE;         /* [ncell]                                        */
     int64_t step;
@@ -328,14 +333,65 @@ static double or_potential_energy(const or_system* S)
 
 /* ------------------------------------------------------------- spin update */
 
+/* Radial exchange function of a bond of shell sh at distance r (Methods A;
+ * the re-derivation of the radial exchange function):
+ * J(r) = 4 J1 x (1 - J2 x) exp(-x), x = (r / J3)^2, and its derivative
+ * dJ/dr = dJ/dx 2 r / J3^2 with dJ/dx = 4 J1 exp(-x) (1 - x - J2 x (2 - x)). */
+static double or_radial_J(const or_system* S, int32_t sh, double J1, double r)
+{
+    double J2 = S->d.exch_r[sh][0], J3 = S->d.exch_r[sh][1];
+    double x = (r / J3) * (r / J3);
+    return 4.0 * J1 * x * (1.0 - J2 * x) * exp(-x);
+}
+
+static double or_radial_dJdr(const or_system* S, int32_t sh, double J1, double r)
+{
+    double J2 = S->d.exch_r[sh][0], J3 = S->d.exch_r[sh][1];
+    double x = (r / J3) * (r / J3);
+    double dJdx = 4.0 * J1 * exp(-x) * (1.0 - x - J2 * x * (2.0 - x));
+    return dJdx * 2.0 * r / (J3 * J3);
+}
+
+/* Coupling of neighbour entry q of atom i: the constant, or the radial
+ * function at the pair's current minimum-image distance. */
+static double or_bond_J(const or_system* S, int32_t i, int32_t q)
+{
+    if (!S->d.exch_radial) return S->nbr_J[q];
+    double d[3];
+    or_min_image(&S->x[3 * i], &S->x[3 * S->nbr_j[q]], S->d.box, d);
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    return or_radial_J(S, S->nbr_sh[q], S->nbr_J[q], r);
+}
+
 /* Exchange field sum_j J_ij s_j (eV) from the current spins. */
 static void or_exchange_sum(const or_system* S, int32_t i, double h[3])
 {
     h[0] = h[1] = h[2] = 0.0;
     for (int32_t q = S->nbr_off[i]; q < S->nbr_off[i + 1]; ++q) {
         int32_t j = S->nbr_j[q];
-        for (int k = 0; k < 3; ++k) h[k] += S->nbr_J[q] * S->s[3 * j + k];
+        double J = or_bond_J(S, i, q);
+        for (int k = 0; k < 3; ++k) h[k] += J * S->s[3 * j + k];
     }
+}
+
+/* Exchange force on every atom (radial exchange only; zero otherwise):
+ * F_i = -grad_i of -sum_bonds J(r_ij) s_i.s_j = sum_j (s_i.s_j) dJ/dr (x_i - x_j)/r,
+ * each bond entered from both of its atoms. */
+static void or_exchange_forces(const or_system* S, double* F)
+{
+    memset(F, 0, sizeof(double) * 3 * S->n);
+    if (!S->d.exch_radial) return;
+    for (int32_t i = 0; i < S->n; ++i)
+        for (int32_t q = S->nbr_off[i]; q < S->nbr_off[i + 1]; ++q) {
+            int32_t j = S->nbr_j[q];
+            double d[3];
+            or_min_image(&S->x[3 * i], &S->x[3 * j], S->d.box, d);     /* x_j - x_i */
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double ss = S->s[3 * i] * S->s[3 * j] + S->s[3 * i + 1] * S->s[3 * j + 1] +
+                        S->s[3 * i + 2] * S->s[3 * j + 2];
+            double c = ss * or_radial_dJdr(S, S->nbr_sh[q], S->nbr_J[q], r) / r;
+            for (int k = 0; k < 3; ++k) F[3 * i + k] -= c * d[k];
+        }
 }
 
 /* Exact solution of Eq. (1) over a time tau for a precession vector omega
@@ -426,22 +482,28 @@ static void or_spin_step(or_system* S)
 
 /* ---------------------------------------------------------- lattice update */
 
-/* Velocity Verlet: half kick, drift (wrapped into the box), new forces,
- * half kick. */
+/* Velocity Verlet with the spins held at their values after the sweep:
+ * half kick, drift (wrapped into the box), new forces, half kick.  The force
+ * is the pair force plus, with radial exchange, the bonds' exchange force
+ * (S->F keeps the pair force of the current positions). */
 static void or_lattice_step(or_system* S)
 {
     int32_t n = S->n;
     double dt = S->d.dt;
+    double* Fe = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    or_exchange_forces(S, Fe);
     for (int32_t i = 0; i < n; ++i)
         for (int k = 0; k < 3; ++k)
-            S->v[3 * i + k] += 0.5 * dt * S->F[3 * i + k] / (S->mass[i] * OR_MVV2E);
+            S->v[3 * i + k] += 0.5 * dt * (S->F[3 * i + k] + Fe[3 * i + k]) / (S->mass[i] * OR_MVV2E);
     for (int32_t i = 0; i < n; ++i)
         for (int k = 0; k < 3; ++k)
             S->x[3 * i + k] = or_wrap(S->x[3 * i + k] + dt * S->v[3 * i + k], S->d.box[k]);
     or_compute_forces(S);
+    or_exchange_forces(S, Fe);
     for (int32_t i = 0; i < n; ++i)
         for (int k = 0; k < 3; ++k)
-            S->v[3 * i + k] += 0.5 * dt * S->F[3 * i + k] / (S->mass[i] * OR_MVV2E);
+            S->v[3 * i + k] += 0.5 * dt * (S->F[3 * i + k] + Fe[3 * i + k]) / (S->mass[i] * OR_MVV2E);
+    free(Fe);
 }
 
 /* Electron-phonon exchange as an exact Ornstein-Uhlenbeck step on the
@@ -563,6 +625,7 @@ or_system* or_create(const or_desc* d)
     int32_t nnz = S->nbr_off[n];
     S->nbr_j = (int32_t*)or_copy(d->nbr_j, sizeof(int32_t) * nnz);
     S->nbr_J = (double*)or_copy(d->nbr_J, sizeof(double) * nnz);
+    S->nbr_sh = (int32_t*)or_copy(d->nbr_sh, sizeof(int32_t) * nnz);
     S->mu = (double*)malloc(sizeof(double) * n);
     S->mass = (double*)malloc(sizeof(double) * n);
     S->K = (double*)malloc(sizeof(double) * n);
@@ -577,6 +640,7 @@ or_system* or_create(const or_desc* d)
     /* the description's pointers are not kept */
     S->d.colour = S->d.ctr_id = S->d.species = S->d.nbr_off = S->d.nbr_j = NULL;
     S->d.nbr_J = S->d.x0 = S->d.v0 = S->d.s0 = S->d.Te0 = NULL;
+    S->d.nbr_sh = NULL;
     S->d.mu_s = S->d.mass_s = NULL;
     if (d->lattice_live) or_compute_forces(S);
     return S;
@@ -587,7 +651,7 @@ void or_destroy(or_system* S)
     if (!S) return;
     free(S->s); free(S->x); free(S->v); free(S->F); free(S->mu); free(S->mass); free(S->K);
     free(S->colour); free(S->ctr_id); free(S->species); free(S->nbr_off); free(S->nbr_j);
-    free(S->nbr_J); free(S->Te); free(S->dE);
+    free(S->nbr_J); free(S->nbr_sh); free(S->Te); free(S->dE);
     free(S);
 }
 
@@ -627,6 +691,15 @@ void or_get_state(const or_system* S, double* x, double* v, double* s, double* F
 }
 
 void or_set_spins(or_system* S, const double* s) { memcpy(S->s, s, sizeof(double) * 3 * S->n); }
+
+/* Exchange forces of the current state ([n][3]; zero without radial exchange). */
+void or_get_exchange_forces(const or_system* S, double* F) { or_exchange_forces(S, F); }
+
+/* Replaces the positions (test hook: finite differences of the energy). */
+void or_set_positions(or_system* S, const double* x)
+{
+    for (int32_t i = 0; i < 3 * S->n; ++i) S->x[i] = or_wrap(x[i], S->d.box[i % 3]);
+}
 
 int64_t or_get_step(const or_system* S) { return S->step; }
 

@@ -142,6 +142,10 @@ template <typename T> struct RunDev {
     double Kd[4];                    // K, eV
     T kan[4];                        // its field per unit s_z, 2 K / (mu mu_B), T
     double stT[3], stEnd[2];         // stepped T_e profile (grid mode 2): K, ps
+    // radial exchange: J[shell] holds the amplitudes J1 of
+    // J(r) = J1 4 x (1 - J2 x) e^{-x}, x = (r / J3)^2, per shell
+    int32_t radial;
+    T rJ2[2], rinvJ3sq[2];           // J2 and 1 / J3^2 per shell
 };
 
 // ------------------------------------------------------- memory access
@@ -307,29 +311,31 @@ __device__ __forceinline__ Around around(const Geom& g, uint32_t x, uint32_t xh,
 //   their half shifts the neighbour lies half a constant either way (the
 //   same cell and the one below when b is not shifted there, the same cell
 //   and the one above when it is), on the third axis in the same cell.
-template <typename T, typename VW, int LAT, bool MULTI>
-__device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V, int k, const Around& a,
-                                                int sp)
+template <int LAT> struct Bonds {
+    static constexpr int NB = LAT == SL_LATTICE_SC ? 6 : (LAT == SL_LATTICE_FCC ? 12 : 14);
+    uint32_t col[NB], off[NB];   // neighbour q: colour block and offset inside it
+    int sh[NB];                  // its shell
+    int nn;                      // bonds in use (bcc: 8 with one shell)
+};
+
+template <int LAT, typename T>
+__device__ __forceinline__ Bonds<LAT> bond_list(const RunDev<T>& R, int k, const Around& a)
 {
-    using M = typename VW::Mem;
-    constexpr int NN = LAT == SL_LATTICE_SC ? 6 : (LAT == SL_LATTICE_FCC ? 12 : 14);
-    const uint32_t H = (uint32_t)R.g.H;
-    uint32_t col[NN], off[NN];
-    int sh[NN];
-    int nn;
+    constexpr int NN = Bonds<LAT>::NB;
+    Bonds<LAT> B;
     const int p = k & 1;
     if (LAT == SL_LATTICE_SC) {
-        nn = 6;
+        B.nn = 6;
         const uint32_t o[6] = {a.xm + a.y0 + a.z0, a.xp + a.y0 + a.z0, a.x0 + a.ym + a.z0,
                                a.x0 + a.yp + a.z0, a.x0 + a.y0 + a.zm, a.x0 + a.y0 + a.zp};
 #pragma unroll
         for (int q = 0; q < NN; ++q) {
-            col[q] = (uint32_t)(1 - p);
-            off[q] = o[q];
-            sh[q] = 0;
+            B.col[q] = (uint32_t)(1 - p);
+            B.off[q] = o[q];
+            B.sh[q] = 0;
         }
     } else if (LAT == SL_LATTICE_FCC) {
-        nn = 12;
+        B.nn = 12;
         const uint32_t hb = basis_half_bits(4, k);
         // per axis: [0] and [1] the two cells of a shifted axis, [2] the same cell
         const uint32_t X[3] = {(hb & 1u) ? a.x0 : a.xm, (hb & 1u) ? a.xp : a.x0, a.x0};
@@ -344,12 +350,12 @@ __device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V,
             const int sx = ax ? (u & 1) : 2;
             const int sy = ay ? (ax ? (u >> 1) & 1 : u & 1) : 2;
             const int sz = az ? (u >> 1) & 1 : 2;
-            col[q] = (uint32_t)bp;
-            off[q] = X[sx] + Y[sy] + Z[sz];
-            sh[q] = 0;
+            B.col[q] = (uint32_t)bp;
+            B.off[q] = X[sx] + Y[sy] + Z[sz];
+            B.sh[q] = 0;
         }
     } else {
-        nn = R.n_shells > 1 ? 14 : 8;
+        B.nn = R.n_shells > 1 ? 14 : 8;
         const int b = k >> 1;
         const uint32_t X[2] = {b == 0 ? a.xm : a.x0, b == 0 ? a.x0 : a.xp};
         const uint32_t Y[2] = {b == 0 ? a.ym : a.y0, b == 0 ? a.y0 : a.yp};
@@ -358,29 +364,73 @@ __device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V,
         for (int q = 0; q < 8; ++q) {
             const int mx = q & 1, my = (q >> 1) & 1, mz = q >> 2;
             // cell shift sum is mx+my+mz (b = 1) or that minus 3 (b = 0)
-            col[q] = (uint32_t)(2 * (1 - b) + ((p + mx + my + mz + (1 - b)) & 1));
-            off[q] = X[mx] + Y[my] + Z[mz];
-            sh[q] = 0;
+            B.col[q] = (uint32_t)(2 * (1 - b) + ((p + mx + my + mz + (1 - b)) & 1));
+            B.off[q] = X[mx] + Y[my] + Z[mz];
+            B.sh[q] = 0;
         }
         const uint32_t o2[6] = {a.xm + a.y0 + a.z0, a.xp + a.y0 + a.z0, a.x0 + a.ym + a.z0,
                                 a.x0 + a.yp + a.z0, a.x0 + a.y0 + a.zm, a.x0 + a.y0 + a.zp};
 #pragma unroll
         for (int q = 8; q < NN; ++q) {
-            col[q] = (uint32_t)(2 * b + (1 - p));
-            off[q] = o2[(q - 8) % 6];
-            sh[q] = 1;
+            B.col[q] = (uint32_t)(2 * b + (1 - p));
+            B.off[q] = o2[(q - 8) % 6];
+            B.sh[q] = 1;
         }
     }
+    return B;
+}
+
+// Radial exchange (Methods A and the re-derivation of the radial exchange
+// function): a bond's coupling is its amplitude J1 times
+// f(x) = 4 x (1 - J2 x) e^{-x}, x = (r / J3)^2, at the bond's current
+// minimum-image length r (J2, J3 per shell); (1/r) df/dr = 2 g(x) / J3^2 with
+// g(x) = df/dx = 4 e^{-x} (1 - x - J2 x (2 - x)).
+template <typename T> __device__ __forceinline__ T radial_f(const RunDev<T>& R, int sh, T r2)
+{
+    const T x = r2 * R.rinvJ3sq[sh];
+    return T(4) * x * (T(1) - R.rJ2[sh] * x) * expo(-x);
+}
+template <typename T> __device__ __forceinline__ T radial_dfr(const RunDev<T>& R, int sh, T r2)
+{
+    const T x = r2 * R.rinvJ3sq[sh];
+    const T g = T(4) * expo(-x) * (T(1) - x - R.rJ2[sh] * x * (T(2) - x));
+    return T(2) * R.rinvJ3sq[sh] * g;
+}
+
+template <typename T, typename VW>
+__device__ __forceinline__ V3<T> separation(const RunDev<T>& R, const VW& V, const Pos4<T>& pi,
+                                            uint32_t j);
+
+template <typename T, typename VW, int LAT, bool MULTI, bool RADIAL = false>
+__device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V, int k, const Around& a,
+                                                int sp)
+{
+    using M = typename VW::Mem;
+    constexpr int NN = Bonds<LAT>::NB;
+    const uint32_t H = (uint32_t)R.g.H;
+    const Bonds<LAT> B = bond_list<LAT>(R, k, a);
+    const int nn = B.nn;
     T ax[NN], ay[NN], az[NN];
     int sj[NN];
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
         if (q < nn) {
-            const uint32_t cb = col[q] * H;
-            ax[q] = M::ld(V.sx + cb, off[q]);
-            ay[q] = M::ld(V.sy + cb, off[q]);
-            az[q] = M::ld(V.sz + cb, off[q]);
-            sj[q] = MULTI ? (int)M::ld(V.species + cb, off[q]) : 0;
+            const uint32_t cb = B.col[q] * H;
+            ax[q] = M::ld(V.sx + cb, B.off[q]);
+            ay[q] = M::ld(V.sy + cb, B.off[q]);
+            az[q] = M::ld(V.sz + cb, B.off[q]);
+            sj[q] = MULTI ? (int)M::ld(V.species + cb, B.off[q]) : 0;
+        }
+    }
+    T fr[NN];
+    if constexpr (RADIAL) {
+        const Pos4<T> pi = VW::PosMem::ld(V.pos, (uint32_t)k * H + a.x0 + a.y0 + a.z0);
+#pragma unroll
+        for (int q = 0; q < NN; ++q) {
+            if (q < nn) {
+                const V3<T> d = separation(R, V, pi, B.col[q] * H + B.off[q]);
+                fr[q] = radial_f(R, B.sh[q], d.x * d.x + d.y * d.y + d.z * d.z);
+            }
         }
     }
     T row[2][4];
@@ -394,9 +444,10 @@ __device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V,
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
         if (q < nn) {
-            const T Jv = !MULTI ? row[sh[q]][0]
-                         : sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
-                                      : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
+            T Jv = !MULTI ? row[B.sh[q]][0]
+                   : B.sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
+                                  : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
+            if constexpr (RADIAL) Jv *= fr[q];
             h.x += Jv * ax[q];
             h.y += Jv * ay[q];
             h.z += Jv * az[q];
@@ -405,11 +456,54 @@ __device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V,
     return h;
 }
 
-// Dispatch on the run's lattice and species count (uniform per run).
+// The radial bonds' force on the atom at site (k, a) with spin s and wrapped
+// position pi: minus the gradient of -sum_j J(r_ij) s.s_j, i.e.
+// F = -sum_j (s . s_j) J1_ij (1/r) df/dr (x_j - x_i).
+template <typename T, typename VW, int LAT>
+__device__ __forceinline__ V3<T> exchange_force_t(const RunDev<T>& R, const VW& V, int k, const Around& a,
+                                                  int sp, const V3<T>& s, const Pos4<T>& pi)
+{
+    using M = typename VW::Mem;
+    constexpr int NN = Bonds<LAT>::NB;
+    const uint32_t H = (uint32_t)R.g.H;
+    const Bonds<LAT> B = bond_list<LAT>(R, k, a);
+    V3<T> F{T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+        if (q < B.nn) {
+            const uint32_t j = B.col[q] * H + B.off[q];
+            const T sx = M::ld(V.sx, j), sy = M::ld(V.sy, j), sz = M::ld(V.sz, j);
+            const int sj = (int)M::ld(V.species, j);
+            const V3<T> d = separation(R, V, pi, j);
+            const T J1 = B.sh[q] == 0 ? select4(sp, select4(sj, R.J[0][0][0], R.J[0][0][1], R.J[0][0][2], R.J[0][0][3]),
+                                                select4(sj, R.J[0][1][0], R.J[0][1][1], R.J[0][1][2], R.J[0][1][3]),
+                                                select4(sj, R.J[0][2][0], R.J[0][2][1], R.J[0][2][2], R.J[0][2][3]),
+                                                select4(sj, R.J[0][3][0], R.J[0][3][1], R.J[0][3][2], R.J[0][3][3]))
+                                      : select4(sp, select4(sj, R.J[1][0][0], R.J[1][0][1], R.J[1][0][2], R.J[1][0][3]),
+                                                select4(sj, R.J[1][1][0], R.J[1][1][1], R.J[1][1][2], R.J[1][1][3]),
+                                                select4(sj, R.J[1][2][0], R.J[1][2][1], R.J[1][2][2], R.J[1][2][3]),
+                                                select4(sj, R.J[1][3][0], R.J[1][3][1], R.J[1][3][2], R.J[1][3][3]));
+            const T c = (s.x * sx + s.y * sy + s.z * sz) * J1 *
+                        radial_dfr(R, B.sh[q], d.x * d.x + d.y * d.y + d.z * d.z);
+            F.x -= c * d.x;
+            F.y -= c * d.y;
+            F.z -= c * d.z;
+        }
+    }
+    return F;
+}
+
+// Dispatch on the run's lattice and species count (uniform per run); runs
+// with radial exchange take the species-resolved instantiation.
 template <typename T, typename VW>
 __device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, const VW& V, int k, const Around& a,
                                               int sp)
 {
+    if (R.radial) {
+        if (R.lattice == SL_LATTICE_SC) return exchange_sum_t<T, VW, SL_LATTICE_SC, true, true>(R, V, k, a, sp);
+        if (R.lattice == SL_LATTICE_FCC) return exchange_sum_t<T, VW, SL_LATTICE_FCC, true, true>(R, V, k, a, sp);
+        return exchange_sum_t<T, VW, SL_LATTICE_BCC, true, true>(R, V, k, a, sp);
+    }
     if (R.lattice == SL_LATTICE_SC)
         return R.n_species > 1 ? exchange_sum_t<T, VW, SL_LATTICE_SC, true>(R, V, k, a, sp)
                                : exchange_sum_t<T, VW, SL_LATTICE_SC, false>(R, V, k, a, sp);
@@ -418,6 +512,15 @@ __device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, const VW& V, i
                                : exchange_sum_t<T, VW, SL_LATTICE_FCC, false>(R, V, k, a, sp);
     return R.n_species > 1 ? exchange_sum_t<T, VW, SL_LATTICE_BCC, true>(R, V, k, a, sp)
                            : exchange_sum_t<T, VW, SL_LATTICE_BCC, false>(R, V, k, a, sp);
+}
+
+template <typename T, typename VW>
+__device__ __forceinline__ V3<T> exchange_force(const RunDev<T>& R, const VW& V, int k, const Around& a,
+                                                int sp, const V3<T>& s, const Pos4<T>& pi)
+{
+    if (R.lattice == SL_LATTICE_SC) return exchange_force_t<T, VW, SL_LATTICE_SC>(R, V, k, a, sp, s, pi);
+    if (R.lattice == SL_LATTICE_FCC) return exchange_force_t<T, VW, SL_LATTICE_FCC>(R, V, k, a, sp, s, pi);
+    return exchange_force_t<T, VW, SL_LATTICE_BCC>(R, V, k, a, sp, s, pi);
 }
 
 // sqrt of a cell temperature in the storage precision
@@ -617,7 +720,7 @@ __device__ inline double cell_energy(const RunDev<T>& R, double e0, unsigned lon
 template <typename T> __device__ inline double cell_e0(const RunDev<T>& R, double T0);
 __device__ inline double cell_temp(double e, double ge);
 
-template <typename T, typename VW, int LAT, bool MULTI, bool ANISO>
+template <typename T, typename VW, int LAT, bool MULTI, bool ANISO, bool RADIAL = false>
 __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int colour, T tau,
                                             uint32_t l, int64_t step, bool cur = true,
                                             bool has_prev = false, PrevHalf prev = {})
@@ -628,7 +731,7 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
     const uint32_t kH = (uint32_t)colour * (uint32_t)R.g.H;
     const uint32_t idx = kH + l;
     const int sp = MULTI ? (int)M::ld(V.species, idx) : 0;
-    const V3<T> h = exchange_sum_t<T, VW, LAT, MULTI>(R, V, colour, a, sp);
+    const V3<T> h = exchange_sum_t<T, VW, LAT, MULTI, RADIAL>(R, V, colour, a, sp);
     const T imu = MULTI ? select4(sp, R.inv_mumb[0], R.inv_mumb[1], R.inv_mumb[2], R.inv_mumb[3])
                         : R.inv_mumb[0];
     const T H0x = h.x * imu + R.B[0];
@@ -682,36 +785,39 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
     if (bad) atomicOr(&R.st->err, ERR_NUMERIC);
 }
 
-// Dispatch on the run's lattice and species count (uniform per run).
+// Dispatch on the run's lattice, species count, anisotropy and exchange form
+// (uniform per run).  Runs with anisotropy or radial exchange take their
+// own instantiations, so the others keep the site update's code unchanged.
+template <typename T, typename VW, bool ANISO, bool RADIAL>
+__device__ __forceinline__ void spin_site_lat(const RunDev<T>& R, const VW& V, int colour, T tau,
+                                              uint32_t l, int64_t step, bool cur, bool has_prev,
+                                              PrevHalf prev)
+{
+    const bool multi = RADIAL || R.n_species > 1;
+    if (R.lattice == SL_LATTICE_SC) {
+        if (multi) spin_site_t<T, VW, SL_LATTICE_SC, true, ANISO, RADIAL>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else if constexpr (!RADIAL) spin_site_t<T, VW, SL_LATTICE_SC, false, ANISO>(R, V, colour, tau, l, step, cur, has_prev, prev);
+    } else if (R.lattice == SL_LATTICE_FCC) {
+        if (multi) spin_site_t<T, VW, SL_LATTICE_FCC, true, ANISO, RADIAL>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else if constexpr (!RADIAL) spin_site_t<T, VW, SL_LATTICE_FCC, false, ANISO>(R, V, colour, tau, l, step, cur, has_prev, prev);
+    } else {
+        if (multi) spin_site_t<T, VW, SL_LATTICE_BCC, true, ANISO, RADIAL>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else if constexpr (!RADIAL) spin_site_t<T, VW, SL_LATTICE_BCC, false, ANISO>(R, V, colour, tau, l, step, cur, has_prev, prev);
+    }
+}
+
 template <typename T, typename VW>
 __device__ __forceinline__ void spin_site(const RunDev<T>& R, const VW& V, int colour, T tau,
                                           uint32_t l, int64_t step, bool cur = true,
                                           bool has_prev = false, PrevHalf prev = {})
 {
-    // runs with anisotropy take their own instantiation, so those without
-    // keep the site update's code unchanged
-    if (R.aniso) {
-        if (R.lattice == SL_LATTICE_SC) {
-            if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-            else spin_site_t<T, VW, SL_LATTICE_SC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        } else if (R.lattice == SL_LATTICE_FCC) {
-            if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_FCC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-            else spin_site_t<T, VW, SL_LATTICE_FCC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        } else {
-            if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-            else spin_site_t<T, VW, SL_LATTICE_BCC, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        }
-        return;
-    }
-    if (R.lattice == SL_LATTICE_SC) {
-        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_SC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        else spin_site_t<T, VW, SL_LATTICE_SC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
-    } else if (R.lattice == SL_LATTICE_FCC) {
-        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_FCC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        else spin_site_t<T, VW, SL_LATTICE_FCC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+    if (R.radial) {
+        if (R.aniso) spin_site_lat<T, VW, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        else spin_site_lat<T, VW, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+    } else if (R.aniso) {
+        spin_site_lat<T, VW, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     } else {
-        if (R.n_species > 1) spin_site_t<T, VW, SL_LATTICE_BCC, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        else spin_site_t<T, VW, SL_LATTICE_BCC, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        spin_site_lat<T, VW, false, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     }
 }
 
@@ -723,20 +829,56 @@ template <typename T> __device__ inline void pass_colour(const RunDev<T>& R, int
 }
 
 // ------------------------------------------------------------ lattice
+// The atom of internal index i: its site, the offsets around it and its
+// species.
+template <typename T, typename VW>
+__device__ __forceinline__ Around around_atom(const RunDev<T>& R, const Site& si, uint32_t i)
+{
+    const uint32_t l = i - (uint32_t)si.k * (uint32_t)R.g.H;
+    return around(R.g, (uint32_t)si.x, l - __umul24(fdiv(l, R.g.divLxh), (uint32_t)R.g.Lxh),
+                  (uint32_t)si.y, (uint32_t)si.z);
+}
+
+// First half kick of an atom of a run with radial exchange: the stored pair
+// force (at x^n) plus the bonds' exchange force at x^n with the spins the
+// sweep just produced, so that with the kick and drift after the sweep a
+// step is the symmetric splitting spins -> lattice with the spins held.  The
+// wrapped positions are read only (the drift writes them in a later launch
+// or phase).
+template <typename T, typename VW>
+__device__ __forceinline__ void half_kick_radial(const RunDev<T>& R, const VW& V, uint32_t i)
+{
+    using M = typename VW::Mem;
+    const Site si = decode_site(R.g, i);
+    const int sp = species_of(R, V, i);
+    const V3<T> s{M::ld(V.sx, i), M::ld(V.sy, i), M::ld(V.sz, i)};
+    const V3<T> Fe = exchange_force(R, V, si.k, around_atom<T, VW>(R, si, i), sp, s,
+                                    VW::PosMem::ld(V.pos, i));
+    const T k = select4(sp, R.hdtm[0], R.hdtm[1], R.hdtm[2], R.hdtm[3]);
+    gst(R.vx, i, gld(R.vx, i) + k * (gld(R.fx, i) + Fe.x));
+    gst(R.vy, i, gld(R.vy, i) + k * (gld(R.fy, i) + Fe.y));
+    gst(R.vz, i, gld(R.vz, i) + k * (gld(R.fz, i) + Fe.z));
+}
+
 // Half kick and drift of atom i (step phase), then its electron cell and
 // wrapped position; returns whether it moved more than half the skin since
-// its list was built.
+// its list was built.  `kicked`: the half kick was applied already
+// (half_kick_radial), only the drift remains.
 template <typename T, typename VW>
-__device__ __forceinline__ bool kick_drift_atom(const RunDev<T>& R, const VW& V, uint32_t i, int phase)
+__device__ __forceinline__ bool kick_drift_atom(const RunDev<T>& R, const VW& V, uint32_t i, int phase,
+                                                bool kicked = false)
 {
     const Site s = decode_site(R.g, i);
     bool far = false;
     if (phase == PHASE_STEP) {
         const int sp = species_of(R, V, i);
         const T k = select4(sp, R.hdtm[0], R.hdtm[1], R.hdtm[2], R.hdtm[3]);
-        T vx = gld(R.vx, i) + k * gld(R.fx, i);
-        T vy = gld(R.vy, i) + k * gld(R.fy, i);
-        T vz = gld(R.vz, i) + k * gld(R.fz, i);
+        T vx = gld(R.vx, i), vy = gld(R.vy, i), vz = gld(R.vz, i);
+        if (!kicked) {
+            vx += k * gld(R.fx, i);
+            vy += k * gld(R.fy, i);
+            vz += k * gld(R.fz, i);
+        }
         T ux = gld(R.ux, i) + R.dt * vx;
         T uy = gld(R.uy, i) + R.dt * vy;
         T uz = gld(R.uz, i) + R.dt * vz;
@@ -1065,9 +1207,19 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
         const T me = select4(sp, R.m_e[0], R.m_e[1], R.m_e[2], R.m_e[3]);
         if (phase == PHASE_STEP) {
             const T k = select4(sp, R.hdtm[0], R.hdtm[1], R.hdtm[2], R.hdtm[3]);
-            vx += k * Fx;
-            vy += k * Fy;
-            vz += k * Fz;
+            if (R.radial) {
+                // the bonds' exchange force at x^{n+1} with this step's spins
+                // (the stored force stays the pair force alone)
+                const V3<T> s{M::ld(V.sx, i), M::ld(V.sy, i), M::ld(V.sz, i)};
+                const V3<T> Fe = exchange_force(R, V, si.k, around_atom<T, VW>(R, si, i), sp, s, pi);
+                vx += k * (Fx + Fe.x);
+                vy += k * (Fy + Fe.y);
+                vz += k * (Fz + Fe.z);
+            } else {
+                vx += k * Fx;
+                vy += k * Fy;
+                vz += k * Fz;
+            }
             if (R.ttm_mode == 1) {
                 const uint32_t c = M::ld(V.cell, i);
                 const double Te = M::ld(V.Te, c);
@@ -1111,10 +1263,7 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
     }
     if (obs) {
         const double s0 = M::ld(V.sx, i), s1 = M::ld(V.sy, i), s2 = M::ld(V.sz, i);
-        const uint32_t l = i - (uint32_t)si.k * (uint32_t)R.g.H;
-        const Around a = around(R.g, (uint32_t)si.x, l - __umul24(fdiv(l, R.g.divLxh), (uint32_t)R.g.Lxh),
-                                (uint32_t)si.y, (uint32_t)si.z);
-        const V3<T> h = exchange_sum(R, V, si.k, a, sp);
+        const V3<T> h = exchange_sum(R, V, si.k, around_atom<T, VW>(R, si, i), sp);
         const double h0 = h.x, h1 = h.y, h2 = h.z;
         const double mb = select4(sp, R.mumb[0], R.mumb[1], R.mumb[2], R.mumb[3]);
         o.eex = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
@@ -1426,7 +1575,8 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
         const uint32_t i = (uint32_t)w.y + threadIdx.x;
         if (i >= (uint32_t)R.n) return;
         const GView<T> V = global_view(R, step + 1);
-        if (kick_drift_atom(R, V, i, PHASE_STEP) && *(volatile int32_t*)&R.st->rebuild == 0) {
+        if (kick_drift_atom(R, V, i, PHASE_STEP, R.radial != 0) &&
+            *(volatile int32_t*)&R.st->rebuild == 0) {
             atomicOr(&R.st->rebuild, 1);
             atomicOr(R.any_rebuild, 1);
         }
@@ -1475,6 +1625,21 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
         const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
         if (l < (uint32_t)R.g.H) spin_site(R, V, colour, tau, l, step, cur, prev, ph);
     }
+}
+
+// First half kick of the atoms of runs with radial exchange (the atom table
+// of the kick), after the colour sweep and before the drift: exchange forces
+// at x^n with the new spins.  Other runs' blocks return.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_half_kick(const RunDev<T>* __restrict__ runs,
+                                                      const int2* __restrict__ work_kick)
+{
+    const int2 w = work_kick[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    const int64_t step = R.st->step;
+    if (!R.radial || !R.live || R.st->err != 0 || step >= R.st->target) return;
+    const uint32_t i = (uint32_t)w.y + threadIdx.x;
+    if (i < (uint32_t)R.n) half_kick_radial(R, global_view(R, step), i);
 }
 
 // Initialisation of the lattice arrays of one run: electron cells and
@@ -2051,8 +2216,15 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
         __syncthreads();
         // lattice: kick and drift, list rebuild when flagged
         if (R.live) {
+            if (R.radial) {
+                // the exchange forces read the positions of x^n: all of them
+                // before any drift
+                for (int i = tid; i < n; i += B) half_kick_radial(R, V, (uint32_t)i);
+                __syncthreads();
+            }
             for (int i = tid; i < n; i += B)
-                if (kick_drift_atom(R, V, (uint32_t)i, PHASE_STEP)) atomicOr(&P.flag_rebuild, 1);
+                if (kick_drift_atom(R, V, (uint32_t)i, PHASE_STEP, R.radial != 0))
+                    atomicOr(&P.flag_rebuild, 1);
             if (tid == 0) st->step = step;   // read by the overflow diagnostics
             __syncthreads();
             if (P.flag_rebuild) {

@@ -176,6 +176,13 @@ std::string validate_desc(const sl_system_desc* d)
         if (!(std::fabs(nn - 1.0) <= 1e-6)) return "initial spins must be unit vectors";
     }
     if (d->lattice_mode != 0 && d->lattice_mode != 1) return "lattice_mode must be 0 or 1";
+    if (d->exch_radial != 0 && d->exch_radial != 1) return "exch_radial must be 0 or 1";
+    if (d->exch_radial) {
+        if (d->lattice_mode != 1) return "radial exchange needs a live lattice";
+        for (int k = 0; k < d->n_shells; ++k)
+            if (!(d->exch_r[k][1] > 0.0) || !std::isfinite(d->exch_r[k][0]))
+                return "radial exchange needs J3 > 0 and a finite J2 per shell";
+    }
     if (d->lattice_mode == 1) {
         if (!(d->morse[3] > 0.0) || !(d->skin > 0.0)) return "Morse cutoff and skin must be positive";
         const double reach = d->morse[3] + d->skin;
@@ -945,6 +952,7 @@ private:
         active_blocks_diff = 0, active_blocks_tile = 0;
     int max_sub = 0;
     bool any_live = false;
+    bool any_radial = false;        // a run with radial exchange: kicks after the sweep
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
     // graphs of merged chunks shorter than merge_g, by length (a chunk's
@@ -1073,6 +1081,11 @@ private:
         for (int sh = 0; sh < 2; ++sh)
             for (int a = 0; a < 4; ++a)
                 for (int b = 0; b < 4; ++b) R.J[sh][a][b] = (T)d->J[sh][a][b];
+        R.radial = d->exch_radial;
+        for (int sh = 0; sh < 2; ++sh) {
+            R.rJ2[sh] = (T)d->exch_r[sh][0];
+            R.rinvJ3sq[sh] = d->exch_r[sh][1] > 0.0 ? (T)(1.0 / (d->exch_r[sh][1] * d->exch_r[sh][1])) : T(0);
+        }
         R.mD = (T)d->morse[0];
         R.ma = (T)d->morse[1];
         R.mr0 = (T)d->morse[2];
@@ -1436,7 +1449,11 @@ private:
         merge_run = -1;
         fold = false;
         mk_runs = rl;
-        if (merge_sweeps && !rl.empty()) {
+        any_radial = false;
+        for (int s : rl) any_radial = any_radial || host_rd[s].radial != 0;
+        // runs with radial exchange kick after the whole sweep, so no step
+        // may leave its last colour pass to the next one
+        if (merge_sweeps && !rl.empty() && !any_radial) {
             // several runs merge together when they have the same colour count
             // (they defer the same pass), a common chunk length divides every
             // sample interval, and the runs still stepping are at the same
@@ -1565,7 +1582,7 @@ private:
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
             if (defer_last && pass == 2 * C - 2) break;
             const int merge = merge_first && pass == 0 ? 1 : 0;
-            const bool fused = pass == 1 && active_blocks_kick > 0;
+            const bool fused = pass == 1 && active_blocks_kick > 0 && !any_radial;
             const int nk = fused ? active_blocks_kick : (pass == 0 && fold_k >= 1 ? fold_blocks : 0);
             sl_status e = timed(st, p, fused ? 2 : 0, [&](hipEvent_t a, hipEvent_t b) {
                 const dim3 g(active_blocks_spin + nk);
@@ -1583,6 +1600,19 @@ private:
         }
         const dim3 ga(active_blocks_atom);
         sl_status e;
+        if (any_radial && active_blocks_kick > 0) {
+            // after the sweep: the exchange half kick of radial runs, then the
+            // drift of every live run (a launch of kick blocks only)
+            e = timed(st, p, 2, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_half_kick<T>, dim3(active_blocks_kick), bs, 0, st, a, b, d_runs, d_work_kick);
+            });
+            if (e != SL_OK) return e;
+            e = timed(st, p, 2, [&](hipEvent_t a, hipEvent_t b) {
+                launch(sl::k_spin_pass<T, 1>, dim3(active_blocks_kick), bs, 0, st, a, b, d_runs, d_work_spin,
+                       1, d_work_kick, 0, 0, -1);
+            });
+            if (e != SL_OK) return e;
+        }
         if (active_blocks_kick > 0 && !bin_each_step) {
             // capped grids striding over the atom table, which exit at once
             // unless a run flagged a rebuild

@@ -98,6 +98,10 @@ class SystemSpec:
     # ttm_mode 2: stepped T_e(t), stage temperatures (K) and ends of stages 1, 2 (ps)
     step_T: tuple = (0.0, 0.0, 0.0)
     step_end: tuple = (0.0, 0.0)
+    # radial exchange (live lattices): J holds the amplitudes J1 of
+    # J(r) = 4 J1 x (1 - J2 x) e^{-x}, x = (r / J3)^2; exch_r[shell] = (J2, J3 A)
+    exch_radial: int = 0
+    exch_r: tuple = ((0.0, 0.0), (0.0, 0.0))
 
     @property
     def nbasis(self) -> int:

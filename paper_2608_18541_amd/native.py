@@ -48,6 +48,7 @@ class sl_system_desc(C.Structure):
         ("spin0", C.POINTER(C.c_double)), ("vel0", C.POINTER(C.c_double)),
         ("disp0", C.POINTER(C.c_double)), ("stream", C.c_void_p),
         ("alloc", C.POINTER(sl_allocator)),
+        ("exch_radial", C.c_int32), ("exch_r", (C.c_double * 2) * 2),
     ]
 
 
@@ -257,6 +258,11 @@ def system_desc(spec: I.SystemSpec, state: I.InitialState, precision: int = SL_F
         u0 = np.ascontiguousarray(np.asarray(state.disp, dtype=np.float64).reshape(n, 3))
         keep["u0"] = u0
         d.disp0 = _dp(u0)
+    d.exch_radial = int(getattr(spec, "exch_radial", 0))
+    er = getattr(spec, "exch_r", ((0.0, 0.0), (0.0, 0.0)))
+    for sh in range(2):
+        for q in range(2):
+            d.exch_r[sh][q] = float(er[sh][q])
     d.stream = stream
     if alloc is not None:
         d.alloc = C.pointer(alloc.struct)

@@ -1,0 +1,109 @@
+"""Radial exchange on live lattices (Methods A; the re-derivation of the
+radial exchange function): each bond's coupling J(r) = 4 J1 x (1 - J2 x)
+e^{-x}, x = (r / J3)^2, at its current length, and its force
+-dJ/dr (s_i . s_j) on the atoms.  FP64 against the oracle at 1e-10 per
+component (reading R23) on the multi-kernel step (bcc with both shells
+radial; the fcc alloy with the laser-heated grid) and in the persistent
+kernel; the exchange force is live (a run whose bonds keep their ideal
+coupling moves its atoms differently).
+"""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_18541_amd import exchange as X
+from paper_2608_18541_amd import inputs as I
+from tests.gpu_util import compare_states
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_18541_amd import native
+    native.lib()
+    return native
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _bcc():
+    r1 = X.nearest_neighbour_distance("bcc", 2.8665)
+    _, J2, J3 = X.rederive_radial_exchange(r1)
+    J = (((0.05, 0, 0, 0), (0,) * 4, (0,) * 4, (0,) * 4), ((0.025, 0, 0, 0), (0,) * 4, (0,) * 4, (0,) * 4))
+    spec = I.fe_bcc_spec(L=6, J=J, exch_radial=1, exch_r=((J2, J3), (J2, J3)), seed=51, run_id=2)
+    return spec, I.initial_state(spec, "tilt", T_lattice=600.0)
+
+
+def _fcc_alloy():
+    r1 = X.nearest_neighbour_distance("fcc", 3.6)
+    _, J2, J3 = X.rederive_radial_exchange(r1)
+    spec = replace(I.gdfeco_fcc_spec(L=5, alpha=0.05, seed=52, run_id=3), lattice_mode=1,
+                   skin=0.3, exch_radial=1, exch_r=((J2, J3), (0.0, 0.0)), tn=(3, 3, 3), ttm_mode=1,
+                   Te0=300.0, gamma_e=I.j_per_m3k2_to_metal(225.0), G_el=I.w_per_m3k_to_metal(6.6e17),
+                   S0=0.6, t0=0.005, fwhm=0.005)
+    return spec, I.initial_state(spec, "afm", exact_count=True)
+
+
+@pytest.mark.parametrize("case", ["bcc", "fcc_alloy"])
+def test_radial_exchange_against_oracle(N, case):
+    spec, st = _bcc() if case == "bcc" else _fcc_alloy()
+    _log("radial: %s multi-kernel FP64" % case)
+    g = N.System(spec, st, precision=N.SL_FP64, obs_every=25)
+    o = O.Oracle(spec, st.species, st.spins, st.vel)
+    for chunk in (1, 24, 75):
+        g.step(chunk)
+        o.step(chunk)
+        errs, bad = compare_states(g.state(), o.state(), spec.box, TOL)
+        assert not bad, (case, g.info(), errs)
+    last, ref = g.observables()[-1], o.observables()
+    for k in ("E_ex", "E_z", "KE", "PE"):
+        assert abs(last[k] - ref[k]) <= 1e-9 * max(1.0, abs(ref[k])), (k, last[k], ref[k])
+    g.close()
+
+
+def test_radial_exchange_persistent_kernel(N):
+    spec, st = _bcc()
+    _log("radial: bcc persistent batch run FP64")
+    b = N.Batch(precision=N.SL_FP64, max_runs=1)
+    b.set_tuning(persist_block=512)
+    slot = b.add(spec, st, 100)
+    b.advance(60)
+    avg, cnt = b.advance_profiled(40)
+    assert cnt[4] == 1, cnt
+    o = O.Oracle(spec, st.species, st.spins, st.vel)
+    o.step(100)
+    errs, bad = compare_states(b.get(slot), o.state(), spec.box, TOL)
+    assert not bad, errs
+    b.close()
+
+
+def test_exchange_force_moves_the_atoms(N):
+    """The same run with the bonds' couplings frozen at their ideal-lattice
+    values (no exchange force) ends with other velocities, by far more than
+    the parity tolerance."""
+    spec, st = _bcc()
+    r1, r2 = X.shell_distances("bcc", spec.a)
+    J2, J3 = spec.exch_r[0]
+    J = tuple(tuple(tuple(float(X.radial_exchange(r, 1.0, J2, J3)) * v for v in row) for row in shell)
+              for shell, r in zip(spec.J, (r1, r2)))
+    fixed = replace(spec, exch_radial=0, J=J)
+    out = []
+    for sp in (spec, fixed):
+        g = N.System(sp, st, precision=N.SL_FP64)
+        g.step(100)
+        out.append(g.state())
+        g.close()
+    vr = np.sqrt((out[0]["v"] ** 2).mean())
+    assert np.abs(out[0]["v"] - out[1]["v"]).max() > 1e-4 * vr

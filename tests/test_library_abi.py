@@ -67,6 +67,7 @@ int main(void) {
   printf("sl_system_desc size %zu\n", sizeof(sl_system_desc));
   P(sl_system_desc, a) P(sl_system_desc, species) P(sl_system_desc, J) P(sl_system_desc, B)
   P(sl_system_desc, dt) P(sl_system_desc, seed) P(sl_system_desc, spin0) P(sl_system_desc, alloc)
+  P(sl_system_desc, exch_radial) P(sl_system_desc, exch_r)
   printf("sl_ttm_desc size %zu\n", sizeof(sl_ttm_desc));
   P(sl_ttm_desc, Te_init) P(sl_ttm_desc, n_sub) P(sl_ttm_desc, depth)
   printf("sl_obs size %zu\n", sizeof(sl_obs));

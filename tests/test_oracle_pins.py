@@ -958,3 +958,125 @@ def test_eph_bookkeeping_conserves_energy_on_average():
     assert abs(dE_tot.mean()) < 4.0 * se_tot, (dE_tot.mean(), se_tot)
     assert dE_e.mean() < -10.0 * se_e and dE_e.mean() < -10.0 * se_tot, (dE_e.mean(), se_e, se_tot)
     assert dE_tot.std() > 0.05                     # each run's total does walk
+
+
+# ------------------------------------------------------------ radial exchange
+
+def _radial_bcc(L=6, J1=0.022, dt=2e-4, **kw):
+    from paper_2608_18541_amd import exchange as X
+    r1 = X.nearest_neighbour_distance("bcc", 2.8665)
+    _, J2, J3 = X.rederive_radial_exchange(r1)
+    Jt = (((J1, 0, 0, 0), (0,) * 4, (0,) * 4, (0,) * 4), ((0.5 * J1, 0, 0, 0), (0,) * 4, (0,) * 4, (0,) * 4))
+    return I.fe_bcc_spec(L=L, dt=dt, J=Jt, exch_radial=1, exch_r=((J2, J3), (J2, J3)), **kw)
+
+
+def test_radial_exchange_force_is_minus_the_energy_gradient():
+    """Methods A: the bonds' force -dJ/dr (s_i . s_j) is minus the gradient
+    of the exchange energy -sum_bonds J(r_ij) s_i . s_j with respect to an
+    atom's position (central differences of the oracle's energy, random
+    spins on a thermally displaced bcc block, both shells radial)."""
+    spec = _radial_bcc(L=4, alpha=0.0, B=(0, 0, 0))
+    st = I.initial_state(spec, "random")
+    rng = np.random.default_rng(4)
+    orc = O.Oracle(spec, st.species, st.spins, st.vel)
+    x0 = orc.state()["x"] + 0.05 * rng.standard_normal((spec.n_sites, 3))
+    orc.set_positions(x0)
+    F = orc.exchange_forces()
+    assert np.abs(F).max() > 1e-3
+    h = 1e-6
+    for i in (0, 5, 77):
+        for k in range(3):
+            e = []
+            for sgn in (1, -1):
+                x = x0.copy()
+                x[i, k] += sgn * h
+                orc.set_positions(x)
+                e.append(orc.observables()["E_ex"])
+            g = (e[0] - e[1]) / (2 * h)
+            assert abs(F[i, k] + g) < 1e-7 * max(1.0, abs(g)), (i, k, F[i, k], -g)
+    orc.set_positions(x0)
+    assert np.abs(F.sum(axis=0)).max() < 1e-12        # action and reaction
+
+
+def test_radial_exchange_dimer_oscillation():
+    """Two atoms with parallel spins along an applied field (no torque) move
+    in the effective pair potential V_Morse(r) - J(r): equilibrium r* where
+    V'(r*) = J'(r*), small oscillations at sqrt((V''(r*) - J''(r*)) / m_red),
+    with J(r) = 4 J1 x (1 - J2 x) e^{-x}, x = (r / J3)^2, differentiated by
+    hand here.  A strong amplitude (0.15 eV) moves r* by 0.017 A, 17 times
+    the oscillation amplitude."""
+    from scipy.optimize import brentq
+    D, a, r0 = 0.4174, 1.3885, 2.845
+    J1, J2, J3 = 0.15, 0.405, 3.1677
+
+    def dV(r):
+        e = math.exp(-a * (r - r0))
+        return 2.0 * a * D * (e - e * e)
+
+    def d2V(r):
+        e = math.exp(-a * (r - r0))
+        return 2.0 * a * a * D * (2.0 * e * e - e)
+
+    def dJ(r):          # dJ/dr = dJ/dx dx/dr, dx/dr = 2 r / J3^2
+        x = (r / J3) ** 2
+        return 4.0 * J1 * math.exp(-x) * (1.0 - x - J2 * x * (2.0 - x)) * 2.0 * r / J3 ** 2
+
+    def d2J(r):         # d/dr of the above
+        x = (r / J3) ** 2
+        xr = 2.0 * r / J3 ** 2
+        q = 1.0 - x - J2 * x * (2.0 - x)
+        dq = -1.0 - J2 * (2.0 - 2.0 * x)
+        return 4.0 * J1 * (math.exp(-x) * (dq - q) * xr * xr + math.exp(-x) * q * 2.0 / J3 ** 2)
+
+    rstar = brentq(lambda r: dV(r) - dJ(r), 2.0, 3.5)
+    assert abs(rstar - r0) > 0.01
+    omega_ref = math.sqrt((d2V(rstar) - d2J(rstar)) / (55.845 / 2.0 * MVV2E))
+    J = (((J1, 0, 0, 0), (0,) * 4, (0,) * 4, (0,) * 4), ((0,) * 4,) * 4)
+    spec = spin_only_spec(lattice_mode=1, dt=1e-4, Te0=0.0, mass=(55.845, 0, 0, 0), J=J,
+                          B=(0.0, 0.0, 1.0), morse=(D, a, r0, 8.0), exch_radial=1,
+                          exch_r=((J2, J3), (0.0, 0.0)))
+    top = O.generic_topology(2, [(0, 1)], [0, 1], box=(40.0, 40.0, 40.0),
+                             pos=np.array([[5.0, 5.0, 5.0], [5.0 + rstar + 1e-3, 5.0, 5.0]]))
+    orc = O.Oracle(spec, [0, 0], np.tile([0, 0, 1.0], (2, 1)), topology=top)
+    sep = []
+    for _ in range(14000):
+        orc.step(1)
+        x = orc.state()["x"]
+        sep.append(x[1, 0] - x[0, 0] - rstar)
+    sep = np.array(sep)
+    t = (np.arange(len(sep)) + 1) * spec.dt
+    up = np.nonzero((sep[:-1] < 0) & (sep[1:] >= 0))[0]
+    tc = t[up] + (0 - sep[up]) / (sep[up + 1] - sep[up]) * spec.dt
+    omega = 2 * math.pi / np.mean(np.diff(tc))
+    assert abs(omega / omega_ref - 1.0) < 2e-3, (omega, omega_ref)
+    assert abs(sep.mean()) < 2e-4
+    assert np.abs(orc.state()["s"] - [0, 0, 1.0]).max() < 1e-12     # no torque
+
+
+def test_radial_exchange_energy_conservation_second_order():
+    """alpha = 0, T = 0: spins and lattice exchange energy through the radial
+    bonds, and the total KE + PE + E_ex + E_z is conserved up to the
+    splitting error, which falls as dt^2 (the spin sweep at x^n followed by
+    velocity Verlet with the swept spins held is a symmetric splitting up to
+    a half-step conjugation that leaves the energy unchanged)."""
+    errs, moved = [], []
+    for dt in (2e-4, 1e-4):
+        # Morse cut between neighbour shells: no pair crosses the force's jump
+        spec = _radial_bcc(L=6, J1=0.08, dt=dt, alpha=0.0, B=(0, 0, 0.5),
+                           morse=(0.4174, 1.3885, 2.845, 4.4))
+        st = I.initial_state(spec, "tilt", T_lattice=300.0)
+        orc = O.Oracle(spec, st.species, st.spins, st.vel)
+
+        def total():
+            o = orc.observables()
+            return o["KE"] + o["PE"] + o["E_ex"] + o["E_z"], o["E_ex"]
+        E0, X0 = total()
+        dev = 0.0
+        for _ in range(int(round(0.02 / dt)) // 5):
+            orc.step(5)
+            E, Xe = total()
+            dev = max(dev, abs(E - E0))
+        errs.append(dev)
+        moved.append(abs(Xe - X0))
+    assert min(moved) > 20.0 * errs[0]                  # energy really flowed
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
