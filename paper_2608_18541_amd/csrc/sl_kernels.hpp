@@ -495,11 +495,11 @@ __device__ __forceinline__ V3<T> exchange_force_t(const RunDev<T>& R, const VW& 
 
 // Dispatch on the run's lattice and species count (uniform per run); runs
 // with radial exchange take the species-resolved instantiation.
-template <typename T, typename VW>
+template <typename T, typename VW, bool RADIAL_OK = true>
 __device__ __forceinline__ V3<T> exchange_sum(const RunDev<T>& R, const VW& V, int k, const Around& a,
                                               int sp)
 {
-    if (R.radial) {
+    if (RADIAL_OK && R.radial) {
         if (R.lattice == SL_LATTICE_SC) return exchange_sum_t<T, VW, SL_LATTICE_SC, true, true>(R, V, k, a, sp);
         if (R.lattice == SL_LATTICE_FCC) return exchange_sum_t<T, VW, SL_LATTICE_FCC, true, true>(R, V, k, a, sp);
         return exchange_sum_t<T, VW, SL_LATTICE_BCC, true, true>(R, V, k, a, sp);
@@ -806,14 +806,18 @@ __device__ __forceinline__ void spin_site_lat(const RunDev<T>& R, const VW& V, i
     }
 }
 
-template <typename T, typename VW>
+// RADIAL_OK: the kernel may meet runs with radial exchange (engines without
+// any compile the dispatch without those instantiations).
+template <typename T, typename VW, bool RADIAL_OK = true>
 __device__ __forceinline__ void spin_site(const RunDev<T>& R, const VW& V, int colour, T tau,
                                           uint32_t l, int64_t step, bool cur = true,
                                           bool has_prev = false, PrevHalf prev = {})
 {
-    if (R.radial) {
-        if (R.aniso) spin_site_lat<T, VW, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
-        else spin_site_lat<T, VW, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+    if (RADIAL_OK && R.radial) {
+        if constexpr (RADIAL_OK) {
+            if (R.aniso) spin_site_lat<T, VW, true, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+            else spin_site_lat<T, VW, false, true>(R, V, colour, tau, l, step, cur, has_prev, prev);
+        }
     } else if (R.aniso) {
         spin_site_lat<T, VW, true, false>(R, V, colour, tau, l, step, cur, has_prev, prev);
     } else {
@@ -1157,7 +1161,7 @@ __device__ __forceinline__ void walk_list(const RunDev<T>& R, const VW& V, uint3
 // observable terms.  LPA lanes of a quad share the atom (lane `j` of the
 // group): they split its neighbour list, fold the pair sums, and then all
 // compute the rest while only lane 0 stores.
-template <typename T, typename VW, int LPA = 1>
+template <typename T, typename VW, int LPA = 1, bool RADIAL = false>
 __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V, uint32_t i,
                                                 int phase, int64_t step, bool obs,
                                                 unsigned long long* acc, ObsTerms& o, int j = 0,
@@ -1207,7 +1211,7 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
         const T me = select4(sp, R.m_e[0], R.m_e[1], R.m_e[2], R.m_e[3]);
         if (phase == PHASE_STEP) {
             const T k = select4(sp, R.hdtm[0], R.hdtm[1], R.hdtm[2], R.hdtm[3]);
-            if (R.radial) {
+            if (RADIAL && R.radial) {
                 // the bonds' exchange force at x^{n+1} with this step's spins
                 // (the stored force stays the pair force alone)
                 const V3<T> s{M::ld(V.sx, i), M::ld(V.sy, i), M::ld(V.sz, i)};
@@ -1263,7 +1267,7 @@ __device__ __forceinline__ void atom_final_atom(const RunDev<T>& R, const VW& V,
     }
     if (obs) {
         const double s0 = M::ld(V.sx, i), s1 = M::ld(V.sy, i), s2 = M::ld(V.sz, i);
-        const V3<T> h = exchange_sum(R, V, si.k, around_atom<T, VW>(R, si, i), sp);
+        const V3<T> h = exchange_sum<T, VW, RADIAL>(R, V, si.k, around_atom<T, VW>(R, si, i), sp);
         const double h0 = h.x, h1 = h.y, h2 = h.z;
         const double mb = select4(sp, R.mumb[0], R.mumb[1], R.mumb[2], R.mumb[3]);
         o.eex = -0.5 * (s0 * h0 + s1 * h1 + s2 * h2);
@@ -1554,7 +1558,7 @@ template <typename T> __device__ inline void fold_end_step(const RunDev<T>& R, i
 // spin and the spin blocks read no lattice array.  In a folded chunk the
 // extra blocks of pass 0 end the previous step instead (fold_end_step).
 // `merge` (pass 0): apply the previous step's deferred last half step first.
-template <typename T, int SPT>
+template <typename T, int SPT, bool RADIAL = false>
 __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
                                                       const int2* __restrict__ work, int pass,
                                                       const int2* __restrict__ work_kick,
@@ -1623,7 +1627,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
-        if (l < (uint32_t)R.g.H) spin_site(R, V, colour, tau, l, step, cur, prev, ph);
+        if (l < (uint32_t)R.g.H) spin_site<T, GView<T>, RADIAL>(R, V, colour, tau, l, step, cur, prev, ph);
     }
 }
 
@@ -1640,6 +1644,34 @@ __global__ __launch_bounds__(kBlock) void k_half_kick(const RunDev<T>* __restric
     if (!R.radial || !R.live || R.st->err != 0 || step >= R.st->target) return;
     const uint32_t i = (uint32_t)w.y + threadIdx.x;
     if (i < (uint32_t)R.n) half_kick_radial(R, global_view(R, step), i);
+}
+
+// A colour pass with nothing but the site updates (no kick or step-end
+// blocks, no deferred half step), for engines whose runs on the multi-kernel
+// step share one site-update form: one lattice, one or several species for
+// all, no anisotropy, constant exchange.  The same device function as in
+// k_spin_pass, compiled alone, so the kernel holds fewer registers (more
+// waves per SIMD) and gives the same bits.
+template <typename T, int SPT, int LAT, bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_spin_pass_lean(const RunDev<T>* __restrict__ runs,
+                                                           const int2* __restrict__ work, int pass,
+                                                           int fold_k)
+{
+    const int2 w = work[blockIdx.x];
+    const RunDev<T>& R = runs[w.x];
+    const RunState* st = R.st;
+    const int64_t step = step_at(R, fold_k);
+    if (!fold_ok(st, fold_k) || step >= st->target || pass >= 2 * R.g.C - 1) return;
+    int colour;
+    T tau;
+    pass_colour(R, pass, &colour, &tau);
+    GView<T> V = global_view(R, step);
+    if (fold_k >= 0) V.Te = te_buf(R, fold_k);
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
+        if (l < (uint32_t)R.g.H) spin_site_t<T, GView<T>, LAT, MULTI, false>(R, V, colour, tau, l, step);
+    }
 }
 
 // Initialisation of the lattice arrays of one run: electron cells and
@@ -1728,7 +1760,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
 // (a multiple of 64, so observable rows of 64 atoms never straddle blocks).
 // The run's state is read once for the block, so every wave takes the same
 // branch at the barriers even when another block raises an error meanwhile.
-template <typename T, int LPA>
+template <typename T, int LPA, bool RADIAL = false>
 __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work, int phase,
                                                        int sorted_bins, int fold_k)
@@ -1826,7 +1858,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
         }
         ObsTerms o{};
         if (i < (uint32_t)R.n)
-            atom_final_atom<T, GView<T>, LPA>(R, V, i, phase, step, obs, lds_acc ? cacc : dE, o, lj,
+            atom_final_atom<T, GView<T>, LPA, RADIAL>(R, V, i, phase, step, obs, lds_acc ? cacc : dE, o, lj,
                                               lds_acc ? c_lo : 0u, R.eta_drawn ? R.eta : nullptr);
         if (lds_acc) {
             __syncthreads();
@@ -2089,7 +2121,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const RunDev<T>* __restrict
 // ======================================================= launch tables
 // Writes a single run's launch tables into `base` (then the run list and
 // the persistent list, one int each, at `ints`).
-__global__ __launch_bounds__(kBlock) void k_fill_tables(int2* __restrict__ base, int* __restrict__ ints,
+static __global__ __launch_bounds__(kBlock) void k_fill_tables(int2* __restrict__ base, int* __restrict__ ints,
                                                         TableFill f)
 {
     for (int32_t e = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); e < f.n_int2;
@@ -2168,7 +2200,7 @@ struct PersistShared {
 };
 
 // The run's steps inside one block: load the LDS copies, step, write back.
-template <typename T, typename VW>
+template <typename T, typename VW, bool RADIAL>
 __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, double* Te2,
                                             unsigned long long* acc, PersistShared& P, int nsteps,
                                             bool pos_in_lds)
@@ -2211,16 +2243,18 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
             int colour;
             T tau;
             pass_colour(R, pass, &colour, &tau);
-            for (int l = tid; l < R.g.H; l += B) spin_site(R, V, colour, tau, (uint32_t)l, step);
+            for (int l = tid; l < R.g.H; l += B) spin_site<T, VW, RADIAL>(R, V, colour, tau, (uint32_t)l, step);
         }
         __syncthreads();
         // lattice: kick and drift, list rebuild when flagged
         if (R.live) {
-            if (R.radial) {
-                // the exchange forces read the positions of x^n: all of them
-                // before any drift
-                for (int i = tid; i < n; i += B) half_kick_radial(R, V, (uint32_t)i);
-                __syncthreads();
+            if constexpr (RADIAL) {
+                if (R.radial) {
+                    // the exchange forces read the positions of x^n: all of
+                    // them before any drift
+                    for (int i = tid; i < n; i += B) half_kick_radial(R, V, (uint32_t)i);
+                    __syncthreads();
+                }
             }
             for (int i = tid; i < n; i += B)
                 if (kick_drift_atom(R, V, (uint32_t)i, PHASE_STEP, R.radial != 0))
@@ -2247,7 +2281,7 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
             for (int base = 0; base < n; base += B) {
                 const int i = base + tid;
                 ObsTerms o{};
-                if (i < n) atom_final_atom(R, V, (uint32_t)i, PHASE_STEP, step, obs, acc, o);
+                if (i < n) atom_final_atom<T, VW, 1, RADIAL>(R, V, (uint32_t)i, PHASE_STEP, step, obs, acc, o);
                 if (obs) wave_write_row(o, V.partial, i - (tid & 63), n);
             }
         }
@@ -2291,7 +2325,7 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
 
 // MAXT: the largest block the instantiation is compiled for (512: up to 256
 // registers per lane; 1024: up to 128, with some spilling).
-template <typename T, int MAXT>
+template <typename T, int MAXT, bool RADIAL = false>
 __global__ __launch_bounds__(MAXT) void k_persist(const RunDev<T>* __restrict__ runs,
                                                    const int* __restrict__ run_list, int nsteps,
                                                    uint32_t lds_max)
@@ -2312,10 +2346,10 @@ __global__ __launch_bounds__(MAXT) void k_persist(const RunDev<T>* __restrict__ 
     if (L.pos_in_lds) {
         const View<T, InLds, InLds> V{sx, sx + n, sx + 2 * n, species, cell,
                                       reinterpret_cast<Pos4<T>*>(smem + L.off_pos), Te, partial};
-        persist_run(R, V, Te2, acc, P, nsteps, true);
+        persist_run<T, View<T, InLds, InLds>, RADIAL>(R, V, Te2, acc, P, nsteps, true);
     } else {
         const View<T, InLds, InGlobal> V{sx, sx + n, sx + 2 * n, species, cell, R.pos, Te, partial};
-        persist_run(R, V, Te2, acc, P, nsteps, false);
+        persist_run<T, View<T, InLds, InGlobal>, RADIAL>(R, V, Te2, acc, P, nsteps, false);
     }
 }
 
