@@ -255,6 +255,23 @@ def sublattice_analysis(runs, traj, flags) -> dict:
             "tfls_median_ps": med(tfls)}
 
 
+def tune_batch(N, runs, prec: int, n_steps: int, rounds: int = 2) -> dict:
+    """Launch shape for a batch of these runs, chosen by the autotuner on a
+    probe batch of the same runs (every shape gives the same bits, so the
+    measured batch starts fresh at step 0 with the chosen shape)."""
+    from paper_2608_18541_amd.autotune import autotune
+    probe = N.Batch(precision=prec, max_runs=len(runs))
+    for sp, st in runs:
+        probe.add(sp, st, n_steps)
+    probe.synchronize()
+    t0 = time.perf_counter()
+    best = autotune(probe, steps=64, rounds=rounds, use_cache=False)
+    probe.close()
+    print("bench: tuned batch (%d runs, prec %d) in %.1f s: %s"
+          % (len(runs), prec, time.perf_counter() - t0, json.dumps(best)), file=sys.stderr, flush=True)
+    return best
+
+
 def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     """The alloy phase diagram (8 alpha x 8 peak T_e x seeds, 16^3 runs) in
     one batch, FP32 and FP64; switching probabilities per cell."""
@@ -263,8 +280,11 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
     res = {}
     flags = {}
     mz_mean = {}
+    tunings = {}
     for prec in (N.SL_FP32, N.SL_FP64):
+        tunings[prec] = tune_batch(N, [(r.spec, r.state) for r in runs], prec, n_steps)
         b = N.Batch(precision=prec, max_runs=len(runs))
+        b.set_tuning(**tunings[prec])
         slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
                  for r in runs]
         b.synchronize()
@@ -295,7 +315,7 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
         res["fp32" if prec else "fp64"] = {"seconds": round(el, 3),
                                            "runs_per_s": round(len(runs) / el, 3),
                                            "atom_steps_per_s": len(runs) * 4096 * n_steps / el,
-                                           "failed_runs": failed}
+                                           "failed_runs": failed, "tuning": tunings[prec]}
         res["fp32" if prec else "fp64"].update(sublattice_analysis(runs, traj, fl))
         print("bench: phase diagram prec %d: %.2f s" % (prec, el), file=sys.stderr, flush=True)
         b.close()
@@ -455,7 +475,11 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
     """Poisson request stream served with continuous batching (FP32), and a
     one-request-at-a-time plain FP64 baseline on the same trace."""
     trace = W.request_trace(n=n_req, rate=50.0, seed=7, steps_scale=steps_scale)
+    # launch shape tuned on a probe batch of the first 64 requests of the trace
+    tuning = tune_batch(N, [(q.run.spec, q.run.state) for q in trace[:64]], N.SL_FP32,
+                        max(q.run.n_steps for q in trace[:64]))
     batch = N.Batch(precision=N.SL_FP32, max_runs=512, mem_budget=24 << 30)
+    batch.set_tuning(**tuning)
     srv = S.Server(batch, chunk=500, obs_every=100,
                    progress=lambda m: print("bench: serving: " + m, file=sys.stderr, flush=True))
     res = srv.run(trace)
@@ -473,13 +497,22 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
     from paper_2608_18541_amd.stats import switched
     by_rid = {r.rid: r for r in res}
     cmp_ids = [q.rid for q in trace][::60]
-    dmz, agree = [], 0
+    dmz, agree, measured = [], 0, []
     for q in trace:
         if q.rid not in cmp_ids:
             continue
         s64 = N.System(q.run.spec, q.run.state, precision=N.SL_FP64, obs_every=100,
                        obs_capacity=q.run.n_steps // 100 + 2)
-        s64.step(q.run.n_steps)
+        s64.synchronize()
+        with host_quiet():
+            t0 = time.perf_counter()
+            s64.step(q.run.n_steps)
+            s64.synchronize()
+            el = time.perf_counter() - t0
+        # the one-at-a-time plain run, measured, against the replay's time
+        L = q.run.spec.ncell[0]
+        measured.append({"rid": q.rid, "L": L, "steps": q.run.n_steps, "measured_s": round(el, 4),
+                         "replay_s": round(per_size[L] * q.run.n_steps, 4)})
         mz64 = np.array([o["M"][1][2] for o in s64.observables()])
         s64.close()
         mz32 = by_rid[q.rid].mz_gd
@@ -503,7 +536,14 @@ def serving(N, W, S, n_req: int, steps_scale: float) -> dict:
                                             "path; single trajectories, so FP32 and FP64 diverge "
                                             "chaotically and agree only statistically"},
             "served_chunks": len(srv.log),
-            "plain_latency_method": "FIFO replay of measured plain FP64 per-step times"}
+            "tuning": tuning,
+            "plain_latency_method": "FIFO replay of measured plain FP64 per-step times",
+            "plain_measured_sample": {
+                "requests": measured,
+                "measured_over_replay": round(sum(m["measured_s"] for m in measured) /
+                                              max(1e-12, sum(m["replay_s"] for m in measured)), 4),
+                "note": "the sampled requests run alone on the plain FP64 path, whole runs timed "
+                        "on the host clock"}}
 
 
 def three_temperature_run(N, I, steps: int = 80000) -> dict:
