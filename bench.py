@@ -676,9 +676,28 @@ def field_llg_scale(N, I, L: int = 256, tuning=None) -> dict:
     return out
 
 
+def copy_calibration() -> int:
+    """A plain device-to-device copy of a known size (1 GiB, three times).
+    Run under rocprofv3 --pmc FETCH_SIZE and then WRITE_SIZE, it gives what
+    the counters read for traffic known exactly (1 GiB read and 1 GiB
+    written per copy); the spin-lattice kernels' counters are scaled by it."""
+    import torch
+    n = 256 << 20                      # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied %d bytes three times" % (4 * n), file=sys.stderr)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB device copy that calibrates the traffic counters")
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=100)
@@ -709,6 +728,8 @@ def main() -> int:
                          "default is the shape the autotuner picked, fixed so that the committed "
                          "counter traffic applies")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print("bench.py: measures one GPU; --gpus %d is not supported "
               "(runs are independent replicas; sharding is described with the design notes)" % args.gpus,
