@@ -630,8 +630,10 @@ def large_run(N, I, steps: int) -> dict:
                                       "max_abs_dm": float(np.abs(m32 - m64).max()),
                                       "max_abs_d_strain_zz": float(np.abs(e32 - e64).max()),
                                       "max_abs_strain_zz": float(np.abs(e64).max())},
-            "note": "FP64 reference is the GPU FP64 path (pinned to the oracle at 1e-10 on "
-                    "smaller systems); the all-pairs oracle is too slow at 524288 atoms"}
+            "note": "the reference here is the GPU FP64 path; the same 10-step segment of "
+                    "both precisions against the oracle (FP64 at 1e-10, FP32 spins, M(t) and "
+                    "eps_zz(z)) is the GPU test tests/test_gpu_parity_full.py, since the bench "
+                    "runs no oracle outside its CPU baseline"}
 
 
 def strain_profile(spec, x) -> np.ndarray:

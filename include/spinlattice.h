@@ -174,7 +174,8 @@ typedef struct sl_obs {
 
 typedef struct sl_system_s* sl_system;
 
-/* Creates a run on the device: copies the description and initial state,
+/* Creates a run on the device (Methods A and D: the lattice, its spins and
+ * atoms; the GdFeCo model for fcc alloys): copies the description and initial state,
  * builds the neighbour tables, computes the initial forces and (if
  * obs_every > 0) records the step-0 sample.  The electron grid starts as
  * one fixed cell at T_e = 0 until sl_set_ttm_grid is called.
@@ -182,7 +183,7 @@ typedef struct sl_system_s* sl_system;
  * 3 (rc + skin) in a live dimension; *out is set only on success. */
 sl_status sl_init_system(const sl_system_desc* desc, sl_system* out);
 
-/* Replaces the electron-temperature grid (fields above).  Only before the
+/* Replaces the electron-temperature grid of Methods B (fields above).  Only before the
  * first sl_step.  SL_EINVAL when an explicit diffusion sub-step would be
  * unstable for the initial grid: kappa_e (dt/n_sub) sum_d 2/h_d^2 >
  * gamma_e min T_e (h_d the cell widths; the linearised diffusivity is
@@ -190,6 +191,9 @@ sl_status sl_init_system(const sl_system_desc* desc, sl_system* out);
 sl_status sl_set_ttm_grid(sl_system h, const sl_ttm_desc* ttm);
 
 /* Enqueues n_steps timesteps on the run's stream and returns (asynchronous).
+ * One step is the splitting of Methods A-C: the colour sweep of spin updates
+ * (Eqs. (1)-(2)), the lattice's velocity Verlet step, the electron-phonon
+ * step and the two-temperature grid update (Methods B), then a sample.
  * The first call after creation, a checkpoint restore or a tuning change
  * allocates the launch tables (through the system's allocator) and captures
  * a HIP graph of the steps. */
@@ -211,20 +215,29 @@ sl_status sl_step(sl_system h, int64_t n_steps);
 #define SL_NOALLOC_SCRATCH_BYTES (4u << 20)
 sl_status sl_step_noalloc(sl_system h, int64_t n_steps);
 
-/* Waits for the run's stream.  SL_ENUMERIC if the run hit a numerical error. */
+/* Waits for the run's stream.  SL_ENUMERIC if the run hit a numerical error
+ * (the failure detection of the conventions above: a negative or non-finite
+ * electron energy, a spin that was not a finite unit vector, a non-finite
+ * velocity or displacement, a neighbour table overflow); the run is frozen
+ * at the step where it was found. */
 sl_status sl_synchronize(sl_system h);
 
-/* Waits, then copies up to max_samples observable samples not yet returned,
+/* The observables of Methods G and Results A (sublattice magnetisation,
+ * energies, the three temperatures).
+ * Waits, then copies up to max_samples observable samples not yet returned,
  * oldest first, into out (host).  Samples older than the device ring
  * capacity are lost; *n_out is the number copied. */
 sl_status sl_observables(sl_system h, sl_obs* out, int64_t max_samples, int64_t* n_out);
 
-/* Waits, then copies the state to host arrays in canonical order (any
+/* The dynamical state of Methods A and B (positions, velocities, spins,
+ * electron temperatures).
+ * Waits, then copies the state to host arrays in canonical order (any
  * pointer may be NULL): positions wrapped into the box [n][3], velocities
  * [n][3], spins [n][3], electron temperatures [cells]. */
 sl_status sl_get_state(sl_system h, double* x, double* v, double* s, double* Te);
 
-/* Waits, then replaces parts of the state from host arrays in canonical
+/* Checkpoint restore of the state of Methods A and B.
+ * Waits, then replaces parts of the state from host arrays in canonical
  * order (checkpoint restore; any pointer may be NULL to keep the current
  * values): positions [n][3] in A (any periodic image; stored as the
  * minimum-image displacement from the ideal site), velocities [n][3] in A/ps
@@ -252,17 +265,20 @@ typedef struct {
     int32_t error;            /* the run's error bits (0: none; nonzero: frozen)     */
 } sl_run_stats;
 
-/* Waits, then reads the run's counters.  SL_EINVAL for a null output. */
+/* Waits, then reads the run's counters (the neighbour lists of the live
+ * lattice of Methods A, the error bits).  SL_EINVAL for a null output. */
 sl_status sl_stats(sl_system h, sl_run_stats* out);
 
 /* Number of sites, electron cells and completed steps (host view). */
 sl_status sl_info(sl_system h, int64_t* n_sites, int64_t* n_cells, int64_t* steps);
 
-/* Device bytes a run with this description would hold. */
+/* Device bytes a run with this description would hold (the admission test
+ * of batches of replicas, Methods F). */
 sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
                              size_t* bytes);
 
-/* Runs n_steps (at most 4096) launching every kernel directly, each timed
+/* Measurement, no passage of the method: the steps of sl_step, with timings.
+ * Runs n_steps (at most 4096) launching every kernel directly, each timed
  * by HIP events stamped by its own dispatch; returns the average device time
  * (ms) per launch of each kernel class and the launch counts: 0 spin colour
  * pass, 1 neighbour-list rebuild (when due), lattice forces and
@@ -272,7 +288,8 @@ sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
  * for all steps). */
 sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5]);
 
-/* Launch shape of the step kernels.  Every choice performs the same
+/* Launch shape of the step kernels (no passage of the method: a choice of
+ * the implementation).  Every choice performs the same
  * arithmetic in the same order for each site, atom and cell, so results are
  * bitwise identical; only the speed changes (an autotuner picks it). */
 typedef struct sl_tuning {
@@ -353,16 +370,18 @@ typedef struct sl_run_info {
     int64_t n_samples;        /* samples recorded so far                          */
 } sl_run_info;
 
+/* An empty batch of replica slots (Methods F). */
 sl_status sl_batch_create(const sl_batch_desc* desc, sl_batch* out);
 
-/* Admits a run that will take n_steps steps (desc->precision, stream and
+/* Admits a replica (Methods F; its setup as sl_init_system and
+ * sl_set_ttm_grid) that will take n_steps steps (desc->precision, stream and
  * alloc are ignored: the batch's apply).  SL_EBUSY when no slot is free,
  * SL_ENOMEM when its footprint does not fit the remaining budget. */
 sl_status sl_batch_add(sl_batch b, const sl_system_desc* desc, const sl_ttm_desc* ttm,
                        int64_t n_steps, int32_t* slot);
 
-/* Enqueues up to n_steps steps for every active run (a run stops at its
- * target).  Asynchronous. */
+/* Enqueues up to n_steps steps (as sl_step: Methods A-C) for every active
+ * run (a run stops at its target).  Asynchronous. */
 sl_status sl_batch_advance(sl_batch b, int64_t n_steps);
 
 /* Waits, then reads the counters of the run in a slot (as sl_stats).

@@ -401,36 +401,31 @@ template <typename T, typename VW>
 __device__ __forceinline__ V3<T> separation(const RunDev<T>& R, const VW& V, const Pos4<T>& pi,
                                             uint32_t j);
 
-template <typename T, typename VW, int LAT, bool MULTI, bool RADIAL = false>
-__device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V, int k, const Around& a,
-                                                int sp)
+// The exchange sum over the first NN bonds of B (a compile-time count, so
+// that no term is selected per lane).
+template <typename T, typename VW, int LAT, bool MULTI, bool RADIAL, int NN>
+__device__ __forceinline__ V3<T> exchange_sum_n(const RunDev<T>& R, const VW& V, int k, const Around& a,
+                                                const Bonds<LAT>& B, int sp)
 {
     using M = typename VW::Mem;
-    constexpr int NN = Bonds<LAT>::NB;
     const uint32_t H = (uint32_t)R.g.H;
-    const Bonds<LAT> B = bond_list<LAT>(R, k, a);
-    const int nn = B.nn;
     T ax[NN], ay[NN], az[NN];
     int sj[NN];
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
-        if (q < nn) {
-            const uint32_t cb = B.col[q] * H;
-            ax[q] = M::ld(V.sx + cb, B.off[q]);
-            ay[q] = M::ld(V.sy + cb, B.off[q]);
-            az[q] = M::ld(V.sz + cb, B.off[q]);
-            sj[q] = MULTI ? (int)M::ld(V.species + cb, B.off[q]) : 0;
-        }
+        const uint32_t cb = B.col[q] * H;
+        ax[q] = M::ld(V.sx + cb, B.off[q]);
+        ay[q] = M::ld(V.sy + cb, B.off[q]);
+        az[q] = M::ld(V.sz + cb, B.off[q]);
+        sj[q] = MULTI ? (int)M::ld(V.species + cb, B.off[q]) : 0;
     }
     T fr[NN];
     if constexpr (RADIAL) {
         const Pos4<T> pi = VW::PosMem::ld(V.pos, (uint32_t)k * H + a.x0 + a.y0 + a.z0);
 #pragma unroll
         for (int q = 0; q < NN; ++q) {
-            if (q < nn) {
-                const V3<T> d = separation(R, V, pi, B.col[q] * H + B.off[q]);
-                fr[q] = radial_f(R, B.sh[q], d.x * d.x + d.y * d.y + d.z * d.z);
-            }
+            const V3<T> d = separation(R, V, pi, B.col[q] * H + B.off[q]);
+            fr[q] = radial_f(R, B.sh[q], d.x * d.x + d.y * d.y + d.z * d.z);
         }
     }
     T row[2][4];
@@ -443,17 +438,27 @@ __device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V,
     V3<T> h{T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
-        if (q < nn) {
-            T Jv = !MULTI ? row[B.sh[q]][0]
-                   : B.sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
-                                  : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
-            if constexpr (RADIAL) Jv *= fr[q];
-            h.x += Jv * ax[q];
-            h.y += Jv * ay[q];
-            h.z += Jv * az[q];
-        }
+        T Jv = !MULTI ? row[B.sh[q]][0]
+               : B.sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
+                              : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
+        if constexpr (RADIAL) Jv *= fr[q];
+        h.x += Jv * ax[q];
+        h.y += Jv * ay[q];
+        h.z += Jv * az[q];
     }
     return h;
+}
+
+template <typename T, typename VW, int LAT, bool MULTI, bool RADIAL = false>
+__device__ __forceinline__ V3<T> exchange_sum_t(const RunDev<T>& R, const VW& V, int k, const Around& a,
+                                                int sp)
+{
+    const Bonds<LAT> B = bond_list<LAT>(R, k, a);
+    // bcc with one shell uses the first 8 bonds (a branch uniform per run)
+    if constexpr (LAT == SL_LATTICE_BCC) {
+        if (B.nn < Bonds<LAT>::NB) return exchange_sum_n<T, VW, LAT, MULTI, RADIAL, 8>(R, V, k, a, B, sp);
+    }
+    return exchange_sum_n<T, VW, LAT, MULTI, RADIAL, Bonds<LAT>::NB>(R, V, k, a, B, sp);
 }
 
 // The radial bonds' force on the atom at site (k, a) with spin s and wrapped
