@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import argparse
 import contextlib
+import dataclasses
 import gc
 import json
 import math
@@ -75,7 +76,7 @@ def measured_traffic(kernel: str, workload: str, tuning=None):
 
 
 
-def measured_valu_per_site_step(workload: str = "production16_fp32"):
+def measured_valu_per_site_step(workload: str = "production13fcc_fp32"):
     """VALU wave instructions per site-step of the persistent kernel on
     `workload`, from the committed rocprofv3 counter summary, or None when
     there is none or the kernels changed since the counters were taken."""
@@ -362,7 +363,7 @@ def batched_phase_diagram(N, W, n_steps: int, n_seeds: int) -> dict:
 
 
 def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int = 2000,
-                             lattice: str = "fcc", L: int = 13) -> dict:
+                             lattice: str = "fcc", L: int = 13, tuning=None) -> dict:
     """The production phase diagram: 8 peak T_e (800-2900 K) x 8 cooling
     multipliers (d = 1-8) x seeds of the paper's production model (fcc
     13^3, 8788 sites, exactly 2197 Gd, the literature exchange, moments and
@@ -374,7 +375,10 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int 
     runs = W.production_diagram(L=L, n_seeds=n_seeds, n_steps=n_steps, base_ends=base_ends,
                                 lattice=lattice)
     n_sites = runs[0].spec.n_sites
+    if not tuning:
+        tuning = tune_batch(N, [(r.spec, r.state) for r in runs], N.SL_FP32, n_steps)
     b = N.Batch(precision=N.SL_FP32, max_runs=len(runs))
+    b.set_tuning(**tuning)
     slots = [b.add(r.spec, r.state, r.n_steps, obs_every=20, obs_capacity=n_steps // 20 + 2)
              for r in runs]
     b.synchronize()
@@ -421,6 +425,7 @@ def production_phase_diagram(N, W, n_steps: int, n_seeds: int, plain_steps: int 
         "wilson_halfwidth_max": float(max(h - l for l, h in ci) / 2),
         "stage_note": "the paper gives the stage temperatures and that d scales the durations, "
                       "not the base durations: %g ps and %g ps here" % base_ends,
+        "tuning": tuning,
     }
     # the batch is bound by VALU issue: 256 CUs x 2.4 GHz, one wave64
     # instruction per CU per cycle (four SIMDs, four cycles each)
@@ -641,7 +646,7 @@ def strain_profile(spec, x) -> np.ndarray:
     return strain_zz_profile(spec.ncell, spec.lattice, spec.a, x)
 
 
-def field_llg_scale(N, I, L: int = 256, tuning=None) -> dict:
+def field_llg_scale(N, I, L: int = 256, tuning=None, variants: bool = True) -> dict:
     """The field + LLG colour pass alone (frozen lattice, constant bath) on
     bcc Fe L^3 in FP32, large enough (2 L^3 sites) that the spins do not fit
     in the 256 MB last-level cache: achieved algorithmic bandwidth of one
@@ -675,7 +680,49 @@ def field_llg_scale(N, I, L: int = 256, tuning=None) -> dict:
            "traffic_bytes_per_launch": None if traffic is None else int(traffic)}
     if traffic is not None:
         out["traffic_GBs"] = round(traffic / (us * 1e-6) / 1e9, 1)
+    if variants:
+        # the same pass without a thermal field (alpha = 0: no Philox block,
+        # no Box-Muller, about a third fewer instructions per site): how much
+        # of the time the instruction stream sets
+        quiet = dataclasses.replace(spec, alpha=0.0)
+        st = I.initial_state(quiet, "tilt")
+        s = N.System(quiet, st, precision=N.SL_FP32, obs_every=0)
+        del st
+        s.step(4)
+        s.set_tuning(**tuning)
+        s.step(8)
+        s.synchronize()
+        avg_q, _ = s.step_profiled(10)
+        s.close()
+        out["no_thermal_field_avg_launch_us"] = round(avg_q[0] * 1e3, 3)
+        # what a plain streaming copy reaches, against which the pass's real
+        # traffic rate is read
+        out["device_copy_GBs"] = round(copy_bandwidth(), 1)
+        if traffic is not None:
+            out["traffic_over_device_copy"] = round(out["traffic_GBs"] / out["device_copy_GBs"], 3)
     return out
+
+
+def copy_bandwidth() -> float:
+    """Read plus write GB/s of a plain 1 GiB device-to-device copy (torch's
+    copy kernel, ten copies timed with events): what a streaming kernel
+    reaches on this GPU, against the 8 TB/s peak."""
+    import torch
+    n = 256 << 20
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (ms * 1e-3) / 1e9
 
 
 def copy_calibration() -> int:
@@ -725,6 +772,9 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
     ap.add_argument("--large-steps", type=int, default=500)
+    ap.add_argument("--prod-tuning", default="",
+                    help="JSON launch shape for the production batch ('' autotunes on a probe "
+                         "batch; a fixed shape keeps counter runs to the measured dispatches)")
     ap.add_argument("--scale-tuning", default=SCALE_TUNING,
                     help="JSON launch shape for the 256^3 field+LLG row ('' autotunes); the "
                          "default is the shape the autotuner picked, fixed so that the committed "
@@ -830,7 +880,9 @@ def main() -> int:
     if "production" in extras:
         out["production"] = production_phase_diagram(N, W, args.prod_steps, args.prod_seeds,
                                                      args.prod_plain_steps, args.prod_lattice,
-                                                     args.prod_L)
+                                                     args.prod_L,
+                                                     json.loads(args.prod_tuning)
+                                                     if args.prod_tuning else None)
     if "field" in extras:
         out["field_dependence"] = field_dependence(N, W, args.prod_steps, args.field_seeds,
                                                    args.field_T0, args.field_d, args.prod_lattice,
@@ -845,7 +897,7 @@ def main() -> int:
         row = field_llg_scale(N, I, tuning=json.loads(args.scale_tuning) if args.scale_tuning else None)
         sweep = []
         for L in (128, 192):
-            r = field_llg_scale(N, I, L=L, tuning=row["tuning"])
+            r = field_llg_scale(N, I, L=L, tuning=row["tuning"], variants=False)
             sweep.append({k: r[k] for k in ("workload", "avg_launch_us", "achieved_GBs", "frac")})
         row["sweep_same_tuning"] = sweep
         out["field_llg_scale"] = row
