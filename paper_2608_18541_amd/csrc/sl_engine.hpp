@@ -98,12 +98,12 @@ inline void launch(void (*k)(KA...), dim3 grid, dim3 block, uint32_t shmem, hipS
 // neighbouring rows and planes of a tile in the same L2.  Any order gives the
 // same results; only the cache traffic changes.
 constexpr size_t kXcds = sl::kXcdCount;
-inline void xcd_order(std::vector<int2>& t)
+template <typename E> inline void xcd_order(std::vector<E>& t)
 {
     const size_t m = t.size();
     if (m < 2 * kXcds) return;
     const size_t per = (m + kXcds - 1) / kXcds;
-    std::vector<int2> o;
+    std::vector<E> o;
     o.reserve(m);
     for (size_t j = 0; j < per; ++j)
         for (size_t x = 0; x < kXcds; ++x) {
@@ -371,6 +371,7 @@ public:
     int bin_mode = 0;               // 0 automatic, 1 kick bins every step, 2 rebuild only
     int atom_lanes = 0;             // lanes per atom in k_atom_final (0: by the atom count)
     int merge_sweeps = 1;           // 1: merge adjacent colour half steps when possible
+    int spin_tile = 0;              // 1: LDS-staged colour passes where they apply
     int merge_g = 0;                // >= 2: steps per merged chunk of the multi-kernel runs
     int merge_run = -1;             // a stepping run among them (its step gives the chunk phase)
     std::vector<int> mk_runs;       // the runs on the multi-kernel step
@@ -437,6 +438,18 @@ public:
         SL_HIP(hipFuncGetAttributes(&ta, tk));
         tile_lds_max = per_block > (int)ta.sharedSizeBytes ? (uint32_t)(per_block - (int)ta.sharedSizeBytes) : 0u;
         SL_HIP(hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds_max));
+        const void* sk[3] = {reinterpret_cast<const void*>(&sl::k_spin_tile_bcc<T, 2, 2>),
+                             reinterpret_cast<const void*>(&sl::k_spin_tile_bcc<T, 4, 4>),
+                             reinterpret_cast<const void*>(&sl::k_spin_tile_bcc<T, 4, 4, 1024>)};
+        int sk_static = 0;
+        for (const void* f : sk) {
+            hipFuncAttributes fa{};
+            SL_HIP(hipFuncGetAttributes(&fa, f));
+            sk_static = std::max(sk_static, (int)fa.sharedSizeBytes);
+        }
+        stile_lds_max = per_block > sk_static ? (uint32_t)(per_block - sk_static) : 0u;
+        for (const void* f : sk)
+            SL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)stile_lds_max));
         return SL_OK;
     }
 
@@ -590,7 +603,11 @@ public:
         d_run_list = ints;
         d_persist_list = ints + 1;
         graph_ok = false;
+        // (the LDS-staged pass's tile table is not built here: the
+        // specialised pass, which gives the same bits, runs instead)
+        stile_on = false;
         const sl_status st = advance_core(n, false);
+        stile_on = true;
         d_work_spin = keep_w[0];
         d_work_atom = keep_w[1];
         d_work_kick = keep_w[2];
@@ -956,6 +973,15 @@ private:
     bool persist_radial = false;    // a persistent run with radial exchange
     int lean_lat = -1;              // >= 0: the runs' lattice for the specialised colour pass
     int lean_multi = 0;             // ... and whether they have several species
+    // the LDS-staged colour pass (bcc, one species, constant exchange):
+    // 0 off, 1 tiles of 2 x 2 rows, 2 tiles of 4 x 4 rows, 3 tiles of 4 x 4
+    // rows in 1024-thread blocks
+    int stile = 0;
+    bool stile_on = true;           // off while the allocation-free entry point steps
+    int4* d_work_stile = nullptr;   // block: run, first row, first plane
+    int active_blocks_stile = 0;
+    uint32_t stile_bytes = 0;       // the LDS of its launch
+    uint32_t stile_lds_max = 0;     // dynamic LDS available to it
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
     // graphs of merged chunks shorter than merge_g, by length (a chunk's
@@ -1325,6 +1351,7 @@ private:
     // in the persistent kernel (pl).
     struct Tables {
         std::vector<int2> ws, wa, wk, wc, wd, wt;
+        std::vector<int4> wst;      // LDS-staged colour-pass tiles
         std::vector<int> rl, pl;
     };
 
@@ -1474,6 +1501,53 @@ private:
                 lean_multi = R0.n_species > 1 ? 1 : 0;
             }
         }
+        // the LDS-staged colour pass: bcc runs with one species, tiles of
+        // 2 x 2 rows (4 x 4 when rows are shorter than 64 sites), when the
+        // tile divides every run's rows and planes, a row holds whole 16-byte
+        // vectors (at most one per thread of the block), the spin arrays are
+        // 16-byte aligned and the rows fit in LDS
+        stile = 0;
+        stile_bytes = 0;
+        if (spin_tile && lean_lat == SL_LATTICE_BCC && !lean_multi && !rl.empty()) {
+            const uint32_t vec = 16u / (uint32_t)sizeof(T);
+            bool small = false;
+            for (int s : rl) small = small || host_rd[s].g.Lxh < 64;
+            // long rows: 4 x 4 tiles in 1024-thread blocks while they fit in
+            // LDS (one block per CU), else 2 x 2 in 256-thread blocks
+            auto fits = [&](int kind) {
+                bool ok = true;
+                for (int s : rl) {
+                    const RD& R = host_rd[s];
+                    const int t = kind == 1 ? 2 : 4;
+                    const uint32_t nt = kind == 3 ? 1024u : (uint32_t)sl::kBlock;
+                    const uint32_t b = kind == 1 ? sl::tile_lds_bytes<2, 2>((uint32_t)R.g.Lxh, sizeof(T))
+                                                 : sl::tile_lds_bytes<4, 4>((uint32_t)R.g.Lxh, sizeof(T));
+                    const auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+                    ok = ok && R.g.Ly % t == 0 && R.g.Lz % t == 0 && (uint32_t)R.g.Lxh % vec == 0 &&
+                         (uint32_t)R.g.Lxh <= nt * vec && al(R.sx) && al(R.sy) && al(R.sz) &&
+                         b <= stile_lds_max;
+                }
+                return ok;
+            };
+            const int kind = small ? (fits(2) ? 2 : 0) : (fits(3) ? 3 : (fits(1) ? 1 : 0));
+            const int t = kind == 1 ? 2 : 4;
+            uint32_t bytes = 0;
+            for (int s : rl)
+                bytes = std::max(bytes, kind == 1 ? sl::tile_lds_bytes<2, 2>((uint32_t)host_rd[s].g.Lxh, sizeof(T))
+                                                  : sl::tile_lds_bytes<4, 4>((uint32_t)host_rd[s].g.Lxh, sizeof(T)));
+            if (kind > 0) {
+                stile = kind;
+                stile_bytes = bytes;
+                for (int s : rl) {
+                    const RD& R = host_rd[s];
+                    for (int z0 = 0; z0 < R.g.Lz; z0 += t)
+                        for (int y0 = 0; y0 < R.g.Ly; y0 += t) tb.wst.push_back(make_int4(s, y0, z0, 0));
+                }
+                // each XCD takes one contiguous range of tiles, so the rows two
+                // neighbouring tiles both stage come through the same L2
+                xcd_order(tb.wst);
+            }
+        }
         // runs with radial exchange kick after the whole sweep, so no step
         // may leave its last colour pass to the next one
         if (merge_sweeps && !rl.empty() && !any_radial) {
@@ -1526,6 +1600,7 @@ private:
         active_blocks_cell = (int)wc.size();
         active_blocks_diff = (int)wd.size();
         active_blocks_tile = (int)wt.size();
+        active_blocks_stile = (int)tb.wst.size();
         active_runs = (int)rl.size();
         persist_runs = (int)pl.size();
         persist_radial = false;
@@ -1538,6 +1613,7 @@ private:
         for (void* p : tables) alloc.put(p);
         tables.clear();
         d_work_spin = d_work_atom = d_work_kick = d_work_cell = d_work_diff = d_work_tile = nullptr;
+        d_work_stile = nullptr;
         d_run_list = nullptr;
         d_persist_list = nullptr;
         auto up = [&](const void* src, size_t bytes, void** dst) -> sl_status {
@@ -1556,6 +1632,7 @@ private:
         if ((st = up(tb.wc.data(), sizeof(int2) * tb.wc.size(), (void**)&d_work_cell)) != SL_OK) return st;
         if ((st = up(tb.wd.data(), sizeof(int2) * tb.wd.size(), (void**)&d_work_diff)) != SL_OK) return st;
         if ((st = up(tb.wt.data(), sizeof(int2) * tb.wt.size(), (void**)&d_work_tile)) != SL_OK) return st;
+        if ((st = up(tb.wst.data(), sizeof(int4) * tb.wst.size(), (void**)&d_work_stile)) != SL_OK) return st;
         if ((st = up(tb.rl.data(), sizeof(int) * tb.rl.size(), (void**)&d_run_list)) != SL_OK) return st;
         if ((st = up(tb.pl.data(), sizeof(int) * tb.pl.size(), (void**)&d_persist_list)) != SL_OK) return st;
         SL_HIP(hipStreamSynchronize(stream));
@@ -1612,6 +1689,19 @@ private:
             sl_status e = timed(st, p, fused ? 2 : 0, [&](hipEvent_t a, hipEvent_t b) {
                 const dim3 g(active_blocks_spin + nk);
                 if (nk == 0 && merge == 0 && lean_lat >= 0) {
+                    if (stile > 0 && stile_on) {
+                        const dim3 gt(active_blocks_stile), bt2(sl::kBlock);
+                        if (stile == 1)
+                            launch(sl::k_spin_tile_bcc<T, 2, 2>, gt, bt2, stile_bytes, st, a, b, d_runs,
+                                   d_work_stile, pass, fold_k);
+                        else if (stile == 2)
+                            launch(sl::k_spin_tile_bcc<T, 4, 4>, gt, bt2, stile_bytes, st, a, b, d_runs,
+                                   d_work_stile, pass, fold_k);
+                        else
+                            launch(sl::k_spin_tile_bcc<T, 4, 4, 1024>, gt, dim3(1024), stile_bytes, st, a,
+                                   b, d_runs, d_work_stile, pass, fold_k);
+                        return;
+                    }
                     launch_lean(g, bs, st, a, b, pass, fold_k);
                     return;
                 }

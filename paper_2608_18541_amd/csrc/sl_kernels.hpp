@@ -401,6 +401,36 @@ template <typename T, typename VW>
 __device__ __forceinline__ V3<T> separation(const RunDev<T>& R, const VW& V, const Pos4<T>& pi,
                                             uint32_t j);
 
+// h = sum_q J_q s_q over NN neighbour spins already loaded, in bond order:
+// the coupling of bond q by its shell sh[q] (and the neighbour's species
+// sj[q]; times the radial factor fr[q] with radial exchange).  Every colour
+// pass sums the field here, whichever memory its neighbours came from.
+template <typename T, bool MULTI, bool RADIAL, int NN>
+__device__ __forceinline__ V3<T> exchange_accum(const RunDev<T>& R, const int* sh, const T* ax,
+                                                const T* ay, const T* az, const int* sj,
+                                                const T* fr, int sp)
+{
+    T row[2][4];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            row[s2][t] = MULTI ? select4(sp, R.J[s2][0][t], R.J[s2][1][t], R.J[s2][2][t], R.J[s2][3][t])
+                               : R.J[s2][0][0];
+    V3<T> h{T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+        T Jv = !MULTI ? row[sh[q]][0]
+               : sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
+                            : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
+        if constexpr (RADIAL) Jv *= fr[q];
+        h.x += Jv * ax[q];
+        h.y += Jv * ay[q];
+        h.z += Jv * az[q];
+    }
+    return h;
+}
+
 // The exchange sum over the first NN bonds of B (a compile-time count, so
 // that no term is selected per lane).
 template <typename T, typename VW, int LAT, bool MULTI, bool RADIAL, int NN>
@@ -428,25 +458,7 @@ __device__ __forceinline__ V3<T> exchange_sum_n(const RunDev<T>& R, const VW& V,
             fr[q] = radial_f(R, B.sh[q], d.x * d.x + d.y * d.y + d.z * d.z);
         }
     }
-    T row[2][4];
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            row[s2][t] = MULTI ? select4(sp, R.J[s2][0][t], R.J[s2][1][t], R.J[s2][2][t], R.J[s2][3][t])
-                               : R.J[s2][0][0];
-    V3<T> h{T(0), T(0), T(0)};
-#pragma unroll
-    for (int q = 0; q < NN; ++q) {
-        T Jv = !MULTI ? row[B.sh[q]][0]
-               : B.sh[q] == 0 ? select4(sj[q], row[0][0], row[0][1], row[0][2], row[0][3])
-                              : select4(sj[q], row[1][0], row[1][1], row[1][2], row[1][3]);
-        if constexpr (RADIAL) Jv *= fr[q];
-        h.x += Jv * ax[q];
-        h.y += Jv * ay[q];
-        h.z += Jv * az[q];
-    }
-    return h;
+    return exchange_accum<T, MULTI, RADIAL, NN>(R, B.sh, ax, ay, az, sj, fr, sp);
 }
 
 template <typename T, typename VW, int LAT, bool MULTI, bool RADIAL = false>
@@ -725,18 +737,16 @@ __device__ inline double cell_energy(const RunDev<T>& R, double e0, unsigned lon
 template <typename T> __device__ inline double cell_e0(const RunDev<T>& R, double T0);
 __device__ inline double cell_temp(double e, double ge);
 
-template <typename T, typename VW, int LAT, bool MULTI, bool ANISO, bool RADIAL = false>
-__device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int colour, T tau,
-                                            uint32_t l, int64_t step, bool cur = true,
-                                            bool has_prev = false, PrevHalf prev = {})
+// The rest of a site update once its exchange sum h (eV) is known: the
+// field, the thermal field of each rotation and the exact flows, from the
+// site's own spin s; returns the new spin.  `bad` is set by the watchdog.
+template <typename T, typename VW, int LAT, bool MULTI, bool ANISO>
+__device__ __forceinline__ V3<T> site_rotate(const RunDev<T>& R, const VW& V, int colour, T tau,
+                                             const Cell3& c, uint32_t idx, int sp, const V3<T>& h,
+                                             V3<T> s, int64_t step, bool cur, bool has_prev,
+                                             const PrevHalf& prev, bool& bad)
 {
     using M = typename VW::Mem;
-    const Cell3 c = cell_of(R.g, colour, l);
-    const Around a = around(R.g, c.x, c.xh, c.y, c.z);
-    const uint32_t kH = (uint32_t)colour * (uint32_t)R.g.H;
-    const uint32_t idx = kH + l;
-    const int sp = MULTI ? (int)M::ld(V.species, idx) : 0;
-    const V3<T> h = exchange_sum_t<T, VW, LAT, MULTI, RADIAL>(R, V, colour, a, sp);
     const T imu = MULTI ? select4(sp, R.inv_mumb[0], R.inv_mumb[1], R.inv_mumb[2], R.inv_mumb[3])
                         : R.inv_mumb[0];
     const T H0x = h.x * imu + R.B[0];
@@ -746,7 +756,6 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
     const uint32_t canon =
         __umul24(__umul24(c.z, (uint32_t)R.g.Ly) + c.y, (uint32_t)R.g.Lx) * (uint32_t)R.g.nb +
         c.x * (uint32_t)R.g.nb + (uint32_t)b;
-    bool bad = false;   // the watchdog: a spin that was not a finite unit vector
     // one exact rotation over tau_ with the thermal field of step stp at T_e
     auto rotate = [&](V3<T> s0, int64_t stp, double Te, T tau_) {
         T Hx = H0x, Hy = H0y, Hz = H0z;
@@ -766,7 +775,6 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
         const V3<T> wv{R.gam * Hx, R.gam * Hy, R.gam * Hz};
         return llg_flow(s0, wv, R.alpha, tau_, R.inv1pa2, bad);
     };
-    V3<T> s{M::ld(V.sx + kH, l), M::ld(V.sy + kH, l), M::ld(V.sz + kH, l)};
     if (has_prev) {
         const double Te = R.noisy ? gld(prev.Te, (uint32_t)gld(prev.cell, idx)) : 0.0;
         s = rotate(s, step - 1, Te, R.tau_half);
@@ -784,6 +792,25 @@ __device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int
         }
         s = rotate(s, step, Te, tau);
     }
+    return s;
+}
+
+template <typename T, typename VW, int LAT, bool MULTI, bool ANISO, bool RADIAL = false>
+__device__ __forceinline__ void spin_site_t(const RunDev<T>& R, const VW& V, int colour, T tau,
+                                            uint32_t l, int64_t step, bool cur = true,
+                                            bool has_prev = false, PrevHalf prev = {})
+{
+    using M = typename VW::Mem;
+    const Cell3 c = cell_of(R.g, colour, l);
+    const Around a = around(R.g, c.x, c.xh, c.y, c.z);
+    const uint32_t kH = (uint32_t)colour * (uint32_t)R.g.H;
+    const uint32_t idx = kH + l;
+    const int sp = MULTI ? (int)M::ld(V.species, idx) : 0;
+    const V3<T> h = exchange_sum_t<T, VW, LAT, MULTI, RADIAL>(R, V, colour, a, sp);
+    bool bad = false;   // the watchdog: a spin that was not a finite unit vector
+    V3<T> s{M::ld(V.sx + kH, l), M::ld(V.sy + kH, l), M::ld(V.sz + kH, l)};
+    s = site_rotate<T, VW, LAT, MULTI, ANISO>(R, V, colour, tau, c, idx, sp, h, s, step, cur,
+                                              has_prev, prev, bad);
     M::st(V.sx + kH, l, s.x);
     M::st(V.sy + kH, l, s.y);
     M::st(V.sz + kH, l, s.z);
@@ -1676,6 +1703,214 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass_lean(const RunDev<T>* __re
     for (int k = 0; k < SPT; ++k) {
         const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
         if (l < (uint32_t)R.g.H) spin_site_t<T, GView<T>, LAT, MULTI, false>(R, V, colour, tau, l, step);
+    }
+}
+
+// ------------------------------------------------ LDS-staged colour pass
+// A colour pass of bcc runs with one species and constant exchange (the
+// runs the specialised pass takes) in which a block updates a tile of
+// TY x TZ whole rows of its colour (rows y0 <= y < y0 + TY, planes
+// z0 <= z < z0 + TZ, every x) from rows staged in LDS.  First the block
+// copies, with 16-byte loads, every row its sites read: the other basis's
+// two colours on (TY + 1)(TZ + 1) rows (the first shell lies half a cell
+// away along every axis), the same basis's other colour on (TY + 2)(TZ + 2)
+// rows (the second shell, one cell away along one axis) and its own
+// colour's TY TZ rows.  Then each site gathers its 14 (or 8) neighbours from
+// LDS and runs the pass's own field sum, in bond order, and rotation, so the
+// results have the same bits as the pass that gathers from global memory.
+// What changes is the memory instruction stream: one 16-byte load per four
+// (FP32) or two (FP64) sites of a staged row instead of one 4- or 8-byte
+// gather per neighbour component, which the gathers' address processing had
+// made the limit of the pass at scale.
+// Staged row slots: [0, 2 NA) the other basis's colours (colour 2(1 - b)
+// first), [2 NA, 2 NA + NB) the second shell's colour, then the own rows;
+// slot s holds its three spin components as rows of Lxh values at
+// (3 s + comp) Lxh.
+template <int TY, int TZ> struct TileRows {
+    static constexpr int NA = (TY + 1) * (TZ + 1);
+    static constexpr int NB = (TY + 2) * (TZ + 2);
+    static constexpr int NOWN = TY * TZ;
+    static constexpr int N = 2 * NA + NB + NOWN;
+};
+
+// Rows of the staged tile in LDS bytes, for the host's launch.
+template <int TY, int TZ> __host__ __device__ constexpr uint32_t tile_lds_bytes(uint32_t Lxh, uint32_t tsize)
+{
+    return (uint32_t)TileRows<TY, TZ>::N * 3u * Lxh * tsize;
+}
+
+template <typename T, int TY, int TZ, int NT = kBlock>
+__global__ __launch_bounds__(NT) void k_spin_tile_bcc(const RunDev<T>* __restrict__ runs,
+                                                      const int4* __restrict__ work, int pass,
+                                                      int fold_k)
+{
+    typedef TileRows<TY, TZ> TR;
+    extern __shared__ __align__(16) unsigned char tile_smem[];
+    T* rows = reinterpret_cast<T*>(tile_smem);
+    __shared__ int32_t b_go;
+    __shared__ uint32_t b_off[TR::N];
+    const int4 w = work[blockIdx.x];   // run, first row y0, first plane z0
+    const RunDev<T>& R = runs[w.x];
+    const RunState* st = R.st;
+    // the run's state, read once for the block: every thread takes the same
+    // branch at the barrier even if another block raises an error meanwhile
+    if (threadIdx.x == 0)
+        b_go = fold_ok(st, fold_k) && step_at(R, fold_k) < st->target && pass < 2 * R.g.C - 1;
+    __syncthreads();
+    if (!b_go) return;
+    const int64_t step = step_at(R, fold_k);
+    int colour;
+    T tau;
+    pass_colour(R, pass, &colour, &tau);
+    GView<T> V = global_view(R, step);
+    if (fold_k >= 0) V.Te = te_buf(R, fold_k);
+    const uint32_t Lxh = (uint32_t)R.g.Lxh, Ly = (uint32_t)R.g.Ly, Lz = (uint32_t)R.g.Lz;
+    const uint32_t H = (uint32_t)R.g.H;
+    const int b = colour >> 1, p = colour & 1;
+    const int y0 = w.y, z0 = w.z;
+    // ---- staging.  First each staged row's offset in its colour-major
+    // arrays, once per block; then the rows themselves as 16-byte vectors,
+    // consecutive lanes along a row, a group of spb rows per sweep of the
+    // block (the host keeps Lxh <= NT vectors)
+    if (threadIdx.x < (uint32_t)TR::N) {
+        const int slot = (int)threadIdx.x;
+        int col, gy, gz;
+        if (slot < 2 * TR::NA) {
+            const int cc = slot / TR::NA, q = slot - cc * TR::NA;
+            const int lz = q / (TY + 1), ly = q - lz * (TY + 1);
+            col = 2 * (1 - b) + cc;
+            gy = y0 - (b == 0 ? 1 : 0) + ly;
+            gz = z0 - (b == 0 ? 1 : 0) + lz;
+        } else if (slot < 2 * TR::NA + TR::NB) {
+            const int q = slot - 2 * TR::NA;
+            const int lz = q / (TY + 2), ly = q - lz * (TY + 2);
+            col = 2 * b + (1 - p);
+            gy = y0 - 1 + ly;
+            gz = z0 - 1 + lz;
+        } else {
+            const int q = slot - 2 * TR::NA - TR::NB;
+            const int lz = q / TY, ly = q - lz * TY;
+            col = colour;
+            gy = y0 + ly;
+            gz = z0 + lz;
+        }
+        gy = gy < 0 ? gy + (int)Ly : (gy >= (int)Ly ? gy - (int)Ly : gy);
+        gz = gz < 0 ? gz + (int)Lz : (gz >= (int)Lz ? gz - (int)Lz : gz);
+        b_off[slot] = (uint32_t)col * H + Lxh * ((uint32_t)gy + Ly * (uint32_t)gz);
+    }
+    __syncthreads();
+    constexpr uint32_t VEC = 16u / (uint32_t)sizeof(T);
+    typedef typename Vec4<float>::type F4;
+    {
+        const uint32_t e0 = threadIdx.x * VEC;
+        const uint32_t slot0 = fdiv(e0, R.g.divLxh);          // first row of this lane
+        const uint32_t j = e0 - slot0 * Lxh;                  // its vector in the row
+        const uint32_t spb = fdiv(blockDim.x * VEC, R.g.divLxh);   // rows per sweep
+        const uint32_t rstride = 3u * Lxh * (uint32_t)sizeof(T);   // bytes per staged row
+        const uint32_t cstride = Lxh * (uint32_t)sizeof(T);        // bytes per component
+        // up to U rows' loads in flight before their stores to LDS
+        constexpr int U = NT >= 1024 ? 4 : 8;
+        for (uint32_t base = slot0; slot0 < spb && base < (uint32_t)TR::N; base += U * spb) {
+            F4 vx[U], vy[U], vz[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t slot = base + (uint32_t)u * spb;
+                if (slot < (uint32_t)TR::N) {
+                    const uint32_t go = (b_off[slot] + j) * (uint32_t)sizeof(T);
+                    vx[u] = *(const SL_GLOBAL F4*)((const SL_GLOBAL char*)V.sx + go);
+                    vy[u] = *(const SL_GLOBAL F4*)((const SL_GLOBAL char*)V.sy + go);
+                    vz[u] = *(const SL_GLOBAL F4*)((const SL_GLOBAL char*)V.sz + go);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t slot = base + (uint32_t)u * spb;
+                if (slot < (uint32_t)TR::N) {
+                    SL_LDS char* dst = (SL_LDS char*)rows + __umul24(slot, rstride) + j * (uint32_t)sizeof(T);
+                    *(SL_LDS F4*)dst = vx[u];
+                    *(SL_LDS F4*)(dst + cstride) = vy[u];
+                    *(SL_LDS F4*)(dst + 2u * cstride) = vz[u];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- the tile's sites
+    const uint32_t nsite = (uint32_t)(TY * TZ) * Lxh;
+    const bool two = R.n_shells > 1;
+    const uint32_t L3 = 3u * Lxh;   // elements per staged row
+    // each bond's staged row relative to the site's own row in its group
+    // (uniform over the block: scalar products)
+    uint32_t dq[14];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int mx = q & 1, my = (q >> 1) & 1, mz = q >> 2;
+        const int cc = (p + mx + my + mz + (1 - b)) & 1;
+        dq[q] = __builtin_amdgcn_readfirstlane((uint32_t)(cc * TR::NA + mz * (TY + 1) + my) * L3);
+    }
+    {
+        const uint32_t c0 = (uint32_t)(2 * TR::NA + (TY + 2) + 1);
+        const uint32_t dz = (uint32_t)(TY + 2);
+        dq[8] = dq[9] = __builtin_amdgcn_readfirstlane(c0 * L3);
+        dq[10] = __builtin_amdgcn_readfirstlane((c0 - 1u) * L3);
+        dq[11] = __builtin_amdgcn_readfirstlane((c0 + 1u) * L3);
+        dq[12] = __builtin_amdgcn_readfirstlane((c0 - dz) * L3);
+        dq[13] = __builtin_amdgcn_readfirstlane((c0 + dz) * L3);
+    }
+    const uint32_t down = __builtin_amdgcn_readfirstlane((uint32_t)(2 * TR::NA + TR::NB) * L3);
+    for (uint32_t t = threadIdx.x; t < nsite; t += blockDim.x) {
+        const uint32_t r = fdiv(t, R.g.divLxh);
+        const uint32_t xh = t - __umul24(r, Lxh);
+        const int ty = (int)(r % TY), tz = (int)(r / TY);
+        Cell3 c;
+        c.xh = xh;
+        c.y = (uint32_t)(y0 + ty);
+        c.z = (uint32_t)(z0 + tz);
+        c.x = 2 * xh + (((uint32_t)colour + c.y + c.z) & 1u);
+        // the half-x indices of x - 1, x, x + 1 in a row (as the global pass)
+        const uint32_t xm = (c.x & 1u) ? xh : (xh == 0 ? Lxh - 1 : xh - 1);
+        const uint32_t xp = (c.x & 1u) ? (xh == Lxh - 1 ? 0 : xh + 1) : xh;
+        const uint32_t X[2] = {b == 0 ? xm : xh, b == 0 ? xh : xp};
+        // the site's row in each group: first shell, second shell, own
+        const uint32_t rA = __umul24((uint32_t)(tz * (TY + 1) + ty), L3);
+        const uint32_t rB = __umul24((uint32_t)(tz * (TY + 2) + ty), L3);
+        const uint32_t rO = __umul24(r, L3);
+        uint32_t at[14];   // each bond's element in the staged rows (component 0)
+        int sh[14];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            at[q] = rA + dq[q] + X[(q & 1)];
+            sh[q] = 0;
+        }
+        at[8] = rB + dq[8] + xm;
+        at[9] = rB + dq[9] + xp;
+#pragma unroll
+        for (int q = 10; q < 14; ++q) at[q] = rB + dq[q] + xh;
+#pragma unroll
+        for (int q = 8; q < 14; ++q) sh[q] = 1;
+        T ax[14], ay[14], az[14];
+        int sj[14];
+        T fr[14];
+#pragma unroll
+        for (int q = 0; q < 14; ++q) {
+            ax[q] = sld(rows, at[q]);
+            ay[q] = sld(rows, at[q] + Lxh);
+            az[q] = sld(rows, at[q] + 2u * Lxh);
+            sj[q] = 0;
+        }
+        const V3<T> h = two ? exchange_accum<T, false, false, 14>(R, sh, ax, ay, az, sj, fr, 0)
+                            : exchange_accum<T, false, false, 8>(R, sh, ax, ay, az, sj, fr, 0);
+        const uint32_t own = rO + down + xh;
+        V3<T> s{sld(rows, own), sld(rows, own + Lxh), sld(rows, own + 2u * Lxh)};
+        const uint32_t l = xh + __umul24(Lxh, c.y + __umul24(Ly, c.z));
+        const uint32_t kH = (uint32_t)colour * H;
+        bool bad = false;
+        s = site_rotate<T, GView<T>, SL_LATTICE_BCC, false, false>(R, V, colour, tau, c, kH + l, 0, h, s,
+                                                                   step, true, false, PrevHalf{}, bad);
+        gst(V.sx + kH, l, s.x);
+        gst(V.sy + kH, l, s.y);
+        gst(V.sz + kH, l, s.z);
+        if (bad) atomicOr(&R.st->err, ERR_NUMERIC);
     }
 }
 

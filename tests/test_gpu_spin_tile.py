@@ -1,0 +1,104 @@
+"""The LDS-staged colour pass (bcc, one species, constant exchange): a block
+stages the neighbour rows of a tile of 2 x 2 (or 4 x 4) rows in LDS and
+runs the same site arithmetic as the pass that gathers from global memory.
+
+* Bit for bit against that pass (spin_tile 0), FP32 and FP64, frozen and
+  live lattices, one and two exchange shells, with merged sweeps on (its
+  passes 2.. take the staged pass) and off, on every tile shape: 4 x 4
+  rows in 256-thread blocks (rows shorter than 64 sites), 4 x 4 rows in
+  1024-thread blocks and 2 x 2 rows (longer rows, by what fits in LDS).
+* FP64 against the oracle at 1e-10 per component (reading R23), with the
+  staged pass on, across the list rebuilds of a hot live lattice.
+"""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_18541_amd import inputs as I
+from tests.gpu_util import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_18541_amd import native
+    native.lib()
+    return native
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(N, spec, st, prec, tile, steps, merge=1):
+    g = N.System(spec, st, precision=prec, obs_every=10)
+    g.set_tuning(spin_tile=tile, merge_sweeps=merge)
+    for k in (3, steps - 3):
+        g.step(k)
+    out = g.state()
+    obs = g.observables()
+    g.close()
+    return out, obs
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["frozen_two_shells", "live_two_shells", "frozen_one_shell",
+                                  "live_unmerged"])
+def test_staged_pass_bitwise(N, prec, case):
+    # 8^3 cells: 4 sites per colour row, whole 16-byte vectors in FP32 and
+    # FP64, 4 x 4 tiles
+    spec = I.fe_bcc_spec(L=8, seed=71, run_id=1)
+    if case.startswith("frozen"):
+        spec = replace(spec, lattice_mode=0)
+    if case.endswith("one_shell"):
+        spec = replace(spec, n_shells=1)
+    merge = 0 if case == "live_unmerged" else 1
+    st = I.initial_state(spec, "tilt", T_lattice=600.0)
+    _log("staged pass bitwise: %s prec %d" % (case, prec))
+    a, oa = _run(N, spec, st, prec, 1, 60, merge)
+    b, ob = _run(N, spec, st, prec, 0, 60, merge)
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(a[k], b[k]), (case, k)
+    assert len(oa) == len(ob)
+    for p, q in zip(oa, ob):
+        assert np.array_equal(p["M"], q["M"]) and p["E_ex"] == q["E_ex"]
+
+
+@pytest.mark.parametrize("prec,ncell", [(1, (128, 128, 128)), (1, (256, 8, 4)), (0, (256, 8, 4)),
+                                        (1, (32, 8, 8))])
+def test_staged_pass_bitwise_long_rows(N, prec, ncell):
+    # frozen lattices with long colour rows: 4 x 4 tiles in 1024-thread
+    # blocks (FP32 128^3 with 64 sites per row, FP32 rows of 128 sites), 2 x 2
+    # tiles where those do not fit in LDS (FP64 rows of 128 sites), and 4 x 4
+    # tiles in 256-thread blocks for rows of 16 sites; one launch per pass
+    spec = replace(I.fe_bcc_spec(L=8, lattice_mode=0, seed=72, run_id=0), ncell=ncell)
+    st = I.initial_state(spec, "tilt")
+    _log("staged pass bitwise: %s prec %d" % (str(ncell), prec))
+    a, _ = _run(N, spec, st, prec, 1, 12, merge=0)
+    b, _ = _run(N, spec, st, prec, 0, 12, merge=0)
+    assert np.array_equal(a["s"], b["s"])
+
+
+def test_staged_pass_against_oracle(N):
+    # a hot live lattice with a thin skin (several list rebuilds), FP64
+    spec = replace(I.fe_bcc_spec(L=8, seed=73, run_id=2), skin=0.05)
+    st = I.initial_state(spec, "tilt", T_lattice=900.0)
+    _log("staged pass against the oracle: bcc 8^3 FP64")
+    g = N.System(spec, st, precision=N.SL_FP64, obs_every=10)
+    g.set_tuning(spin_tile=1)
+    o = O.Oracle(spec, st.species, st.spins, st.vel)
+    for chunk in (7, 53, 60):
+        g.step(chunk)
+        o.step(chunk)
+        errs, bad = compare_states(g.state(), o.state(), spec.box, 1e-10)
+        assert not bad, (chunk, errs)
+    assert g.stats()["list_rebuilds"] >= 3, g.stats()
+    g.close()
