@@ -1720,8 +1720,11 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass_lean(const RunDev<T>* __re
 // results have the same bits as the pass that gathers from global memory.
 // What changes is the memory instruction stream: one 16-byte load per four
 // (FP32) or two (FP64) sites of a staged row instead of one 4- or 8-byte
-// gather per neighbour component, which the gathers' address processing had
-// made the limit of the pass at scale.
+// gather per neighbour component, about six times fewer load instructions.
+// It is a launch shape to choose, not the default: at 256^3 in FP32 it ran
+// slower than the gathering pass, because the staged rows (6.4 per computed
+// row with 4 x 4 tiles) are the L2 traffic the gathers already draw through
+// their L1, and a tile's LDS leaves room for one block per CU.
 // Staged row slots: [0, 2 NA) the other basis's colours (colour 2(1 - b)
 // first), [2 NA, 2 NA + NB) the second shell's colour, then the own rows;
 // slot s holds its three spin components as rows of Lxh values at

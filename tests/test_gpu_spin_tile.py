@@ -102,3 +102,25 @@ def test_staged_pass_against_oracle(N):
         assert not bad, (chunk, errs)
     assert g.stats()["list_rebuilds"] >= 3, g.stats()
     g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_staged_pass_batch_equals_alone(N, prec):
+    # a batch of bcc runs of two sizes (8^3 and 16^3 cells, 4 x 4 tiles of
+    # both in one launch) on the multi-kernel step with the staged pass: each
+    # run keeps the bits it has alone with the gathering pass
+    runs = []
+    for k, L in enumerate((8, 16, 8)):
+        spec = replace(I.fe_bcc_spec(L=L, seed=80 + k, run_id=k), lattice_mode=0 if k == 1 else 1)
+        runs.append((spec, I.initial_state(spec, "tilt", T_lattice=500.0)))
+    _log("staged pass batch: prec %d" % prec)
+    b = N.Batch(precision=prec, max_runs=3)
+    b.set_tuning(persist_block=0, spin_tile=1)
+    slots = [b.add(sp, st, 40, obs_every=10) for sp, st in runs]
+    b.advance(40)
+    for (sp, st), s in zip(runs, slots):
+        g = b.get(s)
+        a, _ = _run(N, sp, st, prec, 0, 40)
+        for key in ("s", "x", "v"):
+            assert np.array_equal(a[key], g[key]), (sp.ncell, key)
+    b.close()
