@@ -52,7 +52,7 @@ def source_digest() -> str:
 # (every timed pass updates its sites once)
 SCALE_TUNING = json.dumps({"spin_block": 256, "spin_spt": 2, "atom_block": 256, "graph_steps": 16,
                            "persist_block": 0, "xcd_order": 0, "bin_mode": 0, "atom_lanes": 0,
-                           "merge_sweeps": 0, "spin_tile": 0})
+                           "merge_sweeps": 0, "spin_access": 0})
 
 
 def measured_traffic(kernel: str, workload: str, tuning=None):
@@ -666,14 +666,15 @@ def field_llg_scale(N, I, L: int = 256, tuning=None, variants: bool = True) -> d
         autotune(s, steps=8, rounds=2, use_cache=False)
     tuning = s.tuning()
     avg, cnt = s.step_profiled(10)
-    staged_us = None
+    access_us = {}
     if variants:
         # the same passes with the neighbour rows staged in LDS (same bits)
-        s.set_tuning(**dict(tuning, spin_tile=1))
-        s.step(8)
-        s.synchronize()
-        avg_t, _ = s.step_profiled(10)
-        staged_us = round(avg_t[0] * 1e3, 3)
+        for mode, key in ((1, "lds_staged"),):
+            s.set_tuning(**dict(tuning, spin_access=mode))
+            s.step(8)
+            s.synchronize()
+            avg_t, _ = s.step_profiled(10)
+            access_us[key] = round(avg_t[0] * 1e3, 3)
     s.close()
     H = spec.n_sites / 4
     bpu = bytes_per_unit("spin_pass", 1, spec.n_species, 0)
@@ -704,7 +705,7 @@ def field_llg_scale(N, I, L: int = 256, tuning=None, variants: bool = True) -> d
         avg_q, _ = s.step_profiled(10)
         s.close()
         out["no_thermal_field_avg_launch_us"] = round(avg_q[0] * 1e3, 3)
-        out["lds_staged_avg_launch_us"] = staged_us
+        out["lds_staged_avg_launch_us"] = access_us.get("lds_staged")
         # what a plain streaming copy reaches, against which the pass's real
         # traffic rate is read
         out["device_copy_GBs"] = round(copy_bandwidth(), 1)

@@ -334,16 +334,17 @@ typedef struct sl_tuning {
                                  either way, except that a negative electron
                                  energy met at a folded step end stops the run
                                  one step later (SL_ENUMERIC either way)      */
-    int32_t spin_tile;        /* 1: the colour passes of bcc runs with one species
+    int32_t spin_access;      /* how the colour passes of bcc runs with one species
                                  and constant exchange that carry no lattice
-                                 kick and no deferred half step stage the
-                                 neighbour rows of a tile of 4 x 4 (or 2 x 2)
-                                 rows in LDS with 16-byte loads, when the tile
-                                 divides the rows and planes and a row holds
-                                 whole 16-byte vectors.  0 (default): every
-                                 site gathers its neighbours from global
-                                 memory, which measured faster.  Same bits
-                                 either way                                   */
+                                 kick and no deferred half step read their
+                                 neighbours.  0 (default): every site gathers
+                                 them from global memory, which measured
+                                 fastest.  1: a block stages the neighbour
+                                 rows of a tile of 4 x 4 (or 2 x 2) rows in
+                                 LDS with 16-byte loads (when the tile divides
+                                 the rows and planes and a row holds whole
+                                 16-byte vectors; otherwise 0 runs).  Same
+                                 bits either way                              */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of

@@ -27,7 +27,7 @@ KNOBS = {
     "xcd_order": (0, 1),
     "bin_mode": (0, 1, 2),
     "merge_sweeps": (1, 0),
-    "spin_tile": (0, 1),
+    "spin_access": (0, 1),
 }
 
 _CACHE_FILE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2608_18541_amd",

@@ -371,7 +371,8 @@ public:
     int bin_mode = 0;               // 0 automatic, 1 kick bins every step, 2 rebuild only
     int atom_lanes = 0;             // lanes per atom in k_atom_final (0: by the atom count)
     int merge_sweeps = 1;           // 1: merge adjacent colour half steps when possible
-    int spin_tile = 0;              // 1: LDS-staged colour passes where they apply
+    int spin_access = 0;            // colour-pass neighbour access: 0 gathers per site,
+                                    // 1 LDS-staged rows (where they apply)
     int merge_g = 0;                // >= 2: steps per merged chunk of the multi-kernel runs
     int merge_run = -1;             // a stepping run among them (its step gives the chunk phase)
     std::vector<int> mk_runs;       // the runs on the multi-kernel step
@@ -1508,7 +1509,7 @@ private:
         // 16-byte aligned and the rows fit in LDS
         stile = 0;
         stile_bytes = 0;
-        if (spin_tile && lean_lat == SL_LATTICE_BCC && !lean_multi && !rl.empty()) {
+        if (spin_access == 1 && lean_lat == SL_LATTICE_BCC && !lean_multi && !rl.empty()) {
             const uint32_t vec = 16u / (uint32_t)sizeof(T);
             bool small = false;
             for (int s : rl) small = small || host_rd[s].g.Lxh < 64;

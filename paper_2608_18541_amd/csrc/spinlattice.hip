@@ -207,7 +207,7 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     if (t->atom_lanes > 0 && t->atom_block / t->atom_lanes < 64)
         return fail(SL_EINVAL, "atom_block / atom_lanes must be at least 64");
     if (t->merge_sweeps != 0 && t->merge_sweeps != 1) return fail(SL_EINVAL, "merge_sweeps must be 0 or 1");
-    if (t->spin_tile != 0 && t->spin_tile != 1) return fail(SL_EINVAL, "spin_tile must be 0 or 1");
+    if (t->spin_access != 0 && t->spin_access != 1) return fail(SL_EINVAL, "spin_access must be 0 or 1");
     e->spin_block = t->spin_block;
     e->spin_spt = t->spin_spt;
     e->atom_block = t->atom_block;
@@ -217,7 +217,7 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     e->bin_mode = t->bin_mode;
     e->atom_lanes = t->atom_lanes;
     e->merge_sweeps = t->merge_sweeps;
-    e->spin_tile = t->spin_tile;
+    e->spin_access = t->spin_access;
     return e->retune();
 }
 
@@ -232,7 +232,7 @@ static void get_tuning(const Engine* e, sl_tuning* t)
     t->bin_mode = e->bin_mode;
     t->atom_lanes = e->atom_lanes;
     t->merge_sweeps = e->merge_sweeps;
-    t->spin_tile = e->spin_tile;
+    t->spin_access = e->spin_access;
 }
 
 sl_status sl_set_tuning(sl_system h, const sl_tuning* t)

@@ -84,7 +84,7 @@ class sl_tuning(C.Structure):
     _fields_ = [("spin_block", C.c_int32), ("spin_spt", C.c_int32), ("atom_block", C.c_int32),
                 ("graph_steps", C.c_int32), ("persist_block", C.c_int32),
                 ("xcd_order", C.c_int32), ("bin_mode", C.c_int32), ("atom_lanes", C.c_int32),
-                ("merge_sweeps", C.c_int32), ("spin_tile", C.c_int32)]
+                ("merge_sweeps", C.c_int32), ("spin_access", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1,14 +1,16 @@
-"""The LDS-staged colour pass (bcc, one species, constant exchange): a block
-stages the neighbour rows of a tile of 2 x 2 (or 4 x 4) rows in LDS and
-runs the same site arithmetic as the pass that gathers from global memory.
+"""The LDS-staged colour pass of bcc runs with one species and constant
+exchange (tuning spin_access 1): a block stages the neighbour rows of a tile
+of 2 x 2 (or 4 x 4) rows in LDS and runs the same site arithmetic as the
+pass that gathers per site (spin_access 0).
 
-* Bit for bit against that pass (spin_tile 0), FP32 and FP64, frozen and
-  live lattices, one and two exchange shells, with merged sweeps on (its
-  passes 2.. take the staged pass) and off, on every tile shape: 4 x 4
+* Bit for bit against that pass, FP32 and FP64, frozen and live lattices,
+  one and two exchange shells, with merged sweeps on (its passes 2.. take
+  the chosen access) and off; for the staged rows on every tile shape: 4 x 4
   rows in 256-thread blocks (rows shorter than 64 sites), 4 x 4 rows in
   1024-thread blocks and 2 x 2 rows (longer rows, by what fits in LDS).
 * FP64 against the oracle at 1e-10 per component (reading R23), with the
-  staged pass on, across the list rebuilds of a hot live lattice.
+  staged rows, across the list rebuilds of a hot live lattice.
+* A batch of runs of two sizes against the runs alone.
 """
 import sys
 from dataclasses import replace
@@ -38,9 +40,9 @@ def _log(msg):
     sys.stdout.flush()
 
 
-def _run(N, spec, st, prec, tile, steps, merge=1):
+def _run(N, spec, st, prec, mode, steps, merge=1):
     g = N.System(spec, st, precision=prec, obs_every=10)
-    g.set_tuning(spin_tile=tile, merge_sweeps=merge)
+    g.set_tuning(spin_access=mode, merge_sweeps=merge)
     for k in (3, steps - 3):
         g.step(k)
     out = g.state()
@@ -49,10 +51,11 @@ def _run(N, spec, st, prec, tile, steps, merge=1):
     return out, obs
 
 
+@pytest.mark.parametrize("mode", [1])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("case", ["frozen_two_shells", "live_two_shells", "frozen_one_shell",
                                   "live_unmerged"])
-def test_staged_pass_bitwise(N, prec, case):
+def test_access_mode_bitwise(N, mode, prec, case):
     # 8^3 cells: 4 sites per colour row, whole 16-byte vectors in FP32 and
     # FP64, 4 x 4 tiles
     spec = I.fe_bcc_spec(L=8, seed=71, run_id=1)
@@ -62,8 +65,8 @@ def test_staged_pass_bitwise(N, prec, case):
         spec = replace(spec, n_shells=1)
     merge = 0 if case == "live_unmerged" else 1
     st = I.initial_state(spec, "tilt", T_lattice=600.0)
-    _log("staged pass bitwise: %s prec %d" % (case, prec))
-    a, oa = _run(N, spec, st, prec, 1, 60, merge)
+    _log("access mode %d bitwise: %s prec %d" % (mode, case, prec))
+    a, oa = _run(N, spec, st, prec, mode, 60, merge)
     b, ob = _run(N, spec, st, prec, 0, 60, merge)
     for k in ("s", "x", "v", "Te"):
         assert np.array_equal(a[k], b[k]), (case, k)
@@ -74,26 +77,27 @@ def test_staged_pass_bitwise(N, prec, case):
 
 @pytest.mark.parametrize("prec,ncell", [(1, (128, 128, 128)), (1, (256, 8, 4)), (0, (256, 8, 4)),
                                         (1, (32, 8, 8))])
-def test_staged_pass_bitwise_long_rows(N, prec, ncell):
+def test_access_mode_bitwise_long_rows(N, prec, ncell):
     # frozen lattices with long colour rows: 4 x 4 tiles in 1024-thread
     # blocks (FP32 128^3 with 64 sites per row, FP32 rows of 128 sites), 2 x 2
     # tiles where those do not fit in LDS (FP64 rows of 128 sites), and 4 x 4
     # tiles in 256-thread blocks for rows of 16 sites; one launch per pass
     spec = replace(I.fe_bcc_spec(L=8, lattice_mode=0, seed=72, run_id=0), ncell=ncell)
     st = I.initial_state(spec, "tilt")
-    _log("staged pass bitwise: %s prec %d" % (str(ncell), prec))
-    a, _ = _run(N, spec, st, prec, 1, 12, merge=0)
+    _log("staged rows bitwise: %s prec %d" % (str(ncell), prec))
     b, _ = _run(N, spec, st, prec, 0, 12, merge=0)
+    a, _ = _run(N, spec, st, prec, 1, 12, merge=0)
     assert np.array_equal(a["s"], b["s"])
 
 
-def test_staged_pass_against_oracle(N):
+@pytest.mark.parametrize("mode", [1])
+def test_access_mode_against_oracle(N, mode):
     # a hot live lattice with a thin skin (several list rebuilds), FP64
     spec = replace(I.fe_bcc_spec(L=8, seed=73, run_id=2), skin=0.05)
     st = I.initial_state(spec, "tilt", T_lattice=900.0)
-    _log("staged pass against the oracle: bcc 8^3 FP64")
+    _log("access mode %d against the oracle: bcc 8^3 FP64" % mode)
     g = N.System(spec, st, precision=N.SL_FP64, obs_every=10)
-    g.set_tuning(spin_tile=1)
+    g.set_tuning(spin_access=mode)
     o = O.Oracle(spec, st.species, st.spins, st.vel)
     for chunk in (7, 53, 60):
         g.step(chunk)
@@ -104,8 +108,9 @@ def test_staged_pass_against_oracle(N):
     g.close()
 
 
+@pytest.mark.parametrize("mode", [1])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_staged_pass_batch_equals_alone(N, prec):
+def test_access_mode_batch_equals_alone(N, mode, prec):
     # a batch of bcc runs of two sizes (8^3 and 16^3 cells, 4 x 4 tiles of
     # both in one launch) on the multi-kernel step with the staged pass: each
     # run keeps the bits it has alone with the gathering pass
@@ -113,9 +118,9 @@ def test_staged_pass_batch_equals_alone(N, prec):
     for k, L in enumerate((8, 16, 8)):
         spec = replace(I.fe_bcc_spec(L=L, seed=80 + k, run_id=k), lattice_mode=0 if k == 1 else 1)
         runs.append((spec, I.initial_state(spec, "tilt", T_lattice=500.0)))
-    _log("staged pass batch: prec %d" % prec)
+    _log("access mode %d batch: prec %d" % (mode, prec))
     b = N.Batch(precision=prec, max_runs=3)
-    b.set_tuning(persist_block=0, spin_tile=1)
+    b.set_tuning(persist_block=0, spin_access=mode)
     slots = [b.add(sp, st, 40, obs_every=10) for sp, st in runs]
     b.advance(40)
     for (sp, st), s in zip(runs, slots):
