@@ -83,3 +83,24 @@ def test_noalloc_equals_step_two_calls(N):
     _same(N, a, b)
     for s in (a, b, c, d):
         s.close()
+
+
+def test_noalloc_with_staged_rows_requested(N):
+    # a bcc run whose tuning asks for LDS-staged colour passes: sl_step takes
+    # them, the allocation-free call (which builds no tile table) the
+    # per-site gathers; the same bits, and the staged passes still run after
+    spec = I.fe_bcc_spec(L=8, lattice_mode=0, seed=22, run_id=4)
+    st = I.initial_state(spec, "tilt")
+    _log("noalloc: 8^3 bcc FP32 with spin_access 1")
+    a, b = _pair(N, spec, st, N.SL_FP32, 10, spin_access=1, merge_sweeps=0)
+    n0 = a._alloc.n_allocs
+    a.step_noalloc(33)
+    a.synchronize()
+    assert a._alloc.n_allocs == n0
+    b.step(33)
+    _same(N, a, b)
+    a.step(20)
+    b.step(20)
+    _same(N, a, b)
+    a.close()
+    b.close()
