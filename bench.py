@@ -853,6 +853,10 @@ def main() -> int:
     per_step = {k: avg[i] * cnt[i] / args.profile_steps for i, k in enumerate(KERNELS)}
     dom = max(per_step, key=per_step.get)
     di = KERNELS.index(dom)
+    # lanes per atom of the force launch in the automatic shape (4 up to 2^16
+    # atoms on the multi-kernel step)
+    lanes_used = tuning_used.get("atom_lanes") or (4 if spec.n_sites <= (1 << 16) else
+                                                   (2 if spec.n_sites <= (1 << 17) else 1))
     # mean neighbour-list length of the Morse list at this density
     z_list = 18.0
     alg_bytes = launch_bytes(dom, 0, spec.n_species, z_list, spec.n_sites, 2)
@@ -862,7 +866,12 @@ def main() -> int:
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": None if traffic is None else int(traffic),
             "avg_launch_us": round(avg[di] * 1e3, 3), "bytes_per_launch": int(alg_bytes),
-            "per_step_us": {k: round(v * 1e3, 3) for k, v in per_step.items()}}
+            "per_step_us": {k: round(v * 1e3, 3) for k, v in per_step.items()},
+            "note": "one run of %d atoms: the force launch holds %d waves (%d lanes per atom), "
+                    "%.1f per SIMD of the 1024, and runs at the latency of each atom's FP64 "
+                    "chain (list walk, Morse exp and sqrt, O-step), not at HBM bandwidth"
+                    % (spec.n_sites, -(-spec.n_sites * lanes_used // 64), lanes_used,
+                       spec.n_sites * lanes_used / 64 / 1024)}
     sys_.close()
 
     out = {
