@@ -107,3 +107,46 @@ def test_exchange_force_moves_the_atoms(N):
         g.close()
     vr = np.sqrt((out[0]["v"] ** 2).mean())
     assert np.abs(out[0]["v"] - out[1]["v"]).max() > 1e-4 * vr
+
+
+def test_radial_fp32_close_to_fp64(N):
+    """The FP32 path with radial exchange over 100 steps: within
+    single-precision bounds of FP64, and its exchange force is live (the same
+    FP32 run with the couplings frozen at their ideal values moves the atoms
+    ten times further from it than FP32 is from FP64)."""
+    spec, st = _bcc()
+    r1, r2 = X.shell_distances("bcc", spec.a)
+    J2, J3 = spec.exch_r[0]
+    J = tuple(tuple(tuple(float(X.radial_exchange(r, 1.0, J2, J3)) * v for v in row) for row in shell)
+              for shell, r in zip(spec.J, (r1, r2)))
+    fixed = replace(spec, exch_radial=0, J=J)
+    _log("radial: bcc FP32 against FP64 and against frozen couplings, 100 steps")
+    out = {}
+    for key, sp, prec in (("r64", spec, N.SL_FP64), ("r32", spec, N.SL_FP32), ("f32", fixed, N.SL_FP32)):
+        g = N.System(sp, st, precision=prec)
+        g.step(100)
+        out[key] = g.state()
+        g.close()
+    vr = float(np.sqrt((out["r64"]["v"] ** 2).mean()))
+    d_prec = float(np.abs(out["r32"]["v"] - out["r64"]["v"]).max())
+    d_force = float(np.abs(out["r32"]["v"] - out["f32"]["v"]).max())
+    _log("  max|dv| FP32-FP64 %.3e, radial-frozen %.3e (v_rms %.3e)" % (d_prec, d_force, vr))
+    assert np.abs(out["r32"]["s"] - out["r64"]["s"]).max() < 5e-3
+    assert d_prec < 1e-3 * vr
+    assert d_force > 10.0 * d_prec
+
+
+def test_radial_allocation_free_equals_step(N):
+    """sl_step_noalloc on a run with radial exchange (the half kick after the
+    sweep, no merged sweeps) gives the bits of sl_step."""
+    spec, st = _fcc_alloy()
+    _log("radial: fcc alloy, allocation-free against sl_step")
+    a = N.System(spec, st, precision=N.SL_FP64, obs_every=10)
+    b = N.System(spec, st, precision=N.SL_FP64, obs_every=10)
+    a.step_noalloc(35)
+    b.step(35)
+    sa, sb = a.state(), b.state()
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(sa[k], sb[k]), k
+    a.close()
+    b.close()
