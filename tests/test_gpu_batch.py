@@ -226,6 +226,38 @@ def test_fp32_production_ensemble_matches_fp64(N):
     # the pulse demagnetised the TM sublattice (it starts at -1)
     assert a[:, :, 1].mean(axis=0).max() > -0.97
 
+def test_fp32_fcc_production_ensemble_matches_fp64(N):
+    """The same check on the paper's production lattice: fcc GdFeCo (5^3
+    cells, 500 sites, exact-count alloy, Table 1 exchange, anisotropy,
+    stepped T_e) in the persistent executor, FP32 against FP64 ensembles of
+    sublattice M_z(t) over 24 seeds."""
+    nrun = 24
+    steps, every = 1500, 100
+    means = {}
+    for prec in (0, 1):
+        b = N.Batch(precision=prec, max_runs=nrun)
+        slots = []
+        for r in range(nrun):
+            spec = replace(I.gdfeco_fcc_spec(L=5, alpha=0.05, seed=610, run_id=r), tn=(2, 2, 2),
+                           ttm_mode=2, step_T=(1400.0, 700.0, 300.0), step_end=(0.05, 0.1))
+            slots.append(b.add(spec, I.initial_state(spec, "afm", exact_count=True), steps,
+                               obs_every=every))
+        b.advance(steps)
+        traj = []
+        for s in slots:
+            obs = b.get(s)["obs"]
+            traj.append([[o["M"][1][2], o["M"][0][2]] for o in obs])
+        means[prec] = np.array(traj)           # [run, sample, (Gd, TM)]
+    a, c = means[0], means[1]
+    diff = a.mean(axis=0) - c.mean(axis=0)
+    err = np.sqrt(a.var(axis=0, ddof=1) / nrun + c.var(axis=0, ddof=1) / nrun) + 1e-6
+    _log("fcc production FP32-FP64 max |dM| = %.3e, max |dM|/err = %.2f"
+         % (np.abs(diff).max(), (np.abs(diff) / err).max()))
+    assert np.all(np.abs(diff) < 4.0 * err + 2e-3)
+    # the pulse demagnetised the TM sublattice (it starts at -1)
+    assert a[:, :, 1].mean(axis=0).max() > -0.97
+
+
 def test_launch_shapes_are_bitwise_identical(N):
     """Every launch shape the autotuner may choose gives the same bits: a
     batch stepped under several settings (and then autotuned) equals the
