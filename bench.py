@@ -28,7 +28,7 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 OBS_EVERY = 100          # samples of the plain run every 100 steps (10 fs)
-KERNELS = ["spin_pass", "atom_final", "spin_kick", "end_step", "persist"]
+KERNELS = ["spin_pass", "atom_final", "spin_kick", "end_step", "persist", "spin_force"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -52,7 +52,7 @@ def source_digest() -> str:
 # (every timed pass updates its sites once)
 SCALE_TUNING = json.dumps({"spin_block": 256, "spin_spt": 2, "atom_block": 256, "graph_steps": 16,
                            "persist_block": 0, "xcd_order": 0, "bin_mode": 0, "atom_lanes": 0,
-                           "merge_sweeps": 0, "spin_access": 0})
+                           "merge_sweeps": 0, "spin_access": 0, "fuse_force": 1})
 
 
 def measured_traffic(kernel: str, workload: str, tuning=None):
@@ -121,6 +121,9 @@ def launch_bytes(kernel: str, fp: int, n_species: int, z_list: float, n_sites: i
                 bytes_per_unit("kick", fp, n_species, z_list) * n_sites)
     if kernel == "atom_final":
         return bytes_per_unit("atom_final", fp, n_species, z_list) * n_sites
+    if kernel == "spin_force":             # colour pass 1 carrying the force kernel
+        return (bytes_per_unit("spin_pass", fp, n_species, z_list) * H +
+                bytes_per_unit("atom_final", fp, n_species, z_list) * n_sites)
     return 0.0
 
 
@@ -867,11 +870,13 @@ def main() -> int:
             "traffic": None if traffic is None else int(traffic),
             "avg_launch_us": round(avg[di] * 1e3, 3), "bytes_per_launch": int(alg_bytes),
             "per_step_us": {k: round(v * 1e3, 3) for k, v in per_step.items()},
-            "note": "one run of %d atoms: the force launch holds %d waves (%d lanes per atom), "
+            "note": "one run of %d atoms: the force kernel holds %d waves (%d lanes per atom), "
                     "%.1f per SIMD of the 1024, and runs at the latency of each atom's FP64 "
-                    "chain (list walk, Morse exp and sqrt, O-step), not at HBM bandwidth"
+                    "chain (list walk, Morse exp and sqrt, O-step), not at HBM bandwidth%s"
                     % (spec.n_sites, -(-spec.n_sites * lanes_used // 64), lanes_used,
-                       spec.n_sites * lanes_used / 64 / 1024)}
+                       spec.n_sites * lanes_used / 64 / 1024,
+                       "; its launch also carries colour pass 1 (%d sites), whose chain is "
+                       "shorter" % (spec.n_sites // 2) if dom == "spin_force" else "")}
     sys_.close()
 
     out = {

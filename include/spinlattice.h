@@ -282,11 +282,12 @@ sl_status sl_footprint_bytes(const sl_system_desc* desc, const sl_ttm_desc* ttm,
  * by HIP events stamped by its own dispatch; returns the average device time
  * (ms) per launch of each kernel class and the launch counts: 0 spin colour
  * pass, 1 neighbour-list rebuild (when due), lattice forces and
- * electron-phonon step, 2 colour pass 1 carrying the lattice's kick, drift
+ * electron-phonon step, 2 colour pass carrying the lattice's kick, drift
  * and binning (live lattices), 3 binning for a rebuild (large engines),
  * electron grid and end-of-step reductions, 4 persistent kernel (one launch
- * for all steps). */
-sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5]);
+ * for all steps), 5 colour pass 1 carrying the force kernel of class 1
+ * (tuning fuse_force). */
+sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[6], int64_t launches[6]);
 
 /* Launch shape of the step kernels (no passage of the method: a choice of
  * the implementation).  Every choice performs the same
@@ -345,6 +346,16 @@ typedef struct sl_tuning {
                                  the rows and planes and a row holds whole
                                  16-byte vectors; otherwise 0 runs).  Same
                                  bits either way                              */
+    int32_t fuse_force;       /* 1 (default): in the folded chunks of a single run
+                                 with a live lattice, constant exchange and no
+                                 anisotropy (one site per thread, atom_block a
+                                 multiple of the colour-pass block), each step
+                                 kicks the atoms in colour pass 0 and runs the
+                                 force kernel in the launch of colour pass 1,
+                                 but for the chunk's last step: two launches
+                                 per step instead of three.  0: the kick rides with
+                                 colour pass 1 and the force kernel follows the
+                                 sweep.  Same bits either way                 */
 } sl_tuning;
 
 /* Waits for the stream, then applies a launch shape (SL_EINVAL if out of
@@ -413,8 +424,8 @@ sl_status sl_batch_remove(sl_batch b, int32_t slot);
 /* As sl_batch_advance, launching every kernel directly with HIP events
  * around each; returns the average device time (ms) per launch of each
  * kernel class (as sl_step_profiled) and the launch counts. */
-sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[5],
-                                    int64_t launches[5]);
+sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[6],
+                                    int64_t launches[6]);
 
 /* Launch shape of a batch (as sl_set_tuning / sl_get_tuning). */
 sl_status sl_batch_set_tuning(sl_batch b, const sl_tuning* t);

@@ -28,6 +28,7 @@ KNOBS = {
     "bin_mode": (0, 1, 2),
     "merge_sweeps": (1, 0),
     "spin_access": (0, 1),
+    "fuse_force": (1, 0),
 }
 
 _CACHE_FILE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2608_18541_amd",

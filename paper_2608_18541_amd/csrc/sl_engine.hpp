@@ -306,7 +306,8 @@ template <typename T> inline size_t main_bytes(const sl_system_desc* d, const Si
     }
     if (live) c.take<sl::Pos4<T>>(n);
     c.take<int8_t>(n);
-    c.take<uint16_t>(n);                                            // cell ids, two buffers
+    c.take<uint16_t>(n);                                            // cell ids, three buffers
+    c.take<uint16_t>(n);
     c.take<uint16_t>(n);
     c.take<double>((size_t)z.n_part * sl::NQ);
     c.take<sl_obs>((size_t)std::max(1, d->obs_capacity));
@@ -354,7 +355,7 @@ public:
     virtual sl_status remove(int slot) = 0;
     virtual sl_status stats(int slot, sl_run_stats* out) = 0;
     virtual sl_status sync() = 0;
-    virtual sl_status profiled(int64_t n, double avg[5], int64_t cnt[5]) = 0;
+    virtual sl_status profiled(int64_t n, double avg[6], int64_t cnt[6]) = 0;
     std::vector<Run> runs;
     DevAlloc alloc;
     hipStream_t stream = nullptr;
@@ -373,11 +374,15 @@ public:
     int merge_sweeps = 1;           // 1: merge adjacent colour half steps when possible
     int spin_access = 0;            // colour-pass neighbour access: 0 gathers per site,
                                     // 1 LDS-staged rows (where they apply)
+    int fuse_force = 1;             // 1: folded chunks kick in colour pass 0 and run the
+                                    // force kernel in the launch of colour pass 1
     int merge_g = 0;                // >= 2: steps per merged chunk of the multi-kernel runs
     int merge_run = -1;             // a stepping run among them (its step gives the chunk phase)
     std::vector<int> mk_runs;       // the runs on the multi-kernel step
     bool fold = false;              // chunks end each step inside the next one's colour pass 0
     int fold_blocks = 0;            // the blocks of colour pass 0 that end the previous step
+    bool fused = false;             // fuse_force applies to the folded chunks
+    int force_spin_blocks = 0;      // blocks of k_spin_force holding the colour pass
     int lanes_eff = 1;              // the lanes in use (tables are built for it)
     virtual sl_status retune() = 0;
     virtual sl_status init_device() = 0;
@@ -689,7 +694,7 @@ public:
         return SL_OK;
     }
 
-    sl_status profiled(int64_t n, double avg[5], int64_t cnt[5]) override
+    sl_status profiled(int64_t n, double avg[6], int64_t cnt[6]) override
     {
         if (n > kPersistChunk) return fail(SL_EINVAL, "profile at most 4096 steps per call");
         if (tables_dirty) {
@@ -730,8 +735,8 @@ public:
             if (st != SL_OK) return st;
         }
         SL_HIP(hipStreamSynchronize(stream));
-        double tot[5] = {0, 0, 0, 0, 0};
-        int64_t c[5] = {0, 0, 0, 0, 0};
+        double tot[6] = {0, 0, 0, 0, 0, 0};
+        int64_t c[6] = {0, 0, 0, 0, 0, 0};
         for (size_t k = 0; k + 1 < ev.size(); k += 2) {
             float ms = 0.f;
             SL_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
@@ -739,7 +744,7 @@ public:
             c[cls[k / 2]] += 1;
         }
         for (auto e : ev) (void)hipEventDestroy(e);
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 6; ++k) {
             avg[k] = c[k] ? tot[k] / c[k] : 0.0;
             cnt[k] = c[k];
         }
@@ -1150,8 +1155,7 @@ private:
         }
         if (R.live) R.pos = c.take<sl::Pos4<T>>(n);
         R.species = c.take<int8_t>(n);
-        R.cellb[0] = c.take<uint16_t>(n);
-        R.cellb[1] = c.take<uint16_t>(n);
+        for (int k = 0; k < 3; ++k) R.cellb[k] = c.take<uint16_t>(n);
         R.n_part = r.z.n_part;
         R.partial = c.take<double>((size_t)r.z.n_part * sl::NQ);
         R.ring = c.take<sl_obs>((size_t)R.obs_cap);
@@ -1503,10 +1507,11 @@ private:
             }
         }
         // the LDS-staged colour pass: bcc runs with one species, tiles of
-        // 2 x 2 rows (4 x 4 when rows are shorter than 64 sites), when the
-        // tile divides every run's rows and planes, a row holds whole 16-byte
-        // vectors (at most one per thread of the block), the spin arrays are
-        // 16-byte aligned and the rows fit in LDS
+        // 4 x 4 rows (in 1024-thread blocks when rows have 64 sites or more,
+        // else 2 x 2 rows in 256-thread blocks when those do not fit), when
+        // the tile divides every run's rows and planes, a row holds whole
+        // 16-byte vectors (at most one per thread of the block), the spin
+        // arrays are 16-byte aligned and the rows fit in LDS
         stile = 0;
         stile_bytes = 0;
         if (spin_access == 1 && lean_lat == SL_LATTICE_BCC && !lean_multi && !rl.empty()) {
@@ -1595,6 +1600,18 @@ private:
                 }
             }
         }
+        // the fused schedule (tuning fuse_force): a folded run with a live
+        // lattice and the specialised site update (merging already excludes
+        // radial exchange), one site per thread, and force blocks that hold
+        // whole colour-pass tiles
+        fused = false;
+        force_spin_blocks = 0;
+        if (fold && fuse_force && host_rd[rl[0]].live && lean_lat >= 0 && spin_spt == 1 &&
+            atom_block % spin_eff == 0 && !wk.empty()) {
+            fused = true;
+            const int per = atom_block / spin_eff;
+            force_spin_blocks = ((int)ws.size() + per - 1) / per;
+        }
         active_blocks_spin = (int)ws.size();
         active_blocks_atom = (int)wa.size();
         active_blocks_kick = (int)wk.size();
@@ -1665,29 +1682,68 @@ private:
         return SL_OK;
     }
 
+    // Binning for a rebuild, between the kick and the force kernel, in
+    // engines whose kick does not bin: capped grids striding over the atom
+    // table, which exit at once unless a run flagged a rebuild.
+    sl_status enqueue_binning(hipStream_t st, Prof* p, int fold_k)
+    {
+        if (active_blocks_kick == 0 || bin_each_step) return SL_OK;
+        // one thread per atom of the atom table's tiles
+        const dim3 gb(std::min(active_blocks_atom, kBinGrid)), bt(atom_block / lanes_eff);
+        sl_status e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+            launch(sl::k_nbr_bin<T>, gb, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
+                   fold_k, active_blocks_atom, (const int32_t*)d_any_rebuild);
+        });
+        if (e != SL_OK) return e;
+        return timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
+            launch(sl::k_nbr_sort<T>, gb, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
+                   fold_k, active_blocks_atom, (const int32_t*)d_any_rebuild);
+        });
+    }
+
     // One step of every run on the multi-kernel path.  Profiling classes:
     // 0 colour pass, 1 list rebuild (when flagged) and force / e-ph kernel,
-    // 2 colour pass 1 carrying the lattice kick and drift, 3 binning for a
-    // rebuild, electron grid and end of step.
+    // 2 colour pass carrying the lattice kick and drift, 3 binning for a
+    // rebuild, electron grid and end of step, 5 colour pass 1 carrying the
+    // force kernel.
     // merge_first: colour pass 0 applies the previous step's deferred last
     // half step first; defer_last: this step's last colour pass is left to
-    // the next step's pass 0.  The lattice kick rides on colour pass 1.
+    // the next step's pass 0.  The lattice kick rides on colour pass 1 (on
+    // pass 0 in the fused schedule).
     // fold_k >= 0: position of the step in a folded chunk of chunk_len steps
     // (its pass 0 ends the previous step, and only the chunk's last step has
-    // a k_finalize).
+    // a k_finalize).  In the fused schedule the force kernel of every step
+    // but the chunk's last (a sample step, whose force kernel reads the
+    // spins after the whole sweep) runs in the launch of colour pass 1.
     sl_status enqueue_step(hipStream_t st, Prof* p, bool merge_first = false, bool defer_last = false,
                            int fold_k = -1, int chunk_len = 0)
     {
         const int C = max_colours();
-        // the atom table's tiles hold atom_block / atom_lanes atoms: the
-        // binning launches take one thread per atom, k_atom_final atom_lanes
-        const dim3 bs(spin_eff), ba(atom_block), bt(atom_block / lanes_eff), bk(sl::kBlock);
+        // the atom table's tiles hold atom_block / atom_lanes atoms:
+        // k_atom_final gives each atom_lanes threads
+        const dim3 bs(spin_eff), ba(atom_block), bk(sl::kBlock);
+        const bool kick0 = fused && fold_k >= 0;
+        const bool force1 = kick0 && fold_k < (chunk_len > 0 ? chunk_len : merge_g) - 1;
+        sl_status e;
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
             if (defer_last && pass == 2 * C - 2) break;
             const int merge = merge_first && pass == 0 ? 1 : 0;
-            const bool fused = pass == 1 && active_blocks_kick > 0 && !any_radial;
-            const int nk = fused ? active_blocks_kick : (pass == 0 && fold_k >= 1 ? fold_blocks : 0);
-            sl_status e = timed(st, p, fused ? 2 : 0, [&](hipEvent_t a, hipEvent_t b) {
+            if (force1 && pass == 1) {
+                e = timed(st, p, 5, [&](hipEvent_t a, hipEvent_t b) {
+                    if (lanes_eff == 4)
+                        spin_force_lanes<4>(st, a, b, pass, fold_k);
+                    else if (lanes_eff == 2)
+                        spin_force_lanes<2>(st, a, b, pass, fold_k);
+                    else
+                        spin_force_lanes<1>(st, a, b, pass, fold_k);
+                });
+                if (e != SL_OK) return e;
+                continue;
+            }
+            const bool kicks = kick0 ? pass == 0 : pass == 1 && active_blocks_kick > 0 && !any_radial;
+            const int nf = pass == 0 && fold_k >= 1 ? fold_blocks : 0;
+            const int nk = (kicks ? active_blocks_kick : 0) + nf;
+            e = timed(st, p, kicks ? 2 : 0, [&](hipEvent_t a, hipEvent_t b) {
                 const dim3 g(active_blocks_spin + nk);
                 if (nk == 0 && merge == 0 && lean_lat >= 0) {
                     if (stile > 0 && stile_on) {
@@ -1709,27 +1765,30 @@ private:
                 if (any_radial) {
                     if (spin_spt == 4)
                         launch(sl::k_spin_pass<T, 4, true>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                               d_work_kick, active_blocks_spin, merge, fold_k);
+                               d_work_kick, active_blocks_spin, nf, merge, fold_k);
                     else if (spin_spt == 2)
                         launch(sl::k_spin_pass<T, 2, true>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                               d_work_kick, active_blocks_spin, merge, fold_k);
+                               d_work_kick, active_blocks_spin, nf, merge, fold_k);
                     else
                         launch(sl::k_spin_pass<T, 1, true>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                               d_work_kick, active_blocks_spin, merge, fold_k);
+                               d_work_kick, active_blocks_spin, nf, merge, fold_k);
                 } else if (spin_spt == 4)
                     launch(sl::k_spin_pass<T, 4>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin, merge, fold_k);
+                           d_work_kick, active_blocks_spin, nf, merge, fold_k);
                 else if (spin_spt == 2)
                     launch(sl::k_spin_pass<T, 2>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin, merge, fold_k);
+                           d_work_kick, active_blocks_spin, nf, merge, fold_k);
                 else
                     launch(sl::k_spin_pass<T, 1>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-                           d_work_kick, active_blocks_spin, merge, fold_k);
+                           d_work_kick, active_blocks_spin, nf, merge, fold_k);
             });
             if (e != SL_OK) return e;
+            if (kick0 && pass == 0) {
+                e = enqueue_binning(st, p, fold_k);
+                if (e != SL_OK) return e;
+            }
         }
         const dim3 ga(active_blocks_atom);
-        sl_status e;
         if (any_radial && active_blocks_kick > 0) {
             // after the sweep: the exchange half kick of radial runs, then the
             // drift of every live run (a launch of kick blocks only)
@@ -1739,48 +1798,39 @@ private:
             if (e != SL_OK) return e;
             e = timed(st, p, 2, [&](hipEvent_t a, hipEvent_t b) {
                 launch(sl::k_spin_pass<T, 1>, dim3(active_blocks_kick), bs, 0, st, a, b, d_runs, d_work_spin,
-                       1, d_work_kick, 0, 0, -1);
+                       1, d_work_kick, 0, 0, 0, -1);
             });
             if (e != SL_OK) return e;
         }
-        if (active_blocks_kick > 0 && !bin_each_step) {
-            // capped grids striding over the atom table, which exit at once
-            // unless a run flagged a rebuild
-            const dim3 gb(std::min(active_blocks_atom, kBinGrid));
-            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_bin<T>, gb, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
-                       fold_k, active_blocks_atom, (const int32_t*)d_any_rebuild);
-            });
-            if (e != SL_OK) return e;
-            e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
-                launch(sl::k_nbr_sort<T>, gb, bt, 0, st, a, b, d_runs, d_work_atom, (int)sl::PHASE_STEP,
-                       fold_k, active_blocks_atom, (const int32_t*)d_any_rebuild);
-            });
+        if (!kick0) {
+            e = enqueue_binning(st, p, fold_k);
             if (e != SL_OK) return e;
         }
-        e = timed(st, p, 1, [&](hipEvent_t a, hipEvent_t b) {
-            const int sorted = bin_each_step ? 0 : 1;
-            if (any_radial) {
-                if (lanes_eff == 4)
-                    launch(sl::k_atom_final<T, 4, true>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+        if (!force1) {
+            e = timed(st, p, 1, [&](hipEvent_t a, hipEvent_t b) {
+                const int sorted = bin_each_step ? 0 : 1;
+                if (any_radial) {
+                    if (lanes_eff == 4)
+                        launch(sl::k_atom_final<T, 4, true>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                               (int)sl::PHASE_STEP, sorted, fold_k);
+                    else if (lanes_eff == 2)
+                        launch(sl::k_atom_final<T, 2, true>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                               (int)sl::PHASE_STEP, sorted, fold_k);
+                    else
+                        launch(sl::k_atom_final<T, 1, true>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                               (int)sl::PHASE_STEP, sorted, fold_k);
+                } else if (lanes_eff == 4)
+                    launch(sl::k_atom_final<T, 4>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
                            (int)sl::PHASE_STEP, sorted, fold_k);
                 else if (lanes_eff == 2)
-                    launch(sl::k_atom_final<T, 2, true>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                    launch(sl::k_atom_final<T, 2>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
                            (int)sl::PHASE_STEP, sorted, fold_k);
                 else
-                    launch(sl::k_atom_final<T, 1, true>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
+                    launch(sl::k_atom_final<T, 1>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
                            (int)sl::PHASE_STEP, sorted, fold_k);
-            } else if (lanes_eff == 4)
-                launch(sl::k_atom_final<T, 4>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       (int)sl::PHASE_STEP, sorted, fold_k);
-            else if (lanes_eff == 2)
-                launch(sl::k_atom_final<T, 2>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       (int)sl::PHASE_STEP, sorted, fold_k);
-            else
-                launch(sl::k_atom_final<T, 1>, ga, ba, 0, st, a, b, d_runs, d_work_atom,
-                       (int)sl::PHASE_STEP, sorted, fold_k);
-        });
-        if (e != SL_OK) return e;
+            });
+            if (e != SL_OK) return e;
+        }
         if (active_blocks_tile > 0) {
             e = timed(st, p, 3, [&](hipEvent_t a, hipEvent_t b) {
                 launch(sl::k_ttm_tile<T>, dim3(active_blocks_tile), dim3(sl::kTileBlock), tile_bytes, st, a,
@@ -1823,6 +1873,29 @@ private:
                 launch(sl::k_persist<T, 512, true>, g, bl, persist_bytes, st, a, b, d_runs, d_persist_list, nsteps, lds_max);
             else
                 launch(sl::k_persist<T, 512>, g, bl, persist_bytes, st, a, b, d_runs, d_persist_list, nsteps, lds_max);
+        }
+    }
+
+    // Colour pass `pass` with the force kernel (k_spin_force) for the lanes
+    // per atom and the site-update form in use.
+    template <int LPA, int LAT, bool MULTI>
+    void spin_force_as(hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int fold_k)
+    {
+        const dim3 g(force_spin_blocks + active_blocks_atom), bl(atom_block);
+        launch(sl::k_spin_force<T, LPA, LAT, MULTI>, g, bl, 0, st, a, b, d_runs, d_work_spin, active_blocks_spin,
+               spin_eff, force_spin_blocks, d_work_atom, pass, bin_each_step ? 0 : 1, fold_k);
+    }
+    template <int LPA> void spin_force_lanes(hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int fold_k)
+    {
+        if (lean_lat == SL_LATTICE_SC) {
+            if (lean_multi) spin_force_as<LPA, SL_LATTICE_SC, true>(st, a, b, pass, fold_k);
+            else spin_force_as<LPA, SL_LATTICE_SC, false>(st, a, b, pass, fold_k);
+        } else if (lean_lat == SL_LATTICE_FCC) {
+            if (lean_multi) spin_force_as<LPA, SL_LATTICE_FCC, true>(st, a, b, pass, fold_k);
+            else spin_force_as<LPA, SL_LATTICE_FCC, false>(st, a, b, pass, fold_k);
+        } else {
+            if (lean_multi) spin_force_as<LPA, SL_LATTICE_BCC, true>(st, a, b, pass, fold_k);
+            else spin_force_as<LPA, SL_LATTICE_BCC, false>(st, a, b, pass, fold_k);
         }
     }
 

@@ -77,6 +77,9 @@ struct RunState {
                          // end that met a negative electron energy (0: none)
     int32_t n_rescan;    // bins scanned again by a list build from unsorted bins
                          // (more than kBinKeep accepted atoms)
+    int32_t force_done;  // force blocks that have finished a colour pass carrying the
+                         // force kernel on a list-rebuild step (the last one clears the
+                         // bins and the rebuild flags, then this count)
 };
 
 // Wrapped absolute position of an atom, padded to a 16/32-byte vector so a
@@ -124,7 +127,7 @@ template <typename T> struct RunDev {
     T *sx, *sy, *sz, *ux, *uy, *uz, *vx, *vy, *vz, *fx, *fy, *fz, *rx, *ry, *rz;
     Pos4<T>* pos;                    // wrap(ideal site + u), refreshed by k_kick_drift
     int8_t* species;
-    uint16_t* cellb[2];              // electron-cell id of x^n in cellb[n & 1]
+    uint16_t* cellb[3];              // electron-cell id of x^n in cellb[n mod 3]
     int32_t *nbr, *nbr_n;
     int32_t *bin_n, *bin_atoms;      // [nbins], [nbins][bin_cap]
     double *Te, *ee, *Te_alt;        // T_e, energy density, diffusion ping-pong buffer
@@ -242,11 +245,19 @@ template <typename T, typename M, typename P> struct View {
 
 template <typename T> using GView = View<T, InGlobal, InGlobal>;
 
-// View of the run's global arrays with the electron-cell ids of x^n,
-// n & 1 == parity.
-template <typename T> __device__ inline GView<T> global_view(const RunDev<T>& R, int64_t parity)
+// The cell-id buffer of x^n.  Three buffers: a launch that drifts the atoms
+// to x^{n+1} may run beside colour passes that still read the cells of x^n
+// and x^{n-1}.
+__host__ __device__ inline int cell_slot(int64_t n)
 {
-    return GView<T>{R.sx, R.sy, R.sz, R.species, R.cellb[parity & 1], R.pos, R.Te, R.partial};
+    const int r = (int)(n % 3);
+    return r < 0 ? r + 3 : r;
+}
+
+// View of the run's global arrays with the electron-cell ids of x^n.
+template <typename T> __device__ inline GView<T> global_view(const RunDev<T>& R, int64_t n)
+{
+    return GView<T>{R.sx, R.sy, R.sz, R.species, R.cellb[cell_slot(n)], R.pos, R.Te, R.partial};
 }
 
 template <typename T, typename VW>
@@ -1552,12 +1563,16 @@ template <typename T> __device__ inline bool sample_due(const RunDev<T>& R, int 
 // pass 0 of step k (k >= 1; this is block f of them, one thread per cell):
 // the small electron grid from the buffers of position k - 1 into those of
 // position k (the sums of position k - 1 are read by this pass's spin
-// blocks and cleared by the force kernel of step k), the bins emptied (when
-// no binning has filled them since they were last emptied they are empty
-// already, so no block needs the rebuild flag that the first block clears)
-// and the flags cleared.  Chunks end on sample steps, so no sample falls
-// here; the step counter moves at the chunk's end.
-template <typename T> __device__ inline void fold_end_step(const RunDev<T>& R, int k, int f, int nf)
+// blocks and cleared by the force kernel of step k), and with `clear` the
+// bins emptied (when no binning has filled them since they were last
+// emptied they are empty already, so no block needs the rebuild flag that
+// the first block clears) and the flags cleared.  Without `clear` the
+// launch also kicks the atoms of step k, which bin and flag again: the
+// force launch of step k - 1 has cleared them instead.  Chunks end on
+// sample steps, so no sample falls here; the step counter moves at the
+// chunk's end.
+template <typename T>
+__device__ inline void fold_end_step(const RunDev<T>& R, int k, int f, int nf, bool clear)
 {
     RunState* st = R.st;
     const int64_t step = st->step + k - 1;
@@ -1570,66 +1585,59 @@ template <typename T> __device__ inline void fold_end_step(const RunDev<T>& R, i
         for (int c = t; c < R.ncell; c += nt)
             cell_update_from(R, Tp[c], Ep[c], Tn, (unsigned long long*)nullptr, c, step, nullptr, k);
     }
-    if (R.live)
+    if (R.live && clear)
         for (int b = t; b < R.nbins; b += nt) R.bin_n[b] = 0;
     if (t == 0) {
-        if (R.live) {
+        if (R.live && clear) {
             st->bin_over = 0;
             st->rebuild = 0;
         }
         st->chunk_done = k;
-        *R.any_rebuild = 0;
+        if (clear) *R.any_rebuild = 0;
     }
 }
 
-// Colour pass `pass` over the sites of every active run.  Blocks from
-// n_spin_blocks on (the launch of pass 1 carries them when lattices are
-// live) take atoms instead: half kick, drift, the electron cell of the new
-// position (into the other cell buffer, so the spin blocks of this launch
-// still see the cells of x^n), the skin check and binning.  They read no
-// spin and the spin blocks read no lattice array.  In a folded chunk the
-// extra blocks of pass 0 end the previous step instead (fold_end_step).
-// `merge` (pass 0): apply the previous step's deferred last half step first.
-template <typename T, int SPT, bool RADIAL = false>
-__global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
-                                                      const int2* __restrict__ work, int pass,
-                                                      const int2* __restrict__ work_kick,
-                                                      int n_spin_blocks, int merge, int fold_k)
+// One atom of the kick table (a block of a colour pass beyond its spin
+// blocks): half kick, drift, the electron cell of the new position (into
+// the buffer of x^{n+1}, so the spin blocks of the launch still see the
+// cells of x^n and x^{n-1}), the skin check and binning, and the step's
+// electron-phonon normals when the force kernel gives an atom several
+// lanes.  It reads no spin.
+template <typename T>
+__device__ __forceinline__ void kick_atom_step(const RunDev<T>* __restrict__ runs, int2 w, int fold_k,
+                                               uint32_t lane)
 {
-    if ((int)blockIdx.x >= n_spin_blocks) {
-        // colour pass 0 at position k >= 1 of a folded chunk: the extra
-        // blocks end step k - 1
-        if (fold_k >= 1 && pass == 0) {
-            fold_end_step(runs[work[0].x], fold_k, (int)blockIdx.x - n_spin_blocks,
-                          (int)gridDim.x - n_spin_blocks);
-            return;
-        }
-        const int2 w = work_kick[blockIdx.x - n_spin_blocks];
-        const RunDev<T>& R = runs[w.x];
-        const int64_t step = step_at(R, fold_k);
-        if (!fold_ok(R.st, fold_k) || step >= R.st->target || !R.live) return;
-        const uint32_t i = (uint32_t)w.y + threadIdx.x;
-        if (i >= (uint32_t)R.n) return;
-        const GView<T> V = global_view(R, step + 1);
-        if (kick_drift_atom(R, V, i, PHASE_STEP, R.radial != 0) &&
-            *(volatile int32_t*)&R.st->rebuild == 0) {
-            atomicOr(&R.st->rebuild, 1);
-            atomicOr(R.any_rebuild, 1);
-        }
-        if (R.bin_step) nbr_bin_atom(R, V, i);
-        if (R.ttm_mode == 1 && R.eta_drawn) {
-            // this step's electron-phonon normals for the force kernel, one
-            // atom per lane (the force kernel gives an atom several)
-            const Site si = decode_site(R.g, i);
-            const uint32_t canon = (((uint32_t)si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
-            const Normals3<T> eta = normals3<T>(R.seed, R.run_id, canon, step, 1u);
-            gst(R.eta, i, eta.a);
-            gst(R.eta + R.n, i, eta.b);
-            gst(R.eta + 2 * R.n, i, eta.c);
-        }
-        return;
+    const RunDev<T>& R = runs[w.x];
+    const int64_t step = step_at(R, fold_k);
+    if (!fold_ok(R.st, fold_k) || step >= R.st->target || !R.live) return;
+    const uint32_t i = (uint32_t)w.y + lane;
+    if (i >= (uint32_t)R.n) return;
+    const GView<T> V = global_view(R, step + 1);
+    if (kick_drift_atom(R, V, i, PHASE_STEP, R.radial != 0) &&
+        *(volatile int32_t*)&R.st->rebuild == 0) {
+        atomicOr(&R.st->rebuild, 1);
+        atomicOr(R.any_rebuild, 1);
     }
-    const int2 w = work[blockIdx.x];
+    if (R.bin_step) nbr_bin_atom(R, V, i);
+    if (R.ttm_mode == 1 && R.eta_drawn) {
+        // this step's electron-phonon normals for the force kernel, one
+        // atom per lane (the force kernel gives an atom several)
+        const Site si = decode_site(R.g, i);
+        const uint32_t canon = (((uint32_t)si.z * R.g.Ly + si.y) * R.g.Lx + si.x) * R.g.nb + si.b;
+        const Normals3<T> eta = normals3<T>(R.seed, R.run_id, canon, step, 1u);
+        gst(R.eta, i, eta.a);
+        gst(R.eta + R.n, i, eta.b);
+        gst(R.eta + 2 * R.n, i, eta.c);
+    }
+}
+
+// The sites of one tile of a colour pass: site first + k nt + lane of the
+// colour, k < SPT.  `merge` (pass 0): apply the previous step's deferred
+// last half step first.
+template <typename T, int SPT, bool RADIAL>
+__device__ __forceinline__ void spin_pass_tile(const RunDev<T>* __restrict__ runs, int2 w, int pass,
+                                               int merge, int fold_k, uint32_t lane, uint32_t nt)
+{
     const RunDev<T>& R = runs[w.x];
     const RunState* st = R.st;
     const int64_t step = step_at(R, fold_k);
@@ -1652,15 +1660,39 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
     // buffer (and this step's T_e is computed from it, its end running in
     // this launch); otherwise kept by the grid update (two-temperature or
     // prescribed) in the second buffer; a fixed grid never changes
-    PrevHalf ph{R.cellb[(step - 1) & 1], R.ttm_mode != 0 ? R.Te_alt : R.Te, nullptr};
+    PrevHalf ph{R.cellb[cell_slot(step - 1)], R.ttm_mode != 0 ? R.Te_alt : R.Te, nullptr};
     if (fold_k >= 1 && pass == 0)
-        ph = PrevHalf{R.cellb[(step - 1) & 1], te_buf(R, fold_k - 1),
+        ph = PrevHalf{R.cellb[cell_slot(step - 1)], te_buf(R, fold_k - 1),
                       R.ttm_mode == 1 ? de_buf(R, fold_k - 1) : nullptr};
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
-        const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
+        const uint32_t l = (uint32_t)w.y + k * nt + lane;
         if (l < (uint32_t)R.g.H) spin_site<T, GView<T>, RADIAL>(R, V, colour, tau, l, step, cur, prev, ph);
     }
+}
+
+// Colour pass `pass` over the sites of every active run.  Blocks from
+// n_spin_blocks on take other work: the first n_fold of them end the
+// previous step of a folded chunk (colour pass 0 at position k >= 1,
+// fold_end_step), the rest kick the atoms of live runs (kick_atom_step).
+// Those read no spin and the spin blocks read no lattice array.
+template <typename T, int SPT, bool RADIAL = false>
+__global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
+                                                      const int2* __restrict__ work, int pass,
+                                                      const int2* __restrict__ work_kick,
+                                                      int n_spin_blocks, int n_fold, int merge, int fold_k)
+{
+    const int e = (int)blockIdx.x - n_spin_blocks;
+    if (e >= 0) {
+        if (e < n_fold) {
+            // the bins and flags are cleared here unless the launch also kicks
+            fold_end_step(runs[work[0].x], fold_k, e, n_fold, (int)gridDim.x - n_spin_blocks == n_fold);
+            return;
+        }
+        kick_atom_step(runs, work_kick[e - n_fold], fold_k, threadIdx.x);
+        return;
+    }
+    spin_pass_tile<T, SPT, RADIAL>(runs, work[blockIdx.x], pass, merge, fold_k, threadIdx.x, blockDim.x);
 }
 
 // First half kick of the atoms of runs with radial exchange (the atom table
@@ -1685,11 +1717,9 @@ __global__ __launch_bounds__(kBlock) void k_half_kick(const RunDev<T>* __restric
 // k_spin_pass, compiled alone, so the kernel holds fewer registers (more
 // waves per SIMD) and gives the same bits.
 template <typename T, int SPT, int LAT, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_spin_pass_lean(const RunDev<T>* __restrict__ runs,
-                                                           const int2* __restrict__ work, int pass,
-                                                           int fold_k)
+__device__ __forceinline__ void spin_lean_tile(const RunDev<T>* __restrict__ runs, int2 w, int pass,
+                                               int fold_k, uint32_t lane, uint32_t nt)
 {
-    const int2 w = work[blockIdx.x];
     const RunDev<T>& R = runs[w.x];
     const RunState* st = R.st;
     const int64_t step = step_at(R, fold_k);
@@ -1701,9 +1731,17 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass_lean(const RunDev<T>* __re
     if (fold_k >= 0) V.Te = te_buf(R, fold_k);
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
-        const uint32_t l = (uint32_t)w.y + k * blockDim.x + threadIdx.x;
+        const uint32_t l = (uint32_t)w.y + k * nt + lane;
         if (l < (uint32_t)R.g.H) spin_site_t<T, GView<T>, LAT, MULTI, false>(R, V, colour, tau, l, step);
     }
+}
+
+template <typename T, int SPT, int LAT, bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_spin_pass_lean(const RunDev<T>* __restrict__ runs,
+                                                           const int2* __restrict__ work, int pass,
+                                                           int fold_k)
+{
+    spin_lean_tile<T, SPT, LAT, MULTI>(runs, work[blockIdx.x], pass, fold_k, threadIdx.x, blockDim.x);
 }
 
 // ------------------------------------------------ LDS-staged colour pass
@@ -1918,9 +1956,9 @@ __global__ __launch_bounds__(NT) void k_spin_tile_bcc(const RunDev<T>* __restric
 }
 
 // Initialisation of the lattice arrays of one run: electron cells and
-// wrapped positions of the current positions, the cell ids into both
+// wrapped positions of the current positions, the cell ids into all three
 // buffers (a frozen lattice never rewrites them).  In steps the kick is
-// carried by colour pass 1.
+// carried by a colour pass.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_lattice(const RunDev<T>* __restrict__ runs,
                                                          const int2* __restrict__ work)
@@ -1931,7 +1969,9 @@ __global__ __launch_bounds__(kBlock) void k_init_lattice(const RunDev<T>* __rest
     const uint32_t i = (uint32_t)w.y + threadIdx.x;
     if (i >= (uint32_t)R.n) return;
     kick_drift_atom(R, global_view(R, step), i, PHASE_INIT);
-    gst(R.cellb[(step + 1) & 1], i, gld(R.cellb[step & 1], i));
+    const uint16_t c = gld(R.cellb[cell_slot(step)], i);
+    gst(R.cellb[cell_slot(step + 1)], i, c);
+    gst(R.cellb[cell_slot(step + 2)], i, c);
 }
 
 // Binning on its own, for a rebuild: at initialisation, and every step for
@@ -1994,34 +2034,42 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const RunDev<T>* __restric
     if (i < (uint32_t)R.n) nbr_build_atom<T, GView<T>, true>(R, global_view(R, 0), i);
 }
 
-// Forces, the second half kick, the electron-phonon step and the
-// observable rows.  In a step whose kick flagged a rebuild, each block first
-// rebuilds the lists of its own atoms: positions and bins are final after
-// the kick, and an atom's forces read only its own list.  `sorted_bins`
-// tells how the bins were filled (unsorted by the kick, or sorted).
-// LPA lanes per atom: a block of B threads takes B / LPA consecutive atoms
-// (a multiple of 64, so observable rows of 64 atoms never straddle blocks).
-// The run's state is read once for the block, so every wave takes the same
-// branch at the barriers even when another block raises an error meanwhile.
-template <typename T, int LPA, bool RADIAL = false>
-__global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
-                                                       const int2* __restrict__ work, int phase,
-                                                       int sorted_bins, int fold_k)
-{
-    __shared__ ObsTerms ostage[LPA > 1 ? kBlock / LPA : 1];
-    // the list build's per-thread bin buffers and the per-cell sums are never
-    // live together (a barrier separates them): one region, 16 KB, so five
-    // 256-thread blocks fit a CU
-    __shared__ union {
+// LDS of one block of the force kernel.  The list build's per-thread bin
+// buffers and the per-cell sums are never live together (a barrier
+// separates them): one region, 16 KB, so five 256-thread blocks fit a CU.
+template <int LPA> struct ForceShared {
+    ObsTerms ostage[LPA > 1 ? kBlock / LPA : 1];
+    union {
         int keep[kBinKeep * kBlock];
         unsigned long long cacc[kLdsCells];
     } lds;
-    unsigned long long* const cacc = lds.cacc;
-    int* const keep = lds.keep;
-    __shared__ int64_t b_step;
-    __shared__ int32_t b_go, b_rebuild;
-    __shared__ uint32_t b_lo[kBlock / 64], b_hi[kBlock / 64];   // per-wave cell ranges
-    const int2 w = work[blockIdx.x];
+    int64_t b_step;
+    int32_t b_go, b_rebuild, b_last;
+    uint32_t b_lo[kBlock / 64], b_hi[kBlock / 64];   // per-wave cell ranges
+};
+
+// Forces, the second half kick, the electron-phonon step and the
+// observable rows of the atoms of one entry w of the atom table.  In a step
+// whose kick flagged a rebuild, each block first rebuilds the lists of its
+// own atoms: positions and bins are final after the kick, and an atom's
+// forces read only its own list.  `sorted_bins` tells how the bins were
+// filled (unsorted by the kick, or sorted).  LPA lanes per atom: a block of
+// B threads takes B / LPA consecutive atoms (a multiple of 64, so
+// observable rows of 64 atoms never straddle blocks).  The run's state is
+// read once for the block, so every wave takes the same branch at the
+// barriers even when another block raises an error meanwhile.
+template <typename T, int LPA, bool RADIAL>
+__device__ __forceinline__ void atom_final_block(const RunDev<T>* __restrict__ runs, int2 w, int phase,
+                                                 int sorted_bins, int fold_k, ForceShared<LPA>& S)
+{
+    ObsTerms* const ostage = S.ostage;
+    unsigned long long* const cacc = S.lds.cacc;
+    int* const keep = S.lds.keep;
+    int64_t& b_step = S.b_step;
+    int32_t& b_go = S.b_go;
+    int32_t& b_rebuild = S.b_rebuild;
+    uint32_t* const b_lo = S.b_lo;
+    uint32_t* const b_hi = S.b_hi;
     const RunDev<T>& R = runs[w.x];
     RunState* st = R.st;
     // the run's state, read once for the block
@@ -2122,6 +2170,82 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
                                    w.y + (int)(threadIdx.x & ~63u), R.n);
             }
         }
+    }
+}
+
+template <typename T, int LPA, bool RADIAL = false>
+__global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restrict__ runs,
+                                                       const int2* __restrict__ work, int phase,
+                                                       int sorted_bins, int fold_k)
+{
+    __shared__ ForceShared<LPA> S;
+    atom_final_block<T, LPA, RADIAL>(runs, work[blockIdx.x], phase, sorted_bins, fold_k, S);
+}
+
+// Colour pass `pass` (no merged half step) beside the force kernel of the
+// same step of a folded chunk's single run, whose kick ran in colour pass
+// 0.  Blocks below n_spin_blocks take n_spin_tiles tiles of the spin table
+// (spin_bt threads each, a multiple of 64, so every wave has one tile) with
+// the specialised site update of k_spin_pass_lean; the others take the atom
+// table.  The force kernel reads spins only on sample steps, which end a
+// chunk and never take this launch.  The step's kick set the bins and
+// flags, and the next step's kick runs beside the end of this step, so this
+// launch clears them: on a step without a list rebuild the force blocks
+// empty the bins in shares; on a rebuild step, when they read them, the
+// last force block to finish does.  (A count of finished blocks on every
+// step cost about 10 ns per block: the atomics on one address serialise.)
+template <typename T, int LPA, int LAT, bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restrict__ runs,
+                                                       const int2* __restrict__ work_spin, int n_spin_tiles,
+                                                       int spin_bt, int n_spin_blocks,
+                                                       const int2* __restrict__ work_atom, int pass,
+                                                       int sorted_bins, int fold_k)
+{
+    __shared__ ForceShared<LPA> S;
+    if ((int)blockIdx.x < n_spin_blocks) {
+        const int per = (int)blockDim.x / spin_bt;
+        const int t = __builtin_amdgcn_readfirstlane((int)blockIdx.x * per + (int)threadIdx.x / spin_bt);
+        if (t < n_spin_tiles)
+            spin_lean_tile<T, 1, LAT, MULTI>(runs, work_spin[t], pass, fold_k, threadIdx.x % (uint32_t)spin_bt,
+                                             (uint32_t)spin_bt);
+        return;
+    }
+    const int2 w = work_atom[blockIdx.x - n_spin_blocks];
+    atom_final_block<T, LPA, false>(runs, w, PHASE_STEP, sorted_bins, fold_k, S);
+    const RunDev<T>& R = runs[w.x];
+    RunState* st = R.st;
+    if (!R.live) return;
+    if (S.b_rebuild == 0) {
+        // no list is built in this launch, so no block reads the bins or
+        // the overflow flag: each force block empties its share of the bins
+        // the kick filled (the rebuild flags are clear)
+        const int nb = (int)gridDim.x - n_spin_blocks, f = (int)blockIdx.x - n_spin_blocks;
+        const int per = (R.nbins + nb - 1) / nb;
+        const int hi = min(R.nbins, (f + 1) * per);
+        if (R.bin_step)
+            for (int b = f * per + (int)threadIdx.x; b < hi; b += blockDim.x) R.bin_n[b] = 0;
+        if (f == 0 && threadIdx.x == 0) st->bin_over = 0;
+        return;
+    }
+    // a rebuild step: every block reads the bins and flags, so the last one
+    // to finish clears them.  No memory fence: a block's reads have returned
+    // (their values were used) before its barrier and count; the clearing
+    // stores reach the next launch at the kernel boundary; and a device
+    // fence would write back and invalidate the L2 of the block's XCD under
+    // the blocks still running there.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int before = atomicAdd(&st->force_done, 1);
+        S.b_last = before == (int)gridDim.x - n_spin_blocks - 1;
+    }
+    __syncthreads();
+    if (!S.b_last) return;
+    for (int b = threadIdx.x; b < R.nbins; b += blockDim.x) R.bin_n[b] = 0;
+    if (threadIdx.x == 0) {
+        st->bin_over = 0;
+        st->rebuild = 0;
+        *R.any_rebuild = 0;
+        st->force_done = 0;
     }
 }
 
@@ -2452,7 +2576,7 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
     const int tid = threadIdx.x, B = blockDim.x;
     const int n = R.n, nc = R.ncell;
     // load the run into LDS
-    const uint16_t* cell_in = R.cellb[st->step & 1];
+    const uint16_t* cell_in = R.cellb[cell_slot(st->step)];
     for (int i = tid; i < n; i += B) {
         V.sx[i] = gld(R.sx, i);
         V.sy[i] = gld(R.sy, i);
@@ -2549,9 +2673,9 @@ __device__ __forceinline__ void persist_run(const RunDev<T>& R, const VW& V, dou
         ++step;
     }
     __syncthreads();
-    // write the run back (cell ids of the current positions to the buffer
-    // of the current step's parity)
-    uint16_t* cell_out = R.cellb[step & 1];
+    // write the run back (cell ids of the current positions to the current
+    // step's buffer)
+    uint16_t* cell_out = R.cellb[cell_slot(step)];
     for (int i = tid; i < n; i += B) {
         gst(R.sx, i, V.sx[i]);
         gst(R.sy, i, V.sy[i]);

@@ -142,7 +142,7 @@ sl_status sl_step_noalloc(sl_system h, int64_t n_steps)
     return h->eng->advance_noalloc(n_steps, p, SL_NOALLOC_SCRATCH_BYTES);
 }
 
-sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[5], int64_t launches[5])
+sl_status sl_step_profiled(sl_system h, int64_t n_steps, double avg_ms[6], int64_t launches[6])
 {
     if (!h || !avg_ms || !launches) return fail(SL_EINVAL, "null argument");
     return h->eng->profiled(n_steps, avg_ms, launches);
@@ -208,6 +208,7 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
         return fail(SL_EINVAL, "atom_block / atom_lanes must be at least 64");
     if (t->merge_sweeps != 0 && t->merge_sweeps != 1) return fail(SL_EINVAL, "merge_sweeps must be 0 or 1");
     if (t->spin_access != 0 && t->spin_access != 1) return fail(SL_EINVAL, "spin_access must be 0 or 1");
+    if (t->fuse_force != 0 && t->fuse_force != 1) return fail(SL_EINVAL, "fuse_force must be 0 or 1");
     e->spin_block = t->spin_block;
     e->spin_spt = t->spin_spt;
     e->atom_block = t->atom_block;
@@ -218,6 +219,7 @@ static sl_status set_tuning(Engine* e, const sl_tuning* t)
     e->atom_lanes = t->atom_lanes;
     e->merge_sweeps = t->merge_sweeps;
     e->spin_access = t->spin_access;
+    e->fuse_force = t->fuse_force;
     return e->retune();
 }
 
@@ -233,6 +235,7 @@ static void get_tuning(const Engine* e, sl_tuning* t)
     t->atom_lanes = e->atom_lanes;
     t->merge_sweeps = e->merge_sweeps;
     t->spin_access = e->spin_access;
+    t->fuse_force = e->fuse_force;
 }
 
 sl_status sl_set_tuning(sl_system h, const sl_tuning* t)
@@ -299,7 +302,7 @@ sl_status sl_batch_advance(sl_batch b, int64_t n_steps)
     return b->eng->advance(n_steps);
 }
 
-sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[5], int64_t launches[5])
+sl_status sl_batch_advance_profiled(sl_batch b, int64_t n_steps, double avg_ms[6], int64_t launches[6])
 {
     if (!b || !avg_ms || !launches) return fail(SL_EINVAL, "null argument");
     return b->eng->profiled(n_steps, avg_ms, launches);

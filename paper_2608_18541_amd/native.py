@@ -84,7 +84,8 @@ class sl_tuning(C.Structure):
     _fields_ = [("spin_block", C.c_int32), ("spin_spt", C.c_int32), ("atom_block", C.c_int32),
                 ("graph_steps", C.c_int32), ("persist_block", C.c_int32),
                 ("xcd_order", C.c_int32), ("bin_mode", C.c_int32), ("atom_lanes", C.c_int32),
-                ("merge_sweeps", C.c_int32), ("spin_access", C.c_int32)]
+                ("merge_sweeps", C.c_int32), ("spin_access", C.c_int32),
+                ("fuse_force", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -384,8 +385,8 @@ class System:
         return a.value, b.value, c.value
 
     def step_profiled(self, n: int):
-        avg = (C.c_double * 5)()
-        cnt = (C.c_int64 * 5)()
+        avg = (C.c_double * 6)()
+        cnt = (C.c_int64 * 6)()
         check(lib().sl_step_profiled(self._h, int(n), avg, cnt))
         return list(avg), list(cnt)
 
@@ -480,8 +481,8 @@ class Batch:
         return out.to_dict()
 
     def advance_profiled(self, n: int):
-        avg = (C.c_double * 5)()
-        cnt = (C.c_int64 * 5)()
+        avg = (C.c_double * 6)()
+        cnt = (C.c_int64 * 6)()
         check(lib().sl_batch_advance_profiled(self._h, int(n), avg, cnt))
         return list(avg), list(cnt)
 

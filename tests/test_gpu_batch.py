@@ -285,7 +285,7 @@ def test_launch_shapes_are_bitwise_identical(N):
         best = autotune(b, steps=8, use_cache=False)
         assert set(best) == {"spin_block", "spin_spt", "atom_block", "graph_steps",
                              "persist_block", "xcd_order", "bin_mode", "atom_lanes",
-                             "merge_sweeps", "spin_access"}
+                             "merge_sweeps", "spin_access", "fuse_force"}
         info = {r["slot"]: r["steps_done"] for r in b.runs()}
         for (sp, st), s in zip(runs, slots):
             alone = N.System(sp, st, precision=prec)

@@ -1,0 +1,123 @@
+"""The fused schedule (tuning fuse_force): in the folded chunks of a single
+run with a live lattice, each step kicks the atoms in colour pass 0 and runs
+the force kernel in the launch of colour pass 1; the chunk's last step (a
+sample step) keeps its force kernel after the sweep.  The schedule changes
+which launch carries the work, not the work: it must give the bits of the
+unfused schedule in every launch shape, across list rebuilds, with binning
+by separate launches, and in both precisions.  Against the oracle the
+default (fused) schedule is held by the rebuild and full-size windows.
+"""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_18541_amd import inputs as I
+from tests.gpu_util import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_18541_amd import native
+    native.lib()
+    return native
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _case(name):
+    if name == "alloy_laser":
+        # laser-heated sc alloy, 3^3 electron grid updated every step
+        spec = I.gdfeco_sc_spec(L=12, tn=3, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005, seed=8, run_id=3)
+        return spec, I.initial_state(spec, "afm"), 10
+    # bcc Fe with a 0.05 A skin at 600 K: a list rebuild every few tens of steps
+    spec = replace(I.fe_bcc_spec(L=6, seed=31, run_id=2, alpha=0.05), skin=0.05)
+    return spec, I.initial_state(spec, "tilt", T_lattice=600.0), 20
+
+
+SHAPES = [
+    {},                                            # automatic: 64-thread colour passes, 4 lanes per atom
+    {"atom_lanes": 1},
+    {"atom_lanes": 2},
+    {"spin_block": 128},
+    {"spin_block": 256},
+    {"spin_block": 64, "atom_block": 128, "atom_lanes": 2},
+    {"bin_mode": 2},                               # binning launches between the kick and the forces
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["alloy_laser", "bcc_rebuilds"])
+@pytest.mark.parametrize("shape", range(len(SHAPES)))
+def test_fused_equals_unfused(N, case, prec, shape):
+    spec, st, every = _case(case)
+    tun = SHAPES[shape]
+    _log("case: %s prec=%d shape=%s" % (case, prec, tun))
+    ref = N.System(spec, st, precision=prec, obs_every=every)
+    ref.set_tuning(fuse_force=0, **tun)
+    fz = N.System(spec, st, precision=prec, obs_every=every)
+    fz.set_tuning(fuse_force=1, **tun)
+    for chunk in (7, 23, 15, 40, 1, 34):
+        ref.step(chunk)
+        fz.step(chunk)
+        a, b = ref.state(), fz.state()
+        for k in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[k], b[k]), (case, chunk, k)
+    # the same schedules with every launch timed: only the fused one has
+    # colour passes carrying the force kernel (class 5)
+    _, cr = ref.step_profiled(2 * every)
+    _, cf = fz.step_profiled(2 * every)
+    assert cr[5] == 0 and cf[5] == 2 * (every - 1), (cr, cf)
+    assert cf[1] == 2 and cr[1] == 2 * every, (cr, cf)
+    a, b = ref.state(), fz.state()
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(a[k], b[k]), (case, "profiled", k)
+    oa, ob = ref.observables(), fz.observables()
+    assert [o["step"] for o in oa] == [o["step"] for o in ob]
+    for x, y in zip(oa, ob):
+        for k in ("E_ex", "E_z", "KE", "PE", "m_abs", "Te_mean"):
+            assert x[k] == y[k], (case, x["step"], k)
+    sr, sf = ref.stats(), fz.stats()
+    assert sr["list_rebuilds"] == sf["list_rebuilds"]
+    if case == "bcc_rebuilds":
+        assert sf["list_rebuilds"] >= 4, sf
+    ref.close()
+    fz.close()
+
+
+def test_fused_rebuild_window_against_oracle(N):
+    """The fused schedule (the default, checked in the tuning) in chunks of
+    20 steps against the oracle over 150 steps that cross at least three
+    list rebuilds, FP64 at 1e-10 per component."""
+    spec, st, every = _case("bcc_rebuilds")
+    _log("fused: bcc 6^3 skin 0.05 600 K against the oracle")
+    g = N.System(spec, st, precision=N.SL_FP64, obs_every=every)
+    assert g.tuning()["fuse_force"] == 1
+    g.step(150)
+    stats = g.stats()
+    o = O.Oracle(spec, st.species, st.spins, st.vel)
+    o.step(150)
+    errs, bad = compare_states(g.state(), o.state(), spec.box, 1e-10)
+    assert not bad, errs
+    assert stats["list_rebuilds"] >= 4, stats
+    g.close()
+
+
+def test_fuse_knob_rejects_other_values(N):
+    spec, st, every = _case("alloy_laser")
+    g = N.System(spec, st, precision=0, obs_every=every)
+    with pytest.raises(N.SLError) as e:
+        g.set_tuning(fuse_force=2)
+    assert e.value.code == N.SL_EINVAL
+    assert g.tuning()["fuse_force"] == 1
+    g.close()

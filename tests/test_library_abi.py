@@ -76,6 +76,7 @@ int main(void) {
   P(sl_batch_desc, mem_budget) P(sl_batch_desc, alloc)
   printf("sl_tuning size %zu\n", sizeof(sl_tuning));
   P(sl_tuning, graph_steps) P(sl_tuning, persist_block) P(sl_tuning, xcd_order) P(sl_tuning, bin_mode) P(sl_tuning, atom_lanes) P(sl_tuning, merge_sweeps) P(sl_tuning, spin_access)
+  P(sl_tuning, fuse_force)
   printf("sl_run_stats size %zu\n", sizeof(sl_run_stats));
   P(sl_run_stats, list_rebuilds) P(sl_run_stats, max_list) P(sl_run_stats, list_capacity)
   P(sl_run_stats, list_rescans) P(sl_run_stats, error)
