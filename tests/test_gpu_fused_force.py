@@ -121,3 +121,79 @@ def test_fuse_knob_rejects_other_values(N):
     assert e.value.code == N.SL_EINVAL
     assert g.tuning()["fuse_force"] == 1
     g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_batch_run_ends_inside_a_chunk(N, prec):
+    """A batch's only run (multi-kernel, so it folds and fuses) reaches its
+    target at step 37 inside a chunk of 10: the steps after it in the chunk
+    skip their kick and force work, the chunk's end moves the counter to 37,
+    and the run has the bits of the unfused system stepped 37 times."""
+    spec, st, every = _case("alloy_laser")
+    _log("fused: batch run ending at step 37, prec=%d" % prec)
+    b = N.Batch(precision=prec, max_runs=1)
+    b.set_tuning(persist_block=0)
+    slot = b.add(spec, st, 37, obs_every=every)
+    b.advance(60)
+    g = b.get(slot)
+    assert b.stats(slot)["steps"] == 37
+    ref = N.System(spec, st, precision=prec, obs_every=every)
+    ref.set_tuning(fuse_force=0)
+    ref.step(37)
+    a = ref.state()
+    for k in ("s", "x", "v", "Te"):
+        assert np.array_equal(a[k], g[k]), k
+    assert [o["step"] for o in g["obs"]] == [0, 10, 20, 30]
+    b.close()
+    ref.close()
+
+
+def test_fused_set_state_mid_run(N):
+    """A checkpoint restored into a running system (lists, cells and forces
+    recomputed) continues with the same bits under both schedules."""
+    spec, st, every = _case("bcc_rebuilds")
+    _log("fused: set_state after 25 steps")
+    out = []
+    for fz in (0, 1):
+        g = N.System(spec, st, precision=N.SL_FP64, obs_every=every)
+        g.set_tuning(fuse_force=fz)
+        g.step(25)
+        a = g.state()
+        g.set_state(x=a["x"], v=a["v"], s=a["s"])
+        g.step(55)
+        out.append(g.state())
+        g.close()
+    for k in ("s", "x", "v"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def _poke_nan(alloc, block, fp32):
+    import torch
+    t = alloc._live[block]
+    off = block - t.data_ptr()
+    b = np.array([np.nan], dtype=np.float32 if fp32 else np.float64).view(np.uint8).copy()
+    t[off:off + b.size] = torch.from_numpy(b).to(t.device)
+    torch.cuda.synchronize()
+
+
+def test_fused_watchdog_stops_the_run(N):
+    """A NaN written into the spins of a batch's only run between advances
+    (the fused schedule): the run stops with SL_ENUMERIC and its watchdog
+    bit before its target, and the advance after it returns."""
+    spec, st, every = _case("alloy_laser")
+    _log("fused: watchdog on a single folded run")
+    b = N.Batch(precision=0, max_runs=1)
+    b.set_tuning(persist_block=0)
+    h0 = len(b._alloc.history)
+    slot = b.add(spec, st, 120, obs_every=every)
+    block = b._alloc.history[h0][0]
+    b.advance(40)
+    b.synchronize()
+    _poke_nan(b._alloc, block, False)
+    b.advance(80)
+    with pytest.raises(N.SLError) as e:
+        b.synchronize()
+    assert e.value.code == N.SL_ENUMERIC
+    s = b.stats(slot)
+    assert s["error"] & 16 and s["steps"] < 120, s
+    b.close()
