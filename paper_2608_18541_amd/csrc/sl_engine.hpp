@@ -1762,6 +1762,10 @@ private:
                     launch_lean(g, bs, st, a, b, pass, fold_k);
                     return;
                 }
+                if (lean_lat >= 0 && spin_spt == 1) {
+                    spin_pass_form(g, bs, st, a, b, pass, nf, merge, fold_k);
+                    return;
+                }
                 if (any_radial) {
                     if (spin_spt == 4)
                         launch(sl::k_spin_pass<T, 4, true>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
@@ -1873,6 +1877,30 @@ private:
                 launch(sl::k_persist<T, 512, true>, g, bl, persist_bytes, st, a, b, d_runs, d_persist_list, nsteps, lds_max);
             else
                 launch(sl::k_persist<T, 512>, g, bl, persist_bytes, st, a, b, d_runs, d_persist_list, nsteps, lds_max);
+        }
+    }
+
+    // A colour pass with extra blocks (or a deferred half step) whose spin
+    // blocks take the specialised site update of the engine's form.
+    template <int LAT, bool MULTI>
+    void spin_pass_as(dim3 g, dim3 bs, hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int nf, int merge,
+                      int fold_k)
+    {
+        launch(sl::k_spin_pass<T, 1, false, LAT, MULTI>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
+               d_work_kick, active_blocks_spin, nf, merge, fold_k);
+    }
+    void spin_pass_form(dim3 g, dim3 bs, hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int nf, int merge,
+                        int fold_k)
+    {
+        if (lean_lat == SL_LATTICE_SC) {
+            if (lean_multi) spin_pass_as<SL_LATTICE_SC, true>(g, bs, st, a, b, pass, nf, merge, fold_k);
+            else spin_pass_as<SL_LATTICE_SC, false>(g, bs, st, a, b, pass, nf, merge, fold_k);
+        } else if (lean_lat == SL_LATTICE_FCC) {
+            if (lean_multi) spin_pass_as<SL_LATTICE_FCC, true>(g, bs, st, a, b, pass, nf, merge, fold_k);
+            else spin_pass_as<SL_LATTICE_FCC, false>(g, bs, st, a, b, pass, nf, merge, fold_k);
+        } else {
+            if (lean_multi) spin_pass_as<SL_LATTICE_BCC, true>(g, bs, st, a, b, pass, nf, merge, fold_k);
+            else spin_pass_as<SL_LATTICE_BCC, false>(g, bs, st, a, b, pass, nf, merge, fold_k);
         }
     }
 

@@ -1633,8 +1633,10 @@ __device__ __forceinline__ void kick_atom_step(const RunDev<T>* __restrict__ run
 
 // The sites of one tile of a colour pass: site first + k nt + lane of the
 // colour, k < SPT.  `merge` (pass 0): apply the previous step's deferred
-// last half step first.
-template <typename T, int SPT, bool RADIAL>
+// last half step first.  LAT >= 0: the specialised site update of that
+// lattice and species form (no anisotropy, constant exchange), which the
+// engine takes when every run has that form.
+template <typename T, int SPT, bool RADIAL, int LAT = -1, bool MULTI = false>
 __device__ __forceinline__ void spin_pass_tile(const RunDev<T>* __restrict__ runs, int2 w, int pass,
                                                int merge, int fold_k, uint32_t lane, uint32_t nt)
 {
@@ -1667,7 +1669,12 @@ __device__ __forceinline__ void spin_pass_tile(const RunDev<T>* __restrict__ run
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const uint32_t l = (uint32_t)w.y + k * nt + lane;
-        if (l < (uint32_t)R.g.H) spin_site<T, GView<T>, RADIAL>(R, V, colour, tau, l, step, cur, prev, ph);
+        if (l < (uint32_t)R.g.H) {
+            if constexpr (LAT >= 0)
+                spin_site_t<T, GView<T>, LAT, MULTI, false>(R, V, colour, tau, l, step, cur, prev, ph);
+            else
+                spin_site<T, GView<T>, RADIAL>(R, V, colour, tau, l, step, cur, prev, ph);
+        }
     }
 }
 
@@ -1675,8 +1682,9 @@ __device__ __forceinline__ void spin_pass_tile(const RunDev<T>* __restrict__ run
 // n_spin_blocks on take other work: the first n_fold of them end the
 // previous step of a folded chunk (colour pass 0 at position k >= 1,
 // fold_end_step), the rest kick the atoms of live runs (kick_atom_step).
-// Those read no spin and the spin blocks read no lattice array.
-template <typename T, int SPT, bool RADIAL = false>
+// Those read no spin and the spin blocks read no lattice array.  LAT >= 0:
+// the spin blocks take the specialised site update (spin_pass_tile).
+template <typename T, int SPT, bool RADIAL = false, int LAT = -1, bool MULTI = false>
 __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restrict__ runs,
                                                       const int2* __restrict__ work, int pass,
                                                       const int2* __restrict__ work_kick,
@@ -1692,7 +1700,8 @@ __global__ __launch_bounds__(kBlock) void k_spin_pass(const RunDev<T>* __restric
         kick_atom_step(runs, work_kick[e - n_fold], fold_k, threadIdx.x);
         return;
     }
-    spin_pass_tile<T, SPT, RADIAL>(runs, work[blockIdx.x], pass, merge, fold_k, threadIdx.x, blockDim.x);
+    spin_pass_tile<T, SPT, RADIAL, LAT, MULTI>(runs, work[blockIdx.x], pass, merge, fold_k, threadIdx.x,
+                                               blockDim.x);
 }
 
 // First half kick of the atoms of runs with radial exchange (the atom table
