@@ -346,14 +346,14 @@ typedef struct sl_tuning {
                                  the rows and planes and a row holds whole
                                  16-byte vectors; otherwise 0 runs).  Same
                                  bits either way                              */
-    int32_t fuse_force;       /* 1 (default): in the folded chunks of a single run
-                                 with a live lattice, constant exchange and no
-                                 anisotropy (one site per thread, atom_block a
-                                 multiple of the colour-pass block), each step
-                                 kicks the atoms in colour pass 0 and runs the
-                                 force kernel in the launch of colour pass 1,
-                                 but for the chunk's last step: two launches
-                                 per step instead of three.  0: the kick rides with
+    int32_t fuse_force;       /* 1 (default): in the merged chunks (merge_sweeps)
+                                 of multi-kernel runs with constant exchange and
+                                 no anisotropy, a live lattice among them (one site
+                                 per thread, atom_block a multiple of the
+                                 colour-pass block), each step kicks the atoms
+                                 in colour pass 0 and runs the force kernel in
+                                 the launch of colour pass 1, but for the
+                                 chunk's last step: one launch fewer per step.  0: the kick rides with
                                  colour pass 1 and the force kernel follows the
                                  sweep.  Same bits either way                 */
 } sl_tuning;

@@ -381,7 +381,7 @@ public:
     std::vector<int> mk_runs;       // the runs on the multi-kernel step
     bool fold = false;              // chunks end each step inside the next one's colour pass 0
     int fold_blocks = 0;            // the blocks of colour pass 0 that end the previous step
-    bool fused = false;             // fuse_force applies to the folded chunks
+    bool fused = false;             // fuse_force applies to the merged chunks
     int force_spin_blocks = 0;      // blocks of k_spin_force holding the colour pass
     int lanes_eff = 1;              // the lanes in use (tables are built for it)
     virtual sl_status retune() = 0;
@@ -1600,14 +1600,14 @@ private:
                 }
             }
         }
-        // the fused schedule (tuning fuse_force): a folded run with a live
-        // lattice and the specialised site update (merging already excludes
-        // radial exchange), one site per thread, and force blocks that hold
-        // whole colour-pass tiles
+        // the fused schedule (tuning fuse_force): merged chunks of runs with
+        // the specialised site update (merging already excludes radial
+        // exchange), a live lattice among them, one site per thread, and
+        // force blocks that hold whole colour-pass tiles
         fused = false;
         force_spin_blocks = 0;
-        if (fold && fuse_force && host_rd[rl[0]].live && lean_lat >= 0 && spin_spt == 1 &&
-            atom_block % spin_eff == 0 && !wk.empty()) {
+        if (merge_g >= 2 && fuse_force && lean_lat >= 0 && spin_spt == 1 && atom_block % spin_eff == 0 &&
+            !wk.empty()) {
             fused = true;
             const int per = atom_block / spin_eff;
             force_spin_blocks = ((int)ws.size() + per - 1) / per;
@@ -1712,9 +1712,10 @@ private:
     // pass 0 in the fused schedule).
     // fold_k >= 0: position of the step in a folded chunk of chunk_len steps
     // (its pass 0 ends the previous step, and only the chunk's last step has
-    // a k_finalize).  In the fused schedule the force kernel of every step
-    // but the chunk's last (a sample step, whose force kernel reads the
-    // spins after the whole sweep) runs in the launch of colour pass 1.
+    // a k_finalize).  In the fused schedule (merged chunks) the force
+    // kernel of every step but the chunk's last (a sample step, whose force
+    // kernel reads the spins after the whole sweep) runs in the launch of
+    // colour pass 1.
     sl_status enqueue_step(hipStream_t st, Prof* p, bool merge_first = false, bool defer_last = false,
                            int fold_k = -1, int chunk_len = 0)
     {
@@ -1722,8 +1723,8 @@ private:
         // the atom table's tiles hold atom_block / atom_lanes atoms:
         // k_atom_final gives each atom_lanes threads
         const dim3 bs(spin_eff), ba(atom_block), bk(sl::kBlock);
-        const bool kick0 = fused && fold_k >= 0;
-        const bool force1 = kick0 && fold_k < (chunk_len > 0 ? chunk_len : merge_g) - 1;
+        const bool kick0 = fused && chunk_len > 0;
+        const bool force1 = kick0 && defer_last;
         sl_status e;
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
             if (defer_last && pass == 2 * C - 2) break;
@@ -1911,7 +1912,7 @@ private:
     {
         const dim3 g(force_spin_blocks + active_blocks_atom), bl(atom_block);
         launch(sl::k_spin_force<T, LPA, LAT, MULTI>, g, bl, 0, st, a, b, d_runs, d_work_spin, active_blocks_spin,
-               spin_eff, force_spin_blocks, d_work_atom, pass, bin_each_step ? 0 : 1, fold_k);
+               spin_eff, force_spin_blocks, d_work_atom, pass, bin_each_step ? 0 : 1, fold_k, fold ? 1 : 0);
     }
     template <int LPA> void spin_force_lanes(hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int fold_k)
     {

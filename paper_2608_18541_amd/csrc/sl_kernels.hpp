@@ -2192,23 +2192,23 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
 }
 
 // Colour pass `pass` (no merged half step) beside the force kernel of the
-// same step of a folded chunk's single run, whose kick ran in colour pass
-// 0.  Blocks below n_spin_blocks take n_spin_tiles tiles of the spin table
+// same step of a merged chunk, whose kick ran in colour pass 0.  Blocks below n_spin_blocks take n_spin_tiles tiles of the spin table
 // (spin_bt threads each, a multiple of 64, so every wave has one tile) with
 // the specialised site update of k_spin_pass_lean; the others take the atom
 // table.  The force kernel reads spins only on sample steps, which end a
-// chunk and never take this launch.  The step's kick set the bins and
-// flags, and the next step's kick runs beside the end of this step, so this
-// launch clears them: on a step without a list rebuild the force blocks
-// empty the bins in shares; on a rebuild step, when they read them, the
-// last force block to finish does.  (A count of finished blocks on every
+// chunk and never take this launch.  Unfolded, each step's k_finalize
+// clears the bins and flags the kick set.  In a folded chunk (`clear`, a
+// single run) the next step's kick runs beside the end of this step, so
+// this launch clears them: on a step without a list rebuild the force
+// blocks empty the bins in shares; on a rebuild step, when they read them,
+// the last force block to finish does.  (A count of finished blocks on every
 // step cost about 10 ns per block: the atomics on one address serialise.)
 template <typename T, int LPA, int LAT, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work_spin, int n_spin_tiles,
                                                        int spin_bt, int n_spin_blocks,
                                                        const int2* __restrict__ work_atom, int pass,
-                                                       int sorted_bins, int fold_k)
+                                                       int sorted_bins, int fold_k, int clear)
 {
     __shared__ ForceShared<LPA> S;
     if ((int)blockIdx.x < n_spin_blocks) {
@@ -2223,7 +2223,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restri
     atom_final_block<T, LPA, false>(runs, w, PHASE_STEP, sorted_bins, fold_k, S);
     const RunDev<T>& R = runs[w.x];
     RunState* st = R.st;
-    if (!R.live) return;
+    if (!clear || !R.live) return;
     if (S.b_rebuild == 0) {
         // no list is built in this launch, so no block reads the bins or
         // the overflow flag: each force block empties its share of the bins

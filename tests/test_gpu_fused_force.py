@@ -197,3 +197,62 @@ def test_fused_watchdog_stops_the_run(N):
     s = b.stats(slot)
     assert s["error"] & 16 and s["steps"] < 120, s
     b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_batch_of_runs_merging_together(N, prec):
+    """Three live runs on the multi-kernel step merging together (unfolded:
+    each step ends in k_finalize, which clears the bins and flags): the fused
+    schedule gives the bits of the unfused one and of each run alone."""
+    specs = [replace(I.gdfeco_sc_spec(L=10, tn=2, alpha=0.03, S0=0.6, t0=0.005, fwhm=0.005,
+                                      seed=60 + k, run_id=k), skin=0.1) for k in range(3)]
+    states = [I.initial_state(sp, "afm", T_lattice=600.0) for sp in specs]
+    _log("fused: batch of three merging runs, prec=%d" % prec)
+    got = []
+    for fz in (0, 1):
+        b = N.Batch(precision=prec, max_runs=3)
+        b.set_tuning(persist_block=0, fuse_force=fz)
+        slots = [b.add(sp, st, 90, obs_every=10) for sp, st in zip(specs, states)]
+        b.advance(23)
+        _, cnt = b.advance_profiled(27)
+        assert (cnt[5] > 0) == (fz == 1), cnt
+        b.advance(60)
+        got.append([b.get(s) for s in slots])
+        b.close()
+    for k, sp in enumerate(specs):
+        for key in ("s", "x", "v", "Te"):
+            assert np.array_equal(got[0][k][key], got[1][k][key]), (k, key)
+        alone = N.System(sp, states[k], precision=prec, obs_every=10)
+        alone.step(90)
+        a = alone.state()
+        for key in ("s", "x", "v", "Te"):
+            assert np.array_equal(a[key], got[1][k][key]), (k, key)
+        assert [o["step"] for o in got[1][k]["obs"]] == list(range(0, 91, 10))
+        alone.close()
+
+
+def test_fused_unfolded_single_run_with_diffusion(N):
+    """A single run whose diffusing electron grid keeps its own launches (no
+    folding) still merges and fuses: same bits as unfused, against the
+    oracle within 1e-10 after 40 steps."""
+    spec = replace(I.gdfeco_sc_spec(L=8, tn=2, alpha=0.05, S0=0.6, t0=0.005, fwhm=0.005,
+                                    kappa_e=I.w_per_mk_to_metal(80.0), n_sub=2, seed=71, run_id=1),
+                   tn=(2, 2, 4))
+    st = I.initial_state(spec, "afm")
+    _log("fused: unfolded single run with diffusion")
+    out = []
+    for fz in (0, 1):
+        g = N.System(spec, st, precision=N.SL_FP64, obs_every=10)
+        g.set_tuning(fuse_force=fz)
+        g.step(13)
+        _, cnt = g.step_profiled(17)
+        assert (cnt[5] > 0) == (fz == 1), cnt
+        g.step(10)
+        out.append(g.state())
+        g.close()
+    for key in ("s", "x", "v", "Te"):
+        assert np.array_equal(out[0][key], out[1][key]), key
+    o = O.Oracle(spec, st.species, st.spins, st.vel)
+    o.step(40)
+    errs, bad = compare_states(out[1], o.state(), spec.box, 1e-10)
+    assert not bad, errs

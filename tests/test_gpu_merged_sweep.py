@@ -166,26 +166,33 @@ def test_negative_electron_energy_inside_a_chunk(N):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_runs_merge_together(N, prec):
+@pytest.mark.parametrize("fuse", [0, 1])
+def test_batch_runs_merge_together(N, prec, fuse):
     """Three sc alloys added together to a batch on the multi-kernel step
     (same colour count, sample interval 10) advance in merged chunks: one
     colour pass without the kick per step instead of two, except at a
-    chunk's last step.  Each run keeps the bits it has alone stepped one by
-    one; two of them reach their targets inside a chunk."""
+    chunk's last step (with the force kernel beside colour pass 1: no
+    colour pass alone but a chunk's last step's two).  Each run keeps the
+    bits it has alone stepped one by one; two of them reach their targets
+    inside a chunk."""
     specs = [I.gdfeco_sc_spec(L=L, tn=2, alpha=0.02 * (k + 1), S0=0.6, t0=0.005, fwhm=0.005,
                               seed=20 + k, run_id=k) for k, L in enumerate((8, 10, 12))]
     states = [I.initial_state(sp, "afm") for sp in specs]
     targets = [37, 50, 44]
     _log("case: batch of 3 sc alloys, prec=%d" % prec)
     b = N.Batch(precision=prec, max_runs=4)
-    b.set_tuning(persist_block=0)
+    b.set_tuning(persist_block=0, fuse_force=fuse)
     slots = [b.add(sp, st, t, obs_every=10) for sp, st, t in zip(specs, states, targets)]
     b.advance(23)
     # a shorter merged chunk of 7 steps up to step 30, then two chunks of 10:
-    # one colour pass without the kick per step, plus the last step's
-    # closing pass in each chunk
+    # unfused, one colour pass without the kick per step, plus the last
+    # step's closing pass in each chunk; fused, every colour pass 0 carries
+    # the kick and every colour pass 1 but a chunk's last the force kernel
     avg, cnt = b.advance_profiled(27)
-    assert cnt[0] == (7 + 1) + 2 * 11, cnt
+    if fuse:
+        assert cnt[0] == 2 * 3 and cnt[2] == 27 and cnt[5] == 27 - 3 and cnt[1] == 3, cnt
+    else:
+        assert cnt[0] == (7 + 1) + 2 * 11 and cnt[5] == 0, cnt
     for sp, st, t, s in zip(specs, states, targets, slots):
         g = b.get(s)
         ref = N.System(sp, st, precision=prec, obs_every=1)
