@@ -374,7 +374,7 @@ public:
     int merge_sweeps = 1;           // 1: merge adjacent colour half steps when possible
     int spin_access = 0;            // colour-pass neighbour access: 0 gathers per site,
                                     // 1 LDS-staged rows (where they apply)
-    int fuse_force = 1;             // 1: folded chunks kick in colour pass 0 and run the
+    int fuse_force = 1;             // 1: merged chunks kick in colour pass 0 and run the
                                     // force kernel in the launch of colour pass 1
     int merge_g = 0;                // >= 2: steps per merged chunk of the multi-kernel runs
     int merge_run = -1;             // a stepping run among them (its step gives the chunk phase)

@@ -11,14 +11,18 @@
 //                          pass 1 also carries the lattice's half kick +
 //                          drift, electron-cell id, skin check and binning
 //                          (they read no spin, and the cell ids of the new
-//                          positions go to the other of two buffers).  In a
-//                          merged chunk a step leaves its last pass (colour
-//                          0, half step) to the next step's pass 0, which
-//                          applies it before its own: 2C-2 passes per step;
-//                          when the chunk is folded, extra blocks of pass 0
-//                          also end the previous step (small electron grid,
-//                          bins, flags) while its spin blocks compute the
-//                          new T_e of their cells from the same inputs
+//                          positions go to the third of three buffers).  In
+//                          a merged chunk a step leaves its last pass
+//                          (colour 0, half step) to the next step's pass 0,
+//                          which applies it before its own: 2C-2 passes per
+//                          step; when the chunk is folded, extra blocks of
+//                          pass 0 also end the previous step (small electron
+//                          grid, bins, flags) while its spin blocks compute
+//                          the new T_e of their cells from the same inputs.
+//                          In the fused schedule of merged chunks pass 0
+//                          carries the kick and pass 1 is k_spin_force,
+//                          which also runs k_atom_final's work, for every
+//                          step but a chunk's last
 //   k_nbr_bin, k_nbr_sort  binning for a rebuild (large engines; exit at
 //                          once unless a rebuild is flagged)
 //   k_atom_final           Verlet-list rebuild of its own atoms when flagged,
