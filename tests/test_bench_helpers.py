@@ -34,6 +34,17 @@ def test_algorithmic_bytes_per_unit():
     assert bench.bytes_per_unit("atom_final", 1, 2, 18.0) == 127
 
 
+def test_launch_bytes_of_the_fused_launch():
+    """Colour pass 1 carrying the force kernel moves the bytes of both: the
+    colour's sites (half of an sc lattice) and every atom."""
+    n, z = 32768, 18.0
+    sp = bench.launch_bytes("spin_pass", 0, 2, z, n, 2)
+    af = bench.launch_bytes("atom_final", 0, 2, z, n, 2)
+    assert sp == 51 * n / 2 and af == 175 * n
+    assert bench.launch_bytes("spin_force", 0, 2, z, n, 2) == sp + af == 6569984
+    assert "spin_force" in bench.KERNELS and bench.KERNELS.index("spin_force") == 5
+
+
 def _write_profile(tmp_path, name, digest, tuning=None, value=12345.0):
     lines = ["# test", "traffic_bytes_per_launch: %.0f" % value, "source_sha256: %s" % digest]
     if tuning is not None:
