@@ -382,7 +382,8 @@ public:
     bool fold = false;              // chunks end each step inside the next one's colour pass 0
     int fold_blocks = 0;            // the blocks of colour pass 0 that end the previous step
     bool fused = false;             // fuse_force applies to the merged chunks
-    int force_spin_blocks = 0;      // blocks of k_spin_force holding the colour pass
+    int force_spin_blocks = 0;      // blocks of k_spin_force holding the colour pass (after
+                                    // those of the atom table)
     int lanes_eff = 1;              // the lanes in use (tables are built for it)
     virtual sl_status retune() = 0;
     virtual sl_status init_device() = 0;
@@ -1912,7 +1913,7 @@ private:
     {
         const dim3 g(force_spin_blocks + active_blocks_atom), bl(atom_block);
         launch(sl::k_spin_force<T, LPA, LAT, MULTI>, g, bl, 0, st, a, b, d_runs, d_work_spin, active_blocks_spin,
-               spin_eff, force_spin_blocks, d_work_atom, pass, bin_each_step ? 0 : 1, fold_k, fold ? 1 : 0);
+               spin_eff, active_blocks_atom, d_work_atom, pass, bin_each_step ? 0 : 1, fold_k, fold ? 1 : 0);
     }
     template <int LPA> void spin_force_lanes(hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int fold_k)
     {

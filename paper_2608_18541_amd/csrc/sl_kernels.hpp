@@ -2196,34 +2196,37 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
 }
 
 // Colour pass `pass` (no merged half step) beside the force kernel of the
-// same step of a merged chunk, whose kick ran in colour pass 0.  Blocks below n_spin_blocks take n_spin_tiles tiles of the spin table
-// (spin_bt threads each, a multiple of 64, so every wave has one tile) with
-// the specialised site update of k_spin_pass_lean; the others take the atom
-// table.  The force kernel reads spins only on sample steps, which end a
-// chunk and never take this launch.  Unfolded, each step's k_finalize
-// clears the bins and flags the kick set.  In a folded chunk (`clear`, a
-// single run) the next step's kick runs beside the end of this step, so
-// this launch clears them: on a step without a list rebuild the force
-// blocks empty the bins in shares; on a rebuild step, when they read them,
-// the last force block to finish does.  (A count of finished blocks on every
-// step cost about 10 ns per block: the atomics on one address serialise.)
+// same step of a merged chunk, whose kick ran in colour pass 0.  The first
+// n_atom_blocks blocks take the atom table (the force kernel, the longer
+// chain, is dispatched first); the others take n_spin_tiles tiles of the
+// spin table (spin_bt threads each, a multiple of 64, so every wave has one
+// tile) with the specialised site update of k_spin_pass_lean.  The force
+// kernel reads spins only on sample steps, which end a chunk and never take
+// this launch.  Unfolded, each step's k_finalize clears the bins and flags
+// the kick set.  In a folded chunk (`clear`, a single run) the next step's
+// kick runs beside the end of this step, so this launch clears them: on a
+// step without a list rebuild the force blocks empty the bins in shares; on
+// a rebuild step, when they read them, the last force block to finish does.
+// (A count of finished blocks on every step cost about 10 ns per block: the
+// atomics on one address serialise.)
 template <typename T, int LPA, int LAT, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work_spin, int n_spin_tiles,
-                                                       int spin_bt, int n_spin_blocks,
+                                                       int spin_bt, int n_atom_blocks,
                                                        const int2* __restrict__ work_atom, int pass,
                                                        int sorted_bins, int fold_k, int clear)
 {
     __shared__ ForceShared<LPA> S;
-    if ((int)blockIdx.x < n_spin_blocks) {
+    if ((int)blockIdx.x >= n_atom_blocks) {
         const int per = (int)blockDim.x / spin_bt;
-        const int t = __builtin_amdgcn_readfirstlane((int)blockIdx.x * per + (int)threadIdx.x / spin_bt);
+        const int t = __builtin_amdgcn_readfirstlane(((int)blockIdx.x - n_atom_blocks) * per +
+                                                     (int)threadIdx.x / spin_bt);
         if (t < n_spin_tiles)
             spin_lean_tile<T, 1, LAT, MULTI>(runs, work_spin[t], pass, fold_k, threadIdx.x % (uint32_t)spin_bt,
                                              (uint32_t)spin_bt);
         return;
     }
-    const int2 w = work_atom[blockIdx.x - n_spin_blocks];
+    const int2 w = work_atom[blockIdx.x];
     atom_final_block<T, LPA, false>(runs, w, PHASE_STEP, sorted_bins, fold_k, S);
     const RunDev<T>& R = runs[w.x];
     RunState* st = R.st;
@@ -2232,7 +2235,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restri
         // no list is built in this launch, so no block reads the bins or
         // the overflow flag: each force block empties its share of the bins
         // the kick filled (the rebuild flags are clear)
-        const int nb = (int)gridDim.x - n_spin_blocks, f = (int)blockIdx.x - n_spin_blocks;
+        const int nb = n_atom_blocks, f = (int)blockIdx.x;
         const int per = (R.nbins + nb - 1) / nb;
         const int hi = min(R.nbins, (f + 1) * per);
         if (R.bin_step)
@@ -2249,7 +2252,7 @@ __global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restri
     __syncthreads();
     if (threadIdx.x == 0) {
         const int before = atomicAdd(&st->force_done, 1);
-        S.b_last = before == (int)gridDim.x - n_spin_blocks - 1;
+        S.b_last = before == n_atom_blocks - 1;
     }
     __syncthreads();
     if (!S.b_last) return;
