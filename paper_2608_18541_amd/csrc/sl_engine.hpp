@@ -648,10 +648,10 @@ public:
         const int G = graph_len();
         // a merged chunk shorter than the chunk length: replayed from a graph
         // kept per length, or launched directly
-        auto short_chunk = [&](int len) -> sl_status {
-            if (!with_graph) return enqueue_chunk(stream, nullptr, len);
+        auto short_chunk = [&](int len, bool free_end) -> sl_status {
+            if (!with_graph) return enqueue_chunk(stream, nullptr, len, free_end);
             hipGraphExec_t ex = nullptr;
-            sl_status st = chunk_graph(len, &ex);
+            sl_status st = chunk_graph(len, free_end, &ex);
             if (st != SL_OK) return st;
             SL_HIP(hipGraphLaunch(ex, stream));
             return SL_OK;
@@ -661,7 +661,7 @@ public:
             // length (it ends on no sample step: those are multiples of it)
             const int64_t head = std::min<int64_t>(chunk_head(), left);
             if (head > 0) {
-                sl_status st = short_chunk((int)head);
+                sl_status st = short_chunk((int)head, head < chunk_head());
                 if (st != SL_OK) return st;
             }
             left -= head;
@@ -683,7 +683,7 @@ public:
         }
         if (merge_g >= 2 && left > 0) {
             // the rest as one shorter merged chunk from a chunk boundary
-            sl_status st = short_chunk((int)left);
+            sl_status st = short_chunk((int)left, true);
             if (st != SL_OK) return st;
             left = 0;
         }
@@ -717,7 +717,7 @@ public:
         if (merge_g >= 2 && left > 0) {
             const int64_t head = std::min<int64_t>(chunk_head(), left);
             if (head > 0) {
-                sl_status st = enqueue_chunk(stream, &p, (int)head);
+                sl_status st = enqueue_chunk(stream, &p, (int)head, head < chunk_head());
                 if (st != SL_OK) return st;
             }
             left -= head;
@@ -726,7 +726,7 @@ public:
                 if (st != SL_OK) return st;
             }
             if (left > 0) {
-                sl_status st = enqueue_chunk(stream, &p, (int)left);
+                sl_status st = enqueue_chunk(stream, &p, (int)left, true);
                 if (st != SL_OK) return st;
                 left = 0;
             }
@@ -994,7 +994,7 @@ private:
     // graphs of merged chunks shorter than merge_g, by length (a chunk's
     // launches depend on its length only; every kernel reads the steps from
     // the run state)
-    std::vector<std::pair<int, hipGraphExec_t>> short_exec;
+    std::vector<std::pair<int, hipGraphExec_t>> short_exec;   // by 2 len + free_end
     bool tables_dirty = true;
     // persistent executor: runs that fit in LDS, one block each
     hipStream_t side_stream = nullptr;
@@ -1716,16 +1716,17 @@ private:
     // a k_finalize).  In the fused schedule (merged chunks) the force
     // kernel of every step but the chunk's last (a sample step, whose force
     // kernel reads the spins after the whole sweep) runs in the launch of
-    // colour pass 1.
+    // colour pass 1; free_end: the chunk ends off a chunk boundary, so on no
+    // sample step, and its last step's force kernel does too.
     sl_status enqueue_step(hipStream_t st, Prof* p, bool merge_first = false, bool defer_last = false,
-                           int fold_k = -1, int chunk_len = 0)
+                           int fold_k = -1, int chunk_len = 0, bool free_end = false)
     {
         const int C = max_colours();
         // the atom table's tiles hold atom_block / atom_lanes atoms:
         // k_atom_final gives each atom_lanes threads
         const dim3 bs(spin_eff), ba(atom_block), bk(sl::kBlock);
         const bool kick0 = fused && chunk_len > 0;
-        const bool force1 = kick0 && defer_last;
+        const bool force1 = kick0 && (defer_last || free_end);
         sl_status e;
         for (int pass = 0; pass < 2 * C - 1; ++pass) {
             if (defer_last && pass == 2 * C - 2) break;
@@ -1965,11 +1966,11 @@ private:
     // the last defers its last colour half step, every step but the first
     // applies the one deferred before it, so the chunk ends with complete
     // sweeps.
-    sl_status enqueue_chunk(hipStream_t st, Prof* p, int len = 0)
+    sl_status enqueue_chunk(hipStream_t st, Prof* p, int len = 0, bool free_end = false)
     {
         if (len <= 0) len = merge_g;
         for (int k = 0; k < len; ++k) {
-            sl_status e = enqueue_step(st, p, k > 0, k < len - 1, fold ? k : -1, len);
+            sl_status e = enqueue_step(st, p, k > 0, k < len - 1, fold ? k : -1, len, free_end);
             if (e != SL_OK) return e;
         }
         return SL_OK;
@@ -1989,23 +1990,24 @@ private:
     }
 
     // The graph of a merged chunk of len < merge_g steps (captured on first use).
-    sl_status chunk_graph(int len, hipGraphExec_t* out)
+    sl_status chunk_graph(int len, bool free_end, hipGraphExec_t* out)
     {
+        const int key = 2 * len + (free_end ? 1 : 0);
         for (auto& e : short_exec)
-            if (e.first == len) {
+            if (e.first == key) {
                 *out = e.second;
                 return SL_OK;
             }
         hipGraph_t graph = nullptr;
         SL_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue_chunk(cap_stream, nullptr, len);
+        enqueue_chunk(cap_stream, nullptr, len, free_end);
         hipError_t e = hipStreamEndCapture(cap_stream, &graph);
         if (e != hipSuccess) return fail(SL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
         hipGraphExec_t ex = nullptr;
         e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(SL_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-        short_exec.emplace_back(len, ex);
+        short_exec.emplace_back(key, ex);
         *out = ex;
         return SL_OK;
     }
