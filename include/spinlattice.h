@@ -348,9 +348,9 @@ typedef struct sl_tuning {
                                  bits either way                              */
     int32_t fuse_force;       /* 1 (default): in the merged chunks (merge_sweeps)
                                  of multi-kernel runs with constant exchange and
-                                 no anisotropy, a live lattice among them (one site
-                                 per thread, atom_block a multiple of the
-                                 colour-pass block), each step kicks the atoms
+                                 no anisotropy, a live lattice among them (one or
+                                 two sites per thread, atom_block a multiple of
+                                 the colour-pass block), each step kicks the atoms
                                  in colour pass 0 and runs the force kernel in
                                  the launch of colour pass 1, but for the
                                  chunk's last step: one launch fewer per step.  0: the kick rides with

@@ -1603,12 +1603,11 @@ private:
         }
         // the fused schedule (tuning fuse_force): merged chunks of runs with
         // the specialised site update (merging already excludes radial
-        // exchange), a live lattice among them, one site per thread, and
-        // force blocks that hold whole colour-pass tiles
+        // exchange; at most two sites per thread), a live lattice among them,
+        // and force blocks that hold whole colour-pass tiles
         fused = false;
         force_spin_blocks = 0;
-        if (merge_g >= 2 && fuse_force && lean_lat >= 0 && spin_spt == 1 && atom_block % spin_eff == 0 &&
-            !wk.empty()) {
+        if (merge_g >= 2 && fuse_force && lean_lat >= 0 && atom_block % spin_eff == 0 && !wk.empty()) {
             fused = true;
             const int per = atom_block / spin_eff;
             force_spin_blocks = ((int)ws.size() + per - 1) / per;
@@ -1765,7 +1764,7 @@ private:
                     launch_lean(g, bs, st, a, b, pass, fold_k);
                     return;
                 }
-                if (lean_lat >= 0 && spin_spt == 1) {
+                if (lean_lat >= 0) {
                     spin_pass_form(g, bs, st, a, b, pass, nf, merge, fold_k);
                     return;
                 }
@@ -1889,8 +1888,12 @@ private:
     void spin_pass_as(dim3 g, dim3 bs, hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int nf, int merge,
                       int fold_k)
     {
-        launch(sl::k_spin_pass<T, 1, false, LAT, MULTI>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
-               d_work_kick, active_blocks_spin, nf, merge, fold_k);
+        if (spin_spt == 2)
+            launch(sl::k_spin_pass<T, 2, false, LAT, MULTI>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
+                   d_work_kick, active_blocks_spin, nf, merge, fold_k);
+        else
+            launch(sl::k_spin_pass<T, 1, false, LAT, MULTI>, g, bs, 0, st, a, b, d_runs, d_work_spin, pass,
+                   d_work_kick, active_blocks_spin, nf, merge, fold_k);
     }
     void spin_pass_form(dim3 g, dim3 bs, hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int nf, int merge,
                         int fold_k)
@@ -1913,8 +1916,14 @@ private:
     void spin_force_as(hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int fold_k)
     {
         const dim3 g(force_spin_blocks + active_blocks_atom), bl(atom_block);
-        launch(sl::k_spin_force<T, LPA, LAT, MULTI>, g, bl, 0, st, a, b, d_runs, d_work_spin, active_blocks_spin,
-               spin_eff, active_blocks_atom, d_work_atom, pass, bin_each_step ? 0 : 1, fold_k, fold ? 1 : 0);
+        if (spin_spt == 2)
+            launch(sl::k_spin_force<T, LPA, LAT, MULTI, 2>, g, bl, 0, st, a, b, d_runs, d_work_spin,
+                   active_blocks_spin, spin_eff, active_blocks_atom, d_work_atom, pass, bin_each_step ? 0 : 1,
+                   fold_k, fold ? 1 : 0);
+        else
+            launch(sl::k_spin_force<T, LPA, LAT, MULTI>, g, bl, 0, st, a, b, d_runs, d_work_spin,
+                   active_blocks_spin, spin_eff, active_blocks_atom, d_work_atom, pass, bin_each_step ? 0 : 1,
+                   fold_k, fold ? 1 : 0);
     }
     template <int LPA> void spin_force_lanes(hipStream_t st, hipEvent_t a, hipEvent_t b, int pass, int fold_k)
     {

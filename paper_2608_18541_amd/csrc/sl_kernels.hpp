@@ -2200,7 +2200,8 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
 // n_atom_blocks blocks take the atom table (the force kernel, the longer
 // chain, is dispatched first); the others take n_spin_tiles tiles of the
 // spin table (spin_bt threads each, a multiple of 64, so every wave has one
-// tile) with the specialised site update of k_spin_pass_lean.  The force
+// tile; SPT sites per thread) with the specialised site update of
+// k_spin_pass_lean.  The force
 // kernel reads spins only on sample steps, which end a chunk and never take
 // this launch.  Unfolded, each step's k_finalize clears the bins and flags
 // the kick set.  In a folded chunk (`clear`, a single run) the next step's
@@ -2209,7 +2210,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_final(const RunDev<T>* __restri
 // a rebuild step, when they read them, the last force block to finish does.
 // (A count of finished blocks on every step cost about 10 ns per block: the
 // atomics on one address serialise.)
-template <typename T, int LPA, int LAT, bool MULTI>
+template <typename T, int LPA, int LAT, bool MULTI, int SPT = 1>
 __global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restrict__ runs,
                                                        const int2* __restrict__ work_spin, int n_spin_tiles,
                                                        int spin_bt, int n_atom_blocks,
@@ -2222,8 +2223,8 @@ __global__ __launch_bounds__(kBlock) void k_spin_force(const RunDev<T>* __restri
         const int t = __builtin_amdgcn_readfirstlane(((int)blockIdx.x - n_atom_blocks) * per +
                                                      (int)threadIdx.x / spin_bt);
         if (t < n_spin_tiles)
-            spin_lean_tile<T, 1, LAT, MULTI>(runs, work_spin[t], pass, fold_k, threadIdx.x % (uint32_t)spin_bt,
-                                             (uint32_t)spin_bt);
+            spin_lean_tile<T, SPT, LAT, MULTI>(runs, work_spin[t], pass, fold_k,
+                                               threadIdx.x % (uint32_t)spin_bt, (uint32_t)spin_bt);
         return;
     }
     const int2 w = work_atom[blockIdx.x];

@@ -53,6 +53,8 @@ SHAPES = [
     {"spin_block": 256},
     {"spin_block": 64, "atom_block": 128, "atom_lanes": 2},
     {"bin_mode": 2},                               # binning launches between the kick and the forces
+    {"spin_spt": 2},                               # two sites per thread in the colour passes
+    {"spin_spt": 2, "spin_block": 128},
 ]
 
 
